@@ -1,0 +1,216 @@
+/*
+ * qed.h - C ABI of the MI355X (gfx950) QED Monte Carlo particle step.
+ *
+ * Method: Wang, Sheng, Gibbon & Li, "Modeling of photon and pair production due
+ * to quantum electrodynamics effects in particle-in-cell simulation",
+ * arXiv:1608.06356.  Photon emission (nonlinear Compton) with the spectrum of
+ * Eq. (1) ("formula I") or Eq. (4) ("formula II"), pair creation (Breit-Wheeler)
+ * with Eq. (6), quantum parameters chi_e / chi_ph from Eqs. (2)-(3), photon
+ * energies by inverting the cumulative spectrum (Eq. 7) with the infrared cutoff
+ * xi_min eps_e = 2 m_e c^2, and the event generator of the paper's method II
+ * written as an optical depth.
+ *
+ * Units (the paper's normalisation, stated below Eqs. 2-3): time 1/omega_0,
+ * length c/omega_0, momentum m_e c, fields m_e c omega_0 / e.  The Schwinger field
+ * is E_S = m_e c^2 / (hbar omega_0) at lambda_0 = 1 um (412148.4...).
+ *
+ * Conventions for every entry point
+ *   - Return QED_OK (0) or a negative QED_ERR_* code; qed_last_error() gives text.
+ *   - Argument errors are detected on the host before anything is enqueued.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and is
+ *     asynchronous.  Device-side conditions (capacity exceeded, NaN chi, chi out of
+ *     table range, scan time-out) set counters in the context; qed_get_status()
+ *     synchronises the stream and returns and clears them.
+ *   - Every particle and field buffer is device memory owned by the caller, which
+ *     must keep it alive until the enqueued work has finished.  The library only
+ *     allocates its own context memory (tables, emitter list, counters, scan state)
+ *     in qed_create / qed_build_tables / qed_reserve.
+ *   - Particle counts live in device memory (qed_species_t.count), so a sequence of
+ *     calls needs no host synchronisation.
+ *
+ * Ordering contract: appended particles are ordered by (parent index, event
+ * number); new ids are next_id + rank (photons) or next_id + 2 rank and
+ * next_id + 2 rank + 1 (electron, positron of pair `rank`).  Given identical
+ * decisions, counts and positions of every appended or compacted particle are
+ * deterministic and independent of the launch configuration.
+ *
+ * Random numbers: Philox4x32-10 (Salmon et al., SC'11), key = (id_lo, id_hi ^ seed),
+ * counter = (step_lo, (step_hi & 0xFFFFFF) | purpose << 24, k, 0); uniform
+ * u = ((x >> 9) + 0.5) * 2^-23.
+ */
+#ifndef QED_H
+#define QED_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define QED_OK            0
+#define QED_ERR_ARG      (-1)   /* invalid argument (null pointer, size, enum)   */
+#define QED_ERR_HIP      (-2)   /* a HIP runtime call failed                     */
+#define QED_ERR_CAPACITY (-3)   /* an append exceeded a species' capacity        */
+#define QED_ERR_RANGE    (-4)   /* a size beyond what the context was reserved for */
+#define QED_ERR_STATE    (-5)   /* call order violated (tables missing, ...)     */
+
+/* element type of positions and momenta */
+#define QED_F32 0
+#define QED_F64 1
+
+/* photon spectrum used for the emission tables */
+#define QED_FORMULA_I  1        /* Eq. (1) */
+#define QED_FORMULA_II 2        /* Eq. (4) */
+
+/* field kinds */
+#define QED_FIELD_UNIFORM      0   /* E, B constant (qed_fields_t.E/B)             */
+#define QED_FIELD_GRID         1   /* periodic collocated grid, quadratic (TSC)    */
+#define QED_FIELD_PER_PARTICLE 2   /* one E, B per particle (arrays indexed like x) */
+
+/* qed_params_t.flags */
+#define QED_FLAG_NO_RECOIL     1u  /* leptons keep their momentum when emitting   */
+#define QED_FLAG_STATIC_PHOTONS 2u /* qed_create_pairs does not move photons      */
+
+#define QED_DEAD_ID UINT64_MAX     /* id of a particle removed by pair creation */
+
+#if defined(__GNUC__)
+#define QED_API __attribute__((visibility("default")))
+#else
+#define QED_API
+#endif
+
+typedef struct qed_ctx *qed_ctx_t;
+
+typedef struct {
+  uint32_t seed;      /* xor-ed into the Philox key                                  */
+  int32_t  kmax;      /* max events per lepton per step, 1..8 (cap is counted)       */
+  uint32_t flags;     /* QED_FLAG_*                                                  */
+  int32_t  reserved;
+} qed_params_t;
+
+/* Structure-of-arrays particle storage (caller-owned device memory).
+   Leptons: p = momentum.  Photons: p = k = gamma_ph * direction.
+   Live particles are [0, *count); each array holds `capacity` elements. */
+typedef struct {
+  int32_t   dtype;             /* QED_F32 or QED_F64: type of x..pz        */
+  int32_t   reserved;
+  void     *x, *y, *z;
+  void     *px, *py, *pz;
+  double   *tau;               /* optical depth (always float64)            */
+  uint64_t *id;                /* unique id; QED_DEAD_ID marks a dead one   */
+  int64_t   capacity;
+  int64_t  *count;             /* device int64                              */
+} qed_species_t;
+
+typedef struct {
+  int32_t kind;                /* QED_FIELD_*                                          */
+  int32_t nx, ny, nz;          /* GRID: nodes per axis                                 */
+  const float *grid;           /* GRID: 6 floats per node (Ex Ey Ez Bx By Bz),
+                                  node (i,j,k) at ((k*ny + j)*nx + i)*6; node i sits at
+                                  x = i*dx; the box [0, n*d) is periodic             */
+  double dx, dy, dz;
+  double E[3], B[3];           /* UNIFORM                                              */
+  const float *pE[3], *pB[3];  /* PER_PARTICLE: device arrays, element i for particle i */
+} qed_fields_t;
+
+/* Device-side event counters, accumulated since the last qed_get_status. */
+typedef struct {
+  int64_t events;              /* lepton optical-depth events                 */
+  int64_t photons;             /* photons appended                            */
+  int64_t rejected;            /* events below xi_min = 2/gamma (thinned)     */
+  int64_t capped;              /* leptons that reached kmax events in a step  */
+  int64_t pairs;               /* pairs appended                              */
+  int64_t dropped;             /* appends lost to a full species              */
+  int64_t chi_out_of_range;    /* lookups outside the tables' chi range        */
+  int64_t nan_chi;             /* particles skipped because chi was not finite */
+  int64_t scan_timeouts;       /* prefix-scan waits that gave up (must be 0)  */
+  int64_t compacted;           /* particles removed by qed_compact            */
+} qed_counters_t;
+
+/* Creates a context on the current HIP device.  Allocates counters only. */
+QED_API int qed_create(qed_ctx_t *ctx, const qed_params_t *params);
+QED_API void qed_destroy(qed_ctx_t ctx);
+QED_API const char *qed_last_error(qed_ctx_t ctx);
+
+/* Reserves the context's emitter list and scan state for species of up to
+   `max_particles` elements (allocates; call before graph capture). */
+QED_API int qed_reserve(qed_ctx_t ctx, int64_t max_particles);
+
+/* Sets the next id handed to appended particles (device counter). */
+QED_API int qed_set_next_id(qed_ctx_t ctx, uint64_t next_id, void *stream);
+QED_API int qed_get_next_id(qed_ctx_t ctx, uint64_t *next_id, void *stream);   /* syncs */
+
+/* Builds all tables on the device in float64 by quadrature of the paper's spectra:
+   the photon rate h(chi) and inverse CDF (Eq. 1 if formula == QED_FORMULA_I,
+   Eq. 4 if QED_FORMULA_II; text after Eq. 7) on 256 chi nodes over [1e-3, 1e2],
+   256 quantile nodes each; the pair rate (Eq. 6) on 512 chi nodes over [1e-2, 1e2]
+   and the half-spectrum inverse CDF on 256 x 256 nodes.  Also writes the float32 /
+   16-bit copies the single-precision kernels stage in LDS. */
+QED_API int qed_build_tables(qed_ctx_t ctx, int formula, void *stream);
+
+/* Copies a table to host memory (synchronous).  which: 0 rad ln h [256] f64,
+   1 rad logit-xi quantiles [256*256] f64, 2 pair ln h + 8/(3 chi) [512] f64,
+   3 pair quantiles [256*256] f64, 4 rad 16-bit codes [256*256] u16,
+   5 rad row offset/scale [2*256] f32, 6 pair 16-bit codes, 7 pair offset/scale. */
+QED_API int qed_get_table(qed_ctx_t ctx, int which, void *host, size_t bytes);
+
+/* tau = -ln u for particles [0, *count) (Philox purpose 0, counter k = 0). */
+QED_API int qed_init_optical_depth(qed_ctx_t ctx, qed_species_t *sp, int64_t step, void *stream);
+
+/* Fills a grid with the circularly polarised standing wave
+   E = a0 cos x (0, cos t, sin t), B = a0 sin x (0, cos t, sin t) at time t on n^3
+   nodes of spacing L/n (layout of qed_fields_t.grid). */
+QED_API int qed_fill_standing_wave(qed_ctx_t ctx, float *grid, int n, double L, double a0,
+                           double t, void *stream);
+
+/* Lepton pass, every particle [0, *count): field at x^n, relativistic Boris push
+   (charge = -1 electron, +1 positron), x^{n+1} = x^n + v dt (wrapped into a GRID
+   box), chi_e from Eq. (2) in float64, W = alpha E_S h(chi)/gamma, and the optical
+   depth decrement tau -= W dt.  Particles whose optical depth runs out within the
+   step are written, in index order, to the context's emitter list with the fields
+   they saw and the time left after their first event; qed_emit_photons finishes
+   them.  Fails with QED_ERR_STATE if the tables are missing. */
+QED_API int qed_gather_push(qed_ctx_t ctx, const qed_fields_t *fields, qed_species_t *leptons,
+                    int charge, double dt, int64_t step, void *stream);
+
+/* Emission events of the emitters found by the last qed_gather_push on `leptons`:
+   per event k draws xi from the inverse CDF (Eq. 7), rejects xi < 2/gamma, appends
+   a photon of energy xi gamma along p with its own optical depth, recoils the lepton
+   to (1 - xi) gamma, draws a new tau, and continues while the optical depth runs out
+   again within the step (at most kmax events).  Photons are appended after
+   photons->count in (emitter index, k) order. */
+QED_API int qed_emit_photons(qed_ctx_t ctx, qed_species_t *leptons, qed_species_t *photons,
+                     int64_t step, void *stream);
+
+/* Photon pass, every photon [0, *count): ballistic move (unless
+   QED_FLAG_STATIC_PHOTONS), chi_ph from Eq. (3), W_pair = alpha E_S h_pair/gamma_ph
+   (zero below gamma_ph = 2), optical depth; on an event xi = eps_e/eps_ph from the
+   half-spectrum of Eq. (6), the electron gets xi gamma_ph and the positron the rest,
+   both along the photon, appended at the same rank; the photon's id becomes
+   QED_DEAD_ID (remove it with qed_compact). */
+QED_API int qed_create_pairs(qed_ctx_t ctx, const qed_fields_t *fields, qed_species_t *photons,
+                     qed_species_t *electrons, qed_species_t *positrons, double dt,
+                     int64_t step, void *stream);
+
+/* Stable in-place removal of particles whose id is QED_DEAD_ID. */
+QED_API int qed_compact(qed_ctx_t ctx, qed_species_t *sp, void *stream);
+
+/* Standalone lookups: for n particles with chi (f64) and gamma (f64) and the ids
+   used for their streams, writes ln W_rad (f32, uncut rate, -inf if zero) and one
+   xi sample (f32, event k = 0 of `step`); precision selects the table copy:
+   QED_F64 master tables or QED_F32 (16-bit LDS copy).  ln W_pair likewise if
+   lnw_pair != NULL (gamma taken as gamma_ph). */
+QED_API int qed_sample(qed_ctx_t ctx, const double *chi, const double *gamma, const uint64_t *id,
+               int64_t n, int precision, int64_t step, float *lnw_rad, float *xi,
+               float *lnw_pair, void *stream);
+
+/* Synchronises `stream`, returns the counters and clears them.  Returns
+   QED_ERR_CAPACITY if appends were dropped since the last call. */
+QED_API int qed_get_status(qed_ctx_t ctx, qed_counters_t *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QED_H */

@@ -1,0 +1,270 @@
+"""Python binding of libqedmi (the gfx950 QED Monte Carlo step).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+``csrc/``.  The names follow the C ABI in ``include/qed.h``.  PyTorch provides
+device memory and streams.  Importing this module does not load the library;
+the first call does, and it raises if ``libqedmi.so`` is missing (build it with
+``python -m paper_1608_06356_amd.build`` or ``__graft_entry__.build()``).
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqedmi.so")
+
+QED_OK, QED_ERR_ARG, QED_ERR_HIP, QED_ERR_CAPACITY, QED_ERR_RANGE, QED_ERR_STATE = 0, -1, -2, -3, -4, -5
+QED_F32, QED_F64 = 0, 1
+QED_FORMULA_I, QED_FORMULA_II = 1, 2
+QED_FIELD_UNIFORM, QED_FIELD_GRID, QED_FIELD_PER_PARTICLE = 0, 1, 2
+QED_FLAG_NO_RECOIL, QED_FLAG_STATIC_PHOTONS = 1, 2
+DEAD_ID = 0xFFFFFFFFFFFFFFFF
+EXPORTS = ["qed_create", "qed_destroy", "qed_last_error", "qed_reserve", "qed_set_next_id",
+           "qed_get_next_id", "qed_build_tables", "qed_get_table", "qed_init_optical_depth",
+           "qed_fill_standing_wave", "qed_gather_push", "qed_emit_photons", "qed_create_pairs",
+           "qed_compact", "qed_sample", "qed_get_status"]
+
+
+class qed_params_t(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint32), ("kmax", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_int32)]
+
+
+class qed_species_t(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
+                ("px", ctypes.c_void_p), ("py", ctypes.c_void_p), ("pz", ctypes.c_void_p),
+                ("tau", ctypes.c_void_p), ("id", ctypes.c_void_p),
+                ("capacity", ctypes.c_int64), ("count", ctypes.c_void_p)]
+
+
+class qed_fields_t(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("nz", ctypes.c_int32), ("grid", ctypes.c_void_p),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+                ("E", ctypes.c_double * 3), ("B", ctypes.c_double * 3),
+                ("pE", ctypes.c_void_p * 3), ("pB", ctypes.c_void_p * 3)]
+
+
+class qed_counters_t(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "events", "photons", "rejected", "capped", "pairs", "dropped", "chi_out_of_range",
+        "nan_chi", "scan_timeouts", "compacted")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Loads libqedmi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} not built: run python -m paper_1608_06356_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64
+        sig = {
+            "qed_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(qed_params_t)]),
+            "qed_destroy": (None, [vp]),
+            "qed_last_error": (ctypes.c_char_p, [vp]),
+            "qed_reserve": (ctypes.c_int, [vp, i64]),
+            "qed_set_next_id": (ctypes.c_int, [vp, u64, vp]),
+            "qed_get_next_id": (ctypes.c_int, [vp, ctypes.POINTER(u64), vp]),
+            "qed_build_tables": (ctypes.c_int, [vp, ctypes.c_int, vp]),
+            "qed_get_table": (ctypes.c_int, [vp, ctypes.c_int, vp, ctypes.c_size_t]),
+            "qed_init_optical_depth": (ctypes.c_int, [vp, ctypes.POINTER(qed_species_t), i64, vp]),
+            "qed_fill_standing_wave": (ctypes.c_int, [vp, vp, ctypes.c_int, ctypes.c_double,
+                                                      ctypes.c_double, ctypes.c_double, vp]),
+            "qed_gather_push": (ctypes.c_int, [vp, ctypes.POINTER(qed_fields_t), ctypes.POINTER(qed_species_t),
+                                               ctypes.c_int, ctypes.c_double, i64, vp]),
+            "qed_emit_photons": (ctypes.c_int, [vp, ctypes.POINTER(qed_species_t),
+                                                ctypes.POINTER(qed_species_t), i64, vp]),
+            "qed_create_pairs": (ctypes.c_int, [vp, ctypes.POINTER(qed_fields_t), ctypes.POINTER(qed_species_t),
+                                                ctypes.POINTER(qed_species_t), ctypes.POINTER(qed_species_t),
+                                                ctypes.c_double, i64, vp]),
+            "qed_compact": (ctypes.c_int, [vp, ctypes.POINTER(qed_species_t), vp]),
+            "qed_sample": (ctypes.c_int, [vp, vp, vp, vp, i64, ctypes.c_int, i64, vp, vp, vp, vp]),
+            "qed_get_status": (ctypes.c_int, [vp, ctypes.POINTER(qed_counters_t), vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class QEDError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"qed error {code}: {msg}")
+        self.code = code
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(stream)
+
+
+class Context:
+    """Owns a qed_ctx_t; methods are the C entry points with the same names."""
+
+    def __init__(self, seed=0, kmax=4, flags=0):
+        self.params = qed_params_t(seed, kmax, flags, 0)
+        h = ctypes.c_void_p()
+        rc = lib().qed_create(ctypes.byref(h), ctypes.byref(self.params))
+        if rc != QED_OK:
+            raise QEDError(rc, "qed_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().qed_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != QED_OK:
+            raise QEDError(rc, lib().qed_last_error(self.h).decode())
+        return rc
+
+    def qed_reserve(self, n):
+        return self._check(lib().qed_reserve(self.h, int(n)))
+
+    def qed_set_next_id(self, v, stream=None):
+        return self._check(lib().qed_set_next_id(self.h, int(v), _stream(stream)))
+
+    def qed_get_next_id(self, stream=None):
+        v = ctypes.c_uint64()
+        self._check(lib().qed_get_next_id(self.h, ctypes.byref(v), _stream(stream)))
+        return v.value
+
+    def qed_build_tables(self, formula=QED_FORMULA_I, stream=None):
+        return self._check(lib().qed_build_tables(self.h, formula, _stream(stream)))
+
+    def qed_get_table(self, which):
+        import numpy as np
+        shapes = {0: (np.float64, (256,)), 1: (np.float64, (256, 256)), 2: (np.float64, (512,)),
+                  3: (np.float64, (256, 256)), 4: (np.uint16, (256, 256)), 5: (np.float32, (256, 2)),
+                  6: (np.uint16, (256, 256)), 7: (np.float32, (256, 2))}
+        dt, shp = shapes[which]
+        out = np.empty(shp, dtype=dt)
+        self._check(lib().qed_get_table(self.h, which, out.ctypes.data_as(ctypes.c_void_p), out.nbytes))
+        return out
+
+    def qed_init_optical_depth(self, sp, step=0, stream=None):
+        return self._check(lib().qed_init_optical_depth(self.h, ctypes.byref(sp.c), int(step), _stream(stream)))
+
+    def qed_fill_standing_wave(self, grid, n, L, a0, t, stream=None):
+        return self._check(lib().qed_fill_standing_wave(self.h, ctypes.c_void_p(grid.data_ptr()), int(n),
+                                                        float(L), float(a0), float(t), _stream(stream)))
+
+    def qed_gather_push(self, fields, leptons, charge, dt, step, stream=None):
+        return self._check(lib().qed_gather_push(self.h, ctypes.byref(fields.c), ctypes.byref(leptons.c),
+                                                 int(charge), float(dt), int(step), _stream(stream)))
+
+    def qed_emit_photons(self, leptons, photons, step, stream=None):
+        return self._check(lib().qed_emit_photons(self.h, ctypes.byref(leptons.c), ctypes.byref(photons.c),
+                                                  int(step), _stream(stream)))
+
+    def qed_create_pairs(self, fields, photons, electrons, positrons, dt, step, stream=None):
+        return self._check(lib().qed_create_pairs(self.h, ctypes.byref(fields.c), ctypes.byref(photons.c),
+                                                  ctypes.byref(electrons.c), ctypes.byref(positrons.c),
+                                                  float(dt), int(step), _stream(stream)))
+
+    def qed_compact(self, sp, stream=None):
+        return self._check(lib().qed_compact(self.h, ctypes.byref(sp.c), _stream(stream)))
+
+    def qed_sample(self, chi, gamma, ids, precision, step, lnw, xi, lnwp=None, stream=None):
+        n = chi.numel()
+        p = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p()
+        return self._check(lib().qed_sample(self.h, p(chi), p(gamma), p(ids), n, precision, int(step),
+                                            p(lnw), p(xi), p(lnwp), _stream(stream)))
+
+    def qed_get_status(self, stream=None, check=True):
+        c = qed_counters_t()
+        rc = lib().qed_get_status(self.h, ctypes.byref(c), _stream(stream))
+        if check:
+            self._check(rc)
+        return c.as_dict(), rc
+
+
+class Species:
+    """Structure-of-arrays particle storage in torch device tensors."""
+
+    def __init__(self, capacity, dtype="f32", device="cuda"):
+        import torch
+        self.torch_dtype = torch.float32 if dtype == "f32" else torch.float64
+        self.capacity = int(capacity)
+        t = lambda dt: torch.zeros(self.capacity, dtype=dt, device=device)
+        self.x, self.y, self.z = t(self.torch_dtype), t(self.torch_dtype), t(self.torch_dtype)
+        self.px, self.py, self.pz = t(self.torch_dtype), t(self.torch_dtype), t(self.torch_dtype)
+        self.tau = t(torch.float64)
+        self.id = torch.full((self.capacity,), -1, dtype=torch.int64, device=device)
+        self.count = torch.zeros(1, dtype=torch.int64, device=device)
+        p = lambda a: ctypes.c_void_p(a.data_ptr())
+        self.c = qed_species_t(QED_F32 if dtype == "f32" else QED_F64, 0, p(self.x), p(self.y), p(self.z),
+                               p(self.px), p(self.py), p(self.pz), p(self.tau), p(self.id),
+                               self.capacity, p(self.count))
+
+    def load(self, x, p, tau=None, ids=None):
+        """Copies host arrays x (n,3), p (n,3), tau (n,), ids (n,) into [0, n)."""
+        import numpy as np
+        import torch
+        n = x.shape[0]
+        if n > self.capacity:
+            raise ValueError("more particles than capacity")
+        for a, col in ((self.x, x[:, 0]), (self.y, x[:, 1]), (self.z, x[:, 2]),
+                       (self.px, p[:, 0]), (self.py, p[:, 1]), (self.pz, p[:, 2])):
+            a[:n].copy_(torch.from_numpy(np.ascontiguousarray(col)).to(self.torch_dtype))
+        if tau is not None:
+            self.tau[:n].copy_(torch.from_numpy(np.ascontiguousarray(tau, dtype=np.float64)))
+        if ids is not None:
+            self.id[:n].copy_(torch.from_numpy(np.ascontiguousarray(ids).astype(np.uint64).view(np.int64)))
+        self.count.fill_(n)
+
+    def n(self):
+        return int(self.count.item())
+
+    def to_numpy(self):
+        import numpy as np
+        n = self.n()
+        g = lambda a: a[:n].double().cpu().numpy()
+        return dict(x=np.stack([g(self.x), g(self.y), g(self.z)], -1),
+                    p=np.stack([g(self.px), g(self.py), g(self.pz)], -1),
+                    tau=self.tau[:n].cpu().numpy(),
+                    id=self.id[:n].cpu().numpy().view(np.uint64))
+
+
+class Fields:
+    """qed_fields_t with the device tensors it points to kept alive."""
+
+    def __init__(self, kind, **kw):
+        self.c = qed_fields_t()
+        self.c.kind = kind
+        self._keep = []
+        if kind == QED_FIELD_UNIFORM:
+            for k in range(3):
+                self.c.E[k] = float(kw.get("E", (0, 0, 0))[k])
+                self.c.B[k] = float(kw.get("B", (0, 0, 0))[k])
+        elif kind == QED_FIELD_GRID:
+            g = kw["grid"]
+            n = kw["n"]
+            d = kw["L"] / n
+            self.c.nx = self.c.ny = self.c.nz = n
+            self.c.dx = self.c.dy = self.c.dz = d
+            self.c.grid = ctypes.c_void_p(g.data_ptr())
+            self._keep.append(g)
+        elif kind == QED_FIELD_PER_PARTICLE:
+            for k in range(3):
+                self.c.pE[k] = ctypes.c_void_p(kw["E"][k].data_ptr())
+                self.c.pB[k] = ctypes.c_void_p(kw["B"][k].data_ptr())
+                self._keep += [kw["E"][k], kw["B"][k]]

@@ -1,0 +1,295 @@
+// extern "C" entry points of the QED step library: argument checks on the host,
+// context memory, and the launches of the kernels in step.hip / tables.hip.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "internal.h"
+#include "qed_device.h"
+
+namespace {
+
+int fail(qed_ctx *c, int code, const std::string &msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_fail(qed_ctx *c, hipError_t e, const char *where) {
+  return fail(c, QED_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+int check_species(qed_ctx *c, const qed_species_t *s, const char *name) {
+  if (!s) return fail(c, QED_ERR_ARG, std::string(name) + " is null");
+  if (s->dtype != QED_F32 && s->dtype != QED_F64)
+    return fail(c, QED_ERR_ARG, std::string(name) + ": dtype must be QED_F32 or QED_F64");
+  if (!s->x || !s->y || !s->z || !s->px || !s->py || !s->pz || !s->tau || !s->id || !s->count)
+    return fail(c, QED_ERR_ARG, std::string(name) + ": null array");
+  if (s->capacity <= 0 || s->capacity > (int64_t)INT32_MAX)
+    return fail(c, QED_ERR_ARG, std::string(name) + ": capacity must be in [1, 2^31)");
+  return QED_OK;
+}
+
+int check_fields(qed_ctx *c, const qed_fields_t *f) {
+  if (!f) return fail(c, QED_ERR_ARG, "fields is null");
+  if (f->kind == QED_FIELD_UNIFORM) return QED_OK;
+  if (f->kind == QED_FIELD_GRID) {
+    if (!f->grid || f->nx < 3 || f->ny < 3 || f->nz < 3 || !(f->dx > 0) || !(f->dy > 0) || !(f->dz > 0))
+      return fail(c, QED_ERR_ARG, "grid fields: need grid pointer, n >= 3 and d > 0 on every axis");
+    if (((uintptr_t)f->grid) % 8)
+      return fail(c, QED_ERR_ARG, "grid fields: pointer must be 8-byte aligned");
+    if ((int64_t)f->nx * f->ny * f->nz * 6 > (int64_t)1 << 40)
+      return fail(c, QED_ERR_ARG, "grid fields: too many nodes");
+    return QED_OK;
+  }
+  if (f->kind == QED_FIELD_PER_PARTICLE) {
+    for (int k = 0; k < 3; ++k)
+      if (!f->pE[k] || !f->pB[k]) return fail(c, QED_ERR_ARG, "per-particle fields: null array");
+    return QED_OK;
+  }
+  return fail(c, QED_ERR_ARG, "unknown field kind");
+}
+
+template <typename T> hipError_t dalloc(T **p, size_t n) {
+  return hipMalloc((void **)p, n * sizeof(T) > 0 ? n * sizeof(T) : 1);
+}
+
+void free_emitters(qed_ctx *c) {
+  (void)hipFree(c->em_idx); (void)hipFree(c->em_fld); (void)hipFree(c->em_rem); (void)hipFree(c->d_status);
+  c->em_idx = nullptr; c->em_fld = nullptr; c->em_rem = nullptr; c->d_status = nullptr;
+  c->reserved = 0; c->status_len = 0;
+}
+
+int ensure_reserved(qed_ctx *c, int64_t n) {
+  if (n <= c->reserved) return QED_OK;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(c, e, "reserve");
+  free_emitters(c);
+  const int64_t status_len = n / 256 + 64;
+  if ((e = dalloc(&c->em_idx, n)) != hipSuccess || (e = dalloc(&c->em_fld, 8 * n)) != hipSuccess ||
+      (e = dalloc(&c->em_rem, n)) != hipSuccess || (e = dalloc(&c->d_status, status_len)) != hipSuccess) {
+    free_emitters(c);
+    return hip_fail(c, e, "reserve: hipMalloc");
+  }
+  c->reserved = n;
+  c->status_len = status_len;
+  c->em_owner = nullptr;
+  return QED_OK;
+}
+
+hipStream_t S(void *s) { return (hipStream_t)s; }
+
+}  // namespace
+
+extern "C" {
+
+int qed_create(qed_ctx_t *out, const qed_params_t *p) {
+  if (!out || !p) return QED_ERR_ARG;
+  *out = nullptr;
+  if (p->kmax < 1 || p->kmax > 4) return QED_ERR_ARG;
+  qed_ctx *c = new (std::nothrow) qed_ctx();
+  if (!c) return QED_ERR_ARG;
+  c->params = *p;
+  hipError_t e = hipGetDevice(&c->device);
+  int ncu = 0;
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+  if (e == hipSuccess) c->n_cu = ncu > 0 ? ncu : 256;
+  if (e == hipSuccess) e = dalloc(&c->d_counters, qed::cNumCounters);
+  if (e == hipSuccess) e = dalloc(&c->d_next_id, 1);
+  if (e == hipSuccess) e = dalloc(&c->d_n_emit, 1);
+  if (e == hipSuccess) e = dalloc(&c->d_ticket, 1);
+  if (e == hipSuccess) e = hipMemset(c->d_counters, 0, sizeof(unsigned long long) * qed::cNumCounters);
+  if (e == hipSuccess) e = hipMemset(c->d_next_id, 0, sizeof(uint64_t));
+  if (e == hipSuccess) e = hipMemset(c->d_n_emit, 0, sizeof(int64_t));
+  if (e != hipSuccess) {
+    qed_destroy(c);
+    return QED_ERR_HIP;
+  }
+  *out = c;
+  return QED_OK;
+}
+
+void qed_destroy(qed_ctx_t c) {
+  if (!c) return;
+  (void)hipDeviceSynchronize();
+  free_emitters(c);
+  void *ptrs[] = {c->rad_lnh64, c->rad_S64, c->rad_lnh32, c->rad_s0sc, c->rad_q16, c->pair_L64,
+                  c->pair_S64, c->pair_L32, c->pair_s0sc, c->pair_q16, c->tab_work, c->d_counters,
+                  c->d_next_id, c->d_n_emit, c->d_ticket};
+  for (void *p : ptrs) (void)hipFree(p);
+  delete c;
+}
+
+const char *qed_last_error(qed_ctx_t c) { return c ? c->err.c_str() : "null context"; }
+
+int qed_reserve(qed_ctx_t c, int64_t n) {
+  if (!c) return QED_ERR_ARG;
+  if (n <= 0 || n > (int64_t)INT32_MAX) return fail(c, QED_ERR_ARG, "reserve: n must be in [1, 2^31)");
+  return ensure_reserved(c, n);
+}
+
+int qed_set_next_id(qed_ctx_t c, uint64_t v, void *st) {
+  if (!c) return QED_ERR_ARG;
+  // the value is copied from a host temporary, so wait for the copy
+  hipError_t e = hipMemcpyAsync(c->d_next_id, &v, sizeof(v), hipMemcpyHostToDevice, S(st));
+  if (e == hipSuccess) e = hipStreamSynchronize(S(st));
+  return e == hipSuccess ? QED_OK : hip_fail(c, e, "set_next_id");
+}
+
+int qed_get_next_id(qed_ctx_t c, uint64_t *v, void *st) {
+  if (!c || !v) return QED_ERR_ARG;
+  hipError_t e = hipMemcpyAsync(v, c->d_next_id, sizeof(*v), hipMemcpyDeviceToHost, S(st));
+  if (e == hipSuccess) e = hipStreamSynchronize(S(st));
+  return e == hipSuccess ? QED_OK : hip_fail(c, e, "get_next_id");
+}
+
+int qed_build_tables(qed_ctx_t c, int formula, void *st) {
+  if (!c) return QED_ERR_ARG;
+  if (formula != QED_FORMULA_I && formula != QED_FORMULA_II)
+    return fail(c, QED_ERR_ARG, "formula must be QED_FORMULA_I or QED_FORMULA_II");
+  using namespace qed;
+  hipError_t e = hipSuccess;
+  if (!c->rad_lnh64) {
+    const size_t work = (size_t)(kRadNChi + kPairNRate + kPairNCdf) * (4 * 1024 + 1);
+    if ((e = dalloc(&c->rad_lnh64, kRadNChi)) != hipSuccess || (e = dalloc(&c->rad_S64, kRadNChi * kNU)) != hipSuccess ||
+        (e = dalloc(&c->rad_lnh32, kRadNChi)) != hipSuccess || (e = dalloc(&c->rad_s0sc, 2 * kRadNChi)) != hipSuccess ||
+        (e = dalloc(&c->rad_q16, kRadNChi * kNU)) != hipSuccess || (e = dalloc(&c->pair_L64, kPairNRate)) != hipSuccess ||
+        (e = dalloc(&c->pair_S64, kPairNCdf * kNU)) != hipSuccess || (e = dalloc(&c->pair_L32, kPairNRate)) != hipSuccess ||
+        (e = dalloc(&c->pair_s0sc, 2 * kPairNCdf)) != hipSuccess || (e = dalloc(&c->pair_q16, kPairNCdf * kNU)) != hipSuccess ||
+        (e = dalloc(&c->tab_work, work)) != hipSuccess)
+      return hip_fail(c, e, "build_tables: hipMalloc");
+    c->tab_work_elems = work;
+  }
+  c->tables_ready = false;
+  if ((e = launch_build_tables(c, formula, S(st))) != hipSuccess) return hip_fail(c, e, "build_tables");
+  c->tables_ready = true;
+  c->formula = formula;
+  return QED_OK;
+}
+
+int qed_get_table(qed_ctx_t c, int which, void *host, size_t bytes) {
+  if (!c || !host) return QED_ERR_ARG;
+  if (!c->tables_ready) return fail(c, QED_ERR_STATE, "tables not built");
+  using namespace qed;
+  const void *src = nullptr;
+  size_t need = 0;
+  switch (which) {
+    case 0: src = c->rad_lnh64; need = kRadNChi * 8; break;
+    case 1: src = c->rad_S64; need = kRadNChi * kNU * 8; break;
+    case 2: src = c->pair_L64; need = kPairNRate * 8; break;
+    case 3: src = c->pair_S64; need = kPairNCdf * kNU * 8; break;
+    case 4: src = c->rad_q16; need = kRadNChi * kNU * 2; break;
+    case 5: src = c->rad_s0sc; need = 2 * kRadNChi * 4; break;
+    case 6: src = c->pair_q16; need = kPairNCdf * kNU * 2; break;
+    case 7: src = c->pair_s0sc; need = 2 * kPairNCdf * 4; break;
+    default: return fail(c, QED_ERR_ARG, "get_table: unknown table");
+  }
+  if (bytes != need) return fail(c, QED_ERR_ARG, "get_table: wrong byte count, need " + std::to_string(need));
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(host, src, need, hipMemcpyDeviceToHost);
+  return e == hipSuccess ? QED_OK : hip_fail(c, e, "get_table");
+}
+
+int qed_init_optical_depth(qed_ctx_t c, qed_species_t *sp, int64_t step, void *st) {
+  if (!c) return QED_ERR_ARG;
+  int r = check_species(c, sp, "species");
+  if (r) return r;
+  if (step < 0) return fail(c, QED_ERR_ARG, "step must be >= 0");
+  hipError_t e = qed::launch_init_tau(c, sp, step, S(st));
+  return e == hipSuccess ? QED_OK : hip_fail(c, e, "init_optical_depth");
+}
+
+int qed_fill_standing_wave(qed_ctx_t c, float *grid, int n, double L, double a0, double t, void *st) {
+  if (!c) return QED_ERR_ARG;
+  if (!grid || n < 3 || n > 4096 || !(L > 0)) return fail(c, QED_ERR_ARG, "fill_standing_wave: bad grid");
+  hipError_t e = qed::launch_standing_wave(grid, n, L, a0, t, S(st));
+  return e == hipSuccess ? QED_OK : hip_fail(c, e, "fill_standing_wave");
+}
+
+int qed_gather_push(qed_ctx_t c, const qed_fields_t *f, qed_species_t *lep, int charge, double dt,
+                    int64_t step, void *st) {
+  (void)step;
+  if (!c) return QED_ERR_ARG;
+  int r = check_species(c, lep, "leptons");
+  if (r) return r;
+  if ((r = check_fields(c, f))) return r;
+  if (charge != -1 && charge != 1) return fail(c, QED_ERR_ARG, "charge must be -1 or +1");
+  if (!(dt > 0)) return fail(c, QED_ERR_ARG, "dt must be > 0");
+  if (!c->tables_ready) return fail(c, QED_ERR_STATE, "tables not built (call qed_build_tables)");
+  if ((r = ensure_reserved(c, lep->capacity))) return r;
+  hipError_t e = qed::launch_gather_push(c, f, lep, charge, dt, S(st));
+  if (e != hipSuccess) return hip_fail(c, e, "gather_push");
+  c->em_owner = lep->x;
+  c->em_dtype = lep->dtype;
+  return QED_OK;
+}
+
+int qed_emit_photons(qed_ctx_t c, qed_species_t *lep, qed_species_t *ph, int64_t step, void *st) {
+  if (!c) return QED_ERR_ARG;
+  int r = check_species(c, lep, "leptons");
+  if (r) return r;
+  if ((r = check_species(c, ph, "photons"))) return r;
+  if (lep->dtype != ph->dtype) return fail(c, QED_ERR_ARG, "leptons and photons must share dtype");
+  if (step < 0) return fail(c, QED_ERR_ARG, "step must be >= 0");
+  if (!c->tables_ready) return fail(c, QED_ERR_STATE, "tables not built");
+  if (c->em_owner != lep->x || c->em_dtype != lep->dtype)
+    return fail(c, QED_ERR_STATE, "emit_photons must follow qed_gather_push on the same leptons");
+  hipError_t e = qed::launch_emit(c, lep, ph, step, S(st));
+  if (e != hipSuccess) return hip_fail(c, e, "emit_photons");
+  c->em_owner = nullptr;
+  return QED_OK;
+}
+
+int qed_create_pairs(qed_ctx_t c, const qed_fields_t *f, qed_species_t *ph, qed_species_t *el,
+                     qed_species_t *po, double dt, int64_t step, void *st) {
+  if (!c) return QED_ERR_ARG;
+  int r = check_species(c, ph, "photons");
+  if (r) return r;
+  if ((r = check_species(c, el, "electrons")) || (r = check_species(c, po, "positrons"))) return r;
+  if ((r = check_fields(c, f))) return r;
+  if (ph->dtype != el->dtype || ph->dtype != po->dtype)
+    return fail(c, QED_ERR_ARG, "photons, electrons and positrons must share dtype");
+  if (!(dt > 0)) return fail(c, QED_ERR_ARG, "dt must be > 0");
+  if (step < 0) return fail(c, QED_ERR_ARG, "step must be >= 0");
+  if (!c->tables_ready) return fail(c, QED_ERR_STATE, "tables not built");
+  if ((r = ensure_reserved(c, ph->capacity))) return r;
+  hipError_t e = qed::launch_pairs(c, f, ph, el, po, dt, step, S(st));
+  return e == hipSuccess ? QED_OK : hip_fail(c, e, "create_pairs");
+}
+
+int qed_compact(qed_ctx_t c, qed_species_t *sp, void *st) {
+  if (!c) return QED_ERR_ARG;
+  int r = check_species(c, sp, "species");
+  if (r) return r;
+  if ((r = ensure_reserved(c, sp->capacity))) return r;
+  hipError_t e = qed::launch_compact(c, sp, S(st));
+  return e == hipSuccess ? QED_OK : hip_fail(c, e, "compact");
+}
+
+int qed_sample(qed_ctx_t c, const double *chi, const double *gamma, const uint64_t *id, int64_t n,
+               int precision, int64_t step, float *lnw, float *xi, float *lnwp, void *st) {
+  if (!c) return QED_ERR_ARG;
+  if (!chi || !gamma || !id || !lnw || !xi || n < 0) return fail(c, QED_ERR_ARG, "sample: bad arguments");
+  if (precision != QED_F32 && precision != QED_F64) return fail(c, QED_ERR_ARG, "sample: bad precision");
+  if (!c->tables_ready) return fail(c, QED_ERR_STATE, "tables not built");
+  if (n == 0) return QED_OK;
+  hipError_t e = qed::launch_sample(c, chi, gamma, id, n, precision, step, lnw, xi, lnwp, S(st));
+  return e == hipSuccess ? QED_OK : hip_fail(c, e, "sample");
+}
+
+int qed_get_status(qed_ctx_t c, qed_counters_t *out, void *st) {
+  if (!c || !out) return QED_ERR_ARG;
+  unsigned long long h[qed::cNumCounters];
+  hipError_t e = hipStreamSynchronize(S(st));
+  if (e == hipSuccess) e = hipMemcpy(h, c->d_counters, sizeof(h), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemset(c->d_counters, 0, sizeof(h));
+  if (e != hipSuccess) return hip_fail(c, e, "get_status");
+  int64_t *o = (int64_t *)out;
+  for (int k = 0; k < qed::cNumCounters; ++k) o[k] = (int64_t)h[k];
+  if (out->scan_timeouts) return fail(c, QED_ERR_STATE, "prefix scan timed out");
+  if (out->dropped) return fail(c, QED_ERR_CAPACITY, "appends dropped: species capacity exceeded");
+  return QED_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,67 @@
+// Host-side context of the QED step library and the launchers the entry points use.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+
+#include "../../include/qed.h"
+
+struct qed_ctx {
+  int device = 0;
+  qed_params_t params{};
+  std::string err;
+
+  // tables (library-owned device memory)
+  bool tables_ready = false;
+  int formula = 0;
+  double *rad_lnh64 = nullptr, *rad_S64 = nullptr;       // [256], [256*256]
+  float *rad_lnh32 = nullptr, *rad_s0sc = nullptr;       // [256], [2*256]
+  uint16_t *rad_q16 = nullptr;                           // [256*256]
+  double *pair_L64 = nullptr, *pair_S64 = nullptr;       // [512], [256*256]
+  float *pair_L32 = nullptr, *pair_s0sc = nullptr;       // [512], [2*256]
+  uint16_t *pair_q16 = nullptr;
+  double *tab_work = nullptr;                            // quadrature scratch
+  size_t tab_work_elems = 0;
+
+  // counters and ids
+  unsigned long long *d_counters = nullptr;              // qed_counters_t layout
+  uint64_t *d_next_id = nullptr;
+
+  // emitter list produced by qed_gather_push
+  int64_t reserved = 0;
+  int32_t *em_idx = nullptr;
+  double *em_fld = nullptr;      // 6 * reserved doubles (float-packed for f32 species)
+  double *em_rem = nullptr;
+  int64_t *d_n_emit = nullptr;
+  const void *em_owner = nullptr;   // species (x pointer) the list belongs to
+  int em_dtype = -1;
+  int em_charge = 0;
+  double em_dt = 0.0;
+
+  // decoupled look-back scan state
+  uint32_t *d_ticket = nullptr;
+  uint64_t *d_status = nullptr;
+  int64_t status_len = 0;
+
+  int n_cu = 256;
+};
+
+namespace qed {
+hipError_t launch_build_tables(qed_ctx *c, int formula, hipStream_t s);
+}
+
+namespace qed {
+hipError_t launch_gather_push(qed_ctx *c, const qed_fields_t *f, const qed_species_t *sp, int charge,
+                              double dt, hipStream_t st);
+hipError_t launch_emit(qed_ctx *c, const qed_species_t *lep, const qed_species_t *ph, int64_t step,
+                       hipStream_t st);
+hipError_t launch_pairs(qed_ctx *c, const qed_fields_t *f, const qed_species_t *ph,
+                        const qed_species_t *el, const qed_species_t *po, double dt, int64_t step,
+                        hipStream_t st);
+hipError_t launch_compact(qed_ctx *c, const qed_species_t *sp, hipStream_t st);
+hipError_t launch_init_tau(qed_ctx *c, const qed_species_t *sp, int64_t step, hipStream_t st);
+hipError_t launch_standing_wave(float *grid, int n, double L, double a0, double t, hipStream_t st);
+hipError_t launch_sample(qed_ctx *c, const double *chi, const double *gamma, const uint64_t *id,
+                         int64_t n, int precision, int64_t step, float *lnw, float *xi, float *lnwp,
+                         hipStream_t st);
+}  // namespace qed

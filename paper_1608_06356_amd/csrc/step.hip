@@ -1,0 +1,799 @@
+// Kernels of the QED Monte Carlo step on gfx950.
+//
+//   k_gather_push  every lepton: field, Boris push, x advance, chi (Eq. 2, float64),
+//                  rate, optical depth; emitters appended (index order) to a list
+//   k_emit         every emitter: inverse-CDF xi (Eq. 7), infrared cut, recoil,
+//                  further events within the step, photons appended in order
+//   k_pairs        every photon: chi_ph (Eq. 3), pair rate (Eq. 6), optical depth,
+//                  electron/positron appended at the same rank, photon killed
+//   k_compact      stable in-place removal of dead particles
+// Every append is a wave ballot / workgroup scan plus a single-pass decoupled
+// look-back across workgroups, so output order never depends on scheduling.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "internal.h"
+#include "lookup.h"
+#include "qed_device.h"
+
+namespace qed {
+
+constexpr int kKmaxMax = 4;
+
+struct SpeciesDev {
+  void *x, *y, *z, *px, *py, *pz;
+  double *tau;
+  uint64_t *id;
+  int64_t cap;
+  int64_t *count;
+};
+
+struct FieldDev {
+  int kind, nx, ny, nz;
+  const float *grid;
+  double dx, dy, dz;
+  double E[3], B[3];
+  const float *pE[3], *pB[3];
+};
+
+struct ScanDev {
+  uint32_t *ticket;
+  uint64_t *status;
+};
+
+// --------------------------------------------------------------- fields
+template <typename R>
+__device__ __forceinline__ void wrap_coord(R &x, R L) {
+  if (x < (R)0) x += L; else if (x >= L) x -= L;
+}
+
+template <typename R>
+__device__ __forceinline__ void weights_tsc(R x, R d, int n, int &j, R w[3]) {
+  const R g = x / d;
+  const R jf = floor(g + (R)0.5);
+  const R t = g - jf;
+  w[0] = (R)0.5 * ((R)0.5 - t) * ((R)0.5 - t);
+  w[1] = (R)0.75 - t * t;
+  w[2] = (R)0.5 * ((R)0.5 + t) * ((R)0.5 + t);
+  int jj = (int)jf;
+  j = jj < 0 ? 0 : (jj > n ? n : jj);
+}
+
+// Quadratic-spline (TSC) gather on the periodic collocated grid.
+template <typename R>
+__device__ __forceinline__ void gather_grid(const FieldDev &f, R x, R y, R z, R F[6]) {
+  int jx, jy, jz;
+  R wx[3], wy[3], wz[3];
+  weights_tsc<R>(x, (R)f.dx, f.nx, jx, wx);
+  weights_tsc<R>(y, (R)f.dy, f.ny, jy, wy);
+  weights_tsc<R>(z, (R)f.dz, f.nz, jz, wz);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) F[c] = (R)0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int iz = (jz + c - 1 + f.nz) % f.nz;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const int iy = (jy + b - 1 + f.ny) % f.ny;
+      const R wyz = wy[b] * wz[c];
+      const float *row = f.grid + ((int64_t)iz * f.ny + iy) * (int64_t)f.nx * 6;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int ix = (jx + a - 1 + f.nx) % f.nx;
+        const float2 *p2 = reinterpret_cast<const float2 *>(row + (int64_t)ix * 6);
+        const float2 v0 = p2[0], v1 = p2[1], v2 = p2[2];
+        const R w = wx[a] * wyz;
+        F[0] += w * (R)v0.x; F[1] += w * (R)v0.y; F[2] += w * (R)v1.x;
+        F[3] += w * (R)v1.y; F[4] += w * (R)v2.x; F[5] += w * (R)v2.y;
+      }
+    }
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void field_at(const FieldDev &f, int64_t i, R x, R y, R z, R F[6]) {
+  if (f.kind == QED_FIELD_UNIFORM) {
+    F[0] = (R)f.E[0]; F[1] = (R)f.E[1]; F[2] = (R)f.E[2];
+    F[3] = (R)f.B[0]; F[4] = (R)f.B[1]; F[5] = (R)f.B[2];
+  } else if (f.kind == QED_FIELD_GRID) {
+    gather_grid<R>(f, x, y, z, F);
+  } else {
+    F[0] = (R)f.pE[0][i]; F[1] = (R)f.pE[1][i]; F[2] = (R)f.pE[2][i];
+    F[3] = (R)f.pB[0][i]; F[4] = (R)f.pB[1][i]; F[5] = (R)f.pB[2][i];
+  }
+}
+
+__device__ __forceinline__ void count_add(unsigned long long *c, int which, uint32_t v) {
+  // one atomic per wave
+  const uint32_t lane = threadIdx.x & 63;
+  uint32_t s = v;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0 && s) atomicAdd(&c[which], (unsigned long long)s);
+}
+
+// Workgroup: obtain a tile id from the ticket (thread 0) and broadcast.
+__device__ __forceinline__ uint32_t next_tile(uint32_t *ticket, uint32_t *lds) {
+  __syncthreads();
+  if (threadIdx.x == 0) *lds = atomicAdd(ticket, 1u);
+  __syncthreads();
+  return *lds;
+}
+
+// Exclusive device-wide offset of this workgroup's tile given its per-thread count.
+__device__ __forceinline__ uint64_t tile_offset(uint32_t tile, uint32_t agg, const ScanDev &sc,
+                                                unsigned long long *counters, uint64_t *lds64) {
+  if (threadIdx.x < 64) {
+    const uint64_t e = lookback_scan(sc.status, tile, agg, &counters[cScanTimeout]);
+    if (threadIdx.x == 0) *lds64 = e;
+  }
+  __syncthreads();
+  return *lds64;
+}
+
+// ========================================================= gather / push
+template <typename R>
+struct GPArgs {
+  SpeciesDev sp;
+  FieldDev f;
+  const R *lnh;          // rad ln h table (float32 or float64 copy)
+  R q, dt;
+  double dtd;
+  int32_t *em_idx;
+  R *em_fld;             // 6 planes of em_cap
+  double *em_chi, *em_w, *em_rem;
+  int64_t em_cap;
+  int64_t *n_emit;
+  ScanDev sc;
+  unsigned long long *counters;
+};
+
+constexpr int kGPThreads = 256, kGPItems = 4, kGPTile = kGPThreads * kGPItems;
+
+template <typename R>
+__global__ __launch_bounds__(kGPThreads) void k_gather_push(GPArgs<R> a) {
+  __shared__ R lnh_s[kRadNChi];
+  __shared__ uint32_t scan_s[16];
+  __shared__ uint32_t tile_s;
+  __shared__ uint64_t off_s;
+  for (int k = threadIdx.x; k < kRadNChi; k += blockDim.x) lnh_s[k] = a.lnh[k];
+  const uint32_t tile = next_tile(a.sc.ticket, &tile_s);
+  const int64_t n = *a.sp.count;
+  const int64_t base = (int64_t)tile * kGPTile;
+  if (base >= n) {
+    if (tile == 0 && threadIdx.x == 0) *a.n_emit = 0;
+    return;
+  }
+  R *X = (R *)a.sp.x, *Y = (R *)a.sp.y, *Z = (R *)a.sp.z;
+  R *PX = (R *)a.sp.px, *PY = (R *)a.sp.py, *PZ = (R *)a.sp.pz;
+  const R Lx = (R)(a.f.dx * a.f.nx), Ly = (R)(a.f.dy * a.f.ny), Lz = (R)(a.f.dz * a.f.nz);
+
+  uint32_t flags = 0, nflag = 0, nnan = 0, nrange = 0;
+  R fld[kGPItems][6];
+  double chi_e[kGPItems], w_e[kGPItems], rem_e[kGPItems];
+  const int64_t i0 = base + (int64_t)threadIdx.x * kGPItems;
+#pragma unroll
+  for (int it = 0; it < kGPItems; ++it) {
+    const int64_t i = i0 + it;
+    if (i >= n) break;
+    R x = X[i], y = Y[i], z = Z[i];
+    R px = PX[i], py = PY[i], pz = PZ[i];
+    double tau = a.sp.tau[i];
+    R F[6];
+    field_at<R>(a.f, i, x, y, z, F);
+    boris<R>(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5], a.q, a.dt);
+    const R g = sqrt((R)1 + px * px + py * py + pz * pz);
+    x += px / g * a.dt; y += py / g * a.dt; z += pz / g * a.dt;
+    if (a.f.kind == QED_FIELD_GRID) { wrap_coord<R>(x, Lx); wrap_coord<R>(y, Ly); wrap_coord<R>(z, Lz); }
+    X[i] = x; Y[i] = y; Z[i] = z; PX[i] = px; PY[i] = py; PZ[i] = pz;
+    const double chi = chi_lepton(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5]);
+    double W = 0.0;
+    if (isfinite(chi)) {
+      nrange += chi > kRadChiMax;
+      W = kRateUnit * (double)(h_rad<R>((R)chi, lnh_s) / g);
+    } else {
+      ++nnan;
+    }
+    if (W > 0.0 && tau <= W * a.dtd) {
+      flags |= 1u << it;
+      ++nflag;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) fld[it][c] = F[c];
+      chi_e[it] = chi;
+      w_e[it] = W;
+      rem_e[it] = a.dtd - tau / W;
+    } else {
+      a.sp.tau[i] = tau - W * a.dtd;
+    }
+  }
+  count_add(a.counters, cNanChi, nnan);
+  count_add(a.counters, cChiRange, nrange);
+
+  uint32_t total;
+  const uint32_t off = block_exclusive(nflag, scan_s, &total);
+  const uint64_t toff = tile_offset(tile, total, a.sc, a.counters, &off_s);
+  uint64_t r = toff + off;
+#pragma unroll
+  for (int it = 0; it < kGPItems; ++it) {
+    if (flags & (1u << it)) {
+      a.em_idx[r] = (int32_t)(i0 + it);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) a.em_fld[c * a.em_cap + r] = fld[it][c];
+      a.em_chi[r] = chi_e[it];
+      a.em_w[r] = w_e[it];
+      a.em_rem[r] = rem_e[it];
+      ++r;
+    }
+  }
+  const int64_t last = (n - 1) / kGPTile;
+  if ((int64_t)tile == last && threadIdx.x == 0) *a.n_emit = (int64_t)(toff + total);
+}
+
+// ================================================================ emit
+template <typename R>
+struct EmitArgs {
+  SpeciesDev lep, ph;
+  const R *lnh;
+  const double *S64;           // float64 quantiles (R = double)
+  const uint16_t *q16;         // 16-bit quantiles (R = float)
+  const float *s0sc;
+  const int32_t *em_idx;
+  const R *em_fld;
+  const double *em_chi, *em_w, *em_rem;
+  int64_t em_cap;
+  const int64_t *n_emit;
+  uint64_t *next_id;
+  uint32_t seed;
+  int kmax;
+  int recoil;
+  uint64_t step;
+  ScanDev sc;
+  unsigned long long *counters;
+};
+
+constexpr int kEmitThreads = 1024;
+
+template <typename R, typename Tab>
+__device__ void emit_tile(const EmitArgs<R> &a, const Tab &tab, const R *lnh, uint32_t tile,
+                          uint32_t *scan_s, uint64_t *off_s, int64_t n_em, int64_t ph_count0,
+                          uint64_t id0) {
+  const int64_t r = (int64_t)tile * kEmitThreads + threadIdx.x;
+  const bool valid = r < n_em;
+  R gph[kKmaxMax];
+  double tph[kKmaxMax];
+  uint32_t nacc = 0, nev = 0, nrej = 0, ncap = 0;
+  R nx = 0, ny = 0, nz = 0, x = 0, y = 0, z = 0;
+  if (valid) {
+    const int64_t i = a.em_idx[r];
+    R F[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) F[c] = a.em_fld[c * a.em_cap + r];
+    double chi = a.em_chi[r], W = a.em_w[r], rem = a.em_rem[r];
+    R *PX = (R *)a.lep.px, *PY = (R *)a.lep.py, *PZ = (R *)a.lep.pz;
+    R px = PX[i], py = PY[i], pz = PZ[i];
+    x = ((R *)a.lep.x)[i]; y = ((R *)a.lep.y)[i]; z = ((R *)a.lep.z)[i];
+    const uint64_t id = a.lep.id[i];
+    const R pa = sqrt(px * px + py * py + pz * pz);
+    if (pa > (R)0) { nx = px / pa; ny = py / pa; nz = pz / pa; }
+    R g = sqrt((R)1 + px * px + py * py + pz * pz);
+    double tau = 0.0;
+    bool recoiled = false;
+    int k = 0;
+    while (true) {
+      const uint4 u = stream4(id, a.seed, a.step, kLeptonEvent, (uint32_t)k);
+      R xi, om;
+      sample_rad<R>(tab, (R)chi, unit<R>(u.x), unit<R>(u.z), xi, om);
+      const R gp = xi * g;
+      ++nev;
+      if (gp >= (R)2) {
+#pragma unroll
+        for (int s = 0; s < kKmaxMax; ++s)
+          if (s == (int)nacc) { gph[s] = gp; tph[s] = -log(unit<double>(u.w)); }
+        ++nacc;
+        if (a.recoil) {
+          const R gn = fmax(om * g, (R)1);
+          const R pm = sqrt(fmax(gn * gn - (R)1, (R)0));
+          px = nx * pm; py = ny * pm; pz = nz * pm;
+          g = gn;
+          recoiled = true;
+          chi = chi_lepton(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5]);
+          W = isfinite(chi) ? kRateUnit * (double)(h_rad<R>((R)chi, lnh) / g) : 0.0;
+        }
+      } else {
+        ++nrej;
+      }
+      tau = -log(unit<double>(u.y));
+      ++k;
+      const bool again = W > 0.0 && tau <= W * rem;
+      if (!again) break;
+      if (k >= a.kmax) { ++ncap; break; }
+      rem -= tau / W;
+    }
+    a.lep.tau[i] = tau - W * rem;
+    if (recoiled) { PX[i] = px; PY[i] = py; PZ[i] = pz; }
+  }
+  count_add(a.counters, cEvents, nev);
+  count_add(a.counters, cRejected, nrej);
+  count_add(a.counters, cCapped, ncap);
+  count_add(a.counters, cPhotons, nacc);
+
+  uint32_t total;
+  const uint32_t off = block_exclusive(nacc, scan_s, &total);
+  const uint64_t toff = tile_offset(tile, total, a.sc, a.counters, off_s);
+  R *X = (R *)a.ph.x, *Y = (R *)a.ph.y, *Z = (R *)a.ph.z;
+  R *KX = (R *)a.ph.px, *KY = (R *)a.ph.py, *KZ = (R *)a.ph.pz;
+  uint32_t ndrop = 0;
+#pragma unroll
+  for (int s = 0; s < kKmaxMax; ++s) {
+    if (s < (int)nacc) {
+      const uint64_t rank = toff + off + s;
+      const int64_t j = ph_count0 + (int64_t)rank;
+      if (j < a.ph.cap) {
+        X[j] = x; Y[j] = y; Z[j] = z;
+        KX[j] = nx * gph[s]; KY[j] = ny * gph[s]; KZ[j] = nz * gph[s];
+        a.ph.tau[j] = tph[s];
+        a.ph.id[j] = id0 + rank;
+      } else {
+        ++ndrop;
+      }
+    }
+  }
+  count_add(a.counters, cDropped, ndrop);
+  const int64_t last = (n_em - 1) / kEmitThreads;
+  if ((int64_t)tile == last && threadIdx.x == 0) {
+    const int64_t tot = (int64_t)(toff + total);
+    *a.ph.count = ph_count0 + tot < a.ph.cap ? ph_count0 + tot : a.ph.cap;
+    *a.next_id = id0 + (uint64_t)tot;
+  }
+}
+
+// float path: 16-bit quantile table + float32 ln h staged in LDS
+__global__ __launch_bounds__(kEmitThreads) void k_emit_f32(EmitArgs<float> a) {
+  __shared__ uint4 q_s[kRadNChi * kNU / 8];
+  __shared__ float s0sc_s[2 * kRadNChi];
+  __shared__ float lnh_s[kRadNChi];
+  __shared__ uint32_t scan_s[16];
+  __shared__ uint32_t tile_s;
+  __shared__ uint64_t off_s;
+  const int64_t n_em = *a.n_emit;
+  const int64_t ph0 = *a.ph.count;
+  const uint64_t id0 = *a.next_id;
+  if (n_em == 0) return;
+  const uint4 *gq = reinterpret_cast<const uint4 *>(a.q16);
+  for (int k = threadIdx.x; k < kRadNChi * kNU / 8; k += blockDim.x) q_s[k] = gq[k];
+  for (int k = threadIdx.x; k < 2 * kRadNChi; k += blockDim.x) s0sc_s[k] = a.s0sc[k];
+  for (int k = threadIdx.x; k < kRadNChi; k += blockDim.x) lnh_s[k] = a.lnh[k];
+  const RowQ16 tab{reinterpret_cast<const uint16_t *>(q_s), s0sc_s};
+  while (true) {
+    const uint32_t tile = next_tile(a.sc.ticket, &tile_s);
+    if ((int64_t)tile * kEmitThreads >= n_em) break;
+    emit_tile<float>(a, tab, lnh_s, tile, scan_s, &off_s, n_em, ph0, id0);
+  }
+}
+
+// double path: float64 master tables read through the caches
+__global__ __launch_bounds__(kEmitThreads) void k_emit_f64(EmitArgs<double> a) {
+  __shared__ double lnh_s[kRadNChi];
+  __shared__ uint32_t scan_s[16];
+  __shared__ uint32_t tile_s;
+  __shared__ uint64_t off_s;
+  const int64_t n_em = *a.n_emit;
+  const int64_t ph0 = *a.ph.count;
+  const uint64_t id0 = *a.next_id;
+  if (n_em == 0) return;
+  for (int k = threadIdx.x; k < kRadNChi; k += blockDim.x) lnh_s[k] = a.lnh[k];
+  const RowF64 tab{a.S64};
+  while (true) {
+    const uint32_t tile = next_tile(a.sc.ticket, &tile_s);
+    if ((int64_t)tile * kEmitThreads >= n_em) break;
+    emit_tile<double>(a, tab, lnh_s, tile, scan_s, &off_s, n_em, ph0, id0);
+  }
+}
+
+// ================================================================ pairs
+template <typename R>
+struct PairArgs {
+  SpeciesDev ph, el, po;
+  FieldDev f;
+  const R *L;
+  const double *S64;
+  const uint16_t *q16;
+  const float *s0sc;
+  R dt;
+  double dtd;
+  int move;
+  uint64_t *next_id;
+  uint32_t seed;
+  uint64_t step;
+  ScanDev sc;
+  unsigned long long *counters;
+};
+
+constexpr int kPairThreads = 1024;
+
+template <typename R, typename Tab>
+__device__ void pair_tile(const PairArgs<R> &a, const Tab &tab, const R *L, uint32_t tile,
+                          uint32_t *scan_s, uint64_t *off_s, int64_t n, int64_t e0, int64_t p0,
+                          uint64_t id0) {
+  const int64_t i = (int64_t)tile * kPairThreads + threadIdx.x;
+  uint32_t ev = 0, nrange = 0, nnan = 0;
+  R x = 0, y = 0, z = 0, kxh = 0, kyh = 0, kzh = 0, ge = 0, gpos = 0;
+  double te = 0, tp = 0;
+  if (i < n) {
+    R *X = (R *)a.ph.x, *Y = (R *)a.ph.y, *Z = (R *)a.ph.z;
+    const R kx = ((R *)a.ph.px)[i], ky = ((R *)a.ph.py)[i], kz = ((R *)a.ph.pz)[i];
+    x = X[i]; y = Y[i]; z = Z[i];
+    const R gph = sqrt(kx * kx + ky * ky + kz * kz);
+    if (gph > (R)0) { kxh = kx / gph; kyh = ky / gph; kzh = kz / gph; }
+    if (a.move) {
+      x += kxh * a.dt; y += kyh * a.dt; z += kzh * a.dt;
+      if (a.f.kind == QED_FIELD_GRID) {
+        wrap_coord<R>(x, (R)(a.f.dx * a.f.nx)); wrap_coord<R>(y, (R)(a.f.dy * a.f.ny));
+        wrap_coord<R>(z, (R)(a.f.dz * a.f.nz));
+      }
+      X[i] = x; Y[i] = y; Z[i] = z;
+    }
+    R F[6];
+    field_at<R>(a.f, i, x, y, z, F);
+    const double chi = chi_photon(kx, ky, kz, F[0], F[1], F[2], F[3], F[4], F[5]);
+    double W = 0.0;
+    if (isfinite(chi)) {
+      nrange += chi > kPairChiMax;
+      if (gph >= (R)2) W = kRateUnit * (double)(h_pair<R>((R)chi, L) / gph);
+    } else {
+      ++nnan;
+    }
+    const double tau = a.ph.tau[i];
+    if (W > 0.0 && tau <= W * a.dtd) {
+      ev = 1;
+      const uint64_t id = a.ph.id[i];
+      const uint4 u = stream4(id, a.seed, a.step, kPhotonEvent, 0u);
+      R xh, omh;
+      sample_pair_half<R>(tab, (R)chi, unit<R>(u.x), unit<R>(u.y), xh, omh);
+      const bool flip = u.y & 1u;
+      const R xe = flip ? omh : xh, xp = flip ? xh : omh;
+      ge = xe * gph;
+      gpos = xp * gph;
+      te = -log(unit<double>(u.z));
+      tp = -log(unit<double>(u.w));
+      a.ph.id[i] = kDeadId;
+    } else {
+      a.ph.tau[i] = tau - W * a.dtd;
+    }
+  }
+  count_add(a.counters, cChiRange, nrange);
+  count_add(a.counters, cNanChi, nnan);
+  count_add(a.counters, cPairs, ev);
+  uint32_t total;
+  const uint32_t off = block_exclusive(ev, scan_s, &total);
+  const uint64_t toff = tile_offset(tile, total, a.sc, a.counters, off_s);
+  uint32_t ndrop = 0;
+  if (ev) {
+    const uint64_t rank = toff + off;
+    const int64_t je = e0 + (int64_t)rank, jp = p0 + (int64_t)rank;
+    if (je < a.el.cap && jp < a.po.cap) {
+      const R pe = sqrt(fmax(ge * ge - (R)1, (R)0)), pp = sqrt(fmax(gpos * gpos - (R)1, (R)0));
+      ((R *)a.el.x)[je] = x; ((R *)a.el.y)[je] = y; ((R *)a.el.z)[je] = z;
+      ((R *)a.el.px)[je] = kxh * pe; ((R *)a.el.py)[je] = kyh * pe; ((R *)a.el.pz)[je] = kzh * pe;
+      a.el.tau[je] = te; a.el.id[je] = id0 + 2 * rank;
+      ((R *)a.po.x)[jp] = x; ((R *)a.po.y)[jp] = y; ((R *)a.po.z)[jp] = z;
+      ((R *)a.po.px)[jp] = kxh * pp; ((R *)a.po.py)[jp] = kyh * pp; ((R *)a.po.pz)[jp] = kzh * pp;
+      a.po.tau[jp] = tp; a.po.id[jp] = id0 + 2 * rank + 1;
+    } else {
+      ndrop = 2;
+    }
+  }
+  count_add(a.counters, cDropped, ndrop);
+  const int64_t last = (n - 1) / kPairThreads;
+  if ((int64_t)tile == last && threadIdx.x == 0) {
+    const int64_t tot = (int64_t)(toff + total);
+    *a.el.count = e0 + tot < a.el.cap ? e0 + tot : a.el.cap;
+    *a.po.count = p0 + tot < a.po.cap ? p0 + tot : a.po.cap;
+    *a.next_id = id0 + 2 * (uint64_t)tot;
+  }
+}
+
+__global__ __launch_bounds__(kPairThreads) void k_pairs_f32(PairArgs<float> a) {
+  __shared__ uint4 q_s[kPairNCdf * kNU / 8];
+  __shared__ float s0sc_s[2 * kPairNCdf];
+  __shared__ float L_s[kPairNRate];
+  __shared__ uint32_t scan_s[16];
+  __shared__ uint32_t tile_s;
+  __shared__ uint64_t off_s;
+  const int64_t n = *a.ph.count;
+  if (n == 0) return;
+  const int64_t e0 = *a.el.count, p0 = *a.po.count;
+  const uint64_t id0 = *a.next_id;
+  const uint4 *gq = reinterpret_cast<const uint4 *>(a.q16);
+  for (int k = threadIdx.x; k < kPairNCdf * kNU / 8; k += blockDim.x) q_s[k] = gq[k];
+  for (int k = threadIdx.x; k < 2 * kPairNCdf; k += blockDim.x) s0sc_s[k] = a.s0sc[k];
+  for (int k = threadIdx.x; k < kPairNRate; k += blockDim.x) L_s[k] = a.L[k];
+  const RowQ16 tab{reinterpret_cast<const uint16_t *>(q_s), s0sc_s};
+  while (true) {
+    const uint32_t tile = next_tile(a.sc.ticket, &tile_s);
+    if ((int64_t)tile * kPairThreads >= n) break;
+    pair_tile<float>(a, tab, L_s, tile, scan_s, &off_s, n, e0, p0, id0);
+  }
+}
+
+__global__ __launch_bounds__(kPairThreads) void k_pairs_f64(PairArgs<double> a) {
+  __shared__ double L_s[kPairNRate];
+  __shared__ uint32_t scan_s[16];
+  __shared__ uint32_t tile_s;
+  __shared__ uint64_t off_s;
+  const int64_t n = *a.ph.count;
+  if (n == 0) return;
+  const int64_t e0 = *a.el.count, p0 = *a.po.count;
+  const uint64_t id0 = *a.next_id;
+  for (int k = threadIdx.x; k < kPairNRate; k += blockDim.x) L_s[k] = a.L[k];
+  const RowF64 tab{a.S64};
+  while (true) {
+    const uint32_t tile = next_tile(a.sc.ticket, &tile_s);
+    if ((int64_t)tile * kPairThreads >= n) break;
+    pair_tile<double>(a, tab, L_s, tile, scan_s, &off_s, n, e0, p0, id0);
+  }
+}
+
+// ============================================================== compact
+constexpr int kCThreads = 256, kCItems = 4, kCTile = kCThreads * kCItems;
+
+template <typename R>
+__global__ __launch_bounds__(kCThreads) void k_compact(SpeciesDev sp, ScanDev sc,
+                                                       unsigned long long *counters) {
+  __shared__ uint32_t scan_s[16];
+  __shared__ uint32_t tile_s;
+  __shared__ uint64_t off_s;
+  const uint32_t tile = next_tile(sc.ticket, &tile_s);
+  const int64_t n = *sp.count;
+  const int64_t base = (int64_t)tile * kCTile;
+  if (base >= n) return;
+  R *A[6] = {(R *)sp.x, (R *)sp.y, (R *)sp.z, (R *)sp.px, (R *)sp.py, (R *)sp.pz};
+  R v[kCItems][6];
+  double tau[kCItems];
+  uint64_t id[kCItems];
+  uint32_t alive = 0, na = 0;
+  const int64_t i0 = base + (int64_t)threadIdx.x * kCItems;
+#pragma unroll
+  for (int it = 0; it < kCItems; ++it) {
+    const int64_t i = i0 + it;
+    id[it] = kDeadId;
+    if (i < n) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) v[it][c] = A[c][i];
+      tau[it] = sp.tau[i];
+      id[it] = sp.id[i];
+    }
+    if (id[it] != kDeadId) { alive |= 1u << it; ++na; }
+  }
+  __threadfence();   // every load of the tile has completed before its count is published
+  uint32_t total;
+  const uint32_t off = block_exclusive(na, scan_s, &total);
+  const uint64_t toff = tile_offset(tile, total, sc, counters, &off_s);
+  uint64_t r = toff + off;
+#pragma unroll
+  for (int it = 0; it < kCItems; ++it) {
+    if (alive & (1u << it)) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) A[c][r] = v[it][c];
+      sp.tau[r] = tau[it];
+      sp.id[r] = id[it];
+      ++r;
+    }
+  }
+  const int64_t last = (n - 1) / kCTile;
+  if ((int64_t)tile == last && threadIdx.x == 0) {
+    const int64_t nn = (int64_t)(toff + total);
+    atomicAdd(&counters[cCompacted], (unsigned long long)(n - nn));
+    *sp.count = nn;
+  }
+}
+
+// ================================================================ misc
+__global__ void k_zero_scan(uint32_t *ticket, uint64_t *status, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i == 0) *ticket = 0;
+  if (i < n) status[i] = 0;
+}
+
+__global__ void k_init_tau(const uint64_t *id, double *tau, const int64_t *count, uint32_t seed,
+                           uint64_t step, int64_t cap) {
+  const int64_t n = *count;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n && i < cap;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint4 u = stream4(id[i], seed, step, kInitTau, 0u);
+    tau[i] = -log(unit<double>(u.x));
+  }
+}
+
+__global__ void k_standing_wave(float *grid, int n, double dx, double a0, double t) {
+  const int64_t total = (int64_t)n * n * n;
+  const double ct = cos(t), st = sin(t);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int ix = (int)(i % n);
+    const double x = ix * dx;
+    const double ca = a0 * cos(x), sa = a0 * sin(x);
+    float2 *o = reinterpret_cast<float2 *>(grid + i * 6);
+    o[0] = make_float2(0.0f, (float)(ca * ct));
+    o[1] = make_float2((float)(ca * st), 0.0f);
+    o[2] = make_float2((float)(sa * ct), (float)(sa * st));
+  }
+}
+
+template <typename R, typename Tab>
+__device__ void sample_one(const Tab &tab, const R *lnh, const R *L, double chi, double gamma,
+                           uint64_t id, uint32_t seed, uint64_t step, float *lnw, float *xi_out,
+                           float *lnwp, int64_t i) {
+  const R h = h_rad<R>((R)chi, lnh);
+  lnw[i] = (float)log(kRateUnit * (double)h / gamma);
+  const uint4 u = stream4(id, seed, step, kLeptonEvent, 0u);
+  R xi, om;
+  sample_rad<R>(tab, (R)chi, unit<R>(u.x), unit<R>(u.z), xi, om);
+  xi_out[i] = (float)xi;
+  if (lnwp) {
+    const R hp = gamma >= 2.0 ? h_pair<R>((R)chi, L) : (R)0;
+    lnwp[i] = (float)log(kRateUnit * (double)hp / gamma);
+  }
+}
+
+__global__ void k_sample_f64(const double *chi, const double *gamma, const uint64_t *id, int64_t n,
+                             const double *lnh, const double *L, const double *S64, uint32_t seed,
+                             uint64_t step, float *lnw, float *xi, float *lnwp) {
+  const RowF64 tab{S64};
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    sample_one<double>(tab, lnh, L, chi[i], gamma[i], id[i], seed, step, lnw, xi, lnwp, i);
+}
+
+__global__ void k_sample_f32(const double *chi, const double *gamma, const uint64_t *id, int64_t n,
+                             const float *lnh, const float *L, const uint16_t *q16, const float *s0sc,
+                             uint32_t seed, uint64_t step, float *lnw, float *xi, float *lnwp) {
+  const RowQ16 tab{q16, s0sc};
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    sample_one<float>(tab, lnh, L, chi[i], gamma[i], id[i], seed, step, lnw, xi, lnwp, i);
+}
+
+}  // namespace qed
+
+// =============================================================== launchers
+namespace qed {
+
+static SpeciesDev dev_species(const qed_species_t *s) {
+  return SpeciesDev{s->x, s->y, s->z, s->px, s->py, s->pz, s->tau, s->id, s->capacity, s->count};
+}
+
+static FieldDev dev_fields(const qed_fields_t *f) {
+  FieldDev d{};
+  if (!f) { d.kind = QED_FIELD_UNIFORM; return d; }
+  d.kind = f->kind; d.nx = f->nx; d.ny = f->ny; d.nz = f->nz; d.grid = f->grid;
+  d.dx = f->dx; d.dy = f->dy; d.dz = f->dz;
+  for (int c = 0; c < 3; ++c) { d.E[c] = f->E[c]; d.B[c] = f->B[c]; d.pE[c] = f->pE[c]; d.pB[c] = f->pB[c]; }
+  return d;
+}
+
+static hipError_t zero_scan(qed_ctx *c, int64_t ntiles, hipStream_t st) {
+  const int64_t n = ntiles + 1;
+  hipLaunchKernelGGL(k_zero_scan, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, c->d_ticket,
+                     c->d_status, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_push(qed_ctx *c, const qed_fields_t *f, const qed_species_t *sp, int charge,
+                              double dt, hipStream_t st) {
+  const int64_t ntiles = (sp->capacity + kGPTile - 1) / kGPTile;
+  hipError_t e = zero_scan(c, ntiles, st);
+  if (e != hipSuccess) return e;
+  const ScanDev sc{c->d_ticket, c->d_status};
+  if (sp->dtype == QED_F32) {
+    GPArgs<float> a{dev_species(sp), dev_fields(f), c->rad_lnh32, (float)charge, (float)dt, dt,
+                    c->em_idx, (float *)c->em_fld, c->em_fld + 3 * c->reserved,
+                    c->em_fld + 4 * c->reserved, c->em_rem, c->reserved, c->d_n_emit, sc,
+                    c->d_counters};
+    hipLaunchKernelGGL(k_gather_push<float>, dim3((unsigned)ntiles), dim3(kGPThreads), 0, st, a);
+  } else {
+    GPArgs<double> a{dev_species(sp), dev_fields(f), c->rad_lnh64, (double)charge, dt, dt,
+                     c->em_idx, c->em_fld, c->em_fld + 6 * c->reserved, c->em_fld + 7 * c->reserved,
+                     c->em_rem, c->reserved, c->d_n_emit, sc, c->d_counters};
+    hipLaunchKernelGGL(k_gather_push<double>, dim3((unsigned)ntiles), dim3(kGPThreads), 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_emit(qed_ctx *c, const qed_species_t *lep, const qed_species_t *ph, int64_t step,
+                       hipStream_t st) {
+  const int64_t ntiles = (lep->capacity + kEmitThreads - 1) / kEmitThreads;
+  hipError_t e = zero_scan(c, ntiles, st);
+  if (e != hipSuccess) return e;
+  const ScanDev sc{c->d_ticket, c->d_status};
+  const int recoil = (c->params.flags & QED_FLAG_NO_RECOIL) ? 0 : 1;
+  const unsigned grid = (unsigned)(ntiles < c->n_cu ? ntiles : c->n_cu);
+  if (lep->dtype == QED_F32) {
+    EmitArgs<float> a{dev_species(lep), dev_species(ph), c->rad_lnh32, c->rad_S64, c->rad_q16,
+                      c->rad_s0sc, c->em_idx, (const float *)c->em_fld, c->em_fld + 3 * c->reserved,
+                      c->em_fld + 4 * c->reserved, c->em_rem, c->reserved, c->d_n_emit,
+                      c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, sc,
+                      c->d_counters};
+    hipLaunchKernelGGL(k_emit_f32, dim3(grid), dim3(kEmitThreads), 0, st, a);
+  } else {
+    EmitArgs<double> a{dev_species(lep), dev_species(ph), c->rad_lnh64, c->rad_S64, c->rad_q16,
+                       c->rad_s0sc, c->em_idx, (const double *)c->em_fld, c->em_fld + 6 * c->reserved,
+                       c->em_fld + 7 * c->reserved, c->em_rem, c->reserved, c->d_n_emit,
+                       c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, sc,
+                       c->d_counters};
+    hipLaunchKernelGGL(k_emit_f64, dim3(grid), dim3(kEmitThreads), 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pairs(qed_ctx *c, const qed_fields_t *f, const qed_species_t *ph,
+                        const qed_species_t *el, const qed_species_t *po, double dt, int64_t step,
+                        hipStream_t st) {
+  const int64_t ntiles = (ph->capacity + kPairThreads - 1) / kPairThreads;
+  hipError_t e = zero_scan(c, ntiles, st);
+  if (e != hipSuccess) return e;
+  const ScanDev sc{c->d_ticket, c->d_status};
+  const int move = (c->params.flags & QED_FLAG_STATIC_PHOTONS) ? 0 : 1;
+  const unsigned grid = (unsigned)(ntiles < c->n_cu ? ntiles : c->n_cu);
+  if (ph->dtype == QED_F32) {
+    PairArgs<float> a{dev_species(ph), dev_species(el), dev_species(po), dev_fields(f), c->pair_L32,
+                      c->pair_S64, c->pair_q16, c->pair_s0sc, (float)dt, dt, move, c->d_next_id,
+                      c->params.seed, (uint64_t)step, sc, c->d_counters};
+    hipLaunchKernelGGL(k_pairs_f32, dim3(grid), dim3(kPairThreads), 0, st, a);
+  } else {
+    PairArgs<double> a{dev_species(ph), dev_species(el), dev_species(po), dev_fields(f), c->pair_L64,
+                       c->pair_S64, c->pair_q16, c->pair_s0sc, dt, dt, move, c->d_next_id,
+                       c->params.seed, (uint64_t)step, sc, c->d_counters};
+    hipLaunchKernelGGL(k_pairs_f64, dim3(grid), dim3(kPairThreads), 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_compact(qed_ctx *c, const qed_species_t *sp, hipStream_t st) {
+  const int64_t ntiles = (sp->capacity + kCTile - 1) / kCTile;
+  hipError_t e = zero_scan(c, ntiles, st);
+  if (e != hipSuccess) return e;
+  const ScanDev sc{c->d_ticket, c->d_status};
+  if (sp->dtype == QED_F32)
+    hipLaunchKernelGGL(k_compact<float>, dim3((unsigned)ntiles), dim3(kCThreads), 0, st,
+                       dev_species(sp), sc, c->d_counters);
+  else
+    hipLaunchKernelGGL(k_compact<double>, dim3((unsigned)ntiles), dim3(kCThreads), 0, st,
+                       dev_species(sp), sc, c->d_counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_tau(qed_ctx *c, const qed_species_t *sp, int64_t step, hipStream_t st) {
+  int64_t blocks = (sp->capacity + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_init_tau, dim3((unsigned)blocks), dim3(256), 0, st, sp->id, sp->tau,
+                     sp->count, c->params.seed, (uint64_t)step, sp->capacity);
+  return hipGetLastError();
+}
+
+hipError_t launch_standing_wave(float *grid, int n, double L, double a0, double t, hipStream_t st) {
+  const int64_t total = (int64_t)n * n * n;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_standing_wave, dim3((unsigned)blocks), dim3(256), 0, st, grid, n, L / n, a0, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample(qed_ctx *c, const double *chi, const double *gamma, const uint64_t *id,
+                         int64_t n, int precision, int64_t step, float *lnw, float *xi, float *lnwp,
+                         hipStream_t st) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  if (precision == QED_F64)
+    hipLaunchKernelGGL(k_sample_f64, dim3((unsigned)blocks), dim3(256), 0, st, chi, gamma, id, n,
+                       c->rad_lnh64, c->pair_L64, c->rad_S64, c->params.seed, (uint64_t)step, lnw,
+                       xi, lnwp);
+  else
+    hipLaunchKernelGGL(k_sample_f32, dim3((unsigned)blocks), dim3(256), 0, st, chi, gamma, id, n,
+                       c->rad_lnh32, c->pair_L32, c->rad_q16, c->rad_s0sc, c->params.seed,
+                       (uint64_t)step, lnw, xi, lnwp);
+  return hipGetLastError();
+}
+
+}  // namespace qed

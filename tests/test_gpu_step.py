@@ -1,0 +1,136 @@
+"""Parity of the GPU Monte Carlo step against the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mc, tables
+from oracle.constants import E_S
+from tests.gpu_helpers import need_gpu
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def test_init_optical_depth():
+    torch, q = need_gpu()
+    ctx = q.Context(seed=17)
+    sp = q.Species(5000, "f64")
+    ids = np.arange(10**9, 10**9 + 4321, dtype=np.uint64)
+    sp.load(np.zeros((ids.size, 3)), np.zeros((ids.size, 3)), ids=ids)
+    ctx.qed_init_optical_depth(sp, step=3)
+    got = sp.to_numpy()["tau"]
+    ref = mc.init_tau(ids, seed=17, step=3)
+    np.testing.assert_allclose(got, ref, rtol=5e-16, atol=0)   # log differs by <= 1 ulp
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_compact_bitexact(dtype):
+    torch, q = need_gpu()
+    ctx = q.Context()
+    rng = np.random.default_rng(5)
+    for n in (0, 1, 1023, 1024, 1025, 70001):
+        sp = q.Species(max(n, 1) + 17, dtype)
+        x = rng.normal(size=(n, 3))
+        p = rng.normal(size=(n, 3))
+        tau = rng.uniform(size=n)
+        ids = np.arange(n, dtype=np.uint64)
+        dead = rng.uniform(size=n) < (0.5 if n % 2 else 0.02)
+        ids[dead] = mc.DEAD_ID
+        sp.load(x, p, tau, ids)
+        ctx.qed_compact(sp)
+        st, rc = ctx.qed_get_status()
+        got = sp.to_numpy()
+        cast = (lambda a: a.astype(np.float32).astype(np.float64)) if dtype == "f32" else (lambda a: a)
+        oid, ox, op, otau = mc.compact(ids, cast(x), cast(p), tau)
+        assert sp.n() == oid.size
+        np.testing.assert_array_equal(got["id"], oid)
+        np.testing.assert_array_equal(got["x"], ox)
+        np.testing.assert_array_equal(got["p"], op)
+        np.testing.assert_array_equal(got["tau"], otau)
+        assert st["compacted"] == n - oid.size and st["scan_timeouts"] == 0
+
+
+def _uniform_run(q, ctx, rad_sampler, n_per, steps, dt=0.01, seed=0, recoil=True):
+    """Runs the three uniform-B ensembles on GPU and oracle side by side."""
+    ens = workloads.uniform_b_ensembles(n_per, seed=seed)
+    results = []
+    for k, e in enumerate(ens):
+        n = e["id"].size
+        lep = q.Species(n, "f64")
+        ph = q.Species(n * 4 * steps + 16, "f64")
+        tau0 = mc.init_tau(e["id"], seed=seed)
+        lep.load(e["x"], e["p"], tau0, e["id"])
+        nid = 10**6 * (k + 1)
+        ctx.qed_set_next_id(nid)
+        fld = q.Fields(q.QED_FIELD_UNIFORM, E=(0, 0, 0), B=(0, 0, e["b0"]))
+        E = np.zeros((n, 3))
+        B = np.tile([0.0, 0.0, e["b0"]], (n, 1))
+        ox, op, otau = e["x"].copy(), e["p"].copy(), tau0.copy()
+        oph = []
+        for s in range(steps):
+            ctx.qed_gather_push(fld, lep, -1, dt, s)
+            ctx.qed_emit_photons(lep, ph, s)
+            r = mc.lepton_step(ox, op, otau, e["id"], E, B, q=-1.0, dt=dt, step=s, seed=seed,
+                               sampler=rad_sampler, next_id=nid, recoil=recoil)
+            ox, op, otau, nid = r["x"], r["p"], r["tau"], r["next_id"]
+            oph.append(r["photons"])
+        st, rc = ctx.qed_get_status()
+        assert st["scan_timeouts"] == 0 and st["dropped"] == 0
+        results.append((lep.to_numpy(), ph.to_numpy(), dict(x=ox, p=op, tau=otau), oph, nid,
+                        ctx.qed_get_next_id()))
+    return results
+
+
+def test_uniform_field_f64_parity(rad_table_I):
+    """Three Fig. 1 ensembles, float64 state: positions, momenta, optical depths,
+    photon lists (order, ids, energies, optical depths) against the oracle."""
+    torch, q = need_gpu()
+    ctx = q.Context(seed=0, kmax=4)
+    ctx.qed_build_tables(q.QED_FORMULA_I)
+    rad = mc.RadSampler(rad_table_I, "f64")
+    for g, gph, o, oph, nid, gnid in _uniform_run(q, ctx, rad, 3000, 12):
+        np.testing.assert_allclose(g["p"], o["p"], rtol=1e-11, atol=1e-9)
+        np.testing.assert_allclose(g["x"], o["x"], rtol=1e-11, atol=1e-9)
+        np.testing.assert_allclose(g["tau"], o["tau"], rtol=1e-9, atol=1e-9)
+        ph_ref = {k: np.concatenate([p[k] for p in oph]) for k in ("x", "k", "tau", "id")}
+        assert gph["id"].size == ph_ref["id"].size and nid == gnid
+        np.testing.assert_array_equal(gph["id"], ph_ref["id"])
+        np.testing.assert_allclose(gph["p"], ph_ref["k"], rtol=1e-10, atol=1e-9)
+        np.testing.assert_allclose(gph["tau"], ph_ref["tau"], rtol=1e-12)
+        np.testing.assert_allclose(gph["x"], ph_ref["x"], rtol=1e-11, atol=1e-9)
+
+
+def test_sample_entry_point(rad_table_I, pair_table):
+    torch, q = need_gpu()
+    ctx = q.Context(seed=4)
+    ctx.qed_build_tables(q.QED_FORMULA_I)
+    inp = workloads.sampler_inputs(200000, seed=3)
+    chi = np.concatenate([inp["chi"], [1e-6, 5e-4, 1e-3, 99.9, 100.0, 300.0]])
+    gam = np.concatenate([inp["gamma"], [1e3] * 6])
+    ids = np.arange(chi.size, dtype=np.uint64)
+    dev = lambda a, dt: torch.from_numpy(a).to("cuda", dt)
+    tchi, tg = dev(chi, torch.float64), dev(gam, torch.float64)
+    tid = dev(ids.view(np.int64), torch.int64)
+    from oracle import philox
+    r = philox.stream(ids, 4, 7, philox.LEPTON_EVENT, 0)
+    u = philox.uniform(r)
+    for prec, storage, rtol_w, tol_s in ((q.QED_F64, "f64", 1e-6, 1e-10), (q.QED_F32, "q16", 2e-5, 3e-3)):
+        lnw = torch.empty(chi.size, dtype=torch.float32, device="cuda")
+        xi = torch.empty_like(lnw)
+        lnwp = torch.empty_like(lnw)
+        ctx.qed_sample(tchi, tg, tid, prec, 7, lnw, xi, lnwp)
+        torch.cuda.synchronize()
+        rs = mc.RadSampler(rad_table_I, storage)
+        ps = mc.PairSampler(pair_table, storage)
+        w_ref = rs.rate(chi, gam)
+        np.testing.assert_allclose(np.exp(lnw.cpu().numpy().astype(np.float64)), w_ref, rtol=rtol_w)
+        wp = ps.rate(chi, gam)
+        ok = wp > 1e-30
+        np.testing.assert_allclose(np.exp(lnwp.cpu().numpy().astype(np.float64))[ok], wp[ok], rtol=rtol_w * 10)
+        xr, _ = rs.sample(chi, u[:, 0], u[:, 2])
+        xg = xi.cpu().numpy().astype(np.float64)
+        # tol_s is the logit tolerance of the table copy; the output is float32
+        lim = tol_s * xr * (1 - xr) + 1.2e-7 * xr
+        assert np.all(np.abs(xg - xr) <= lim), np.max(np.abs(xg - xr) / lim)
