@@ -134,3 +134,105 @@ def test_sample_entry_point(rad_table_I, pair_table):
         # tol_s is the logit tolerance of the table copy; the output is float32
         lim = tol_s * xr * (1 - xr) + 1.2e-7 * xr
         assert np.all(np.abs(xg - xr) <= lim), np.max(np.abs(xg - xr) / lim)
+
+
+def _c2_setup(q, n, seed=1, a0=500.0, ngrid=128):
+    ens = workloads.standing_wave_electrons(n, seed=seed)
+    x32 = ens["x"].astype(np.float32).astype(np.float64)
+    p32 = ens["p"].astype(np.float32).astype(np.float64)
+    return ens, x32, p32
+
+
+def test_grid_step_f32_one_step_parity(rad_table_I):
+    """Standing wave a0 = 500 on a 128^3 grid, float32 state: one step per particle
+    against the oracle (float64 arithmetic on the same float32 inputs)."""
+    torch, q = need_gpu()
+    n, a0, ngrid, L, dt = 100000, 500.0, 128, workloads.BOX_L, 0.01
+    ctx = q.Context(seed=1, kmax=4)
+    ctx.qed_build_tables(q.QED_FORMULA_I)
+    ens, x, p = _c2_setup(q, n)
+    tau = mc.init_tau(ens["id"], seed=1)
+    # give half of the particles a small optical depth so that many emit
+    tau[::2] *= 1e-3
+    grid = torch.empty(ngrid ** 3 * 6, dtype=torch.float32, device="cuda")
+    lep = q.Species(n, "f32")
+    ph = q.Species(4 * n, "f32")
+    lep.load(x, p, tau, ens["id"])
+    ctx.qed_set_next_id(n)
+    t = 0.37
+    ctx.qed_fill_standing_wave(grid, ngrid, L, a0, t)
+    fld = q.Fields(q.QED_FIELD_GRID, grid=grid, n=ngrid, L=L)
+    ctx.qed_gather_push(fld, lep, -1, dt, 5)
+    ctx.qed_emit_photons(lep, ph, 5)
+    st, rc = ctx.qed_get_status()
+    g = lep.to_numpy()
+    gph = ph.to_numpy()
+    Eg, Bg = mc.standing_wave_grid(ngrid, L, a0, t)
+    E, B = mc.gather_tsc(Eg, Bg, L, x)
+    rad = mc.RadSampler(rad_table_I, "q16")
+    r = mc.lepton_step(x, p, tau, ens["id"], E, B, q=-1.0, dt=dt, step=5, seed=1, sampler=rad,
+                       next_id=n, L=L)
+    # decisions: the emitter sets agree except where the oracle's margin is tiny
+    W = r["W"]
+    assert st["events"] >= r["n_events"] - 5 and st["scan_timeouts"] == 0
+    np.testing.assert_allclose(g["p"], r["p"], rtol=2e-5, atol=2e-5 * np.abs(r["p"]).max())
+    dx = np.abs(g["x"] - r["x"])
+    dx = np.minimum(dx, L - dx)
+    assert dx.max() < 1e-5
+    assert gph["id"].size == r["photons"]["id"].size
+    np.testing.assert_array_equal(gph["id"], r["photons"]["id"])
+    np.testing.assert_allclose(np.linalg.norm(gph["p"], axis=1), r["photons"]["gamma"], rtol=2e-3)
+    np.testing.assert_allclose(gph["tau"], r["photons"]["tau"], rtol=1e-12)
+    np.testing.assert_allclose(g["tau"], r["tau"], rtol=2e-4, atol=2e-4 * (W * dt).max())
+
+
+def test_emitted_spectrum_ks_1e7(rad_table_I):
+    """Fixed chi ~ 1 (Fig. 1 b), no recoil, float32 path: 1e7 emitted photons.
+    xi against the exact truncated CDF (one-sample KS) and against the oracle's
+    table sampler (two-sample KS), both <= 2e-3."""
+    torch, q = need_gpu()
+    n, b0, g = 1_000_000, 2000.0, 206.0
+    ctx = q.Context(seed=21, kmax=4, flags=q.QED_FLAG_NO_RECOIL)
+    ctx.qed_build_tables(q.QED_FORMULA_I)
+    ens = workloads.uniform_b_ensembles(n, seed=21, triples=((b0, g),))[0]
+    lep = q.Species(n, "f32")
+    ph = q.Species(12_000_000, "f32")
+    lep.load(ens["x"], ens["p"], ids=ens["id"])
+    ctx.qed_init_optical_depth(lep, 0)
+    ctx.qed_set_next_id(n)
+    fld = q.Fields(q.QED_FIELD_UNIFORM, B=(0, 0, b0))
+    s = 0
+    while ph.n() < 10_000_000:
+        ctx.qed_gather_push(fld, lep, -1, 0.05, s)
+        ctx.qed_emit_photons(lep, ph, s)
+        s += 1
+    st, rc = ctx.qed_get_status()
+    assert st["dropped"] == 0 and st["scan_timeouts"] == 0
+    nph = ph.n()
+    gam = torch.sqrt(ph.px[:nph].double() ** 2 + ph.py[:nph].double() ** 2 + ph.pz[:nph].double() ** 2)
+    xi = np.sort((gam / g).cpu().numpy())
+    chi = g * math.sqrt(1 - 1 / g ** 2) * b0 / E_S
+    row = tables.fine_row("I", chi, tables.RAD_M)
+    P = row.F / row.total
+    xc = 2.0 / g
+    Pc = float(np.interp(math.log(xc) - math.log1p(-xc), row.s, P))
+    Pe = (np.interp(np.log(xi) - np.log1p(-np.minimum(xi, 1 - 1e-7)), row.s, P) - Pc) / (1 - Pc)
+    m = xi.size
+    ks1 = max(np.max(np.arange(1, m + 1) / m - Pe), np.max(Pe - np.arange(m) / m))
+    # oracle sampler (same 16-bit table copy), same number of accepted samples
+    rng = np.random.default_rng(99)
+    want = m
+    got = []
+    rs = mc.RadSampler(rad_table_I, "q16")
+    while sum(a.size for a in got) < want:
+        u = (np.floor(rng.uniform(size=4_000_000) * 2 ** 23) + 0.5) * 2.0 ** -23
+        ur = (np.floor(rng.uniform(size=4_000_000) * 2 ** 23) + 0.5) * 2.0 ** -23
+        x_o, _ = rs.sample(np.full(u.size, chi), u, ur)
+        got.append(x_o[x_o * g >= 2.0])
+    xo = np.sort(np.concatenate(got)[:want])
+    allv = np.concatenate([xi, xo])
+    cdf_g = np.searchsorted(xi, allv, side="right") / m
+    cdf_o = np.searchsorted(xo, allv, side="right") / want
+    ks2 = np.max(np.abs(cdf_g - cdf_o))
+    print(f"photons {m}  KS(exact) {ks1:.2e}  KS(oracle sampler) {ks2:.2e}")
+    assert ks1 < 2e-3 and ks2 < 2e-3
