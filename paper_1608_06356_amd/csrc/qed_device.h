@@ -125,14 +125,18 @@ __device__ __forceinline__ void boris(R &px, R &py, R &pz, R ex, R ey, R ez, R b
 // Tiles take increasing ids from an atomic ticket, so every tile a later tile
 // waits on is held by a workgroup that is already running.  Status word:
 // bits 62-63 flag (1 = tile aggregate, 2 = inclusive prefix), bits 0-61 value.
+// Flag and value travel in one 64-bit word, so the status accesses are relaxed
+// device-scope atomics: acquire/release at device scope would write back or
+// invalidate the whole (per-XCD, non-coherent) L2 on every spin.  Callers that
+// need their own loads finished before publishing wait for them explicitly.
 constexpr uint64_t kFlagAgg = 1ull << 62, kFlagPre = 2ull << 62, kValMask = (1ull << 62) - 1;
 constexpr uint32_t kSpinLimit = 1u << 24;
 
-__device__ __forceinline__ uint64_t ld_acquire(const uint64_t *p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ uint64_t ld_status(const uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void st_release(uint64_t *p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ void st_status(uint64_t *p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
@@ -147,20 +151,20 @@ __device__ uint64_t lookback_scan(uint64_t *status, uint32_t tile, uint64_t agg,
                                   unsigned long long *timeouts) {
   const int lane = threadIdx.x & 63;
   if (tile == 0) {
-    if (lane == 0) st_release(&status[0], kFlagPre | agg);
+    if (lane == 0) st_status(&status[0], kFlagPre | agg);
     return 0;
   }
-  if (lane == 0) st_release(&status[tile], kFlagAgg | agg);
+  if (lane == 0) st_status(&status[tile], kFlagAgg | agg);
   uint64_t excl = 0;
   int64_t j = (int64_t)tile - 1;
   while (true) {
     const int64_t idx = j - lane;
-    uint64_t s = idx >= 0 ? ld_acquire(&status[idx]) : kFlagPre;
+    uint64_t s = idx >= 0 ? ld_status(&status[idx]) : kFlagPre;
     uint32_t spins = 0;
     while (__any((s >> 62) == 0)) {
       if ((s >> 62) == 0) {
         __builtin_amdgcn_s_sleep(1);
-        s = ld_acquire(&status[idx]);
+        s = ld_status(&status[idx]);
         if (++spins > kSpinLimit && (s >> 62) == 0) {
           atomicAdd(timeouts, 1ull);
           s = kFlagPre;              // give up: treat as zero so the wave exits
@@ -176,7 +180,7 @@ __device__ uint64_t lookback_scan(uint64_t *status, uint32_t tile, uint64_t agg,
     excl += wave_sum_u64(s & kValMask);
     j -= 64;
   }
-  if (lane == 0) st_release(&status[tile], kFlagPre | (excl + agg));
+  if (lane == 0) st_status(&status[tile], kFlagPre | (excl + agg));
   return excl;
 }
 

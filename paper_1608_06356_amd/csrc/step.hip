@@ -59,6 +59,12 @@ __device__ __forceinline__ void weights_tsc(R x, R d, int n, int &j, R w[3]) {
   j = jj < 0 ? 0 : (jj > n ? n : jj);
 }
 
+// j in [-1, n+1] -> [0, n)
+__device__ __forceinline__ int wrap_index(int j, int n) {
+  j = j < 0 ? j + n : j;
+  return j >= n ? j - n : j;
+}
+
 // Quadratic-spline (TSC) gather on the periodic collocated grid.
 template <typename R>
 __device__ __forceinline__ void gather_grid(const FieldDev &f, R x, R y, R z, R F[6]) {
@@ -71,15 +77,15 @@ __device__ __forceinline__ void gather_grid(const FieldDev &f, R x, R y, R z, R 
   for (int c = 0; c < 6; ++c) F[c] = (R)0;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const int iz = (jz + c - 1 + f.nz) % f.nz;
+    const int iz = wrap_index(jz + c - 1, f.nz);
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-      const int iy = (jy + b - 1 + f.ny) % f.ny;
+      const int iy = wrap_index(jy + b - 1, f.ny);
       const R wyz = wy[b] * wz[c];
       const float *row = f.grid + ((int64_t)iz * f.ny + iy) * (int64_t)f.nx * 6;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        const int ix = (jx + a - 1 + f.nx) % f.nx;
+        const int ix = wrap_index(jx + a - 1, f.nx);
         const float2 *p2 = reinterpret_cast<const float2 *>(row + (int64_t)ix * 6);
         const float2 v0 = p2[0], v1 = p2[1], v2 = p2[2];
         const R w = wx[a] * wyz;
@@ -148,8 +154,11 @@ struct GPArgs {
   unsigned long long *counters;
 };
 
-constexpr int kGPThreads = 256, kGPItems = 4, kGPTile = kGPThreads * kGPItems;
+constexpr int kGPThreads = 256, kGPTile = kGPThreads;
 
+// One particle per thread; a tile is one workgroup.  Emitters (optical depth
+// exhausted within the step) are appended in index order with the fields,
+// chi, rate and remaining time of their first event.
 template <typename R>
 __global__ __launch_bounds__(kGPThreads) void k_gather_push(GPArgs<R> a) {
   __shared__ R lnh_s[kRadNChi];
@@ -166,42 +175,33 @@ __global__ __launch_bounds__(kGPThreads) void k_gather_push(GPArgs<R> a) {
   }
   R *X = (R *)a.sp.x, *Y = (R *)a.sp.y, *Z = (R *)a.sp.z;
   R *PX = (R *)a.sp.px, *PY = (R *)a.sp.py, *PZ = (R *)a.sp.pz;
-  const R Lx = (R)(a.f.dx * a.f.nx), Ly = (R)(a.f.dy * a.f.ny), Lz = (R)(a.f.dz * a.f.nz);
-
-  uint32_t flags = 0, nflag = 0, nnan = 0, nrange = 0;
-  R fld[kGPItems][6];
-  double chi_e[kGPItems], w_e[kGPItems], rem_e[kGPItems];
-  const int64_t i0 = base + (int64_t)threadIdx.x * kGPItems;
-#pragma unroll
-  for (int it = 0; it < kGPItems; ++it) {
-    const int64_t i = i0 + it;
-    if (i >= n) break;
+  const int64_t i = base + threadIdx.x;
+  uint32_t flag = 0, nnan = 0, nrange = 0;
+  R F[6];
+  double chi = 0.0, W = 0.0, rem = 0.0;
+  if (i < n) {
     R x = X[i], y = Y[i], z = Z[i];
     R px = PX[i], py = PY[i], pz = PZ[i];
-    double tau = a.sp.tau[i];
-    R F[6];
+    const double tau = a.sp.tau[i];
     field_at<R>(a.f, i, x, y, z, F);
     boris<R>(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5], a.q, a.dt);
     const R g = sqrt((R)1 + px * px + py * py + pz * pz);
     x += px / g * a.dt; y += py / g * a.dt; z += pz / g * a.dt;
-    if (a.f.kind == QED_FIELD_GRID) { wrap_coord<R>(x, Lx); wrap_coord<R>(y, Ly); wrap_coord<R>(z, Lz); }
+    if (a.f.kind == QED_FIELD_GRID) {
+      wrap_coord<R>(x, (R)(a.f.dx * a.f.nx)); wrap_coord<R>(y, (R)(a.f.dy * a.f.ny));
+      wrap_coord<R>(z, (R)(a.f.dz * a.f.nz));
+    }
     X[i] = x; Y[i] = y; Z[i] = z; PX[i] = px; PY[i] = py; PZ[i] = pz;
-    const double chi = chi_lepton(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5]);
-    double W = 0.0;
+    chi = chi_lepton(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5]);
     if (isfinite(chi)) {
-      nrange += chi > kRadChiMax;
+      nrange = chi > kRadChiMax;
       W = kRateUnit * (double)(h_rad<R>((R)chi, lnh_s) / g);
     } else {
-      ++nnan;
+      nnan = 1;
     }
     if (W > 0.0 && tau <= W * a.dtd) {
-      flags |= 1u << it;
-      ++nflag;
-#pragma unroll
-      for (int c = 0; c < 6; ++c) fld[it][c] = F[c];
-      chi_e[it] = chi;
-      w_e[it] = W;
-      rem_e[it] = a.dtd - tau / W;
+      flag = 1;
+      rem = a.dtd - tau / W;
     } else {
       a.sp.tau[i] = tau - W * a.dtd;
     }
@@ -210,20 +210,16 @@ __global__ __launch_bounds__(kGPThreads) void k_gather_push(GPArgs<R> a) {
   count_add(a.counters, cChiRange, nrange);
 
   uint32_t total;
-  const uint32_t off = block_exclusive(nflag, scan_s, &total);
+  const uint32_t off = block_exclusive(flag, scan_s, &total);
   const uint64_t toff = tile_offset(tile, total, a.sc, a.counters, &off_s);
-  uint64_t r = toff + off;
+  if (flag) {
+    const uint64_t r = toff + off;
+    a.em_idx[r] = (int32_t)i;
 #pragma unroll
-  for (int it = 0; it < kGPItems; ++it) {
-    if (flags & (1u << it)) {
-      a.em_idx[r] = (int32_t)(i0 + it);
-#pragma unroll
-      for (int c = 0; c < 6; ++c) a.em_fld[c * a.em_cap + r] = fld[it][c];
-      a.em_chi[r] = chi_e[it];
-      a.em_w[r] = w_e[it];
-      a.em_rem[r] = rem_e[it];
-      ++r;
-    }
+    for (int c = 0; c < 6; ++c) a.em_fld[c * a.em_cap + r] = F[c];
+    a.em_chi[r] = chi;
+    a.em_w[r] = W;
+    a.em_rem[r] = rem;
   }
   const int64_t last = (n - 1) / kGPTile;
   if ((int64_t)tile == last && threadIdx.x == 0) *a.n_emit = (int64_t)(toff + total);
@@ -355,9 +351,11 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_f32(EmitArgs<float> a) {
   __shared__ uint32_t scan_s[16];
   __shared__ uint32_t tile_s;
   __shared__ uint64_t off_s;
-  const int64_t n_em = *a.n_emit;
-  const int64_t ph0 = *a.ph.count;
-  const uint64_t id0 = *a.next_id;
+  __shared__ int64_t hdr_s[3];
+  if (threadIdx.x == 0) { hdr_s[0] = *a.n_emit; hdr_s[1] = *a.ph.count; hdr_s[2] = (int64_t)*a.next_id; }
+  __syncthreads();
+  const int64_t n_em = hdr_s[0], ph0 = hdr_s[1];
+  const uint64_t id0 = (uint64_t)hdr_s[2];
   if (n_em == 0) return;
   const uint4 *gq = reinterpret_cast<const uint4 *>(a.q16);
   for (int k = threadIdx.x; k < kRadNChi * kNU / 8; k += blockDim.x) q_s[k] = gq[k];
@@ -377,9 +375,11 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_f64(EmitArgs<double> a) {
   __shared__ uint32_t scan_s[16];
   __shared__ uint32_t tile_s;
   __shared__ uint64_t off_s;
-  const int64_t n_em = *a.n_emit;
-  const int64_t ph0 = *a.ph.count;
-  const uint64_t id0 = *a.next_id;
+  __shared__ int64_t hdr_s[3];
+  if (threadIdx.x == 0) { hdr_s[0] = *a.n_emit; hdr_s[1] = *a.ph.count; hdr_s[2] = (int64_t)*a.next_id; }
+  __syncthreads();
+  const int64_t n_em = hdr_s[0], ph0 = hdr_s[1];
+  const uint64_t id0 = (uint64_t)hdr_s[2];
   if (n_em == 0) return;
   for (int k = threadIdx.x; k < kRadNChi; k += blockDim.x) lnh_s[k] = a.lnh[k];
   const RowF64 tab{a.S64};
@@ -500,10 +500,15 @@ __global__ __launch_bounds__(kPairThreads) void k_pairs_f32(PairArgs<float> a) {
   __shared__ uint32_t scan_s[16];
   __shared__ uint32_t tile_s;
   __shared__ uint64_t off_s;
-  const int64_t n = *a.ph.count;
+  __shared__ int64_t hdr_s[4];
+  if (threadIdx.x == 0) {
+    hdr_s[0] = *a.ph.count; hdr_s[1] = *a.el.count; hdr_s[2] = *a.po.count;
+    hdr_s[3] = (int64_t)*a.next_id;
+  }
+  __syncthreads();
+  const int64_t n = hdr_s[0], e0 = hdr_s[1], p0 = hdr_s[2];
+  const uint64_t id0 = (uint64_t)hdr_s[3];
   if (n == 0) return;
-  const int64_t e0 = *a.el.count, p0 = *a.po.count;
-  const uint64_t id0 = *a.next_id;
   const uint4 *gq = reinterpret_cast<const uint4 *>(a.q16);
   for (int k = threadIdx.x; k < kPairNCdf * kNU / 8; k += blockDim.x) q_s[k] = gq[k];
   for (int k = threadIdx.x; k < 2 * kPairNCdf; k += blockDim.x) s0sc_s[k] = a.s0sc[k];
@@ -521,10 +526,15 @@ __global__ __launch_bounds__(kPairThreads) void k_pairs_f64(PairArgs<double> a) 
   __shared__ uint32_t scan_s[16];
   __shared__ uint32_t tile_s;
   __shared__ uint64_t off_s;
-  const int64_t n = *a.ph.count;
+  __shared__ int64_t hdr_s[4];
+  if (threadIdx.x == 0) {
+    hdr_s[0] = *a.ph.count; hdr_s[1] = *a.el.count; hdr_s[2] = *a.po.count;
+    hdr_s[3] = (int64_t)*a.next_id;
+  }
+  __syncthreads();
+  const int64_t n = hdr_s[0], e0 = hdr_s[1], p0 = hdr_s[2];
+  const uint64_t id0 = (uint64_t)hdr_s[3];
   if (n == 0) return;
-  const int64_t e0 = *a.el.count, p0 = *a.po.count;
-  const uint64_t id0 = *a.next_id;
   for (int k = threadIdx.x; k < kPairNRate; k += blockDim.x) L_s[k] = a.L[k];
   const RowF64 tab{a.S64};
   while (true) {
@@ -565,7 +575,9 @@ __global__ __launch_bounds__(kCThreads) void k_compact(SpeciesDev sp, ScanDev sc
     }
     if (id[it] != kDeadId) { alive |= 1u << it; ++na; }
   }
-  __threadfence();   // every load of the tile has completed before its count is published
+  // every load of the tile has returned before its count is published: later
+  // tiles may overwrite these elements as soon as they see the count
+  __builtin_amdgcn_s_waitcnt(0);
   uint32_t total;
   const uint32_t off = block_exclusive(na, scan_s, &total);
   const uint64_t toff = tile_offset(tile, total, sc, counters, &off_s);
