@@ -236,3 +236,103 @@ def test_emitted_spectrum_ks_1e7(rad_table_I):
     ks2 = np.max(np.abs(cdf_g - cdf_o))
     print(f"photons {m}  KS(exact) {ks1:.2e}  KS(oracle sampler) {ks2:.2e}")
     assert ks1 < 2e-3 and ks2 < 2e-3
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_pairs_one_step_parity(pair_table, dtype):
+    """Photons with chi_ph log-uniform in [1e-2, 1e2] in per-particle fields: pair
+    decisions, electron/positron records (rank order, ids, momenta, optical depth),
+    dead photons and surviving optical depths against the oracle."""
+    torch, q = need_gpu()
+    n = 200000
+    ph_in = workloads.pair_photons(n, E_S, seed=2)
+    tau = mc.init_tau(ph_in["id"], seed=2) * 0.05      # many events in one step
+    cast = (lambda a: a.astype(np.float32).astype(np.float64)) if dtype == "f32" else (lambda a: a)
+    k = cast(ph_in["k"])
+    E, B = cast(ph_in["E"]), cast(ph_in["B"])
+    ctx = q.Context(seed=2, kmax=4, flags=q.QED_FLAG_STATIC_PHOTONS)
+    ctx.qed_build_tables(q.QED_FORMULA_I)
+    ph = q.Species(n, dtype)
+    el = q.Species(n + 10, dtype)
+    po = q.Species(n + 10, dtype)
+    ph.load(ph_in["x"], k, tau, ph_in["id"])
+    ctx.qed_set_next_id(n)
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda", torch.float32)
+    fld = q.Fields(q.QED_FIELD_PER_PARTICLE, E=[dev(E[:, c]) for c in range(3)],
+                   B=[dev(B[:, c]) for c in range(3)])
+    dt = 0.01
+    ctx.qed_create_pairs(fld, ph, el, po, dt, 3)
+    st, rc = ctx.qed_get_status()
+    ps = mc.PairSampler(pair_table, "f64" if dtype == "f64" else "q16")
+    E32 = E.astype(np.float32).astype(np.float64)
+    B32 = B.astype(np.float32).astype(np.float64)
+    r = mc.photon_step(ph_in["x"], k, tau, ph_in["id"], E32, B32, dt=dt, step=3, seed=2,
+                       sampler=ps, next_id=n, move=False)
+    g_ph, g_el, g_po = ph.to_numpy(), el.to_numpy(), po.to_numpy()
+    assert st["pairs"] == r["pairs"].size and st["scan_timeouts"] == 0 and st["dropped"] == 0
+    np.testing.assert_array_equal(g_ph["id"], r["id"])
+    np.testing.assert_array_equal(g_el["id"], r["electrons"]["id"])
+    np.testing.assert_array_equal(g_po["id"], r["positrons"]["id"])
+    rt = 1e-10 if dtype == "f64" else 3e-3
+    for g, o in ((g_el, r["electrons"]), (g_po, r["positrons"])):
+        ge = np.sqrt(1 + np.sum(g["p"] ** 2, axis=1))
+        go = np.sqrt(1 + np.sum(o["p"] ** 2, axis=1))
+        np.testing.assert_allclose(ge, go, rtol=rt)
+        np.testing.assert_allclose(g["tau"], o["tau"], rtol=1e-12)
+    alive = r["id"] != mc.DEAD_ID
+    W = r["W"]
+    np.testing.assert_allclose(g_ph["tau"][alive], r["tau"][alive], rtol=1e-9 if dtype == "f64" else 1e-4,
+                               atol=(1e-9 if dtype == "f64" else 1e-4) * (W * dt).max())
+    # compaction removes exactly the converted photons, in order
+    ctx.qed_compact(ph)
+    np.testing.assert_array_equal(ph.to_numpy()["id"], r["id"][alive])
+
+
+def test_pair_spectrum_and_yield_1e7(pair_table):
+    """1e7 photons at chi_ph = 1 (gamma_ph = 1000): pair yield in one step against
+    1 - exp(-W dt) with W from the oracle quadrature (binomial z-test), and the
+    electron energy fraction against the exact Eq. (6) CDF (one-sample KS) and the
+    oracle's table sampler (two-sample KS), float32 path."""
+    torch, q = need_gpu()
+    n, gph, chi = 10_000_000, 1000.0, 1.0
+    ctx = q.Context(seed=31, kmax=4, flags=q.QED_FLAG_STATIC_PHOTONS)
+    ctx.qed_build_tables(q.QED_FORMULA_I)
+    ph = q.Species(n, "f32")
+    el = q.Species(n, "f32")
+    po = q.Species(n, "f32")
+    # photons along +x in B = b z: chi_ph = gamma_ph b / E_S
+    b = chi * E_S / gph
+    ph.load(np.zeros((n, 3)), np.tile([gph, 0.0, 0.0], (n, 1)), ids=np.arange(n, dtype=np.uint64))
+    ctx.qed_init_optical_depth(ph, 0)
+    ctx.qed_set_next_id(n)
+    fld = q.Fields(q.QED_FIELD_UNIFORM, B=(0, 0, b))
+    row = tables.fine_row("pair", chi, tables.PAIR_M)
+    from oracle.constants import RATE_UNIT
+    W = RATE_UNIT * 2 * row.total / gph
+    dt = 1.0 / W                                   # P(pair) = 1 - e^-1
+    ctx.qed_create_pairs(fld, ph, el, po, dt, 0)
+    st, rc = ctx.qed_get_status()
+    m = el.n()
+    pr = 1 - math.exp(-W * dt)
+    z = (m - n * pr) / math.sqrt(n * pr * (1 - pr))
+    assert abs(z) < 4, z
+    ge = torch.sqrt(1 + el.px[:m].double() ** 2 + el.py[:m].double() ** 2 + el.pz[:m].double() ** 2)
+    xi = np.sort((ge / gph).cpu().numpy())
+    # exact CDF of the full (symmetric) spectrum from the half-spectrum CDF
+    P = row.F / row.total
+    s_samp = np.log(xi) - np.log1p(-xi)
+    Ph = np.interp(-np.abs(s_samp), row.s, P)          # half CDF at min(xi, 1-xi)
+    Pe = np.where(s_samp <= 0, 0.5 * Ph, 1 - 0.5 * Ph)
+    ks1 = max(np.max(np.arange(1, m + 1) / m - Pe), np.max(Pe - np.arange(m) / m))
+    rng = np.random.default_rng(5)
+    ps = mc.PairSampler(pair_table, "q16")
+    u = (np.floor(rng.uniform(size=m) * 2 ** 23) + 0.5) * 2.0 ** -23
+    ur = (np.floor(rng.uniform(size=m) * 2 ** 23) + 0.5) * 2.0 ** -23
+    xh, omh = ps.sample_half(np.full(m, chi), u, ur)
+    flip = rng.uniform(size=m) < 0.5
+    xo = np.sort(np.where(flip, omh, xh))
+    allv = np.concatenate([xi, xo])
+    ks2 = np.max(np.abs(np.searchsorted(xi, allv, side="right") / m - np.searchsorted(xo, allv, side="right") / m))
+    print(f"pairs {m} (z = {z:.2f})  KS(exact) {ks1:.2e}  KS(oracle sampler) {ks2:.2e}")
+    assert ks1 < 2e-3 and ks2 < 2e-3
