@@ -61,6 +61,9 @@ extern "C" {
 #define QED_F64 1
 
 /* photon spectrum used for the emission tables */
+/* qed_sample: table copy, or the surrogate networks with table fallback */
+#define QED_SAMPLER_MLP 2
+
 #define QED_FORMULA_I  1        /* Eq. (1) */
 #define QED_FORMULA_II 2        /* Eq. (4) */
 
@@ -127,7 +130,18 @@ typedef struct {
   int64_t nan_chi;             /* particles skipped because chi was not finite */
   int64_t scan_timeouts;       /* prefix-scan waits that gave up (must be 0)  */
   int64_t compacted;           /* particles removed by qed_compact            */
+  int64_t mlp_fallback_xi;     /* surrogate xi samples that fell back to the table */
+  int64_t mlp_fallback_rate;   /* surrogate rates that fell back to the table     */
 } qed_counters_t;
+
+/* Surrogate training (not part of the paper; see qed_surrogate_train). */
+typedef struct {
+  int64_t steps;       /* Adam steps per net                                     */
+  int64_t batch;       /* samples per step (drawn from the float64 master tables) */
+  double lr;           /* peak learning rate (cosine decay to 0)                  */
+  uint32_t seed;
+  int32_t nets;        /* bit 0: xi net (A), bit 1: rate net (B)                  */
+} qed_train_spec_t;
 
 /* Creates a context on the current HIP device.  Allocates counters only. */
 QED_API int qed_create(qed_ctx_t *ctx, const qed_params_t *params);
@@ -205,6 +219,33 @@ QED_API int qed_compact(qed_ctx_t ctx, qed_species_t *sp, void *stream);
 QED_API int qed_sample(qed_ctx_t ctx, const double *chi, const double *gamma, const uint64_t *id,
                int64_t n, int precision, int64_t step, float *lnw_rad, float *xi,
                float *lnw_pair, void *stream);
+
+/* Surrogate networks.  Not in the paper: two multilayer perceptrons (3 hidden
+   layers of 64, SiLU) replace table lookups, the tables staying the fallback.
+   Net A (0): (log10 chi, logit u) -> logit(xi) - ln chi - 3 ln u; net B (1):
+   log10 chi -> (ln h_rad - ln chi, ln h_pair + 8/(3 chi) - ln chi), with fixed
+   affine normalisations.  The 64x64 layers run on BF16 matrix cores with a two-term
+   split of every operand (three products, float32 accumulation).
+   qed_surrogate_train: trains the nets selected by spec->nets with Adam on batches
+   drawn (Philox, spec->seed) from the float64 master tables; requires
+   qed_build_tables.  qed_surrogate_params: parameter count of a net.
+   qed_surrogate_io: copies a net's float32 parameters to (direction 0) or from
+   (direction 1) host memory; layout W1 b1 W2 b2 W3 b3 W4 b4 (row-major [out][in]).
+   qed_surrogate_forward: raw normalised outputs for n inputs (device, [n][nin] ->
+   [n][nout] float32).  qed_surrogate_grad: gradient of the mean squared error
+   sum_o mask*(y - t)^2 / n over an external batch (device float32 arrays) into
+   grad (device, params floats).
+   qed_sample with precision QED_SAMPLER_MLP uses both nets; a rate outside
+   0 < h <= 1.001 * 5 chi / (2 sqrt3) or chi outside [1e-3, 1e2] falls back to the
+   table, and a xi sample falls back when u is outside [1e-4, 1 - 1e-4] or the
+   tabulated CDF at the predicted xi differs from u by more than 2e-3.  Fallbacks
+   are counted (mlp_fallback_*). */
+QED_API int qed_surrogate_params(int net);
+QED_API int qed_surrogate_train(qed_ctx_t ctx, const qed_train_spec_t *spec, void *stream);
+QED_API int qed_surrogate_io(qed_ctx_t ctx, int net, float *host, size_t bytes, int direction);
+QED_API int qed_surrogate_forward(qed_ctx_t ctx, int net, const float *x, int64_t n, float *y, void *stream);
+QED_API int qed_surrogate_grad(qed_ctx_t ctx, int net, const float *x, const float *t, const float *mask,
+                               int64_t n, float *grad, void *stream);
 
 /* Synchronises `stream`, returns the counters and clears them.  Returns
    QED_ERR_CAPACITY if appends were dropped since the last call. */

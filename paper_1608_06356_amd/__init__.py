@@ -17,11 +17,13 @@ QED_F32, QED_F64 = 0, 1
 QED_FORMULA_I, QED_FORMULA_II = 1, 2
 QED_FIELD_UNIFORM, QED_FIELD_GRID, QED_FIELD_PER_PARTICLE = 0, 1, 2
 QED_FLAG_NO_RECOIL, QED_FLAG_STATIC_PHOTONS = 1, 2
+QED_SAMPLER_MLP = 2
 DEAD_ID = 0xFFFFFFFFFFFFFFFF
 EXPORTS = ["qed_create", "qed_destroy", "qed_last_error", "qed_reserve", "qed_set_next_id",
            "qed_get_next_id", "qed_build_tables", "qed_get_table", "qed_init_optical_depth",
            "qed_fill_standing_wave", "qed_gather_push", "qed_emit_photons", "qed_create_pairs",
-           "qed_compact", "qed_sample", "qed_get_status"]
+           "qed_compact", "qed_sample", "qed_get_status", "qed_surrogate_params",
+           "qed_surrogate_train", "qed_surrogate_io", "qed_surrogate_forward", "qed_surrogate_grad"]
 
 
 class qed_params_t(ctypes.Structure):
@@ -48,10 +50,15 @@ class qed_fields_t(ctypes.Structure):
 class qed_counters_t(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "events", "photons", "rejected", "capped", "pairs", "dropped", "chi_out_of_range",
-        "nan_chi", "scan_timeouts", "compacted")]
+        "nan_chi", "scan_timeouts", "compacted", "mlp_fallback_xi", "mlp_fallback_rate")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class qed_train_spec_t(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("batch", ctypes.c_int64), ("lr", ctypes.c_double),
+                ("seed", ctypes.c_uint32), ("nets", ctypes.c_int32)]
 
 
 _lib = None
@@ -87,6 +94,11 @@ def lib():
             "qed_compact": (ctypes.c_int, [vp, ctypes.POINTER(qed_species_t), vp]),
             "qed_sample": (ctypes.c_int, [vp, vp, vp, vp, i64, ctypes.c_int, i64, vp, vp, vp, vp]),
             "qed_get_status": (ctypes.c_int, [vp, ctypes.POINTER(qed_counters_t), vp]),
+            "qed_surrogate_params": (ctypes.c_int, [ctypes.c_int]),
+            "qed_surrogate_train": (ctypes.c_int, [vp, ctypes.POINTER(qed_train_spec_t), vp]),
+            "qed_surrogate_io": (ctypes.c_int, [vp, ctypes.c_int, vp, ctypes.c_size_t, ctypes.c_int]),
+            "qed_surrogate_forward": (ctypes.c_int, [vp, ctypes.c_int, vp, i64, vp, vp]),
+            "qed_surrogate_grad": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp, i64, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -188,6 +200,32 @@ class Context:
         p = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p()
         return self._check(lib().qed_sample(self.h, p(chi), p(gamma), p(ids), n, precision, int(step),
                                             p(lnw), p(xi), p(lnwp), _stream(stream)))
+
+    def qed_surrogate_train(self, steps, batch=4096, lr=3e-3, seed=0, nets=3, stream=None):
+        spec = qed_train_spec_t(int(steps), int(batch), float(lr), int(seed), int(nets))
+        return self._check(lib().qed_surrogate_train(self.h, ctypes.byref(spec), _stream(stream)))
+
+    def qed_surrogate_io(self, net, weights=None):
+        """Returns the float32 parameters of `net` (weights None) or loads them."""
+        import numpy as np
+        n = lib().qed_surrogate_params(net)
+        if weights is None:
+            out = np.empty(n, dtype=np.float32)
+            self._check(lib().qed_surrogate_io(self.h, net, out.ctypes.data_as(ctypes.c_void_p), out.nbytes, 0))
+            return out
+        w = np.ascontiguousarray(weights, dtype=np.float32)
+        assert w.size == n
+        self._check(lib().qed_surrogate_io(self.h, net, w.ctypes.data_as(ctypes.c_void_p), w.nbytes, 1))
+
+    def qed_surrogate_forward(self, net, x, y, stream=None):
+        return self._check(lib().qed_surrogate_forward(self.h, net, ctypes.c_void_p(x.data_ptr()), x.shape[0],
+                                                       ctypes.c_void_p(y.data_ptr()), _stream(stream)))
+
+    def qed_surrogate_grad(self, net, x, t, mask, grad, stream=None):
+        m = ctypes.c_void_p(mask.data_ptr()) if mask is not None else ctypes.c_void_p()
+        return self._check(lib().qed_surrogate_grad(self.h, net, ctypes.c_void_p(x.data_ptr()),
+                                                    ctypes.c_void_p(t.data_ptr()), m, x.shape[0],
+                                                    ctypes.c_void_p(grad.data_ptr()), _stream(stream)))
 
     def qed_get_status(self, stream=None, check=True):
         c = qed_counters_t()

@@ -116,7 +116,8 @@ void qed_destroy(qed_ctx_t c) {
   free_emitters(c);
   void *ptrs[] = {c->rad_lnh64, c->rad_S64, c->rad_lnh32, c->rad_s0sc, c->rad_q16, c->pair_L64,
                   c->pair_S64, c->pair_L32, c->pair_s0sc, c->pair_q16, c->tab_work, c->d_counters,
-                  c->d_next_id, c->d_n_emit, c->d_ticket};
+                  c->d_next_id, c->d_n_emit, c->d_ticket, c->rad_chk, c->mlp_theta[0], c->mlp_theta[1],
+                  c->mlp_grad[0], c->mlp_grad[1], c->mlp_m[0], c->mlp_m[1], c->mlp_v[0], c->mlp_v[1]};
   for (void *p : ptrs) (void)hipFree(p);
   delete c;
 }
@@ -157,7 +158,7 @@ int qed_build_tables(qed_ctx_t c, int formula, void *st) {
         (e = dalloc(&c->rad_q16, kRadNChi * kNU)) != hipSuccess || (e = dalloc(&c->pair_L64, kPairNRate)) != hipSuccess ||
         (e = dalloc(&c->pair_S64, kPairNCdf * kNU)) != hipSuccess || (e = dalloc(&c->pair_L32, kPairNRate)) != hipSuccess ||
         (e = dalloc(&c->pair_s0sc, 2 * kPairNCdf)) != hipSuccess || (e = dalloc(&c->pair_q16, kPairNCdf * kNU)) != hipSuccess ||
-        (e = dalloc(&c->tab_work, work)) != hipSuccess)
+        (e = dalloc(&c->rad_chk, kRadNChi * 82)) != hipSuccess || (e = dalloc(&c->tab_work, work)) != hipSuccess)
       return hip_fail(c, e, "build_tables: hipMalloc");
     c->tab_work_elems = work;
   }
@@ -271,11 +272,98 @@ int qed_sample(qed_ctx_t c, const double *chi, const double *gamma, const uint64
                int precision, int64_t step, float *lnw, float *xi, float *lnwp, void *st) {
   if (!c) return QED_ERR_ARG;
   if (!chi || !gamma || !id || !lnw || !xi || n < 0) return fail(c, QED_ERR_ARG, "sample: bad arguments");
-  if (precision != QED_F32 && precision != QED_F64) return fail(c, QED_ERR_ARG, "sample: bad precision");
+  if (precision != QED_F32 && precision != QED_F64 && precision != QED_SAMPLER_MLP)
+    return fail(c, QED_ERR_ARG, "sample: bad precision");
   if (!c->tables_ready) return fail(c, QED_ERR_STATE, "tables not built");
+  if (precision == QED_SAMPLER_MLP && !c->mlp_ready)
+    return fail(c, QED_ERR_STATE, "surrogate not trained or loaded");
   if (n == 0) return QED_OK;
-  hipError_t e = qed::launch_sample(c, chi, gamma, id, n, precision, step, lnw, xi, lnwp, S(st));
+  hipError_t e = precision == QED_SAMPLER_MLP
+                     ? qed::launch_mlp_sample(c, chi, gamma, id, n, step, lnw, xi, lnwp, 2e-3f, S(st))
+                     : qed::launch_sample(c, chi, gamma, id, n, precision, step, lnw, xi, lnwp, S(st));
   return e == hipSuccess ? QED_OK : hip_fail(c, e, "sample");
+}
+
+static int mlp_alloc(qed_ctx *c) {
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+    if (c->mlp_theta[k]) continue;
+    const int n = qed::mlp_params(k);
+    if ((e = dalloc(&c->mlp_theta[k], n)) == hipSuccess && (e = dalloc(&c->mlp_grad[k], n)) == hipSuccess &&
+        (e = dalloc(&c->mlp_m[k], n)) == hipSuccess && (e = dalloc(&c->mlp_v[k], n)) == hipSuccess)
+      e = hipMemset(c->mlp_grad[k], 0, n * sizeof(float));
+  }
+  return e == hipSuccess ? QED_OK : hip_fail(c, e, "surrogate: hipMalloc");
+}
+
+int qed_surrogate_params(int net) { return (net == 0 || net == 1) ? qed::mlp_params(net) : QED_ERR_ARG; }
+
+int qed_surrogate_train(qed_ctx_t c, const qed_train_spec_t *spec, void *st) {
+  if (!c || !spec) return QED_ERR_ARG;
+  if (!c->tables_ready) return fail(c, QED_ERR_STATE, "tables not built");
+  if (spec->steps < 0 || spec->batch < 16 || spec->batch > (1 << 22) || !(spec->lr > 0))
+    return fail(c, QED_ERR_ARG, "train: need steps >= 0, 16 <= batch <= 2^22, lr > 0");
+  int r = mlp_alloc(c);
+  if (r) return r;
+  hipStream_t s = S(st);
+  for (int k = 0; k < 2; ++k) {
+    if (!(spec->nets & (1 << k))) continue;
+    const int n = qed::mlp_params(k);
+    hipError_t e = qed::launch_mlp_init(c->mlp_theta[k], k, spec->seed + 977u * k, s);
+    if (e == hipSuccess) e = hipMemsetAsync(c->mlp_m[k], 0, n * sizeof(float), s);
+    if (e == hipSuccess) e = hipMemsetAsync(c->mlp_v[k], 0, n * sizeof(float), s);
+    if (e == hipSuccess) e = hipMemsetAsync(c->mlp_grad[k], 0, n * sizeof(float), s);
+    double b1t = 1.0, b2t = 1.0;
+    for (int64_t it = 0; it < spec->steps && e == hipSuccess; ++it) {
+      const double lr = spec->lr * 0.5 * (1.0 + cos(3.141592653589793 * (double)it / (double)spec->steps));
+      b1t *= 0.9; b2t *= 0.999;
+      e = qed::launch_mlp_grad(k, c->mlp_theta[k], c->mlp_grad[k], c->rad_S64, c->rad_lnh64, c->pair_L64, nullptr,
+                               nullptr, nullptr, spec->batch, (uint64_t)it * (uint64_t)spec->batch, spec->seed, s);
+      if (e == hipSuccess)
+        e = qed::launch_adam(c->mlp_theta[k], c->mlp_grad[k], c->mlp_m[k], c->mlp_v[k], k, (float)lr,
+                             (float)b1t, (float)b2t, s);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "surrogate_train");
+  }
+  if ((spec->nets & 3) == 3 || (c->mlp_ready && spec->nets)) c->mlp_ready = true;
+  return QED_OK;
+}
+
+int qed_surrogate_io(qed_ctx_t c, int net, float *host, size_t bytes, int direction) {
+  if (!c || !host || (net != 0 && net != 1) || (direction != 0 && direction != 1)) return QED_ERR_ARG;
+  const size_t need = (size_t)qed::mlp_params(net) * sizeof(float);
+  if (bytes != need) return fail(c, QED_ERR_ARG, "surrogate_io: wrong byte count, need " + std::to_string(need));
+  int r = mlp_alloc(c);
+  if (r) return r;
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess)
+    e = direction == 0 ? hipMemcpy(host, c->mlp_theta[net], need, hipMemcpyDeviceToHost)
+                       : hipMemcpy(c->mlp_theta[net], host, need, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(c, e, "surrogate_io");
+  if (direction == 1) {
+    static bool loaded[2];
+    (void)loaded;
+    c->mlp_ready = c->mlp_ready || net == 1 || net == 0;
+  }
+  return QED_OK;
+}
+
+int qed_surrogate_forward(qed_ctx_t c, int net, const float *x, int64_t n, float *y, void *st) {
+  if (!c || !x || !y || n < 0 || (net != 0 && net != 1)) return QED_ERR_ARG;
+  if (!c->mlp_theta[net]) return fail(c, QED_ERR_STATE, "surrogate weights not set");
+  if (n == 0) return QED_OK;
+  hipError_t e = qed::launch_mlp_forward(c->mlp_theta[net], net, x, n, y, S(st));
+  return e == hipSuccess ? QED_OK : hip_fail(c, e, "surrogate_forward");
+}
+
+int qed_surrogate_grad(qed_ctx_t c, int net, const float *x, const float *t, const float *mask, int64_t n,
+                       float *grad, void *st) {
+  if (!c || !x || !t || !grad || n < 1 || (net != 0 && net != 1)) return QED_ERR_ARG;
+  if (!c->mlp_theta[net]) return fail(c, QED_ERR_STATE, "surrogate weights not set");
+  hipError_t e = hipMemsetAsync(grad, 0, qed::mlp_params(net) * sizeof(float), S(st));
+  if (e == hipSuccess)
+    e = qed::launch_mlp_grad(net, c->mlp_theta[net], grad, nullptr, nullptr, nullptr, x, t, mask, n, 0, 0, S(st));
+  return e == hipSuccess ? QED_OK : hip_fail(c, e, "surrogate_grad");
 }
 
 int qed_get_status(qed_ctx_t c, qed_counters_t *out, void *st) {

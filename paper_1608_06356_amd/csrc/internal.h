@@ -20,6 +20,7 @@ struct qed_ctx {
   double *pair_L64 = nullptr, *pair_S64 = nullptr;       // [512], [256*256]
   float *pair_L32 = nullptr, *pair_s0sc = nullptr;       // [512], [2*256]
   uint16_t *pair_q16 = nullptr;
+  float *rad_chk = nullptr;                              // [256 * 82] Hermite CDF check rows
   double *tab_work = nullptr;                            // quadrature scratch
   size_t tab_work_elems = 0;
 
@@ -44,10 +45,25 @@ struct qed_ctx {
   int64_t status_len = 0;
 
   int n_cu = 256;
+
+  // surrogate networks (0: xi net, 1: rate net): float32 parameters, Adam state
+  bool mlp_ready = false;
+  float *mlp_theta[2] = {nullptr, nullptr}, *mlp_grad[2] = {nullptr, nullptr};
+  float *mlp_m[2] = {nullptr, nullptr}, *mlp_v[2] = {nullptr, nullptr};
 };
 
 namespace qed {
 hipError_t launch_build_tables(qed_ctx *c, int formula, hipStream_t s);
+int mlp_params(int net);
+hipError_t launch_mlp_init(float *theta, int net, uint32_t seed, hipStream_t st);
+hipError_t launch_mlp_grad(int net, const float *theta, float *grad, const double *S64, const double *lnh,
+                           const double *L, const float *ext_x, const float *ext_t, const float *ext_m,
+                           int64_t nbatch, uint64_t sample0, uint32_t seed, hipStream_t st);
+hipError_t launch_adam(float *theta, float *grad, float *m, float *v, int net, float lr, float b1t, float b2t,
+                       hipStream_t st);
+hipError_t launch_mlp_forward(const float *theta, int net, const float *x, int64_t n, float *y, hipStream_t st);
+hipError_t launch_mlp_sample(qed_ctx *c, const double *chi, const double *gamma, const uint64_t *id, int64_t n,
+                             int64_t step, float *lnw, float *xi, float *lnwp, float tol, hipStream_t st);
 }
 
 namespace qed {

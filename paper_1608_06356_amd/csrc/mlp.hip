@@ -1,0 +1,628 @@
+// Surrogate networks of the QED step and their training, on gfx950 matrix cores.
+//
+//   net A  (log10 chi, logit u) -> r,  logit(xi) = r + ln chi + 3 ln u
+//   net B  log10 chi -> (ln h_rad - ln chi, ln h_pair + 8/(3 chi) - ln chi)
+//
+// Three hidden layers of width 64 with SiLU.  The two 64x64 layers run on
+// v_mfma_f32_16x16x16_bf16 with every operand split into bf16 hi + lo parts and
+// the three products hi*hi + hi*lo + lo*hi accumulated in float32 (about 16
+// significant bits; one bf16 product alone would leave ~3e-3 relative error,
+// too coarse for the 1e-3 rate target).  Input and output layers (1-2 inputs,
+// 1-2 outputs) are float32 vector code.
+//
+// A wave handles 16 samples.  With the 16x16x16 layout, lane l holds features
+// mt*16 + 4*(l/16) + v (mt, v = 0..3) of sample l%16 both as the D result and as
+// the B operand of the next layer, so activations stay in registers between
+// layers.  Training (forward, backward, weight gradients, Adam) uses the same
+// products; training data are drawn from the float64 master tables.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "internal.h"
+#include "lookup.h"
+#include "qed_device.h"
+
+namespace qed {
+namespace {
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int H = 64;
+constexpr double kTmax = 9.2102403669758;   // logit(1 - 1e-4)
+constexpr float kXShift = 0.5f, kXScale = 2.5f;
+constexpr float kAShift = -1.0f, kAScale = 2.0f;
+constexpr float kBShift0 = -0.4f, kBScale0 = 0.5f, kBShift1 = -2.0f, kBScale1 = 0.5f;
+constexpr uint32_t kTrainPurpose = 3, kInitPurpose = 4;
+
+struct Layout {
+  int nin, nout, W1, b1, W2, b2, W3, b3, W4, b4, n;
+};
+__host__ __device__ constexpr Layout make_layout(int nin, int nout) {
+  return Layout{nin, nout, 0, H * nin, H * nin + H, H * nin + H + H * H, H * nin + 2 * H + H * H,
+                H * nin + 2 * H + 2 * H * H, H * nin + 3 * H + 2 * H * H,
+                H * nin + 3 * H + 2 * H * H + nout * H, H * nin + 3 * H + 2 * H * H + nout * H + nout};
+}
+constexpr Layout kA = make_layout(2, 1), kB = make_layout(1, 2);
+
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+// x = hi + lo with hi = bf16(x), lo = bf16(x - hi), packed four at a time
+__device__ __forceinline__ void split4(const float x[4], s4 &hi, s4 &lo) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const uint16_t h = bf16_rne(x[v]);
+    hi[v] = (short)h;
+    lo[v] = (short)bf16_rne(x[v] - bf16_f(h));
+  }
+}
+__device__ __forceinline__ void split1(float x, uint16_t &hi, uint16_t &lo) {
+  hi = bf16_rne(x);
+  lo = bf16_rne(x - bf16_f(hi));
+}
+__device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu(float z) { return z * sigm(z); }
+__device__ __forceinline__ float dsilu(float z) {
+  const float s = sigm(z);
+  return s * (1.0f + z * (1.0f - s));
+}
+
+// Weights of one net staged in LDS: split 64x64 layers (row-major [out][in]),
+// optionally their transposes, and the float32 small layers.
+struct NetLds {
+  uint16_t W2h[H * H], W2l[H * H], W3h[H * H], W3l[H * H];
+  float W1[H * 2], b1[H], b2[H], b3[H], W4[2 * H], b4[2];
+};
+struct NetLdsT {
+  uint16_t W2h[H * H], W2l[H * H], W3h[H * H], W3l[H * H];   // transposed
+};
+
+__device__ void stage_net(const float *th, const Layout &L, NetLds *s, NetLdsT *t) {
+  for (int k = threadIdx.x; k < H * H; k += blockDim.x) {
+    uint16_t h, l;
+    split1(th[L.W2 + k], h, l);
+    s->W2h[k] = h; s->W2l[k] = l;
+    if (t) { const int tk = (k % H) * H + k / H; t->W2h[tk] = h; t->W2l[tk] = l; }
+    split1(th[L.W3 + k], h, l);
+    s->W3h[k] = h; s->W3l[k] = l;
+    if (t) { const int tk = (k % H) * H + k / H; t->W3h[tk] = h; t->W3l[tk] = l; }
+  }
+  for (int k = threadIdx.x; k < H; k += blockDim.x) {
+    s->b1[k] = th[L.b1 + k]; s->b2[k] = th[L.b2 + k]; s->b3[k] = th[L.b3 + k];
+    for (int c = 0; c < L.nin; ++c) s->W1[k * L.nin + c] = th[L.W1 + k * L.nin + c];
+    for (int o = 0; o < L.nout; ++o) s->W4[o * H + k] = th[L.W4 + o * H + k];
+  }
+  if (threadIdx.x < L.nout) s->b4[threadIdx.x] = th[L.b4 + threadIdx.x];
+}
+
+// out = W a (64x64 layer, split products); a and out in the lane layout.
+__device__ __forceinline__ void mm64(const uint16_t *Wh, const uint16_t *Wl, const float a[4][4],
+                                     float out[4][4]) {
+  const int lane = threadIdx.x & 63;
+  s4 bh[4], bl[4];
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) split4(a[ks], bh[ks], bl[ks]);
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int off = (mt * 16 + (lane & 15)) * H + ks * 16 + 4 * (lane >> 4);
+      const s4 ah = *reinterpret_cast<const s4 *>(Wh + off);
+      const s4 al = *reinterpret_cast<const s4 *>(Wl + off);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh[ks], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl[ks], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh[ks], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) out[mt][v] = acc[v];
+  }
+}
+
+// Keeps LDS-resident weights from being hoisted into registers across tiles
+// (the loop-invariant loads of two nets would exceed the register file).
+__device__ __forceinline__ void reload_barrier() { asm volatile("" ::: "memory"); }
+
+__device__ __forceinline__ int feat(int mt, int v) { return mt * 16 + 4 * ((threadIdx.x & 63) >> 4) + v; }
+
+struct Cache {
+  float z1[4][4], z2[4][4], z3[4][4], a3[4][4];
+};
+
+// Forward pass of one 16-sample tile; x0, x1 are the inputs of this lane's sample.
+__device__ __forceinline__ void forward(const NetLds &s, int nin, int nout, float x0, float x1,
+                                        float y[2], Cache &c) {
+  float a[4][4], z[4][4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int f = feat(mt, v);
+      float t = s.b1[f] + s.W1[f * nin] * x0;
+      if (nin > 1) t += s.W1[f * nin + 1] * x1;
+      c.z1[mt][v] = t;
+      a[mt][v] = silu(t);
+    }
+  mm64(s.W2h, s.W2l, a, z);
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) { z[mt][v] += s.b2[feat(mt, v)]; c.z2[mt][v] = z[mt][v]; a[mt][v] = silu(z[mt][v]); }
+  mm64(s.W3h, s.W3l, a, z);
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) { z[mt][v] += s.b3[feat(mt, v)]; c.z3[mt][v] = z[mt][v]; c.a3[mt][v] = silu(z[mt][v]); }
+  for (int o = 0; o < nout; ++o) {
+    float p = 0.f;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) p += s.W4[o * H + feat(mt, v)] * c.a3[mt][v];
+    p += __shfl_xor(p, 16, 64);
+    p += __shfl_xor(p, 32, 64);
+    y[o] = p + s.b4[o];
+  }
+}
+
+// Forward pass without the training cache (inference).
+__device__ __forceinline__ void forward_nc(const NetLds &s, int nin, int nout, float x0, float x1, float y[2]) {
+  float a[4][4], z[4][4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int f = feat(mt, v);
+      float t = s.b1[f] + s.W1[f * nin] * x0;
+      if (nin > 1) t += s.W1[f * nin + 1] * x1;
+      a[mt][v] = silu(t);
+    }
+  mm64(s.W2h, s.W2l, a, z);
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) a[mt][v] = silu(z[mt][v] + s.b2[feat(mt, v)]);
+  mm64(s.W3h, s.W3l, a, z);
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) a[mt][v] = silu(z[mt][v] + s.b3[feat(mt, v)]);
+  for (int o = 0; o < nout; ++o) {
+    float p = 0.f;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) p += s.W4[o * H + feat(mt, v)] * a[mt][v];
+    p += __shfl_xor(p, 16, 64);
+    p += __shfl_xor(p, 32, 64);
+    y[o] = p + s.b4[o];
+  }
+}
+
+// ------------------------------------------------------------- inputs/targets
+__device__ __forceinline__ float xin(double chi) { return (float)((log10(chi) + kXShift) / kXScale); }
+
+// Training sample g of net A: chi at a table row, logit u uniform in
+// [-Tmax, Tmax]; target from the float64 master inverse CDF of that row.
+__device__ void sample_A(uint64_t g, uint32_t seed, const double *S64, float &x0, float &x1, float &yt) {
+  const uint4 r = philox4x32_10(make_uint4((uint32_t)g, (uint32_t)(g >> 32), kTrainPurpose << 24, 0u),
+                                make_uint2(seed, 0xA5A5A5A5u));
+  const int row = (int)(r.x >> 24);                                     // 0..255
+  const double t = -kTmax + 2.0 * kTmax * unit<double>(r.y);
+  const double chi = exp(log(kRadChiMin) + row * ((log(kRadChiMax) - log(kRadChiMin)) / (kRadNChi - 1)));
+  const double tlo = log(kRadULo) - log1p(-kRadULo), thi = log(kRadUHi) - log1p(-kRadUHi);
+  const double dtn = (thi - tlo) / (kNU - 1);
+  const double y = (t - tlo) / dtn;
+  int j = (int)floor(y);
+  j = j < 0 ? 0 : (j > kNU - 2 ? kNU - 2 : j);
+  const double f = y - j;
+  const double s = (1.0 - f) * S64[row * kNU + j] + f * S64[row * kNU + j + 1];
+  const double lnu = -log1p(exp(-t));
+  x0 = xin(chi);
+  x1 = (float)(t / kTmax);
+  yt = (float)((s - log(chi) - 3.0 * lnu - kAShift) / kAScale);
+}
+
+// Training sample g of net B: log10 chi uniform in [-3, 2]; targets from the
+// float64 master rate tables (pair output masked below chi = 1e-2).
+__device__ void sample_B(uint64_t g, uint32_t seed, const double *lnh, const double *L, float &x0,
+                         float yt[2], float m[2]) {
+  const uint4 r = philox4x32_10(make_uint4((uint32_t)g, (uint32_t)(g >> 32), (kTrainPurpose << 24) | 1u, 0u),
+                                make_uint2(seed, 0x5A5A5A5Au));
+  const double lx = -3.0 + 5.0 * unit<double>(r.x);
+  const double chi = pow(10.0, lx);
+  x0 = xin(chi);
+  yt[0] = (float)((log(h_rad<double>(chi, lnh)) - log(chi) - kBShift0) / kBScale0);
+  if (chi >= kPairChiMin) {
+    const double x = Grid<double>::pos(log(chi), kPairChiMin, kPairChiMax, kPairNRate);
+    int i = (int)floor(x);
+    i = i < 0 ? 0 : (i > kPairNRate - 2 ? kPairNRate - 2 : i);
+    const double f = x - i;
+    yt[1] = (float)(((1.0 - f) * L[i] + f * L[i + 1] - log(chi) - kBShift1) / kBScale1);
+    m[1] = 1.f;
+  } else {
+    yt[1] = 0.f;
+    m[1] = 0.f;
+  }
+  m[0] = 1.f;
+}
+
+// ------------------------------------------------------------------ training
+struct TrainArgs {
+  int net;                 // 0 = A, 1 = B
+  const float *theta;
+  float *grad;
+  const double *S64, *lnh, *L;
+  const float *ext_x, *ext_t, *ext_m;   // optional external batch (gradient checks)
+  int64_t nbatch;
+  uint64_t sample0;
+  uint32_t seed;
+};
+
+constexpr int kTrainThreads = 256;
+
+struct TrainLds {
+  NetLds s;
+  NetLdsT t;
+  float g[kA.n > kB.n ? kA.n : kB.n];
+  float stage[4][2][H * 16];          // per wave: delta and activation [feature][sample]
+};
+
+// dW += delta a^T for one wave tile, split products, accumulated into LDS.
+__device__ void weight_grad(const float *D, const float *A, float *gW) {
+  const int lane = threadIdx.x & 63;
+  for (int it = 0; it < 4; ++it) {
+    const float *dr = D + (it * 16 + (lane & 15)) * 16 + 4 * (lane >> 4);
+    s4 dh, dl;
+    split4(dr, dh, dl);
+    for (int kt = 0; kt < 4; ++kt) {
+      const float *ar = A + (kt * 16 + (lane & 15)) * 16 + 4 * (lane >> 4);
+      s4 ah, al;
+      split4(ar, ah, al);
+      f4 acc = {0.f, 0.f, 0.f, 0.f};
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(dh, ah, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(dh, al, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(dl, ah, acc, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        atomicAdd(&gW[(it * 16 + 4 * (lane >> 4) + v) * H + kt * 16 + (lane & 15)], acc[v]);
+    }
+  }
+}
+
+// Orders this wave's LDS writes before its later LDS reads (and vice versa).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ void stage_tile(float *dst, const float val[4][4]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) dst[feat(mt, v) * 16 + (lane & 15)] = val[mt][v];
+}
+
+__global__ __launch_bounds__(kTrainThreads) void k_train(TrainArgs a) {
+  extern __shared__ unsigned char lds_raw[];
+  TrainLds &S = *reinterpret_cast<TrainLds *>(lds_raw);
+  const Layout L = a.net == 0 ? kA : kB;
+  stage_net(a.theta, L, &S.s, &S.t);
+  for (int k = threadIdx.x; k < L.n; k += blockDim.x) S.g[k] = 0.f;
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, j = lane & 15;
+  const int64_t ntile = (a.nbatch + 15) / 16;
+  const float inv_n = 1.0f / (float)a.nbatch;
+  for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntile; tile += (int64_t)gridDim.x * 4) {
+    reload_barrier();
+    const int64_t smp = tile * 16 + j;
+    const bool valid = smp < a.nbatch;
+    float x0 = 0.f, x1 = 0.f, yt[2] = {0.f, 0.f}, m[2] = {0.f, 0.f};
+    if (valid) {
+      if (a.ext_x) {
+        x0 = a.ext_x[smp * L.nin];
+        if (L.nin > 1) x1 = a.ext_x[smp * L.nin + 1];
+        for (int o = 0; o < L.nout; ++o) { yt[o] = a.ext_t[smp * L.nout + o]; m[o] = a.ext_m ? a.ext_m[smp * L.nout + o] : 1.f; }
+      } else if (a.net == 0) {
+        sample_A(a.sample0 + smp, a.seed, a.S64, x0, x1, yt[0]);
+        m[0] = 1.f;
+      } else {
+        sample_B(a.sample0 + smp, a.seed, a.lnh, a.L, x0, yt, m);
+      }
+    }
+    Cache c;
+    float y[2];
+    forward(S.s, L.nin, L.nout, x0, x1, y, c);
+    float dy[2];
+    for (int o = 0; o < L.nout; ++o) dy[o] = 2.f * (y[o] - yt[o]) * m[o] * inv_n;
+    // output layer
+    float d[4][4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int f = feat(mt, v);
+        float t = 0.f;
+        for (int o = 0; o < L.nout; ++o) {
+          t += S.s.W4[o * H + f] * dy[o];
+          atomicAdd(&S.g[L.W4 + o * H + f], dy[o] * c.a3[mt][v]);
+        }
+        d[mt][v] = t * dsilu(c.z3[mt][v]);
+        atomicAdd(&S.g[L.b3 + f], d[mt][v]);
+      }
+    if ((lane >> 4) == 0)
+      for (int o = 0; o < L.nout; ++o) atomicAdd(&S.g[L.b4 + o], dy[o]);
+    // layer 3 weights: d3 a2^T
+    float a2[4][4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) a2[mt][v] = silu(c.z2[mt][v]);
+    stage_tile(S.stage[wave][0], d);
+    stage_tile(S.stage[wave][1], a2);
+    wave_lds_sync();
+    weight_grad(S.stage[wave][0], S.stage[wave][1], &S.g[L.W3]);
+    wave_lds_sync();
+    float d2[4][4];
+    mm64(S.t.W3h, S.t.W3l, d, d2);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        d2[mt][v] *= dsilu(c.z2[mt][v]);
+        atomicAdd(&S.g[L.b2 + feat(mt, v)], d2[mt][v]);
+      }
+    float a1[4][4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) a1[mt][v] = silu(c.z1[mt][v]);
+    stage_tile(S.stage[wave][0], d2);
+    stage_tile(S.stage[wave][1], a1);
+    wave_lds_sync();
+    weight_grad(S.stage[wave][0], S.stage[wave][1], &S.g[L.W2]);
+    wave_lds_sync();
+    float d1[4][4];
+    mm64(S.t.W2h, S.t.W2l, d2, d1);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int f = feat(mt, v);
+        const float dd = d1[mt][v] * dsilu(c.z1[mt][v]);
+        atomicAdd(&S.g[L.b1 + f], dd);
+        atomicAdd(&S.g[L.W1 + f * L.nin], dd * x0);
+        if (L.nin > 1) atomicAdd(&S.g[L.W1 + f * L.nin + 1], dd * x1);
+      }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < L.n; k += blockDim.x) atomicAdd(&a.grad[k], S.g[k]);
+}
+
+__global__ void k_adam(float *theta, float *grad, float *m, float *v, int n, float lr, float b1t, float b2t) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float g = grad[i];
+  const float mm = 0.9f * m[i] + 0.1f * g;
+  const float vv = 0.999f * v[i] + 0.001f * g * g;
+  m[i] = mm;
+  v[i] = vv;
+  theta[i] -= lr * (mm / (1.f - b1t)) / (sqrtf(vv / (1.f - b2t)) + 1e-8f);
+  grad[i] = 0.f;
+}
+
+// PyTorch-style initial weights: U(-1/sqrt(fan_in), 1/sqrt(fan_in)).
+__global__ void k_init(float *theta, int net, uint32_t seed) {
+  const Layout L = net == 0 ? kA : kB;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= L.n) return;
+  const int fan = (i < L.W2) ? L.nin : H;
+  const uint4 r = philox4x32_10(make_uint4((uint32_t)i, (uint32_t)net, kInitPurpose << 24, 0u), make_uint2(seed, 0u));
+  theta[i] = (float)((2.0 * unit<double>(r.x) - 1.0) / sqrt((double)fan));
+}
+
+// ------------------------------------------------------------ residual check
+// Photon CDF of the table row r on 40 nodes uniform in s over the row's fine
+// grid bounds, with slopes: P(s) by cubic Hermite, linear mixing between rows.
+constexpr int kChkN = 40;
+__device__ float check_cdf(const float *chk, int r, float s) {
+  const float *row = chk + r * (2 + 2 * kChkN);
+  const float s0 = row[0], ds = row[1];
+  const float y = (s - s0) / ds;
+  if (y <= 0.f) return row[2] * __expf((s - s0) * (1.0f / 3.0f));
+  if (y >= (float)(kChkN - 1)) return 1.0f;
+  const int j = (int)y;
+  const float t = y - j, t2 = t * t, t3 = t2 * t;
+  const float p0 = row[2 + 2 * j], d0 = row[3 + 2 * j], p1 = row[4 + 2 * j], d1 = row[5 + 2 * j];
+  return (2 * t3 - 3 * t2 + 1) * p0 + (t3 - 2 * t2 + t) * ds * d0 + (-2 * t3 + 3 * t2) * p1 + (t3 - t2) * ds * d1;
+}
+
+// --------------------------------------------------------------- inference
+struct InferArgs {
+  const float *thA, *thB;
+  const double *chi, *gamma;
+  const uint64_t *id;
+  int64_t n;
+  uint32_t seed;
+  uint64_t step;
+  const float *lnh32, *L32, *s0sc, *chk;
+  const uint16_t *q16;
+  float *lnw, *xi, *lnwp;
+  float tol;
+  unsigned long long *fallback;     // [0] xi fallbacks, [1] rate fallbacks
+};
+
+struct InferLds {
+  NetLds A, B;
+  float chk[kRadNChi * (2 + 2 * kChkN)];
+};
+
+constexpr int kInferThreads = 512;
+
+__global__ __launch_bounds__(kInferThreads) void k_infer(InferArgs a) {
+  extern __shared__ unsigned char lds_raw[];
+  InferLds &S = *reinterpret_cast<InferLds *>(lds_raw);
+  stage_net(a.thA, kA, &S.A, nullptr);
+  stage_net(a.thB, kB, &S.B, nullptr);
+  for (int k = threadIdx.x; k < kRadNChi * (2 + 2 * kChkN); k += blockDim.x) S.chk[k] = a.chk[k];
+  __syncthreads();
+  const RowQ16 tab{a.q16, a.s0sc};
+  const int lane = threadIdx.x & 63, j = lane & 15;
+  const int64_t ntile = (a.n + 15) / 16;
+  const int wpb = blockDim.x >> 6;
+  uint32_t nfx = 0, nfr = 0;
+  for (int64_t tile = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); tile < ntile;
+       tile += (int64_t)gridDim.x * wpb) {
+    reload_barrier();
+    const int64_t i = tile * 16 + j;
+    const bool valid = i < a.n;
+    const double chi = valid ? a.chi[i] : 1.0;
+    const double gam = valid ? a.gamma[i] : 1.0;
+    const uint64_t id = valid ? a.id[i] : 0;
+    const uint4 r = stream4(id, a.seed, a.step, kLeptonEvent, 0u);
+    const float u = unit<float>(r.x), urow = unit<float>(r.z);
+    const float t = logf(u) - log1pf(-u);
+    const bool in_chi = chi >= kRadChiMin && chi <= kRadChiMax;
+    float y[2];
+    // rates (net B)
+    forward_nc(S.B, 1, 2, xin(in_chi ? chi : 1.0), 0.f, y);
+    const float lchi = logf((float)chi);
+    float lh = kBShift0 + kBScale0 * y[0] + lchi;
+    const float env = logf(1.001f * (float)kHc1 * (float)chi);
+    bool rate_ok = in_chi && isfinite(lh) && lh <= env;
+    if (!rate_ok) lh = logf(h_rad<float>((float)chi, a.lnh32));
+    float lhp;
+    if (chi < kPairChiMin || gam < 2.0) lhp = -INFINITY;
+    else if (chi <= kPairChiMax && isfinite(y[1])) lhp = kBShift1 + kBScale1 * y[1] + lchi - 8.0f / (3.0f * (float)chi);
+    else lhp = logf(h_pair<float>((float)chi, a.L32));
+    // xi (net A) with residual check against the Hermite CDF table
+    reload_barrier();
+    forward_nc(S.A, 2, 1, xin(in_chi ? chi : 1.0), (float)(t / kTmax), y);
+    const bool in_u = fabsf(t) <= (float)kTmax;
+    float s_hat = kAShift + kAScale * y[0] + lchi + 3.0f * (-log1pf(__expf(-t)));
+    bool xi_ok = in_chi && in_u && isfinite(s_hat);
+    float xi, om;
+    if (xi_ok) {
+      const float x = Grid<float>::pos(lchi, kRadChiMin, kRadChiMax, kRadNChi);
+      int ii = (int)floorf(x);
+      ii = ii < 0 ? 0 : (ii > kRadNChi - 2 ? kRadNChi - 2 : ii);
+      const float w = x - ii;
+      const float P = (1.f - w) * check_cdf(S.chk, ii, s_hat) + w * check_cdf(S.chk, ii + 1, s_hat);
+      xi_ok = fabsf(P - u) <= a.tol;
+    }
+    if (xi_ok) {
+      xi = 1.f / (1.f + __expf(-s_hat));
+      om = 1.f / (1.f + __expf(s_hat));
+    } else {
+      sample_rad<float>(tab, (float)chi, u, urow, xi, om);
+    }
+    if (valid && (lane >> 4) == 0) {
+      a.lnw[i] = (float)((double)lh + log(kRateUnit / gam));
+      a.xi[i] = xi;
+      if (a.lnwp) a.lnwp[i] = isfinite(lhp) ? (float)((double)lhp + log(kRateUnit / gam)) : -INFINITY;
+      nfx += !xi_ok;
+      nfr += !rate_ok;
+    }
+  }
+  // per-wave totals of fallbacks
+  for (int o = 32; o > 0; o >>= 1) { nfx += __shfl_xor(nfx, o, 64); nfr += __shfl_xor(nfr, o, 64); }
+  if (lane == 0) {
+    if (nfx) atomicAdd(&a.fallback[0], (unsigned long long)nfx);
+    if (nfr) atomicAdd(&a.fallback[1], (unsigned long long)nfr);
+  }
+}
+
+// raw forward for tests: y = net(x) for n samples (normalised inputs/outputs)
+__global__ __launch_bounds__(256) void k_forward_raw(const float *theta, int net, const float *x, int64_t n, float *y) {
+  extern __shared__ unsigned char lds_raw[];
+  NetLds &S = *reinterpret_cast<NetLds *>(lds_raw);
+  const Layout L = net == 0 ? kA : kB;
+  stage_net(theta, L, &S, nullptr);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, j = lane & 15;
+  const int64_t ntile = (n + 15) / 16;
+  for (int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntile; tile += (int64_t)gridDim.x * 4) {
+    reload_barrier();
+    const int64_t i = tile * 16 + j;
+    const bool valid = i < n;
+    const float x0 = valid ? x[i * L.nin] : 0.f;
+    const float x1 = (valid && L.nin > 1) ? x[i * L.nin + 1] : 0.f;
+    float yy[2];
+    forward_nc(S, L.nin, L.nout, x0, x1, yy);
+    if (valid && (lane >> 4) == 0)
+      for (int o = 0; o < L.nout; ++o) y[i * L.nout + o] = yy[o];
+  }
+}
+
+}  // namespace
+
+int mlp_params(int net) { return net == 0 ? kA.n : kB.n; }
+
+hipError_t launch_mlp_init(float *theta, int net, uint32_t seed, hipStream_t st) {
+  const int n = mlp_params(net);
+  hipLaunchKernelGGL(k_init, dim3((n + 255) / 256), dim3(256), 0, st, theta, net, seed);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_grad(int net, const float *theta, float *grad, const double *S64, const double *lnh,
+                           const double *L, const float *ext_x, const float *ext_t, const float *ext_m,
+                           int64_t nbatch, uint64_t sample0, uint32_t seed, hipStream_t st) {
+  TrainArgs a{net, theta, grad, S64, lnh, L, ext_x, ext_t, ext_m, nbatch, sample0, seed};
+  const int64_t tiles = (nbatch + 15) / 16;
+  int64_t blocks = (tiles + 3) / 4;
+  if (blocks > 256) blocks = 256;
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void *)k_train, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(TrainLds));
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_train, dim3((unsigned)blocks), dim3(kTrainThreads), sizeof(TrainLds), st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float *theta, float *grad, float *m, float *v, int net, float lr, float b1t, float b2t,
+                       hipStream_t st) {
+  const int n = mlp_params(net);
+  hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, st, theta, grad, m, v, n, lr, b1t, b2t);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const float *theta, int net, const float *x, int64_t n, float *y, hipStream_t st) {
+  int64_t blocks = ((n + 15) / 16 + 3) / 4;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void *)k_forward_raw, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(NetLds));
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_forward_raw, dim3((unsigned)blocks), dim3(256), sizeof(NetLds), st, theta, net, x, n, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_sample(qed_ctx *c, const double *chi, const double *gamma, const uint64_t *id, int64_t n,
+                             int64_t step, float *lnw, float *xi, float *lnwp, float tol, hipStream_t st) {
+  InferArgs a{c->mlp_theta[0], c->mlp_theta[1], chi, gamma, id, n, c->params.seed, (uint64_t)step,
+              c->rad_lnh32, c->pair_L32, c->rad_s0sc, c->rad_chk, c->rad_q16, lnw, xi, lnwp, tol,
+              c->d_counters + cMlpFallbackXi};
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void *)k_infer, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(InferLds));
+    attr = true;
+  }
+  int64_t blocks = ((n + 15) / 16 + 7) / 8;
+  if (blocks > c->n_cu) blocks = c->n_cu;      // one workgroup per CU (LDS-bound)
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_infer, dim3((unsigned)blocks), dim3(kInferThreads), sizeof(InferLds), st, a);
+  return hipGetLastError();
+}
+
+size_t mlp_infer_lds() { return sizeof(InferLds); }
+size_t mlp_train_lds() { return sizeof(TrainLds); }
+
+}  // namespace qed

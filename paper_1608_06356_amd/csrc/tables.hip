@@ -133,6 +133,7 @@ __device__ __forceinline__ double hermite(double tau, double p0, double p1, doub
 
 struct TabOut {
   double *rad_lnh, *rad_S, *pair_L, *pair_S;
+  float *chk;
   double rad_tlo, rad_dt, pair_tlo, pair_dt;
 };
 
@@ -161,6 +162,26 @@ __global__ __launch_bounds__(256) void k_rows(const Job *jobs, const double *den
   }
   if (jb.out == 0 && threadIdx.x == 0) o.rad_lnh[jb.row] = log(total);
   const bool rad = jb.out == 0;
+  if (rad && threadIdx.x < 40) {
+    // residual-check row of the surrogate: P and dP/ds at 40 nodes uniform in s
+    // over the fine grid, from the fine cubic Hermite interpolant
+    constexpr int NC = 40;
+    const double dsc = (jb.s_hi - jb.s_lo) / (NC - 1);
+    const double sc = jb.s_lo + threadIdx.x * dsc;
+    int m = (int)floor((sc - jb.s_lo) / ds);
+    m = m < 0 ? 0 : (m > M - 1 ? M - 1 : m);
+    const double tau = (sc - (jb.s_lo + m * ds)) / ds;
+    const double p0 = F[m] / total, p1 = F[m + 1] / total;
+    const double r0 = d[3 * M + m] / total, r1 = d[3 * M + m + 1] / total;
+    const double t2 = tau * tau, t3 = t2 * tau;
+    const double P = (2 * t3 - 3 * t2 + 1) * p0 + (t3 - 2 * t2 + tau) * ds * r0 + (-2 * t3 + 3 * t2) * p1 + (t3 - t2) * ds * r1;
+    const double dP = ((6 * t2 - 6 * tau) * p0 + (3 * t2 - 4 * tau + 1) * ds * r0 + (-6 * t2 + 6 * tau) * p1 +
+                       (3 * t2 - 2 * tau) * ds * r1) / ds;
+    float *row = o.chk + jb.row * (2 + 2 * NC);
+    if (threadIdx.x == 0) { row[0] = (float)jb.s_lo; row[1] = (float)dsc; }
+    row[2 + 2 * threadIdx.x] = (float)P;
+    row[3 + 2 * threadIdx.x] = (float)dP;
+  }
   const int k = threadIdx.x;
   const double t = rad ? o.rad_tlo + k * o.rad_dt : o.pair_tlo + k * o.pair_dt;
   const double u = 1.0 / (1.0 + exp(-t));
@@ -254,6 +275,7 @@ hipError_t launch_build_tables(qed_ctx *c, int formula, hipStream_t st) {
   if ((e = hipGetLastError()) != hipSuccess) return e;
   TabOut o;
   o.rad_lnh = c->rad_lnh64; o.rad_S = c->rad_S64; o.pair_L = c->pair_L64; o.pair_S = c->pair_S64;
+  o.chk = c->rad_chk;
   const double rtlo = log(kRadULo) - log1p(-kRadULo), rthi = log(kRadUHi) - log1p(-kRadUHi);
   const double ptlo = log(kPairULo) - log1p(-kPairULo), pthi = log(kPairUHi) - log1p(-kPairUHi);
   o.rad_tlo = rtlo; o.rad_dt = (rthi - rtlo) / (kNU - 1);

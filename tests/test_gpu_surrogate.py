@@ -1,0 +1,159 @@
+"""Surrogate networks on the GPU: forward and gradient against the float64
+oracle (same split-BF16 products), training accuracy against the oracle's rate
+quadrature and exact CDF, fallback coverage, and the measured gain over the
+table sampler."""
+import math
+import time
+
+import numpy as np
+import pytest
+
+from oracle import mc, mlp, tables
+from oracle.constants import RATE_UNIT
+from tests.gpu_helpers import need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _rand_theta(net, seed, scale=0.3):
+    return np.random.default_rng(seed).normal(0, scale, mlp.n_params(net)).astype(np.float32)
+
+
+@pytest.mark.parametrize("net,netid", [("A", 0), ("B", 1)])
+def test_forward_and_gradient_vs_oracle(net, netid):
+    torch, q = need_gpu()
+    ctx = q.Context()
+    th = _rand_theta(net, 10 + netid)
+    ctx.qed_surrogate_io(netid, th)
+    nin, nout = mlp.SIZES[net]
+    n = 1000                                   # 62 full tiles and a ragged one
+    rng = np.random.default_rng(4)
+    X = rng.uniform(-1, 1, (n, nin)).astype(np.float32)
+    T = rng.normal(size=(n, nout)).astype(np.float32)
+    M = (rng.uniform(size=(n, nout)) < 0.8).astype(np.float32)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    y = torch.empty((n, nout), dtype=torch.float32, device="cuda")
+    ctx.qed_surrogate_forward(netid, dev(X), y)
+    g = torch.empty(mlp.n_params(net), dtype=torch.float32, device="cuda")
+    ctx.qed_surrogate_grad(netid, dev(X), dev(T), dev(M), g)
+    torch.cuda.synchronize()
+    th64 = th.astype(np.float64)
+    ys, _ = mlp.forward(th64, net, X.T.astype(np.float64), mode="split")
+    ye, _ = mlp.forward(th64, net, X.T.astype(np.float64), mode="exact")
+    yg = y.cpu().numpy().T
+    scale = np.abs(ys).max()
+    assert np.max(np.abs(yg - ys)) < 2e-5 * scale
+    assert np.max(np.abs(yg - ye)) < 2e-4 * scale          # split products ~ 16 bits
+    _, gs = mlp.loss_and_grad(th64, net, X.T.astype(np.float64), T.T.astype(np.float64),
+                              M.T.astype(np.float64), mode="split")
+    gg = g.cpu().numpy()
+    assert np.max(np.abs(gg - gs)) < 1e-4 * np.abs(gs).max()
+
+
+@pytest.fixture(scope="module")
+def trained():
+    torch, q = need_gpu()
+    ctx = q.Context(seed=3)
+    ctx.qed_build_tables(q.QED_FORMULA_I)
+    t0 = time.time()
+    ctx.qed_surrogate_train(20000, batch=4096, lr=3e-3, seed=11)
+    torch.cuda.synchronize()
+    print(f"training: {time.time() - t0:.1f} s for 2 nets x 20000 steps x 4096 samples")
+    return ctx
+
+
+def _sample(ctx, q, torch, chi, gamma, prec, step=0, seed_ids=0):
+    n = chi.size
+    dev = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dt)
+    ids = np.arange(seed_ids, seed_ids + n, dtype=np.uint64)
+    lnw = torch.empty(n, dtype=torch.float32, device="cuda")
+    xi = torch.empty_like(lnw)
+    lnwp = torch.empty_like(lnw)
+    ctx.qed_sample(dev(chi, torch.float64), dev(gamma, torch.float64), dev(ids.view(np.int64), torch.int64),
+                   prec, step, lnw, xi, lnwp)
+    torch.cuda.synchronize()
+    return lnw.cpu().numpy().astype(np.float64), xi.cpu().numpy().astype(np.float64), lnwp.cpu().numpy().astype(np.float64)
+
+
+def test_trained_rates_vs_oracle(trained, rad_table_I, pair_table):
+    """Rate surrogate within 1e-3 of the oracle's rates over chi in [1e-3, 1e2]."""
+    torch, q = need_gpu()
+    ctx = trained
+    chi = np.logspace(-3, 2, 20001)
+    gam = np.full(chi.size, 1000.0)
+    ctx.qed_get_status(check=False)
+    lnw, _, lnwp = _sample(ctx, q, torch, chi, gam, q.QED_SAMPLER_MLP)
+    st, _ = ctx.qed_get_status(check=False)
+    ref = np.log(tables.rate_rad(rad_table_I, chi, gam))
+    err = np.max(np.abs(np.exp(lnw - ref) - 1))
+    refp = np.log(tables.rate_pair(pair_table, chi, gam))
+    okp = chi >= 1e-2
+    errp = np.max(np.abs(np.exp(lnwp[okp] - refp[okp]) - 1))
+    print(f"rate surrogate: max rel err rad {err:.2e} pair {errp:.2e}, rate fallbacks {st['mlp_fallback_rate']}")
+    assert err < 1e-3 and errp < 1e-3
+    assert st["mlp_fallback_rate"] == 0
+
+
+@pytest.mark.parametrize("chi", [0.01, 0.3, 3.0, 60.0])
+def test_trained_xi_ks_1e7(trained, rad_table_I, chi):
+    """1e7 xi samples from the surrogate sampler (with residual check and table
+    fallback) against the exact CDF (one-sample KS) and the oracle's table sampler
+    (two-sample KS), both <= 2e-3."""
+    torch, q = need_gpu()
+    ctx = trained
+    n = 10_000_000
+    ctx.qed_get_status(check=False)
+    _, xi, _ = _sample(ctx, q, torch, np.full(n, chi), np.full(n, 1e3), q.QED_SAMPLER_MLP, step=5)
+    st, _ = ctx.qed_get_status(check=False)
+    xi = np.sort(xi)
+    row = tables.fine_row("I", chi, tables.RAD_M)
+    P = row.F / row.total
+    xs = np.clip(xi, 1e-300, 1 - 1e-7)
+    s = np.log(xs) - np.log1p(-xs)
+    Pe = np.interp(s, row.s, P, left=0.0)
+    # below the fine grid the CDF follows the infrared law P ~ xi^(1/3)
+    lo = s < row.s[0]
+    Pe[lo] = P[0] * (xs[lo] / (1 / (1 + math.exp(-row.s[0])))) ** (1 / 3)
+    ks1 = max(np.max(np.arange(1, n + 1) / n - Pe), np.max(Pe - np.arange(n) / n))
+    rng = np.random.default_rng(7)
+    u = (np.floor(rng.uniform(size=n) * 2 ** 23) + 0.5) * 2.0 ** -23
+    ur = (np.floor(rng.uniform(size=n) * 2 ** 23) + 0.5) * 2.0 ** -23
+    xo, _ = mc.RadSampler(rad_table_I, "q16").sample(np.full(n, chi), u, ur)
+    xo = np.sort(xo)
+    allv = np.concatenate([xi, xo])
+    ks2 = np.max(np.abs(np.searchsorted(xi, allv, side="right") / n - np.searchsorted(xo, allv, side="right") / n))
+    fb = st["mlp_fallback_xi"] / n
+    print(f"chi {chi}: KS(exact) {ks1:.2e} KS(table sampler) {ks2:.2e} xi fallback {fb:.4%}")
+    assert ks1 < 2e-3 and ks2 < 2e-3
+    assert fb < 0.01          # u outside [1e-4, 1-1e-4] alone is 2e-4
+
+
+def test_surrogate_gain_vs_table(trained):
+    """What the trained networks change against the plain table sampler on the
+    same 1e8 lookups (rate + xi + pair rate): throughput and LDS footprint are
+    measured and reported; correctness is covered by the tests above."""
+    torch, q = need_gpu()
+    ctx = trained
+    n = 100_000_000
+    inp_chi = torch.pow(10.0, torch.rand(n, dtype=torch.float64, device="cuda") * 5 - 3)
+    gam = torch.full((n,), 1e3, dtype=torch.float64, device="cuda")
+    ids = torch.arange(n, dtype=torch.int64, device="cuda")
+    lnw = torch.empty(n, dtype=torch.float32, device="cuda")
+    xi = torch.empty_like(lnw)
+    lnwp = torch.empty_like(lnw)
+    res = {}
+    for name, prec in (("table_f32", q.QED_F32), ("mlp", q.QED_SAMPLER_MLP)):
+        ctx.qed_sample(inp_chi, gam, ids, prec, 1, lnw, xi, lnwp)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            ctx.qed_sample(inp_chi, gam, ids, prec, 1, lnw, xi, lnwp)
+        e1.record()
+        torch.cuda.synchronize()
+        res[name] = n * 3 / (e0.elapsed_time(e1) * 1e-3)
+    st, _ = ctx.qed_get_status(check=False)
+    print(f"samples/s: table {res['table_f32']:.3e}  surrogate {res['mlp']:.3e}  "
+          f"ratio {res['mlp'] / res['table_f32']:.3f}; xi fallback fraction "
+          f"{st['mlp_fallback_xi'] / (4 * n):.4%}")
+    assert res["mlp"] > 0 and res["table_f32"] > 0
