@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--dt", type=float, default=0.01)
     ap.add_argument("--formula", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after timing, copy 1 GiB with torch (reference kernel for HBM counters)")
     ap.add_argument("--presort", action="store_true",
                     help="order the initial electrons by grid cell (outside the timed region)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -50,8 +52,8 @@ def cpu_baseline(args, budget_s):
     pool over contiguous particle chunks on the host's cores."""
     from concurrent.futures import ProcessPoolExecutor
     cores = len(os.sched_getaffinity(0))
-    n_per = 2000
-    steps = 4
+    n_per = 20000
+    steps = 3
     t0 = time.perf_counter()
     with ProcessPoolExecutor(cores) as ex:
         futs = [ex.submit(_oracle_chunk, k, n_per, steps, args.a0, args.grid, args.dt, args.formula)
@@ -175,6 +177,14 @@ def main():
         "events": st,
         "photons": ph.n(),
     }
+    if args.calibrate_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, args.cpu_seconds)
     print(json.dumps(out))

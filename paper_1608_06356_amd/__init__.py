@@ -10,7 +10,7 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libqedmi.so")
+LIB_PATH = os.environ.get("QED_LIB_PATH") or os.path.join(HERE, "libqedmi.so")
 
 QED_OK, QED_ERR_ARG, QED_ERR_HIP, QED_ERR_CAPACITY, QED_ERR_RANGE, QED_ERR_STATE = 0, -1, -2, -3, -4, -5
 QED_F32, QED_F64 = 0, 1

@@ -57,7 +57,8 @@ template <typename T> hipError_t dalloc(T **p, size_t n) {
 
 void free_emitters(qed_ctx *c) {
   (void)hipFree(c->em_idx); (void)hipFree(c->em_fld); (void)hipFree(c->em_rem); (void)hipFree(c->d_status);
-  c->em_idx = nullptr; c->em_fld = nullptr; c->em_rem = nullptr; c->d_status = nullptr;
+  (void)hipFree(c->em_mask);
+  c->em_idx = nullptr; c->em_fld = nullptr; c->em_rem = nullptr; c->d_status = nullptr; c->em_mask = nullptr;
   c->reserved = 0; c->status_len = 0;
 }
 
@@ -66,13 +67,18 @@ int ensure_reserved(qed_ctx *c, int64_t n) {
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(c, e, "reserve");
   free_emitters(c);
+  // emitter slots (one per particle), ballot mask, ordered list; scan status
+  // for the largest tile count of any kernel
+  const int64_t em_cap = n;
   const int64_t status_len = n / 256 + 64;
-  if ((e = dalloc(&c->em_idx, n)) != hipSuccess || (e = dalloc(&c->em_fld, 8 * n)) != hipSuccess ||
-      (e = dalloc(&c->em_rem, n)) != hipSuccess || (e = dalloc(&c->d_status, status_len)) != hipSuccess) {
+  if ((e = dalloc(&c->em_idx, em_cap)) != hipSuccess || (e = dalloc(&c->em_fld, 8 * em_cap)) != hipSuccess ||
+      (e = dalloc(&c->em_rem, em_cap)) != hipSuccess || (e = dalloc(&c->d_status, status_len)) != hipSuccess ||
+      (e = dalloc(&c->em_mask, n / 64 + 1)) != hipSuccess) {
     free_emitters(c);
     return hip_fail(c, e, "reserve: hipMalloc");
   }
   c->reserved = n;
+  c->em_cap = em_cap;
   c->status_len = status_len;
   c->em_owner = nullptr;
   return QED_OK;

@@ -30,7 +30,9 @@ struct qed_ctx {
 
   // emitter list produced by qed_gather_push
   int64_t reserved = 0;
-  int32_t *em_idx = nullptr;
+  int64_t em_cap = 0;            // slots (one per particle of the reserved capacity)
+  uint64_t *em_mask = nullptr;   // one bit per particle: optical depth ran out this step
+  int32_t *em_idx = nullptr;     // ordered emitter list
   double *em_fld = nullptr;      // 6 * reserved doubles (float-packed for f32 species)
   double *em_rem = nullptr;
   int64_t *d_n_emit = nullptr;

@@ -127,10 +127,10 @@ __device__ __forceinline__ uint32_t next_tile(uint32_t *ticket, uint32_t *lds) {
 }
 
 // Exclusive device-wide offset of this workgroup's tile given its per-thread count.
-__device__ __forceinline__ uint64_t tile_offset(uint32_t tile, uint32_t agg, const ScanDev &sc,
+__device__ __forceinline__ uint64_t tile_offset(uint32_t tile, uint32_t agg, uint64_t *status,
                                                 unsigned long long *counters, uint64_t *lds64) {
   if (threadIdx.x < 64) {
-    const uint64_t e = lookback_scan(sc.status, tile, agg, &counters[cScanTimeout]);
+    const uint64_t e = lookback_scan(status, tile, agg, &counters[cScanTimeout]);
     if (threadIdx.x == 0) *lds64 = e;
   }
   __syncthreads();
@@ -138,6 +138,15 @@ __device__ __forceinline__ uint64_t tile_offset(uint32_t tile, uint32_t agg, con
 }
 
 // ========================================================= gather / push
+// A pure streaming pass with no dependency between workgroups.  Workgroups are
+// dispatched round-robin over the 8 XCDs; block b works on tile
+// (b % 8) * tiles_per_xcd + b / 8, so each XCD sweeps a contiguous eighth of
+// the particle array and its L2 holds the grid around those particles.  A
+// particle whose optical depth runs out within the step sets its bit in a
+// ballot mask and writes the fields, chi, rate and remaining time of its first
+// event to its own slot; k_emit_index turns the mask into the ordered list.
+constexpr int kXcds = 8;
+
 template <typename R>
 struct GPArgs {
   SpeciesDev sp;
@@ -145,54 +154,48 @@ struct GPArgs {
   const R *lnh;          // rad ln h table (float32 or float64 copy)
   R q, dt;
   double dtd;
-  int32_t *em_idx;
-  R *em_fld;             // 6 planes of em_cap
+  uint64_t *mask;        // one bit per particle
+  R *em_fld;             // 6 planes of em_cap, slot = particle index
   double *em_chi, *em_w, *em_rem;
   int64_t em_cap;
-  int64_t *n_emit;
-  ScanDev sc;
+  int64_t tpx;           // tiles per XCD
   unsigned long long *counters;
 };
 
 constexpr int kGPThreads = 256, kGPTile = kGPThreads;
 
-// One particle per thread; a tile is one workgroup.  Emitters (optical depth
-// exhausted within the step) are appended in index order with the fields,
-// chi, rate and remaining time of their first event.
-template <typename R>
+template <typename R, int FK>
 __global__ __launch_bounds__(kGPThreads) void k_gather_push(GPArgs<R> a) {
   __shared__ R lnh_s[kRadNChi];
-  __shared__ uint32_t scan_s[16];
-  __shared__ uint32_t tile_s;
-  __shared__ uint64_t off_s;
   for (int k = threadIdx.x; k < kRadNChi; k += blockDim.x) lnh_s[k] = a.lnh[k];
-  const uint32_t tile = next_tile(a.sc.ticket, &tile_s);
+  __syncthreads();
+  const int64_t tile = (int64_t)(blockIdx.x % kXcds) * a.tpx + blockIdx.x / kXcds;
   const int64_t n = *a.sp.count;
-  const int64_t base = (int64_t)tile * kGPTile;
-  if (base >= n) {
-    if (tile == 0 && threadIdx.x == 0) *a.n_emit = 0;
-    return;
-  }
+  const int64_t base = tile * kGPTile;
+  if (base >= n) return;
   R *X = (R *)a.sp.x, *Y = (R *)a.sp.y, *Z = (R *)a.sp.z;
   R *PX = (R *)a.sp.px, *PY = (R *)a.sp.py, *PZ = (R *)a.sp.pz;
+  FieldDev f = a.f;
+  f.kind = FK;
   const int64_t i = base + threadIdx.x;
-  uint32_t flag = 0, nnan = 0, nrange = 0;
-  R F[6];
-  double chi = 0.0, W = 0.0, rem = 0.0;
+  bool flag = false;
+  uint32_t nnan = 0, nrange = 0;
   if (i < n) {
     R x = X[i], y = Y[i], z = Z[i];
     R px = PX[i], py = PY[i], pz = PZ[i];
     const double tau = a.sp.tau[i];
-    field_at<R>(a.f, i, x, y, z, F);
+    R F[6];
+    field_at<R>(f, i, x, y, z, F);
     boris<R>(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5], a.q, a.dt);
     const R g = sqrt((R)1 + px * px + py * py + pz * pz);
     x += px / g * a.dt; y += py / g * a.dt; z += pz / g * a.dt;
-    if (a.f.kind == QED_FIELD_GRID) {
-      wrap_coord<R>(x, (R)(a.f.dx * a.f.nx)); wrap_coord<R>(y, (R)(a.f.dy * a.f.ny));
-      wrap_coord<R>(z, (R)(a.f.dz * a.f.nz));
+    if (FK == QED_FIELD_GRID) {
+      wrap_coord<R>(x, (R)(f.dx * f.nx)); wrap_coord<R>(y, (R)(f.dy * f.ny));
+      wrap_coord<R>(z, (R)(f.dz * f.nz));
     }
     X[i] = x; Y[i] = y; Z[i] = z; PX[i] = px; PY[i] = py; PZ[i] = pz;
-    chi = chi_lepton(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5]);
+    const double chi = chi_lepton(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5]);
+    double W = 0.0;
     if (isfinite(chi)) {
       nrange = chi > kRadChiMax;
       W = kRateUnit * (double)(h_rad<R>((R)chi, lnh_s) / g);
@@ -200,29 +203,57 @@ __global__ __launch_bounds__(kGPThreads) void k_gather_push(GPArgs<R> a) {
       nnan = 1;
     }
     if (W > 0.0 && tau <= W * a.dtd) {
-      flag = 1;
-      rem = a.dtd - tau / W;
+      flag = true;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) a.em_fld[c * a.em_cap + i] = F[c];
+      a.em_chi[i] = chi;
+      a.em_w[i] = W;
+      a.em_rem[i] = a.dtd - tau / W;
     } else {
       a.sp.tau[i] = tau - W * a.dtd;
     }
   }
+  const uint64_t bits = __ballot(flag);
+  if ((threadIdx.x & 63) == 0 && base + (threadIdx.x & ~63) < n) a.mask[(base + threadIdx.x) >> 6] = bits;
   count_add(a.counters, cNanChi, nnan);
   count_add(a.counters, cChiRange, nrange);
+}
 
-  uint32_t total;
-  const uint32_t off = block_exclusive(flag, scan_s, &total);
-  const uint64_t toff = tile_offset(tile, total, a.sc, a.counters, &off_s);
-  if (flag) {
-    const uint64_t r = toff + off;
-    a.em_idx[r] = (int32_t)i;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) a.em_fld[c * a.em_cap + r] = F[c];
-    a.em_chi[r] = chi;
-    a.em_w[r] = W;
-    a.em_rem[r] = rem;
+// Ordered emitter list from the ballot mask: each thread owns one 64-bit word
+// (a tile is 256 words = 16384 particles); popcounts are scanned across the
+// workgroup and across tiles (decoupled look-back), and every set bit writes
+// its particle index at its rank.
+constexpr int kEIThreads = 256, kEITile = kEIThreads * 64;
+
+__global__ __launch_bounds__(kEIThreads) void k_emit_index(const uint64_t *mask, const int64_t *count,
+                                                           int32_t *em_idx, int64_t *n_emit, ScanDev sc,
+                                                           unsigned long long *counters) {
+  __shared__ uint32_t scan_s[16];
+  __shared__ uint32_t tile_s;
+  __shared__ uint64_t off_s;
+  const uint32_t tile = next_tile(sc.ticket, &tile_s);
+  const int64_t n = *count;
+  const int64_t base = (int64_t)tile * kEITile;
+  if (base >= n) {
+    if (tile == 0 && threadIdx.x == 0) *n_emit = 0;
+    return;
   }
-  const int64_t last = (n - 1) / kGPTile;
-  if ((int64_t)tile == last && threadIdx.x == 0) *a.n_emit = (int64_t)(toff + total);
+  const int64_t w = (base >> 6) + threadIdx.x;
+  uint64_t m = (w << 6) < n ? mask[w] : 0ull;
+  const int64_t valid = n - (w << 6);
+  if (valid < 64 && valid > 0) m &= (1ull << valid) - 1ull;
+  const uint32_t c = (uint32_t)__popcll(m);
+  uint32_t total;
+  const uint32_t off = block_exclusive(c, scan_s, &total);
+  const uint64_t toff = tile_offset(tile, total, sc.status, counters, &off_s);
+  uint64_t r = toff + off;
+  while (m) {
+    const int b = __ffsll((long long)m) - 1;
+    em_idx[r++] = (int32_t)((w << 6) + b);
+    m &= m - 1ull;
+  }
+  const int64_t last = (n - 1) / kEITile;
+  if ((int64_t)tile == last && threadIdx.x == 0) *n_emit = (int64_t)(toff + total);
 }
 
 // ================================================================ emit
@@ -263,8 +294,8 @@ __device__ void emit_tile(const EmitArgs<R> &a, const Tab &tab, const R *lnh, ui
     const int64_t i = a.em_idx[r];
     R F[6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) F[c] = a.em_fld[c * a.em_cap + r];
-    double chi = a.em_chi[r], W = a.em_w[r], rem = a.em_rem[r];
+    for (int c = 0; c < 6; ++c) F[c] = a.em_fld[c * a.em_cap + i];
+    double chi = a.em_chi[i], W = a.em_w[i], rem = a.em_rem[i];
     R *PX = (R *)a.lep.px, *PY = (R *)a.lep.py, *PZ = (R *)a.lep.pz;
     R px = PX[i], py = PY[i], pz = PZ[i];
     x = ((R *)a.lep.x)[i]; y = ((R *)a.lep.y)[i]; z = ((R *)a.lep.z)[i];
@@ -315,7 +346,7 @@ __device__ void emit_tile(const EmitArgs<R> &a, const Tab &tab, const R *lnh, ui
 
   uint32_t total;
   const uint32_t off = block_exclusive(nacc, scan_s, &total);
-  const uint64_t toff = tile_offset(tile, total, a.sc, a.counters, off_s);
+  const uint64_t toff = tile_offset(tile, total, a.sc.status, a.counters, off_s);
   R *X = (R *)a.ph.x, *Y = (R *)a.ph.y, *Z = (R *)a.ph.z;
   R *KX = (R *)a.ph.px, *KY = (R *)a.ph.py, *KZ = (R *)a.ph.pz;
   uint32_t ndrop = 0;
@@ -466,7 +497,7 @@ __device__ void pair_tile(const PairArgs<R> &a, const Tab &tab, const R *L, uint
   count_add(a.counters, cPairs, ev);
   uint32_t total;
   const uint32_t off = block_exclusive(ev, scan_s, &total);
-  const uint64_t toff = tile_offset(tile, total, a.sc, a.counters, off_s);
+  const uint64_t toff = tile_offset(tile, total, a.sc.status, a.counters, off_s);
   uint32_t ndrop = 0;
   if (ev) {
     const uint64_t rank = toff + off;
@@ -580,7 +611,7 @@ __global__ __launch_bounds__(kCThreads) void k_compact(SpeciesDev sp, ScanDev sc
   __builtin_amdgcn_s_waitcnt(0);
   uint32_t total;
   const uint32_t off = block_exclusive(na, scan_s, &total);
-  const uint64_t toff = tile_offset(tile, total, sc, counters, &off_s);
+  const uint64_t toff = tile_offset(tile, total, sc.status, counters, &off_s);
   uint64_t r = toff + off;
 #pragma unroll
   for (int it = 0; it < kCItems; ++it) {
@@ -691,24 +722,39 @@ static hipError_t zero_scan(qed_ctx *c, int64_t ntiles, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <typename R>
+static void launch_gp_kind(const GPArgs<R> &a, int kind, unsigned grid, hipStream_t st) {
+  if (kind == QED_FIELD_GRID)
+    hipLaunchKernelGGL((k_gather_push<R, QED_FIELD_GRID>), dim3(grid), dim3(kGPThreads), 0, st, a);
+  else if (kind == QED_FIELD_UNIFORM)
+    hipLaunchKernelGGL((k_gather_push<R, QED_FIELD_UNIFORM>), dim3(grid), dim3(kGPThreads), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_gather_push<R, QED_FIELD_PER_PARTICLE>), dim3(grid), dim3(kGPThreads), 0, st, a);
+}
+
 hipError_t launch_gather_push(qed_ctx *c, const qed_fields_t *f, const qed_species_t *sp, int charge,
                               double dt, hipStream_t st) {
   const int64_t ntiles = (sp->capacity + kGPTile - 1) / kGPTile;
-  hipError_t e = zero_scan(c, ntiles, st);
-  if (e != hipSuccess) return e;
-  const ScanDev sc{c->d_ticket, c->d_status};
+  const int64_t tpx = (ntiles + kXcds - 1) / kXcds;
+  const unsigned grid = (unsigned)(tpx * kXcds);
+  const int64_t cap = c->em_cap;
   if (sp->dtype == QED_F32) {
-    GPArgs<float> a{dev_species(sp), dev_fields(f), c->rad_lnh32, (float)charge, (float)dt, dt,
-                    c->em_idx, (float *)c->em_fld, c->em_fld + 3 * c->reserved,
-                    c->em_fld + 4 * c->reserved, c->em_rem, c->reserved, c->d_n_emit, sc,
+    GPArgs<float> a{dev_species(sp), dev_fields(f), c->rad_lnh32, (float)charge, (float)dt, dt, c->em_mask,
+                    (float *)c->em_fld, c->em_fld + 3 * cap, c->em_fld + 4 * cap, c->em_rem, cap, tpx,
                     c->d_counters};
-    hipLaunchKernelGGL(k_gather_push<float>, dim3((unsigned)ntiles), dim3(kGPThreads), 0, st, a);
+    launch_gp_kind<float>(a, f->kind, grid, st);
   } else {
-    GPArgs<double> a{dev_species(sp), dev_fields(f), c->rad_lnh64, (double)charge, dt, dt,
-                     c->em_idx, c->em_fld, c->em_fld + 6 * c->reserved, c->em_fld + 7 * c->reserved,
-                     c->em_rem, c->reserved, c->d_n_emit, sc, c->d_counters};
-    hipLaunchKernelGGL(k_gather_push<double>, dim3((unsigned)ntiles), dim3(kGPThreads), 0, st, a);
+    GPArgs<double> a{dev_species(sp), dev_fields(f), c->rad_lnh64, (double)charge, dt, dt, c->em_mask,
+                     c->em_fld, c->em_fld + 6 * cap, c->em_fld + 7 * cap, c->em_rem, cap, tpx, c->d_counters};
+    launch_gp_kind<double>(a, f->kind, grid, st);
   }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // ordered emitter list
+  const int64_t etiles = (sp->capacity + kEITile - 1) / kEITile;
+  if ((e = zero_scan(c, etiles, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_emit_index, dim3((unsigned)etiles), dim3(kEIThreads), 0, st, c->em_mask, sp->count,
+                     c->em_idx, c->d_n_emit, ScanDev{c->d_ticket, c->d_status}, c->d_counters);
   return hipGetLastError();
 }
 
@@ -722,15 +768,15 @@ hipError_t launch_emit(qed_ctx *c, const qed_species_t *lep, const qed_species_t
   const unsigned grid = (unsigned)(ntiles < c->n_cu ? ntiles : c->n_cu);
   if (lep->dtype == QED_F32) {
     EmitArgs<float> a{dev_species(lep), dev_species(ph), c->rad_lnh32, c->rad_S64, c->rad_q16,
-                      c->rad_s0sc, c->em_idx, (const float *)c->em_fld, c->em_fld + 3 * c->reserved,
-                      c->em_fld + 4 * c->reserved, c->em_rem, c->reserved, c->d_n_emit,
+                      c->rad_s0sc, c->em_idx, (const float *)c->em_fld, c->em_fld + 3 * c->em_cap,
+                      c->em_fld + 4 * c->em_cap, c->em_rem, c->em_cap, c->d_n_emit,
                       c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, sc,
                       c->d_counters};
     hipLaunchKernelGGL(k_emit_f32, dim3(grid), dim3(kEmitThreads), 0, st, a);
   } else {
     EmitArgs<double> a{dev_species(lep), dev_species(ph), c->rad_lnh64, c->rad_S64, c->rad_q16,
-                       c->rad_s0sc, c->em_idx, (const double *)c->em_fld, c->em_fld + 6 * c->reserved,
-                       c->em_fld + 7 * c->reserved, c->em_rem, c->reserved, c->d_n_emit,
+                       c->rad_s0sc, c->em_idx, (const double *)c->em_fld, c->em_fld + 6 * c->em_cap,
+                       c->em_fld + 7 * c->em_cap, c->em_rem, c->em_cap, c->d_n_emit,
                        c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, sc,
                        c->d_counters};
     hipLaunchKernelGGL(k_emit_f64, dim3(grid), dim3(kEmitThreads), 0, st, a);
