@@ -208,6 +208,15 @@ QED_API int qed_create_pairs(qed_ctx_t ctx, const qed_fields_t *fields, qed_spec
                      qed_species_t *electrons, qed_species_t *positrons, double dt,
                      int64_t step, void *stream);
 
+/* Stable reordering of src into dst (caller-owned, same dtype, capacity >= src's)
+   by the grid cell of each particle's nearest node, so that the quadratic-spline
+   gather of neighbouring threads reads neighbouring nodes.  Ids, optical depths
+   and therefore every random stream move with the particles.  A periodic sort is
+   what keeps qed_gather_push's field reads local.  Allocates its scratch on the
+   first call for a given capacity (call once before graph capture). */
+QED_API int qed_sort_by_cell(qed_ctx_t ctx, const qed_fields_t *fields, qed_species_t *src,
+                             qed_species_t *dst, void *stream);
+
 /* Stable in-place removal of particles whose id is QED_DEAD_ID. */
 QED_API int qed_compact(qed_ctx_t ctx, qed_species_t *sp, void *stream);
 

@@ -23,7 +23,8 @@ EXPORTS = ["qed_create", "qed_destroy", "qed_last_error", "qed_reserve", "qed_se
            "qed_get_next_id", "qed_build_tables", "qed_get_table", "qed_init_optical_depth",
            "qed_fill_standing_wave", "qed_gather_push", "qed_emit_photons", "qed_create_pairs",
            "qed_compact", "qed_sample", "qed_get_status", "qed_surrogate_params",
-           "qed_surrogate_train", "qed_surrogate_io", "qed_surrogate_forward", "qed_surrogate_grad"]
+           "qed_surrogate_train", "qed_surrogate_io", "qed_surrogate_forward", "qed_surrogate_grad",
+           "qed_sort_by_cell"]
 
 
 class qed_params_t(ctypes.Structure):
@@ -94,6 +95,8 @@ def lib():
             "qed_compact": (ctypes.c_int, [vp, ctypes.POINTER(qed_species_t), vp]),
             "qed_sample": (ctypes.c_int, [vp, vp, vp, vp, i64, ctypes.c_int, i64, vp, vp, vp, vp]),
             "qed_get_status": (ctypes.c_int, [vp, ctypes.POINTER(qed_counters_t), vp]),
+            "qed_sort_by_cell": (ctypes.c_int, [vp, ctypes.POINTER(qed_fields_t), ctypes.POINTER(qed_species_t),
+                                                ctypes.POINTER(qed_species_t), vp]),
             "qed_surrogate_params": (ctypes.c_int, [ctypes.c_int]),
             "qed_surrogate_train": (ctypes.c_int, [vp, ctypes.POINTER(qed_train_spec_t), vp]),
             "qed_surrogate_io": (ctypes.c_int, [vp, ctypes.c_int, vp, ctypes.c_size_t, ctypes.c_int]),
@@ -191,6 +194,10 @@ class Context:
         return self._check(lib().qed_create_pairs(self.h, ctypes.byref(fields.c), ctypes.byref(photons.c),
                                                   ctypes.byref(electrons.c), ctypes.byref(positrons.c),
                                                   float(dt), int(step), _stream(stream)))
+
+    def qed_sort_by_cell(self, fields, src, dst, stream=None):
+        return self._check(lib().qed_sort_by_cell(self.h, ctypes.byref(fields.c), ctypes.byref(src.c),
+                                                  ctypes.byref(dst.c), _stream(stream)))
 
     def qed_compact(self, sp, stream=None):
         return self._check(lib().qed_compact(self.h, ctypes.byref(sp.c), _stream(stream)))

@@ -123,7 +123,8 @@ void qed_destroy(qed_ctx_t c) {
   void *ptrs[] = {c->rad_lnh64, c->rad_S64, c->rad_lnh32, c->rad_s0sc, c->rad_q16, c->pair_L64,
                   c->pair_S64, c->pair_L32, c->pair_s0sc, c->pair_q16, c->tab_work, c->d_counters,
                   c->d_next_id, c->d_n_emit, c->d_ticket, c->rad_chk, c->mlp_theta[0], c->mlp_theta[1],
-                  c->mlp_grad[0], c->mlp_grad[1], c->mlp_m[0], c->mlp_m[1], c->mlp_v[0], c->mlp_v[1]};
+                  c->mlp_grad[0], c->mlp_grad[1], c->mlp_m[0], c->mlp_m[1], c->mlp_v[0], c->mlp_v[1],
+                  c->sort_keys, c->sort_vals, c->sort_tmp};
   for (void *p : ptrs) (void)hipFree(p);
   delete c;
 }
@@ -272,6 +273,20 @@ int qed_compact(qed_ctx_t c, qed_species_t *sp, void *st) {
   if ((r = ensure_reserved(c, sp->capacity))) return r;
   hipError_t e = qed::launch_compact(c, sp, S(st));
   return e == hipSuccess ? QED_OK : hip_fail(c, e, "compact");
+}
+
+int qed_sort_by_cell(qed_ctx_t c, const qed_fields_t *f, qed_species_t *src, qed_species_t *dst, void *st) {
+  if (!c) return QED_ERR_ARG;
+  int r = check_species(c, src, "src");
+  if (r) return r;
+  if ((r = check_species(c, dst, "dst"))) return r;
+  if ((r = check_fields(c, f))) return r;
+  if (f->kind != QED_FIELD_GRID) return fail(c, QED_ERR_ARG, "sort_by_cell needs grid fields");
+  if (src->dtype != dst->dtype || dst->capacity < src->capacity)
+    return fail(c, QED_ERR_ARG, "sort_by_cell: dst must share dtype and hold src's capacity");
+  if (src->x == dst->x) return fail(c, QED_ERR_ARG, "sort_by_cell: src and dst must differ");
+  hipError_t e = qed::launch_sort_by_cell(c, f, src, dst, S(st));
+  return e == hipSuccess ? QED_OK : hip_fail(c, e, "sort_by_cell");
 }
 
 int qed_sample(qed_ctx_t c, const double *chi, const double *gamma, const uint64_t *id, int64_t n,

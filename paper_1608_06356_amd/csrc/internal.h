@@ -48,6 +48,12 @@ struct qed_ctx {
 
   int n_cu = 256;
 
+  // cell sort scratch
+  uint32_t *sort_keys = nullptr, *sort_vals = nullptr;
+  int64_t sort_cap = 0;
+  void *sort_tmp = nullptr;
+  size_t sort_tmp_bytes = 0;
+
   // surrogate networks (0: xi net, 1: rate net): float32 parameters, Adam state
   bool mlp_ready = false;
   float *mlp_theta[2] = {nullptr, nullptr}, *mlp_grad[2] = {nullptr, nullptr};
@@ -57,6 +63,8 @@ struct qed_ctx {
 namespace qed {
 hipError_t launch_build_tables(qed_ctx *c, int formula, hipStream_t s);
 int mlp_params(int net);
+hipError_t launch_sort_by_cell(qed_ctx *c, const qed_fields_t *f, const qed_species_t *s, qed_species_t *d,
+                               hipStream_t st);
 hipError_t launch_mlp_init(float *theta, int net, uint32_t seed, hipStream_t st);
 hipError_t launch_mlp_grad(int net, const float *theta, float *grad, const double *S64, const double *lnh,
                            const double *L, const float *ext_x, const float *ext_t, const float *ext_m,

@@ -1,0 +1,103 @@
+// Stable reordering of a species by grid cell (nearest node of the quadratic
+// stencil), so that the field gather of neighbouring threads touches
+// neighbouring nodes.  Keys are radix-sorted with rocPRIM (stable), then every
+// array is gathered into the destination species.  Particle ids, and therefore
+// every random stream, travel with the particles, so the physics is unchanged;
+// only the storage order (and with it the append order) changes.
+#include <hip/hip_runtime.h>
+#include <rocprim/device/device_radix_sort.hpp>
+
+#include "internal.h"
+#include "qed_device.h"
+
+namespace qed {
+namespace {
+
+template <typename R>
+__global__ void k_cell_keys(const R *x, const R *y, const R *z, const int64_t *count, int64_t cap, int nx,
+                            int ny, int nz, double dx, double dy, double dz, uint32_t *keys, uint32_t *vals) {
+  const int64_t n = *count;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cap; i += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t key = 0xFFFFFFFFu;
+    if (i < n) {
+      int jx = (int)floor((double)x[i] / dx + 0.5), jy = (int)floor((double)y[i] / dy + 0.5),
+          jz = (int)floor((double)z[i] / dz + 0.5);
+      jx = jx < 0 ? 0 : (jx >= nx ? jx - nx : jx);
+      jy = jy < 0 ? 0 : (jy >= ny ? jy - ny : jy);
+      jz = jz < 0 ? 0 : (jz >= nz ? jz - nz : jz);
+      jx = jx >= nx ? nx - 1 : jx; jy = jy >= ny ? ny - 1 : jy; jz = jz >= nz ? nz - 1 : jz;
+      key = (uint32_t)(((int64_t)jz * ny + jy) * nx + jx);
+    }
+    keys[i] = key;
+    vals[i] = (uint32_t)i;
+  }
+}
+
+template <typename R>
+__global__ void k_permute(const R *sx, const R *sy, const R *sz, const R *spx, const R *spy, const R *spz,
+                          const double *stau, const uint64_t *sid, R *dx_, R *dy_, R *dz_, R *dpx, R *dpy, R *dpz,
+                          double *dtau, uint64_t *did, const uint32_t *perm, const int64_t *count,
+                          int64_t *dcount) {
+  const int64_t n = *count;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t i = perm[j];
+    dx_[j] = sx[i]; dy_[j] = sy[i]; dz_[j] = sz[i];
+    dpx[j] = spx[i]; dpy[j] = spy[i]; dpz[j] = spz[i];
+    dtau[j] = stau[i]; did[j] = sid[i];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *dcount = n;
+}
+
+template <typename R>
+hipError_t sort_impl(qed_ctx *c, const qed_fields_t *f, const qed_species_t *s, qed_species_t *d, hipStream_t st) {
+  const int64_t cap = s->capacity;
+  int64_t blocks = (cap + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  uint32_t *k0 = c->sort_keys, *k1 = c->sort_keys + cap, *v0 = c->sort_vals, *v1 = c->sort_vals + cap;
+  hipLaunchKernelGGL(k_cell_keys<R>, dim3((unsigned)blocks), dim3(256), 0, st, (const R *)s->x, (const R *)s->y,
+                     (const R *)s->z, s->count, cap, f->nx, f->ny, f->nz, f->dx, f->dy, f->dz, k0, v0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const uint64_t cells = (uint64_t)f->nx * f->ny * f->nz;
+  unsigned bits = 1;
+  while ((1ull << bits) <= cells) ++bits;
+  ++bits;   // the all-ones sentinel of unused slots sorts last
+  if (bits > 32) bits = 32;
+  size_t need = 0;
+  if ((e = rocprim::radix_sort_pairs(nullptr, need, k0, k1, v0, v1, (size_t)cap, 0u, bits, st)) != hipSuccess) return e;
+  if (need > c->sort_tmp_bytes) {
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    (void)hipFree(c->sort_tmp);
+    c->sort_tmp = nullptr;
+    c->sort_tmp_bytes = 0;
+    if ((e = hipMalloc(&c->sort_tmp, need)) != hipSuccess) return e;
+    c->sort_tmp_bytes = need;
+  }
+  if ((e = rocprim::radix_sort_pairs(c->sort_tmp, need, k0, k1, v0, v1, (size_t)cap, 0u, bits, st)) != hipSuccess)
+    return e;
+  hipLaunchKernelGGL(k_permute<R>, dim3((unsigned)blocks), dim3(256), 0, st, (const R *)s->x, (const R *)s->y,
+                     (const R *)s->z, (const R *)s->px, (const R *)s->py, (const R *)s->pz, s->tau, s->id,
+                     (R *)d->x, (R *)d->y, (R *)d->z, (R *)d->px, (R *)d->py, (R *)d->pz, d->tau, d->id, v1,
+                     s->count, d->count);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_sort_by_cell(qed_ctx *c, const qed_fields_t *f, const qed_species_t *s, qed_species_t *d,
+                               hipStream_t st) {
+  if (s->capacity > c->sort_cap) {
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    (void)hipFree(c->sort_keys);
+    (void)hipFree(c->sort_vals);
+    c->sort_keys = c->sort_vals = nullptr;
+    c->sort_cap = 0;
+    if ((e = hipMalloc(&c->sort_keys, 2 * s->capacity * sizeof(uint32_t))) != hipSuccess) return e;
+    if ((e = hipMalloc(&c->sort_vals, 2 * s->capacity * sizeof(uint32_t))) != hipSuccess) return e;
+    c->sort_cap = s->capacity;
+  }
+  return s->dtype == QED_F32 ? sort_impl<float>(c, f, s, d, st) : sort_impl<double>(c, f, s, d, st);
+}
+
+}  // namespace qed

@@ -336,3 +336,32 @@ def test_pair_spectrum_and_yield_1e7(pair_table):
     ks2 = np.max(np.abs(np.searchsorted(xi, allv, side="right") / m - np.searchsorted(xo, allv, side="right") / m))
     print(f"pairs {m} (z = {z:.2f})  KS(exact) {ks1:.2e}  KS(oracle sampler) {ks2:.2e}")
     assert ks1 < 2e-3 and ks2 < 2e-3
+
+
+def test_sort_by_cell_stable_permutation():
+    """qed_sort_by_cell: destination = source permuted by a stable sort of the
+    nearest-node cell index; counts and every array travel together."""
+    torch, q = need_gpu()
+    ctx = q.Context()
+    n, cap, ng, L = 100003, 120000, 32, workloads.BOX_L
+    rng = np.random.default_rng(9)
+    x = rng.uniform(0, L, (n, 3)).astype(np.float32).astype(np.float64)
+    x[:50] = x[50:100]              # repeated cells exercise stability
+    p = rng.normal(size=(n, 3))
+    tau = rng.uniform(size=n)
+    ids = rng.permutation(n).astype(np.uint64)
+    a, b = q.Species(cap, "f32"), q.Species(cap, "f32")
+    a.load(x, p, tau, ids)
+    grid = torch.zeros(ng ** 3 * 6, dtype=torch.float32, device="cuda")
+    fld = q.Fields(q.QED_FIELD_GRID, grid=grid, n=ng, L=L)
+    ctx.qed_sort_by_cell(fld, a, b)
+    got = b.to_numpy()
+    d = L / ng
+    j = np.floor(x / d + 0.5).astype(np.int64)
+    j[j >= ng] -= ng
+    key = (j[:, 2] * ng + j[:, 1]) * ng + j[:, 0]
+    order = np.argsort(key, kind="stable")
+    assert b.n() == n
+    np.testing.assert_array_equal(got["id"], ids[order])
+    np.testing.assert_array_equal(got["x"], x[order])
+    np.testing.assert_array_equal(got["tau"], tau[order])
