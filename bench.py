@@ -26,6 +26,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PROFILE = os.path.join(ROOT, "profiles", "gather_push_standing_wave_1e7.md")
+
+
+def measured_traffic():
+    """HBM bytes per gather/push launch from the committed rocprofv3 counter
+    summary, or None if the kernel source changed since it was taken."""
+    import hashlib
+    try:
+        text = open(PROFILE).read()
+        src = open(os.path.join(ROOT, "paper_1608_06356_amd", "csrc", "step.hip"), "rb").read()
+    except OSError:
+        return None
+    vals = dict(l.split(": ", 1) for l in text.splitlines() if l.startswith(("traffic_bytes_per_launch", "source")))
+    sha = hashlib.sha256(src).hexdigest()[:16]
+    if "source" not in vals or sha not in vals["source"]:
+        return None
+    return int(vals["traffic_bytes_per_launch"])
 
 
 def parse():
@@ -182,7 +199,7 @@ def main():
                    "global_batch": n, "dt": args.dt, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": "k_gather_push<float>", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "algorithmic_bytes_per_launch": algo,
+                     "traffic": measured_traffic(), "algorithmic_bytes_per_launch": algo,
                      "avg_launch_ms": gp_ms},
         "events": st,
         "photons": ph.n(),

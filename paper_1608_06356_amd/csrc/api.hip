@@ -56,9 +56,8 @@ template <typename T> hipError_t dalloc(T **p, size_t n) {
 }
 
 void free_emitters(qed_ctx *c) {
-  (void)hipFree(c->em_idx); (void)hipFree(c->em_fld); (void)hipFree(c->em_rem); (void)hipFree(c->d_status);
-  (void)hipFree(c->em_mask);
-  c->em_idx = nullptr; c->em_fld = nullptr; c->em_rem = nullptr; c->d_status = nullptr; c->em_mask = nullptr;
+  (void)hipFree(c->em_idx); (void)hipFree(c->em_rec); (void)hipFree(c->d_status); (void)hipFree(c->em_mask);
+  c->em_idx = nullptr; c->em_rec = nullptr; c->d_status = nullptr; c->em_mask = nullptr;
   c->reserved = 0; c->status_len = 0;
 }
 
@@ -71,9 +70,8 @@ int ensure_reserved(qed_ctx *c, int64_t n) {
   // for the largest tile count of any kernel
   const int64_t em_cap = n;
   const int64_t status_len = n / 256 + 64;
-  if ((e = dalloc(&c->em_idx, em_cap)) != hipSuccess || (e = dalloc(&c->em_fld, 8 * em_cap)) != hipSuccess ||
-      (e = dalloc(&c->em_rem, em_cap)) != hipSuccess || (e = dalloc(&c->d_status, status_len)) != hipSuccess ||
-      (e = dalloc(&c->em_mask, n / 64 + 1)) != hipSuccess) {
+  if ((e = dalloc(&c->em_idx, em_cap)) != hipSuccess || (e = dalloc(&c->em_rec, 128 * em_cap)) != hipSuccess ||
+      (e = dalloc(&c->d_status, status_len)) != hipSuccess || (e = dalloc(&c->em_mask, n / 64 + 1)) != hipSuccess) {
     free_emitters(c);
     return hip_fail(c, e, "reserve: hipMalloc");
   }

@@ -33,8 +33,7 @@ struct qed_ctx {
   int64_t em_cap = 0;            // slots (one per particle of the reserved capacity)
   uint64_t *em_mask = nullptr;   // one bit per particle: optical depth ran out this step
   int32_t *em_idx = nullptr;     // ordered emitter list
-  double *em_fld = nullptr;      // 6 * reserved doubles (float-packed for f32 species)
-  double *em_rem = nullptr;
+  unsigned char *em_rec = nullptr;   // em_cap records of up to 128 bytes, slot = particle index
   int64_t *d_n_emit = nullptr;
   const void *em_owner = nullptr;   // species (x pointer) the list belongs to
   int em_dtype = -1;

@@ -147,6 +147,15 @@ __device__ __forceinline__ uint64_t tile_offset(uint32_t tile, uint32_t agg, uin
 // event to its own slot; k_emit_index turns the mask into the ordered list.
 constexpr int kXcds = 8;
 
+// Emitter record, written by the emitter to its own slot and read once by
+// k_emit: everything the event loop needs, in one or two cache lines.
+template <typename R>
+struct alignas(16) EmRec {
+  R x[3], p[3], F[6];       // position after the push, momentum p^{n+1/2}, E and B at x^n
+  uint64_t id;
+  double chi, W, rem;       // chi and rate of the first event, time left after it
+};
+
 template <typename R>
 struct GPArgs {
   SpeciesDev sp;
@@ -155,9 +164,7 @@ struct GPArgs {
   R q, dt;
   double dtd;
   uint64_t *mask;        // one bit per particle
-  R *em_fld;             // 6 planes of em_cap, slot = particle index
-  double *em_chi, *em_w, *em_rem;
-  int64_t em_cap;
+  EmRec<R> *rec;         // slot = particle index
   int64_t tpx;           // tiles per XCD
   unsigned long long *counters;
 };
@@ -204,11 +211,15 @@ __global__ __launch_bounds__(kGPThreads) void k_gather_push(GPArgs<R> a) {
     }
     if (W > 0.0 && tau <= W * a.dtd) {
       flag = true;
+      EmRec<R> r;
+      r.x[0] = x; r.x[1] = y; r.x[2] = z; r.p[0] = px; r.p[1] = py; r.p[2] = pz;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) a.em_fld[c * a.em_cap + i] = F[c];
-      a.em_chi[i] = chi;
-      a.em_w[i] = W;
-      a.em_rem[i] = a.dtd - tau / W;
+      for (int c = 0; c < 6; ++c) r.F[c] = F[c];
+      r.id = a.sp.id[i];
+      r.chi = chi;
+      r.W = W;
+      r.rem = a.dtd - tau / W;
+      a.rec[i] = r;
     } else {
       a.sp.tau[i] = tau - W * a.dtd;
     }
@@ -265,9 +276,7 @@ struct EmitArgs {
   const uint16_t *q16;         // 16-bit quantiles (R = float)
   const float *s0sc;
   const int32_t *em_idx;
-  const R *em_fld;
-  const double *em_chi, *em_w, *em_rem;
-  int64_t em_cap;
+  const EmRec<R> *rec;
   const int64_t *n_emit;
   uint64_t *next_id;
   uint32_t seed;
@@ -292,14 +301,15 @@ __device__ void emit_tile(const EmitArgs<R> &a, const Tab &tab, const R *lnh, ui
   R nx = 0, ny = 0, nz = 0, x = 0, y = 0, z = 0;
   if (valid) {
     const int64_t i = a.em_idx[r];
+    const EmRec<R> rc = a.rec[i];
     R F[6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) F[c] = a.em_fld[c * a.em_cap + i];
-    double chi = a.em_chi[i], W = a.em_w[i], rem = a.em_rem[i];
+    for (int c = 0; c < 6; ++c) F[c] = rc.F[c];
+    double chi = rc.chi, W = rc.W, rem = rc.rem;
     R *PX = (R *)a.lep.px, *PY = (R *)a.lep.py, *PZ = (R *)a.lep.pz;
-    R px = PX[i], py = PY[i], pz = PZ[i];
-    x = ((R *)a.lep.x)[i]; y = ((R *)a.lep.y)[i]; z = ((R *)a.lep.z)[i];
-    const uint64_t id = a.lep.id[i];
+    R px = rc.p[0], py = rc.p[1], pz = rc.p[2];
+    x = rc.x[0]; y = rc.x[1]; z = rc.x[2];
+    const uint64_t id = rc.id;
     const R pa = sqrt(px * px + py * py + pz * pz);
     if (pa > (R)0) { nx = px / pa; ny = py / pa; nz = pz / pa; }
     R g = sqrt((R)1 + px * px + py * py + pz * pz);
@@ -702,6 +712,8 @@ __global__ void k_sample_f32(const double *chi, const double *gamma, const uint6
 // =============================================================== launchers
 namespace qed {
 
+static_assert(sizeof(EmRec<float>) == 80 && sizeof(EmRec<double>) == 128, "emitter record size");
+
 static SpeciesDev dev_species(const qed_species_t *s) {
   return SpeciesDev{s->x, s->y, s->z, s->px, s->py, s->pz, s->tau, s->id, s->capacity, s->count};
 }
@@ -737,15 +749,13 @@ hipError_t launch_gather_push(qed_ctx *c, const qed_fields_t *f, const qed_speci
   const int64_t ntiles = (sp->capacity + kGPTile - 1) / kGPTile;
   const int64_t tpx = (ntiles + kXcds - 1) / kXcds;
   const unsigned grid = (unsigned)(tpx * kXcds);
-  const int64_t cap = c->em_cap;
   if (sp->dtype == QED_F32) {
     GPArgs<float> a{dev_species(sp), dev_fields(f), c->rad_lnh32, (float)charge, (float)dt, dt, c->em_mask,
-                    (float *)c->em_fld, c->em_fld + 3 * cap, c->em_fld + 4 * cap, c->em_rem, cap, tpx,
-                    c->d_counters};
+                    (EmRec<float> *)c->em_rec, tpx, c->d_counters};
     launch_gp_kind<float>(a, f->kind, grid, st);
   } else {
     GPArgs<double> a{dev_species(sp), dev_fields(f), c->rad_lnh64, (double)charge, dt, dt, c->em_mask,
-                     c->em_fld, c->em_fld + 6 * cap, c->em_fld + 7 * cap, c->em_rem, cap, tpx, c->d_counters};
+                     (EmRec<double> *)c->em_rec, tpx, c->d_counters};
     launch_gp_kind<double>(a, f->kind, grid, st);
   }
   hipError_t e = hipGetLastError();
@@ -768,15 +778,13 @@ hipError_t launch_emit(qed_ctx *c, const qed_species_t *lep, const qed_species_t
   const unsigned grid = (unsigned)(ntiles < c->n_cu ? ntiles : c->n_cu);
   if (lep->dtype == QED_F32) {
     EmitArgs<float> a{dev_species(lep), dev_species(ph), c->rad_lnh32, c->rad_S64, c->rad_q16,
-                      c->rad_s0sc, c->em_idx, (const float *)c->em_fld, c->em_fld + 3 * c->em_cap,
-                      c->em_fld + 4 * c->em_cap, c->em_rem, c->em_cap, c->d_n_emit,
+                      c->rad_s0sc, c->em_idx, (const EmRec<float> *)c->em_rec, c->d_n_emit,
                       c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, sc,
                       c->d_counters};
     hipLaunchKernelGGL(k_emit_f32, dim3(grid), dim3(kEmitThreads), 0, st, a);
   } else {
     EmitArgs<double> a{dev_species(lep), dev_species(ph), c->rad_lnh64, c->rad_S64, c->rad_q16,
-                       c->rad_s0sc, c->em_idx, (const double *)c->em_fld, c->em_fld + 6 * c->em_cap,
-                       c->em_fld + 7 * c->em_cap, c->em_rem, c->em_cap, c->d_n_emit,
+                       c->rad_s0sc, c->em_idx, (const EmRec<double> *)c->em_rec, c->d_n_emit,
                        c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, sc,
                        c->d_counters};
     hipLaunchKernelGGL(k_emit_f64, dim3(grid), dim3(kEmitThreads), 0, st, a);
