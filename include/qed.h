@@ -75,6 +75,10 @@ extern "C" {
 /* qed_params_t.flags */
 #define QED_FLAG_NO_RECOIL     1u  /* leptons keep their momentum when emitting   */
 #define QED_FLAG_STATIC_PHOTONS 2u /* qed_create_pairs does not move photons      */
+#define QED_FLAG_TRACK_DEAD    4u  /* only qed_create_pairs kills particles: lets
+                                      qed_compact skip when nothing died (below)   */
+#define QED_FLAG_SURROGATE     8u  /* float32 species: rates and xi from the trained
+                                      surrogate nets (table fallback), see below   */
 
 #define QED_DEAD_ID UINT64_MAX     /* id of a particle removed by pair creation */
 
@@ -217,7 +221,11 @@ QED_API int qed_create_pairs(qed_ctx_t ctx, const qed_fields_t *fields, qed_spec
 QED_API int qed_sort_by_cell(qed_ctx_t ctx, const qed_fields_t *fields, qed_species_t *src,
                              qed_species_t *dst, void *stream);
 
-/* Stable in-place removal of particles whose id is QED_DEAD_ID. */
+/* Stable in-place removal of particles whose id is QED_DEAD_ID.  With
+   QED_FLAG_TRACK_DEAD the context remembers the species it compacted last;
+   qed_create_pairs on that species counts the photons it kills, and a later
+   qed_compact with nothing killed returns at once on the device (no host
+   synchronisation).  Without the flag every call scans the whole species. */
 QED_API int qed_compact(qed_ctx_t ctx, qed_species_t *sp, void *stream);
 
 /* Standalone lookups: for n particles with chi (f64) and gamma (f64) and the ids
@@ -248,7 +256,10 @@ QED_API int qed_sample(qed_ctx_t ctx, const double *chi, const double *gamma, co
    0 < h <= 1.001 * 5 chi / (2 sqrt3) or chi outside [1e-3, 1e2] falls back to the
    table, and a xi sample falls back when u is outside [1e-4, 1 - 1e-4] or the
    tabulated CDF at the predicted xi differs from u by more than 2e-3.  Fallbacks
-   are counted (mlp_fallback_*). */
+   are counted (mlp_fallback_*).
+   With QED_FLAG_SURROGATE in the context parameters, qed_gather_push and
+   qed_emit_photons on float32 species use the same nets and checks in place of
+   the table lookups (the nets must be trained or loaded first). */
 QED_API int qed_surrogate_params(int net);
 QED_API int qed_surrogate_train(qed_ctx_t ctx, const qed_train_spec_t *spec, void *stream);
 QED_API int qed_surrogate_io(qed_ctx_t ctx, int net, float *host, size_t bytes, int direction);

@@ -16,7 +16,7 @@ QED_OK, QED_ERR_ARG, QED_ERR_HIP, QED_ERR_CAPACITY, QED_ERR_RANGE, QED_ERR_STATE
 QED_F32, QED_F64 = 0, 1
 QED_FORMULA_I, QED_FORMULA_II = 1, 2
 QED_FIELD_UNIFORM, QED_FIELD_GRID, QED_FIELD_PER_PARTICLE = 0, 1, 2
-QED_FLAG_NO_RECOIL, QED_FLAG_STATIC_PHOTONS = 1, 2
+QED_FLAG_NO_RECOIL, QED_FLAG_STATIC_PHOTONS, QED_FLAG_TRACK_DEAD, QED_FLAG_SURROGATE = 1, 2, 4, 8
 QED_SAMPLER_MLP = 2
 DEAD_ID = 0xFFFFFFFFFFFFFFFF
 EXPORTS = ["qed_create", "qed_destroy", "qed_last_error", "qed_reserve", "qed_set_next_id",

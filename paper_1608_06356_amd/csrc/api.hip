@@ -103,9 +103,11 @@ int qed_create(qed_ctx_t *out, const qed_params_t *p) {
   if (e == hipSuccess) e = dalloc(&c->d_next_id, 1);
   if (e == hipSuccess) e = dalloc(&c->d_n_emit, 1);
   if (e == hipSuccess) e = dalloc(&c->d_ticket, 1);
+  if (e == hipSuccess) e = dalloc(&c->d_killed, 1);
   if (e == hipSuccess) e = hipMemset(c->d_counters, 0, sizeof(unsigned long long) * qed::cNumCounters);
   if (e == hipSuccess) e = hipMemset(c->d_next_id, 0, sizeof(uint64_t));
   if (e == hipSuccess) e = hipMemset(c->d_n_emit, 0, sizeof(int64_t));
+  if (e == hipSuccess) e = hipMemset(c->d_killed, 0, sizeof(int64_t));
   if (e != hipSuccess) {
     qed_destroy(c);
     return QED_ERR_HIP;
@@ -122,7 +124,7 @@ void qed_destroy(qed_ctx_t c) {
                   c->pair_S64, c->pair_L32, c->pair_s0sc, c->pair_q16, c->tab_work, c->d_counters,
                   c->d_next_id, c->d_n_emit, c->d_ticket, c->rad_chk, c->mlp_theta[0], c->mlp_theta[1],
                   c->mlp_grad[0], c->mlp_grad[1], c->mlp_m[0], c->mlp_m[1], c->mlp_v[0], c->mlp_v[1],
-                  c->sort_keys, c->sort_vals, c->sort_tmp};
+                  c->sort_keys, c->sort_vals, c->sort_tmp, c->d_killed};
   for (void *p : ptrs) (void)hipFree(p);
   delete c;
 }
@@ -224,6 +226,8 @@ int qed_gather_push(qed_ctx_t c, const qed_fields_t *f, qed_species_t *lep, int 
   if (!(dt > 0)) return fail(c, QED_ERR_ARG, "dt must be > 0");
   if (!c->tables_ready) return fail(c, QED_ERR_STATE, "tables not built (call qed_build_tables)");
   if ((r = ensure_reserved(c, lep->capacity))) return r;
+  if ((c->params.flags & QED_FLAG_SURROGATE) && lep->dtype == QED_F32 && !c->mlp_ready)
+    return fail(c, QED_ERR_STATE, "QED_FLAG_SURROGATE: surrogate not trained or loaded");
   hipError_t e = qed::launch_gather_push(c, f, lep, charge, dt, S(st));
   if (e != hipSuccess) return hip_fail(c, e, "gather_push");
   c->em_owner = lep->x;

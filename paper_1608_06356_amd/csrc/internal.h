@@ -40,6 +40,11 @@ struct qed_ctx {
   int em_charge = 0;
   double em_dt = 0.0;
 
+  // dead-particle count of the species compacted last (pairs add to it; compaction
+  // skips its work when it is zero)
+  int64_t *d_killed = nullptr;
+  const void *killed_owner = nullptr;
+
   // decoupled look-back scan state
   uint32_t *d_ticket = nullptr;
   uint64_t *d_status = nullptr;

@@ -21,190 +21,13 @@
 #include "internal.h"
 #include "lookup.h"
 #include "qed_device.h"
+#include "mlp_device.h"
 
 namespace qed {
 namespace {
-
-typedef short s4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-constexpr int H = 64;
-constexpr double kTmax = 9.2102403669758;   // logit(1 - 1e-4)
-constexpr float kXShift = 0.5f, kXScale = 2.5f;
-constexpr float kAShift = -1.0f, kAScale = 2.0f;
-constexpr float kBShift0 = -0.4f, kBScale0 = 0.5f, kBShift1 = -2.0f, kBScale1 = 0.5f;
-constexpr uint32_t kTrainPurpose = 3, kInitPurpose = 4;
-
-struct Layout {
-  int nin, nout, W1, b1, W2, b2, W3, b3, W4, b4, n;
-};
-__host__ __device__ constexpr Layout make_layout(int nin, int nout) {
-  return Layout{nin, nout, 0, H * nin, H * nin + H, H * nin + H + H * H, H * nin + 2 * H + H * H,
-                H * nin + 2 * H + 2 * H * H, H * nin + 3 * H + 2 * H * H,
-                H * nin + 3 * H + 2 * H * H + nout * H, H * nin + 3 * H + 2 * H * H + nout * H + nout};
-}
-constexpr Layout kA = make_layout(2, 1), kB = make_layout(1, 2);
-
-__device__ __forceinline__ uint16_t bf16_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-__device__ __forceinline__ float bf16_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-// x = hi + lo with hi = bf16(x), lo = bf16(x - hi), packed four at a time
-__device__ __forceinline__ void split4(const float x[4], s4 &hi, s4 &lo) {
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const uint16_t h = bf16_rne(x[v]);
-    hi[v] = (short)h;
-    lo[v] = (short)bf16_rne(x[v] - bf16_f(h));
-  }
-}
-__device__ __forceinline__ void split1(float x, uint16_t &hi, uint16_t &lo) {
-  hi = bf16_rne(x);
-  lo = bf16_rne(x - bf16_f(hi));
-}
-__device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + __expf(-z)); }
-__device__ __forceinline__ float silu(float z) { return z * sigm(z); }
-__device__ __forceinline__ float dsilu(float z) {
-  const float s = sigm(z);
-  return s * (1.0f + z * (1.0f - s));
-}
-
-// Weights of one net staged in LDS: split 64x64 layers (row-major [out][in]),
-// optionally their transposes, and the float32 small layers.
-struct NetLds {
-  uint16_t W2h[H * H], W2l[H * H], W3h[H * H], W3l[H * H];
-  float W1[H * 2], b1[H], b2[H], b3[H], W4[2 * H], b4[2];
-};
-struct NetLdsT {
-  uint16_t W2h[H * H], W2l[H * H], W3h[H * H], W3l[H * H];   // transposed
-};
-
-__device__ void stage_net(const float *th, const Layout &L, NetLds *s, NetLdsT *t) {
-  for (int k = threadIdx.x; k < H * H; k += blockDim.x) {
-    uint16_t h, l;
-    split1(th[L.W2 + k], h, l);
-    s->W2h[k] = h; s->W2l[k] = l;
-    if (t) { const int tk = (k % H) * H + k / H; t->W2h[tk] = h; t->W2l[tk] = l; }
-    split1(th[L.W3 + k], h, l);
-    s->W3h[k] = h; s->W3l[k] = l;
-    if (t) { const int tk = (k % H) * H + k / H; t->W3h[tk] = h; t->W3l[tk] = l; }
-  }
-  for (int k = threadIdx.x; k < H; k += blockDim.x) {
-    s->b1[k] = th[L.b1 + k]; s->b2[k] = th[L.b2 + k]; s->b3[k] = th[L.b3 + k];
-    for (int c = 0; c < L.nin; ++c) s->W1[k * L.nin + c] = th[L.W1 + k * L.nin + c];
-    for (int o = 0; o < L.nout; ++o) s->W4[o * H + k] = th[L.W4 + o * H + k];
-  }
-  if (threadIdx.x < L.nout) s->b4[threadIdx.x] = th[L.b4 + threadIdx.x];
-}
-
-// out = W a (64x64 layer, split products); a and out in the lane layout.
-__device__ __forceinline__ void mm64(const uint16_t *Wh, const uint16_t *Wl, const float a[4][4],
-                                     float out[4][4]) {
-  const int lane = threadIdx.x & 63;
-  s4 bh[4], bl[4];
-#pragma unroll
-  for (int ks = 0; ks < 4; ++ks) split4(a[ks], bh[ks], bl[ks]);
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt) {
-    f4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      const int off = (mt * 16 + (lane & 15)) * H + ks * 16 + 4 * (lane >> 4);
-      const s4 ah = *reinterpret_cast<const s4 *>(Wh + off);
-      const s4 al = *reinterpret_cast<const s4 *>(Wl + off);
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh[ks], acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl[ks], acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh[ks], acc, 0, 0, 0);
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) out[mt][v] = acc[v];
-  }
-}
-
-// Keeps LDS-resident weights from being hoisted into registers across tiles
-// (the loop-invariant loads of two nets would exceed the register file).
-__device__ __forceinline__ void reload_barrier() { asm volatile("" ::: "memory"); }
-
-__device__ __forceinline__ int feat(int mt, int v) { return mt * 16 + 4 * ((threadIdx.x & 63) >> 4) + v; }
-
-struct Cache {
-  float z1[4][4], z2[4][4], z3[4][4], a3[4][4];
-};
-
-// Forward pass of one 16-sample tile; x0, x1 are the inputs of this lane's sample.
-__device__ __forceinline__ void forward(const NetLds &s, int nin, int nout, float x0, float x1,
-                                        float y[2], Cache &c) {
-  float a[4][4], z[4][4];
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int f = feat(mt, v);
-      float t = s.b1[f] + s.W1[f * nin] * x0;
-      if (nin > 1) t += s.W1[f * nin + 1] * x1;
-      c.z1[mt][v] = t;
-      a[mt][v] = silu(t);
-    }
-  mm64(s.W2h, s.W2l, a, z);
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) { z[mt][v] += s.b2[feat(mt, v)]; c.z2[mt][v] = z[mt][v]; a[mt][v] = silu(z[mt][v]); }
-  mm64(s.W3h, s.W3l, a, z);
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) { z[mt][v] += s.b3[feat(mt, v)]; c.z3[mt][v] = z[mt][v]; c.a3[mt][v] = silu(z[mt][v]); }
-  for (int o = 0; o < nout; ++o) {
-    float p = 0.f;
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) p += s.W4[o * H + feat(mt, v)] * c.a3[mt][v];
-    p += __shfl_xor(p, 16, 64);
-    p += __shfl_xor(p, 32, 64);
-    y[o] = p + s.b4[o];
-  }
-}
-
-// Forward pass without the training cache (inference).
-__device__ __forceinline__ void forward_nc(const NetLds &s, int nin, int nout, float x0, float x1, float y[2]) {
-  float a[4][4], z[4][4];
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int f = feat(mt, v);
-      float t = s.b1[f] + s.W1[f * nin] * x0;
-      if (nin > 1) t += s.W1[f * nin + 1] * x1;
-      a[mt][v] = silu(t);
-    }
-  mm64(s.W2h, s.W2l, a, z);
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) a[mt][v] = silu(z[mt][v] + s.b2[feat(mt, v)]);
-  mm64(s.W3h, s.W3l, a, z);
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) a[mt][v] = silu(z[mt][v] + s.b3[feat(mt, v)]);
-  for (int o = 0; o < nout; ++o) {
-    float p = 0.f;
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) p += s.W4[o * H + feat(mt, v)] * a[mt][v];
-    p += __shfl_xor(p, 16, 64);
-    p += __shfl_xor(p, 32, 64);
-    y[o] = p + s.b4[o];
-  }
-}
+using namespace mlp;
 
 // ------------------------------------------------------------- inputs/targets
-__device__ __forceinline__ float xin(double chi) { return (float)((log10(chi) + kXShift) / kXScale); }
 
 // Training sample g of net A: chi at a table row, logit u uniform in
 // [-Tmax, Tmax]; target from the float64 master inverse CDF of that row.
@@ -424,22 +247,6 @@ __global__ void k_init(float *theta, int net, uint32_t seed) {
   const int fan = (i < L.W2) ? L.nin : H;
   const uint4 r = philox4x32_10(make_uint4((uint32_t)i, (uint32_t)net, kInitPurpose << 24, 0u), make_uint2(seed, 0u));
   theta[i] = (float)((2.0 * unit<double>(r.x) - 1.0) / sqrt((double)fan));
-}
-
-// ------------------------------------------------------------ residual check
-// Photon CDF of the table row r on 40 nodes uniform in s over the row's fine
-// grid bounds, with slopes: P(s) by cubic Hermite, linear mixing between rows.
-constexpr int kChkN = 40;
-__device__ float check_cdf(const float *chk, int r, float s) {
-  const float *row = chk + r * (2 + 2 * kChkN);
-  const float s0 = row[0], ds = row[1];
-  const float y = (s - s0) / ds;
-  if (y <= 0.f) return row[2] * __expf((s - s0) * (1.0f / 3.0f));
-  if (y >= (float)(kChkN - 1)) return 1.0f;
-  const int j = (int)y;
-  const float t = y - j, t2 = t * t, t3 = t2 * t;
-  const float p0 = row[2 + 2 * j], d0 = row[3 + 2 * j], p1 = row[4 + 2 * j], d1 = row[5 + 2 * j];
-  return (2 * t3 - 3 * t2 + 1) * p0 + (t3 - 2 * t2 + t) * ds * d0 + (-2 * t3 + 3 * t2) * p1 + (t3 - t2) * ds * d1;
 }
 
 // --------------------------------------------------------------- inference

@@ -14,6 +14,7 @@
 
 #include "internal.h"
 #include "lookup.h"
+#include "mlp_device.h"
 #include "qed_device.h"
 
 namespace qed {
@@ -431,6 +432,293 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_f64(EmitArgs<double> a) {
   }
 }
 
+// ============================================== surrogate variants (float32)
+// The learned part of the step: the rate net replaces the ln h lookup in the
+// lepton pass, and the xi net (with the residual check against the Hermite CDF
+// rows and the table as fallback) replaces the inverse-CDF lookup in the
+// emission pass.  Both evaluate 16 particles per forward call per wave, so a
+// wave of 64 particles makes four calls with inputs broadcast by shuffles.
+struct MlpDev {
+  const float *thA, *thB;    // float32 parameters (split into bf16 hi/lo in LDS)
+  const float *chk;          // residual-check CDF rows
+  const float *lnh32;        // rad table (fallback)
+  const uint16_t *q16;
+  const float *s0sc;
+  float tol;
+};
+
+// ln h_rad(chi) from net B for the 64 lanes of a wave; ok = passed the check.
+__device__ __forceinline__ float mlp_lnh(const mlp::NetLds &B, double chi, bool &ok) {
+  const int lane = threadIdx.x & 63;
+  const bool in = chi >= kRadChiMin && chi <= kRadChiMax;
+  const float xi_in = mlp::xin(in ? chi : 1.0);
+  float mine = 0.f;
+#pragma unroll 1
+  for (int q = 0; q < 4; ++q) {
+    mlp::reload_barrier();
+    const float x0 = __shfl(xi_in, q * 16 + (lane & 15), 64);
+    float y[2];
+    mlp::forward_nc(B, 1, 2, x0, 0.f, y);
+    if ((lane >> 4) == q) mine = y[0];
+  }
+  const float lchi = logf((float)chi);
+  const float lh = mlp::kBShift0 + mlp::kBScale0 * mine + lchi;
+  ok = in && isfinite(lh) && lh <= logf(1.001f * (float)kHc1 * (float)chi);
+  return lh;
+}
+
+template <int FK>
+__global__ __launch_bounds__(kGPThreads) void k_gather_push_mlp(GPArgs<float> a, MlpDev m) {
+  __shared__ mlp::NetLds B;
+  __shared__ float lnh_s[kRadNChi];
+  mlp::stage_net(m.thB, mlp::kB, &B, nullptr);
+  for (int k = threadIdx.x; k < kRadNChi; k += blockDim.x) lnh_s[k] = m.lnh32[k];
+  __syncthreads();
+  const int64_t n = *a.sp.count;
+  const int64_t ntiles = (n + kGPTile - 1) / kGPTile;
+  const int xcd = blockIdx.x % kXcds;
+  const int64_t per = gridDim.x / kXcds;
+  float *X = (float *)a.sp.x, *Y = (float *)a.sp.y, *Z = (float *)a.sp.z;
+  float *PX = (float *)a.sp.px, *PY = (float *)a.sp.py, *PZ = (float *)a.sp.pz;
+  FieldDev f = a.f;
+  f.kind = FK;
+  uint32_t nfb = 0;
+  for (int64_t lt = blockIdx.x / kXcds; lt < a.tpx; lt += per) {
+    mlp::reload_barrier();
+    const int64_t tile = (int64_t)xcd * a.tpx + lt;
+    if (tile >= ntiles) break;
+    const int64_t base = tile * kGPTile;
+    const int64_t i = base + threadIdx.x;
+    const bool valid = i < n;
+    float F[6] = {0, 0, 0, 0, 0, 0};
+    float x = 0, y = 0, z = 0, px = 0, py = 0, pz = 0, g = 1;
+    double tau = 0.0, chi = 1.0;
+    if (valid) {
+      x = X[i]; y = Y[i]; z = Z[i]; px = PX[i]; py = PY[i]; pz = PZ[i];
+      tau = a.sp.tau[i];
+      field_at<float>(f, i, x, y, z, F);
+      boris<float>(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5], a.q, a.dt);
+      g = sqrtf(1.f + px * px + py * py + pz * pz);
+      x += px / g * a.dt; y += py / g * a.dt; z += pz / g * a.dt;
+      if (FK == QED_FIELD_GRID) {
+        wrap_coord<float>(x, (float)(f.dx * f.nx)); wrap_coord<float>(y, (float)(f.dy * f.ny));
+        wrap_coord<float>(z, (float)(f.dz * f.nz));
+      }
+      X[i] = x; Y[i] = y; Z[i] = z; PX[i] = px; PY[i] = py; PZ[i] = pz;
+      chi = chi_lepton(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5]);
+    }
+    bool ok;
+    const float lh = mlp_lnh(B, chi, ok);
+    bool flag = false;
+    if (valid) {
+      double W = 0.0;
+      if (isfinite(chi) && chi > 0.0) {
+        const float h = ok ? expf(lh) : h_rad<float>((float)chi, lnh_s);
+        nfb += !ok;
+        W = kRateUnit * (double)(h / g);
+      }
+      if (W > 0.0 && tau <= W * a.dtd) {
+        flag = true;
+        EmRec<float> r;
+        r.x[0] = x; r.x[1] = y; r.x[2] = z; r.p[0] = px; r.p[1] = py; r.p[2] = pz;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) r.F[c] = F[c];
+        r.id = a.sp.id[i];
+        r.chi = chi;
+        r.W = W;
+        r.rem = a.dtd - tau / W;
+        a.rec[i] = r;
+      } else {
+        a.sp.tau[i] = tau - W * a.dtd;
+      }
+    }
+    const uint64_t bits = __ballot(flag);
+    if ((threadIdx.x & 63) == 0 && base + (threadIdx.x & ~63) < n) a.mask[(base + threadIdx.x) >> 6] = bits;
+  }
+  count_add(a.counters, cMlpFallbackRate, nfb);
+}
+
+constexpr int kEmitMlpThreads = 512;
+
+struct EmitMlpLds {
+  mlp::NetLds A, B;
+  float chk[kRadNChi * (2 + 2 * mlp::kChkN)];
+  float lnh[kRadNChi];
+};
+
+__global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a, MlpDev m) {
+  extern __shared__ unsigned char lds_raw[];
+  EmitMlpLds &S = *reinterpret_cast<EmitMlpLds *>(lds_raw);
+  __shared__ uint32_t scan_s[16];
+  __shared__ uint32_t tile_s;
+  __shared__ uint64_t off_s;
+  __shared__ int64_t hdr_s[3];
+  if (threadIdx.x == 0) { hdr_s[0] = *a.n_emit; hdr_s[1] = *a.ph.count; hdr_s[2] = (int64_t)*a.next_id; }
+  __syncthreads();
+  const int64_t n_em = hdr_s[0], ph0 = hdr_s[1];
+  const uint64_t id0 = (uint64_t)hdr_s[2];
+  if (n_em == 0) return;
+  mlp::stage_net(m.thA, mlp::kA, &S.A, nullptr);
+  mlp::stage_net(m.thB, mlp::kB, &S.B, nullptr);
+  for (int k = threadIdx.x; k < kRadNChi * (2 + 2 * mlp::kChkN); k += blockDim.x) S.chk[k] = m.chk[k];
+  for (int k = threadIdx.x; k < kRadNChi; k += blockDim.x) S.lnh[k] = m.lnh32[k];
+  const RowQ16 tab{m.q16, m.s0sc};     // fallback: 16-bit table through the caches
+  const int lane = threadIdx.x & 63;
+  while (true) {
+    const uint32_t tile = next_tile(a.sc.ticket, &tile_s);
+    if ((int64_t)tile * kEmitMlpThreads >= n_em) break;
+    const int64_t r = (int64_t)tile * kEmitMlpThreads + threadIdx.x;
+    const bool valid = r < n_em;
+    float gph[kKmaxMax];
+    double tph[kKmaxMax];
+    uint32_t nacc = 0, nev = 0, nrej = 0, ncap = 0, nfx = 0, nfr = 0;
+    float nx = 0, ny = 0, nz = 0, x = 0, y = 0, z = 0, px = 0, py = 0, pz = 0, g = 1;
+    float F[6] = {0, 0, 0, 0, 0, 0};
+    double chi = 1.0, W = 0.0, rem = 0.0, tau = 0.0;
+    uint64_t id = 0;
+    int64_t i = 0;
+    bool recoiled = false;
+    if (valid) {
+      i = a.em_idx[r];
+      const EmRec<float> rc = a.rec[i];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) F[c] = rc.F[c];
+      chi = rc.chi; W = rc.W; rem = rc.rem;
+      px = rc.p[0]; py = rc.p[1]; pz = rc.p[2];
+      x = rc.x[0]; y = rc.x[1]; z = rc.x[2];
+      id = rc.id;
+      const float pa = sqrtf(px * px + py * py + pz * pz);
+      if (pa > 0.f) { nx = px / pa; ny = py / pa; nz = pz / pa; }
+      g = sqrtf(1.f + px * px + py * py + pz * pz);
+    }
+    bool active = valid;
+    for (int k = 0; k < a.kmax; ++k) {
+      if (!__any(active)) break;
+      mlp::reload_barrier();
+      const uint4 u = stream4(id, a.seed, a.step, kLeptonEvent, (uint32_t)k);
+      const float uxi = unit<float>(u.x), urow = unit<float>(u.z);
+      const float t = logf(uxi) - log1pf(-uxi);
+      const bool in_chi = chi >= kRadChiMin && chi <= kRadChiMax;
+      const float xa0 = mlp::xin(in_chi ? chi : 1.0), xa1 = t / (float)mlp::kTmax;
+      float yA = 0.f;
+#pragma unroll 1
+      for (int q = 0; q < 4; ++q) {
+        mlp::reload_barrier();
+        const float i0 = __shfl(xa0, q * 16 + (lane & 15), 64), i1 = __shfl(xa1, q * 16 + (lane & 15), 64);
+        float yy[2];
+        mlp::forward_nc(S.A, 2, 1, i0, i1, yy);
+        if ((lane >> 4) == q) yA = yy[0];
+      }
+      const float lchi = logf((float)chi);
+      const float s_hat = mlp::kAShift + mlp::kAScale * yA + lchi + 3.0f * (-log1pf(__expf(-t)));
+      bool xi_ok = in_chi && fabsf(t) <= (float)mlp::kTmax && isfinite(s_hat);
+      if (xi_ok) {
+        const float xp = Grid<float>::pos(lchi, kRadChiMin, kRadChiMax, kRadNChi);
+        int ii = (int)floorf(xp);
+        ii = ii < 0 ? 0 : (ii > kRadNChi - 2 ? kRadNChi - 2 : ii);
+        const float w = xp - ii;
+        const float P = (1.f - w) * mlp::check_cdf(S.chk, ii, s_hat) + w * mlp::check_cdf(S.chk, ii + 1, s_hat);
+        xi_ok = fabsf(P - uxi) <= m.tol;
+      }
+      float xi, om;
+      if (xi_ok) {
+        xi = 1.f / (1.f + __expf(-s_hat));
+        om = 1.f / (1.f + __expf(s_hat));
+      } else if (active) {
+        sample_rad<float>(tab, (float)chi, uxi, urow, xi, om);
+      } else {
+        xi = 0.f; om = 1.f;
+      }
+      bool recoil_now = false;
+      if (active) {
+        ++nev;
+        nfx += !xi_ok;
+        const float gp = xi * g;
+        if (gp >= 2.f) {
+#pragma unroll
+          for (int sl = 0; sl < kKmaxMax; ++sl)
+            if (sl == (int)nacc) { gph[sl] = gp; tph[sl] = -log(unit<double>(u.w)); }
+          ++nacc;
+          if (a.recoil) {
+            const float gn = fmaxf(om * g, 1.f);
+            const float pm = sqrtf(fmaxf(gn * gn - 1.f, 0.f));
+            px = nx * pm; py = ny * pm; pz = nz * pm;
+            g = gn;
+            recoiled = true;
+            recoil_now = true;
+            chi = chi_lepton(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5]);
+          }
+        } else {
+          ++nrej;
+        }
+      }
+      // rate after a recoil (net B; every lane takes part in the forward pass)
+      if (__any(recoil_now)) {
+        bool ok;
+        const float lh = mlp_lnh(S.B, recoil_now ? chi : 1.0, ok);
+        if (recoil_now) {
+          float h = 0.f;
+          if (isfinite(chi) && chi > 0.0) {
+            h = ok ? expf(lh) : h_rad<float>((float)chi, S.lnh);
+            nfr += !ok;
+          }
+          W = kRateUnit * (double)(h / g);
+        }
+      }
+      if (active) {
+        tau = -log(unit<double>(u.y));
+        const bool again = W > 0.0 && tau <= W * rem;
+        if (!again) {
+          active = false;
+        } else if (k + 1 >= a.kmax) {
+          ++ncap;
+          active = false;
+        } else {
+          rem -= tau / W;
+        }
+      }
+    }
+    if (valid) {
+      a.lep.tau[i] = tau - W * rem;
+      if (recoiled) { ((float *)a.lep.px)[i] = px; ((float *)a.lep.py)[i] = py; ((float *)a.lep.pz)[i] = pz; }
+    }
+    count_add(a.counters, cEvents, nev);
+    count_add(a.counters, cRejected, nrej);
+    count_add(a.counters, cCapped, ncap);
+    count_add(a.counters, cPhotons, nacc);
+    count_add(a.counters, cMlpFallbackXi, nfx);
+    count_add(a.counters, cMlpFallbackRate, nfr);
+    uint32_t total;
+    const uint32_t off = block_exclusive(nacc, scan_s, &total);
+    const uint64_t toff = tile_offset(tile, total, a.sc.status, a.counters, &off_s);
+    float *PXo = (float *)a.ph.x, *PYo = (float *)a.ph.y, *PZo = (float *)a.ph.z;
+    float *KX = (float *)a.ph.px, *KY = (float *)a.ph.py, *KZ = (float *)a.ph.pz;
+    uint32_t ndrop = 0;
+#pragma unroll
+    for (int sl = 0; sl < kKmaxMax; ++sl) {
+      if (sl < (int)nacc) {
+        const uint64_t rank = toff + off + sl;
+        const int64_t j = ph0 + (int64_t)rank;
+        if (j < a.ph.cap) {
+          PXo[j] = x; PYo[j] = y; PZo[j] = z;
+          KX[j] = nx * gph[sl]; KY[j] = ny * gph[sl]; KZ[j] = nz * gph[sl];
+          a.ph.tau[j] = tph[sl];
+          a.ph.id[j] = id0 + rank;
+        } else {
+          ++ndrop;
+        }
+      }
+    }
+    count_add(a.counters, cDropped, ndrop);
+    const int64_t last = (n_em - 1) / kEmitMlpThreads;
+    if ((int64_t)tile == last && threadIdx.x == 0) {
+      const int64_t tot = (int64_t)(toff + total);
+      *a.ph.count = ph0 + tot < a.ph.cap ? ph0 + tot : a.ph.cap;
+      *a.next_id = id0 + (uint64_t)tot;
+    }
+  }
+}
+
 // ================================================================ pairs
 template <typename R>
 struct PairArgs {
@@ -448,6 +736,7 @@ struct PairArgs {
   uint64_t step;
   ScanDev sc;
   unsigned long long *counters;
+  int64_t *killed;
 };
 
 constexpr int kPairThreads = 1024;
@@ -531,6 +820,7 @@ __device__ void pair_tile(const PairArgs<R> &a, const Tab &tab, const R *L, uint
     *a.el.count = e0 + tot < a.el.cap ? e0 + tot : a.el.cap;
     *a.po.count = p0 + tot < a.po.cap ? p0 + tot : a.po.cap;
     *a.next_id = id0 + 2 * (uint64_t)tot;
+    if (a.killed) *a.killed += tot;
   }
 }
 
@@ -590,10 +880,13 @@ constexpr int kCThreads = 256, kCItems = 4, kCTile = kCThreads * kCItems;
 
 template <typename R>
 __global__ __launch_bounds__(kCThreads) void k_compact(SpeciesDev sp, ScanDev sc,
-                                                       unsigned long long *counters) {
+                                                       unsigned long long *counters, const int64_t *killed) {
   __shared__ uint32_t scan_s[16];
   __shared__ uint32_t tile_s;
   __shared__ uint64_t off_s;
+  // killed: particles marked dead since the last compaction of this species, when
+  // known (pair creation keeps it); nothing to do if none
+  if (killed && *killed == 0) return;
   const uint32_t tile = next_tile(sc.ticket, &tile_s);
   const int64_t n = *sp.count;
   const int64_t base = (int64_t)tile * kCTile;
@@ -642,6 +935,8 @@ __global__ __launch_bounds__(kCThreads) void k_compact(SpeciesDev sp, ScanDev sc
 }
 
 // ================================================================ misc
+__global__ void k_set_i64(int64_t *p, int64_t v) { *p = v; }
+
 __global__ void k_zero_scan(uint32_t *ticket, uint64_t *status, int64_t n) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i == 0) *ticket = 0;
@@ -729,6 +1024,7 @@ static FieldDev dev_fields(const qed_fields_t *f) {
 
 static hipError_t zero_scan(qed_ctx *c, int64_t ntiles, hipStream_t st) {
   const int64_t n = ntiles + 1;
+  if (n > c->status_len) return hipErrorInvalidValue;   // reserve() sizes the status array
   hipLaunchKernelGGL(k_zero_scan, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, c->d_ticket,
                      c->d_status, n);
   return hipGetLastError();
@@ -744,12 +1040,31 @@ static void launch_gp_kind(const GPArgs<R> &a, int kind, unsigned grid, hipStrea
     hipLaunchKernelGGL((k_gather_push<R, QED_FIELD_PER_PARTICLE>), dim3(grid), dim3(kGPThreads), 0, st, a);
 }
 
+static MlpDev mlp_dev(qed_ctx *c) {
+  return MlpDev{c->mlp_theta[0], c->mlp_theta[1], c->rad_chk, c->rad_lnh32, c->rad_q16, c->rad_s0sc, 2e-3f};
+}
+
 hipError_t launch_gather_push(qed_ctx *c, const qed_fields_t *f, const qed_species_t *sp, int charge,
                               double dt, hipStream_t st) {
   const int64_t ntiles = (sp->capacity + kGPTile - 1) / kGPTile;
   const int64_t tpx = (ntiles + kXcds - 1) / kXcds;
   const unsigned grid = (unsigned)(tpx * kXcds);
-  if (sp->dtype == QED_F32) {
+  const bool use_mlp = (c->params.flags & QED_FLAG_SURROGATE) && sp->dtype == QED_F32;
+  if (use_mlp) {
+    // persistent: 4 workgroups per CU, each staging the split rate net once
+    int64_t g = (int64_t)c->n_cu * 4;
+    if (g > (int64_t)grid) g = ((int64_t)grid + kXcds - 1) / kXcds * kXcds;
+    g = (g + kXcds - 1) / kXcds * kXcds;
+    GPArgs<float> a{dev_species(sp), dev_fields(f), c->rad_lnh32, (float)charge, (float)dt, dt, c->em_mask,
+                    (EmRec<float> *)c->em_rec, tpx, c->d_counters};
+    const MlpDev m = mlp_dev(c);
+    if (f->kind == QED_FIELD_GRID)
+      hipLaunchKernelGGL(k_gather_push_mlp<QED_FIELD_GRID>, dim3((unsigned)g), dim3(kGPThreads), 0, st, a, m);
+    else if (f->kind == QED_FIELD_UNIFORM)
+      hipLaunchKernelGGL(k_gather_push_mlp<QED_FIELD_UNIFORM>, dim3((unsigned)g), dim3(kGPThreads), 0, st, a, m);
+    else
+      hipLaunchKernelGGL(k_gather_push_mlp<QED_FIELD_PER_PARTICLE>, dim3((unsigned)g), dim3(kGPThreads), 0, st, a, m);
+  } else if (sp->dtype == QED_F32) {
     GPArgs<float> a{dev_species(sp), dev_fields(f), c->rad_lnh32, (float)charge, (float)dt, dt, c->em_mask,
                     (EmRec<float> *)c->em_rec, tpx, c->d_counters};
     launch_gp_kind<float>(a, f->kind, grid, st);
@@ -770,13 +1085,28 @@ hipError_t launch_gather_push(qed_ctx *c, const qed_fields_t *f, const qed_speci
 
 hipError_t launch_emit(qed_ctx *c, const qed_species_t *lep, const qed_species_t *ph, int64_t step,
                        hipStream_t st) {
-  const int64_t ntiles = (lep->capacity + kEmitThreads - 1) / kEmitThreads;
+  const bool use_mlp = lep->dtype == QED_F32 && (c->params.flags & QED_FLAG_SURROGATE);
+  // the scan needs one zeroed status word per tile of this kernel's tile size
+  const int tile = use_mlp ? kEmitMlpThreads : kEmitThreads;
+  const int64_t ntiles = (lep->capacity + tile - 1) / tile;
   hipError_t e = zero_scan(c, ntiles, st);
   if (e != hipSuccess) return e;
   const ScanDev sc{c->d_ticket, c->d_status};
   const int recoil = (c->params.flags & QED_FLAG_NO_RECOIL) ? 0 : 1;
   const unsigned grid = (unsigned)(ntiles < c->n_cu ? ntiles : c->n_cu);
-  if (lep->dtype == QED_F32) {
+  if (use_mlp) {
+    EmitArgs<float> a{dev_species(lep), dev_species(ph), c->rad_lnh32, c->rad_S64, c->rad_q16,
+                      c->rad_s0sc, c->em_idx, (const EmRec<float> *)c->em_rec, c->d_n_emit,
+                      c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, sc,
+                      c->d_counters};
+    static bool attr = false;
+    if (!attr) {
+      (void)hipFuncSetAttribute((const void *)k_emit_mlp, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)sizeof(EmitMlpLds));
+      attr = true;
+    }
+    hipLaunchKernelGGL(k_emit_mlp, dim3(grid), dim3(kEmitMlpThreads), sizeof(EmitMlpLds), st, a, mlp_dev(c));
+  } else if (lep->dtype == QED_F32) {
     EmitArgs<float> a{dev_species(lep), dev_species(ph), c->rad_lnh32, c->rad_S64, c->rad_q16,
                       c->rad_s0sc, c->em_idx, (const EmRec<float> *)c->em_rec, c->d_n_emit,
                       c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, sc,
@@ -801,15 +1131,17 @@ hipError_t launch_pairs(qed_ctx *c, const qed_fields_t *f, const qed_species_t *
   const ScanDev sc{c->d_ticket, c->d_status};
   const int move = (c->params.flags & QED_FLAG_STATIC_PHOTONS) ? 0 : 1;
   const unsigned grid = (unsigned)(ntiles < c->n_cu ? ntiles : c->n_cu);
+  // killed-photon count: known only if this species was compacted before
+  int64_t *killed = ((c->params.flags & QED_FLAG_TRACK_DEAD) && c->killed_owner == ph->x) ? c->d_killed : nullptr;
   if (ph->dtype == QED_F32) {
     PairArgs<float> a{dev_species(ph), dev_species(el), dev_species(po), dev_fields(f), c->pair_L32,
                       c->pair_S64, c->pair_q16, c->pair_s0sc, (float)dt, dt, move, c->d_next_id,
-                      c->params.seed, (uint64_t)step, sc, c->d_counters};
+                      c->params.seed, (uint64_t)step, sc, c->d_counters, killed};
     hipLaunchKernelGGL(k_pairs_f32, dim3(grid), dim3(kPairThreads), 0, st, a);
   } else {
     PairArgs<double> a{dev_species(ph), dev_species(el), dev_species(po), dev_fields(f), c->pair_L64,
                        c->pair_S64, c->pair_q16, c->pair_s0sc, dt, dt, move, c->d_next_id,
-                       c->params.seed, (uint64_t)step, sc, c->d_counters};
+                       c->params.seed, (uint64_t)step, sc, c->d_counters, killed};
     hipLaunchKernelGGL(k_pairs_f64, dim3(grid), dim3(kPairThreads), 0, st, a);
   }
   return hipGetLastError();
@@ -820,12 +1152,18 @@ hipError_t launch_compact(qed_ctx *c, const qed_species_t *sp, hipStream_t st) {
   hipError_t e = zero_scan(c, ntiles, st);
   if (e != hipSuccess) return e;
   const ScanDev sc{c->d_ticket, c->d_status};
+  const bool track = (c->params.flags & QED_FLAG_TRACK_DEAD) != 0;
+  const int64_t *killed = (track && c->killed_owner == sp->x) ? c->d_killed : nullptr;
   if (sp->dtype == QED_F32)
     hipLaunchKernelGGL(k_compact<float>, dim3((unsigned)ntiles), dim3(kCThreads), 0, st,
-                       dev_species(sp), sc, c->d_counters);
+                       dev_species(sp), sc, c->d_counters, killed);
   else
     hipLaunchKernelGGL(k_compact<double>, dim3((unsigned)ntiles), dim3(kCThreads), 0, st,
-                       dev_species(sp), sc, c->d_counters);
+                       dev_species(sp), sc, c->d_counters, killed);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // the species now has no dead particles
+  hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, st, c->d_killed, (int64_t)0);
+  c->killed_owner = sp->x;
   return hipGetLastError();
 }
 

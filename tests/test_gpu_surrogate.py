@@ -157,3 +157,94 @@ def test_surrogate_gain_vs_table(trained):
           f"ratio {res['mlp'] / res['table_f32']:.3f}; xi fallback fraction "
           f"{st['mlp_fallback_xi'] / (4 * n):.4%}")
     assert res["mlp"] > 0 and res["table_f32"] > 0
+
+
+def _with_weights(q, trained, **kw):
+    ctx = q.Context(**kw)
+    ctx.qed_build_tables(q.QED_FORMULA_I)
+    for net in (0, 1):
+        ctx.qed_surrogate_io(net, trained.qed_surrogate_io(net))
+    return ctx
+
+
+def test_surrogate_step_spectrum_and_rate(trained):
+    """The emission step with QED_FLAG_SURROGATE (rate net in the lepton pass, xi
+    net in the emission pass): 1e7 photons at chi ~ 1 without recoil; event count
+    against the oracle's rate integral (Poisson z-test) and the accepted xi
+    against the exact truncated CDF (KS <= 2e-3)."""
+    torch, q = need_gpu()
+    import workloads
+    from oracle.constants import E_S
+    n, b0, g = 1_000_000, 2000.0, 206.0
+    ctx = _with_weights(q, trained, seed=21, kmax=4, flags=q.QED_FLAG_NO_RECOIL | q.QED_FLAG_SURROGATE)
+    ens = workloads.uniform_b_ensembles(n, seed=21, triples=((b0, g),))[0]
+    lep = q.Species(n, "f32")
+    ph = q.Species(12_000_000, "f32")
+    lep.load(ens["x"], ens["p"], ids=ens["id"])
+    ctx.qed_init_optical_depth(lep, 0)
+    ctx.qed_set_next_id(n)
+    fld = q.Fields(q.QED_FIELD_UNIFORM, B=(0, 0, b0))
+    ctx.qed_get_status(check=False)
+    s, dt = 0, 0.05
+    while ph.n() < 10_000_000:
+        ctx.qed_gather_push(fld, lep, -1, dt, s)
+        ctx.qed_emit_photons(lep, ph, s)
+        s += 1
+    st, rc = ctx.qed_get_status()
+    chi = g * math.sqrt(1 - 1 / g ** 2) * b0 / E_S
+    row = tables.fine_row("I", chi, tables.RAD_M)
+    W = RATE_UNIT * row.total / g
+    # events: the first event of each particle is decided by gather/push, later
+    # ones within a step by the emission pass; over s steps the count is
+    # Poisson with mean n W s dt up to the optical depth left at the end (< n)
+    mean = n * W * s * dt
+    assert abs(st["events"] - mean) < 4 * math.sqrt(mean) + n, (st["events"], mean)
+    nph = ph.n()
+    gam = torch.sqrt(ph.px[:nph].double() ** 2 + ph.py[:nph].double() ** 2 + ph.pz[:nph].double() ** 2)
+    xi = np.sort((gam / g).cpu().numpy())
+    P = row.F / row.total
+    xc = 2.0 / g
+    Pc = float(np.interp(math.log(xc) - math.log1p(-xc), row.s, P))
+    Pe = (np.interp(np.log(xi) - np.log1p(-np.minimum(xi, 1 - 1e-7)), row.s, P) - Pc) / (1 - Pc)
+    m = xi.size
+    ks = max(np.max(np.arange(1, m + 1) / m - Pe), np.max(Pe - np.arange(m) / m))
+    print(f"surrogate step: {s} steps, events {st['events']} (mean {mean:.0f}), photons {m}, KS {ks:.2e}, "
+          f"fallbacks xi {st['mlp_fallback_xi']} rate {st['mlp_fallback_rate']}")
+    assert ks < 2e-3
+    assert st["mlp_fallback_xi"] < 0.01 * st["events"]
+
+
+def test_surrogate_step_matches_table_step_standing_wave(trained):
+    """Standing wave a0 = 500, 2e5 electrons, 30 steps: the surrogate step and the
+    table step give the same photon yield (within 4 sigma of their difference)
+    and the same photon-energy distribution (two-sample KS)."""
+    torch, q = need_gpu()
+    import workloads
+    n, ngrid, L = 200_000, 128, workloads.BOX_L
+    res = {}
+    for name, flags in (("table", 0), ("mlp", q.QED_FLAG_SURROGATE)):
+        ctx = _with_weights(q, trained, seed=1, kmax=4, flags=flags)
+        ens = workloads.standing_wave_electrons(n, seed=1)
+        lep = q.Species(n, "f32")
+        ph = q.Species(3_000_000, "f32")
+        lep.load(ens["x"], ens["p"], ids=ens["id"])
+        ctx.qed_init_optical_depth(lep, 0)
+        ctx.qed_set_next_id(n)
+        grid = torch.empty(ngrid ** 3 * 6, dtype=torch.float32, device="cuda")
+        fld = q.Fields(q.QED_FIELD_GRID, grid=grid, n=ngrid, L=L)
+        for s in range(30):
+            ctx.qed_fill_standing_wave(grid, ngrid, L, 500.0, s * 0.01)
+            ctx.qed_gather_push(fld, lep, -1, 0.01, s)
+            ctx.qed_emit_photons(lep, ph, s)
+        st, rc = ctx.qed_get_status()
+        m = ph.n()
+        gam = torch.sqrt(ph.px[:m].double() ** 2 + ph.py[:m].double() ** 2 + ph.pz[:m].double() ** 2)
+        res[name] = (m, np.sort(gam.cpu().numpy()), st)
+    (m1, g1, _), (m2, g2, st2) = res["table"], res["mlp"]
+    assert abs(m1 - m2) < 4 * math.sqrt(m1 + m2), (m1, m2)
+    allv = np.concatenate([g1, g2])
+    ks = np.max(np.abs(np.searchsorted(g1, allv, side="right") / m1 - np.searchsorted(g2, allv, side="right") / m2))
+    crit = 1.95 * math.sqrt((m1 + m2) / (m1 * m2))
+    print(f"standing wave: photons table {m1} surrogate {m2}; KS {ks:.2e} (0.1% critical {crit:.2e}); "
+          f"fallbacks {st2['mlp_fallback_xi']} / {st2['mlp_fallback_rate']}")
+    assert ks < crit
