@@ -13,6 +13,9 @@ region.
 Prints one JSON line.  `value` = electron-steps per second over the timed
 steps.  `roofline` is for the dominant kernel (the lepton gather/push pass),
 whose duration is measured with HIP events on the stream it runs on.
+`surrogate` repeats the same workload with the trained networks in place of
+the table lookups (QED_FLAG_SURROGATE) and gates it on the two-sample KS
+distance of the photon-energy spectra of the two runs (<= 2e-3).
 `cpu_baseline` times the CPU oracle on a bounded sample of the same workload.
 """
 import argparse
@@ -58,6 +61,9 @@ def parse():
     ap.add_argument("--dt", type=float, default=0.01)
     ap.add_argument("--formula", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the surrogate-network run of the same workload")
+    ap.add_argument("--train-steps", type=int, default=20000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after timing, copy 1 GiB with torch (reference kernel for HBM counters)")
     ap.add_argument("--presort", type=int, default=1,
@@ -115,19 +121,20 @@ def _oracle_chunk(k, n, steps, a0, ngrid, dt, formula):
     return n * steps, time.perf_counter() - t0
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
-        sys.exit(2)
-    import torch
-    import paper_1608_06356_amd as q
+def run_workload(args, q, torch, flags, train_steps=0):
+    """Times the standing-wave step; returns timing, counters and the sorted
+    photon energies (for the spectrum comparison)."""
     import workloads
-
     dev = "cuda"
     n, ngrid, L = args.n, args.grid, workloads.BOX_L
-    ctx = q.Context(seed=1, kmax=4, flags=q.QED_FLAG_TRACK_DEAD)
+    ctx = q.Context(seed=1, kmax=4, flags=q.QED_FLAG_TRACK_DEAD | flags)
     ctx.qed_build_tables(args.formula)
+    train_s = None
+    if train_steps:
+        t0 = time.perf_counter()
+        ctx.qed_surrogate_train(train_steps, batch=4096, lr=3e-3, seed=11)
+        torch.cuda.synchronize()
+        train_s = time.perf_counter() - t0
     ens = workloads.standing_wave_electrons(n, seed=1)
     if args.presort:
         # initial storage order by grid cell (input layout, not timed)
@@ -182,7 +189,35 @@ def main():
     if rc != 0:
         print(f"bench.py: status {rc}: {st}", file=sys.stderr)
         sys.exit(1)
+    m = ph.n()
+    gam = torch.sqrt(ph.px[:m] ** 2 + ph.py[:m] ** 2 + ph.pz[:m] ** 2)
+    gam = torch.sort(gam).values
+    out = dict(total_ms=total_ms, gp_ms=gp_ms, st=st, photons=m, gamma=gam, train_s=train_s)
+    del ph, lep, lep_b, cur, grid
+    ctx.close()
+    return out
 
+
+def ks_two_sample(a, b):
+    """Two-sample Kolmogorov-Smirnov statistic of sorted device tensors."""
+    import torch
+    allv = torch.cat([a, b])
+    fa = torch.searchsorted(a, allv, right=True).double() / a.numel()
+    fb = torch.searchsorted(b, allv, right=True).double() / b.numel()
+    return float(torch.max(torch.abs(fa - fb)))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1608_06356_amd as q
+
+    n, ngrid = args.n, args.grid
+    tab = run_workload(args, q, torch, 0)
+    total_ms, gp_ms, st = tab["total_ms"], tab["gp_ms"], tab["st"]
     ms_per_step = total_ms / args.steps
     value = n * args.steps / (total_ms * 1e-3)
     # algorithmic bytes of one gather/push launch: read x,y,z,px,py,pz (24 B) and
@@ -205,10 +240,23 @@ def main():
                      "traffic": measured_traffic(), "algorithmic_bytes_per_launch": algo,
                      "avg_launch_ms": gp_ms},
         "events": st,
-        "photons": ph.n(),
+        "photons": tab["photons"],
     }
+    if not args.no_surrogate:
+        sur = run_workload(args, q, torch, q.QED_FLAG_SURROGATE, train_steps=args.train_steps)
+        ks = ks_two_sample(tab["gamma"], sur["gamma"])
+        out["surrogate"] = {
+            "value": n * args.steps / (sur["total_ms"] * 1e-3), "ms_per_step": sur["total_ms"] / args.steps,
+            "gather_push_ms": sur["gp_ms"], "photons": sur["photons"],
+            "ks_photon_energy_vs_table": ks, "ks_gate": 2e-3, "ks_pass": ks <= 2e-3,
+            "fallback_xi": sur["st"]["mlp_fallback_xi"], "fallback_rate": sur["st"]["mlp_fallback_rate"],
+            "events": sur["st"]["events"], "train_s": sur["train_s"],
+            "ratio_vs_table": (sur["total_ms"] and total_ms / sur["total_ms"]),
+        }
+        del sur
+    del tab
     if args.calibrate_copy:
-        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         src.fill_(1.0)
         torch.cuda.synchronize()
