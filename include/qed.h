@@ -81,6 +81,7 @@ extern "C" {
                                       surrogate nets (table fallback), see below   */
 
 #define QED_DEAD_ID UINT64_MAX     /* id of a particle removed by pair creation */
+#define QED_STEP_DEVICE (-1)       /* step argument: use the context's device step index */
 
 #if defined(__GNUC__)
 #define QED_API __attribute__((visibility("default")))
@@ -182,6 +183,17 @@ QED_API int qed_init_optical_depth(qed_ctx_t ctx, qed_species_t *sp, int64_t ste
    nodes of spacing L/n (layout of qed_fields_t.grid). */
 QED_API int qed_fill_standing_wave(qed_ctx_t ctx, float *grid, int n, double L, double a0,
                            double t, void *stream);
+
+/* Step index in device memory, so that one captured hipGraph of a step can be
+   replayed: pass step = QED_STEP_DEVICE to the entry points that take a step
+   (their random streams then use the device index), fill the grid with
+   qed_fill_standing_wave_at_step (t = t0 + dt * step), and end the step with
+   qed_advance_step.  All three enqueue small kernels only (no memset, no host
+   synchronisation). */
+QED_API int qed_set_step(qed_ctx_t ctx, int64_t step, void *stream);
+QED_API int qed_advance_step(qed_ctx_t ctx, void *stream);
+QED_API int qed_fill_standing_wave_at_step(qed_ctx_t ctx, float *grid, int n, double L, double a0,
+                                           double t0, double dt, void *stream);
 
 /* Lepton pass, every particle [0, *count): field at x^n, relativistic Boris push
    (charge = -1 electron, +1 positron), x^{n+1} = x^n + v dt (wrapped into a GRID

@@ -24,7 +24,8 @@ EXPORTS = ["qed_create", "qed_destroy", "qed_last_error", "qed_reserve", "qed_se
            "qed_fill_standing_wave", "qed_gather_push", "qed_emit_photons", "qed_create_pairs",
            "qed_compact", "qed_sample", "qed_get_status", "qed_surrogate_params",
            "qed_surrogate_train", "qed_surrogate_io", "qed_surrogate_forward", "qed_surrogate_grad",
-           "qed_sort_by_cell"]
+           "qed_sort_by_cell", "qed_set_step", "qed_advance_step", "qed_fill_standing_wave_at_step"]
+QED_STEP_DEVICE = -1
 
 
 class qed_params_t(ctypes.Structure):
@@ -95,6 +96,10 @@ def lib():
             "qed_compact": (ctypes.c_int, [vp, ctypes.POINTER(qed_species_t), vp]),
             "qed_sample": (ctypes.c_int, [vp, vp, vp, vp, i64, ctypes.c_int, i64, vp, vp, vp, vp]),
             "qed_get_status": (ctypes.c_int, [vp, ctypes.POINTER(qed_counters_t), vp]),
+            "qed_set_step": (ctypes.c_int, [vp, i64, vp]),
+            "qed_advance_step": (ctypes.c_int, [vp, vp]),
+            "qed_fill_standing_wave_at_step": (ctypes.c_int, [vp, vp, ctypes.c_int, ctypes.c_double,
+                                                              ctypes.c_double, ctypes.c_double, ctypes.c_double, vp]),
             "qed_sort_by_cell": (ctypes.c_int, [vp, ctypes.POINTER(qed_fields_t), ctypes.POINTER(qed_species_t),
                                                 ctypes.POINTER(qed_species_t), vp]),
             "qed_surrogate_params": (ctypes.c_int, [ctypes.c_int]),
@@ -181,6 +186,17 @@ class Context:
     def qed_fill_standing_wave(self, grid, n, L, a0, t, stream=None):
         return self._check(lib().qed_fill_standing_wave(self.h, ctypes.c_void_p(grid.data_ptr()), int(n),
                                                         float(L), float(a0), float(t), _stream(stream)))
+
+    def qed_set_step(self, step, stream=None):
+        return self._check(lib().qed_set_step(self.h, int(step), _stream(stream)))
+
+    def qed_advance_step(self, stream=None):
+        return self._check(lib().qed_advance_step(self.h, _stream(stream)))
+
+    def qed_fill_standing_wave_at_step(self, grid, n, L, a0, t0, dt, stream=None):
+        return self._check(lib().qed_fill_standing_wave_at_step(self.h, ctypes.c_void_p(grid.data_ptr()), int(n),
+                                                                float(L), float(a0), float(t0), float(dt),
+                                                                _stream(stream)))
 
     def qed_gather_push(self, fields, leptons, charge, dt, step, stream=None):
         return self._check(lib().qed_gather_push(self.h, ctypes.byref(fields.c), ctypes.byref(leptons.c),

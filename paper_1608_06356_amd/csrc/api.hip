@@ -104,6 +104,8 @@ int qed_create(qed_ctx_t *out, const qed_params_t *p) {
   if (e == hipSuccess) e = dalloc(&c->d_n_emit, 1);
   if (e == hipSuccess) e = dalloc(&c->d_ticket, 1);
   if (e == hipSuccess) e = dalloc(&c->d_killed, 1);
+  if (e == hipSuccess) e = dalloc(&c->d_step, 1);
+  if (e == hipSuccess) e = hipMemset(c->d_step, 0, sizeof(int64_t));
   if (e == hipSuccess) e = hipMemset(c->d_counters, 0, sizeof(unsigned long long) * qed::cNumCounters);
   if (e == hipSuccess) e = hipMemset(c->d_next_id, 0, sizeof(uint64_t));
   if (e == hipSuccess) e = hipMemset(c->d_n_emit, 0, sizeof(int64_t));
@@ -124,7 +126,7 @@ void qed_destroy(qed_ctx_t c) {
                   c->pair_S64, c->pair_L32, c->pair_s0sc, c->pair_q16, c->tab_work, c->d_counters,
                   c->d_next_id, c->d_n_emit, c->d_ticket, c->rad_chk, c->mlp_theta[0], c->mlp_theta[1],
                   c->mlp_grad[0], c->mlp_grad[1], c->mlp_m[0], c->mlp_m[1], c->mlp_v[0], c->mlp_v[1],
-                  c->sort_keys, c->sort_vals, c->sort_tmp, c->d_killed};
+                  c->sort_keys, c->sort_vals, c->sort_tmp, c->d_killed, c->d_step};
   for (void *p : ptrs) (void)hipFree(p);
   delete c;
 }
@@ -203,7 +205,7 @@ int qed_init_optical_depth(qed_ctx_t c, qed_species_t *sp, int64_t step, void *s
   if (!c) return QED_ERR_ARG;
   int r = check_species(c, sp, "species");
   if (r) return r;
-  if (step < 0) return fail(c, QED_ERR_ARG, "step must be >= 0");
+  if (step < 0 && step != QED_STEP_DEVICE) return fail(c, QED_ERR_ARG, "step must be >= 0 or QED_STEP_DEVICE");
   hipError_t e = qed::launch_init_tau(c, sp, step, S(st));
   return e == hipSuccess ? QED_OK : hip_fail(c, e, "init_optical_depth");
 }
@@ -211,8 +213,29 @@ int qed_init_optical_depth(qed_ctx_t c, qed_species_t *sp, int64_t step, void *s
 int qed_fill_standing_wave(qed_ctx_t c, float *grid, int n, double L, double a0, double t, void *st) {
   if (!c) return QED_ERR_ARG;
   if (!grid || n < 3 || n > 4096 || !(L > 0)) return fail(c, QED_ERR_ARG, "fill_standing_wave: bad grid");
-  hipError_t e = qed::launch_standing_wave(grid, n, L, a0, t, S(st));
+  hipError_t e = qed::launch_standing_wave(grid, n, L, a0, t, 0.0, nullptr, S(st));
   return e == hipSuccess ? QED_OK : hip_fail(c, e, "fill_standing_wave");
+}
+
+int qed_fill_standing_wave_at_step(qed_ctx_t c, float *grid, int n, double L, double a0, double t0, double dt,
+                                   void *st) {
+  if (!c) return QED_ERR_ARG;
+  if (!grid || n < 3 || n > 4096 || !(L > 0)) return fail(c, QED_ERR_ARG, "fill_standing_wave: bad grid");
+  hipError_t e = qed::launch_standing_wave(grid, n, L, a0, t0, dt, c->d_step, S(st));
+  return e == hipSuccess ? QED_OK : hip_fail(c, e, "fill_standing_wave_at_step");
+}
+
+int qed_set_step(qed_ctx_t c, int64_t step, void *st) {
+  if (!c) return QED_ERR_ARG;
+  if (step < 0) return fail(c, QED_ERR_ARG, "set_step: step must be >= 0");
+  hipError_t e = qed::launch_set_step(c, step, 0, S(st));
+  return e == hipSuccess ? QED_OK : hip_fail(c, e, "set_step");
+}
+
+int qed_advance_step(qed_ctx_t c, void *st) {
+  if (!c) return QED_ERR_ARG;
+  hipError_t e = qed::launch_set_step(c, 1, 1, S(st));
+  return e == hipSuccess ? QED_OK : hip_fail(c, e, "advance_step");
 }
 
 int qed_gather_push(qed_ctx_t c, const qed_fields_t *f, qed_species_t *lep, int charge, double dt,
@@ -241,7 +264,7 @@ int qed_emit_photons(qed_ctx_t c, qed_species_t *lep, qed_species_t *ph, int64_t
   if (r) return r;
   if ((r = check_species(c, ph, "photons"))) return r;
   if (lep->dtype != ph->dtype) return fail(c, QED_ERR_ARG, "leptons and photons must share dtype");
-  if (step < 0) return fail(c, QED_ERR_ARG, "step must be >= 0");
+  if (step < 0 && step != QED_STEP_DEVICE) return fail(c, QED_ERR_ARG, "step must be >= 0 or QED_STEP_DEVICE");
   if (!c->tables_ready) return fail(c, QED_ERR_STATE, "tables not built");
   if (c->em_owner != lep->x || c->em_dtype != lep->dtype)
     return fail(c, QED_ERR_STATE, "emit_photons must follow qed_gather_push on the same leptons");
@@ -261,7 +284,7 @@ int qed_create_pairs(qed_ctx_t c, const qed_fields_t *f, qed_species_t *ph, qed_
   if (ph->dtype != el->dtype || ph->dtype != po->dtype)
     return fail(c, QED_ERR_ARG, "photons, electrons and positrons must share dtype");
   if (!(dt > 0)) return fail(c, QED_ERR_ARG, "dt must be > 0");
-  if (step < 0) return fail(c, QED_ERR_ARG, "step must be >= 0");
+  if (step < 0 && step != QED_STEP_DEVICE) return fail(c, QED_ERR_ARG, "step must be >= 0 or QED_STEP_DEVICE");
   if (!c->tables_ready) return fail(c, QED_ERR_STATE, "tables not built");
   if ((r = ensure_reserved(c, ph->capacity))) return r;
   hipError_t e = qed::launch_pairs(c, f, ph, el, po, dt, step, S(st));

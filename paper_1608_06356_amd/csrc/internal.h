@@ -27,6 +27,7 @@ struct qed_ctx {
   // counters and ids
   unsigned long long *d_counters = nullptr;              // qed_counters_t layout
   uint64_t *d_next_id = nullptr;
+  int64_t *d_step = nullptr;     // device step index (QED_STEP_DEVICE)
 
   // emitter list produced by qed_gather_push
   int64_t reserved = 0;
@@ -90,7 +91,9 @@ hipError_t launch_pairs(qed_ctx *c, const qed_fields_t *f, const qed_species_t *
                         hipStream_t st);
 hipError_t launch_compact(qed_ctx *c, const qed_species_t *sp, hipStream_t st);
 hipError_t launch_init_tau(qed_ctx *c, const qed_species_t *sp, int64_t step, hipStream_t st);
-hipError_t launch_standing_wave(float *grid, int n, double L, double a0, double t, hipStream_t st);
+hipError_t launch_standing_wave(float *grid, int n, double L, double a0, double t0, double dt_step,
+                                const int64_t *d_step, hipStream_t st);
+hipError_t launch_set_step(qed_ctx *c, int64_t v, int add, hipStream_t st);
 hipError_t launch_sample(qed_ctx *c, const double *chi, const double *gamma, const uint64_t *id,
                          int64_t n, int precision, int64_t step, float *lnw, float *xi, float *lnwp,
                          hipStream_t st);

@@ -257,6 +257,7 @@ struct InferArgs {
   int64_t n;
   uint32_t seed;
   uint64_t step;
+  const int64_t *d_step;
   const float *lnh32, *L32, *s0sc, *chk;
   const uint16_t *q16;
   float *lnw, *xi, *lnwp;
@@ -291,7 +292,7 @@ __global__ __launch_bounds__(kInferThreads) void k_infer(InferArgs a) {
     const double chi = valid ? a.chi[i] : 1.0;
     const double gam = valid ? a.gamma[i] : 1.0;
     const uint64_t id = valid ? a.id[i] : 0;
-    const uint4 r = stream4(id, a.seed, a.step, kLeptonEvent, 0u);
+    const uint4 r = stream4(id, a.seed, a.d_step ? (uint64_t)*a.d_step : a.step, kLeptonEvent, 0u);
     const float u = unit<float>(r.x), urow = unit<float>(r.z);
     const float t = logf(u) - log1pf(-u);
     const bool in_chi = chi >= kRadChiMin && chi <= kRadChiMax;
@@ -415,6 +416,7 @@ hipError_t launch_mlp_forward(const float *theta, int net, const float *x, int64
 hipError_t launch_mlp_sample(qed_ctx *c, const double *chi, const double *gamma, const uint64_t *id, int64_t n,
                              int64_t step, float *lnw, float *xi, float *lnwp, float tol, hipStream_t st) {
   InferArgs a{c->mlp_theta[0], c->mlp_theta[1], chi, gamma, id, n, c->params.seed, (uint64_t)step,
+              step < 0 ? c->d_step : nullptr,
               c->rad_lnh32, c->pair_L32, c->rad_s0sc, c->rad_chk, c->rad_q16, lnw, xi, lnwp, tol,
               c->d_counters + cMlpFallbackXi};
   static bool attr = false;

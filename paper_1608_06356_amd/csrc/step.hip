@@ -284,11 +284,14 @@ struct EmitArgs {
   int kmax;
   int recoil;
   uint64_t step;
+  const int64_t *d_step;       // if set, the step index is read from the device
   ScanDev sc;
   unsigned long long *counters;
 };
 
 constexpr int kEmitThreads = 1024;
+
+__device__ __forceinline__ uint64_t step_of(uint64_t v, const int64_t *p) { return p ? (uint64_t)*p : v; }
 
 template <typename R, typename Tab>
 __device__ void emit_tile(const EmitArgs<R> &a, const Tab &tab, const R *lnh, uint32_t tile,
@@ -318,7 +321,7 @@ __device__ void emit_tile(const EmitArgs<R> &a, const Tab &tab, const R *lnh, ui
     bool recoiled = false;
     int k = 0;
     while (true) {
-      const uint4 u = stream4(id, a.seed, a.step, kLeptonEvent, (uint32_t)k);
+      const uint4 u = stream4(id, a.seed, step_of(a.step, a.d_step), kLeptonEvent, (uint32_t)k);
       R xi, om;
       sample_rad<R>(tab, (R)chi, unit<R>(u.x), unit<R>(u.z), xi, om);
       const R gp = xi * g;
@@ -595,7 +598,7 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
     for (int k = 0; k < a.kmax; ++k) {
       if (!__any(active)) break;
       mlp::reload_barrier();
-      const uint4 u = stream4(id, a.seed, a.step, kLeptonEvent, (uint32_t)k);
+      const uint4 u = stream4(id, a.seed, step_of(a.step, a.d_step), kLeptonEvent, (uint32_t)k);
       const float uxi = unit<float>(u.x), urow = unit<float>(u.z);
       const float t = logf(uxi) - log1pf(-uxi);
       const bool in_chi = chi >= kRadChiMin && chi <= kRadChiMax;
@@ -734,6 +737,7 @@ struct PairArgs {
   uint64_t *next_id;
   uint32_t seed;
   uint64_t step;
+  const int64_t *d_step;
   ScanDev sc;
   unsigned long long *counters;
   int64_t *killed;
@@ -777,7 +781,7 @@ __device__ void pair_tile(const PairArgs<R> &a, const Tab &tab, const R *L, uint
     if (W > 0.0 && tau <= W * a.dtd) {
       ev = 1;
       const uint64_t id = a.ph.id[i];
-      const uint4 u = stream4(id, a.seed, a.step, kPhotonEvent, 0u);
+      const uint4 u = stream4(id, a.seed, step_of(a.step, a.d_step), kPhotonEvent, 0u);
       R xh, omh;
       sample_pair_half<R>(tab, (R)chi, unit<R>(u.x), unit<R>(u.y), xh, omh);
       const bool flip = u.y & 1u;
@@ -944,8 +948,9 @@ __global__ void k_zero_scan(uint32_t *ticket, uint64_t *status, int64_t n) {
 }
 
 __global__ void k_init_tau(const uint64_t *id, double *tau, const int64_t *count, uint32_t seed,
-                           uint64_t step, int64_t cap) {
+                           uint64_t step_v, const int64_t *d_step, int64_t cap) {
   const int64_t n = *count;
+  const uint64_t step = step_of(step_v, d_step);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n && i < cap;
        i += (int64_t)gridDim.x * blockDim.x) {
     const uint4 u = stream4(id[i], seed, step, kInitTau, 0u);
@@ -953,8 +958,10 @@ __global__ void k_init_tau(const uint64_t *id, double *tau, const int64_t *count
   }
 }
 
-__global__ void k_standing_wave(float *grid, int n, double dx, double a0, double t) {
+__global__ void k_standing_wave(float *grid, int n, double dx, double a0, double t0, double dt_step,
+                                const int64_t *d_step) {
   const int64_t total = (int64_t)n * n * n;
+  const double t = d_step ? t0 + dt_step * (double)*d_step : t0;
   const double ct = cos(t), st = sin(t);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -986,7 +993,8 @@ __device__ void sample_one(const Tab &tab, const R *lnh, const R *L, double chi,
 
 __global__ void k_sample_f64(const double *chi, const double *gamma, const uint64_t *id, int64_t n,
                              const double *lnh, const double *L, const double *S64, uint32_t seed,
-                             uint64_t step, float *lnw, float *xi, float *lnwp) {
+                             uint64_t step_v, const int64_t *d_step, float *lnw, float *xi, float *lnwp) {
+  const uint64_t step = step_of(step_v, d_step);
   const RowF64 tab{S64};
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -995,7 +1003,9 @@ __global__ void k_sample_f64(const double *chi, const double *gamma, const uint6
 
 __global__ void k_sample_f32(const double *chi, const double *gamma, const uint64_t *id, int64_t n,
                              const float *lnh, const float *L, const uint16_t *q16, const float *s0sc,
-                             uint32_t seed, uint64_t step, float *lnw, float *xi, float *lnwp) {
+                             uint32_t seed, uint64_t step_v, const int64_t *d_step, float *lnw, float *xi,
+                             float *lnwp) {
+  const uint64_t step = step_of(step_v, d_step);
   const RowQ16 tab{q16, s0sc};
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -1094,10 +1104,11 @@ hipError_t launch_emit(qed_ctx *c, const qed_species_t *lep, const qed_species_t
   const ScanDev sc{c->d_ticket, c->d_status};
   const int recoil = (c->params.flags & QED_FLAG_NO_RECOIL) ? 0 : 1;
   const unsigned grid = (unsigned)(ntiles < c->n_cu ? ntiles : c->n_cu);
+  const int64_t *dstep = step < 0 ? c->d_step : nullptr;
   if (use_mlp) {
     EmitArgs<float> a{dev_species(lep), dev_species(ph), c->rad_lnh32, c->rad_S64, c->rad_q16,
                       c->rad_s0sc, c->em_idx, (const EmRec<float> *)c->em_rec, c->d_n_emit,
-                      c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, sc,
+                      c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, dstep, sc,
                       c->d_counters};
     static bool attr = false;
     if (!attr) {
@@ -1109,13 +1120,13 @@ hipError_t launch_emit(qed_ctx *c, const qed_species_t *lep, const qed_species_t
   } else if (lep->dtype == QED_F32) {
     EmitArgs<float> a{dev_species(lep), dev_species(ph), c->rad_lnh32, c->rad_S64, c->rad_q16,
                       c->rad_s0sc, c->em_idx, (const EmRec<float> *)c->em_rec, c->d_n_emit,
-                      c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, sc,
+                      c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, dstep, sc,
                       c->d_counters};
     hipLaunchKernelGGL(k_emit_f32, dim3(grid), dim3(kEmitThreads), 0, st, a);
   } else {
     EmitArgs<double> a{dev_species(lep), dev_species(ph), c->rad_lnh64, c->rad_S64, c->rad_q16,
                        c->rad_s0sc, c->em_idx, (const EmRec<double> *)c->em_rec, c->d_n_emit,
-                       c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, sc,
+                       c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, dstep, sc,
                        c->d_counters};
     hipLaunchKernelGGL(k_emit_f64, dim3(grid), dim3(kEmitThreads), 0, st, a);
   }
@@ -1136,12 +1147,12 @@ hipError_t launch_pairs(qed_ctx *c, const qed_fields_t *f, const qed_species_t *
   if (ph->dtype == QED_F32) {
     PairArgs<float> a{dev_species(ph), dev_species(el), dev_species(po), dev_fields(f), c->pair_L32,
                       c->pair_S64, c->pair_q16, c->pair_s0sc, (float)dt, dt, move, c->d_next_id,
-                      c->params.seed, (uint64_t)step, sc, c->d_counters, killed};
+                      c->params.seed, (uint64_t)step, step < 0 ? c->d_step : nullptr, sc, c->d_counters, killed};
     hipLaunchKernelGGL(k_pairs_f32, dim3(grid), dim3(kPairThreads), 0, st, a);
   } else {
     PairArgs<double> a{dev_species(ph), dev_species(el), dev_species(po), dev_fields(f), c->pair_L64,
                        c->pair_S64, c->pair_q16, c->pair_s0sc, dt, dt, move, c->d_next_id,
-                       c->params.seed, (uint64_t)step, sc, c->d_counters, killed};
+                       c->params.seed, (uint64_t)step, step < 0 ? c->d_step : nullptr, sc, c->d_counters, killed};
     hipLaunchKernelGGL(k_pairs_f64, dim3(grid), dim3(kPairThreads), 0, st, a);
   }
   return hipGetLastError();
@@ -1171,15 +1182,25 @@ hipError_t launch_init_tau(qed_ctx *c, const qed_species_t *sp, int64_t step, hi
   int64_t blocks = (sp->capacity + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(k_init_tau, dim3((unsigned)blocks), dim3(256), 0, st, sp->id, sp->tau,
-                     sp->count, c->params.seed, (uint64_t)step, sp->capacity);
+                     sp->count, c->params.seed, (uint64_t)step, step < 0 ? c->d_step : nullptr, sp->capacity);
   return hipGetLastError();
 }
 
-hipError_t launch_standing_wave(float *grid, int n, double L, double a0, double t, hipStream_t st) {
+hipError_t launch_standing_wave(float *grid, int n, double L, double a0, double t0, double dt_step,
+                                const int64_t *d_step, hipStream_t st) {
   const int64_t total = (int64_t)n * n * n;
   int64_t blocks = (total + 255) / 256;
   if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(k_standing_wave, dim3((unsigned)blocks), dim3(256), 0, st, grid, n, L / n, a0, t);
+  hipLaunchKernelGGL(k_standing_wave, dim3((unsigned)blocks), dim3(256), 0, st, grid, n, L / n, a0, t0, dt_step,
+                     d_step);
+  return hipGetLastError();
+}
+
+__global__ void k_add_i64(int64_t *p, int64_t v) { *p += v; }
+
+hipError_t launch_set_step(qed_ctx *c, int64_t v, int add, hipStream_t st) {
+  if (add) hipLaunchKernelGGL(k_add_i64, dim3(1), dim3(1), 0, st, c->d_step, v);
+  else hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, st, c->d_step, v);
   return hipGetLastError();
 }
 
@@ -1191,12 +1212,13 @@ hipError_t launch_sample(qed_ctx *c, const double *chi, const double *gamma, con
   if (blocks < 1) blocks = 1;
   if (precision == QED_F64)
     hipLaunchKernelGGL(k_sample_f64, dim3((unsigned)blocks), dim3(256), 0, st, chi, gamma, id, n,
-                       c->rad_lnh64, c->pair_L64, c->rad_S64, c->params.seed, (uint64_t)step, lnw,
+                       c->rad_lnh64, c->pair_L64, c->rad_S64, c->params.seed, (uint64_t)step,
+                       step < 0 ? c->d_step : nullptr, lnw,
                        xi, lnwp);
   else
     hipLaunchKernelGGL(k_sample_f32, dim3((unsigned)blocks), dim3(256), 0, st, chi, gamma, id, n,
                        c->rad_lnh32, c->pair_L32, c->rad_q16, c->rad_s0sc, c->params.seed,
-                       (uint64_t)step, lnw, xi, lnwp);
+                       (uint64_t)step, step < 0 ? c->d_step : nullptr, lnw, xi, lnwp);
   return hipGetLastError();
 }
 
