@@ -79,6 +79,11 @@ extern "C" {
                                       qed_compact skip when nothing died (below)   */
 #define QED_FLAG_SURROGATE     8u  /* float32 species: rates and xi from the trained
                                       surrogate nets (table fallback), see below   */
+#define QED_FLAG_METHOD_I     16u  /* the paper's method I generator (text after
+                                      Eq. 7): an event in a (sub-)step if W Dt > r_1,
+                                      at most one per sub-step, with the step split
+                                      into N = ceil(W Dt / 0.2) sub-steps             */
+#define QED_FLAG_NO_SUBSTEP   32u  /* with QED_FLAG_METHOD_I: N = 1 (no adaptive step) */
 
 #define QED_DEAD_ID UINT64_MAX     /* id of a particle removed by pair creation */
 #define QED_STEP_DEVICE (-1)       /* step argument: use the context's device step index */

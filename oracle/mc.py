@@ -224,6 +224,76 @@ def lepton_step(x, p, tau, ids, E, B, *, q, dt, step, seed, sampler, next_id,
                 n_capped=n_capped, next_id=int(next_id) + nph)
 
 
+def lepton_step_method1_full(x, p, ids, E, B, *, q, dt, step, seed, sampler, next_id, L=None,
+                             kmax=KMAX, recoil=True, substep=True, w_max=0.2, nmax=1024):
+    """The paper's adopted generator (method I, text after Eq. 7, with the
+    adaptive step of its Fig. 3 discussion): the step is split into
+    N = ceil(W Dt / 0.2) sub-steps (N = 1 without sub-stepping); in sub-step j
+    an event happens if W Dt / N > r_1, at most one per sub-step, with W
+    recomputed after a recoil.  Sub-step j uses counter k = j of the particle's
+    LEPTON_EVENT stream: outputs (u_xi, r_1, u_row, u_ph).  At most kmax events
+    per step.  N is fixed by the rate at the start of the step."""
+    x = np.array(x, dtype=np.float64)
+    p = np.array(p, dtype=np.float64)
+    ids = np.asarray(ids, dtype=np.uint64)
+    n = x.shape[0]
+    p = boris(p, E, B, q, dt)
+    gam = np.sqrt(1.0 + np.sum(p * p, axis=-1))
+    x = wrap(x + p / gam[:, None] * dt, L)
+    pabs0 = np.sqrt(np.sum(p * p, axis=-1))
+    nhat = p / np.where(pabs0 > 0, pabs0, 1.0)[:, None]
+    chi = spectra.chi_lepton(p, E, B)
+    W = sampler.rate(chi, gam)
+    N = np.ones(n, dtype=np.int64)
+    if substep:
+        N = np.where(W > 0, np.maximum(1, np.ceil(W * dt / w_max)), 1).astype(np.int64)
+        N = np.minimum(N, nmax)
+    j = np.zeros(n, dtype=np.int64)
+    nev = np.zeros(n, dtype=np.int64)
+    active = W > 0
+    recs = []
+    emitters = None
+    n_capped = 0
+    while np.any(active):
+        idx = np.nonzero(active)[0]
+        r = philox.stream(ids[idx], seed, step, philox.LEPTON_EVENT, j[idx].astype(np.uint32))
+        u = philox.uniform(r)
+        fire = W[idx] * dt / N[idx] > u[:, 1]
+        f = idx[fire]
+        if f.size:
+            uf = u[fire]
+            xi, om = sampler.sample(chi[f], uf[:, 0], uf[:, 2])
+            gph = xi * gam[f]
+            acc = gph >= PHOTON_XI_MIN_GAMMA
+            for par, k_ev, g_ph, t_ph in zip(f[acc], nev[f][acc], gph[acc], -np.log(uf[acc, 3])):
+                recs.append((int(par), int(k_ev), float(g_ph), float(t_ph)))
+            a = f[acc]
+            if recoil and a.size:
+                gnew = np.maximum(om[acc] * gam[a], 1.0)
+                pnew = np.sqrt(np.maximum(gnew * gnew - 1.0, 0.0))
+                p[a] = nhat[a] * pnew[:, None]
+                gam[a] = gnew
+                chi[a] = spectra.chi_lepton(p[a], E[a], B[a])
+                W[a] = sampler.rate(chi[a], gam[a])
+            nev[f] += 1
+        j[idx] += 1
+        capped = (nev >= kmax) & (j < N) & active
+        n_capped += int(np.count_nonzero(capped))
+        active = active & (j < N) & (nev < kmax) & (W > 0)
+    recs.sort(key=lambda r: (r[0], r[1]))
+    nph = len(recs)
+    par = np.array([r[0] for r in recs], dtype=np.int64)
+    gph = np.array([r[2] for r in recs], dtype=np.float64)
+    photons = dict(
+        x=x[par] if nph else np.zeros((0, 3)),
+        k=nhat[par] * gph[:, None] if nph else np.zeros((0, 3)),
+        tau=np.array([r[3] for r in recs], dtype=np.float64),
+        id=(np.uint64(next_id) + np.arange(nph, dtype=np.uint64)),
+        parent=par, gamma=gph)
+    return dict(x=x, p=p, id=ids, chi=chi, N=N, photons=photons, n_events=int(nev.sum()),
+                n_capped=n_capped, next_id=int(next_id) + nph)
+
+
 def lepton_step_method1(p, tau_unused, ids, E, B, *, q, dt, step, seed, sampler):
     """Method I of the paper: emit (at most once per step) if W dt > r_1.
     Only the decision is modelled (no push, no recoil), for the time-step

@@ -17,6 +17,7 @@ QED_F32, QED_F64 = 0, 1
 QED_FORMULA_I, QED_FORMULA_II = 1, 2
 QED_FIELD_UNIFORM, QED_FIELD_GRID, QED_FIELD_PER_PARTICLE = 0, 1, 2
 QED_FLAG_NO_RECOIL, QED_FLAG_STATIC_PHOTONS, QED_FLAG_TRACK_DEAD, QED_FLAG_SURROGATE = 1, 2, 4, 8
+QED_FLAG_METHOD_I, QED_FLAG_NO_SUBSTEP = 16, 32
 QED_SAMPLER_MLP = 2
 DEAD_ID = 0xFFFFFFFFFFFFFFFF
 EXPORTS = ["qed_create", "qed_destroy", "qed_last_error", "qed_reserve", "qed_set_next_id",

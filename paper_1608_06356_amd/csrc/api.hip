@@ -70,7 +70,7 @@ int ensure_reserved(qed_ctx *c, int64_t n) {
   // for the largest tile count of any kernel
   const int64_t em_cap = n;
   const int64_t status_len = n / 256 + 64;
-  if ((e = dalloc(&c->em_idx, em_cap)) != hipSuccess || (e = dalloc(&c->em_rec, 128 * em_cap)) != hipSuccess ||
+  if ((e = dalloc(&c->em_idx, em_cap)) != hipSuccess || (e = dalloc(&c->em_rec, 144 * em_cap)) != hipSuccess ||
       (e = dalloc(&c->d_status, status_len)) != hipSuccess || (e = dalloc(&c->em_mask, n / 64 + 1)) != hipSuccess) {
     free_emitters(c);
     return hip_fail(c, e, "reserve: hipMalloc");
@@ -240,7 +240,6 @@ int qed_advance_step(qed_ctx_t c, void *st) {
 
 int qed_gather_push(qed_ctx_t c, const qed_fields_t *f, qed_species_t *lep, int charge, double dt,
                     int64_t step, void *st) {
-  (void)step;
   if (!c) return QED_ERR_ARG;
   int r = check_species(c, lep, "leptons");
   if (r) return r;
@@ -251,10 +250,14 @@ int qed_gather_push(qed_ctx_t c, const qed_fields_t *f, qed_species_t *lep, int 
   if ((r = ensure_reserved(c, lep->capacity))) return r;
   if ((c->params.flags & QED_FLAG_SURROGATE) && lep->dtype == QED_F32 && !c->mlp_ready)
     return fail(c, QED_ERR_STATE, "QED_FLAG_SURROGATE: surrogate not trained or loaded");
-  hipError_t e = qed::launch_gather_push(c, f, lep, charge, dt, S(st));
+  if ((c->params.flags & QED_FLAG_SURROGATE) && (c->params.flags & QED_FLAG_METHOD_I))
+    return fail(c, QED_ERR_ARG, "QED_FLAG_METHOD_I is not available with QED_FLAG_SURROGATE");
+  if (step < 0 && step != QED_STEP_DEVICE) return fail(c, QED_ERR_ARG, "step must be >= 0 or QED_STEP_DEVICE");
+  hipError_t e = qed::launch_gather_push(c, f, lep, charge, dt, step, S(st));
   if (e != hipSuccess) return hip_fail(c, e, "gather_push");
   c->em_owner = lep->x;
   c->em_dtype = lep->dtype;
+  c->em_dt = dt;
   return QED_OK;
 }
 

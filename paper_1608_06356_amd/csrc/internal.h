@@ -83,7 +83,7 @@ hipError_t launch_mlp_sample(qed_ctx *c, const double *chi, const double *gamma,
 
 namespace qed {
 hipError_t launch_gather_push(qed_ctx *c, const qed_fields_t *f, const qed_species_t *sp, int charge,
-                              double dt, hipStream_t st);
+                              double dt, int64_t step, hipStream_t st);
 hipError_t launch_emit(qed_ctx *c, const qed_species_t *lep, const qed_species_t *ph, int64_t step,
                        hipStream_t st);
 hipError_t launch_pairs(qed_ctx *c, const qed_fields_t *f, const qed_species_t *ph,

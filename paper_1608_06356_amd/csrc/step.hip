@@ -155,6 +155,7 @@ struct alignas(16) EmRec {
   R x[3], p[3], F[6];       // position after the push, momentum p^{n+1/2}, E and B at x^n
   uint64_t id;
   double chi, W, rem;       // chi and rate of the first event, time left after it
+  int32_t j0, nsub;         // method I: sub-step of the first event, number of sub-steps
 };
 
 template <typename R>
@@ -168,9 +169,34 @@ struct GPArgs {
   EmRec<R> *rec;         // slot = particle index
   int64_t tpx;           // tiles per XCD
   unsigned long long *counters;
+  int gen;               // 0: optical depth; 1: method I with sub-steps; 2: method I, one step
+  uint32_t seed;
+  uint64_t step;
+  const int64_t *d_step;
 };
 
 constexpr int kGPThreads = 256, kGPTile = kGPThreads;
+constexpr double kSubstepW = 0.2;     // method I: W Dt / N <= 0.2
+constexpr int kMaxSubsteps = 1024;
+
+__device__ __forceinline__ uint64_t step_of(uint64_t v, const int64_t *p) { return p ? (uint64_t)*p : v; }
+
+// Method I: number of sub-steps of the step and the first sub-step j in
+// [j, N) whose draw r_1 (second Philox output of counter j) is below W Dt / N.
+__device__ __forceinline__ int method1_nsub(double W, double dt, int gen) {
+  if (gen != 1 || !(W > 0.0)) return 1;
+  double N = ceil(W * dt / kSubstepW);
+  N = N < 1.0 ? 1.0 : (N > kMaxSubsteps ? kMaxSubsteps : N);
+  return (int)N;
+}
+__device__ __forceinline__ int method1_next(uint64_t id, uint32_t seed, uint64_t step, int j, int N, double W,
+                                            double dt) {
+  for (; j < N; ++j) {
+    const uint4 u = stream4(id, seed, step, kLeptonEvent, (uint32_t)j);
+    if (W * dt / N > unit<double>(u.y)) return j;
+  }
+  return N;
+}
 
 template <typename R, int FK>
 __global__ __launch_bounds__(kGPThreads) void k_gather_push(GPArgs<R> a) {
@@ -210,8 +236,17 @@ __global__ __launch_bounds__(kGPThreads) void k_gather_push(GPArgs<R> a) {
     } else {
       nnan = 1;
     }
-    if (W > 0.0 && tau <= W * a.dtd) {
-      flag = true;
+    int j0 = 0, nsub = 1;
+    if (a.gen) {
+      // method I: first sub-step with an event, if any
+      const uint64_t id = a.sp.id[i];
+      nsub = method1_nsub(W, a.dtd, a.gen);
+      j0 = W > 0.0 ? method1_next(id, a.seed, step_of(a.step, a.d_step), 0, nsub, W, a.dtd) : nsub;
+      flag = j0 < nsub;
+    } else {
+      flag = W > 0.0 && tau <= W * a.dtd;
+    }
+    if (flag) {
       EmRec<R> r;
       r.x[0] = x; r.x[1] = y; r.x[2] = z; r.p[0] = px; r.p[1] = py; r.p[2] = pz;
 #pragma unroll
@@ -220,8 +255,10 @@ __global__ __launch_bounds__(kGPThreads) void k_gather_push(GPArgs<R> a) {
       r.chi = chi;
       r.W = W;
       r.rem = a.dtd - tau / W;
+      r.j0 = j0;
+      r.nsub = nsub;
       a.rec[i] = r;
-    } else {
+    } else if (!a.gen) {
       a.sp.tau[i] = tau - W * a.dtd;
     }
   }
@@ -287,11 +324,11 @@ struct EmitArgs {
   const int64_t *d_step;       // if set, the step index is read from the device
   ScanDev sc;
   unsigned long long *counters;
+  int gen;                     // event generator (see GPArgs)
+  double dtd;
 };
 
 constexpr int kEmitThreads = 1024;
-
-__device__ __forceinline__ uint64_t step_of(uint64_t v, const int64_t *p) { return p ? (uint64_t)*p : v; }
 
 template <typename R, typename Tab>
 __device__ void emit_tile(const EmitArgs<R> &a, const Tab &tab, const R *lnh, uint32_t tile,
@@ -319,9 +356,10 @@ __device__ void emit_tile(const EmitArgs<R> &a, const Tab &tab, const R *lnh, ui
     R g = sqrt((R)1 + px * px + py * py + pz * pz);
     double tau = 0.0;
     bool recoiled = false;
-    int k = 0;
-    while (true) {
-      const uint4 u = stream4(id, a.seed, step_of(a.step, a.d_step), kLeptonEvent, (uint32_t)k);
+    const uint64_t step = step_of(a.step, a.d_step);
+    // one event: sample xi, infrared cut, photon, recoil (counter k of the stream)
+    auto event = [&](uint32_t k) {
+      const uint4 u = stream4(id, a.seed, step, kLeptonEvent, k);
       R xi, om;
       sample_rad<R>(tab, (R)chi, unit<R>(u.x), unit<R>(u.z), xi, om);
       const R gp = xi * g;
@@ -343,14 +381,34 @@ __device__ void emit_tile(const EmitArgs<R> &a, const Tab &tab, const R *lnh, ui
       } else {
         ++nrej;
       }
-      tau = -log(unit<double>(u.y));
-      ++k;
-      const bool again = W > 0.0 && tau <= W * rem;
-      if (!again) break;
-      if (k >= a.kmax) { ++ncap; break; }
-      rem -= tau / W;
+      return u;
+    };
+    if (a.gen) {
+      // method I: at most one event per sub-step, W Dt / N > r_1
+      const int N = rc.nsub;
+      int j = rc.j0, done = 0;
+      while (true) {
+        event((uint32_t)j);
+        ++done;
+        ++j;
+        if (done >= a.kmax) { if (j < N) ++ncap; break; }
+        if (!(W > 0.0)) break;
+        j = method1_next(id, a.seed, step, j, N, W, a.dtd);
+        if (j >= N) break;
+      }
+    } else {
+      int k = 0;
+      while (true) {
+        const uint4 u = event((uint32_t)k);
+        tau = -log(unit<double>(u.y));
+        ++k;
+        const bool again = W > 0.0 && tau <= W * rem;
+        if (!again) break;
+        if (k >= a.kmax) { ++ncap; break; }
+        rem -= tau / W;
+      }
     }
-    a.lep.tau[i] = tau - W * rem;
+    if (!a.gen) a.lep.tau[i] = tau - W * rem;
     if (recoiled) { PX[i] = px; PY[i] = py; PZ[i] = pz; }
   }
   count_add(a.counters, cEvents, nev);
@@ -1017,7 +1075,7 @@ __global__ void k_sample_f32(const double *chi, const double *gamma, const uint6
 // =============================================================== launchers
 namespace qed {
 
-static_assert(sizeof(EmRec<float>) == 80 && sizeof(EmRec<double>) == 128, "emitter record size");
+static_assert(sizeof(EmRec<float>) == 96 && sizeof(EmRec<double>) == 144, "emitter record size");
 
 static SpeciesDev dev_species(const qed_species_t *s) {
   return SpeciesDev{s->x, s->y, s->z, s->px, s->py, s->pz, s->tau, s->id, s->capacity, s->count};
@@ -1054,8 +1112,15 @@ static MlpDev mlp_dev(qed_ctx *c) {
   return MlpDev{c->mlp_theta[0], c->mlp_theta[1], c->rad_chk, c->rad_lnh32, c->rad_q16, c->rad_s0sc, 2e-3f};
 }
 
+static int gen_mode(const qed_ctx *c) {
+  if (!(c->params.flags & QED_FLAG_METHOD_I)) return 0;
+  return (c->params.flags & QED_FLAG_NO_SUBSTEP) ? 2 : 1;
+}
+
 hipError_t launch_gather_push(qed_ctx *c, const qed_fields_t *f, const qed_species_t *sp, int charge,
-                              double dt, hipStream_t st) {
+                              double dt, int64_t step, hipStream_t st) {
+  const int gen = gen_mode(c);
+  const int64_t *dstep = step < 0 ? c->d_step : nullptr;
   const int64_t ntiles = (sp->capacity + kGPTile - 1) / kGPTile;
   const int64_t tpx = (ntiles + kXcds - 1) / kXcds;
   const unsigned grid = (unsigned)(tpx * kXcds);
@@ -1066,7 +1131,7 @@ hipError_t launch_gather_push(qed_ctx *c, const qed_fields_t *f, const qed_speci
     if (g > (int64_t)grid) g = ((int64_t)grid + kXcds - 1) / kXcds * kXcds;
     g = (g + kXcds - 1) / kXcds * kXcds;
     GPArgs<float> a{dev_species(sp), dev_fields(f), c->rad_lnh32, (float)charge, (float)dt, dt, c->em_mask,
-                    (EmRec<float> *)c->em_rec, tpx, c->d_counters};
+                    (EmRec<float> *)c->em_rec, tpx, c->d_counters, 0, c->params.seed, (uint64_t)step, dstep};
     const MlpDev m = mlp_dev(c);
     if (f->kind == QED_FIELD_GRID)
       hipLaunchKernelGGL(k_gather_push_mlp<QED_FIELD_GRID>, dim3((unsigned)g), dim3(kGPThreads), 0, st, a, m);
@@ -1076,11 +1141,11 @@ hipError_t launch_gather_push(qed_ctx *c, const qed_fields_t *f, const qed_speci
       hipLaunchKernelGGL(k_gather_push_mlp<QED_FIELD_PER_PARTICLE>, dim3((unsigned)g), dim3(kGPThreads), 0, st, a, m);
   } else if (sp->dtype == QED_F32) {
     GPArgs<float> a{dev_species(sp), dev_fields(f), c->rad_lnh32, (float)charge, (float)dt, dt, c->em_mask,
-                    (EmRec<float> *)c->em_rec, tpx, c->d_counters};
+                    (EmRec<float> *)c->em_rec, tpx, c->d_counters, gen, c->params.seed, (uint64_t)step, dstep};
     launch_gp_kind<float>(a, f->kind, grid, st);
   } else {
     GPArgs<double> a{dev_species(sp), dev_fields(f), c->rad_lnh64, (double)charge, dt, dt, c->em_mask,
-                     (EmRec<double> *)c->em_rec, tpx, c->d_counters};
+                     (EmRec<double> *)c->em_rec, tpx, c->d_counters, gen, c->params.seed, (uint64_t)step, dstep};
     launch_gp_kind<double>(a, f->kind, grid, st);
   }
   hipError_t e = hipGetLastError();
@@ -1109,7 +1174,7 @@ hipError_t launch_emit(qed_ctx *c, const qed_species_t *lep, const qed_species_t
     EmitArgs<float> a{dev_species(lep), dev_species(ph), c->rad_lnh32, c->rad_S64, c->rad_q16,
                       c->rad_s0sc, c->em_idx, (const EmRec<float> *)c->em_rec, c->d_n_emit,
                       c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, dstep, sc,
-                      c->d_counters};
+                      c->d_counters, gen_mode(c), c->em_dt};
     static bool attr = false;
     if (!attr) {
       (void)hipFuncSetAttribute((const void *)k_emit_mlp, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1121,13 +1186,13 @@ hipError_t launch_emit(qed_ctx *c, const qed_species_t *lep, const qed_species_t
     EmitArgs<float> a{dev_species(lep), dev_species(ph), c->rad_lnh32, c->rad_S64, c->rad_q16,
                       c->rad_s0sc, c->em_idx, (const EmRec<float> *)c->em_rec, c->d_n_emit,
                       c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, dstep, sc,
-                      c->d_counters};
+                      c->d_counters, gen_mode(c), c->em_dt};
     hipLaunchKernelGGL(k_emit_f32, dim3(grid), dim3(kEmitThreads), 0, st, a);
   } else {
     EmitArgs<double> a{dev_species(lep), dev_species(ph), c->rad_lnh64, c->rad_S64, c->rad_q16,
                        c->rad_s0sc, c->em_idx, (const EmRec<double> *)c->em_rec, c->d_n_emit,
                        c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, dstep, sc,
-                       c->d_counters};
+                       c->d_counters, gen_mode(c), c->em_dt};
     hipLaunchKernelGGL(k_emit_f64, dim3(grid), dim3(kEmitThreads), 0, st, a);
   }
   return hipGetLastError();

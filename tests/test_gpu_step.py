@@ -365,3 +365,81 @@ def test_sort_by_cell_stable_permutation():
     np.testing.assert_array_equal(got["id"], ids[order])
     np.testing.assert_array_equal(got["x"], x[order])
     np.testing.assert_array_equal(got["tau"], tau[order])
+
+
+def test_method1_substep_f64_parity(rad_table_I):
+    """The paper's method I with adaptive sub-steps (QED_FLAG_METHOD_I), float64,
+    three Fig. 1 ensembles at dt = 0.03 (W dt = 0.06 / 0.45 / 0.27, i.e. 1, 3 and
+    2 sub-steps): momenta, positions and photon lists against the oracle."""
+    torch, q = need_gpu()
+    ctx = q.Context(seed=5, kmax=4, flags=q.QED_FLAG_METHOD_I)
+    ctx.qed_build_tables(q.QED_FORMULA_I)
+    rad = mc.RadSampler(rad_table_I, "f64")
+    dt, steps = 0.03, 10
+    for k, e in enumerate(workloads.uniform_b_ensembles(2000, seed=5)):
+        n = e["id"].size
+        lep = q.Species(n, "f64")
+        ph = q.Species(n * 4 * steps + 16, "f64")
+        lep.load(e["x"], e["p"], np.zeros(n), e["id"])
+        nid = 10**6 * (k + 1)
+        ctx.qed_set_next_id(nid)
+        fld = q.Fields(q.QED_FIELD_UNIFORM, B=(0, 0, e["b0"]))
+        E = np.zeros((n, 3))
+        B = np.tile([0.0, 0.0, e["b0"]], (n, 1))
+        ox, op = e["x"].copy(), e["p"].copy()
+        ids_ph = []
+        for s in range(steps):
+            ctx.qed_gather_push(fld, lep, -1, dt, s)
+            ctx.qed_emit_photons(lep, ph, s)
+            r = mc.lepton_step_method1_full(ox, op, e["id"], E, B, q=-1.0, dt=dt, step=s, seed=5,
+                                            sampler=rad, next_id=nid)
+            ox, op, nid = r["x"], r["p"], r["next_id"]
+            ids_ph.append(r["photons"]["id"])
+            gam_ref = r["photons"]["gamma"]
+        st, rc = ctx.qed_get_status()
+        g = lep.to_numpy()
+        np.testing.assert_allclose(g["p"], op, rtol=1e-11, atol=1e-9)
+        gph = ph.to_numpy()
+        np.testing.assert_array_equal(gph["id"], np.concatenate(ids_ph))
+        assert ctx.qed_get_next_id() == nid
+
+
+def test_method1_dt_study():
+    """The paper's time-step study (Fig. 3 discussion) with method I, float32, no
+    recoil, chi ~ 1: Dt = 0.2/W and Dt = 6/W with adaptive sub-steps reproduce the
+    rate W; Dt = 6/W without sub-steps saturates at one event per step."""
+    torch, q = need_gpu()
+    from oracle.constants import RATE_UNIT
+    n, b0, g = 200000, 2000.0, 206.0
+    chi = g * math.sqrt(1 - 1 / g ** 2) * b0 / E_S
+    W = RATE_UNIT * tables.fine_row("I", chi, tables.RAD_M, need_rho=False).total / g
+    ens = workloads.uniform_b_ensembles(n, seed=8, triples=((b0, g),))[0]
+    fld = q.Fields(q.QED_FIELD_UNIFORM, B=(0, 0, b0))
+    for wdt, flags in ((0.2, 0), (6.0, 0), (6.0, q.QED_FLAG_NO_SUBSTEP)):
+        ctx = q.Context(seed=8, kmax=4 if wdt < 1 else 4, flags=q.QED_FLAG_METHOD_I | q.QED_FLAG_NO_RECOIL | flags)
+        ctx.qed_build_tables(q.QED_FORMULA_I)
+        lep = q.Species(n, "f32")
+        ph = q.Species(n * 4 * 3 + 16, "f32")
+        lep.load(ens["x"], ens["p"], ids=ens["id"])
+        ctx.qed_set_next_id(n)
+        dt = wdt / W
+        steps = 3
+        for s in range(steps):
+            ctx.qed_gather_push(fld, lep, -1, dt, s)
+            ctx.qed_emit_photons(lep, ph, s)
+        st, rc = ctx.qed_get_status()
+        rate = st["events"] / (n * steps * dt)
+        if flags:
+            assert st["events"] == n * steps            # one event per step: rate 1/Dt = W/6
+            assert abs(rate * dt - 1) < 1e-12
+        elif wdt < 1:
+            mean = n * steps * wdt
+            assert abs(st["events"] - mean) < 4 * math.sqrt(mean)
+        else:
+            # 30 sub-steps of p = 0.2, kmax = 4 caps the events: compare the capped
+            # binomial mean instead
+            from math import comb
+            N, pp = 30, wdt / 30
+            pk = [comb(N, k) * pp ** k * (1 - pp) ** (N - k) for k in range(4)]
+            mean1 = sum(k * pk[k] for k in range(4)) + 4 * (1 - sum(pk))
+            assert abs(st["events"] / (n * steps) - mean1) < 0.01 * mean1

@@ -222,3 +222,30 @@ def test_pair_step_yield_and_kinematics(pair_table):
     # electron takes xi or 1 - xi with equal probability
     frac = np.mean(out["electrons"]["xi"] > 0.5)
     assert abs(frac - 0.5) < 4 * math.sqrt(0.25 / k)
+
+
+def test_method1_substep_rates(rad):
+    """Method I with adaptive sub-steps (W Dt / N <= 0.2): the event rate matches
+    the rate integral for Dt = 0.2/W and Dt = 6/W; without sub-steps Dt = 6/W
+    saturates at one event per step (the paper's Fig. 3 discussion)."""
+    n, b0, g = 20000, 2000.0, 206.0
+    ens, E, B = _ensemble(n, b0, g, seed=6)
+    chi = spectra.chi_lepton(ens["p"][:1], E[:1], B[:1])[0]
+    W = RATE_UNIT * tables.fine_row("I", chi, tables.RAD_M, need_rho=False).total / g
+    for wdt, sub in ((0.2, True), (6.0, True), (6.0, False)):
+        dt = wdt / W
+        r = mc.lepton_step_method1_full(ens["x"], ens["p"], ens["id"], E, B, q=-1.0, dt=dt, step=0, seed=3,
+                                        sampler=rad, next_id=n, recoil=False, kmax=64)
+        if not sub:
+            r = mc.lepton_step_method1_full(ens["x"], ens["p"], ens["id"], E, B, q=-1.0, dt=dt, step=0,
+                                            seed=3, sampler=rad, next_id=n, recoil=False, kmax=64,
+                                            substep=False)
+        rate = r["n_events"] / (n * dt)
+        if sub:
+            # events per particle: Binomial(N, W dt / N) with N = ceil(W dt / 0.2)
+            N = int(np.ceil(wdt / 0.2 - 1e-12))
+            mean, var = n * wdt, n * N * (wdt / N) * (1 - wdt / N)
+            assert abs(r["n_events"] - mean) < 4 * math.sqrt(var)
+            assert np.all(r["N"] == N)
+        else:
+            assert r["n_events"] == n and rate < W / 5
