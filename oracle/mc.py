@@ -379,3 +379,42 @@ def compact(ids, *arrays):
         o[dest[alive]] = np.asarray(a)[alive]
         outs.append(o)
     return outs
+
+
+# ------------------------------------------------------------------ cascade
+def cascade_step(st, *, Eg, Bg, L, dt, step, seed, rad, pair, kmax=KMAX):
+    """One step of the emission and pair cascade, in the order the GPU runs it:
+    photons present at the start move, see the field at their new position and
+    may convert (pairs appended to both lepton species); then electrons (q = -1)
+    and positrons (q = +1) are pushed and emit (photons appended); finally the
+    converted photons are removed.  st: dict with species 'el', 'po', 'ph' (x, p,
+    tau, id) and 'next_id'; updated in place."""
+    ph = st["ph"]
+    if ph["id"].size:
+        g = np.sqrt(np.sum(ph["p"] * ph["p"], axis=-1))
+        kh = ph["p"] / np.where(g > 0, g, 1.0)[:, None]
+        xm = wrap(ph["x"] + kh * dt, L)
+        E, B = gather_tsc(Eg, Bg, L, xm)
+        r = photon_step(xm, ph["p"], ph["tau"], ph["id"], E, B, dt=dt, step=step, seed=seed,
+                        sampler=pair, next_id=st["next_id"], move=False)
+        st["next_id"] = r["next_id"]
+        ph.update(x=xm, tau=r["tau"], id=r["id"])
+        for name, new in (("el", r["electrons"]), ("po", r["positrons"])):
+            sp = st[name]
+            for k in ("x", "p", "tau", "id"):
+                sp[k] = np.concatenate([sp[k], new[k]])
+    for name, q in (("el", -1.0), ("po", 1.0)):
+        sp = st[name]
+        if sp["id"].size == 0:
+            continue
+        E, B = gather_tsc(Eg, Bg, L, sp["x"])
+        r = lepton_step(sp["x"], sp["p"], sp["tau"], sp["id"], E, B, q=q, dt=dt, step=step, seed=seed,
+                        sampler=rad, next_id=st["next_id"], L=L, kmax=kmax)
+        sp.update(x=r["x"], p=r["p"], tau=r["tau"])
+        st["next_id"] = r["next_id"]
+        new = r["photons"]
+        for k, v in (("x", new["x"]), ("p", new["k"]), ("tau", new["tau"]), ("id", new["id"])):
+            ph[k] = np.concatenate([ph[k], v])
+    keep = ph["id"] != DEAD_ID
+    for k in ("x", "p", "tau", "id"):
+        ph[k] = ph[k][keep]
