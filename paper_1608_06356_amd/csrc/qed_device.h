@@ -78,7 +78,7 @@ __device__ __forceinline__ double chi_lepton(double px, double py, double pz,
                                              double ex, double ey, double ez,
                                              double bx, double by, double bz) {
   const double p2 = px * px + py * py + pz * pz;
-  if (!(p2 > 0.0)) return sqrt(ex * ex + ey * ey + ez * ez) / kES;
+  if (p2 == 0.0) return sqrt(ex * ex + ey * ey + ez * ez) / kES;   // at rest: chi = |E| / E_S
   const double pa = sqrt(p2), g2 = 1.0 + p2, g = sqrt(g2);
   const double beta = pa / g;
   const double nx = px / pa, ny = py / pa, nz = pz / pa;

@@ -110,6 +110,11 @@ __device__ __forceinline__ void field_at(const FieldDev &f, int64_t i, R x, R y,
   }
 }
 
+template <typename R>
+__device__ __forceinline__ bool fields_finite(const R F[6]) {
+  return isfinite(F[0]) && isfinite(F[1]) && isfinite(F[2]) && isfinite(F[3]) && isfinite(F[4]) && isfinite(F[5]);
+}
+
 __device__ __forceinline__ void count_add(unsigned long long *c, int which, uint32_t v) {
   // one atomic per wave
   const uint32_t lane = threadIdx.x & 63;
@@ -214,12 +219,17 @@ __global__ __launch_bounds__(kGPThreads) void k_gather_push(GPArgs<R> a) {
   const int64_t i = base + threadIdx.x;
   bool flag = false;
   uint32_t nnan = 0, nrange = 0;
-  if (i < n) {
-    R x = X[i], y = Y[i], z = Z[i];
+  R F[6];
+  bool live = i < n;
+  R x = 0, y = 0, z = 0;
+  if (live) {
+    x = X[i]; y = Y[i]; z = Z[i];
+    field_at<R>(f, i, x, y, z, F);
+    if (!fields_finite<R>(F)) { live = false; nnan = 1; }   // skipped and counted
+  }
+  if (live) {
     R px = PX[i], py = PY[i], pz = PZ[i];
     const double tau = a.sp.tau[i];
-    R F[6];
-    field_at<R>(f, i, x, y, z, F);
     boris<R>(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5], a.q, a.dt);
     const R g = sqrt((R)1 + px * px + py * py + pz * pz);
     x += px / g * a.dt; y += py / g * a.dt; z += pz / g * a.dt;
@@ -543,7 +553,7 @@ __global__ __launch_bounds__(kGPThreads) void k_gather_push_mlp(GPArgs<float> a,
   float *PX = (float *)a.sp.px, *PY = (float *)a.sp.py, *PZ = (float *)a.sp.pz;
   FieldDev f = a.f;
   f.kind = FK;
-  uint32_t nfb = 0;
+  uint32_t nfb = 0, nnan_m = 0;
   for (int64_t lt = blockIdx.x / kXcds; lt < a.tpx; lt += per) {
     mlp::reload_barrier();
     const int64_t tile = (int64_t)xcd * a.tpx + lt;
@@ -554,10 +564,15 @@ __global__ __launch_bounds__(kGPThreads) void k_gather_push_mlp(GPArgs<float> a,
     float F[6] = {0, 0, 0, 0, 0, 0};
     float x = 0, y = 0, z = 0, px = 0, py = 0, pz = 0, g = 1;
     double tau = 0.0, chi = 1.0;
-    if (valid) {
-      x = X[i]; y = Y[i]; z = Z[i]; px = PX[i]; py = PY[i]; pz = PZ[i];
-      tau = a.sp.tau[i];
+    bool live = valid;
+    if (live) {
+      x = X[i]; y = Y[i]; z = Z[i];
       field_at<float>(f, i, x, y, z, F);
+      if (!fields_finite<float>(F)) { live = false; ++nnan_m; }
+    }
+    if (live) {
+      px = PX[i]; py = PY[i]; pz = PZ[i];
+      tau = a.sp.tau[i];
       boris<float>(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5], a.q, a.dt);
       g = sqrtf(1.f + px * px + py * py + pz * pz);
       x += px / g * a.dt; y += py / g * a.dt; z += pz / g * a.dt;
@@ -571,7 +586,7 @@ __global__ __launch_bounds__(kGPThreads) void k_gather_push_mlp(GPArgs<float> a,
     bool ok;
     const float lh = mlp_lnh(B, chi, ok);
     bool flag = false;
-    if (valid) {
+    if (live) {
       double W = 0.0;
       if (isfinite(chi) && chi > 0.0) {
         const float h = ok ? expf(lh) : h_rad<float>((float)chi, lnh_s);
@@ -597,6 +612,7 @@ __global__ __launch_bounds__(kGPThreads) void k_gather_push_mlp(GPArgs<float> a,
     if ((threadIdx.x & 63) == 0 && base + (threadIdx.x & ~63) < n) a.mask[(base + threadIdx.x) >> 6] = bits;
   }
   count_add(a.counters, cMlpFallbackRate, nfb);
+  count_add(a.counters, cNanChi, nnan_m);
 }
 
 constexpr int kEmitMlpThreads = 512;
@@ -827,7 +843,7 @@ __device__ void pair_tile(const PairArgs<R> &a, const Tab &tab, const R *L, uint
     }
     R F[6];
     field_at<R>(a.f, i, x, y, z, F);
-    const double chi = chi_photon(kx, ky, kz, F[0], F[1], F[2], F[3], F[4], F[5]);
+    const double chi = fields_finite<R>(F) ? chi_photon(kx, ky, kz, F[0], F[1], F[2], F[3], F[4], F[5]) : NAN;
     double W = 0.0;
     if (isfinite(chi)) {
       nrange += chi > kPairChiMax;
