@@ -66,6 +66,8 @@ extern "C" {
 
 #define QED_FORMULA_I  1        /* Eq. (1) */
 #define QED_FORMULA_II 2        /* Eq. (4) */
+#define QED_FORMULA_CLASSICAL 3 /* Eq. (5), the hbar -> 0 limit, with z = 2 xi / (3 chi),
+                                   restricted to xi < 1 like the quantum spectra */
 
 /* field kinds */
 #define QED_FIELD_UNIFORM      0   /* E, B constant (qed_fields_t.E/B)             */
@@ -168,7 +170,7 @@ QED_API int qed_get_next_id(qed_ctx_t ctx, uint64_t *next_id, void *stream);   /
 
 /* Builds all tables on the device in float64 by quadrature of the paper's spectra:
    the photon rate h(chi) and inverse CDF (Eq. 1 if formula == QED_FORMULA_I,
-   Eq. 4 if QED_FORMULA_II; text after Eq. 7) on 256 chi nodes over [1e-3, 1e2],
+   Eq. 4 if QED_FORMULA_II, Eq. 5 if QED_FORMULA_CLASSICAL; text after Eq. 7) on 256 chi nodes over [1e-3, 1e2],
    256 quantile nodes each; the pair rate (Eq. 6) on 512 chi nodes over [1e-2, 1e2]
    and the half-spectrum inverse CDF on 256 x 256 nodes.  Also writes the float32 /
    16-bit copies the single-precision kernels stage in LDS. */

@@ -107,6 +107,8 @@ def _density(kind, s, chi):
         S = spectra.formula_II_logit(s, chi)
     elif kind == "pair":
         S = spectra.pair_logit(s, chi)
+    elif kind == "classical":
+        S = spectra.classical(xi, chi)
     else:
         raise ValueError(kind)
     return S * xi * om
@@ -197,7 +199,9 @@ class PairTable:
 
 
 def build_rad_table(kind="I", rows=None):
-    """Photon table for formula I ("I") or II ("II").  rows: optional subset."""
+    """Photon table for formula I ("I"), II ("II") or the classical limit
+    ("classical", Eq. 5 restricted to xi < 1, whose small-xi tail is the same as
+    Eq. 1's).  rows: optional subset."""
     chi = chi_nodes(RAD_NCHI, RAD_CHI_MIN, RAD_CHI_MAX)
     t = t_nodes(RAD_NU, RAD_U_LO, RAD_U_HI)
     u = 1.0 / (1.0 + np.exp(-t))

@@ -14,7 +14,7 @@ LIB_PATH = os.environ.get("QED_LIB_PATH") or os.path.join(HERE, "libqedmi.so")
 
 QED_OK, QED_ERR_ARG, QED_ERR_HIP, QED_ERR_CAPACITY, QED_ERR_RANGE, QED_ERR_STATE = 0, -1, -2, -3, -4, -5
 QED_F32, QED_F64 = 0, 1
-QED_FORMULA_I, QED_FORMULA_II = 1, 2
+QED_FORMULA_I, QED_FORMULA_II, QED_FORMULA_CLASSICAL = 1, 2, 3
 QED_FIELD_UNIFORM, QED_FIELD_GRID, QED_FIELD_PER_PARTICLE = 0, 1, 2
 QED_FLAG_NO_RECOIL, QED_FLAG_STATIC_PHOTONS, QED_FLAG_TRACK_DEAD, QED_FLAG_SURROGATE = 1, 2, 4, 8
 QED_FLAG_METHOD_I, QED_FLAG_NO_SUBSTEP = 16, 32

@@ -156,8 +156,8 @@ int qed_get_next_id(qed_ctx_t c, uint64_t *v, void *st) {
 
 int qed_build_tables(qed_ctx_t c, int formula, void *st) {
   if (!c) return QED_ERR_ARG;
-  if (formula != QED_FORMULA_I && formula != QED_FORMULA_II)
-    return fail(c, QED_ERR_ARG, "formula must be QED_FORMULA_I or QED_FORMULA_II");
+  if (formula != QED_FORMULA_I && formula != QED_FORMULA_II && formula != QED_FORMULA_CLASSICAL)
+    return fail(c, QED_ERR_ARG, "formula must be QED_FORMULA_I, QED_FORMULA_II or QED_FORMULA_CLASSICAL");
   using namespace qed;
   hipError_t e = hipSuccess;
   if (!c->rad_lnh64) {

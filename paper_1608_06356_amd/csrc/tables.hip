@@ -19,7 +19,7 @@ namespace {
 
 constexpr double kInvSqrt3Pi = 0.18377629847393068;   // 1 / (sqrt3 pi)
 constexpr double kGamma23 = 1.3541179394264004;        // Gamma(2/3)
-enum Kind { kFormulaI = 1, kFormulaII = 2, kPair = 3 };
+enum Kind { kFormulaI = 1, kFormulaII = 2, kPair = 3, kClassical = 4 };
 constexpr int kPts = 4 * 1024 + 1;                     // 3M Gauss points + M+1 nodes
 
 struct Job {
@@ -55,6 +55,18 @@ __device__ void bessel_k13_k23(double x, double &k13, double &k23) {
   }
   k13 = h * a;
   k23 = h * b;
+}
+
+// int_x^inf K_{5/3}.
+__device__ double bessel_i53(double x) {
+  const double h = fmin(0.1, 0.35 / sqrt(x));
+  const int n = (int)ceil(acosh(1.0 + 40.0 / x) / h);
+  double a = 0.5 * exp(-x);
+  for (int j = 1; j <= n; ++j) {
+    const double t = j * h, ch = cosh(t);
+    a += exp(-x * ch) * cosh((5.0 / 3.0) * t) / ch;
+  }
+  return h * a;
 }
 
 // J_1..J_3 of Eq. (4) after u = sigma cosh^3(theta): trapezoid in theta with step
@@ -93,6 +105,9 @@ __device__ double density(int kind, double s, double chi) {
     j_integrals(sigma, j1, j2, j3);
     const double f1 = 1.0 + 1.0 / (om * om), f2 = 2.0 / om, f3 = (xi / om) * (xi / om);
     S = xi / (3.0 * kPi * kPi * chi) * (f1 * j1 + f2 * j2 + f3 * j3);
+  } else if (kind == kClassical) {                              // Eq. (5), z = 2 xi / (3 chi)
+    const double z = (2.0 / 3.0) * xi / chi;
+    S = 1.7320508075688772 * chi / (2.0 * kPi * xi) * z * bessel_i53(z);
   } else {                                                      // Eq. (6), "+" sign
     const double d = 2.0 / (3.0 * xi * om * chi);
     double k23, i13;
@@ -241,7 +256,7 @@ double chi_node(int i, int n, double lo, double hi) {
 }  // namespace
 
 hipError_t launch_build_tables(qed_ctx *c, int formula, hipStream_t st) {
-  const int kind_rad = formula == QED_FORMULA_II ? kFormulaII : kFormulaI;
+  const int kind_rad = formula == QED_FORMULA_II ? kFormulaII : (formula == QED_FORMULA_CLASSICAL ? kClassical : kFormulaI);
   const int njobs = kRadNChi + kPairNRate + kPairNCdf;
   Job *h = new Job[njobs];
   int n = 0;

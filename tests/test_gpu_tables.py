@@ -55,3 +55,15 @@ def test_formula_II_table(gpu_tables, rad_table_I):
         assert np.abs(gpu_tables["II_S"][i] - ref.s[i]).max() < 1e-8
     assert np.abs(gpu_tables["II_lnh"] - rad_table_I.ln_h).max() < 1e-10
     assert np.abs(gpu_tables["II_S"] - rad_table_I.s).max() < 1e-7
+
+
+def test_classical_table_vs_oracle():
+    """QED_FORMULA_CLASSICAL (Eq. 5): GPU rows against the oracle's quadrature."""
+    torch, q = need_gpu()
+    ctx = q.Context()
+    ctx.qed_build_tables(q.QED_FORMULA_CLASSICAL)
+    lnh, S = ctx.qed_get_table(0), ctx.qed_get_table(1)
+    ref = tables.build_rad_table("classical", rows=[0, 90, 200, 255])
+    for i in (0, 90, 200, 255):
+        assert abs(lnh[i] - ref.ln_h[i]) < 1e-11
+        assert np.abs(S[i] - ref.s[i]).max() < 1e-8

@@ -312,3 +312,27 @@ def test_uniform_mapping_range():
     assert u[0] == 2.0 ** -24 and u[1] == 2.0 ** -24 and u[2] == 3 * 2.0 ** -24
     assert u[3] == 1 - 2.0 ** -24
     assert np.all(u.astype(np.float32).astype(np.float64) == u)
+
+
+def test_classical_tail_matches_formula_I_tail():
+    """Eq. 5 and Eq. 1 share the xi -> 0 law S ~ Gamma(2/3) 3^(1/6) / pi (chi/xi)^(2/3),
+    so the infrared tail of the tables applies to the classical spectrum too."""
+    for chi in (0.01, 1.0, 30.0):
+        xi = np.array([1e-14 * chi])
+        law = sp.gamma(2 / 3) * 3 ** (1 / 6) / np.pi * (chi / xi) ** (2 / 3)
+        assert abs(spectra.classical(xi, chi)[0] / law - 1) < 1e-6
+        assert abs(spectra.formula_I(xi, chi)[0] / law - 1) < 1e-6
+
+
+def test_classical_overestimates_high_energy():
+    """The paper's Fig. 1 finding: at the Fig. 1 triples the classical formula
+    gives a higher rate dW/dxi than formula I at high photon energies (and a
+    larger tail beyond xi = 1/2)."""
+    for chi in (0.1, 1.0, 10.0):
+        xi = np.array([0.5, 0.8])
+        assert np.all(spectra.classical(xi, chi) > spectra.formula_I(xi, chi))
+        rI = tables.fine_row("I", chi, tables.RAD_M, need_rho=False)
+        rC = tables.fine_row("classical", chi, tables.RAD_M, need_rho=False)
+        tailI = rI.total - np.interp(0.0, rI.s, rI.F)
+        tailC = rC.total - np.interp(0.0, rC.s, rC.F)
+        assert tailC > tailI
