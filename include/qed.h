@@ -176,6 +176,17 @@ QED_API int qed_get_next_id(qed_ctx_t ctx, uint64_t *next_id, void *stream);   /
    16-bit copies the single-precision kernels stage in LDS. */
 QED_API int qed_build_tables(qed_ctx_t ctx, int formula, void *stream);
 
+/* Same as qed_build_tables with the upper ends of the chi ranges chosen by the
+   caller: photon tables on 256 log nodes over [1e-3, rad_chi_max], pair tables
+   over [1e-2, pair_chi_max] (same node counts).  Needed where chi exceeds 1e2, as
+   for the single electron of chi_0 ~ 4e4 in the cascade of Fig. 5; the node
+   spacing grows with the range.  Requires 1 <= rad_chi_max <= 1e6 and
+   10 <= pair_chi_max <= 1e6 (QED_ERR_ARG otherwise).  The surrogate nets cover
+   chi in [1e-3, 1e2] only: with any other range the surrogate entry points and
+   QED_FLAG_SURROGATE return QED_ERR_STATE. */
+QED_API int qed_build_tables_range(qed_ctx_t ctx, int formula, double rad_chi_max, double pair_chi_max,
+                                   void *stream);
+
 /* Copies a table to host memory (synchronous).  which: 0 rad ln h [256] f64,
    1 rad logit-xi quantiles [256*256] f64, 2 pair ln h + 8/(3 chi) [512] f64,
    3 pair quantiles [256*256] f64, 4 rad 16-bit codes [256*256] u16,

@@ -142,13 +142,13 @@ class RadSampler:
             self.ln_h = tab.ln_h.astype(np.float32).astype(np.float64)
         else:
             raise ValueError(storage)
-        self._tab_view = tables.RadTable(tab.kind, tab.chi, self.ln_h, tab.t, self.S)
+        self._tab_view = tables.RadTable(tab.kind, tab.chi, self.ln_h, tab.t, self.S, tab.chi_max)
 
     def rate(self, chi, gamma):
         return tables.rate_rad(self._tab_view, chi, gamma)
 
     def sample(self, chi, u_xi, u_row):
-        return tables.sample_rad(self.S, self.t, chi, u_xi, u_row)
+        return tables.sample_rad(self.S, self.t, chi, u_xi, u_row, self.tab.chi_max)
 
 
 def lepton_step(x, p, tau, ids, E, B, *, q, dt, step, seed, sampler, next_id,
@@ -320,13 +320,13 @@ class PairSampler:
             self.L = tab.L.astype(np.float32).astype(np.float64)
         else:
             raise ValueError(storage)
-        self._tab_view = tables.PairTable(tab.chi_rate, self.L, tab.chi_cdf, tab.t, self.S)
+        self._tab_view = tables.PairTable(tab.chi_rate, self.L, tab.chi_cdf, tab.t, self.S, tab.chi_max)
 
     def rate(self, chi, gamma_ph):
         return tables.rate_pair(self._tab_view, chi, gamma_ph)
 
     def sample_half(self, chi, u_xi, u_row):
-        return tables.sample_pair_half(self.S, self.t, chi, u_xi, u_row)
+        return tables.sample_pair_half(self.S, self.t, chi, u_xi, u_row, self.tab.chi_max)
 
 
 def photon_step(x, k, tau, ids, E, B, *, dt, step, seed, sampler, next_id,
@@ -382,19 +382,30 @@ def compact(ids, *arrays):
 
 
 # ------------------------------------------------------------------ cascade
-def cascade_step(st, *, Eg, Bg, L, dt, step, seed, rad, pair, kmax=KMAX):
+def cascade_step(st, *, Eg=None, Bg=None, L=None, dt, step, seed, rad, pair, kmax=KMAX,
+                 E0=None, B0=None):
     """One step of the emission and pair cascade, in the order the GPU runs it:
     photons present at the start move, see the field at their new position and
     may convert (pairs appended to both lepton species); then electrons (q = -1)
     and positrons (q = +1) are pushed and emit (photons appended); finally the
     converted photons are removed.  st: dict with species 'el', 'po', 'ph' (x, p,
-    tau, id) and 'next_id'; updated in place."""
+    tau, id) and 'next_id'; updated in place.  Fields: the periodic grid Eg, Bg
+    of side L, or (Eg None) the uniform E0, B0 in unbounded space."""
+    if Eg is None:
+        E0, B0 = np.asarray(E0, np.float64), np.asarray(B0, np.float64)
+
+        def fields(x):
+            return np.broadcast_to(E0, x.shape).copy(), np.broadcast_to(B0, x.shape).copy()
+        L = None
+    else:
+        def fields(x):
+            return gather_tsc(Eg, Bg, L, x)
     ph = st["ph"]
     if ph["id"].size:
         g = np.sqrt(np.sum(ph["p"] * ph["p"], axis=-1))
         kh = ph["p"] / np.where(g > 0, g, 1.0)[:, None]
         xm = wrap(ph["x"] + kh * dt, L)
-        E, B = gather_tsc(Eg, Bg, L, xm)
+        E, B = fields(xm)
         r = photon_step(xm, ph["p"], ph["tau"], ph["id"], E, B, dt=dt, step=step, seed=seed,
                         sampler=pair, next_id=st["next_id"], move=False)
         st["next_id"] = r["next_id"]
@@ -407,7 +418,7 @@ def cascade_step(st, *, Eg, Bg, L, dt, step, seed, rad, pair, kmax=KMAX):
         sp = st[name]
         if sp["id"].size == 0:
             continue
-        E, B = gather_tsc(Eg, Bg, L, sp["x"])
+        E, B = fields(sp["x"])
         r = lepton_step(sp["x"], sp["p"], sp["tau"], sp["id"], E, B, q=q, dt=dt, step=step, seed=seed,
                         sampler=rad, next_id=st["next_id"], L=L, kmax=kmax)
         sp.update(x=r["x"], p=r["p"], tau=r["tau"])

@@ -187,6 +187,7 @@ class RadTable:
     ln_h: np.ndarray     # (256,)
     t: np.ndarray        # (256,) quantile nodes in logit(u)
     s: np.ndarray        # (256, 256) logit(xi) at the quantile nodes
+    chi_max: float = RAD_CHI_MAX   # upper end of the chi nodes
 
 
 @dataclass
@@ -196,13 +197,15 @@ class PairTable:
     chi_cdf: np.ndarray    # (256,)
     t: np.ndarray          # (256,)
     s: np.ndarray          # (256, 256) logit(xi) of the half spectrum
+    chi_max: float = PAIR_CHI_MAX  # upper end of both chi grids
 
 
-def build_rad_table(kind="I", rows=None):
+def build_rad_table(kind="I", rows=None, chi_max=RAD_CHI_MAX):
     """Photon table for formula I ("I"), II ("II") or the classical limit
     ("classical", Eq. 5 restricted to xi < 1, whose small-xi tail is the same as
-    Eq. 1's).  rows: optional subset."""
-    chi = chi_nodes(RAD_NCHI, RAD_CHI_MIN, RAD_CHI_MAX)
+    Eq. 1's).  rows: optional subset.  chi_max: upper end of the chi nodes
+    (1e2 by default; larger for chi_0 ~ 4e4 as in Fig. 5)."""
+    chi = chi_nodes(RAD_NCHI, RAD_CHI_MIN, chi_max)
     t = t_nodes(RAD_NU, RAD_U_LO, RAD_U_HI)
     u = 1.0 / (1.0 + np.exp(-t))
     idx = range(RAD_NCHI) if rows is None else rows
@@ -212,12 +215,12 @@ def build_rad_table(kind="I", rows=None):
         row = fine_row(kind, chi[i], RAD_M)
         ln_h[i] = math.log(row.total)
         s[i] = [quantile(row, uk, ir_tail=True) for uk in u]
-    return RadTable(kind=kind, chi=chi, ln_h=ln_h, t=t, s=s)
+    return RadTable(kind=kind, chi=chi, ln_h=ln_h, t=t, s=s, chi_max=chi_max)
 
 
-def build_pair_table(rate_rows=None, cdf_rows=None):
-    chi_r = chi_nodes(PAIR_NRATE, PAIR_CHI_MIN, PAIR_CHI_MAX)
-    chi_c = chi_nodes(PAIR_NCDF, PAIR_CHI_MIN, PAIR_CHI_MAX)
+def build_pair_table(rate_rows=None, cdf_rows=None, chi_max=PAIR_CHI_MAX):
+    chi_r = chi_nodes(PAIR_NRATE, PAIR_CHI_MIN, chi_max)
+    chi_c = chi_nodes(PAIR_NCDF, PAIR_CHI_MIN, chi_max)
     t = t_nodes(PAIR_NU, PAIR_U_LO, PAIR_U_HI)
     u = 1.0 / (1.0 + np.exp(-t))
     L = np.full(PAIR_NRATE, np.nan)
@@ -228,7 +231,7 @@ def build_pair_table(rate_rows=None, cdf_rows=None):
     for i in (range(PAIR_NCDF) if cdf_rows is None else cdf_rows):
         row = fine_row("pair", chi_c[i], PAIR_M)
         s[i] = [quantile(row, uk, ir_tail=False) for uk in u]
-    return PairTable(chi_rate=chi_r, L=L, chi_cdf=chi_c, t=t, s=s)
+    return PairTable(chi_rate=chi_r, L=L, chi_cdf=chi_c, t=t, s=s, chi_max=chi_max)
 
 
 # ---------------------------------------------------------- 16-bit storage
@@ -259,13 +262,14 @@ def h_rad(tab: RadTable, chi):
     out = np.zeros_like(chi)
     pos = chi > 0
     c = np.where(pos, chi, 1.0)
-    x = _grid_pos(c, RAD_NCHI, RAD_CHI_MIN, RAD_CHI_MAX)
+    hi = tab.chi_max
+    x = _grid_pos(c, RAD_NCHI, RAD_CHI_MIN, hi)
     i = np.clip(np.floor(x), 0, RAD_NCHI - 2).astype(np.int64)
     f = x - i
     inside = np.exp((1.0 - f) * tab.ln_h[i] + f * tab.ln_h[i + 1])
     below = H_SMALL_C1 * c * (1.0 - H_SMALL_C2 * c)
-    above = np.exp(tab.ln_h[-1]) * (c / RAD_CHI_MAX) ** (2.0 / 3.0)
-    h = np.where(c < RAD_CHI_MIN, below, np.where(c > RAD_CHI_MAX, above, inside))
+    above = np.exp(tab.ln_h[-1]) * (c / hi) ** (2.0 / 3.0)
+    h = np.where(c < RAD_CHI_MIN, below, np.where(c > hi, above, inside))
     out[pos] = h[pos]
     return out
 
@@ -278,12 +282,13 @@ def rate_rad(tab, chi, gamma):
 def h_pair(tab: PairTable, chi):
     chi = np.asarray(chi, dtype=np.float64)
     c = np.where(chi > 0, chi, 1.0)
-    x = _grid_pos(c, PAIR_NRATE, PAIR_CHI_MIN, PAIR_CHI_MAX)
+    hi = tab.chi_max
+    x = _grid_pos(c, PAIR_NRATE, PAIR_CHI_MIN, hi)
     i = np.clip(np.floor(x), 0, PAIR_NRATE - 2).astype(np.int64)
     f = x - i
     inside = np.exp((1.0 - f) * tab.L[i] + f * tab.L[i + 1] - 8.0 / (3.0 * c))
-    above = np.exp(tab.L[-1] - 8.0 / (3.0 * PAIR_CHI_MAX)) * (c / PAIR_CHI_MAX) ** (2.0 / 3.0)
-    h = np.where(c > PAIR_CHI_MAX, above, inside)
+    above = np.exp(tab.L[-1] - 8.0 / (3.0 * hi)) * (c / hi) ** (2.0 / 3.0)
+    h = np.where(c > hi, above, inside)
     return np.where(chi < PAIR_CHI_MIN, 0.0, h)
 
 
@@ -325,12 +330,12 @@ def _interp_s(S, row, u, t_nodes_, tail_cube, u_lo):
     return s
 
 
-def sample_rad(S, t_nodes_, chi, u_xi, u_row):
+def sample_rad(S, t_nodes_, chi, u_xi, u_row, chi_max=RAD_CHI_MAX):
     """xi and 1-xi from the photon inverse CDF S (256 x 256 logit values).
     Below the table's chi range the row-0 sample is scaled by chi / chi_min
     (the classical spectrum depends on xi / chi); above it, the last row."""
     chi = np.asarray(chi, dtype=np.float64)
-    row = _row_pick(chi, u_row, RAD_NCHI, RAD_CHI_MIN, RAD_CHI_MAX)
+    row = _row_pick(chi, u_row, RAD_NCHI, RAD_CHI_MIN, chi_max)
     s = _interp_s(S, row, np.asarray(u_xi, np.float64), t_nodes_, True, RAD_U_LO)
     xi = 1.0 / (1.0 + np.exp(-s))
     om = 1.0 / (1.0 + np.exp(s))
@@ -340,9 +345,9 @@ def sample_rad(S, t_nodes_, chi, u_xi, u_row):
     return np.where(below, xi_b, xi), np.where(below, 1.0 - xi_b, om)
 
 
-def sample_pair_half(S, t_nodes_, chi, u_xi, u_row):
+def sample_pair_half(S, t_nodes_, chi, u_xi, u_row, chi_max=PAIR_CHI_MAX):
     """xi in (0, 1/2] from the half-spectrum inverse CDF (chi >= 1e-2)."""
     chi = np.asarray(chi, dtype=np.float64)
-    row = _row_pick(chi, u_row, PAIR_NCDF, PAIR_CHI_MIN, PAIR_CHI_MAX)
+    row = _row_pick(chi, u_row, PAIR_NCDF, PAIR_CHI_MIN, chi_max)
     s = _interp_s(S, row, np.asarray(u_xi, np.float64), t_nodes_, False, PAIR_U_LO)
     return 1.0 / (1.0 + np.exp(-s)), 1.0 / (1.0 + np.exp(s))

@@ -21,7 +21,7 @@ QED_FLAG_METHOD_I, QED_FLAG_NO_SUBSTEP = 16, 32
 QED_SAMPLER_MLP = 2
 DEAD_ID = 0xFFFFFFFFFFFFFFFF
 EXPORTS = ["qed_create", "qed_destroy", "qed_last_error", "qed_reserve", "qed_set_next_id",
-           "qed_get_next_id", "qed_build_tables", "qed_get_table", "qed_init_optical_depth",
+           "qed_get_next_id", "qed_build_tables", "qed_build_tables_range", "qed_get_table", "qed_init_optical_depth",
            "qed_fill_standing_wave", "qed_gather_push", "qed_emit_photons", "qed_create_pairs",
            "qed_compact", "qed_sample", "qed_get_status", "qed_surrogate_params",
            "qed_surrogate_train", "qed_surrogate_io", "qed_surrogate_forward", "qed_surrogate_grad",
@@ -83,6 +83,7 @@ def lib():
             "qed_set_next_id": (ctypes.c_int, [vp, u64, vp]),
             "qed_get_next_id": (ctypes.c_int, [vp, ctypes.POINTER(u64), vp]),
             "qed_build_tables": (ctypes.c_int, [vp, ctypes.c_int, vp]),
+            "qed_build_tables_range": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, vp]),
             "qed_get_table": (ctypes.c_int, [vp, ctypes.c_int, vp, ctypes.c_size_t]),
             "qed_init_optical_depth": (ctypes.c_int, [vp, ctypes.POINTER(qed_species_t), i64, vp]),
             "qed_fill_standing_wave": (ctypes.c_int, [vp, vp, ctypes.c_int, ctypes.c_double,
@@ -170,6 +171,10 @@ class Context:
 
     def qed_build_tables(self, formula=QED_FORMULA_I, stream=None):
         return self._check(lib().qed_build_tables(self.h, formula, _stream(stream)))
+
+    def qed_build_tables_range(self, formula, rad_chi_max, pair_chi_max, stream=None):
+        return self._check(lib().qed_build_tables_range(self.h, formula, float(rad_chi_max), float(pair_chi_max),
+                                                        _stream(stream)))
 
     def qed_get_table(self, which):
         import numpy as np

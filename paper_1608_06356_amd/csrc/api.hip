@@ -154,11 +154,24 @@ int qed_get_next_id(qed_ctx_t c, uint64_t *v, void *st) {
   return e == hipSuccess ? QED_OK : hip_fail(c, e, "get_next_id");
 }
 
+// The surrogate nets cover chi in [1e-3, 1e2] and read the tables at the
+// default node positions.
+static bool default_range(const qed_ctx *c) {
+  return c->range.rad_hi == qed::kRadChiMax && c->range.pair_hi == qed::kPairChiMax;
+}
+
 int qed_build_tables(qed_ctx_t c, int formula, void *st) {
+  return qed_build_tables_range(c, formula, qed::kRadChiMax, qed::kPairChiMax, st);
+}
+
+int qed_build_tables_range(qed_ctx_t c, int formula, double rad_chi_max, double pair_chi_max, void *st) {
   if (!c) return QED_ERR_ARG;
   if (formula != QED_FORMULA_I && formula != QED_FORMULA_II && formula != QED_FORMULA_CLASSICAL)
     return fail(c, QED_ERR_ARG, "formula must be QED_FORMULA_I, QED_FORMULA_II or QED_FORMULA_CLASSICAL");
   using namespace qed;
+  if (!(rad_chi_max >= kRadChiMaxLo && rad_chi_max <= kChiMaxHi) ||
+      !(pair_chi_max >= kPairChiMaxLo && pair_chi_max <= kChiMaxHi))
+    return fail(c, QED_ERR_ARG, "build_tables_range: need 1 <= rad_chi_max <= 1e6 and 10 <= pair_chi_max <= 1e6");
   hipError_t e = hipSuccess;
   if (!c->rad_lnh64) {
     const size_t work = (size_t)(kRadNChi + kPairNRate + kPairNCdf) * (4 * 1024 + 1);
@@ -172,9 +185,11 @@ int qed_build_tables(qed_ctx_t c, int formula, void *st) {
     c->tab_work_elems = work;
   }
   c->tables_ready = false;
-  if ((e = launch_build_tables(c, formula, S(st))) != hipSuccess) return hip_fail(c, e, "build_tables");
+  const TabRange rg{rad_chi_max, pair_chi_max};
+  if ((e = launch_build_tables(c, formula, rg, S(st))) != hipSuccess) return hip_fail(c, e, "build_tables");
   c->tables_ready = true;
   c->formula = formula;
+  c->range = rg;
   return QED_OK;
 }
 
@@ -252,6 +267,8 @@ int qed_gather_push(qed_ctx_t c, const qed_fields_t *f, qed_species_t *lep, int 
     return fail(c, QED_ERR_STATE, "QED_FLAG_SURROGATE: surrogate not trained or loaded");
   if ((c->params.flags & QED_FLAG_SURROGATE) && (c->params.flags & QED_FLAG_METHOD_I))
     return fail(c, QED_ERR_ARG, "QED_FLAG_METHOD_I is not available with QED_FLAG_SURROGATE");
+  if ((c->params.flags & QED_FLAG_SURROGATE) && lep->dtype == QED_F32 && !default_range(c))
+    return fail(c, QED_ERR_STATE, "QED_FLAG_SURROGATE needs tables of the default chi range");
   if (step < 0 && step != QED_STEP_DEVICE) return fail(c, QED_ERR_ARG, "step must be >= 0 or QED_STEP_DEVICE");
   hipError_t e = qed::launch_gather_push(c, f, lep, charge, dt, step, S(st));
   if (e != hipSuccess) return hip_fail(c, e, "gather_push");
@@ -326,6 +343,8 @@ int qed_sample(qed_ctx_t c, const double *chi, const double *gamma, const uint64
   if (!c->tables_ready) return fail(c, QED_ERR_STATE, "tables not built");
   if (precision == QED_SAMPLER_MLP && !c->mlp_ready)
     return fail(c, QED_ERR_STATE, "surrogate not trained or loaded");
+  if (precision == QED_SAMPLER_MLP && !default_range(c))
+    return fail(c, QED_ERR_STATE, "surrogate sampling needs tables of the default chi range");
   if (n == 0) return QED_OK;
   hipError_t e = precision == QED_SAMPLER_MLP
                      ? qed::launch_mlp_sample(c, chi, gamma, id, n, step, lnw, xi, lnwp, 2e-3f, S(st))
@@ -350,6 +369,7 @@ int qed_surrogate_params(int net) { return (net == 0 || net == 1) ? qed::mlp_par
 int qed_surrogate_train(qed_ctx_t c, const qed_train_spec_t *spec, void *st) {
   if (!c || !spec) return QED_ERR_ARG;
   if (!c->tables_ready) return fail(c, QED_ERR_STATE, "tables not built");
+  if (!default_range(c)) return fail(c, QED_ERR_STATE, "surrogate training needs tables of the default chi range");
   if (spec->steps < 0 || spec->batch < 16 || spec->batch > (1 << 22) || !(spec->lr > 0))
     return fail(c, QED_ERR_ARG, "train: need steps >= 0, 16 <= batch <= 2^22, lr > 0");
   int r = mlp_alloc(c);

@@ -5,6 +5,7 @@
 #include <string>
 
 #include "../../include/qed.h"
+#include "lookup.h"
 
 struct qed_ctx {
   int device = 0;
@@ -14,6 +15,7 @@ struct qed_ctx {
   // tables (library-owned device memory)
   bool tables_ready = false;
   int formula = 0;
+  qed::TabRange range;            // chi range of the built tables
   double *rad_lnh64 = nullptr, *rad_S64 = nullptr;       // [256], [256*256]
   float *rad_lnh32 = nullptr, *rad_s0sc = nullptr;       // [256], [2*256]
   uint16_t *rad_q16 = nullptr;                           // [256*256]
@@ -66,7 +68,7 @@ struct qed_ctx {
 };
 
 namespace qed {
-hipError_t launch_build_tables(qed_ctx *c, int formula, hipStream_t s);
+hipError_t launch_build_tables(qed_ctx *c, int formula, TabRange rg, hipStream_t s);
 int mlp_params(int net);
 hipError_t launch_sort_by_cell(qed_ctx *c, const qed_fields_t *f, const qed_species_t *s, qed_species_t *d,
                                hipStream_t st);

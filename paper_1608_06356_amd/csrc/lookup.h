@@ -6,6 +6,12 @@
 
 namespace qed {
 
+// Upper ends of the chi ranges of the tables (the lower ends are fixed at 1e-3
+// for photon emission and 1e-2 for pairs); chosen when the tables are built.
+struct TabRange {
+  double rad_hi = kRadChiMax, pair_hi = kPairChiMax;
+};
+
 // ln chi grid positions: x = (ln chi - ln chi_min) / step
 template <typename R> struct Grid {
   static __device__ __forceinline__ R pos(R lnchi, double lo, double hi, int n) {
@@ -17,12 +23,12 @@ template <typename R> struct Grid {
 // Photon rate h(chi): linear in (ln chi, ln h) between nodes; small-chi expansion
 // c1 chi (1 - c2 chi) below, chi^(2/3) growth above; 0 for chi <= 0.
 template <typename R>
-__device__ __forceinline__ R h_rad(R chi, const R *lnh) {
+__device__ __forceinline__ R h_rad(R chi, const R *lnh, const TabRange &rg) {
   if (!(chi > (R)0)) return (R)0;
   if (chi < (R)kRadChiMin) return (R)kHc1 * chi * ((R)1 - (R)kHc2 * chi);
-  if (chi > (R)kRadChiMax)
-    return exp(lnh[kRadNChi - 1] + (R)(2.0 / 3.0) * log(chi / (R)kRadChiMax));
-  const R x = Grid<R>::pos(log(chi), kRadChiMin, kRadChiMax, kRadNChi);
+  if (chi > (R)rg.rad_hi)
+    return exp(lnh[kRadNChi - 1] + (R)(2.0 / 3.0) * log(chi / (R)rg.rad_hi));
+  const R x = Grid<R>::pos(log(chi), kRadChiMin, rg.rad_hi, kRadNChi);
   int i = (int)floor(x);
   i = i < 0 ? 0 : (i > kRadNChi - 2 ? kRadNChi - 2 : i);
   const R f = x - (R)i;
@@ -31,11 +37,11 @@ __device__ __forceinline__ R h_rad(R chi, const R *lnh) {
 
 // Pair rate h_pair(chi) from L = ln h_pair + 8/(3 chi); 0 below chi = 1e-2.
 template <typename R>
-__device__ __forceinline__ R h_pair(R chi, const R *L) {
+__device__ __forceinline__ R h_pair(R chi, const R *L, const TabRange &rg) {
   if (!(chi >= (R)kPairChiMin)) return (R)0;
-  if (chi > (R)kPairChiMax)
-    return exp(L[kPairNRate - 1] - (R)(8.0 / (3.0 * kPairChiMax)) + (R)(2.0 / 3.0) * log(chi / (R)kPairChiMax));
-  const R x = Grid<R>::pos(log(chi), kPairChiMin, kPairChiMax, kPairNRate);
+  if (chi > (R)rg.pair_hi)
+    return exp(L[kPairNRate - 1] - (R)(8.0 / (3.0 * rg.pair_hi)) + (R)(2.0 / 3.0) * log(chi / (R)rg.pair_hi));
+  const R x = Grid<R>::pos(log(chi), kPairChiMin, rg.pair_hi, kPairNRate);
   int i = (int)floor(x);
   i = i < 0 ? 0 : (i > kPairNRate - 2 ? kPairNRate - 2 : i);
   const R f = x - (R)i;
@@ -91,9 +97,9 @@ __device__ __forceinline__ bool interp_s(const Tab &tab, int row, R u, double ul
 // classical spectrum depends on xi/chi); above it the last row is used; below
 // u = 1e-4 the infrared law xi ~ u^3 continues the first node.
 template <typename R, typename Tab>
-__device__ __forceinline__ void sample_rad(const Tab &tab, R chi, R u, R u_row, R &xi, R &om) {
+__device__ __forceinline__ void sample_rad(const Tab &tab, R chi, R u, R u_row, R &xi, R &om, const TabRange &rg) {
   const R lnchi = log(chi);
-  const int row = pick_row<R>(lnchi, u_row, kRadChiMin, kRadChiMax);
+  const int row = pick_row<R>(lnchi, u_row, kRadChiMin, rg.rad_hi);
   R s;
   if (interp_s<R>(tab, row, u, kRadULo, kRadUHi, s)) {
     xi = (R)1 / ((R)1 + exp(-s));
@@ -112,8 +118,9 @@ __device__ __forceinline__ void sample_rad(const Tab &tab, R chi, R u, R u_row, 
 
 // Half-spectrum sample xi in (0, 1/2] of the pair spectrum (Eq. 6), chi >= 1e-2.
 template <typename R, typename Tab>
-__device__ __forceinline__ void sample_pair_half(const Tab &tab, R chi, R u, R u_row, R &xi, R &om) {
-  const int row = pick_row<R>(log(chi), u_row, kPairChiMin, kPairChiMax);
+__device__ __forceinline__ void sample_pair_half(const Tab &tab, R chi, R u, R u_row, R &xi, R &om,
+                                                 const TabRange &rg) {
+  const int row = pick_row<R>(log(chi), u_row, kPairChiMin, rg.pair_hi);
   R s;
   if (!interp_s<R>(tab, row, u, kPairULo, kPairUHi, s)) s = (R)tab.at(row, 0);
   xi = (R)1 / ((R)1 + exp(-s));

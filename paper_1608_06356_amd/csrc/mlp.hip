@@ -59,7 +59,7 @@ __device__ void sample_B(uint64_t g, uint32_t seed, const double *lnh, const dou
   const double lx = -3.0 + 5.0 * unit<double>(r.x);
   const double chi = pow(10.0, lx);
   x0 = xin(chi);
-  yt[0] = (float)((log(h_rad<double>(chi, lnh)) - log(chi) - kBShift0) / kBScale0);
+  yt[0] = (float)((log(h_rad<double>(chi, lnh, TabRange{})) - log(chi) - kBShift0) / kBScale0);
   if (chi >= kPairChiMin) {
     const double x = Grid<double>::pos(log(chi), kPairChiMin, kPairChiMax, kPairNRate);
     int i = (int)floor(x);
@@ -303,11 +303,11 @@ __global__ __launch_bounds__(kInferThreads) void k_infer(InferArgs a) {
     float lh = kBShift0 + kBScale0 * y[0] + lchi;
     const float env = logf(1.001f * (float)kHc1 * (float)chi);
     bool rate_ok = in_chi && isfinite(lh) && lh <= env;
-    if (!rate_ok) lh = logf(h_rad<float>((float)chi, a.lnh32));
+    if (!rate_ok) lh = logf(h_rad<float>((float)chi, a.lnh32, TabRange{}));
     float lhp;
     if (chi < kPairChiMin || gam < 2.0) lhp = -INFINITY;
     else if (chi <= kPairChiMax && isfinite(y[1])) lhp = kBShift1 + kBScale1 * y[1] + lchi - 8.0f / (3.0f * (float)chi);
-    else lhp = logf(h_pair<float>((float)chi, a.L32));
+    else lhp = logf(h_pair<float>((float)chi, a.L32, TabRange{}));
     // xi (net A) with residual check against the Hermite CDF table
     reload_barrier();
     forward_nc(S.A, 2, 1, xin(in_chi ? chi : 1.0), (float)(t / kTmax), y);
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(kInferThreads) void k_infer(InferArgs a) {
       xi = 1.f / (1.f + __expf(-s_hat));
       om = 1.f / (1.f + __expf(s_hat));
     } else {
-      sample_rad<float>(tab, (float)chi, u, urow, xi, om);
+      sample_rad<float>(tab, (float)chi, u, urow, xi, om, TabRange{});
     }
     if (valid && (lane >> 4) == 0) {
       a.lnw[i] = (float)((double)lh + log(kRateUnit / gam));

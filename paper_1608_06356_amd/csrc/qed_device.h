@@ -20,14 +20,16 @@ constexpr double kPi = 3.14159265358979323846;
 
 // Table layout (identical on every path; see qed.h, qed_build_tables).
 constexpr int kRadNChi = 256;
-constexpr double kRadChiMin = 1e-3, kRadChiMax = 1e2;
+constexpr double kRadChiMin = 1e-3, kRadChiMax = 1e2;   // default range
+constexpr double kMlpChiMax = 1e2;                       // surrogate domain [1e-3, 1e2]
 constexpr int kRadM = 1024;
 constexpr double kRadXiLoOverChi = 1e-15;
 constexpr double kRadDHi = 40.0;
 constexpr int kNU = 256;                       // quantile nodes per row (both tables)
 constexpr double kRadULo = 1e-4, kRadUHi = 1.0 - 1e-7;
 constexpr int kPairNRate = 512, kPairNCdf = 256;
-constexpr double kPairChiMin = 1e-2, kPairChiMax = 1e2;
+constexpr double kPairChiMin = 1e-2, kPairChiMax = 1e2;  // default range
+constexpr double kRadChiMaxLo = 1.0, kPairChiMaxLo = 10.0, kChiMaxHi = 1e6;  // allowed upper ends
 constexpr int kPairM = 1024;
 constexpr double kPairDD = 45.0;
 constexpr double kPairULo = 1e-6, kPairUHi = 1.0 - 1e-6;

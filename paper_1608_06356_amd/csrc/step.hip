@@ -178,6 +178,7 @@ struct GPArgs {
   uint32_t seed;
   uint64_t step;
   const int64_t *d_step;
+  TabRange rg;
 };
 
 constexpr int kGPThreads = 256, kGPTile = kGPThreads;
@@ -241,8 +242,8 @@ __global__ __launch_bounds__(kGPThreads) void k_gather_push(GPArgs<R> a) {
     const double chi = chi_lepton(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5]);
     double W = 0.0;
     if (isfinite(chi)) {
-      nrange = chi > kRadChiMax;
-      W = kRateUnit * (double)(h_rad<R>((R)chi, lnh_s) / g);
+      nrange = chi > a.rg.rad_hi;
+      W = kRateUnit * (double)(h_rad<R>((R)chi, lnh_s, a.rg) / g);
     } else {
       nnan = 1;
     }
@@ -336,6 +337,7 @@ struct EmitArgs {
   unsigned long long *counters;
   int gen;                     // event generator (see GPArgs)
   double dtd;
+  TabRange rg;
 };
 
 constexpr int kEmitThreads = 1024;
@@ -371,7 +373,7 @@ __device__ void emit_tile(const EmitArgs<R> &a, const Tab &tab, const R *lnh, ui
     auto event = [&](uint32_t k) {
       const uint4 u = stream4(id, a.seed, step, kLeptonEvent, k);
       R xi, om;
-      sample_rad<R>(tab, (R)chi, unit<R>(u.x), unit<R>(u.z), xi, om);
+      sample_rad<R>(tab, (R)chi, unit<R>(u.x), unit<R>(u.z), xi, om, a.rg);
       const R gp = xi * g;
       ++nev;
       if (gp >= (R)2) {
@@ -386,7 +388,7 @@ __device__ void emit_tile(const EmitArgs<R> &a, const Tab &tab, const R *lnh, ui
           g = gn;
           recoiled = true;
           chi = chi_lepton(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5]);
-          W = isfinite(chi) ? kRateUnit * (double)(h_rad<R>((R)chi, lnh) / g) : 0.0;
+          W = isfinite(chi) ? kRateUnit * (double)(h_rad<R>((R)chi, lnh, a.rg) / g) : 0.0;
         }
       } else {
         ++nrej;
@@ -510,6 +512,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_f64(EmitArgs<double> a) {
 // emission pass.  Both evaluate 16 particles per forward call per wave, so a
 // wave of 64 particles makes four calls with inputs broadcast by shuffles.
 struct MlpDev {
+  TabRange rg;
   const float *thA, *thB;    // float32 parameters (split into bf16 hi/lo in LDS)
   const float *chk;          // residual-check CDF rows
   const float *lnh32;        // rad table (fallback)
@@ -521,7 +524,7 @@ struct MlpDev {
 // ln h_rad(chi) from net B for the 64 lanes of a wave; ok = passed the check.
 __device__ __forceinline__ float mlp_lnh(const mlp::NetLds &B, double chi, bool &ok) {
   const int lane = threadIdx.x & 63;
-  const bool in = chi >= kRadChiMin && chi <= kRadChiMax;
+  const bool in = chi >= kRadChiMin && chi <= kMlpChiMax;
   const float xi_in = mlp::xin(in ? chi : 1.0);
   float mine = 0.f;
 #pragma unroll 1
@@ -589,7 +592,7 @@ __global__ __launch_bounds__(kGPThreads) void k_gather_push_mlp(GPArgs<float> a,
     if (live) {
       double W = 0.0;
       if (isfinite(chi) && chi > 0.0) {
-        const float h = ok ? expf(lh) : h_rad<float>((float)chi, lnh_s);
+        const float h = ok ? expf(lh) : h_rad<float>((float)chi, lnh_s, m.rg);
         nfb += !ok;
         W = kRateUnit * (double)(h / g);
       }
@@ -675,7 +678,7 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
       const uint4 u = stream4(id, a.seed, step_of(a.step, a.d_step), kLeptonEvent, (uint32_t)k);
       const float uxi = unit<float>(u.x), urow = unit<float>(u.z);
       const float t = logf(uxi) - log1pf(-uxi);
-      const bool in_chi = chi >= kRadChiMin && chi <= kRadChiMax;
+      const bool in_chi = chi >= kRadChiMin && chi <= kMlpChiMax;
       const float xa0 = mlp::xin(in_chi ? chi : 1.0), xa1 = t / (float)mlp::kTmax;
       float yA = 0.f;
 #pragma unroll 1
@@ -690,7 +693,7 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
       const float s_hat = mlp::kAShift + mlp::kAScale * yA + lchi + 3.0f * (-log1pf(__expf(-t)));
       bool xi_ok = in_chi && fabsf(t) <= (float)mlp::kTmax && isfinite(s_hat);
       if (xi_ok) {
-        const float xp = Grid<float>::pos(lchi, kRadChiMin, kRadChiMax, kRadNChi);
+        const float xp = Grid<float>::pos(lchi, kRadChiMin, m.rg.rad_hi, kRadNChi);
         int ii = (int)floorf(xp);
         ii = ii < 0 ? 0 : (ii > kRadNChi - 2 ? kRadNChi - 2 : ii);
         const float w = xp - ii;
@@ -702,7 +705,7 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
         xi = 1.f / (1.f + __expf(-s_hat));
         om = 1.f / (1.f + __expf(s_hat));
       } else if (active) {
-        sample_rad<float>(tab, (float)chi, uxi, urow, xi, om);
+        sample_rad<float>(tab, (float)chi, uxi, urow, xi, om, m.rg);
       } else {
         xi = 0.f; om = 1.f;
       }
@@ -736,7 +739,7 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
         if (recoil_now) {
           float h = 0.f;
           if (isfinite(chi) && chi > 0.0) {
-            h = ok ? expf(lh) : h_rad<float>((float)chi, S.lnh);
+            h = ok ? expf(lh) : h_rad<float>((float)chi, S.lnh, m.rg);
             nfr += !ok;
           }
           W = kRateUnit * (double)(h / g);
@@ -815,6 +818,7 @@ struct PairArgs {
   ScanDev sc;
   unsigned long long *counters;
   int64_t *killed;
+  TabRange rg;
 };
 
 constexpr int kPairThreads = 1024;
@@ -846,8 +850,8 @@ __device__ void pair_tile(const PairArgs<R> &a, const Tab &tab, const R *L, uint
     const double chi = fields_finite<R>(F) ? chi_photon(kx, ky, kz, F[0], F[1], F[2], F[3], F[4], F[5]) : NAN;
     double W = 0.0;
     if (isfinite(chi)) {
-      nrange += chi > kPairChiMax;
-      if (gph >= (R)2) W = kRateUnit * (double)(h_pair<R>((R)chi, L) / gph);
+      nrange += chi > a.rg.pair_hi;
+      if (gph >= (R)2) W = kRateUnit * (double)(h_pair<R>((R)chi, L, a.rg) / gph);
     } else {
       ++nnan;
     }
@@ -857,7 +861,7 @@ __device__ void pair_tile(const PairArgs<R> &a, const Tab &tab, const R *L, uint
       const uint64_t id = a.ph.id[i];
       const uint4 u = stream4(id, a.seed, step_of(a.step, a.d_step), kPhotonEvent, 0u);
       R xh, omh;
-      sample_pair_half<R>(tab, (R)chi, unit<R>(u.x), unit<R>(u.y), xh, omh);
+      sample_pair_half<R>(tab, (R)chi, unit<R>(u.x), unit<R>(u.y), xh, omh, a.rg);
       const bool flip = u.y & 1u;
       const R xe = flip ? omh : xh, xp = flip ? xh : omh;
       ge = xe * gph;
@@ -1052,38 +1056,39 @@ __global__ void k_standing_wave(float *grid, int n, double dx, double a0, double
 template <typename R, typename Tab>
 __device__ void sample_one(const Tab &tab, const R *lnh, const R *L, double chi, double gamma,
                            uint64_t id, uint32_t seed, uint64_t step, float *lnw, float *xi_out,
-                           float *lnwp, int64_t i) {
-  const R h = h_rad<R>((R)chi, lnh);
+                           float *lnwp, int64_t i, const TabRange &rg) {
+  const R h = h_rad<R>((R)chi, lnh, rg);
   lnw[i] = (float)log(kRateUnit * (double)h / gamma);
   const uint4 u = stream4(id, seed, step, kLeptonEvent, 0u);
   R xi, om;
-  sample_rad<R>(tab, (R)chi, unit<R>(u.x), unit<R>(u.z), xi, om);
+  sample_rad<R>(tab, (R)chi, unit<R>(u.x), unit<R>(u.z), xi, om, rg);
   xi_out[i] = (float)xi;
   if (lnwp) {
-    const R hp = gamma >= 2.0 ? h_pair<R>((R)chi, L) : (R)0;
+    const R hp = gamma >= 2.0 ? h_pair<R>((R)chi, L, rg) : (R)0;
     lnwp[i] = (float)log(kRateUnit * (double)hp / gamma);
   }
 }
 
 __global__ void k_sample_f64(const double *chi, const double *gamma, const uint64_t *id, int64_t n,
                              const double *lnh, const double *L, const double *S64, uint32_t seed,
-                             uint64_t step_v, const int64_t *d_step, float *lnw, float *xi, float *lnwp) {
+                             uint64_t step_v, const int64_t *d_step, float *lnw, float *xi, float *lnwp,
+                             TabRange rg) {
   const uint64_t step = step_of(step_v, d_step);
   const RowF64 tab{S64};
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
-    sample_one<double>(tab, lnh, L, chi[i], gamma[i], id[i], seed, step, lnw, xi, lnwp, i);
+    sample_one<double>(tab, lnh, L, chi[i], gamma[i], id[i], seed, step, lnw, xi, lnwp, i, rg);
 }
 
 __global__ void k_sample_f32(const double *chi, const double *gamma, const uint64_t *id, int64_t n,
                              const float *lnh, const float *L, const uint16_t *q16, const float *s0sc,
                              uint32_t seed, uint64_t step_v, const int64_t *d_step, float *lnw, float *xi,
-                             float *lnwp) {
+                             float *lnwp, TabRange rg) {
   const uint64_t step = step_of(step_v, d_step);
   const RowQ16 tab{q16, s0sc};
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
-    sample_one<float>(tab, lnh, L, chi[i], gamma[i], id[i], seed, step, lnw, xi, lnwp, i);
+    sample_one<float>(tab, lnh, L, chi[i], gamma[i], id[i], seed, step, lnw, xi, lnwp, i, rg);
 }
 
 }  // namespace qed
@@ -1125,7 +1130,7 @@ static void launch_gp_kind(const GPArgs<R> &a, int kind, unsigned grid, hipStrea
 }
 
 static MlpDev mlp_dev(qed_ctx *c) {
-  return MlpDev{c->mlp_theta[0], c->mlp_theta[1], c->rad_chk, c->rad_lnh32, c->rad_q16, c->rad_s0sc, 2e-3f};
+  return MlpDev{c->range, c->mlp_theta[0], c->mlp_theta[1], c->rad_chk, c->rad_lnh32, c->rad_q16, c->rad_s0sc, 2e-3f};
 }
 
 static int gen_mode(const qed_ctx *c) {
@@ -1147,7 +1152,7 @@ hipError_t launch_gather_push(qed_ctx *c, const qed_fields_t *f, const qed_speci
     if (g > (int64_t)grid) g = ((int64_t)grid + kXcds - 1) / kXcds * kXcds;
     g = (g + kXcds - 1) / kXcds * kXcds;
     GPArgs<float> a{dev_species(sp), dev_fields(f), c->rad_lnh32, (float)charge, (float)dt, dt, c->em_mask,
-                    (EmRec<float> *)c->em_rec, tpx, c->d_counters, 0, c->params.seed, (uint64_t)step, dstep};
+                    (EmRec<float> *)c->em_rec, tpx, c->d_counters, 0, c->params.seed, (uint64_t)step, dstep, c->range};
     const MlpDev m = mlp_dev(c);
     if (f->kind == QED_FIELD_GRID)
       hipLaunchKernelGGL(k_gather_push_mlp<QED_FIELD_GRID>, dim3((unsigned)g), dim3(kGPThreads), 0, st, a, m);
@@ -1157,11 +1162,11 @@ hipError_t launch_gather_push(qed_ctx *c, const qed_fields_t *f, const qed_speci
       hipLaunchKernelGGL(k_gather_push_mlp<QED_FIELD_PER_PARTICLE>, dim3((unsigned)g), dim3(kGPThreads), 0, st, a, m);
   } else if (sp->dtype == QED_F32) {
     GPArgs<float> a{dev_species(sp), dev_fields(f), c->rad_lnh32, (float)charge, (float)dt, dt, c->em_mask,
-                    (EmRec<float> *)c->em_rec, tpx, c->d_counters, gen, c->params.seed, (uint64_t)step, dstep};
+                    (EmRec<float> *)c->em_rec, tpx, c->d_counters, gen, c->params.seed, (uint64_t)step, dstep, c->range};
     launch_gp_kind<float>(a, f->kind, grid, st);
   } else {
     GPArgs<double> a{dev_species(sp), dev_fields(f), c->rad_lnh64, (double)charge, dt, dt, c->em_mask,
-                     (EmRec<double> *)c->em_rec, tpx, c->d_counters, gen, c->params.seed, (uint64_t)step, dstep};
+                     (EmRec<double> *)c->em_rec, tpx, c->d_counters, gen, c->params.seed, (uint64_t)step, dstep, c->range};
     launch_gp_kind<double>(a, f->kind, grid, st);
   }
   hipError_t e = hipGetLastError();
@@ -1190,7 +1195,7 @@ hipError_t launch_emit(qed_ctx *c, const qed_species_t *lep, const qed_species_t
     EmitArgs<float> a{dev_species(lep), dev_species(ph), c->rad_lnh32, c->rad_S64, c->rad_q16,
                       c->rad_s0sc, c->em_idx, (const EmRec<float> *)c->em_rec, c->d_n_emit,
                       c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, dstep, sc,
-                      c->d_counters, gen_mode(c), c->em_dt};
+                      c->d_counters, gen_mode(c), c->em_dt, c->range};
     static bool attr = false;
     if (!attr) {
       (void)hipFuncSetAttribute((const void *)k_emit_mlp, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1202,13 +1207,13 @@ hipError_t launch_emit(qed_ctx *c, const qed_species_t *lep, const qed_species_t
     EmitArgs<float> a{dev_species(lep), dev_species(ph), c->rad_lnh32, c->rad_S64, c->rad_q16,
                       c->rad_s0sc, c->em_idx, (const EmRec<float> *)c->em_rec, c->d_n_emit,
                       c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, dstep, sc,
-                      c->d_counters, gen_mode(c), c->em_dt};
+                      c->d_counters, gen_mode(c), c->em_dt, c->range};
     hipLaunchKernelGGL(k_emit_f32, dim3(grid), dim3(kEmitThreads), 0, st, a);
   } else {
     EmitArgs<double> a{dev_species(lep), dev_species(ph), c->rad_lnh64, c->rad_S64, c->rad_q16,
                        c->rad_s0sc, c->em_idx, (const EmRec<double> *)c->em_rec, c->d_n_emit,
                        c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, dstep, sc,
-                       c->d_counters, gen_mode(c), c->em_dt};
+                       c->d_counters, gen_mode(c), c->em_dt, c->range};
     hipLaunchKernelGGL(k_emit_f64, dim3(grid), dim3(kEmitThreads), 0, st, a);
   }
   return hipGetLastError();
@@ -1228,12 +1233,12 @@ hipError_t launch_pairs(qed_ctx *c, const qed_fields_t *f, const qed_species_t *
   if (ph->dtype == QED_F32) {
     PairArgs<float> a{dev_species(ph), dev_species(el), dev_species(po), dev_fields(f), c->pair_L32,
                       c->pair_S64, c->pair_q16, c->pair_s0sc, (float)dt, dt, move, c->d_next_id,
-                      c->params.seed, (uint64_t)step, step < 0 ? c->d_step : nullptr, sc, c->d_counters, killed};
+                      c->params.seed, (uint64_t)step, step < 0 ? c->d_step : nullptr, sc, c->d_counters, killed, c->range};
     hipLaunchKernelGGL(k_pairs_f32, dim3(grid), dim3(kPairThreads), 0, st, a);
   } else {
     PairArgs<double> a{dev_species(ph), dev_species(el), dev_species(po), dev_fields(f), c->pair_L64,
                        c->pair_S64, c->pair_q16, c->pair_s0sc, dt, dt, move, c->d_next_id,
-                       c->params.seed, (uint64_t)step, step < 0 ? c->d_step : nullptr, sc, c->d_counters, killed};
+                       c->params.seed, (uint64_t)step, step < 0 ? c->d_step : nullptr, sc, c->d_counters, killed, c->range};
     hipLaunchKernelGGL(k_pairs_f64, dim3(grid), dim3(kPairThreads), 0, st, a);
   }
   return hipGetLastError();
@@ -1295,11 +1300,11 @@ hipError_t launch_sample(qed_ctx *c, const double *chi, const double *gamma, con
     hipLaunchKernelGGL(k_sample_f64, dim3((unsigned)blocks), dim3(256), 0, st, chi, gamma, id, n,
                        c->rad_lnh64, c->pair_L64, c->rad_S64, c->params.seed, (uint64_t)step,
                        step < 0 ? c->d_step : nullptr, lnw,
-                       xi, lnwp);
+                       xi, lnwp, c->range);
   else
     hipLaunchKernelGGL(k_sample_f32, dim3((unsigned)blocks), dim3(256), 0, st, chi, gamma, id, n,
                        c->rad_lnh32, c->pair_L32, c->rad_q16, c->rad_s0sc, c->params.seed,
-                       (uint64_t)step, step < 0 ? c->d_step : nullptr, lnw, xi, lnwp);
+                       (uint64_t)step, step < 0 ? c->d_step : nullptr, lnw, xi, lnwp, c->range);
   return hipGetLastError();
 }
 

@@ -255,13 +255,13 @@ double chi_node(int i, int n, double lo, double hi) {
 
 }  // namespace
 
-hipError_t launch_build_tables(qed_ctx *c, int formula, hipStream_t st) {
+hipError_t launch_build_tables(qed_ctx *c, int formula, TabRange rg, hipStream_t st) {
   const int kind_rad = formula == QED_FORMULA_II ? kFormulaII : (formula == QED_FORMULA_CLASSICAL ? kClassical : kFormulaI);
   const int njobs = kRadNChi + kPairNRate + kPairNCdf;
   Job *h = new Job[njobs];
   int n = 0;
   for (int i = 0; i < kRadNChi; ++i) {
-    const double chi = chi_node(i, kRadNChi, kRadChiMin, kRadChiMax);
+    const double chi = chi_node(i, kRadNChi, kRadChiMin, rg.rad_hi);
     const double xi_lo = kRadXiLoOverChi * chi;
     const double tail = kInvSqrt3Pi * 3.0 * kGamma23 * pow(3.0 * chi, 2.0 / 3.0) * pow(xi_lo, 1.0 / 3.0);
     h[n++] = Job{kind_rad, 0, i, chi, log(xi_lo) - log1p(-xi_lo), log(1.5 * kRadDHi * chi), tail};
@@ -272,11 +272,11 @@ hipError_t launch_build_tables(qed_ctx *c, int formula, hipStream_t st) {
     return log(xi_lo) - log1p(-xi_lo);
   };
   for (int i = 0; i < kPairNRate; ++i) {
-    const double chi = chi_node(i, kPairNRate, kPairChiMin, kPairChiMax);
+    const double chi = chi_node(i, kPairNRate, kPairChiMin, rg.pair_hi);
     h[n++] = Job{kPair, 1, i, chi, pair_lo(chi), 0.0, 0.0};
   }
   for (int i = 0; i < kPairNCdf; ++i) {
-    const double chi = chi_node(i, kPairNCdf, kPairChiMin, kPairChiMax);
+    const double chi = chi_node(i, kPairNCdf, kPairChiMin, rg.pair_hi);
     h[n++] = Job{kPair, 2, i, chi, pair_lo(chi), 0.0, 0.0};
   }
   hipError_t e;

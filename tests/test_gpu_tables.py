@@ -67,3 +67,28 @@ def test_classical_table_vs_oracle():
     for i in (0, 90, 200, 255):
         assert abs(lnh[i] - ref.ln_h[i]) < 1e-11
         assert np.abs(S[i] - ref.s[i]).max() < 1e-8
+
+
+def test_wide_range_tables_vs_oracle():
+    """qed_build_tables_range up to chi = 1e5 (the Fig. 5 cascade): sampled rows
+    of every table against the oracle's quadrature on the same nodes; the
+    surrogate entry points refuse tables of a non-default range."""
+    torch, q = need_gpu()
+    ctx = q.Context()
+    ctx.qed_build_tables_range(q.QED_FORMULA_I, 1e5, 1e5)
+    lnh, S, L, PS = (ctx.qed_get_table(w) for w in range(4))
+    rows = [0, 128, 250, 255]
+    ref = tables.build_rad_table("I", rows=rows, chi_max=1e5)
+    pref = tables.build_pair_table(rate_rows=[0, 300, 511], cdf_rows=[0, 128, 255], chi_max=1e5)
+    for i in rows:
+        assert abs(lnh[i] - ref.ln_h[i]) < 1e-11
+        assert np.abs(S[i] - ref.s[i]).max() < 1e-8
+    for i in (0, 300, 511):
+        assert abs(L[i] - pref.L[i]) < 1e-10
+    for i in (0, 128, 255):
+        assert np.abs(PS[i] - pref.s[i]).max() < 1e-8
+    with pytest.raises(q.QEDError):
+        ctx.qed_surrogate_train(steps=1, batch=64, lr=1e-3, seed=0, nets=3)
+    with pytest.raises(q.QEDError):
+        ctx.qed_build_tables_range(q.QED_FORMULA_I, 1e7, 1e5)
+    ctx.close()

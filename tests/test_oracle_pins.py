@@ -253,6 +253,31 @@ def test_rate_table_interpolation(rad_table_I):
                / tables.fine_row("I", c, tables.RAD_M, need_rho=False).total - 1) < 1e-5
 
 
+def test_wide_range_tables():
+    """Tables over chi <= 1e5 (the Fig. 5 cascade, chi_0 ~ 4e4): the nodes end at
+    1e5; between nodes the photon rate stays within 1e-4 and the pair rate
+    within 2e-5 of the quadrature (wider spacing than the default tables); above
+    the range both follow the chi^(2/3) law within the asymptote's own error."""
+    hi = 1e5
+    chi = tables.chi_nodes(tables.RAD_NCHI, tables.RAD_CHI_MIN, hi)
+    assert abs(chi[0] / tables.RAD_CHI_MIN - 1) < 1e-14 and abs(chi[-1] / hi - 1) < 1e-14
+    pick = [60, 140, 200, 250]                 # chi ~ 0.04, 6, 290, 4e4
+    rows = sorted(set(pick + [i + 1 for i in pick] + [255]))
+    tab = tables.build_rad_table("I", rows=rows, chi_max=hi)
+    mids = np.sqrt(chi[pick] * chi[[i + 1 for i in pick]])
+    exact = np.array([tables.fine_row("I", c, tables.RAD_M, need_rho=False).total for c in mids])
+    assert np.max(np.abs(tables.h_rad(tab, mids) / exact - 1)) < 1e-4
+    big = 14 * sp.gamma(2 / 3) / (9 * 3 ** (1 / 3))
+    assert abs(tables.h_rad(tab, np.array([1e6]))[0] / (big * 1e6 ** (2 / 3)) - 1) < 1e-3
+    pchi = tables.chi_nodes(tables.PAIR_NRATE, tables.PAIR_CHI_MIN, hi)
+    ppick = [100, 300, 500]                    # chi_ph ~ 0.24, 5.5e2, 7e4
+    prows = sorted(set(ppick + [i + 1 for i in ppick]))
+    ptab = tables.build_pair_table(rate_rows=prows, cdf_rows=[], chi_max=hi)
+    pm = np.sqrt(pchi[ppick] * pchi[[i + 1 for i in ppick]])
+    pex = np.array([2 * tables.fine_row("pair", c, tables.PAIR_M, need_rho=False).total for c in pm])
+    assert np.max(np.abs(tables.h_pair(ptab, pm) / pex - 1)) < 2e-5
+
+
 def _exact_cdf(kind, chi):
     row = tables.fine_row(kind, chi, tables.RAD_M if kind != "pair" else tables.PAIR_M)
     P = row.F / row.total

@@ -19,6 +19,10 @@ pair_photons  photons with chi_ph log-uniform in [1e-2, 1e2], isotropic
     passes the normalising Schwinger field).
 sampler_inputs  log10 chi uniform in [-3, 2] with gamma = 1000, for the
     standalone sampler.
+single_electron_runs  the Fig. 5 cascade seed: nrun copies of one electron with
+    gamma_0 = 2e5 moving along +x, meant for a static B along z (the field is the
+    caller's).  Run r sits at z = r: with B along z and every momentum in the
+    x-y plane, z never changes, so each particle's z names its run.
 """
 import math
 
@@ -77,3 +81,11 @@ def sampler_inputs(n, seed=3, gamma=1000.0):
     rng = np.random.default_rng(seed)
     chi = 10.0 ** rng.uniform(-3.0, 2.0, n)
     return dict(chi=chi, gamma=np.full(n, gamma), id=np.arange(n, dtype=np.uint64))
+
+
+def single_electron_runs(nrun, gamma0=2e5):
+    x = np.zeros((nrun, 3))
+    x[:, 2] = np.arange(nrun, dtype=np.float64)
+    p = np.zeros((nrun, 3))
+    p[:, 0] = math.sqrt(gamma0 * gamma0 - 1.0)
+    return dict(x=x, p=p, id=np.arange(nrun, dtype=np.uint64))
