@@ -124,7 +124,8 @@ typedef struct {
   int32_t nx, ny, nz;          /* GRID: nodes per axis                                 */
   const float *grid;           /* GRID: 6 floats per node (Ex Ey Ez Bx By Bz),
                                   node (i,j,k) at ((k*ny + j)*nx + i)*6; node i sits at
-                                  x = i*dx; the box [0, n*d) is periodic             */
+                                  x = i*dx; the box [0, n*d) is periodic; at most
+                                  2^32 - 1 floats (nx*ny*nz*6), QED_ERR_ARG beyond   */
   double dx, dy, dz;
   double E[3], B[3];           /* UNIFORM                                              */
   const float *pE[3], *pB[3];  /* PER_PARTICLE: device arrays, element i for particle i */
@@ -244,7 +245,10 @@ QED_API int qed_create_pairs(qed_ctx_t ctx, const qed_fields_t *fields, qed_spec
 
 /* Stable reordering of src into dst (caller-owned, same dtype, capacity >= src's)
    by the grid cell of each particle's nearest node, so that the quadratic-spline
-   gather of neighbouring threads reads neighbouring nodes.  Ids, optical depths
+   gather of neighbouring threads reads neighbouring nodes.  Key of node (i,j,k):
+   cells grouped in 4x4x4 blocks, blocks in z-major order and cells in z-major order
+   inside a block, i.e. ((k/4 * NBy + j/4) * NBx + i/4) * 64 + ((k%4) * 4 + j%4) * 4 + i%4
+   with NBx = ceil(nx/4), NBy = ceil(ny/4).  Ids, optical depths
    and therefore every random stream move with the particles.  A periodic sort is
    what keeps qed_gather_push's field reads local.  Allocates its scratch on the
    first call for a given capacity (call once before graph capture). */

@@ -39,8 +39,8 @@ int check_fields(qed_ctx *c, const qed_fields_t *f) {
       return fail(c, QED_ERR_ARG, "grid fields: need grid pointer, n >= 3 and d > 0 on every axis");
     if (((uintptr_t)f->grid) % 8)
       return fail(c, QED_ERR_ARG, "grid fields: pointer must be 8-byte aligned");
-    if ((int64_t)f->nx * f->ny * f->nz * 6 > (int64_t)1 << 40)
-      return fail(c, QED_ERR_ARG, "grid fields: too many nodes");
+    if ((int64_t)f->nx * f->ny * f->nz * 6 >= (int64_t)1 << 32)
+      return fail(c, QED_ERR_ARG, "grid fields: nx ny nz 6 must be below 2^32 floats");
     return QED_OK;
   }
   if (f->kind == QED_FIELD_PER_PARTICLE) {
@@ -185,7 +185,7 @@ int qed_build_tables_range(qed_ctx_t c, int formula, double rad_chi_max, double 
     c->tab_work_elems = work;
   }
   c->tables_ready = false;
-  const TabRange rg{rad_chi_max, pair_chi_max};
+  const TabRange rg = make_range(rad_chi_max, pair_chi_max);
   if ((e = launch_build_tables(c, formula, rg, S(st))) != hipSuccess) return hip_fail(c, e, "build_tables");
   c->tables_ready = true;
   c->formula = formula;

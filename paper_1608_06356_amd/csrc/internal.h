@@ -15,7 +15,7 @@ struct qed_ctx {
   // tables (library-owned device memory)
   bool tables_ready = false;
   int formula = 0;
-  qed::TabRange range;            // chi range of the built tables
+  qed::TabRange range = qed::make_range(qed::kRadChiMax, qed::kPairChiMax);   // grids of the built tables
   double *rad_lnh64 = nullptr, *rad_S64 = nullptr;       // [256], [256*256]
   float *rad_lnh32 = nullptr, *rad_s0sc = nullptr;       // [256], [2*256]
   uint16_t *rad_q16 = nullptr;                           // [256*256]

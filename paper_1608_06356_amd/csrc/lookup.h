@@ -6,33 +6,58 @@
 
 namespace qed {
 
-// Upper ends of the chi ranges of the tables (the lower ends are fixed at 1e-3
-// for photon emission and 1e-2 for pairs); chosen when the tables are built.
+// Node grids of the tables, computed once on the host when the tables are
+// built: chi nodes log-spaced from 1e-3 (photon) or 1e-2 (pair) to an upper end
+// chosen by the caller, quantile nodes uniform in t = logit(u).  A position on a
+// grid is (coordinate - origin) * inverse spacing.
 struct TabRange {
-  double rad_hi = kRadChiMax, pair_hi = kPairChiMax;
+  double rad_hi, pair_hi;
+  double rad_lnlo, rad_inv;                      // 256 photon chi nodes
+  double pair_lnlo, pair_rate_inv, pair_cdf_inv;   // 512 pair-rate and 256 pair-CDF nodes
+  double rad_tlo, rad_tinv, pair_tlo, pair_tinv;   // 256 quantile nodes each
 };
 
-// ln chi grid positions: x = (ln chi - ln chi_min) / step
-template <typename R> struct Grid {
-  static __device__ __forceinline__ R pos(R lnchi, double lo, double hi, int n) {
-    const double step = (log(hi) - log(lo)) / (n - 1);
-    return (lnchi - (R)log(lo)) / (R)step;
-  }
+__host__ __device__ inline TabRange make_range(double rad_hi, double pair_hi) {
+  TabRange r;
+  r.rad_hi = rad_hi;
+  r.pair_hi = pair_hi;
+  r.rad_lnlo = log(kRadChiMin);
+  r.rad_inv = (kRadNChi - 1) / (log(rad_hi) - log(kRadChiMin));
+  r.pair_lnlo = log(kPairChiMin);
+  r.pair_rate_inv = (kPairNRate - 1) / (log(pair_hi) - log(kPairChiMin));
+  r.pair_cdf_inv = (kPairNCdf - 1) / (log(pair_hi) - log(kPairChiMin));
+  r.rad_tlo = log(kRadULo) - log1p(-kRadULo);
+  r.rad_tinv = (kNU - 1) / ((log(kRadUHi) - log1p(-kRadUHi)) - r.rad_tlo);
+  r.pair_tlo = log(kPairULo) - log1p(-kPairULo);
+  r.pair_tinv = (kNU - 1) / ((log(kPairUHi) - log1p(-kPairUHi)) - r.pair_tlo);
+  return r;
+}
+
+// ln and exp: Fast selects the hardware log2/exp2 instructions in float32
+// (relative error ~1e-6 after the change of base), for the rate of the push.
+template <typename R, bool Fast> struct Math {
+  static __device__ __forceinline__ R ln(R v) { return log(v); }
+  static __device__ __forceinline__ R ex(R v) { return exp(v); }
+};
+template <> struct Math<float, true> {
+  static __device__ __forceinline__ float ln(float v) { return __logf(v); }
+  static __device__ __forceinline__ float ex(float v) { return __expf(v); }
 };
 
 // Photon rate h(chi): linear in (ln chi, ln h) between nodes; small-chi expansion
 // c1 chi (1 - c2 chi) below, chi^(2/3) growth above; 0 for chi <= 0.
-template <typename R>
+template <typename R, bool Fast = false>
 __device__ __forceinline__ R h_rad(R chi, const R *lnh, const TabRange &rg) {
+  using M = Math<R, Fast>;
   if (!(chi > (R)0)) return (R)0;
   if (chi < (R)kRadChiMin) return (R)kHc1 * chi * ((R)1 - (R)kHc2 * chi);
   if (chi > (R)rg.rad_hi)
-    return exp(lnh[kRadNChi - 1] + (R)(2.0 / 3.0) * log(chi / (R)rg.rad_hi));
-  const R x = Grid<R>::pos(log(chi), kRadChiMin, rg.rad_hi, kRadNChi);
+    return M::ex(lnh[kRadNChi - 1] + (R)(2.0 / 3.0) * M::ln(chi / (R)rg.rad_hi));
+  const R x = (M::ln(chi) - (R)rg.rad_lnlo) * (R)rg.rad_inv;
   int i = (int)floor(x);
   i = i < 0 ? 0 : (i > kRadNChi - 2 ? kRadNChi - 2 : i);
   const R f = x - (R)i;
-  return exp(((R)1 - f) * lnh[i] + f * lnh[i + 1]);
+  return M::ex(((R)1 - f) * lnh[i] + f * lnh[i + 1]);
 }
 
 // Pair rate h_pair(chi) from L = ln h_pair + 8/(3 chi); 0 below chi = 1e-2.
@@ -41,7 +66,7 @@ __device__ __forceinline__ R h_pair(R chi, const R *L, const TabRange &rg) {
   if (!(chi >= (R)kPairChiMin)) return (R)0;
   if (chi > (R)rg.pair_hi)
     return exp(L[kPairNRate - 1] - (R)(8.0 / (3.0 * rg.pair_hi)) + (R)(2.0 / 3.0) * log(chi / (R)rg.pair_hi));
-  const R x = Grid<R>::pos(log(chi), kPairChiMin, rg.pair_hi, kPairNRate);
+  const R x = (log(chi) - (R)rg.pair_lnlo) * (R)rg.pair_rate_inv;
   int i = (int)floor(x);
   i = i < 0 ? 0 : (i > kPairNRate - 2 ? kPairNRate - 2 : i);
   const R f = x - (R)i;
@@ -51,8 +76,8 @@ __device__ __forceinline__ R h_pair(R chi, const R *L, const TabRange &rg) {
 // Row of a 256-row table: linear interpolation of the CDF in ln chi realised by
 // taking row i+1 with probability equal to the fractional position.
 template <typename R>
-__device__ __forceinline__ int pick_row(R lnchi, R u_row, double lo, double hi) {
-  const R x = Grid<R>::pos(lnchi, lo, hi, 256);
+__device__ __forceinline__ int pick_row(R lnchi, R u_row, double lnlo, double inv) {
+  const R x = (lnchi - (R)lnlo) * (R)inv;
   int i = (int)floor(x);
   i = i < 0 ? 0 : (i > 254 ? 254 : i);
   const R f = x - (R)i;
@@ -78,11 +103,9 @@ struct RowQ16 {
 // logit(xi) at quantile u: linear in t = logit(u) between the 256 nodes.
 // Returns false in the low tail (t < t_lo), where the caller applies its tail law.
 template <typename R, typename Tab>
-__device__ __forceinline__ bool interp_s(const Tab &tab, int row, R u, double ulo, double uhi, R &s) {
-  const double tlo = log(ulo) - log1p(-ulo), thi = log(uhi) - log1p(-uhi);
-  const double dt = (thi - tlo) / (kNU - 1);
+__device__ __forceinline__ bool interp_s(const Tab &tab, int row, R u, double tlo, double tinv, R &s) {
   const R t = log(u) - log1p(-u);
-  const R y = (t - (R)tlo) / (R)dt;
+  const R y = (t - (R)tlo) * (R)tinv;
   if (y < (R)0) return false;
   if (y >= (R)(kNU - 1)) { s = (R)tab.at(row, kNU - 1); return true; }
   int j = (int)floor(y);
@@ -99,9 +122,9 @@ __device__ __forceinline__ bool interp_s(const Tab &tab, int row, R u, double ul
 template <typename R, typename Tab>
 __device__ __forceinline__ void sample_rad(const Tab &tab, R chi, R u, R u_row, R &xi, R &om, const TabRange &rg) {
   const R lnchi = log(chi);
-  const int row = pick_row<R>(lnchi, u_row, kRadChiMin, rg.rad_hi);
+  const int row = pick_row<R>(lnchi, u_row, rg.rad_lnlo, rg.rad_inv);
   R s;
-  if (interp_s<R>(tab, row, u, kRadULo, kRadUHi, s)) {
+  if (interp_s<R>(tab, row, u, rg.rad_tlo, rg.rad_tinv, s)) {
     xi = (R)1 / ((R)1 + exp(-s));
     om = (R)1 / ((R)1 + exp(s));
   } else {
@@ -120,9 +143,9 @@ __device__ __forceinline__ void sample_rad(const Tab &tab, R chi, R u, R u_row, 
 template <typename R, typename Tab>
 __device__ __forceinline__ void sample_pair_half(const Tab &tab, R chi, R u, R u_row, R &xi, R &om,
                                                  const TabRange &rg) {
-  const int row = pick_row<R>(log(chi), u_row, kPairChiMin, rg.pair_hi);
+  const int row = pick_row<R>(log(chi), u_row, rg.pair_lnlo, rg.pair_cdf_inv);
   R s;
-  if (!interp_s<R>(tab, row, u, kPairULo, kPairUHi, s)) s = (R)tab.at(row, 0);
+  if (!interp_s<R>(tab, row, u, rg.pair_tlo, rg.pair_tinv, s)) s = (R)tab.at(row, 0);
   xi = (R)1 / ((R)1 + exp(-s));
   om = (R)1 / ((R)1 + exp(s));
 }

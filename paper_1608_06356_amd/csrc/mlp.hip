@@ -52,16 +52,16 @@ __device__ void sample_A(uint64_t g, uint32_t seed, const double *S64, float &x0
 
 // Training sample g of net B: log10 chi uniform in [-3, 2]; targets from the
 // float64 master rate tables (pair output masked below chi = 1e-2).
-__device__ void sample_B(uint64_t g, uint32_t seed, const double *lnh, const double *L, float &x0,
-                         float yt[2], float m[2]) {
+__device__ void sample_B(uint64_t g, uint32_t seed, const double *lnh, const double *L, const TabRange &rg,
+                         float &x0, float yt[2], float m[2]) {
   const uint4 r = philox4x32_10(make_uint4((uint32_t)g, (uint32_t)(g >> 32), (kTrainPurpose << 24) | 1u, 0u),
                                 make_uint2(seed, 0x5A5A5A5Au));
   const double lx = -3.0 + 5.0 * unit<double>(r.x);
   const double chi = pow(10.0, lx);
   x0 = xin(chi);
-  yt[0] = (float)((log(h_rad<double>(chi, lnh, TabRange{})) - log(chi) - kBShift0) / kBScale0);
+  yt[0] = (float)((log(h_rad<double>(chi, lnh, rg)) - log(chi) - kBShift0) / kBScale0);
   if (chi >= kPairChiMin) {
-    const double x = Grid<double>::pos(log(chi), kPairChiMin, kPairChiMax, kPairNRate);
+    const double x = (log(chi) - rg.pair_lnlo) * rg.pair_rate_inv;
     int i = (int)floor(x);
     i = i < 0 ? 0 : (i > kPairNRate - 2 ? kPairNRate - 2 : i);
     const double f = x - i;
@@ -84,6 +84,7 @@ struct TrainArgs {
   int64_t nbatch;
   uint64_t sample0;
   uint32_t seed;
+  TabRange rg;             // the default table range (the nets' domain)
 };
 
 constexpr int kTrainThreads = 256;
@@ -155,7 +156,7 @@ __global__ __launch_bounds__(kTrainThreads) void k_train(TrainArgs a) {
         sample_A(a.sample0 + smp, a.seed, a.S64, x0, x1, yt[0]);
         m[0] = 1.f;
       } else {
-        sample_B(a.sample0 + smp, a.seed, a.lnh, a.L, x0, yt, m);
+        sample_B(a.sample0 + smp, a.seed, a.lnh, a.L, a.rg, x0, yt, m);
       }
     }
     Cache c;
@@ -263,6 +264,7 @@ struct InferArgs {
   float *lnw, *xi, *lnwp;
   float tol;
   unsigned long long *fallback;     // [0] xi fallbacks, [1] rate fallbacks
+  TabRange rg;                      // the default table range (the nets' domain)
 };
 
 struct InferLds {
@@ -303,11 +305,11 @@ __global__ __launch_bounds__(kInferThreads) void k_infer(InferArgs a) {
     float lh = kBShift0 + kBScale0 * y[0] + lchi;
     const float env = logf(1.001f * (float)kHc1 * (float)chi);
     bool rate_ok = in_chi && isfinite(lh) && lh <= env;
-    if (!rate_ok) lh = logf(h_rad<float>((float)chi, a.lnh32, TabRange{}));
+    if (!rate_ok) lh = logf(h_rad<float>((float)chi, a.lnh32, a.rg));
     float lhp;
     if (chi < kPairChiMin || gam < 2.0) lhp = -INFINITY;
     else if (chi <= kPairChiMax && isfinite(y[1])) lhp = kBShift1 + kBScale1 * y[1] + lchi - 8.0f / (3.0f * (float)chi);
-    else lhp = logf(h_pair<float>((float)chi, a.L32, TabRange{}));
+    else lhp = logf(h_pair<float>((float)chi, a.L32, a.rg));
     // xi (net A) with residual check against the Hermite CDF table
     reload_barrier();
     forward_nc(S.A, 2, 1, xin(in_chi ? chi : 1.0), (float)(t / kTmax), y);
@@ -316,7 +318,7 @@ __global__ __launch_bounds__(kInferThreads) void k_infer(InferArgs a) {
     bool xi_ok = in_chi && in_u && isfinite(s_hat);
     float xi, om;
     if (xi_ok) {
-      const float x = Grid<float>::pos(lchi, kRadChiMin, kRadChiMax, kRadNChi);
+      const float x = (lchi - (float)a.rg.rad_lnlo) * (float)a.rg.rad_inv;
       int ii = (int)floorf(x);
       ii = ii < 0 ? 0 : (ii > kRadNChi - 2 ? kRadNChi - 2 : ii);
       const float w = x - ii;
@@ -327,7 +329,7 @@ __global__ __launch_bounds__(kInferThreads) void k_infer(InferArgs a) {
       xi = 1.f / (1.f + __expf(-s_hat));
       om = 1.f / (1.f + __expf(s_hat));
     } else {
-      sample_rad<float>(tab, (float)chi, u, urow, xi, om, TabRange{});
+      sample_rad<float>(tab, (float)chi, u, urow, xi, om, a.rg);
     }
     if (valid && (lane >> 4) == 0) {
       a.lnw[i] = (float)((double)lh + log(kRateUnit / gam));
@@ -380,7 +382,8 @@ hipError_t launch_mlp_init(float *theta, int net, uint32_t seed, hipStream_t st)
 hipError_t launch_mlp_grad(int net, const float *theta, float *grad, const double *S64, const double *lnh,
                            const double *L, const float *ext_x, const float *ext_t, const float *ext_m,
                            int64_t nbatch, uint64_t sample0, uint32_t seed, hipStream_t st) {
-  TrainArgs a{net, theta, grad, S64, lnh, L, ext_x, ext_t, ext_m, nbatch, sample0, seed};
+  TrainArgs a{net, theta, grad, S64, lnh, L, ext_x, ext_t, ext_m, nbatch, sample0, seed,
+              make_range(kRadChiMax, kPairChiMax)};
   const int64_t tiles = (nbatch + 15) / 16;
   int64_t blocks = (tiles + 3) / 4;
   if (blocks > 256) blocks = 256;
@@ -418,7 +421,7 @@ hipError_t launch_mlp_sample(qed_ctx *c, const double *chi, const double *gamma,
   InferArgs a{c->mlp_theta[0], c->mlp_theta[1], chi, gamma, id, n, c->params.seed, (uint64_t)step,
               step < 0 ? c->d_step : nullptr,
               c->rad_lnh32, c->pair_L32, c->rad_s0sc, c->rad_chk, c->rad_q16, lnw, xi, lnwp, tol,
-              c->d_counters + cMlpFallbackXi};
+              c->d_counters + cMlpFallbackXi, make_range(kRadChiMax, kPairChiMax)};
   static bool attr = false;
   if (!attr) {
     (void)hipFuncSetAttribute((const void *)k_infer, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(InferLds));

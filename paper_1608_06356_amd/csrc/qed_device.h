@@ -15,6 +15,7 @@ constexpr double kMeC2eV = 510998.95;
 constexpr double kHcEvUm = 1.239841984;
 constexpr double kES = kMeC2eV / kHcEvUm;
 constexpr double kAlpha = 1.0 / 137.035999084;
+constexpr double kInvES = 1.0 / kES;
 constexpr double kRateUnit = kAlpha * kES;          // alpha m c^2 / hbar in omega_0
 constexpr double kPi = 3.14159265358979323846;
 
@@ -80,16 +81,16 @@ __device__ __forceinline__ double chi_lepton(double px, double py, double pz,
                                              double ex, double ey, double ez,
                                              double bx, double by, double bz) {
   const double p2 = px * px + py * py + pz * pz;
-  if (p2 == 0.0) return sqrt(ex * ex + ey * ey + ez * ez) / kES;   // at rest: chi = |E| / E_S
+  if (p2 == 0.0) return sqrt(ex * ex + ey * ey + ez * ez) * kInvES;   // at rest: chi = |E| / E_S
   const double pa = sqrt(p2), g2 = 1.0 + p2, g = sqrt(g2);
-  const double beta = pa / g;
-  const double nx = px / pa, ny = py / pa, nz = pz / pa;
+  const double ipa = 1.0 / pa;
+  const double nx = px * ipa, ny = py * ipa, nz = pz * ipa;
   const double cx = ny * bz - nz * by, cy = nz * bx - nx * bz, cz = nx * by - ny * bx;  // n x B
-  const double f = 1.0 / (g2 * (1.0 + beta));
+  const double f = 1.0 / (g * (g + pa));          // 1 / (gamma^2 (1 + beta))
   const double wx = (ex + cx) - cx * f, wy = (ey + cy) - cy * f, wz = (ez + cz) - cz * f;
   const double ux = ny * wz - nz * wy, uy = nz * wx - nx * wz, uz = nx * wy - ny * wx;  // n x w
   const double ne = nx * ex + ny * ey + nz * ez;
-  return sqrt(g2 * (ux * ux + uy * uy + uz * uz) + ne * ne) / kES;
+  return sqrt(g2 * (ux * ux + uy * uy + uz * uz) + ne * ne) * kInvES;
 }
 
 // Eq. (3) with |v| = 1: chi_ph = gamma_ph / E_S |k^ x (E + k^ x B)|.
@@ -98,11 +99,17 @@ __device__ __forceinline__ double chi_photon(double kx, double ky, double kz,
                                              double bx, double by, double bz) {
   const double g = sqrt(kx * kx + ky * ky + kz * kz);
   if (!(g > 0.0)) return 0.0;
-  const double nx = kx / g, ny = ky / g, nz = kz / g;
+  const double ig = 1.0 / g;
+  const double nx = kx * ig, ny = ky * ig, nz = kz * ig;
   const double wx = ex + (ny * bz - nz * by), wy = ey + (nz * bx - nx * bz), wz = ez + (nx * by - ny * bx);
   const double ux = ny * wz - nz * wy, uy = nz * wx - nx * wz, uz = nx * wy - ny * wx;
-  return g * sqrt(ux * ux + uy * uy + uz * uz) / kES;
+  return g * sqrt(ux * ux + uy * uy + uz * uz) * kInvES;
 }
+
+// Reciprocal: the hardware estimate (1 ulp) in float32, exact division in float64.
+template <typename R> __device__ __forceinline__ R rcp(R x);
+template <> __device__ __forceinline__ float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double rcp<double>(double x) { return 1.0 / x; }
 
 // ---------------------------------------------------------------- push
 // Relativistic Boris rotation (p in m_e c, q in units of e).
@@ -111,10 +118,10 @@ __device__ __forceinline__ void boris(R &px, R &py, R &pz, R ex, R ey, R ez, R b
                                       R q, R dt) {
   const R h = (R)0.5 * q * dt;
   R mx = px + h * ex, my = py + h * ey, mz = pz + h * ez;
-  const R g = sqrt((R)1 + mx * mx + my * my + mz * mz);
-  const R tx = h * bx / g, ty = h * by / g, tz = h * bz / g;
+  const R hg = h * rcp<R>(sqrt((R)1 + mx * mx + my * my + mz * mz));
+  const R tx = hg * bx, ty = hg * by, tz = hg * bz;
   const R ax = mx + (my * tz - mz * ty), ay = my + (mz * tx - mx * tz), az = mz + (mx * ty - my * tx);
-  const R s = (R)2 / ((R)1 + tx * tx + ty * ty + tz * tz);
+  const R s = (R)2 * rcp<R>((R)1 + tx * tx + ty * ty + tz * tz);
   const R sx = s * tx, sy = s * ty, sz = s * tz;
   mx += ay * sz - az * sy;
   my += az * sx - ax * sz;

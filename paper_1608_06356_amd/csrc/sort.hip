@@ -1,6 +1,6 @@
 // Stable reordering of a species by grid cell (nearest node of the quadratic
-// stencil), so that the field gather of neighbouring threads touches
-// neighbouring nodes.  Keys are radix-sorted with rocPRIM (stable), then every
+// stencil, cells grouped in 4x4x4 blocks), so that the field gather of
+// neighbouring threads touches neighbouring nodes.  Keys are radix-sorted with rocPRIM (stable), then every
 // array is gathered into the destination species.  Particle ids, and therefore
 // every random stream, travel with the particles, so the physics is unchanged;
 // only the storage order (and with it the append order) changes.
@@ -12,6 +12,11 @@
 
 namespace qed {
 namespace {
+
+// Cells are grouped in cubes of kBlk^3: the particles of one gather/push
+// workgroup then fill a compact 3-D region, whose stencil box the workgroup
+// stages in LDS.
+constexpr int kBlk = 4;
 
 template <typename R>
 __global__ void k_cell_keys(const R *x, const R *y, const R *z, const int64_t *count, int64_t cap, int nx,
@@ -26,7 +31,10 @@ __global__ void k_cell_keys(const R *x, const R *y, const R *z, const int64_t *c
       jy = jy < 0 ? 0 : (jy >= ny ? jy - ny : jy);
       jz = jz < 0 ? 0 : (jz >= nz ? jz - nz : jz);
       jx = jx >= nx ? nx - 1 : jx; jy = jy >= ny ? ny - 1 : jy; jz = jz >= nz ? nz - 1 : jz;
-      key = (uint32_t)(((int64_t)jz * ny + jy) * nx + jx);
+      // blocks of kBlk^3 cells in z-major order, cells z-major inside a block
+      const int nbx = (nx + kBlk - 1) / kBlk, nby = (ny + kBlk - 1) / kBlk;
+      const uint32_t blk = (uint32_t)(((jz / kBlk) * nby + jy / kBlk) * nbx + jx / kBlk);
+      key = blk * (uint32_t)(kBlk * kBlk * kBlk) + (uint32_t)(((jz % kBlk) * kBlk + jy % kBlk) * kBlk + jx % kBlk);
     }
     keys[i] = key;
     vals[i] = (uint32_t)i;
@@ -58,7 +66,8 @@ hipError_t sort_impl(qed_ctx *c, const qed_fields_t *f, const qed_species_t *s, 
                      (const R *)s->z, s->count, cap, f->nx, f->ny, f->nz, f->dx, f->dy, f->dz, k0, v0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const uint64_t cells = (uint64_t)f->nx * f->ny * f->nz;
+  const uint64_t cells = (uint64_t)((f->nx + kBlk - 1) / kBlk) * ((f->ny + kBlk - 1) / kBlk) *
+                        ((f->nz + kBlk - 1) / kBlk) * (kBlk * kBlk * kBlk);
   unsigned bits = 1;
   while ((1ull << bits) <= cells) ++bits;
   ++bits;   // the all-ones sentinel of unused slots sorts last

@@ -10,6 +10,7 @@
 // Every append is a wave ballot / workgroup scan plus a single-pass decoupled
 // look-back across workgroups, so output order never depends on scheduling.
 #include <hip/hip_runtime.h>
+#include <limits.h>
 #include <math.h>
 
 #include "internal.h"
@@ -33,9 +34,12 @@ struct FieldDev {
   int kind, nx, ny, nz;
   const float *grid;
   double dx, dy, dz;
+  double idx, idy, idz;      // inverse cell sizes
   double E[3], B[3];
   const float *pE[3], *pB[3];
 };
+
+constexpr int kGPThreads = 256, kGPTile = kGPThreads;   // gather/push workgroup = tile
 
 struct ScanDev {
   uint32_t *ticket;
@@ -49,8 +53,8 @@ __device__ __forceinline__ void wrap_coord(R &x, R L) {
 }
 
 template <typename R>
-__device__ __forceinline__ void weights_tsc(R x, R d, int n, int &j, R w[3]) {
-  const R g = x / d;
+__device__ __forceinline__ void weights_tsc(R x, R inv_d, int n, int &j, R w[3]) {
+  const R g = x * inv_d;
   const R jf = floor(g + (R)0.5);
   const R t = g - jf;
   w[0] = (R)0.5 * ((R)0.5 - t) * ((R)0.5 - t);
@@ -66,32 +70,155 @@ __device__ __forceinline__ int wrap_index(int j, int n) {
   return j >= n ? j - n : j;
 }
 
-// Quadratic-spline (TSC) gather on the periodic collocated grid.
+// Quadratic-spline (TSC) stencil of a position: centre node j per axis (in
+// [0, n]; n stands for node 0) and the three weights of nodes j-1, j, j+1.
 template <typename R>
-__device__ __forceinline__ void gather_grid(const FieldDev &f, R x, R y, R z, R F[6]) {
-  int jx, jy, jz;
-  R wx[3], wy[3], wz[3];
-  weights_tsc<R>(x, (R)f.dx, f.nx, jx, wx);
-  weights_tsc<R>(y, (R)f.dy, f.ny, jy, wy);
-  weights_tsc<R>(z, (R)f.dz, f.nz, jz, wz);
+__device__ __forceinline__ void tsc_setup(const FieldDev &f, R x, R y, R z, int j[3], R w[3][3]) {
+  weights_tsc<R>(x, (R)f.idx, f.nx, j[0], w[0]);
+  weights_tsc<R>(y, (R)f.idy, f.ny, j[1], w[1]);
+  weights_tsc<R>(z, (R)f.idz, f.nz, j[2], w[2]);
+}
+
+// TSC gather from the grid in global memory.  Offsets are 32-bit float
+// indices (the API limits a grid to 2^32 floats).
+template <typename R>
+__device__ __forceinline__ void gather_global(const FieldDev &f, const int j[3], const R w[3][3], R F[6]) {
+  uint32_t ox[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) ox[a] = (uint32_t)wrap_index(j[0] + a - 1, f.nx) * 6u;
 #pragma unroll
   for (int c = 0; c < 6; ++c) F[c] = (R)0;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const int iz = wrap_index(jz + c - 1, f.nz);
+    const uint32_t iz = (uint32_t)wrap_index(j[2] + c - 1, f.nz);
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-      const int iy = wrap_index(jy + b - 1, f.ny);
-      const R wyz = wy[b] * wz[c];
-      const float *row = f.grid + ((int64_t)iz * f.ny + iy) * (int64_t)f.nx * 6;
+      const uint32_t iy = (uint32_t)wrap_index(j[1] + b - 1, f.ny);
+      const R wyz = w[1][b] * w[2][c];
+      const uint32_t row = (iz * (uint32_t)f.ny + iy) * (uint32_t)f.nx * 6u;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        const int ix = wrap_index(jx + a - 1, f.nx);
-        const float2 *p2 = reinterpret_cast<const float2 *>(row + (int64_t)ix * 6);
+        const float2 *p2 = reinterpret_cast<const float2 *>(f.grid + (row + ox[a]));
         const float2 v0 = p2[0], v1 = p2[1], v2 = p2[2];
-        const R w = wx[a] * wyz;
-        F[0] += w * (R)v0.x; F[1] += w * (R)v0.y; F[2] += w * (R)v1.x;
-        F[3] += w * (R)v1.y; F[4] += w * (R)v2.x; F[5] += w * (R)v2.y;
+        const R wt = w[0][a] * wyz;
+        F[0] += wt * (R)v0.x; F[1] += wt * (R)v0.y; F[2] += wt * (R)v1.x;
+        F[3] += wt * (R)v1.y; F[4] += wt * (R)v2.x; F[5] += wt * (R)v2.y;
+      }
+    }
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void gather_grid(const FieldDev &f, R x, R y, R z, R F[6]) {
+  int j[3];
+  R w[3][3];
+  tsc_setup<R>(f, x, y, z, j, w);
+  gather_global<R>(f, j, w, F);
+}
+
+// ----------------------------------------------- gather staged through LDS
+// The particles of a workgroup, ordered by cell, usually occupy a compact set
+// of cells.  The workgroup copies the box of grid nodes their stencils touch
+// (the span of their centre nodes, one node wider on each side) into LDS once
+// and every particle reads its 27 nodes from there, which cuts the bytes the
+// vector L1 returns per particle from 27 x 24 to about the box's share.  A
+// workgroup whose box exceeds kBoxCap nodes gathers from global memory.
+constexpr int kBoxCap = 1024;
+
+struct BoxLds {
+  float2 node[kBoxCap * 3];     // 6 floats per node, box order x fastest
+  int ref[3];                   // centre node of the workgroup's first particle
+  int lo[kGPThreads / 64][3], hi[kGPThreads / 64][3];
+  int bmin[3], bdim[3], use;
+};
+
+// j - ref wrapped into [-n/2, n - n/2) (j, ref in [0, n))
+__device__ __forceinline__ int centred(int j, int ref, int n) {
+  int r = j - ref;
+  const int h = n >> 1;
+  if (r >= n - h) r -= n;
+  else if (r < -h) r += n;
+  return r;
+}
+
+// Decides and stages the box; every thread of the workgroup calls it.  live:
+// the thread holds a particle whose stencil j it passes.  Returns whether the
+// box is in LDS, and the thread's centre node relative to the box origin.
+__device__ __forceinline__ bool stage_box(BoxLds &S, const FieldDev &f, bool live, const int j[3], int rel[3]) {
+  const int n3[3] = {f.nx, f.ny, f.nz};
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) S.ref[d] = j[d] == n3[d] ? 0 : j[d];
+  }
+  __syncthreads();
+  int lo[3], hi[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    rel[d] = centred(j[d] == n3[d] ? 0 : j[d], S.ref[d], n3[d]);
+    lo[d] = live ? rel[d] : INT_MAX;
+    hi[d] = live ? rel[d] : INT_MIN;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = min(lo[d], __shfl_xor(lo[d], o, 64));
+      hi[d] = max(hi[d], __shfl_xor(hi[d], o, 64));
+    }
+  }
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) { S.lo[wv][d] = lo[d]; S.hi[wv][d] = hi[d]; }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t vol = 1;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      int l = INT_MAX, h = INT_MIN;
+      for (int k = 0; k < kGPThreads / 64; ++k) { l = min(l, S.lo[k][d]); h = max(h, S.hi[k][d]); }
+      S.bmin[d] = l - 1;
+      S.bdim[d] = h - l + 3;
+      vol *= (int64_t)S.bdim[d];
+    }
+    S.use = vol <= kBoxCap;
+  }
+  __syncthreads();
+  if (!S.use) return false;
+  const int bx = S.bdim[0], bxy = bx * S.bdim[1], vol = bxy * S.bdim[2];
+  for (int p = threadIdx.x; p < vol; p += kGPThreads) {
+    const int pz = p / bxy, q = p - pz * bxy, py = q / bx, px = q - py * bx;
+    const uint32_t gx = (uint32_t)wrap_index(S.ref[0] + S.bmin[0] + px, f.nx);
+    const uint32_t gy = (uint32_t)wrap_index(S.ref[1] + S.bmin[1] + py, f.ny);
+    const uint32_t gz = (uint32_t)wrap_index(S.ref[2] + S.bmin[2] + pz, f.nz);
+    const float2 *g2 = reinterpret_cast<const float2 *>(f.grid + ((gz * (uint32_t)f.ny + gy) * (uint32_t)f.nx + gx) * 6u);
+    const float2 v0 = g2[0], v1 = g2[1], v2 = g2[2];
+    S.node[3 * p] = v0; S.node[3 * p + 1] = v1; S.node[3 * p + 2] = v2;
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) rel[d] -= S.bmin[d] + 1;   // stencil corner (node j-1) in box coordinates
+  __syncthreads();
+  return true;
+}
+
+template <typename R>
+__device__ __forceinline__ void gather_box(const BoxLds &S, const int c0[3], const R w[3][3], R F[6]) {
+  const int bx = S.bdim[0], by = S.bdim[1];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) F[c] = (R)0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const R wyz = w[1][b] * w[2][c];
+      const int row = ((c0[2] + c) * by + (c0[1] + b)) * bx + c0[0];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const float2 v0 = S.node[3 * (row + a)], v1 = S.node[3 * (row + a) + 1], v2 = S.node[3 * (row + a) + 2];
+        const R wt = w[0][a] * wyz;
+        F[0] += wt * (R)v0.x; F[1] += wt * (R)v0.y; F[2] += wt * (R)v1.x;
+        F[3] += wt * (R)v1.y; F[4] += wt * (R)v2.x; F[5] += wt * (R)v2.y;
       }
     }
   }
@@ -122,6 +249,12 @@ __device__ __forceinline__ void count_add(unsigned long long *c, int which, uint
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
   if (lane == 0 && s) atomicAdd(&c[which], (unsigned long long)s);
+}
+
+// Adds the number of lanes of the wave with `set` (one atomic per wave).
+__device__ __forceinline__ void count_flags(unsigned long long *c, int which, bool set) {
+  const uint32_t s = (uint32_t)__popcll(__ballot(set));
+  if ((threadIdx.x & 63) == 0 && s) atomicAdd(&c[which], (unsigned long long)s);
 }
 
 // Workgroup: obtain a tile id from the ticket (thread 0) and broadcast.
@@ -181,7 +314,6 @@ struct GPArgs {
   TabRange rg;
 };
 
-constexpr int kGPThreads = 256, kGPTile = kGPThreads;
 constexpr double kSubstepW = 0.2;     // method I: W Dt / N <= 0.2
 constexpr int kMaxSubsteps = 1024;
 
@@ -204,7 +336,8 @@ __device__ __forceinline__ int method1_next(uint64_t id, uint32_t seed, uint64_t
   return N;
 }
 
-template <typename R, int FK>
+// M1: compiled with the method I generator (a.gen != 0), else optical depth only.
+template <typename R, int FK, bool M1>
 __global__ __launch_bounds__(kGPThreads) void k_gather_push(GPArgs<R> a) {
   __shared__ R lnh_s[kRadNChi];
   for (int k = threadIdx.x; k < kRadNChi; k += blockDim.x) lnh_s[k] = a.lnh[k];
@@ -223,7 +356,21 @@ __global__ __launch_bounds__(kGPThreads) void k_gather_push(GPArgs<R> a) {
   R F[6];
   bool live = i < n;
   R x = 0, y = 0, z = 0;
-  if (live) {
+  if (FK == QED_FIELD_GRID) {
+    __shared__ BoxLds box_s;
+    int j[3] = {0, 0, 0}, rel[3];
+    R w[3][3];
+    if (live) {
+      x = X[i]; y = Y[i]; z = Z[i];
+      tsc_setup<R>(f, x, y, z, j, w);
+    }
+    if (stage_box(box_s, f, live, j, rel)) {
+      if (live) gather_box<R>(box_s, rel, w, F);
+    } else if (live) {
+      gather_global<R>(f, j, w, F);
+    }
+    if (live && !fields_finite<R>(F)) { live = false; nnan = 1; }   // skipped and counted
+  } else if (live) {
     x = X[i]; y = Y[i]; z = Z[i];
     field_at<R>(f, i, x, y, z, F);
     if (!fields_finite<R>(F)) { live = false; nnan = 1; }   // skipped and counted
@@ -233,7 +380,8 @@ __global__ __launch_bounds__(kGPThreads) void k_gather_push(GPArgs<R> a) {
     const double tau = a.sp.tau[i];
     boris<R>(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5], a.q, a.dt);
     const R g = sqrt((R)1 + px * px + py * py + pz * pz);
-    x += px / g * a.dt; y += py / g * a.dt; z += pz / g * a.dt;
+    const R ig = rcp<R>(g), vdt = ig * a.dt;
+    x += px * vdt; y += py * vdt; z += pz * vdt;
     if (FK == QED_FIELD_GRID) {
       wrap_coord<R>(x, (R)(f.dx * f.nx)); wrap_coord<R>(y, (R)(f.dy * f.ny));
       wrap_coord<R>(z, (R)(f.dz * f.nz));
@@ -243,12 +391,12 @@ __global__ __launch_bounds__(kGPThreads) void k_gather_push(GPArgs<R> a) {
     double W = 0.0;
     if (isfinite(chi)) {
       nrange = chi > a.rg.rad_hi;
-      W = kRateUnit * (double)(h_rad<R>((R)chi, lnh_s, a.rg) / g);
+      W = kRateUnit * (double)(h_rad<R, true>((R)chi, lnh_s, a.rg) * ig);
     } else {
       nnan = 1;
     }
     int j0 = 0, nsub = 1;
-    if (a.gen) {
+    if (M1 && a.gen) {
       // method I: first sub-step with an event, if any
       const uint64_t id = a.sp.id[i];
       nsub = method1_nsub(W, a.dtd, a.gen);
@@ -269,14 +417,14 @@ __global__ __launch_bounds__(kGPThreads) void k_gather_push(GPArgs<R> a) {
       r.j0 = j0;
       r.nsub = nsub;
       a.rec[i] = r;
-    } else if (!a.gen) {
+    } else if (!(M1 && a.gen)) {
       a.sp.tau[i] = tau - W * a.dtd;
     }
   }
   const uint64_t bits = __ballot(flag);
   if ((threadIdx.x & 63) == 0 && base + (threadIdx.x & ~63) < n) a.mask[(base + threadIdx.x) >> 6] = bits;
-  count_add(a.counters, cNanChi, nnan);
-  count_add(a.counters, cChiRange, nrange);
+  count_flags(a.counters, cNanChi, nnan != 0);
+  count_flags(a.counters, cChiRange, nrange != 0);
 }
 
 // Ordered emitter list from the ballot mask: each thread owns one 64-bit word
@@ -340,7 +488,7 @@ struct EmitArgs {
   TabRange rg;
 };
 
-constexpr int kEmitThreads = 1024;
+constexpr int kEmitThreads = 512;
 
 template <typename R, typename Tab>
 __device__ void emit_tile(const EmitArgs<R> &a, const Tab &tab, const R *lnh, uint32_t tile,
@@ -542,7 +690,7 @@ __device__ __forceinline__ float mlp_lnh(const mlp::NetLds &B, double chi, bool 
 }
 
 template <int FK>
-__global__ __launch_bounds__(kGPThreads) void k_gather_push_mlp(GPArgs<float> a, MlpDev m) {
+__global__ __launch_bounds__(kGPThreads, 4) void k_gather_push_mlp(GPArgs<float> a, MlpDev m) {
   __shared__ mlp::NetLds B;
   __shared__ float lnh_s[kRadNChi];
   mlp::stage_net(m.thB, mlp::kB, &B, nullptr);
@@ -693,7 +841,7 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
       const float s_hat = mlp::kAShift + mlp::kAScale * yA + lchi + 3.0f * (-log1pf(__expf(-t)));
       bool xi_ok = in_chi && fabsf(t) <= (float)mlp::kTmax && isfinite(s_hat);
       if (xi_ok) {
-        const float xp = Grid<float>::pos(lchi, kRadChiMin, m.rg.rad_hi, kRadNChi);
+        const float xp = (lchi - (float)m.rg.rad_lnlo) * (float)m.rg.rad_inv;
         int ii = (int)floorf(xp);
         ii = ii < 0 ? 0 : (ii > kRadNChi - 2 ? kRadNChi - 2 : ii);
         const float w = xp - ii;
@@ -1107,6 +1255,7 @@ static FieldDev dev_fields(const qed_fields_t *f) {
   if (!f) { d.kind = QED_FIELD_UNIFORM; return d; }
   d.kind = f->kind; d.nx = f->nx; d.ny = f->ny; d.nz = f->nz; d.grid = f->grid;
   d.dx = f->dx; d.dy = f->dy; d.dz = f->dz;
+  if (f->kind == QED_FIELD_GRID) { d.idx = 1.0 / f->dx; d.idy = 1.0 / f->dy; d.idz = 1.0 / f->dz; }
   for (int c = 0; c < 3; ++c) { d.E[c] = f->E[c]; d.B[c] = f->B[c]; d.pE[c] = f->pE[c]; d.pB[c] = f->pB[c]; }
   return d;
 }
@@ -1119,14 +1268,20 @@ static hipError_t zero_scan(qed_ctx *c, int64_t ntiles, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <typename R, bool M1>
+static void launch_gp_kind_m(const GPArgs<R> &a, int kind, unsigned grid, hipStream_t st) {
+  if (kind == QED_FIELD_GRID)
+    hipLaunchKernelGGL((k_gather_push<R, QED_FIELD_GRID, M1>), dim3(grid), dim3(kGPThreads), 0, st, a);
+  else if (kind == QED_FIELD_UNIFORM)
+    hipLaunchKernelGGL((k_gather_push<R, QED_FIELD_UNIFORM, M1>), dim3(grid), dim3(kGPThreads), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_gather_push<R, QED_FIELD_PER_PARTICLE, M1>), dim3(grid), dim3(kGPThreads), 0, st, a);
+}
+
 template <typename R>
 static void launch_gp_kind(const GPArgs<R> &a, int kind, unsigned grid, hipStream_t st) {
-  if (kind == QED_FIELD_GRID)
-    hipLaunchKernelGGL((k_gather_push<R, QED_FIELD_GRID>), dim3(grid), dim3(kGPThreads), 0, st, a);
-  else if (kind == QED_FIELD_UNIFORM)
-    hipLaunchKernelGGL((k_gather_push<R, QED_FIELD_UNIFORM>), dim3(grid), dim3(kGPThreads), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_gather_push<R, QED_FIELD_PER_PARTICLE>), dim3(grid), dim3(kGPThreads), 0, st, a);
+  if (a.gen) launch_gp_kind_m<R, true>(a, kind, grid, st);
+  else launch_gp_kind_m<R, false>(a, kind, grid, st);
 }
 
 static MlpDev mlp_dev(qed_ctx *c) {

@@ -340,10 +340,11 @@ def test_pair_spectrum_and_yield_1e7(pair_table):
 
 def test_sort_by_cell_stable_permutation():
     """qed_sort_by_cell: destination = source permuted by a stable sort of the
-    nearest-node cell index; counts and every array travel together."""
+    nearest-node cell key (4x4x4 blocks in z-major order, cells z-major inside a
+    block); counts and every array travel together."""
     torch, q = need_gpu()
     ctx = q.Context()
-    n, cap, ng, L = 100003, 120000, 32, workloads.BOX_L
+    n, cap, ng, L = 100003, 120000, 30, workloads.BOX_L
     rng = np.random.default_rng(9)
     x = rng.uniform(0, L, (n, 3)).astype(np.float32).astype(np.float64)
     x[:50] = x[50:100]              # repeated cells exercise stability
@@ -359,7 +360,9 @@ def test_sort_by_cell_stable_permutation():
     d = L / ng
     j = np.floor(x / d + 0.5).astype(np.int64)
     j[j >= ng] -= ng
-    key = (j[:, 2] * ng + j[:, 1]) * ng + j[:, 0]
+    nb = (ng + 3) // 4
+    blk = ((j[:, 2] // 4) * nb + j[:, 1] // 4) * nb + j[:, 0] // 4
+    key = blk * 64 + ((j[:, 2] % 4) * 4 + j[:, 1] % 4) * 4 + j[:, 0] % 4
     order = np.argsort(key, kind="stable")
     assert b.n() == n
     np.testing.assert_array_equal(got["id"], ids[order])
