@@ -124,12 +124,13 @@ __device__ __forceinline__ void gather_grid(const FieldDev &f, R x, R y, R z, R 
 // vector L1 returns per particle from 27 x 24 to about the box's share.  A
 // workgroup whose box exceeds kBoxCap nodes gathers from global memory.
 constexpr int kBoxCap = 1024;
+constexpr int kGPWaves = 6;     // LDS allows 6 workgroups of 256 threads per CU
 
 struct BoxLds {
-  float2 node[kBoxCap * 3];     // 6 floats per node, box order x fastest
+  float2 node[kBoxCap * 3];     // 6 floats per node; node (x, y, z) at z * pxy + y * px + x
   int ref[3];                   // centre node of the workgroup's first particle
   int lo[kGPThreads / 64][3], hi[kGPThreads / 64][3];
-  int bmin[3], bdim[3], use;
+  int bad;                      // a particle's stencil left the box (then: global gather)
 };
 
 // j - ref wrapped into [-n/2, n - n/2) (j, ref in [0, n))
@@ -141,78 +142,111 @@ __device__ __forceinline__ int centred(int j, int ref, int n) {
   return r;
 }
 
-// Decides and stages the box; every thread of the workgroup calls it.  live:
-// the thread holds a particle whose stencil j it passes.  Returns whether the
-// box is in LDS, and the thread's centre node relative to the box origin.
-__device__ __forceinline__ bool stage_box(BoxLds &S, const FieldDev &f, bool live, const int j[3], int rel[3]) {
+// Minimum or maximum over the 64 lanes of a wave with DPP moves (quad
+// permutations, half-row and row mirrors, row broadcasts 15 and 31); the
+// result collects in lane 63 and is returned to every lane.
+template <bool Max>
+__device__ __forceinline__ int wave_extreme(int v) {
+  const int id = Max ? INT_MIN : INT_MAX;
+#define QED_DPP_STEP(ctrl, rows)                                                   \
+  {                                                                               \
+    const int t = __builtin_amdgcn_update_dpp(id, v, ctrl, rows, 0xF, false);     \
+    v = Max ? max(v, t) : min(v, t);                                              \
+  }
+  QED_DPP_STEP(0xB1, 0xF)    // quad_perm [1,0,3,2]
+  QED_DPP_STEP(0x4E, 0xF)    // quad_perm [2,3,0,1]
+  QED_DPP_STEP(0x141, 0xF)   // row_half_mirror
+  QED_DPP_STEP(0x140, 0xF)   // row_mirror
+  QED_DPP_STEP(0x142, 0xA)   // row_bcast:15 into rows 1 and 3
+  QED_DPP_STEP(0x143, 0xC)   // row_bcast:31 into rows 2 and 3
+#undef QED_DPP_STEP
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
+// Box of the workgroup.  Every thread calls it; live: the thread holds a
+// particle with stencil centre j.  On success the box is in LDS, rel holds the
+// thread's stencil corner (node j-1) in box coordinates and pit the row and
+// plane pitches (odd, which spreads neighbouring rows and planes over the LDS
+// banks).  Returns false (uniformly) when the box exceeds kBoxCap nodes.  Its
+// first barrier also publishes whatever the caller wrote to LDS before.
+__device__ __forceinline__ bool stage_box(BoxLds &S, const FieldDev &f, bool live, const int j[3], int rel[3],
+                                          int pit[2]) {
   const int n3[3] = {f.nx, f.ny, f.nz};
+  int jj[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) jj[d] = j[d] == n3[d] ? 0 : j[d];
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) S.ref[d] = j[d] == n3[d] ? 0 : j[d];
+    for (int d = 0; d < 3; ++d) S.ref[d] = jj[d];
+    S.bad = 0;
   }
   __syncthreads();
-  int lo[3], hi[3];
+  const int wv = threadIdx.x >> 6;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    rel[d] = centred(j[d] == n3[d] ? 0 : j[d], S.ref[d], n3[d]);
-    lo[d] = live ? rel[d] : INT_MAX;
-    hi[d] = live ? rel[d] : INT_MIN;
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      lo[d] = min(lo[d], __shfl_xor(lo[d], o, 64));
-      hi[d] = max(hi[d], __shfl_xor(hi[d], o, 64));
-    }
-  }
-  const int wv = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) { S.lo[wv][d] = lo[d]; S.hi[wv][d] = hi[d]; }
+    rel[d] = centred(jj[d], S.ref[d], n3[d]);
+    const int lo = wave_extreme<false>(live ? rel[d] : INT_MAX);
+    const int hi = wave_extreme<true>(live ? rel[d] : INT_MIN);
+    if ((threadIdx.x & 63) == 0) { S.lo[wv][d] = lo; S.hi[wv][d] = hi; }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t vol = 1;
+  int bmin[3], bdim[3], ref[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      int l = INT_MAX, h = INT_MIN;
-      for (int k = 0; k < kGPThreads / 64; ++k) { l = min(l, S.lo[k][d]); h = max(h, S.hi[k][d]); }
-      S.bmin[d] = l - 1;
-      S.bdim[d] = h - l + 3;
-      vol *= (int64_t)S.bdim[d];
-    }
-    S.use = vol <= kBoxCap;
+  for (int d = 0; d < 3; ++d) {
+    int l = INT_MAX, h = INT_MIN;
+#pragma unroll
+    for (int k = 0; k < kGPThreads / 64; ++k) { l = min(l, S.lo[k][d]); h = max(h, S.hi[k][d]); }
+    l = __builtin_amdgcn_readfirstlane(l);
+    h = __builtin_amdgcn_readfirstlane(h);
+    ref[d] = __builtin_amdgcn_readfirstlane(S.ref[d]);
+    bmin[d] = l - 1;
+    bdim[d] = h - l + 3;
   }
-  __syncthreads();
-  if (!S.use) return false;
-  const int bx = S.bdim[0], bxy = bx * S.bdim[1], vol = bxy * S.bdim[2];
-  for (int p = threadIdx.x; p < vol; p += kGPThreads) {
-    const int pz = p / bxy, q = p - pz * bxy, py = q / bx, px = q - py * bx;
-    const uint32_t gx = (uint32_t)wrap_index(S.ref[0] + S.bmin[0] + px, f.nx);
-    const uint32_t gy = (uint32_t)wrap_index(S.ref[1] + S.bmin[1] + py, f.ny);
-    const uint32_t gz = (uint32_t)wrap_index(S.ref[2] + S.bmin[2] + pz, f.nz);
+  const int px = bdim[0] | 1, pxy = (px * bdim[1]) | 1;
+  if ((int64_t)pxy * bdim[2] > kBoxCap) return false;
+  // copy the box: node p of the dense enumeration (x fastest) -> (x, y, z)
+  const int bxy = bdim[0] * bdim[1], cnt = bxy * bdim[2];
+  const float inv_bx = 1.0f / (float)bdim[0], inv_bxy = 1.0f / (float)bxy;
+  for (int p = threadIdx.x; p < cnt; p += kGPThreads) {
+    const int z = (int)(((float)p + 0.5f) * inv_bxy);      // exact: p < 2^11, bxy <= 2^10
+    const int q = p - z * bxy;
+    const int y = (int)(((float)q + 0.5f) * inv_bx);
+    const int x = q - y * bdim[0];
+    const uint32_t gx = (uint32_t)wrap_index(ref[0] + bmin[0] + x, f.nx);
+    const uint32_t gy = (uint32_t)wrap_index(ref[1] + bmin[1] + y, f.ny);
+    const uint32_t gz = (uint32_t)wrap_index(ref[2] + bmin[2] + z, f.nz);
     const float2 *g2 = reinterpret_cast<const float2 *>(f.grid + ((gz * (uint32_t)f.ny + gy) * (uint32_t)f.nx + gx) * 6u);
     const float2 v0 = g2[0], v1 = g2[1], v2 = g2[2];
-    S.node[3 * p] = v0; S.node[3 * p + 1] = v1; S.node[3 * p + 2] = v2;
+    const int a = z * pxy + y * px + x;
+    S.node[3 * a] = v0; S.node[3 * a + 1] = v1; S.node[3 * a + 2] = v2;
   }
+  // the stencil of every live particle lies inside the box by construction;
+  // checked anyway, so that the LDS reads below can never leave it
+  bool fits = true;
 #pragma unroll
-  for (int d = 0; d < 3; ++d) rel[d] -= S.bmin[d] + 1;   // stencil corner (node j-1) in box coordinates
+  for (int d = 0; d < 3; ++d) {
+    rel[d] -= bmin[d] + 1;
+    fits = fits && rel[d] >= 0 && rel[d] + 2 < bdim[d];
+  }
+  if (live && !fits) S.bad = 1;
+  pit[0] = px;
+  pit[1] = pxy;
   __syncthreads();
-  return true;
+  return S.bad == 0;
 }
 
 template <typename R>
-__device__ __forceinline__ void gather_box(const BoxLds &S, const int c0[3], const R w[3][3], R F[6]) {
-  const int bx = S.bdim[0], by = S.bdim[1];
+__device__ __forceinline__ void gather_box(const BoxLds &S, const int c0[3], const int pit[2], const R w[3][3],
+                                           R F[6]) {
 #pragma unroll
   for (int c = 0; c < 6; ++c) F[c] = (R)0;
+  const int base = (c0[2] * pit[1] + c0[1] * pit[0]) + c0[0];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
       const R wyz = w[1][b] * w[2][c];
-      const int row = ((c0[2] + c) * by + (c0[1] + b)) * bx + c0[0];
+      const int row = base + c * pit[1] + b * pit[0];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         const float2 v0 = S.node[3 * (row + a)], v1 = S.node[3 * (row + a) + 1], v2 = S.node[3 * (row + a) + 2];
@@ -336,12 +370,16 @@ __device__ __forceinline__ int method1_next(uint64_t id, uint32_t seed, uint64_t
   return N;
 }
 
+// Waves per SIMD the compiler must allow for (bounds the registers): the
+// single-precision grid kernel without method I is the hot one.
+template <typename R, int FK, bool M1> constexpr int gp_waves() {
+  return (sizeof(R) == 4 && FK == QED_FIELD_GRID && !M1) ? kGPWaves : 1;
+}
+
 // M1: compiled with the method I generator (a.gen != 0), else optical depth only.
 template <typename R, int FK, bool M1>
-__global__ __launch_bounds__(kGPThreads) void k_gather_push(GPArgs<R> a) {
+__global__ __launch_bounds__(kGPThreads, (gp_waves<R, FK, M1>())) void k_gather_push(GPArgs<R> a) {
   __shared__ R lnh_s[kRadNChi];
-  for (int k = threadIdx.x; k < kRadNChi; k += blockDim.x) lnh_s[k] = a.lnh[k];
-  __syncthreads();
   const int64_t tile = (int64_t)(blockIdx.x % kXcds) * a.tpx + blockIdx.x / kXcds;
   const int64_t n = *a.sp.count;
   const int64_t base = tile * kGPTile;
@@ -355,29 +393,34 @@ __global__ __launch_bounds__(kGPThreads) void k_gather_push(GPArgs<R> a) {
   uint32_t nnan = 0, nrange = 0;
   R F[6];
   bool live = i < n;
-  R x = 0, y = 0, z = 0;
+  // every load of the particle is issued up front, to overlap with the staging
+  R x = 0, y = 0, z = 0, px = 0, py = 0, pz = 0;
+  double tau = 0.0;
+  if (live) {
+    x = X[i]; y = Y[i]; z = Z[i];
+    px = PX[i]; py = PY[i]; pz = PZ[i];
+    tau = a.sp.tau[i];
+  }
+  for (int k = threadIdx.x; k < kRadNChi; k += blockDim.x) lnh_s[k] = a.lnh[k];
   if (FK == QED_FIELD_GRID) {
     __shared__ BoxLds box_s;
-    int j[3] = {0, 0, 0}, rel[3];
+    int j[3] = {0, 0, 0}, rel[3], pit[2];
     R w[3][3];
-    if (live) {
-      x = X[i]; y = Y[i]; z = Z[i];
-      tsc_setup<R>(f, x, y, z, j, w);
-    }
-    if (stage_box(box_s, f, live, j, rel)) {
-      if (live) gather_box<R>(box_s, rel, w, F);
+    if (live) tsc_setup<R>(f, x, y, z, j, w);
+    if (stage_box(box_s, f, live, j, rel, pit)) {   // its barriers also publish lnh_s
+      if (live) gather_box<R>(box_s, rel, pit, w, F);
     } else if (live) {
       gather_global<R>(f, j, w, F);
     }
     if (live && !fields_finite<R>(F)) { live = false; nnan = 1; }   // skipped and counted
-  } else if (live) {
-    x = X[i]; y = Y[i]; z = Z[i];
-    field_at<R>(f, i, x, y, z, F);
-    if (!fields_finite<R>(F)) { live = false; nnan = 1; }   // skipped and counted
+  } else {
+    __syncthreads();
+    if (live) {
+      field_at<R>(f, i, x, y, z, F);
+      if (!fields_finite<R>(F)) { live = false; nnan = 1; }   // skipped and counted
+    }
   }
   if (live) {
-    R px = PX[i], py = PY[i], pz = PZ[i];
-    const double tau = a.sp.tau[i];
     boris<R>(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5], a.q, a.dt);
     const R g = sqrt((R)1 + px * px + py * py + pz * pz);
     const R ig = rcp<R>(g), vdt = ig * a.dt;
