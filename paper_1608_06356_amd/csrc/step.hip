@@ -285,6 +285,36 @@ __device__ __forceinline__ void count_add(unsigned long long *c, int which, uint
   if (lane == 0 && s) atomicAdd(&c[which], (unsigned long long)s);
 }
 
+// Sum over the 64 lanes of a wave with DPP moves (the pattern of
+// wave_extreme); every lane gets the total.
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#define QED_DPP_ADD(ctrl, rows) v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, ctrl, rows, 0xF, false);
+  QED_DPP_ADD(0xB1, 0xF)    // quad_perm [1,0,3,2]
+  QED_DPP_ADD(0x4E, 0xF)    // quad_perm [2,3,0,1]
+  QED_DPP_ADD(0x141, 0xF)   // row_half_mirror
+  QED_DPP_ADD(0x140, 0xF)   // row_mirror
+  QED_DPP_ADD(0x142, 0xA)   // row_bcast:15 into rows 1 and 3
+  QED_DPP_ADD(0x143, 0xC)   // row_bcast:31 into rows 2 and 3
+#undef QED_DPP_ADD
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Event counts of a workgroup gather in LDS (one LDS atomic per wave) and reach
+// the device counters once, when the workgroup ends: a device atomic per wave on
+// the same few counter words serialises at the L2 when thousands of waves add
+// at once.  Zero the LDS words before the workgroup's first barrier.
+__device__ __forceinline__ void count_lds(uint32_t *c, int which, uint32_t v) {
+  const uint32_t s = wave_sum(v);
+  if ((threadIdx.x & 63) == 0 && s) atomicAdd(&c[which], s);
+}
+__device__ __forceinline__ void count_zero(uint32_t *c) {
+  if (threadIdx.x < cNumCounters) c[threadIdx.x] = 0;
+}
+__device__ __forceinline__ void count_flush(const uint32_t *c, unsigned long long *g) {
+  __syncthreads();
+  if (threadIdx.x < cNumCounters && c[threadIdx.x]) atomicAdd(&g[threadIdx.x], (unsigned long long)c[threadIdx.x]);
+}
+
 // Adds the number of lanes of the wave with `set` (one atomic per wave).
 __device__ __forceinline__ void count_flags(unsigned long long *c, int which, bool set) {
   const uint32_t s = (uint32_t)__popcll(__ballot(set));
@@ -533,10 +563,10 @@ struct EmitArgs {
 
 constexpr int kEmitThreads = 512;
 
-template <typename R, typename Tab>
+template <typename R, bool M1, typename Tab>
 __device__ void emit_tile(const EmitArgs<R> &a, const Tab &tab, const R *lnh, uint32_t tile,
                           uint32_t *scan_s, uint64_t *off_s, int64_t n_em, int64_t ph_count0,
-                          uint64_t id0) {
+                          uint64_t id0, uint32_t *cnt) {
   const int64_t r = (int64_t)tile * kEmitThreads + threadIdx.x;
   const bool valid = r < n_em;
   R gph[kKmaxMax];
@@ -586,7 +616,7 @@ __device__ void emit_tile(const EmitArgs<R> &a, const Tab &tab, const R *lnh, ui
       }
       return u;
     };
-    if (a.gen) {
+    if (M1 && a.gen) {
       // method I: at most one event per sub-step, W Dt / N > r_1
       const int N = rc.nsub;
       int j = rc.j0, done = 0;
@@ -611,13 +641,13 @@ __device__ void emit_tile(const EmitArgs<R> &a, const Tab &tab, const R *lnh, ui
         rem -= tau / W;
       }
     }
-    if (!a.gen) a.lep.tau[i] = tau - W * rem;
+    if (!(M1 && a.gen)) a.lep.tau[i] = tau - W * rem;
     if (recoiled) { PX[i] = px; PY[i] = py; PZ[i] = pz; }
   }
-  count_add(a.counters, cEvents, nev);
-  count_add(a.counters, cRejected, nrej);
-  count_add(a.counters, cCapped, ncap);
-  count_add(a.counters, cPhotons, nacc);
+  count_lds(cnt, cEvents, nev);
+  count_lds(cnt, cRejected, nrej);
+  count_lds(cnt, cCapped, ncap);
+  count_lds(cnt, cPhotons, nacc);
 
   uint32_t total;
   const uint32_t off = block_exclusive(nacc, scan_s, &total);
@@ -640,7 +670,7 @@ __device__ void emit_tile(const EmitArgs<R> &a, const Tab &tab, const R *lnh, ui
       }
     }
   }
-  count_add(a.counters, cDropped, ndrop);
+  count_lds(cnt, cDropped, ndrop);
   const int64_t last = (n_em - 1) / kEmitThreads;
   if ((int64_t)tile == last && threadIdx.x == 0) {
     const int64_t tot = (int64_t)(toff + total);
@@ -650,6 +680,7 @@ __device__ void emit_tile(const EmitArgs<R> &a, const Tab &tab, const R *lnh, ui
 }
 
 // float path: 16-bit quantile table + float32 ln h staged in LDS
+template <bool M1>
 __global__ __launch_bounds__(kEmitThreads) void k_emit_f32(EmitArgs<float> a) {
   __shared__ uint4 q_s[kRadNChi * kNU / 8];
   __shared__ float s0sc_s[2 * kRadNChi];
@@ -658,6 +689,8 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_f32(EmitArgs<float> a) {
   __shared__ uint32_t tile_s;
   __shared__ uint64_t off_s;
   __shared__ int64_t hdr_s[3];
+  __shared__ uint32_t cnt_s[cNumCounters];
+  count_zero(cnt_s);
   if (threadIdx.x == 0) { hdr_s[0] = *a.n_emit; hdr_s[1] = *a.ph.count; hdr_s[2] = (int64_t)*a.next_id; }
   __syncthreads();
   const int64_t n_em = hdr_s[0], ph0 = hdr_s[1];
@@ -671,17 +704,21 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_f32(EmitArgs<float> a) {
   while (true) {
     const uint32_t tile = next_tile(a.sc.ticket, &tile_s);
     if ((int64_t)tile * kEmitThreads >= n_em) break;
-    emit_tile<float>(a, tab, lnh_s, tile, scan_s, &off_s, n_em, ph0, id0);
+    emit_tile<float, M1>(a, tab, lnh_s, tile, scan_s, &off_s, n_em, ph0, id0, cnt_s);
   }
+  count_flush(cnt_s, a.counters);
 }
 
 // double path: float64 master tables read through the caches
+template <bool M1>
 __global__ __launch_bounds__(kEmitThreads) void k_emit_f64(EmitArgs<double> a) {
   __shared__ double lnh_s[kRadNChi];
   __shared__ uint32_t scan_s[16];
   __shared__ uint32_t tile_s;
   __shared__ uint64_t off_s;
   __shared__ int64_t hdr_s[3];
+  __shared__ uint32_t cnt_s[cNumCounters];
+  count_zero(cnt_s);
   if (threadIdx.x == 0) { hdr_s[0] = *a.n_emit; hdr_s[1] = *a.ph.count; hdr_s[2] = (int64_t)*a.next_id; }
   __syncthreads();
   const int64_t n_em = hdr_s[0], ph0 = hdr_s[1];
@@ -692,8 +729,9 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_f64(EmitArgs<double> a) {
   while (true) {
     const uint32_t tile = next_tile(a.sc.ticket, &tile_s);
     if ((int64_t)tile * kEmitThreads >= n_em) break;
-    emit_tile<double>(a, tab, lnh_s, tile, scan_s, &off_s, n_em, ph0, id0);
+    emit_tile<double, M1>(a, tab, lnh_s, tile, scan_s, &off_s, n_em, ph0, id0, cnt_s);
   }
+  count_flush(cnt_s, a.counters);
 }
 
 // ============================================== surrogate variants (float32)
@@ -824,6 +862,8 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
   __shared__ uint32_t tile_s;
   __shared__ uint64_t off_s;
   __shared__ int64_t hdr_s[3];
+  __shared__ uint32_t cnt_s[cNumCounters];
+  count_zero(cnt_s);
   if (threadIdx.x == 0) { hdr_s[0] = *a.n_emit; hdr_s[1] = *a.ph.count; hdr_s[2] = (int64_t)*a.next_id; }
   __syncthreads();
   const int64_t n_em = hdr_s[0], ph0 = hdr_s[1];
@@ -953,12 +993,12 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
       a.lep.tau[i] = tau - W * rem;
       if (recoiled) { ((float *)a.lep.px)[i] = px; ((float *)a.lep.py)[i] = py; ((float *)a.lep.pz)[i] = pz; }
     }
-    count_add(a.counters, cEvents, nev);
-    count_add(a.counters, cRejected, nrej);
-    count_add(a.counters, cCapped, ncap);
-    count_add(a.counters, cPhotons, nacc);
-    count_add(a.counters, cMlpFallbackXi, nfx);
-    count_add(a.counters, cMlpFallbackRate, nfr);
+    count_lds(cnt_s, cEvents, nev);
+    count_lds(cnt_s, cRejected, nrej);
+    count_lds(cnt_s, cCapped, ncap);
+    count_lds(cnt_s, cPhotons, nacc);
+    count_lds(cnt_s, cMlpFallbackXi, nfx);
+    count_lds(cnt_s, cMlpFallbackRate, nfr);
     uint32_t total;
     const uint32_t off = block_exclusive(nacc, scan_s, &total);
     const uint64_t toff = tile_offset(tile, total, a.sc.status, a.counters, &off_s);
@@ -980,7 +1020,7 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
         }
       }
     }
-    count_add(a.counters, cDropped, ndrop);
+    count_lds(cnt_s, cDropped, ndrop);
     const int64_t last = (n_em - 1) / kEmitMlpThreads;
     if ((int64_t)tile == last && threadIdx.x == 0) {
       const int64_t tot = (int64_t)(toff + total);
@@ -988,6 +1028,7 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
       *a.next_id = id0 + (uint64_t)tot;
     }
   }
+  count_flush(cnt_s, a.counters);
 }
 
 // ================================================================ pairs
@@ -1017,7 +1058,7 @@ constexpr int kPairThreads = 1024;
 template <typename R, typename Tab>
 __device__ void pair_tile(const PairArgs<R> &a, const Tab &tab, const R *L, uint32_t tile,
                           uint32_t *scan_s, uint64_t *off_s, int64_t n, int64_t e0, int64_t p0,
-                          uint64_t id0) {
+                          uint64_t id0, uint32_t *cnt) {
   const int64_t i = (int64_t)tile * kPairThreads + threadIdx.x;
   uint32_t ev = 0, nrange = 0, nnan = 0;
   R x = 0, y = 0, z = 0, kxh = 0, kyh = 0, kzh = 0, ge = 0, gpos = 0;
@@ -1064,9 +1105,9 @@ __device__ void pair_tile(const PairArgs<R> &a, const Tab &tab, const R *L, uint
       a.ph.tau[i] = tau - W * a.dtd;
     }
   }
-  count_add(a.counters, cChiRange, nrange);
-  count_add(a.counters, cNanChi, nnan);
-  count_add(a.counters, cPairs, ev);
+  count_lds(cnt, cChiRange, nrange);
+  count_lds(cnt, cNanChi, nnan);
+  count_lds(cnt, cPairs, ev);
   uint32_t total;
   const uint32_t off = block_exclusive(ev, scan_s, &total);
   const uint64_t toff = tile_offset(tile, total, a.sc.status, a.counters, off_s);
@@ -1086,7 +1127,7 @@ __device__ void pair_tile(const PairArgs<R> &a, const Tab &tab, const R *L, uint
       ndrop = 2;
     }
   }
-  count_add(a.counters, cDropped, ndrop);
+  count_lds(cnt, cDropped, ndrop);
   const int64_t last = (n - 1) / kPairThreads;
   if ((int64_t)tile == last && threadIdx.x == 0) {
     const int64_t tot = (int64_t)(toff + total);
@@ -1105,6 +1146,8 @@ __global__ __launch_bounds__(kPairThreads) void k_pairs_f32(PairArgs<float> a) {
   __shared__ uint32_t tile_s;
   __shared__ uint64_t off_s;
   __shared__ int64_t hdr_s[4];
+  __shared__ uint32_t cnt_s[cNumCounters];
+  count_zero(cnt_s);
   if (threadIdx.x == 0) {
     hdr_s[0] = *a.ph.count; hdr_s[1] = *a.el.count; hdr_s[2] = *a.po.count;
     hdr_s[3] = (int64_t)*a.next_id;
@@ -1121,8 +1164,9 @@ __global__ __launch_bounds__(kPairThreads) void k_pairs_f32(PairArgs<float> a) {
   while (true) {
     const uint32_t tile = next_tile(a.sc.ticket, &tile_s);
     if ((int64_t)tile * kPairThreads >= n) break;
-    pair_tile<float>(a, tab, L_s, tile, scan_s, &off_s, n, e0, p0, id0);
+    pair_tile<float>(a, tab, L_s, tile, scan_s, &off_s, n, e0, p0, id0, cnt_s);
   }
+  count_flush(cnt_s, a.counters);
 }
 
 __global__ __launch_bounds__(kPairThreads) void k_pairs_f64(PairArgs<double> a) {
@@ -1131,6 +1175,8 @@ __global__ __launch_bounds__(kPairThreads) void k_pairs_f64(PairArgs<double> a) 
   __shared__ uint32_t tile_s;
   __shared__ uint64_t off_s;
   __shared__ int64_t hdr_s[4];
+  __shared__ uint32_t cnt_s[cNumCounters];
+  count_zero(cnt_s);
   if (threadIdx.x == 0) {
     hdr_s[0] = *a.ph.count; hdr_s[1] = *a.el.count; hdr_s[2] = *a.po.count;
     hdr_s[3] = (int64_t)*a.next_id;
@@ -1144,8 +1190,9 @@ __global__ __launch_bounds__(kPairThreads) void k_pairs_f64(PairArgs<double> a) 
   while (true) {
     const uint32_t tile = next_tile(a.sc.ticket, &tile_s);
     if ((int64_t)tile * kPairThreads >= n) break;
-    pair_tile<double>(a, tab, L_s, tile, scan_s, &off_s, n, e0, p0, id0);
+    pair_tile<double>(a, tab, L_s, tile, scan_s, &off_s, n, e0, p0, id0, cnt_s);
   }
+  count_flush(cnt_s, a.counters);
 }
 
 // ============================================================== compact
@@ -1153,57 +1200,64 @@ constexpr int kCThreads = 256, kCItems = 4, kCTile = kCThreads * kCItems;
 
 template <typename R>
 __global__ __launch_bounds__(kCThreads) void k_compact(SpeciesDev sp, ScanDev sc,
-                                                       unsigned long long *counters, const int64_t *killed) {
+                                                       unsigned long long *counters, int64_t *killed) {
   __shared__ uint32_t scan_s[16];
   __shared__ uint32_t tile_s;
   __shared__ uint64_t off_s;
   // killed: particles marked dead since the last compaction of this species, when
   // known (pair creation keeps it); nothing to do if none
   if (killed && *killed == 0) return;
-  const uint32_t tile = next_tile(sc.ticket, &tile_s);
   const int64_t n = *sp.count;
-  const int64_t base = (int64_t)tile * kCTile;
-  if (base >= n) return;
   R *A[6] = {(R *)sp.x, (R *)sp.y, (R *)sp.z, (R *)sp.px, (R *)sp.py, (R *)sp.pz};
-  R v[kCItems][6];
-  double tau[kCItems];
-  uint64_t id[kCItems];
-  uint32_t alive = 0, na = 0;
-  const int64_t i0 = base + (int64_t)threadIdx.x * kCItems;
-#pragma unroll
-  for (int it = 0; it < kCItems; ++it) {
-    const int64_t i = i0 + it;
-    id[it] = kDeadId;
-    if (i < n) {
-#pragma unroll
-      for (int c = 0; c < 6; ++c) v[it][c] = A[c][i];
-      tau[it] = sp.tau[i];
-      id[it] = sp.id[i];
+  while (true) {
+    const uint32_t tile = next_tile(sc.ticket, &tile_s);
+    const int64_t base = (int64_t)tile * kCTile;
+    if (base >= n) {
+      if (tile == 0 && killed && threadIdx.x == 0) *killed = 0;
+      break;
     }
-    if (id[it] != kDeadId) { alive |= 1u << it; ++na; }
-  }
-  // every load of the tile has returned before its count is published: later
-  // tiles may overwrite these elements as soon as they see the count
-  __builtin_amdgcn_s_waitcnt(0);
-  uint32_t total;
-  const uint32_t off = block_exclusive(na, scan_s, &total);
-  const uint64_t toff = tile_offset(tile, total, sc.status, counters, &off_s);
-  uint64_t r = toff + off;
+    R v[kCItems][6];
+    double tau[kCItems];
+    uint64_t id[kCItems];
+    uint32_t alive = 0, na = 0;
+    const int64_t i0 = base + (int64_t)threadIdx.x * kCItems;
 #pragma unroll
-  for (int it = 0; it < kCItems; ++it) {
-    if (alive & (1u << it)) {
+    for (int it = 0; it < kCItems; ++it) {
+      const int64_t i = i0 + it;
+      id[it] = kDeadId;
+      if (i < n) {
 #pragma unroll
-      for (int c = 0; c < 6; ++c) A[c][r] = v[it][c];
-      sp.tau[r] = tau[it];
-      sp.id[r] = id[it];
-      ++r;
+        for (int c = 0; c < 6; ++c) v[it][c] = A[c][i];
+        tau[it] = sp.tau[i];
+        id[it] = sp.id[i];
+      }
+      if (id[it] != kDeadId) { alive |= 1u << it; ++na; }
     }
-  }
-  const int64_t last = (n - 1) / kCTile;
-  if ((int64_t)tile == last && threadIdx.x == 0) {
-    const int64_t nn = (int64_t)(toff + total);
-    atomicAdd(&counters[cCompacted], (unsigned long long)(n - nn));
-    *sp.count = nn;
+    // every load of the tile has returned before its count is published: later
+    // tiles may overwrite these elements as soon as they see the count
+    __builtin_amdgcn_s_waitcnt(0);
+    uint32_t total;
+    const uint32_t off = block_exclusive(na, scan_s, &total);
+    const uint64_t toff = tile_offset(tile, total, sc.status, counters, &off_s);
+    uint64_t r = toff + off;
+#pragma unroll
+    for (int it = 0; it < kCItems; ++it) {
+      if (alive & (1u << it)) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) A[c][r] = v[it][c];
+        sp.tau[r] = tau[it];
+        sp.id[r] = id[it];
+        ++r;
+      }
+    }
+    const int64_t last = (n - 1) / kCTile;
+    if ((int64_t)tile == last && threadIdx.x == 0) {
+      // every tile has been claimed: workgroups that start later find no tile
+      const int64_t nn = (int64_t)(toff + total);
+      atomicAdd(&counters[cCompacted], (unsigned long long)(n - nn));
+      *sp.count = nn;
+      if (killed) *killed = 0;
+    }
   }
 }
 
@@ -1406,13 +1460,15 @@ hipError_t launch_emit(qed_ctx *c, const qed_species_t *lep, const qed_species_t
                       c->rad_s0sc, c->em_idx, (const EmRec<float> *)c->em_rec, c->d_n_emit,
                       c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, dstep, sc,
                       c->d_counters, gen_mode(c), c->em_dt, c->range};
-    hipLaunchKernelGGL(k_emit_f32, dim3(grid), dim3(kEmitThreads), 0, st, a);
+    if (a.gen) hipLaunchKernelGGL(k_emit_f32<true>, dim3(grid), dim3(kEmitThreads), 0, st, a);
+    else hipLaunchKernelGGL(k_emit_f32<false>, dim3(grid), dim3(kEmitThreads), 0, st, a);
   } else {
     EmitArgs<double> a{dev_species(lep), dev_species(ph), c->rad_lnh64, c->rad_S64, c->rad_q16,
                        c->rad_s0sc, c->em_idx, (const EmRec<double> *)c->em_rec, c->d_n_emit,
                        c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, dstep, sc,
                        c->d_counters, gen_mode(c), c->em_dt, c->range};
-    hipLaunchKernelGGL(k_emit_f64, dim3(grid), dim3(kEmitThreads), 0, st, a);
+    if (a.gen) hipLaunchKernelGGL(k_emit_f64<true>, dim3(grid), dim3(kEmitThreads), 0, st, a);
+    else hipLaunchKernelGGL(k_emit_f64<false>, dim3(grid), dim3(kEmitThreads), 0, st, a);
   }
   return hipGetLastError();
 }
@@ -1448,16 +1504,22 @@ hipError_t launch_compact(qed_ctx *c, const qed_species_t *sp, hipStream_t st) {
   if (e != hipSuccess) return e;
   const ScanDev sc{c->d_ticket, c->d_status};
   const bool track = (c->params.flags & QED_FLAG_TRACK_DEAD) != 0;
-  const int64_t *killed = (track && c->killed_owner == sp->x) ? c->d_killed : nullptr;
+  const bool owner = track && c->killed_owner == sp->x;
+  int64_t *killed = owner ? c->d_killed : nullptr;
+  // persistent workgroups take tiles from the ticket; with nothing killed they
+  // all return at once
+  const int64_t wgs = (int64_t)c->n_cu * 8;
+  const unsigned grid = (unsigned)(ntiles < wgs ? ntiles : wgs);
   if (sp->dtype == QED_F32)
-    hipLaunchKernelGGL(k_compact<float>, dim3((unsigned)ntiles), dim3(kCThreads), 0, st,
-                       dev_species(sp), sc, c->d_counters, killed);
+    hipLaunchKernelGGL(k_compact<float>, dim3(grid), dim3(kCThreads), 0, st, dev_species(sp), sc, c->d_counters,
+                       killed);
   else
-    hipLaunchKernelGGL(k_compact<double>, dim3((unsigned)ntiles), dim3(kCThreads), 0, st,
-                       dev_species(sp), sc, c->d_counters, killed);
+    hipLaunchKernelGGL(k_compact<double>, dim3(grid), dim3(kCThreads), 0, st, dev_species(sp), sc,
+                       c->d_counters, killed);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  // the species now has no dead particles
-  hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, st, c->d_killed, (int64_t)0);
+  // the species now has no dead particles (the kernel clears the count of the
+  // species it tracks already)
+  if (!owner) hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, st, c->d_killed, (int64_t)0);
   c->killed_owner = sp->x;
   return hipGetLastError();
 }
