@@ -1281,20 +1281,22 @@ __global__ void k_init_tau(const uint64_t *id, double *tau, const int64_t *count
   }
 }
 
+// The node values depend on x only through cos x and sin x: each thread owns
+// node columns ix and writes them for a stride of rows (iy, iz).
 __global__ void k_standing_wave(float *grid, int n, double dx, double a0, double t0, double dt_step,
                                 const int64_t *d_step) {
-  const int64_t total = (int64_t)n * n * n;
+  const int64_t rows = (int64_t)n * n;
   const double t = d_step ? t0 + dt_step * (double)*d_step : t0;
   const double ct = cos(t), st = sin(t);
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int ix = (int)(i % n);
+  for (int ix = threadIdx.x; ix < n; ix += blockDim.x) {
     const double x = ix * dx;
     const double ca = a0 * cos(x), sa = a0 * sin(x);
-    float2 *o = reinterpret_cast<float2 *>(grid + i * 6);
-    o[0] = make_float2(0.0f, (float)(ca * ct));
-    o[1] = make_float2((float)(ca * st), 0.0f);
-    o[2] = make_float2((float)(sa * ct), (float)(sa * st));
+    const float2 v0 = make_float2(0.0f, (float)(ca * ct)), v1 = make_float2((float)(ca * st), 0.0f),
+                 v2 = make_float2((float)(sa * ct), (float)(sa * st));
+    for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+      float2 *o = reinterpret_cast<float2 *>(grid + (r * n + ix) * 6);
+      o[0] = v0; o[1] = v1; o[2] = v2;
+    }
   }
 }
 
@@ -1534,11 +1536,11 @@ hipError_t launch_init_tau(qed_ctx *c, const qed_species_t *sp, int64_t step, hi
 
 hipError_t launch_standing_wave(float *grid, int n, double L, double a0, double t0, double dt_step,
                                 const int64_t *d_step, hipStream_t st) {
-  const int64_t total = (int64_t)n * n * n;
-  int64_t blocks = (total + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(k_standing_wave, dim3((unsigned)blocks), dim3(256), 0, st, grid, n, L / n, a0, t0, dt_step,
-                     d_step);
+  const int64_t rows = (int64_t)n * n;
+  const int threads = n >= 256 ? 256 : (n + 63) / 64 * 64;
+  const int64_t blocks = rows < 8192 ? rows : 8192;
+  hipLaunchKernelGGL(k_standing_wave, dim3((unsigned)blocks), dim3(threads), 0, st, grid, n, L / n, a0, t0,
+                     dt_step, d_step);
   return hipGetLastError();
 }
 
