@@ -218,9 +218,10 @@ QED_API int qed_fill_standing_wave_at_step(qed_ctx_t ctx, float *grid, int n, do
    (charge = -1 electron, +1 positron), x^{n+1} = x^n + v dt (wrapped into a GRID
    box), chi_e from Eq. (2) in float64, W = alpha E_S h(chi)/gamma, and the optical
    depth decrement tau -= W dt.  Particles whose optical depth runs out within the
-   step are written, in index order, to the context's emitter list with the fields
-   they saw and the time left after their first event; qed_emit_photons finishes
-   them.  Fails with QED_ERR_STATE if the tables are missing. */
+   step are flagged in the context's emitter mask (one bit per particle) and their
+   record (fields seen, chi, W, time left after the first event) is kept at their
+   index; qed_emit_photons lists them in index order and finishes them.  One kernel
+   launch.  Fails with QED_ERR_STATE if the tables are missing. */
 QED_API int qed_gather_push(qed_ctx_t ctx, const qed_fields_t *fields, qed_species_t *leptons,
                     int charge, double dt, int64_t step, void *stream);
 

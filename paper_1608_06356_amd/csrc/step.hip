@@ -1423,24 +1423,23 @@ hipError_t launch_gather_push(qed_ctx *c, const qed_fields_t *f, const qed_speci
                      (EmRec<double> *)c->em_rec, tpx, c->d_counters, gen, c->params.seed, (uint64_t)step, dstep, c->range};
     launch_gp_kind<double>(a, f->kind, grid, st);
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  // ordered emitter list
-  const int64_t etiles = (sp->capacity + kEITile - 1) / kEITile;
-  if ((e = zero_scan(c, etiles, st)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_emit_index, dim3((unsigned)etiles), dim3(kEIThreads), 0, st, c->em_mask, sp->count,
-                     c->em_idx, c->d_n_emit, ScanDev{c->d_ticket, c->d_status}, c->d_counters);
   return hipGetLastError();
 }
 
 hipError_t launch_emit(qed_ctx *c, const qed_species_t *lep, const qed_species_t *ph, int64_t step,
                        hipStream_t st) {
   const bool use_mlp = lep->dtype == QED_F32 && (c->params.flags & QED_FLAG_SURROGATE);
+  // ordered emitter list from the mask of the last gather/push
+  const int64_t etiles = (lep->capacity + kEITile - 1) / kEITile;
+  hipError_t e = zero_scan(c, etiles, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_emit_index, dim3((unsigned)etiles), dim3(kEIThreads), 0, st, c->em_mask, lep->count,
+                     c->em_idx, c->d_n_emit, ScanDev{c->d_ticket, c->d_status}, c->d_counters);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   // the scan needs one zeroed status word per tile of this kernel's tile size
   const int tile = use_mlp ? kEmitMlpThreads : kEmitThreads;
   const int64_t ntiles = (lep->capacity + tile - 1) / tile;
-  hipError_t e = zero_scan(c, ntiles, st);
-  if (e != hipSuccess) return e;
+  if ((e = zero_scan(c, ntiles, st)) != hipSuccess) return e;
   const ScanDev sc{c->d_ticket, c->d_status};
   const int recoil = (c->params.flags & QED_FLAG_NO_RECOIL) ? 0 : 1;
   const unsigned grid = (unsigned)(ntiles < c->n_cu ? ntiles : c->n_cu);
