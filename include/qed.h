@@ -294,7 +294,8 @@ QED_API int qed_sample(qed_ctx_t ctx, const double *chi, const double *gamma, co
    are counted (mlp_fallback_*).
    With QED_FLAG_SURROGATE in the context parameters, qed_gather_push and
    qed_emit_photons on float32 species use the same nets and checks in place of
-   the table lookups (the nets must be trained or loaded first). */
+   the table lookups.  The surrogate paths need both nets, trained or loaded
+   (QED_ERR_STATE otherwise). */
 QED_API int qed_surrogate_params(int net);
 QED_API int qed_surrogate_train(qed_ctx_t ctx, const qed_train_spec_t *spec, void *stream);
 QED_API int qed_surrogate_io(qed_ctx_t ctx, int net, float *host, size_t bytes, int direction);

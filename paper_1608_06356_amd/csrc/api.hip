@@ -394,7 +394,9 @@ int qed_surrogate_train(qed_ctx_t c, const qed_train_spec_t *spec, void *st) {
     }
     if (e != hipSuccess) return hip_fail(c, e, "surrogate_train");
   }
-  if ((spec->nets & 3) == 3 || (c->mlp_ready && spec->nets)) c->mlp_ready = true;
+  for (int k = 0; k < 2; ++k)
+    if (spec->nets & (1 << k)) c->mlp_have[k] = true;
+  c->mlp_ready = c->mlp_have[0] && c->mlp_have[1];
   return QED_OK;
 }
 
@@ -410,9 +412,8 @@ int qed_surrogate_io(qed_ctx_t c, int net, float *host, size_t bytes, int direct
                        : hipMemcpy(c->mlp_theta[net], host, need, hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(c, e, "surrogate_io");
   if (direction == 1) {
-    static bool loaded[2];
-    (void)loaded;
-    c->mlp_ready = c->mlp_ready || net == 1 || net == 0;
+    c->mlp_have[net] = true;
+    c->mlp_ready = c->mlp_have[0] && c->mlp_have[1];
   }
   return QED_OK;
 }

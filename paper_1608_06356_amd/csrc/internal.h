@@ -63,6 +63,7 @@ struct qed_ctx {
 
   // surrogate networks (0: xi net, 1: rate net): float32 parameters, Adam state
   bool mlp_ready = false;
+  bool mlp_have[2] = {false, false};   // parameters of net A / net B trained or loaded
   float *mlp_theta[2] = {nullptr, nullptr}, *mlp_grad[2] = {nullptr, nullptr};
   float *mlp_m[2] = {nullptr, nullptr}, *mlp_v[2] = {nullptr, nullptr};
 };
