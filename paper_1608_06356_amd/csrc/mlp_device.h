@@ -50,15 +50,23 @@ __device__ __forceinline__ void split1(float x, uint16_t &hi, uint16_t &lo) {
   hi = bf16_rne(x);
   lo = bf16_rne(x - bf16_f(hi));
 }
-__device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float sigm(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 __device__ __forceinline__ float silu(float z) { return z * sigm(z); }
 __device__ __forceinline__ float dsilu(float z) {
   const float s = sigm(z);
   return s * (1.0f + z * (1.0f - s));
 }
 
-// Weights of one net staged in LDS: split 64x64 layers (row-major [out][in]),
-// optionally their transposes, and the float32 small layers.
+// Weights of one net staged in LDS: split 64x64 layers, optionally their
+// transposes, and the float32 small layers.  A 64x64 layer is stored in the
+// order the matrix-core A operand is read: the 16x16 block (mt, ks) holds, for
+// lane L, the four elements (row mt*16 + L%16, columns ks*16 + 4*(L/16) .. +3)
+// at ((mt*4 + ks)*64 + L)*4, so that a wave reads 512 contiguous bytes per
+// block (row-major rows of 128 B put 16 lanes on the same LDS banks).
+__host__ __device__ constexpr int swz(int r, int c) {
+  return (((r >> 4) * 4 + (c >> 4)) * 64 + (r & 15) + 16 * ((c & 15) >> 2)) * 4 + (c & 3);
+}
+
 struct NetLds {
   uint16_t W2h[H * H], W2l[H * H], W3h[H * H], W3l[H * H];
   float W1[H * 2], b1[H], b2[H], b3[H], W4[2 * H], b4[2];
@@ -69,13 +77,14 @@ struct NetLdsT {
 
 __device__ void stage_net(const float *th, const Layout &L, NetLds *s, NetLdsT *t) {
   for (int k = threadIdx.x; k < H * H; k += blockDim.x) {
+    const int r = k / H, c = k % H, sk = swz(r, c), tk = swz(c, r);
     uint16_t h, l;
     split1(th[L.W2 + k], h, l);
-    s->W2h[k] = h; s->W2l[k] = l;
-    if (t) { const int tk = (k % H) * H + k / H; t->W2h[tk] = h; t->W2l[tk] = l; }
+    s->W2h[sk] = h; s->W2l[sk] = l;
+    if (t) { t->W2h[tk] = h; t->W2l[tk] = l; }
     split1(th[L.W3 + k], h, l);
-    s->W3h[k] = h; s->W3l[k] = l;
-    if (t) { const int tk = (k % H) * H + k / H; t->W3h[tk] = h; t->W3l[tk] = l; }
+    s->W3h[sk] = h; s->W3l[sk] = l;
+    if (t) { t->W3h[tk] = h; t->W3l[tk] = l; }
   }
   for (int k = threadIdx.x; k < H; k += blockDim.x) {
     s->b1[k] = th[L.b1 + k]; s->b2[k] = th[L.b2 + k]; s->b3[k] = th[L.b3 + k];
@@ -97,7 +106,7 @@ __device__ __forceinline__ void mm64(const uint16_t *Wh, const uint16_t *Wl, con
     f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
-      const int off = (mt * 16 + (lane & 15)) * H + ks * 16 + 4 * (lane >> 4);
+      const int off = ((mt * 4 + ks) * 64 + lane) * 4;   // = swz(mt*16 + lane%16, ks*16 + 4*(lane/16))
       const s4 ah = *reinterpret_cast<const s4 *>(Wh + off);
       const s4 al = *reinterpret_cast<const s4 *>(Wl + off);
       acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh[ks], acc, 0, 0, 0);
