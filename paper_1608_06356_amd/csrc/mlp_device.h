@@ -37,13 +37,15 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
   return (uint16_t)(u >> 16);
 }
 __device__ __forceinline__ float bf16_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-// x = hi + lo with hi = bf16(x), lo = bf16(x - hi), packed four at a time
+// x = hi + lo with hi = bf16(x), lo = bf16(x - hi) (round to nearest even, the
+// hardware conversion), packed four at a time
 __device__ __forceinline__ void split4(const float x[4], s4 &hi, s4 &lo) {
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const uint16_t h = bf16_rne(x[v]);
-    hi[v] = (short)h;
-    lo[v] = (short)bf16_rne(x[v] - bf16_f(h));
+    const __bf16 h = (__bf16)x[v];
+    const __bf16 l = (__bf16)(x[v] - (float)h);
+    hi[v] = __builtin_bit_cast(short, h);
+    lo[v] = __builtin_bit_cast(short, l);
   }
 }
 __device__ __forceinline__ void split1(float x, uint16_t &hi, uint16_t &lo) {

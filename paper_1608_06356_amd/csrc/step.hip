@@ -761,7 +761,7 @@ __device__ __forceinline__ float mlp_lnh(const mlp::NetLds &B, double chi, bool 
     mlp::reload_barrier();
     const float x0 = __shfl(xi_in, q * 16 + (lane & 15), 64);
     float y[2];
-    mlp::forward_nc(B, 1, 2, x0, 0.f, y);
+    mlp::forward_nc(B, 1, 1, x0, 0.f, y);   // the photon rate head only
     if ((lane >> 4) == q) mine = y[0];
   }
   const float lchi = logf((float)chi);
