@@ -315,6 +315,14 @@ __device__ __forceinline__ void count_flush(const uint32_t *c, unsigned long lon
   if (threadIdx.x < cNumCounters && c[threadIdx.x]) atomicAdd(&g[threadIdx.x], (unsigned long long)c[threadIdx.x]);
 }
 
+// Emitter records are packed per wave: the emitter of particle i keeps its record
+// at (i & ~63) + (number of emitters before it in its wave), so that a wave's
+// records are contiguous.  `bits` is the wave's emitter mask word.
+__device__ __forceinline__ int64_t rec_slot(int64_t i, uint64_t bits) {
+  const uint64_t below = (i & 63) ? bits & ((1ull << (i & 63)) - 1ull) : 0ull;
+  return (i & ~(int64_t)63) + (int64_t)__popcll(below);
+}
+
 // Adds the number of lanes of the wave with `set` (one atomic per wave).
 __device__ __forceinline__ void count_flags(unsigned long long *c, int which, bool set) {
   const uint32_t s = (uint32_t)__popcll(__ballot(set));
@@ -478,6 +486,7 @@ __global__ __launch_bounds__(kGPThreads, (gp_waves<R, FK, M1>())) void k_gather_
     } else {
       flag = W > 0.0 && tau <= W * a.dtd;
     }
+    const uint64_t fbits = __ballot(flag);   // the live lanes' flags (others are not emitters)
     if (flag) {
       EmRec<R> r;
       r.x[0] = x; r.x[1] = y; r.x[2] = z; r.p[0] = px; r.p[1] = py; r.p[2] = pz;
@@ -489,7 +498,7 @@ __global__ __launch_bounds__(kGPThreads, (gp_waves<R, FK, M1>())) void k_gather_
       r.rem = a.dtd - tau / W;
       r.j0 = j0;
       r.nsub = nsub;
-      a.rec[i] = r;
+      a.rec[rec_slot(i, fbits)] = r;
     } else if (!(M1 && a.gen)) {
       a.sp.tau[i] = tau - W * a.dtd;
     }
@@ -546,6 +555,7 @@ struct EmitArgs {
   const uint16_t *q16;         // 16-bit quantiles (R = float)
   const float *s0sc;
   const int32_t *em_idx;
+  const uint64_t *mask;        // emitter mask of the last gather/push (record slots)
   const EmRec<R> *rec;
   const int64_t *n_emit;
   uint64_t *next_id;
@@ -575,7 +585,7 @@ __device__ void emit_tile(const EmitArgs<R> &a, const Tab &tab, const R *lnh, ui
   R nx = 0, ny = 0, nz = 0, x = 0, y = 0, z = 0;
   if (valid) {
     const int64_t i = a.em_idx[r];
-    const EmRec<R> rc = a.rec[i];
+    const EmRec<R> rc = a.rec[rec_slot(i, a.mask[i >> 6])];
     R F[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) F[c] = rc.F[c];
@@ -825,8 +835,9 @@ __global__ __launch_bounds__(kGPThreads, 4) void k_gather_push_mlp(GPArgs<float>
         nfb += !ok;
         W = kRateUnit * (double)(h / g);
       }
-      if (W > 0.0 && tau <= W * a.dtd) {
-        flag = true;
+      flag = W > 0.0 && tau <= W * a.dtd;
+      const uint64_t fbits = __ballot(flag);   // the live lanes' flags (others are not emitters)
+      if (flag) {
         EmRec<float> r;
         r.x[0] = x; r.x[1] = y; r.x[2] = z; r.p[0] = px; r.p[1] = py; r.p[2] = pz;
 #pragma unroll
@@ -835,7 +846,7 @@ __global__ __launch_bounds__(kGPThreads, 4) void k_gather_push_mlp(GPArgs<float>
         r.chi = chi;
         r.W = W;
         r.rem = a.dtd - tau / W;
-        a.rec[i] = r;
+        a.rec[rec_slot(i, fbits)] = r;
       } else {
         a.sp.tau[i] = tau - W * a.dtd;
       }
@@ -891,7 +902,7 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
     bool recoiled = false;
     if (valid) {
       i = a.em_idx[r];
-      const EmRec<float> rc = a.rec[i];
+      const EmRec<float> rc = a.rec[rec_slot(i, a.mask[i >> 6])];
 #pragma unroll
       for (int c = 0; c < 6; ++c) F[c] = rc.F[c];
       chi = rc.chi; W = rc.W; rem = rc.rem;
@@ -1446,7 +1457,7 @@ hipError_t launch_emit(qed_ctx *c, const qed_species_t *lep, const qed_species_t
   const int64_t *dstep = step < 0 ? c->d_step : nullptr;
   if (use_mlp) {
     EmitArgs<float> a{dev_species(lep), dev_species(ph), c->rad_lnh32, c->rad_S64, c->rad_q16,
-                      c->rad_s0sc, c->em_idx, (const EmRec<float> *)c->em_rec, c->d_n_emit,
+                      c->rad_s0sc, c->em_idx, c->em_mask, (const EmRec<float> *)c->em_rec, c->d_n_emit,
                       c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, dstep, sc,
                       c->d_counters, gen_mode(c), c->em_dt, c->range};
     static bool attr = false;
@@ -1458,14 +1469,14 @@ hipError_t launch_emit(qed_ctx *c, const qed_species_t *lep, const qed_species_t
     hipLaunchKernelGGL(k_emit_mlp, dim3(grid), dim3(kEmitMlpThreads), sizeof(EmitMlpLds), st, a, mlp_dev(c));
   } else if (lep->dtype == QED_F32) {
     EmitArgs<float> a{dev_species(lep), dev_species(ph), c->rad_lnh32, c->rad_S64, c->rad_q16,
-                      c->rad_s0sc, c->em_idx, (const EmRec<float> *)c->em_rec, c->d_n_emit,
+                      c->rad_s0sc, c->em_idx, c->em_mask, (const EmRec<float> *)c->em_rec, c->d_n_emit,
                       c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, dstep, sc,
                       c->d_counters, gen_mode(c), c->em_dt, c->range};
     if (a.gen) hipLaunchKernelGGL(k_emit_f32<true>, dim3(grid), dim3(kEmitThreads), 0, st, a);
     else hipLaunchKernelGGL(k_emit_f32<false>, dim3(grid), dim3(kEmitThreads), 0, st, a);
   } else {
     EmitArgs<double> a{dev_species(lep), dev_species(ph), c->rad_lnh64, c->rad_S64, c->rad_q16,
-                       c->rad_s0sc, c->em_idx, (const EmRec<double> *)c->em_rec, c->d_n_emit,
+                       c->rad_s0sc, c->em_idx, c->em_mask, (const EmRec<double> *)c->em_rec, c->d_n_emit,
                        c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, dstep, sc,
                        c->d_counters, gen_mode(c), c->em_dt, c->range};
     if (a.gen) hipLaunchKernelGGL(k_emit_f64<true>, dim3(grid), dim3(kEmitThreads), 0, st, a);
