@@ -99,6 +99,8 @@ int qed_create(qed_ctx_t *out, const qed_params_t *p) {
   int ncu = 0;
   if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
   if (e == hipSuccess) c->n_cu = ncu > 0 ? ncu : 256;
+  if (e == hipSuccess) e = qed::mlp_set_attributes();
+  if (e == hipSuccess) e = qed::step_set_attributes();
   if (e == hipSuccess) e = dalloc(&c->d_counters, qed::cNumCounters);
   if (e == hipSuccess) e = dalloc(&c->d_next_id, 1);
   if (e == hipSuccess) e = dalloc(&c->d_n_emit, 1);

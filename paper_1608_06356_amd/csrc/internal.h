@@ -69,6 +69,8 @@ struct qed_ctx {
 };
 
 namespace qed {
+hipError_t mlp_set_attributes();
+hipError_t step_set_attributes();
 hipError_t launch_build_tables(qed_ctx *c, int formula, TabRange rg, hipStream_t s);
 int mlp_params(int net);
 hipError_t launch_sort_by_cell(qed_ctx *c, const qed_fields_t *f, const qed_species_t *s, qed_species_t *d,

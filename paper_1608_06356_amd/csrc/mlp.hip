@@ -387,13 +387,21 @@ hipError_t launch_mlp_grad(int net, const float *theta, float *grad, const doubl
   const int64_t tiles = (nbatch + 15) / 16;
   int64_t blocks = (tiles + 3) / 4;
   if (blocks > 256) blocks = 256;
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute((const void *)k_train, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(TrainLds));
-    attr = true;
-  }
   hipLaunchKernelGGL(k_train, dim3((unsigned)blocks), dim3(kTrainThreads), sizeof(TrainLds), st, a);
   return hipGetLastError();
+}
+
+// Dynamic LDS above the default limit, for the kernels of this file; called
+// once per context, with the context's device current.
+hipError_t mlp_set_attributes() {
+  hipError_t e = hipFuncSetAttribute((const void *)k_train, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)sizeof(TrainLds));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_forward_raw, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)sizeof(NetLds));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_infer, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(InferLds));
+  return e;
 }
 
 hipError_t launch_adam(float *theta, float *grad, float *m, float *v, int net, float lr, float b1t, float b2t,
@@ -407,11 +415,6 @@ hipError_t launch_mlp_forward(const float *theta, int net, const float *x, int64
   int64_t blocks = ((n + 15) / 16 + 3) / 4;
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute((const void *)k_forward_raw, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(NetLds));
-    attr = true;
-  }
   hipLaunchKernelGGL(k_forward_raw, dim3((unsigned)blocks), dim3(256), sizeof(NetLds), st, theta, net, x, n, y);
   return hipGetLastError();
 }
@@ -422,11 +425,6 @@ hipError_t launch_mlp_sample(qed_ctx *c, const double *chi, const double *gamma,
               step < 0 ? c->d_step : nullptr,
               c->rad_lnh32, c->pair_L32, c->rad_s0sc, c->rad_chk, c->rad_q16, lnw, xi, lnwp, tol,
               c->d_counters + cMlpFallbackXi, make_range(kRadChiMax, kPairChiMax)};
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute((const void *)k_infer, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(InferLds));
-    attr = true;
-  }
   int64_t blocks = ((n + 15) / 16 + 7) / 8;
   if (blocks > c->n_cu) blocks = c->n_cu;      // one workgroup per CU (LDS-bound)
   if (blocks < 1) blocks = 1;

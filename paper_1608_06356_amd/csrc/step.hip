@@ -1398,6 +1398,13 @@ static MlpDev mlp_dev(qed_ctx *c) {
   return MlpDev{c->range, c->mlp_theta[0], c->mlp_theta[1], c->rad_chk, c->rad_lnh32, c->rad_q16, c->rad_s0sc, 2e-3f};
 }
 
+// Dynamic LDS above the default limit (surrogate emission); called once per
+// context, with the context's device current.
+hipError_t step_set_attributes() {
+  return hipFuncSetAttribute((const void *)k_emit_mlp, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)sizeof(EmitMlpLds));
+}
+
 static int gen_mode(const qed_ctx *c) {
   if (!(c->params.flags & QED_FLAG_METHOD_I)) return 0;
   return (c->params.flags & QED_FLAG_NO_SUBSTEP) ? 2 : 1;
@@ -1460,12 +1467,6 @@ hipError_t launch_emit(qed_ctx *c, const qed_species_t *lep, const qed_species_t
                       c->rad_s0sc, c->em_idx, c->em_mask, (const EmRec<float> *)c->em_rec, c->d_n_emit,
                       c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, dstep, sc,
                       c->d_counters, gen_mode(c), c->em_dt, c->range};
-    static bool attr = false;
-    if (!attr) {
-      (void)hipFuncSetAttribute((const void *)k_emit_mlp, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)sizeof(EmitMlpLds));
-      attr = true;
-    }
     hipLaunchKernelGGL(k_emit_mlp, dim3(grid), dim3(kEmitMlpThreads), sizeof(EmitMlpLds), st, a, mlp_dev(c));
   } else if (lep->dtype == QED_F32) {
     EmitArgs<float> a{dev_species(lep), dev_species(ph), c->rad_lnh32, c->rad_S64, c->rad_q16,
