@@ -17,6 +17,10 @@ whose duration is measured with HIP events on the stream it runs on.
 the table lookups (QED_FLAG_SURROGATE) and gates it on the two-sample KS
 distance of the photon-energy spectra of the two runs (<= 2e-3).
 `cpu_baseline` times the CPU oracle on a bounded sample of the same workload.
+`other_configs` times the other configurations on the same GPU: the uniform-B
+ensembles in float64 (three Fig. 1 ensembles of 1e5 electrons, 100 steps), pair
+creation for 2e7 photons (100 steps), and the standalone sampler (table and
+surrogate) on 1e8 lookups.
 """
 import argparse
 import json
@@ -31,6 +35,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# E_S = m_e c^2 / (hbar omega_0) at lambda_0 = 1 um: sets the photon energies of
+# the pair workload from their drawn chi_ph
+E_S_1UM = 510998.95 / 1.239841984
 PROFILE = os.path.join(ROOT, "profiles", "gather_push_standing_wave_1e7.md")
 
 
@@ -71,6 +78,8 @@ def parse():
     ap.add_argument("--sort-every", type=int, default=20,
                     help="re-sort electrons by cell every K steps inside the timed loop (0: never)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-other-configs", action="store_true",
+                    help="skip the uniform-B, pair and sampler configurations")
     return ap.parse_args()
 
 
@@ -192,8 +201,117 @@ def run_workload(args, q, torch, flags, train_steps=0):
     m = ph.n()
     gam = torch.sqrt(ph.px[:m] ** 2 + ph.py[:m] ** 2 + ph.pz[:m] ** 2)
     gam = torch.sort(gam).values
-    out = dict(total_ms=total_ms, gp_ms=gp_ms, st=st, photons=m, gamma=gam, train_s=train_s)
+    weights = [ctx.qed_surrogate_io(k) for k in (0, 1)] if train_steps else None
+    out = dict(total_ms=total_ms, gp_ms=gp_ms, st=st, photons=m, gamma=gam, train_s=train_s, weights=weights)
     del ph, lep, lep_b, cur, grid
+    ctx.close()
+    return out
+
+
+def _timed(torch, fn, steps):
+    """Milliseconds of `steps` calls of fn(k), HIP events on the current stream."""
+    stream = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(stream)
+    for k in range(steps):
+        fn(k)
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b)
+
+
+def run_uniform_b(q, torch, n_per=100_000, steps=100, dt=0.01):
+    """Three Fig. 1 ensembles (b0, gamma) = (200, 206), (2000, 206), (2000, 2060)
+    of n_per electrons each, float64 state, formula I, photons appended."""
+    import workloads
+    ctx = q.Context(seed=0, kmax=4)
+    ctx.qed_build_tables(q.QED_FORMULA_I)
+    runs = []
+    for e in workloads.uniform_b_ensembles(n_per, seed=0):
+        lep, ph = q.Species(n_per, "f64"), q.Species(16 * n_per, "f64")
+        lep.load(e["x"], e["p"], None, e["id"])
+        ctx.qed_init_optical_depth(lep, 0)
+        runs.append((lep, ph, q.Fields(q.QED_FIELD_UNIFORM, E=(0, 0, 0), B=(0, 0, e["b0"]))))
+    ctx.qed_set_next_id(3 * n_per)
+    ctx.qed_reserve(16 * n_per)
+
+    def step(s):
+        for lep, ph, fld in runs:
+            ctx.qed_gather_push(fld, lep, -1, dt, s)
+            ctx.qed_emit_photons(lep, ph, s)
+
+    ms = _timed(torch, step, steps)
+    st, _ = ctx.qed_get_status()
+    out = dict(workload=f"uniform B, 3 x {n_per} electrons (Fig. 1 ensembles), float64, formula I, {steps} steps",
+               value=3 * n_per * steps / (ms * 1e-3), unit="particle-steps/s", ms_per_step=ms / steps,
+               photons=st["photons"], events=st["events"])
+    del runs
+    ctx.close()
+    return out
+
+
+def run_pairs(q, torch, n=20_000_000, steps=100, dt=0.01):
+    """2e7 static photons, chi_ph log-uniform in [1e-2, 1e2], isotropic, each in its
+    own uniform E, B (|E|, |B| <= 2000); pairs appended, float32 state."""
+    import workloads
+    w = workloads.pair_photons(n, E_S_1UM, seed=2)
+    ctx = q.Context(seed=2, kmax=4, flags=q.QED_FLAG_STATIC_PHOTONS)
+    ctx.qed_build_tables(q.QED_FORMULA_I)
+    ph, el, po = q.Species(n, "f32"), q.Species(n, "f32"), q.Species(n, "f32")
+    ph.load(w["x"], w["k"], None, w["id"])
+    e0 = np.zeros((0, 3))
+    el.load(e0, e0, np.zeros(0), np.zeros(0, np.uint64))
+    po.load(e0, e0, np.zeros(0), np.zeros(0, np.uint64))
+    ctx.qed_init_optical_depth(ph, 0)
+    Et = [torch.from_numpy(np.ascontiguousarray(w["E"][:, c], dtype=np.float32)).cuda() for c in range(3)]
+    Bt = [torch.from_numpy(np.ascontiguousarray(w["B"][:, c], dtype=np.float32)).cuda() for c in range(3)]
+    del w
+    fld = q.Fields(q.QED_FIELD_PER_PARTICLE, E=Et, B=Bt)
+    ctx.qed_set_next_id(n)
+    ctx.qed_reserve(n)
+    ms = _timed(torch, lambda s: ctx.qed_create_pairs(fld, ph, el, po, dt, s), steps)
+    st, _ = ctx.qed_get_status()
+    out = dict(workload=f"pair creation, {n} static photons (chi_ph log-uniform 1e-2..1e2, |E|,|B| <= 2000), "
+                        f"float32 state, {steps} steps; every photon slot is checked each step",
+               value=n * steps / (ms * 1e-3), unit="photon-steps/s", ms_per_step=ms / steps, pairs=st["pairs"],
+               chi_out_of_range=st["chi_out_of_range"])
+    del ph, el, po, Et, Bt
+    ctx.close()
+    return out
+
+
+def run_sampler(q, torch, weights, n=100_000_000, reps=5):
+    """Standalone lookups: ln W_rad, one xi sample and ln W_pair for n particles with
+    log10 chi uniform in [-3, 2] and gamma = 1000, from the tables (float32 copies)
+    and from the surrogate nets."""
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(3)
+    chi = torch.pow(10.0, torch.rand(n, generator=gen, device="cuda", dtype=torch.float64) * 5.0 - 3.0)
+    gamma = torch.full((n,), 1000.0, dtype=torch.float64, device="cuda")
+    ids = torch.arange(n, dtype=torch.int64, device="cuda")
+    lnw, xi, lnwp = (torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(3))
+    ctx = q.Context(seed=3)
+    ctx.qed_build_tables(q.QED_FORMULA_I)
+    out = dict(workload=f"sampler, {n} lookups of ln W_rad, xi and ln W_pair (log10 chi uniform in [-3, 2], "
+                        f"gamma = 1000)", unit="samples/s")
+    xs = {}
+    for name, prec in (("table", q.QED_F32), ("surrogate", q.QED_SAMPLER_MLP)):
+        if prec == q.QED_SAMPLER_MLP:
+            if weights is None:
+                continue
+            for k in (0, 1):
+                ctx.qed_surrogate_io(k, weights[k])
+        ctx.qed_sample(chi, gamma, ids, prec, 0, lnw, xi, lnwp)
+        ms = _timed(torch, lambda s: ctx.qed_sample(chi, gamma, ids, prec, 0, lnw, xi, lnwp), reps)
+        out[name] = n * reps / (ms * 1e-3)
+        xs[name] = torch.sort(xi[: 10_000_000].clone()).values
+    st, _ = ctx.qed_get_status()
+    if "surrogate" in xs:
+        out["ks_xi_surrogate_vs_table_1e7"] = ks_two_sample(xs["table"], xs["surrogate"])
+        out["fallback_xi"] = st["mlp_fallback_xi"]
+        out["fallback_rate"] = st["mlp_fallback_rate"]
+    del chi, gamma, ids, lnw, xi, lnwp, xs
     ctx.close()
     return out
 
@@ -253,8 +371,14 @@ def main():
             "events": sur["st"]["events"], "train_s": sur["train_s"],
             "ratio_vs_table": (sur["total_ms"] and total_ms / sur["total_ms"]),
         }
+        weights = sur["weights"]
         del sur
+    else:
+        weights = None
     del tab
+    if not args.no_other_configs:
+        out["other_configs"] = {"uniform_b_f64": run_uniform_b(q, torch), "pairs": run_pairs(q, torch),
+                                "sampler": run_sampler(q, torch, weights)}
     if args.calibrate_copy:
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -335,14 +335,15 @@ def photon_step(x, k, tau, ids, E, B, *, dt, step, seed, sampler, next_id,
     k = np.asarray(k, dtype=np.float64)
     tau = np.array(tau, dtype=np.float64)
     ids = np.array(ids, dtype=np.uint64)
+    alive = ids != DEAD_ID            # photons converted earlier are left as they are
     gph = np.sqrt(np.sum(k * k, axis=-1))
     khat = k / np.where(gph > 0, gph, 1.0)[:, None]
     if move:
-        x = wrap(x + khat * dt, L)
+        x = np.where(alive[:, None], wrap(x + khat * dt, L), x)
     chi = spectra.chi_photon(k, E, B)
-    W = sampler.rate(chi, gph)
-    ev = (W > 0) & (tau <= W * dt)
-    tau = np.where(ev, tau, tau - W * dt)
+    W = np.where(alive, sampler.rate(chi, gph), 0.0)
+    ev = alive & (W > 0) & (tau <= W * dt)
+    tau = np.where(ev | ~alive, tau, tau - W * dt)
     idx = np.nonzero(ev)[0]
     r = philox.stream(ids[idx], seed, step, philox.PHOTON_EVENT, 0)
     u = philox.uniform(r)

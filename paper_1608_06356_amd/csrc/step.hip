@@ -1074,7 +1074,9 @@ __device__ void pair_tile(const PairArgs<R> &a, const Tab &tab, const R *L, uint
   uint32_t ev = 0, nrange = 0, nnan = 0;
   R x = 0, y = 0, z = 0, kxh = 0, kyh = 0, kzh = 0, ge = 0, gpos = 0;
   double te = 0, tp = 0;
-  if (i < n) {
+  // photons converted earlier and not yet compacted away are skipped
+  const uint64_t pid = i < n ? a.ph.id[i] : kDeadId;
+  if (pid != kDeadId) {
     R *X = (R *)a.ph.x, *Y = (R *)a.ph.y, *Z = (R *)a.ph.z;
     const R kx = ((R *)a.ph.px)[i], ky = ((R *)a.ph.py)[i], kz = ((R *)a.ph.pz)[i];
     x = X[i]; y = Y[i]; z = Z[i];
@@ -1101,8 +1103,7 @@ __device__ void pair_tile(const PairArgs<R> &a, const Tab &tab, const R *L, uint
     const double tau = a.ph.tau[i];
     if (W > 0.0 && tau <= W * a.dtd) {
       ev = 1;
-      const uint64_t id = a.ph.id[i];
-      const uint4 u = stream4(id, a.seed, step_of(a.step, a.d_step), kPhotonEvent, 0u);
+      const uint4 u = stream4(pid, a.seed, step_of(a.step, a.d_step), kPhotonEvent, 0u);
       R xh, omh;
       sample_pair_half<R>(tab, (R)chi, unit<R>(u.x), unit<R>(u.y), xh, omh, a.rg);
       const bool flip = u.y & 1u;

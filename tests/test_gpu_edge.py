@@ -110,3 +110,42 @@ def test_call_order_and_argument_errors():
                        torch.zeros(4, dtype=torch.int64, device="cuda"), q.QED_SAMPLER_MLP, 0,
                        torch.empty(4, device="cuda"), torch.empty(4, device="cuda"))
     assert e.value.code == q.QED_ERR_STATE                 # surrogate not trained
+
+
+def test_converted_photons_are_not_converted_twice(pair_table):
+    """Two pair passes without compaction in between: photons marked dead by the
+    first pass are skipped by the second (no second pair, no move, no optical
+    depth change), as in the oracle's photon step."""
+    torch, q = need_gpu()
+    ctx = q.Context(seed=9)
+    ctx.qed_build_tables(q.QED_FORMULA_I)
+    n, b, chi = 4096, 2000.0, 30.0
+    gph = chi * E_S / b
+    x = np.zeros((n, 3))
+    k = np.tile([gph, 0.0, 0.0], (n, 1))
+    tau = np.full(n, 1e-6)                         # every photon converts in the first pass
+    ids = np.arange(n, dtype=np.uint64)
+    for dt in ("f64",):
+        ph, el, po = q.Species(n, dt), q.Species(2 * n, dt), q.Species(2 * n, dt)
+        ph.load(x, k, tau, ids)
+        e0 = np.zeros((0, 3))
+        el.load(e0, e0, np.zeros(0), np.zeros(0, np.uint64))
+        po.load(e0, e0, np.zeros(0), np.zeros(0, np.uint64))
+        ctx.qed_set_next_id(n)
+        fld = q.Fields(q.QED_FIELD_UNIFORM, B=(0, 0, b))
+        ctx.qed_create_pairs(fld, ph, el, po, 0.01, 0)
+        first = ph.to_numpy()
+        ctx.qed_create_pairs(fld, ph, el, po, 0.01, 1)
+        second = ph.to_numpy()
+        st, rc = ctx.qed_get_status()
+        assert st["pairs"] == n and el.n() == n and po.n() == n
+        assert np.all(first["id"] == mc.DEAD_ID)
+        np.testing.assert_array_equal(second["x"], first["x"])
+        np.testing.assert_array_equal(second["tau"], first["tau"])
+        # the oracle's photon step leaves dead photons alone as well
+        E = np.zeros((n, 3))
+        B = np.tile([0.0, 0.0, b], (n, 1))
+        r = mc.photon_step(first["x"], first["p"], first["tau"], first["id"], E, B, dt=0.01, step=1, seed=9,
+                           sampler=mc.PairSampler(pair_table, "f64"), next_id=2 * n)
+        assert r["pairs"].size == 0
+        np.testing.assert_array_equal(r["x"], first["x"])
