@@ -217,4 +217,27 @@ __device__ __forceinline__ uint32_t block_exclusive(uint32_t v, uint32_t *lds, u
   return base + incl - v;
 }
 
+// The same scan for 64-bit values (blockDim multiple of 64, at most 1024
+// threads); `lds` holds >= 16 uint64.
+__device__ __forceinline__ uint64_t block_exclusive64(uint64_t v, uint64_t *lds, uint64_t *total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  uint64_t incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint64_t t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) lds[wave] = incl;
+  __syncthreads();
+  uint64_t base = 0, tot = 0;
+  for (int w = 0; w < nw; ++w) {
+    const uint64_t x = lds[w];
+    if (w < wave) base += x;
+    tot += x;
+  }
+  __syncthreads();
+  *total = tot;
+  return base + incl - v;
+}
+
 }  // namespace qed

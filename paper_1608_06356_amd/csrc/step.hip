@@ -1064,70 +1064,101 @@ struct PairArgs {
   TabRange rg;
 };
 
-constexpr int kPairThreads = 1024;
+constexpr int kPairThreads = 256, kPairItems = 4, kPairTile = kPairThreads * kPairItems;
 
+// Field, chi_ph and pair rate of photon i after its move; false if the fields
+// are not finite (then chi is NaN and W = 0).
+template <typename R>
+__device__ __forceinline__ bool photon_rate(const PairArgs<R> &a, const R *L, int64_t i, R x, R y, R z, R kx,
+                                            R ky, R kz, R gph, double &chi, double &W) {
+  R F[6];
+  field_at<R>(a.f, i, x, y, z, F);
+  W = 0.0;
+  chi = fields_finite<R>(F) ? chi_photon(kx, ky, kz, F[0], F[1], F[2], F[3], F[4], F[5]) : NAN;
+  if (!isfinite(chi)) return false;
+  if (gph >= (R)2) W = kRateUnit * (double)(h_pair<R>((R)chi, L, a.rg) / gph);
+  return true;
+}
+
+// One tile of kPairTile photons, kPairItems per thread (photon base + it *
+// kPairThreads + thread, so that a pass over `it` is coalesced).  Pass 1 moves
+// every photon and decides its event; the offsets of the pairs follow the photon
+// index through one scan of per-level counts packed 16 bits per level; pass 2
+// recomputes the (rare) events from the photon's stream and writes the pairs.
 template <typename R, typename Tab>
 __device__ void pair_tile(const PairArgs<R> &a, const Tab &tab, const R *L, uint32_t tile,
-                          uint32_t *scan_s, uint64_t *off_s, int64_t n, int64_t e0, int64_t p0,
+                          uint64_t *scan_s, uint64_t *off_s, int64_t n, int64_t e0, int64_t p0,
                           uint64_t id0, uint32_t *cnt) {
-  const int64_t i = (int64_t)tile * kPairThreads + threadIdx.x;
-  uint32_t ev = 0, nrange = 0, nnan = 0;
-  R x = 0, y = 0, z = 0, kxh = 0, kyh = 0, kzh = 0, ge = 0, gpos = 0;
-  double te = 0, tp = 0;
-  // photons converted earlier and not yet compacted away are skipped
-  const uint64_t pid = i < n ? a.ph.id[i] : kDeadId;
-  if (pid != kDeadId) {
-    R *X = (R *)a.ph.x, *Y = (R *)a.ph.y, *Z = (R *)a.ph.z;
-    const R kx = ((R *)a.ph.px)[i], ky = ((R *)a.ph.py)[i], kz = ((R *)a.ph.pz)[i];
-    x = X[i]; y = Y[i]; z = Z[i];
+  static_assert(kPairThreads <= 0xFFFF, "per-level counts are packed in 16 bits");
+  const int64_t base = (int64_t)tile * kPairTile;
+  R *X = (R *)a.ph.x, *Y = (R *)a.ph.y, *Z = (R *)a.ph.z;
+  const R *KX = (const R *)a.ph.px, *KY = (const R *)a.ph.py, *KZ = (const R *)a.ph.pz;
+  uint32_t evbits = 0, nrange = 0, nnan = 0;
+#pragma unroll
+  for (int it = 0; it < kPairItems; ++it) {
+    const int64_t i = base + (int64_t)it * kPairThreads + threadIdx.x;
+    // photons converted earlier and not yet compacted away are skipped
+    const uint64_t pid = i < n ? a.ph.id[i] : kDeadId;
+    if (pid == kDeadId) continue;
+    const R kx = KX[i], ky = KY[i], kz = KZ[i];
+    R x = X[i], y = Y[i], z = Z[i];
     const R gph = sqrt(kx * kx + ky * ky + kz * kz);
-    if (gph > (R)0) { kxh = kx / gph; kyh = ky / gph; kzh = kz / gph; }
-    if (a.move) {
-      x += kxh * a.dt; y += kyh * a.dt; z += kzh * a.dt;
+    if (a.move && gph > (R)0) {
+      x += kx / gph * a.dt; y += ky / gph * a.dt; z += kz / gph * a.dt;
       if (a.f.kind == QED_FIELD_GRID) {
         wrap_coord<R>(x, (R)(a.f.dx * a.f.nx)); wrap_coord<R>(y, (R)(a.f.dy * a.f.ny));
         wrap_coord<R>(z, (R)(a.f.dz * a.f.nz));
       }
       X[i] = x; Y[i] = y; Z[i] = z;
     }
-    R F[6];
-    field_at<R>(a.f, i, x, y, z, F);
-    const double chi = fields_finite<R>(F) ? chi_photon(kx, ky, kz, F[0], F[1], F[2], F[3], F[4], F[5]) : NAN;
-    double W = 0.0;
-    if (isfinite(chi)) {
+    double chi, W;
+    if (photon_rate<R>(a, L, i, x, y, z, kx, ky, kz, gph, chi, W)) {
       nrange += chi > a.rg.pair_hi;
-      if (gph >= (R)2) W = kRateUnit * (double)(h_pair<R>((R)chi, L, a.rg) / gph);
     } else {
       ++nnan;
     }
     const double tau = a.ph.tau[i];
-    if (W > 0.0 && tau <= W * a.dtd) {
-      ev = 1;
-      const uint4 u = stream4(pid, a.seed, step_of(a.step, a.d_step), kPhotonEvent, 0u);
-      R xh, omh;
-      sample_pair_half<R>(tab, (R)chi, unit<R>(u.x), unit<R>(u.y), xh, omh, a.rg);
-      const bool flip = u.y & 1u;
-      const R xe = flip ? omh : xh, xp = flip ? xh : omh;
-      ge = xe * gph;
-      gpos = xp * gph;
-      te = -log(unit<double>(u.z));
-      tp = -log(unit<double>(u.w));
-      a.ph.id[i] = kDeadId;
-    } else {
-      a.ph.tau[i] = tau - W * a.dtd;
-    }
+    if (W > 0.0 && tau <= W * a.dtd) evbits |= 1u << it;
+    else a.ph.tau[i] = tau - W * a.dtd;
   }
+  const uint32_t ev = (uint32_t)__popc(evbits);
   count_lds(cnt, cChiRange, nrange);
   count_lds(cnt, cNanChi, nnan);
   count_lds(cnt, cPairs, ev);
-  uint32_t total;
-  const uint32_t off = block_exclusive(ev, scan_s, &total);
+  uint64_t packed = 0;
+#pragma unroll
+  for (int it = 0; it < kPairItems; ++it) packed |= (uint64_t)((evbits >> it) & 1u) << (16 * it);
+  uint64_t tot;
+  const uint64_t excl = block_exclusive64(packed, scan_s, &tot);
+  uint32_t level0[kPairItems], total = 0;
+#pragma unroll
+  for (int it = 0; it < kPairItems; ++it) {
+    level0[it] = total;
+    total += (uint32_t)((tot >> (16 * it)) & 0xFFFFu);
+  }
   const uint64_t toff = tile_offset(tile, total, a.sc.status, a.counters, off_s);
   uint32_t ndrop = 0;
-  if (ev) {
-    const uint64_t rank = toff + off;
+  for (int it = 0; it < kPairItems; ++it) {
+    if (!((evbits >> it) & 1u)) continue;
+    const int64_t i = base + (int64_t)it * kPairThreads + threadIdx.x;
+    const uint64_t pid = a.ph.id[i];
+    const R kx = KX[i], ky = KY[i], kz = KZ[i];
+    const R x = X[i], y = Y[i], z = Z[i];
+    const R gph = sqrt(kx * kx + ky * ky + kz * kz);
+    double chi, W;
+    photon_rate<R>(a, L, i, x, y, z, kx, ky, kz, gph, chi, W);
+    const uint4 u = stream4(pid, a.seed, step_of(a.step, a.d_step), kPhotonEvent, 0u);
+    R xh, omh;
+    sample_pair_half<R>(tab, (R)chi, unit<R>(u.x), unit<R>(u.y), xh, omh, a.rg);
+    const bool flip = u.y & 1u;
+    const R xe = flip ? omh : xh, xp = flip ? xh : omh;
+    const R ge = xe * gph, gpos = xp * gph;
+    const double te = -log(unit<double>(u.z)), tp = -log(unit<double>(u.w));
+    a.ph.id[i] = kDeadId;
+    const uint64_t rank = toff + level0[it] + (uint32_t)((excl >> (16 * it)) & 0xFFFFu);
     const int64_t je = e0 + (int64_t)rank, jp = p0 + (int64_t)rank;
     if (je < a.el.cap && jp < a.po.cap) {
+      const R kxh = kx / gph, kyh = ky / gph, kzh = kz / gph;
       const R pe = sqrt(fmax(ge * ge - (R)1, (R)0)), pp = sqrt(fmax(gpos * gpos - (R)1, (R)0));
       ((R *)a.el.x)[je] = x; ((R *)a.el.y)[je] = y; ((R *)a.el.z)[je] = z;
       ((R *)a.el.px)[je] = kxh * pe; ((R *)a.el.py)[je] = kyh * pe; ((R *)a.el.pz)[je] = kzh * pe;
@@ -1136,25 +1167,23 @@ __device__ void pair_tile(const PairArgs<R> &a, const Tab &tab, const R *L, uint
       ((R *)a.po.px)[jp] = kxh * pp; ((R *)a.po.py)[jp] = kyh * pp; ((R *)a.po.pz)[jp] = kzh * pp;
       a.po.tau[jp] = tp; a.po.id[jp] = id0 + 2 * rank + 1;
     } else {
-      ndrop = 2;
+      ndrop += 2;
     }
   }
   count_lds(cnt, cDropped, ndrop);
-  const int64_t last = (n - 1) / kPairThreads;
+  const int64_t last = (n - 1) / kPairTile;
   if ((int64_t)tile == last && threadIdx.x == 0) {
-    const int64_t tot = (int64_t)(toff + total);
-    *a.el.count = e0 + tot < a.el.cap ? e0 + tot : a.el.cap;
-    *a.po.count = p0 + tot < a.po.cap ? p0 + tot : a.po.cap;
-    *a.next_id = id0 + 2 * (uint64_t)tot;
-    if (a.killed) *a.killed += tot;
+    const int64_t tt = (int64_t)(toff + total);
+    *a.el.count = e0 + tt < a.el.cap ? e0 + tt : a.el.cap;
+    *a.po.count = p0 + tt < a.po.cap ? p0 + tt : a.po.cap;
+    *a.next_id = id0 + 2 * (uint64_t)tt;
+    if (a.killed) *a.killed += tt;
   }
 }
 
 __global__ __launch_bounds__(kPairThreads) void k_pairs_f32(PairArgs<float> a) {
-  __shared__ uint4 q_s[kPairNCdf * kNU / 8];
-  __shared__ float s0sc_s[2 * kPairNCdf];
   __shared__ float L_s[kPairNRate];
-  __shared__ uint32_t scan_s[16];
+  __shared__ uint64_t scan_s[16];
   __shared__ uint32_t tile_s;
   __shared__ uint64_t off_s;
   __shared__ int64_t hdr_s[4];
@@ -1168,14 +1197,13 @@ __global__ __launch_bounds__(kPairThreads) void k_pairs_f32(PairArgs<float> a) {
   const int64_t n = hdr_s[0], e0 = hdr_s[1], p0 = hdr_s[2];
   const uint64_t id0 = (uint64_t)hdr_s[3];
   if (n == 0) return;
-  const uint4 *gq = reinterpret_cast<const uint4 *>(a.q16);
-  for (int k = threadIdx.x; k < kPairNCdf * kNU / 8; k += blockDim.x) q_s[k] = gq[k];
-  for (int k = threadIdx.x; k < 2 * kPairNCdf; k += blockDim.x) s0sc_s[k] = a.s0sc[k];
   for (int k = threadIdx.x; k < kPairNRate; k += blockDim.x) L_s[k] = a.L[k];
-  const RowQ16 tab{reinterpret_cast<const uint16_t *>(q_s), s0sc_s};
+  // the 16-bit inverse-CDF table is read through the caches: only events sample
+  // it, and without it in LDS several workgroups share a CU
+  const RowQ16 tab{a.q16, a.s0sc};
   while (true) {
     const uint32_t tile = next_tile(a.sc.ticket, &tile_s);
-    if ((int64_t)tile * kPairThreads >= n) break;
+    if ((int64_t)tile * kPairTile >= n) break;
     pair_tile<float>(a, tab, L_s, tile, scan_s, &off_s, n, e0, p0, id0, cnt_s);
   }
   count_flush(cnt_s, a.counters);
@@ -1183,7 +1211,7 @@ __global__ __launch_bounds__(kPairThreads) void k_pairs_f32(PairArgs<float> a) {
 
 __global__ __launch_bounds__(kPairThreads) void k_pairs_f64(PairArgs<double> a) {
   __shared__ double L_s[kPairNRate];
-  __shared__ uint32_t scan_s[16];
+  __shared__ uint64_t scan_s[16];
   __shared__ uint32_t tile_s;
   __shared__ uint64_t off_s;
   __shared__ int64_t hdr_s[4];
@@ -1201,7 +1229,7 @@ __global__ __launch_bounds__(kPairThreads) void k_pairs_f64(PairArgs<double> a) 
   const RowF64 tab{a.S64};
   while (true) {
     const uint32_t tile = next_tile(a.sc.ticket, &tile_s);
-    if ((int64_t)tile * kPairThreads >= n) break;
+    if ((int64_t)tile * kPairTile >= n) break;
     pair_tile<double>(a, tab, L_s, tile, scan_s, &off_s, n, e0, p0, id0, cnt_s);
   }
   count_flush(cnt_s, a.counters);
@@ -1490,12 +1518,13 @@ hipError_t launch_emit(qed_ctx *c, const qed_species_t *lep, const qed_species_t
 hipError_t launch_pairs(qed_ctx *c, const qed_fields_t *f, const qed_species_t *ph,
                         const qed_species_t *el, const qed_species_t *po, double dt, int64_t step,
                         hipStream_t st) {
-  const int64_t ntiles = (ph->capacity + kPairThreads - 1) / kPairThreads;
+  const int64_t ntiles = (ph->capacity + kPairTile - 1) / kPairTile;
   hipError_t e = zero_scan(c, ntiles, st);
   if (e != hipSuccess) return e;
   const ScanDev sc{c->d_ticket, c->d_status};
   const int move = (c->params.flags & QED_FLAG_STATIC_PHOTONS) ? 0 : 1;
-  const unsigned grid = (unsigned)(ntiles < c->n_cu ? ntiles : c->n_cu);
+  const int64_t wgs = (int64_t)c->n_cu * 4;   // persistent, tiles from the ticket
+  const unsigned grid = (unsigned)(ntiles < wgs ? ntiles : wgs);
   // killed-photon count: known only if this species was compacted before
   int64_t *killed = ((c->params.flags & QED_FLAG_TRACK_DEAD) && c->killed_owner == ph->x) ? c->d_killed : nullptr;
   if (ph->dtype == QED_F32) {
