@@ -19,8 +19,9 @@ distance of the photon-energy spectra of the two runs (<= 2e-3).
 `cpu_baseline` times the CPU oracle on a bounded sample of the same workload.
 `other_configs` times the other configurations on the same GPU: the uniform-B
 ensembles in float64 (three Fig. 1 ensembles of 1e5 electrons, 100 steps), pair
-creation for 2e7 photons (100 steps), and the standalone sampler (table and
-surrogate) on 1e8 lookups.
+creation for 2e7 photons (100 steps), the standalone sampler (table and
+surrogate) on 1e8 lookups, and the cascade step (pairs, emission, compaction)
+captured in a hipGraph for 2e7 electrons at a0 = 1000 (table and surrogate).
 """
 import argparse
 import json
@@ -316,6 +317,101 @@ def run_sampler(q, torch, weights, n=100_000_000, reps=5):
     return out
 
 
+def run_cascade(q, torch, weights, n=20_000_000, steps=100, dt=0.01, a0=1000.0, ngrid=128, sort_every=20):
+    """The cascade step (pair creation, both lepton passes with emission, photon
+    compaction) on the standing wave at a0 = 1000, captured once as a hipGraph
+    and replayed; electrons re-sorted by cell every `sort_every` steps outside the
+    graph (sorted into a second buffer and copied back, so that the graph's
+    pointers stay valid).  Table path, and surrogate path when weights are given."""
+    import workloads
+    L = workloads.BOX_L
+    res = {}
+    for name in ("table", "surrogate"):
+        if name == "surrogate" and weights is None:
+            continue
+        flags = q.QED_FLAG_TRACK_DEAD | (q.QED_FLAG_SURROGATE if name == "surrogate" else 0)
+        ctx = q.Context(seed=4, kmax=4, flags=flags)
+        ctx.qed_build_tables(q.QED_FORMULA_II)
+        if name == "surrogate":
+            for k in (0, 1):
+                ctx.qed_surrogate_io(k, weights[k])
+        ens = workloads.standing_wave_electrons(n, seed=4)
+        cell = np.floor(ens["x"] / (L / ngrid) + 0.5).astype(np.int64) % ngrid
+        order = np.argsort((cell[:, 2] * ngrid + cell[:, 1]) * ngrid + cell[:, 0], kind="stable")
+        cap_e, cap_p, cap_g = int(1.25 * n), n // 4, 3 * n
+        el, el_b = q.Species(cap_e, "f32"), q.Species(cap_e, "f32")
+        po, ph = q.Species(cap_p, "f32"), q.Species(cap_g, "f32")
+        el.load(ens["x"][order], ens["p"][order], None, ens["id"][order])
+        del ens, cell, order
+        e0 = np.zeros((0, 3))
+        po.load(e0, e0, np.zeros(0), np.zeros(0, np.uint64))
+        ph.load(e0, e0, np.zeros(0), np.zeros(0, np.uint64))
+        ctx.qed_init_optical_depth(el, 0)
+        ctx.qed_set_next_id(n)
+        ctx.qed_reserve(cap_g)
+        grid = torch.empty(ngrid ** 3 * 6, dtype=torch.float32, device="cuda")
+        fld = q.Fields(q.QED_FIELD_GRID, grid=grid, n=ngrid, L=L)
+        ctx.qed_set_step(0)
+
+        def one_step():
+            ctx.qed_fill_standing_wave_at_step(grid, ngrid, L, a0, 0.0, dt)
+            ctx.qed_create_pairs(fld, ph, el, po, dt, q.QED_STEP_DEVICE)
+            for sp, qq in ((el, -1), (po, 1)):
+                ctx.qed_gather_push(fld, sp, qq, dt, q.QED_STEP_DEVICE)
+                ctx.qed_emit_photons(sp, ph, q.QED_STEP_DEVICE)
+            ctx.qed_compact(ph)
+            ctx.qed_advance_step()
+
+        def resort():
+            ctx.qed_sort_by_cell(fld, el, el_b)
+            for a, b in ((el.x, el_b.x), (el.y, el_b.y), (el.z, el_b.z), (el.px, el_b.px), (el.py, el_b.py),
+                         (el.pz, el_b.pz), (el.tau, el_b.tau), (el.id, el_b.id), (el.count, el_b.count)):
+                a.copy_(b)
+
+        one_step()                      # first step eagerly (state advances), then capture
+        resort()                        # allocates the sort's scratch outside the timed loop
+        graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(graph, stream=side):
+                one_step()
+        torch.cuda.current_stream().wait_stream(side)
+        for _ in range(2):              # the first replays upload the graph; not timed
+            graph.replay()
+        torch.cuda.synchronize()
+        ctx.qed_get_status()
+        processed = torch.zeros(1, dtype=torch.int64, device="cuda")
+
+        def step(k):
+            if (k + 1) % sort_every == 0:
+                resort()
+            processed.add_(el.count + po.count + ph.count)
+            graph.replay()
+
+        for k in range(sort_every):     # untimed warm-up through one re-sort
+            step(k)
+        torch.cuda.synchronize()
+        ctx.qed_get_status(check=False)
+        processed.zero_()
+        ms = _timed(torch, step, steps)
+        st, rc = ctx.qed_get_status(check=False)
+        tot = int(processed.item())
+        res[name] = dict(value=tot / (ms * 1e-3), ms_per_step=ms / steps, electrons=el.n(), positrons=po.n(),
+                         photons=ph.n(), pairs=st["pairs"], dropped=st["dropped"],
+                         scan_timeouts=st["scan_timeouts"])
+        del graph, el, el_b, po, ph, grid
+        ctx.close()
+        torch.cuda.empty_cache()
+    res["workload"] = (f"cascade step on the standing wave a0={a0:g}, {n} electrons at start, {ngrid}^3 grid, "
+                       f"formula II, pairs + both lepton passes + photon compaction captured in one hipGraph, "
+                       f"{steps} replays, electrons re-sorted every {sort_every} steps")
+    res["unit"] = "particle-steps/s (electrons + positrons + photons present at the start of each step)"
+    if "surrogate" in res:
+        res["ratio_surrogate_vs_table"] = res["surrogate"]["value"] / res["table"]["value"]
+    return res
+
+
 def ks_two_sample(a, b):
     """Two-sample Kolmogorov-Smirnov statistic of sorted device tensors."""
     import torch
@@ -378,7 +474,8 @@ def main():
     del tab
     if not args.no_other_configs:
         out["other_configs"] = {"uniform_b_f64": run_uniform_b(q, torch), "pairs": run_pairs(q, torch),
-                                "sampler": run_sampler(q, torch, weights)}
+                                "sampler": run_sampler(q, torch, weights),
+                                "cascade_graph": run_cascade(q, torch, weights)}
     if args.calibrate_copy:
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
