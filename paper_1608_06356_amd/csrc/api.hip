@@ -70,7 +70,7 @@ int ensure_reserved(qed_ctx *c, int64_t n) {
   // for the largest tile count of any kernel
   const int64_t em_cap = n;
   const int64_t status_len = n / 256 + 64;
-  if ((e = dalloc(&c->em_idx, em_cap)) != hipSuccess || (e = dalloc(&c->em_rec, 144 * em_cap)) != hipSuccess ||
+  if ((e = dalloc(&c->em_idx, em_cap)) != hipSuccess || (e = dalloc(&c->em_rec, kEmRecMaxBytes * em_cap)) != hipSuccess ||
       (e = dalloc(&c->d_status, status_len)) != hipSuccess || (e = dalloc(&c->em_mask, n / 64 + 1)) != hipSuccess) {
     free_emitters(c);
     return hip_fail(c, e, "reserve: hipMalloc");

@@ -7,6 +7,9 @@
 #include "../../include/qed.h"
 #include "lookup.h"
 
+// Bytes of one emitter record slot (the float64 record; the float32 one is smaller).
+constexpr int64_t kEmRecMaxBytes = 128;
+
 struct qed_ctx {
   int device = 0;
   qed_params_t params{};
@@ -36,7 +39,7 @@ struct qed_ctx {
   int64_t em_cap = 0;            // slots (one per particle of the reserved capacity)
   uint64_t *em_mask = nullptr;   // one bit per particle: optical depth ran out this step
   int32_t *em_idx = nullptr;     // ordered emitter list
-  unsigned char *em_rec = nullptr;   // em_cap records of up to 128 bytes, slot = particle index
+  unsigned char *em_rec = nullptr;   // em_cap records of up to kEmRecMaxBytes, slot = particle index
   int64_t *d_n_emit = nullptr;
   const void *em_owner = nullptr;   // species (x pointer) the list belongs to
   int em_dtype = -1;

@@ -93,6 +93,32 @@ __device__ __forceinline__ double chi_lepton(double px, double py, double pz,
   return sqrt(g2 * (ux * ux + uy * uy + uz * uz) + ne * ne) * kInvES;
 }
 
+// The same expression for the float32 step, whose inputs (p, E, B) are float32.
+// Only E + n x B needs float64: there E and -n x B can nearly cancel, so n must be
+// exact to float64 rounding.  1/|p| comes from the float32 reciprocal square root
+// refined by two Newton steps in float64 (relative error below 1e-15); the
+// 1/(gamma^2 (1 + beta)) term multiplies the remainder of that cancellation and
+// needs only float32, with gamma the float32 Lorentz factor of p; the final
+// square root is taken in float32.  Result: chi to a few float32 ulps for the
+// given inputs.  |p|^2 below 1e-30 (float32 underflow of the estimate) takes the
+// float64 form above.
+__device__ __forceinline__ float chi_lepton_f32(float px, float py, float pz, float g, const float F[6]) {
+  const double dx = px, dy = py, dz = pz;
+  const double p2 = dx * dx + dy * dy + dz * dz;
+  if (!(p2 >= 1e-30)) return (float)chi_lepton(dx, dy, dz, F[0], F[1], F[2], F[3], F[4], F[5]);
+  double y = (double)__builtin_amdgcn_rsqf((float)p2);
+  y = fma(0.5 * y, fma(-p2 * y, y, 1.0), y);
+  y = fma(0.5 * y, fma(-p2 * y, y, 1.0), y);
+  const double nx = dx * y, ny = dy * y, nz = dz * y;
+  const double ex = F[0], ey = F[1], ez = F[2], bx = F[3], by = F[4], bz = F[5];
+  const double cx = ny * bz - nz * by, cy = nz * bx - nx * bz, cz = nx * by - ny * bx;  // n x B
+  const double f = (double)__builtin_amdgcn_rcpf(g * (g + (float)(p2 * y)));
+  const double wx = (ex + cx) - cx * f, wy = (ey + cy) - cy * f, wz = (ez + cz) - cz * f;
+  const double ux = ny * wz - nz * wy, uy = nz * wx - nx * wz, uz = nx * wy - ny * wx;  // n x w
+  const double ne = nx * ex + ny * ey + nz * ez;
+  return __builtin_amdgcn_sqrtf((float)((1.0 + p2) * (ux * ux + uy * uy + uz * uz) + ne * ne)) * (float)kInvES;
+}
+
 // Eq. (3) with |v| = 1: chi_ph = gamma_ph / E_S |k^ x (E + k^ x B)|.
 __device__ __forceinline__ double chi_photon(double kx, double ky, double kz,
                                              double ex, double ey, double ez,
@@ -106,6 +132,11 @@ __device__ __forceinline__ double chi_photon(double kx, double ky, double kz,
   return g * sqrt(ux * ux + uy * uy + uz * uz) * kInvES;
 }
 
+// Square root: the hardware instruction (1 ulp) in float32, correctly rounded in float64.
+template <typename R> __device__ __forceinline__ R root(R x);
+template <> __device__ __forceinline__ float root<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+template <> __device__ __forceinline__ double root<double>(double x) { return sqrt(x); }
+
 // Reciprocal: the hardware estimate (1 ulp) in float32, exact division in float64.
 template <typename R> __device__ __forceinline__ R rcp(R x);
 template <> __device__ __forceinline__ float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -118,7 +149,7 @@ __device__ __forceinline__ void boris(R &px, R &py, R &pz, R ex, R ey, R ez, R b
                                       R q, R dt) {
   const R h = (R)0.5 * q * dt;
   R mx = px + h * ex, my = py + h * ey, mz = pz + h * ez;
-  const R hg = h * rcp<R>(sqrt((R)1 + mx * mx + my * my + mz * mz));
+  const R hg = h * rcp<R>(root<R>((R)1 + mx * mx + my * my + mz * mz));
   const R tx = hg * bx, ty = hg * by, tz = hg * bz;
   const R ax = mx + (my * tz - mz * ty), ay = my + (mz * tx - mx * tz), az = mz + (mx * ty - my * tx);
   const R s = (R)2 * rcp<R>((R)1 + tx * tx + ty * ty + tz * tz);

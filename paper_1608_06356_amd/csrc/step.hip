@@ -35,6 +35,9 @@ struct FieldDev {
   const float *grid;
   double dx, dy, dz;
   double idx, idy, idz;      // inverse cell sizes
+  float fid[3];              // the same in float32
+  double L[3];               // box lengths n * d
+  float fL[3];
   double E[3], B[3];
   const float *pE[3], *pB[3];
 };
@@ -47,10 +50,22 @@ struct ScanDev {
 };
 
 // --------------------------------------------------------------- fields
+// x in [-L, 2L) -> [0, L) (one period at most per step); selects, no branches
 template <typename R>
 __device__ __forceinline__ void wrap_coord(R &x, R L) {
-  if (x < (R)0) x += L; else if (x >= L) x -= L;
+  const R lo = x + L, hi = x - L;
+  x = x < (R)0 ? lo : (x >= L ? hi : x);
 }
+
+// Inverse cell size and box length of axis d in the arithmetic type R.
+template <typename R> __device__ __forceinline__ R inv_cell(const FieldDev &f, int d);
+template <> __device__ __forceinline__ float inv_cell<float>(const FieldDev &f, int d) { return f.fid[d]; }
+template <> __device__ __forceinline__ double inv_cell<double>(const FieldDev &f, int d) {
+  return d == 0 ? f.idx : (d == 1 ? f.idy : f.idz);
+}
+template <typename R> __device__ __forceinline__ R box_len(const FieldDev &f, int d);
+template <> __device__ __forceinline__ float box_len<float>(const FieldDev &f, int d) { return f.fL[d]; }
+template <> __device__ __forceinline__ double box_len<double>(const FieldDev &f, int d) { return f.L[d]; }
 
 template <typename R>
 __device__ __forceinline__ void weights_tsc(R x, R inv_d, int n, int &j, R w[3]) {
@@ -74,9 +89,9 @@ __device__ __forceinline__ int wrap_index(int j, int n) {
 // [0, n]; n stands for node 0) and the three weights of nodes j-1, j, j+1.
 template <typename R>
 __device__ __forceinline__ void tsc_setup(const FieldDev &f, R x, R y, R z, int j[3], R w[3][3]) {
-  weights_tsc<R>(x, (R)f.idx, f.nx, j[0], w[0]);
-  weights_tsc<R>(y, (R)f.idy, f.ny, j[1], w[1]);
-  weights_tsc<R>(z, (R)f.idz, f.nz, j[2], w[2]);
+  weights_tsc<R>(x, inv_cell<R>(f, 0), f.nx, j[0], w[0]);
+  weights_tsc<R>(y, inv_cell<R>(f, 1), f.ny, j[1], w[1]);
+  weights_tsc<R>(z, inv_cell<R>(f, 2), f.nz, j[2], w[2]);
 }
 
 // TSC gather from the grid in global memory.  Offsets are 32-bit float
@@ -137,8 +152,8 @@ struct BoxLds {
 __device__ __forceinline__ int centred(int j, int ref, int n) {
   int r = j - ref;
   const int h = n >> 1;
-  if (r >= n - h) r -= n;
-  else if (r < -h) r += n;
+  r -= r >= n - h ? n : 0;
+  r += r < -h ? n : 0;
   return r;
 }
 
@@ -204,21 +219,46 @@ __device__ __forceinline__ bool stage_box(BoxLds &S, const FieldDev &f, bool liv
   }
   const int px = bdim[0] | 1, pxy = (px * bdim[1]) | 1;
   if ((int64_t)pxy * bdim[2] > kBoxCap) return false;
-  // copy the box: node p of the dense enumeration (x fastest) -> (x, y, z)
+  // copy the box: node p of the dense enumeration (x fastest) -> (x, y, z).
+  // The quotients use the hardware reciprocal (relative error below 2^-22):
+  // (p + 0.5) / d is at least 0.5 / d <= 2^-11 away from an integer and below
+  // 2^11, so the truncation is exact.
   const int bxy = bdim[0] * bdim[1], cnt = bxy * bdim[2];
-  const float inv_bx = 1.0f / (float)bdim[0], inv_bxy = 1.0f / (float)bxy;
-  for (int p = threadIdx.x; p < cnt; p += kGPThreads) {
-    const int z = (int)(((float)p + 0.5f) * inv_bxy);      // exact: p < 2^11, bxy <= 2^10
-    const int q = p - z * bxy;
-    const int y = (int)(((float)q + 0.5f) * inv_bx);
-    const int x = q - y * bdim[0];
-    const uint32_t gx = (uint32_t)wrap_index(ref[0] + bmin[0] + x, f.nx);
-    const uint32_t gy = (uint32_t)wrap_index(ref[1] + bmin[1] + y, f.ny);
-    const uint32_t gz = (uint32_t)wrap_index(ref[2] + bmin[2] + z, f.nz);
-    const float2 *g2 = reinterpret_cast<const float2 *>(f.grid + ((gz * (uint32_t)f.ny + gy) * (uint32_t)f.nx + gx) * 6u);
-    const float2 v0 = g2[0], v1 = g2[1], v2 = g2[2];
-    const int a = z * pxy + y * px + x;
-    S.node[3 * a] = v0; S.node[3 * a + 1] = v1; S.node[3 * a + 2] = v2;
+  const float inv_bx = __builtin_amdgcn_rcpf((float)bdim[0]), inv_bxy = __builtin_amdgcn_rcpf((float)bxy);
+  int g0[3];
+  bool inside = true;      // the box does not cross the periodic boundary
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    g0[d] = ref[d] + bmin[d];
+    inside = inside && g0[d] >= 0 && g0[d] + bdim[d] <= n3[d];
+  }
+  if (inside) {
+    const uint32_t sy = (uint32_t)f.nx, sz = (uint32_t)f.nx * (uint32_t)f.ny;
+    const float *gb = f.grid + ((uint32_t)g0[2] * sz + (uint32_t)g0[1] * sy + (uint32_t)g0[0]) * 6u;
+    for (int p = threadIdx.x; p < cnt; p += kGPThreads) {
+      const int z = (int)(((float)p + 0.5f) * inv_bxy);
+      const int q = p - z * bxy;
+      const int y = (int)(((float)q + 0.5f) * inv_bx);
+      const int x = q - y * bdim[0];
+      const float2 *g2 = reinterpret_cast<const float2 *>(gb + ((uint32_t)z * sz + (uint32_t)y * sy + (uint32_t)x) * 6u);
+      const float2 v0 = g2[0], v1 = g2[1], v2 = g2[2];
+      const int a = z * pxy + y * px + x;
+      S.node[3 * a] = v0; S.node[3 * a + 1] = v1; S.node[3 * a + 2] = v2;
+    }
+  } else {
+    for (int p = threadIdx.x; p < cnt; p += kGPThreads) {
+      const int z = (int)(((float)p + 0.5f) * inv_bxy);
+      const int q = p - z * bxy;
+      const int y = (int)(((float)q + 0.5f) * inv_bx);
+      const int x = q - y * bdim[0];
+      const uint32_t gx = (uint32_t)wrap_index(g0[0] + x, f.nx);
+      const uint32_t gy = (uint32_t)wrap_index(g0[1] + y, f.ny);
+      const uint32_t gz = (uint32_t)wrap_index(g0[2] + z, f.nz);
+      const float2 *g2 = reinterpret_cast<const float2 *>(f.grid + ((gz * (uint32_t)f.ny + gy) * (uint32_t)f.nx + gx) * 6u);
+      const float2 v0 = g2[0], v1 = g2[1], v2 = g2[2];
+      const int a = z * pxy + y * px + x;
+      S.node[3 * a] = v0; S.node[3 * a + 1] = v1; S.node[3 * a + 2] = v2;
+    }
   }
   // the stencil of every live particle lies inside the box by construction;
   // checked anyway, so that the LDS reads below can never leave it
@@ -359,12 +399,11 @@ __device__ __forceinline__ uint64_t tile_offset(uint32_t tile, uint32_t agg, uin
 constexpr int kXcds = 8;
 
 // Emitter record, written by the emitter to its own slot and read once by
-// k_emit: everything the event loop needs, in one or two cache lines.
+// k_emit: what the event loop needs beyond the particle's id.
 template <typename R>
 struct alignas(16) EmRec {
   R x[3], p[3], F[6];       // position after the push, momentum p^{n+1/2}, E and B at x^n
-  uint64_t id;
-  double chi, W, rem;       // chi and rate of the first event, time left after it
+  double tau, chi, W;       // optical depth at the start of the step, chi and rate
   int32_t j0, nsub;         // method I: sub-step of the first event, number of sub-steps
 };
 
@@ -422,11 +461,14 @@ __global__ __launch_bounds__(kGPThreads, (gp_waves<R, FK, M1>())) void k_gather_
   const int64_t n = *a.sp.count;
   const int64_t base = tile * kGPTile;
   if (base >= n) return;
-  R *X = (R *)a.sp.x, *Y = (R *)a.sp.y, *Z = (R *)a.sp.z;
-  R *PX = (R *)a.sp.px, *PY = (R *)a.sp.py, *PZ = (R *)a.sp.pz;
+  // the tile's slices of the arrays (uniform bases, 32-bit thread offsets)
+  const int t = threadIdx.x;
+  R *X = (R *)a.sp.x + base, *Y = (R *)a.sp.y + base, *Z = (R *)a.sp.z + base;
+  R *PX = (R *)a.sp.px + base, *PY = (R *)a.sp.py + base, *PZ = (R *)a.sp.pz + base;
+  double *TAU = a.sp.tau + base;
   FieldDev f = a.f;
   f.kind = FK;
-  const int64_t i = base + threadIdx.x;
+  const int64_t i = base + t;
   bool flag = false;
   uint32_t nnan = 0, nrange = 0;
   R F[6];
@@ -435,9 +477,9 @@ __global__ __launch_bounds__(kGPThreads, (gp_waves<R, FK, M1>())) void k_gather_
   R x = 0, y = 0, z = 0, px = 0, py = 0, pz = 0;
   double tau = 0.0;
   if (live) {
-    x = X[i]; y = Y[i]; z = Z[i];
-    px = PX[i]; py = PY[i]; pz = PZ[i];
-    tau = a.sp.tau[i];
+    x = X[t]; y = Y[t]; z = Z[t];
+    px = PX[t]; py = PY[t]; pz = PZ[t];
+    tau = TAU[t];
   }
   for (int k = threadIdx.x; k < kRadNChi; k += blockDim.x) lnh_s[k] = a.lnh[k];
   if (FK == QED_FIELD_GRID) {
@@ -460,15 +502,17 @@ __global__ __launch_bounds__(kGPThreads, (gp_waves<R, FK, M1>())) void k_gather_
   }
   if (live) {
     boris<R>(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5], a.q, a.dt);
-    const R g = sqrt((R)1 + px * px + py * py + pz * pz);
+    const R g = root<R>((R)1 + px * px + py * py + pz * pz);
     const R ig = rcp<R>(g), vdt = ig * a.dt;
     x += px * vdt; y += py * vdt; z += pz * vdt;
     if (FK == QED_FIELD_GRID) {
-      wrap_coord<R>(x, (R)(f.dx * f.nx)); wrap_coord<R>(y, (R)(f.dy * f.ny));
-      wrap_coord<R>(z, (R)(f.dz * f.nz));
+      wrap_coord<R>(x, box_len<R>(f, 0)); wrap_coord<R>(y, box_len<R>(f, 1));
+      wrap_coord<R>(z, box_len<R>(f, 2));
     }
-    X[i] = x; Y[i] = y; Z[i] = z; PX[i] = px; PY[i] = py; PZ[i] = pz;
-    const double chi = chi_lepton(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5]);
+    X[t] = x; Y[t] = y; Z[t] = z; PX[t] = px; PY[t] = py; PZ[t] = pz;
+    double chi;
+    if constexpr (sizeof(R) == 4) chi = chi_lepton_f32(px, py, pz, g, F);
+    else chi = chi_lepton(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5]);
     double W = 0.0;
     if (isfinite(chi)) {
       nrange = chi > a.rg.rad_hi;
@@ -492,19 +536,18 @@ __global__ __launch_bounds__(kGPThreads, (gp_waves<R, FK, M1>())) void k_gather_
       r.x[0] = x; r.x[1] = y; r.x[2] = z; r.p[0] = px; r.p[1] = py; r.p[2] = pz;
 #pragma unroll
       for (int c = 0; c < 6; ++c) r.F[c] = F[c];
-      r.id = a.sp.id[i];
+      r.tau = tau;
       r.chi = chi;
       r.W = W;
-      r.rem = a.dtd - tau / W;
       r.j0 = j0;
       r.nsub = nsub;
       a.rec[rec_slot(i, fbits)] = r;
     } else if (!(M1 && a.gen)) {
-      a.sp.tau[i] = tau - W * a.dtd;
+      TAU[t] = tau - W * a.dtd;
     }
   }
   const uint64_t bits = __ballot(flag);
-  if ((threadIdx.x & 63) == 0 && base + (threadIdx.x & ~63) < n) a.mask[(base + threadIdx.x) >> 6] = bits;
+  if ((t & 63) == 0 && base + (t & ~63) < n) a.mask[(base + t) >> 6] = bits;
   count_flags(a.counters, cNanChi, nnan != 0);
   count_flags(a.counters, cChiRange, nrange != 0);
 }
@@ -589,11 +632,11 @@ __device__ void emit_tile(const EmitArgs<R> &a, const Tab &tab, const R *lnh, ui
     R F[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) F[c] = rc.F[c];
-    double chi = rc.chi, W = rc.W, rem = rc.rem;
+    const uint64_t id = a.lep.id[i];
+    double chi = rc.chi, W = rc.W, rem = a.dtd - rc.tau / rc.W;   // time left after the first event
     R *PX = (R *)a.lep.px, *PY = (R *)a.lep.py, *PZ = (R *)a.lep.pz;
     R px = rc.p[0], py = rc.p[1], pz = rc.p[2];
     x = rc.x[0]; y = rc.x[1]; z = rc.x[2];
-    const uint64_t id = rc.id;
     const R pa = sqrt(px * px + py * py + pz * pz);
     if (pa > (R)0) { nx = px / pa; ny = py / pa; nz = pz / pa; }
     R g = sqrt((R)1 + px * px + py * py + pz * pz);
@@ -819,8 +862,8 @@ __global__ __launch_bounds__(kGPThreads, 4) void k_gather_push_mlp(GPArgs<float>
       g = sqrtf(1.f + px * px + py * py + pz * pz);
       x += px / g * a.dt; y += py / g * a.dt; z += pz / g * a.dt;
       if (FK == QED_FIELD_GRID) {
-        wrap_coord<float>(x, (float)(f.dx * f.nx)); wrap_coord<float>(y, (float)(f.dy * f.ny));
-        wrap_coord<float>(z, (float)(f.dz * f.nz));
+        wrap_coord<float>(x, box_len<float>(f, 0)); wrap_coord<float>(y, box_len<float>(f, 1));
+        wrap_coord<float>(z, box_len<float>(f, 2));
       }
       X[i] = x; Y[i] = y; Z[i] = z; PX[i] = px; PY[i] = py; PZ[i] = pz;
       chi = chi_lepton(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5]);
@@ -842,10 +885,9 @@ __global__ __launch_bounds__(kGPThreads, 4) void k_gather_push_mlp(GPArgs<float>
         r.x[0] = x; r.x[1] = y; r.x[2] = z; r.p[0] = px; r.p[1] = py; r.p[2] = pz;
 #pragma unroll
         for (int c = 0; c < 6; ++c) r.F[c] = F[c];
-        r.id = a.sp.id[i];
+        r.tau = tau;
         r.chi = chi;
         r.W = W;
-        r.rem = a.dtd - tau / W;
         a.rec[rec_slot(i, fbits)] = r;
       } else {
         a.sp.tau[i] = tau - W * a.dtd;
@@ -902,13 +944,13 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
     bool recoiled = false;
     if (valid) {
       i = a.em_idx[r];
+      id = a.lep.id[i];
       const EmRec<float> rc = a.rec[rec_slot(i, a.mask[i >> 6])];
 #pragma unroll
       for (int c = 0; c < 6; ++c) F[c] = rc.F[c];
-      chi = rc.chi; W = rc.W; rem = rc.rem;
+      chi = rc.chi; W = rc.W; rem = a.dtd - rc.tau / rc.W;
       px = rc.p[0]; py = rc.p[1]; pz = rc.p[2];
       x = rc.x[0]; y = rc.x[1]; z = rc.x[2];
-      id = rc.id;
       const float pa = sqrtf(px * px + py * py + pz * pz);
       if (pa > 0.f) { nx = px / pa; ny = py / pa; nz = pz / pa; }
       g = sqrtf(1.f + px * px + py * py + pz * pz);
@@ -1106,8 +1148,8 @@ __device__ void pair_tile(const PairArgs<R> &a, const Tab &tab, const R *L, uint
     if (a.move && gph > (R)0) {
       x += kx / gph * a.dt; y += ky / gph * a.dt; z += kz / gph * a.dt;
       if (a.f.kind == QED_FIELD_GRID) {
-        wrap_coord<R>(x, (R)(a.f.dx * a.f.nx)); wrap_coord<R>(y, (R)(a.f.dy * a.f.ny));
-        wrap_coord<R>(z, (R)(a.f.dz * a.f.nz));
+        wrap_coord<R>(x, box_len<R>(a.f, 0)); wrap_coord<R>(y, box_len<R>(a.f, 1));
+        wrap_coord<R>(z, box_len<R>(a.f, 2));
       }
       X[i] = x; Y[i] = y; Z[i] = z;
     }
@@ -1383,7 +1425,7 @@ __global__ void k_sample_f32(const double *chi, const double *gamma, const uint6
 // =============================================================== launchers
 namespace qed {
 
-static_assert(sizeof(EmRec<float>) == 96 && sizeof(EmRec<double>) == 144, "emitter record size");
+static_assert(sizeof(EmRec<float>) == 80 && sizeof(EmRec<double>) == kEmRecMaxBytes, "emitter record size");
 
 static SpeciesDev dev_species(const qed_species_t *s) {
   return SpeciesDev{s->x, s->y, s->z, s->px, s->py, s->pz, s->tau, s->id, s->capacity, s->count};
@@ -1394,7 +1436,12 @@ static FieldDev dev_fields(const qed_fields_t *f) {
   if (!f) { d.kind = QED_FIELD_UNIFORM; return d; }
   d.kind = f->kind; d.nx = f->nx; d.ny = f->ny; d.nz = f->nz; d.grid = f->grid;
   d.dx = f->dx; d.dy = f->dy; d.dz = f->dz;
-  if (f->kind == QED_FIELD_GRID) { d.idx = 1.0 / f->dx; d.idy = 1.0 / f->dy; d.idz = 1.0 / f->dz; }
+  if (f->kind == QED_FIELD_GRID) {
+    d.idx = 1.0 / f->dx; d.idy = 1.0 / f->dy; d.idz = 1.0 / f->dz;
+    d.fid[0] = (float)d.idx; d.fid[1] = (float)d.idy; d.fid[2] = (float)d.idz;
+    d.L[0] = f->dx * f->nx; d.L[1] = f->dy * f->ny; d.L[2] = f->dz * f->nz;
+    for (int c = 0; c < 3; ++c) d.fL[c] = (float)d.L[c];
+  }
   for (int c = 0; c < 3; ++c) { d.E[c] = f->E[c]; d.B[c] = f->B[c]; d.pE[c] = f->pE[c]; d.pB[c] = f->pB[c]; }
   return d;
 }
