@@ -11,6 +11,9 @@ LIB = os.path.join(HERE, "libqedmi.so")
 SOURCES = ["tables.hip", "step.hip", "mlp.hip", "sort.hip", "api.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-fvisibility=hidden"]
+# step.hip: every atomic there is issued by chosen lanes on purpose (row leaders,
+# lane 0); the compiler's atomic optimizer would turn each into a loop over lanes.
+EXTRA = {"step.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
 
 
 def hipcc():
@@ -26,7 +29,7 @@ def build(verbose=False):
 
     def one(src):
         obj = os.path.join(OBJ, src + ".o")
-        cmd = [cc, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [cc, *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")

@@ -103,14 +103,17 @@ __device__ __forceinline__ void gather_global(const FieldDev &f, const int j[3],
   for (int a = 0; a < 3; ++a) ox[a] = (uint32_t)wrap_index(j[0] + a - 1, f.nx) * 6u;
 #pragma unroll
   for (int c = 0; c < 6; ++c) F[c] = (R)0;
+  const uint32_t sy6 = (uint32_t)f.nx * 6u, sz6 = sy6 * (uint32_t)f.ny;
+  uint32_t oy[3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) oy[b] = (uint32_t)wrap_index(j[1] + b - 1, f.ny) * sy6;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const uint32_t iz = (uint32_t)wrap_index(j[2] + c - 1, f.nz);
+    const uint32_t oz = (uint32_t)wrap_index(j[2] + c - 1, f.nz) * sz6;
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-      const uint32_t iy = (uint32_t)wrap_index(j[1] + b - 1, f.ny);
       const R wyz = w[1][b] * w[2][c];
-      const uint32_t row = (iz * (uint32_t)f.ny + iy) * (uint32_t)f.nx * 6u;
+      const uint32_t row = oz + oy[b];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         const float2 *p2 = reinterpret_cast<const float2 *>(f.grid + (row + ox[a]));
@@ -144,7 +147,7 @@ constexpr int kGPWaves = 6;     // LDS allows 6 workgroups of 256 threads per CU
 struct BoxLds {
   float2 node[kBoxCap * 3];     // 6 floats per node; node (x, y, z) at z * pxy + y * px + x
   int ref[3];                   // centre node of the workgroup's first particle
-  int lo[kGPThreads / 64][3], hi[kGPThreads / 64][3];
+  int lo[3], hi[3];             // extremes of the centre nodes relative to ref
   int bad;                      // a particle's stencil left the box (then: global gather)
 };
 
@@ -157,25 +160,23 @@ __device__ __forceinline__ int centred(int j, int ref, int n) {
   return r;
 }
 
-// Minimum or maximum over the 64 lanes of a wave with DPP moves (quad
-// permutations, half-row and row mirrors, row broadcasts 15 and 31); the
-// result collects in lane 63 and is returned to every lane.
+// Minimum or maximum over each row of 16 lanes with DPP moves (quad
+// permutations, half-row and row mirrors); every lane of a row gets its row's
+// result.
 template <bool Max>
-__device__ __forceinline__ int wave_extreme(int v) {
+__device__ __forceinline__ int row_extreme(int v) {
   const int id = Max ? INT_MIN : INT_MAX;
-#define QED_DPP_STEP(ctrl, rows)                                                   \
+#define QED_DPP_STEP(ctrl)                                                        \
   {                                                                               \
-    const int t = __builtin_amdgcn_update_dpp(id, v, ctrl, rows, 0xF, false);     \
+    const int t = __builtin_amdgcn_update_dpp(id, v, ctrl, 0xF, 0xF, false);      \
     v = Max ? max(v, t) : min(v, t);                                              \
   }
-  QED_DPP_STEP(0xB1, 0xF)    // quad_perm [1,0,3,2]
-  QED_DPP_STEP(0x4E, 0xF)    // quad_perm [2,3,0,1]
-  QED_DPP_STEP(0x141, 0xF)   // row_half_mirror
-  QED_DPP_STEP(0x140, 0xF)   // row_mirror
-  QED_DPP_STEP(0x142, 0xA)   // row_bcast:15 into rows 1 and 3
-  QED_DPP_STEP(0x143, 0xC)   // row_bcast:31 into rows 2 and 3
+  QED_DPP_STEP(0xB1)    // quad_perm [1,0,3,2]
+  QED_DPP_STEP(0x4E)    // quad_perm [2,3,0,1]
+  QED_DPP_STEP(0x141)   // row_half_mirror
+  QED_DPP_STEP(0x140)   // row_mirror
 #undef QED_DPP_STEP
-  return __builtin_amdgcn_readlane(v, 63);
+  return v;
 }
 
 // Box of the workgroup.  Every thread calls it; live: the thread holds a
@@ -192,27 +193,24 @@ __device__ __forceinline__ bool stage_box(BoxLds &S, const FieldDev &f, bool liv
   for (int d = 0; d < 3; ++d) jj[d] = j[d] == n3[d] ? 0 : j[d];
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) S.ref[d] = jj[d];
+    for (int d = 0; d < 3; ++d) { S.ref[d] = jj[d]; S.lo[d] = INT_MAX; S.hi[d] = INT_MIN; }
     S.bad = 0;
   }
   __syncthreads();
-  const int wv = threadIdx.x >> 6;
+  // row extremes, then one LDS atomic per row of 16 lanes
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     rel[d] = centred(jj[d], S.ref[d], n3[d]);
-    const int lo = wave_extreme<false>(live ? rel[d] : INT_MAX);
-    const int hi = wave_extreme<true>(live ? rel[d] : INT_MIN);
-    if ((threadIdx.x & 63) == 0) { S.lo[wv][d] = lo; S.hi[wv][d] = hi; }
+    const int lo = row_extreme<false>(live ? rel[d] : INT_MAX);
+    const int hi = row_extreme<true>(live ? rel[d] : INT_MIN);
+    if ((threadIdx.x & 15) == 0) { atomicMin(&S.lo[d], lo); atomicMax(&S.hi[d], hi); }
   }
   __syncthreads();
   int bmin[3], bdim[3], ref[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    int l = INT_MAX, h = INT_MIN;
-#pragma unroll
-    for (int k = 0; k < kGPThreads / 64; ++k) { l = min(l, S.lo[k][d]); h = max(h, S.hi[k][d]); }
-    l = __builtin_amdgcn_readfirstlane(l);
-    h = __builtin_amdgcn_readfirstlane(h);
+    const int l = __builtin_amdgcn_readfirstlane(S.lo[d]);
+    const int h = __builtin_amdgcn_readfirstlane(S.hi[d]);
     ref[d] = __builtin_amdgcn_readfirstlane(S.ref[d]);
     bmin[d] = l - 1;
     bdim[d] = h - l + 3;
@@ -232,32 +230,38 @@ __device__ __forceinline__ bool stage_box(BoxLds &S, const FieldDev &f, bool liv
     g0[d] = ref[d] + bmin[d];
     inside = inside && g0[d] >= 0 && g0[d] + bdim[d] <= n3[d];
   }
+  // box coordinates are below 2^11 and pitches below 2^11 (24-bit products);
+  // the grid plane stride in floats may exceed 2^24 (full 32-bit product)
+  unsigned char *lds = reinterpret_cast<unsigned char *>(S.node);
   if (inside) {
-    const uint32_t sy = (uint32_t)f.nx, sz = (uint32_t)f.nx * (uint32_t)f.ny;
-    const float *gb = f.grid + ((uint32_t)g0[2] * sz + (uint32_t)g0[1] * sy + (uint32_t)g0[0]) * 6u;
+    const uint32_t sy6 = (uint32_t)f.nx * 6u, sz6 = (uint32_t)f.nx * (uint32_t)f.ny * 6u;
+    const float *gb = f.grid + (uint32_t)g0[2] * sz6 + (uint32_t)g0[1] * sy6 + (uint32_t)g0[0] * 6u;
     for (int p = threadIdx.x; p < cnt; p += kGPThreads) {
-      const int z = (int)(((float)p + 0.5f) * inv_bxy);
-      const int q = p - z * bxy;
-      const int y = (int)(((float)q + 0.5f) * inv_bx);
-      const int x = q - y * bdim[0];
-      const float2 *g2 = reinterpret_cast<const float2 *>(gb + ((uint32_t)z * sz + (uint32_t)y * sy + (uint32_t)x) * 6u);
+      const uint32_t z = (uint32_t)(((float)p + 0.5f) * inv_bxy);
+      const uint32_t q = (uint32_t)p - __umul24(z, (uint32_t)bxy);
+      const uint32_t y = (uint32_t)(((float)q + 0.5f) * inv_bx);
+      const uint32_t x = q - __umul24(y, (uint32_t)bdim[0]);
+      const uint32_t go = z * sz6 + (y * sy6 + __umul24(x, 6u));
+      const float2 *g2 = reinterpret_cast<const float2 *>(gb + go);
       const float2 v0 = g2[0], v1 = g2[1], v2 = g2[2];
-      const int a = z * pxy + y * px + x;
-      S.node[3 * a] = v0; S.node[3 * a + 1] = v1; S.node[3 * a + 2] = v2;
+      const uint32_t a = __umul24(z, (uint32_t)pxy) + __umul24(y, (uint32_t)px) + x;
+      float2 *d = reinterpret_cast<float2 *>(lds + __umul24(a, 24u));
+      d[0] = v0; d[1] = v1; d[2] = v2;
     }
   } else {
     for (int p = threadIdx.x; p < cnt; p += kGPThreads) {
       const int z = (int)(((float)p + 0.5f) * inv_bxy);
-      const int q = p - z * bxy;
+      const int q = p - (int)__umul24((uint32_t)z, (uint32_t)bxy);
       const int y = (int)(((float)q + 0.5f) * inv_bx);
-      const int x = q - y * bdim[0];
+      const int x = q - (int)__umul24((uint32_t)y, (uint32_t)bdim[0]);
       const uint32_t gx = (uint32_t)wrap_index(g0[0] + x, f.nx);
       const uint32_t gy = (uint32_t)wrap_index(g0[1] + y, f.ny);
       const uint32_t gz = (uint32_t)wrap_index(g0[2] + z, f.nz);
       const float2 *g2 = reinterpret_cast<const float2 *>(f.grid + ((gz * (uint32_t)f.ny + gy) * (uint32_t)f.nx + gx) * 6u);
       const float2 v0 = g2[0], v1 = g2[1], v2 = g2[2];
-      const int a = z * pxy + y * px + x;
-      S.node[3 * a] = v0; S.node[3 * a + 1] = v1; S.node[3 * a + 2] = v2;
+      const uint32_t a = __umul24((uint32_t)z, (uint32_t)pxy) + __umul24((uint32_t)y, (uint32_t)px) + (uint32_t)x;
+      float2 *d = reinterpret_cast<float2 *>(lds + __umul24(a, 24u));
+      d[0] = v0; d[1] = v1; d[2] = v2;
     }
   }
   // the stencil of every live particle lies inside the box by construction;
@@ -275,25 +279,36 @@ __device__ __forceinline__ bool stage_box(BoxLds &S, const FieldDev &f, bool liv
   return S.bad == 0;
 }
 
+// Gather from the staged box.  A row of the stencil (three nodes along x) is
+// 72 contiguous bytes of LDS; row offsets are byte offsets built from the
+// pitches with adds only, and the next row's reads are issued before the
+// current row's products so that LDS latency overlaps the arithmetic.
 template <typename R>
 __device__ __forceinline__ void gather_box(const BoxLds &S, const int c0[3], const int pit[2], const R w[3][3],
                                            R F[6]) {
 #pragma unroll
   for (int c = 0; c < 6; ++c) F[c] = (R)0;
-  const int base = (c0[2] * pit[1] + c0[1] * pit[0]) + c0[0];
+  const uint32_t pb0 = (uint32_t)pit[0] * 24u, pb1 = (uint32_t)pit[1] * 24u;   // uniform
+  const uint32_t b0 = (uint32_t)__umul24((uint32_t)c0[2], pb1) + (uint32_t)__umul24((uint32_t)c0[1], pb0) +
+                      (uint32_t)c0[0] * 24u;
+  const unsigned char *lds = reinterpret_cast<const unsigned char *>(S.node);
+  float2 v[2][9];
+  auto load_row = [&](float2 *dst, int r) {
+    const float2 *q = reinterpret_cast<const float2 *>(lds + b0 + (uint32_t)(r / 3) * pb1 + (uint32_t)(r % 3) * pb0);
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
+    for (int k = 0; k < 9; ++k) dst[k] = q[k];
+  };
+  load_row(v[0], 0);
 #pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      const R wyz = w[1][b] * w[2][c];
-      const int row = base + c * pit[1] + b * pit[0];
+  for (int r = 0; r < 9; ++r) {
+    if (r + 1 < 9) load_row(v[(r + 1) & 1], r + 1);
+    const float2 *u = v[r & 1];
+    const R wyz = w[1][r % 3] * w[2][r / 3];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const float2 v0 = S.node[3 * (row + a)], v1 = S.node[3 * (row + a) + 1], v2 = S.node[3 * (row + a) + 2];
-        const R wt = w[0][a] * wyz;
-        F[0] += wt * (R)v0.x; F[1] += wt * (R)v0.y; F[2] += wt * (R)v1.x;
-        F[3] += wt * (R)v1.y; F[4] += wt * (R)v2.x; F[5] += wt * (R)v2.y;
-      }
+    for (int a = 0; a < 3; ++a) {
+      const R wt = w[0][a] * wyz;
+      F[0] += wt * (R)u[3 * a].x; F[1] += wt * (R)u[3 * a].y; F[2] += wt * (R)u[3 * a + 1].x;
+      F[3] += wt * (R)u[3 * a + 1].y; F[4] += wt * (R)u[3 * a + 2].x; F[5] += wt * (R)u[3 * a + 2].y;
     }
   }
 }
@@ -325,8 +340,9 @@ __device__ __forceinline__ void count_add(unsigned long long *c, int which, uint
   if (lane == 0 && s) atomicAdd(&c[which], (unsigned long long)s);
 }
 
-// Sum over the 64 lanes of a wave with DPP moves (the pattern of
-// wave_extreme); every lane gets the total.
+// Sum over the 64 lanes of a wave with DPP moves: the row steps of
+// row_extreme, then row broadcasts 15 and 31; the total collects in lane 63 and
+// is returned to every lane.
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 #define QED_DPP_ADD(ctrl, rows) v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, ctrl, rows, 0xF, false);
   QED_DPP_ADD(0xB1, 0xF)    // quad_perm [1,0,3,2]
