@@ -47,7 +47,12 @@ __global__ void k_permute(const R *sx, const R *sy, const R *sz, const R *spx, c
                           double *dtau, uint64_t *did, const uint32_t *perm, const int64_t *count,
                           int64_t *dcount) {
   const int64_t n = *count;
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+  // gridDim.x is a multiple of 8: block b takes chunk (b % 8) * (gridDim.x / 8) + b / 8, so
+  // that each XCD (blocks are dealt round-robin over the 8) gathers from one
+  // contiguous stretch of the sorted order and its L2 keeps that stretch's
+  // source lines
+  const int64_t lb = (int64_t)(blockIdx.x % 8u) * (gridDim.x / 8u) + blockIdx.x / 8u;
+  for (int64_t j = lb * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t i = perm[j];
     dx_[j] = sx[i]; dy_[j] = sy[i]; dz_[j] = sz[i];
     dpx[j] = spx[i]; dpy[j] = spy[i]; dpz[j] = spz[i];
@@ -84,7 +89,8 @@ hipError_t sort_impl(qed_ctx *c, const qed_fields_t *f, const qed_species_t *s, 
   }
   if ((e = rocprim::radix_sort_pairs(c->sort_tmp, need, k0, k1, v0, v1, (size_t)cap, 0u, bits, st)) != hipSuccess)
     return e;
-  hipLaunchKernelGGL(k_permute<R>, dim3((unsigned)blocks), dim3(256), 0, st, (const R *)s->x, (const R *)s->y,
+  const int64_t pblocks = (blocks + 7) / 8 * 8;
+  hipLaunchKernelGGL(k_permute<R>, dim3((unsigned)pblocks), dim3(256), 0, st, (const R *)s->x, (const R *)s->y,
                      (const R *)s->z, (const R *)s->px, (const R *)s->py, (const R *)s->pz, s->tau, s->id,
                      (R *)d->x, (R *)d->y, (R *)d->z, (R *)d->px, (R *)d->py, (R *)d->pz, d->tau, d->id, v1,
                      s->count, d->count);
