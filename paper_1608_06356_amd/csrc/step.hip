@@ -568,11 +568,12 @@ __global__ __launch_bounds__(kGPThreads, (gp_waves<R, FK, M1>())) void k_gather_
   count_flags(a.counters, cChiRange, nrange != 0);
 }
 
-// Ordered emitter list from the ballot mask: each thread owns one 64-bit word
-// (a tile is 256 words = 16384 particles); popcounts are scanned across the
+// Ordered emitter list from the ballot mask: each thread owns kEIWords
+// consecutive 64-bit words (a tile is 2048 words = 131072 particles, so the
+// look-back chain across tiles stays short); popcounts are scanned across the
 // workgroup and across tiles (decoupled look-back), and every set bit writes
 // its particle index at its rank.
-constexpr int kEIThreads = 256, kEITile = kEIThreads * 64;
+constexpr int kEIThreads = 256, kEIWords = 8, kEITile = kEIThreads * kEIWords * 64;
 
 __global__ __launch_bounds__(kEIThreads) void k_emit_index(const uint64_t *mask, const int64_t *count,
                                                            int32_t *em_idx, int64_t *n_emit, ScanDev sc,
@@ -587,19 +588,28 @@ __global__ __launch_bounds__(kEIThreads) void k_emit_index(const uint64_t *mask,
     if (tile == 0 && threadIdx.x == 0) *n_emit = 0;
     return;
   }
-  const int64_t w = (base >> 6) + threadIdx.x;
-  uint64_t m = (w << 6) < n ? mask[w] : 0ull;
-  const int64_t valid = n - (w << 6);
-  if (valid < 64 && valid > 0) m &= (1ull << valid) - 1ull;
-  const uint32_t c = (uint32_t)__popcll(m);
+  const int64_t w0 = (base >> 6) + (int64_t)threadIdx.x * kEIWords;
+  uint64_t m[kEIWords];
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < kEIWords; ++k) {
+    const int64_t w = w0 + k;
+    m[k] = (w << 6) < n ? mask[w] : 0ull;
+    const int64_t valid = n - (w << 6);
+    if (valid < 64 && valid > 0) m[k] &= (1ull << valid) - 1ull;
+    c += (uint32_t)__popcll(m[k]);
+  }
   uint32_t total;
   const uint32_t off = block_exclusive(c, scan_s, &total);
   const uint64_t toff = tile_offset(tile, total, sc.status, counters, &off_s);
   uint64_t r = toff + off;
-  while (m) {
-    const int b = __ffsll((long long)m) - 1;
-    em_idx[r++] = (int32_t)((w << 6) + b);
-    m &= m - 1ull;
+#pragma unroll
+  for (int k = 0; k < kEIWords; ++k) {
+    uint64_t b = m[k];
+    while (b) {
+      em_idx[r++] = (int32_t)(((w0 + k) << 6) + (__ffsll((long long)b) - 1));
+      b &= b - 1ull;
+    }
   }
   const int64_t last = (n - 1) / kEITile;
   if ((int64_t)tile == last && threadIdx.x == 0) *n_emit = (int64_t)(toff + total);
@@ -748,11 +758,10 @@ __device__ void emit_tile(const EmitArgs<R> &a, const Tab &tab, const R *lnh, ui
   }
 }
 
-// float path: 16-bit quantile table + float32 ln h staged in LDS
+// float path: 16-bit quantile table read through the caches (an emission step
+// touches few rows), float32 ln h staged in LDS
 template <bool M1>
 __global__ __launch_bounds__(kEmitThreads) void k_emit_f32(EmitArgs<float> a) {
-  __shared__ uint4 q_s[kRadNChi * kNU / 8];
-  __shared__ float s0sc_s[2 * kRadNChi];
   __shared__ float lnh_s[kRadNChi];
   __shared__ uint32_t scan_s[16];
   __shared__ uint32_t tile_s;
@@ -765,11 +774,8 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_f32(EmitArgs<float> a) {
   const int64_t n_em = hdr_s[0], ph0 = hdr_s[1];
   const uint64_t id0 = (uint64_t)hdr_s[2];
   if (n_em == 0) return;
-  const uint4 *gq = reinterpret_cast<const uint4 *>(a.q16);
-  for (int k = threadIdx.x; k < kRadNChi * kNU / 8; k += blockDim.x) q_s[k] = gq[k];
-  for (int k = threadIdx.x; k < 2 * kRadNChi; k += blockDim.x) s0sc_s[k] = a.s0sc[k];
   for (int k = threadIdx.x; k < kRadNChi; k += blockDim.x) lnh_s[k] = a.lnh[k];
-  const RowQ16 tab{reinterpret_cast<const uint16_t *>(q_s), s0sc_s};
+  const RowQ16 tab{a.q16, a.s0sc};     // 16-bit quantile table through the caches
   while (true) {
     const uint32_t tile = next_tile(a.sc.ticket, &tile_s);
     if ((int64_t)tile * kEmitThreads >= n_em) break;
@@ -1552,7 +1558,10 @@ hipError_t launch_emit(qed_ctx *c, const qed_species_t *lep, const qed_species_t
   if ((e = zero_scan(c, ntiles, st)) != hipSuccess) return e;
   const ScanDev sc{c->d_ticket, c->d_status};
   const int recoil = (c->params.flags & QED_FLAG_NO_RECOIL) ? 0 : 1;
-  const unsigned grid = (unsigned)(ntiles < c->n_cu ? ntiles : c->n_cu);
+  // persistent workgroups: one per CU for the surrogate (its nets fill the LDS),
+  // up to four per CU otherwise
+  const int64_t wgs = use_mlp ? (int64_t)c->n_cu : 4 * (int64_t)c->n_cu;
+  const unsigned grid = (unsigned)(ntiles < wgs ? ntiles : wgs);
   const int64_t *dstep = step < 0 ? c->d_step : nullptr;
   if (use_mlp) {
     EmitArgs<float> a{dev_species(lep), dev_species(ph), c->rad_lnh32, c->rad_S64, c->rad_q16,
