@@ -6,7 +6,7 @@ state with float64 chi and optical depth, formula II tables, dt = 0.01.  One
 step = refill the grid for t = n dt, gather/push every electron, finish every
 emission event, append the photons (stream-compacted) and compact the photon
 arrays (a no-op on the device while no photon has been removed), plus a stable
-re-sort of the electrons by grid cell every 20 steps.  Inputs are resident
+re-sort of the electrons by grid cell every 15 steps.  Inputs are resident
 in HBM before timing; table build and initialisation are outside the timed
 region.
 
@@ -76,7 +76,7 @@ def parse():
                     help="after timing, copy 1 GiB with torch (reference kernel for HBM counters)")
     ap.add_argument("--presort", type=int, default=1,
                     help="order the initial electrons by grid cell (outside the timed region)")
-    ap.add_argument("--sort-every", type=int, default=20,
+    ap.add_argument("--sort-every", type=int, default=15,
                     help="re-sort electrons by cell every K steps inside the timed loop (0: never)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-other-configs", action="store_true",
