@@ -568,13 +568,16 @@ __global__ __launch_bounds__(kGPThreads, (gp_waves<R, FK, M1>())) void k_gather_
   count_flags(a.counters, cChiRange, nrange != 0);
 }
 
-// Ordered emitter list from the ballot mask: each thread owns kEIWords
-// consecutive 64-bit words (a tile is 2048 words = 131072 particles, so the
-// look-back chain across tiles stays short); popcounts are scanned across the
-// workgroup and across tiles (decoupled look-back), and every set bit writes
-// its particle index at its rank.
-constexpr int kEIThreads = 256, kEIWords = 8, kEITile = kEIThreads * kEIWords * 64;
+// Ordered emitter list from the ballot mask: each thread owns W consecutive
+// 64-bit words; popcounts are scanned across the workgroup and across tiles
+// (decoupled look-back), and every set bit writes its particle index at its
+// rank.  Large species take W = 8 (tiles of 131072 particles, a short look-back
+// chain), small ones W = 1 (more workgroups).
+constexpr int kEIThreads = 256;
+template <int W> constexpr int64_t ei_tile() { return (int64_t)kEIThreads * W * 64; }
+constexpr int64_t kEIWideFrom = (int64_t)1 << 22;   // capacity from which W = 8
 
+template <int W>
 __global__ __launch_bounds__(kEIThreads) void k_emit_index(const uint64_t *mask, const int64_t *count,
                                                            int32_t *em_idx, int64_t *n_emit, ScanDev sc,
                                                            unsigned long long *counters) {
@@ -583,16 +586,16 @@ __global__ __launch_bounds__(kEIThreads) void k_emit_index(const uint64_t *mask,
   __shared__ uint64_t off_s;
   const uint32_t tile = next_tile(sc.ticket, &tile_s);
   const int64_t n = *count;
-  const int64_t base = (int64_t)tile * kEITile;
+  const int64_t base = (int64_t)tile * ei_tile<W>();
   if (base >= n) {
     if (tile == 0 && threadIdx.x == 0) *n_emit = 0;
     return;
   }
-  const int64_t w0 = (base >> 6) + (int64_t)threadIdx.x * kEIWords;
-  uint64_t m[kEIWords];
+  const int64_t w0 = (base >> 6) + (int64_t)threadIdx.x * W;
+  uint64_t m[W];
   uint32_t c = 0;
 #pragma unroll
-  for (int k = 0; k < kEIWords; ++k) {
+  for (int k = 0; k < W; ++k) {
     const int64_t w = w0 + k;
     m[k] = (w << 6) < n ? mask[w] : 0ull;
     const int64_t valid = n - (w << 6);
@@ -604,14 +607,14 @@ __global__ __launch_bounds__(kEIThreads) void k_emit_index(const uint64_t *mask,
   const uint64_t toff = tile_offset(tile, total, sc.status, counters, &off_s);
   uint64_t r = toff + off;
 #pragma unroll
-  for (int k = 0; k < kEIWords; ++k) {
+  for (int k = 0; k < W; ++k) {
     uint64_t b = m[k];
     while (b) {
       em_idx[r++] = (int32_t)(((w0 + k) << 6) + (__ffsll((long long)b) - 1));
       b &= b - 1ull;
     }
   }
-  const int64_t last = (n - 1) / kEITile;
+  const int64_t last = (n - 1) / ei_tile<W>();
   if ((int64_t)tile == last && threadIdx.x == 0) *n_emit = (int64_t)(toff + total);
 }
 
@@ -1245,7 +1248,9 @@ __device__ void pair_tile(const PairArgs<R> &a, const Tab &tab, const R *L, uint
   }
 }
 
-__global__ __launch_bounds__(kPairThreads) void k_pairs_f32(PairArgs<float> a) {
+// three waves per SIMD (at most 168 registers): its four photons per thread
+// otherwise take 172 and two waves
+__global__ __launch_bounds__(kPairThreads, 3) void k_pairs_f32(PairArgs<float> a) {
   __shared__ float L_s[kPairNRate];
   __shared__ uint64_t scan_s[16];
   __shared__ uint32_t tile_s;
@@ -1546,10 +1551,16 @@ hipError_t launch_emit(qed_ctx *c, const qed_species_t *lep, const qed_species_t
                        hipStream_t st) {
   const bool use_mlp = lep->dtype == QED_F32 && (c->params.flags & QED_FLAG_SURROGATE);
   // ordered emitter list from the mask of the last gather/push
-  const int64_t etiles = (lep->capacity + kEITile - 1) / kEITile;
+  const bool wide = lep->capacity >= kEIWideFrom;
+  const int64_t eit = wide ? ei_tile<8>() : ei_tile<1>();
+  const int64_t etiles = (lep->capacity + eit - 1) / eit;
   hipError_t e = zero_scan(c, etiles, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_emit_index, dim3((unsigned)etiles), dim3(kEIThreads), 0, st, c->em_mask, lep->count,
+  if (wide)
+    hipLaunchKernelGGL(k_emit_index<8>, dim3((unsigned)etiles), dim3(kEIThreads), 0, st, c->em_mask, lep->count,
+                     c->em_idx, c->d_n_emit, ScanDev{c->d_ticket, c->d_status}, c->d_counters);
+  else
+    hipLaunchKernelGGL(k_emit_index<1>, dim3((unsigned)etiles), dim3(kEIThreads), 0, st, c->em_mask, lep->count,
                      c->em_idx, c->d_n_emit, ScanDev{c->d_ticket, c->d_status}, c->d_counters);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // the scan needs one zeroed status word per tile of this kernel's tile size
