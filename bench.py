@@ -40,6 +40,8 @@ HBM_PEAK_GBS = 8000.0
 # the pair workload from their drawn chi_ph
 E_S_1UM = 510998.95 / 1.239841984
 PROFILE = os.path.join(ROOT, "profiles", "gather_push_standing_wave_1e7.md")
+# sources the gather/push kernel is compiled from (the counters hold while they are unchanged)
+PROFILED_SOURCES = ("step.hip", "qed_device.h", "lookup.h")
 
 
 def measured_traffic():
@@ -48,7 +50,8 @@ def measured_traffic():
     import hashlib
     try:
         text = open(PROFILE).read()
-        src = open(os.path.join(ROOT, "paper_1608_06356_amd", "csrc", "step.hip"), "rb").read()
+        src = b"".join(open(os.path.join(ROOT, "paper_1608_06356_amd", "csrc", f), "rb").read()
+                       for f in PROFILED_SOURCES)
     except OSError:
         return None
     vals = dict(l.split(": ", 1) for l in text.splitlines() if l.startswith(("traffic_bytes_per_launch", "source")))
