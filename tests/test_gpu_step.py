@@ -4,7 +4,7 @@ import math
 import numpy as np
 import pytest
 
-from oracle import mc, tables
+from oracle import mc, spectra, tables
 from oracle.constants import E_S
 from tests.gpu_helpers import need_gpu
 
@@ -100,6 +100,57 @@ def test_uniform_field_f64_parity(rad_table_I):
         np.testing.assert_allclose(gph["p"], ph_ref["k"], rtol=1e-10, atol=1e-9)
         np.testing.assert_allclose(gph["tau"], ph_ref["tau"], rtol=1e-12)
         np.testing.assert_allclose(gph["x"], ph_ref["x"], rtol=1e-11, atol=1e-9)
+
+
+def test_f32_chi_where_fields_cancel(rad_table_I):
+    """Float32 path, chi (Eq. 2) where E + v x B nearly cancels: a uniform crossed
+    field E = E0 y, B = E0 z (a plane wave moving along +x) and electrons moving
+    within 1e-2 rad of +x (chi ~ gamma (1 - beta) E0 / E_S, down to ~2e-6) or of -x
+    (chi up to ~20).  The rate each electron applied to its optical depth,
+    W = (tau0 - tau1) / dt, is compared with the oracle's rate (the same table) at
+    the oracle's chi of the GPU's pushed float32 momentum; a float32 evaluation
+    of Eq. 2 would be off by ~1e-7 gamma^2 in the co-moving half.  The oracle's
+    float64 chi is itself checked against an 80-bit evaluation of Eq. 2."""
+    torch, q = need_gpu()
+    rng = np.random.default_rng(5)
+    n, E0, dt, tau0 = 20000, 2000.0, 1e-3, 50.0
+    gam = 10.0 ** rng.uniform(1.0, 3.0, n)
+    th = rng.uniform(0.0, 1e-2, n) * np.where(np.arange(n) % 2 == 0, 1.0, 0.0)
+    th[np.arange(n) % 4 == 1] = 0.0
+    ph = rng.uniform(0.0, 2.0 * math.pi, n)
+    sgn = np.where(np.arange(n) % 4 == 3, -1.0, 1.0)     # a quarter counter-propagating
+    pa = np.sqrt(gam ** 2 - 1.0)
+    p = np.stack([sgn * pa * np.cos(th), pa * np.sin(th) * np.cos(ph), pa * np.sin(th) * np.sin(ph)], -1)
+    p = p.astype(np.float32).astype(np.float64)
+    ctx = q.Context(seed=2, kmax=4)
+    ctx.qed_build_tables(q.QED_FORMULA_I)
+    lep = q.Species(n, "f32")
+    ids = np.arange(n, dtype=np.uint64)
+    lep.load(np.zeros((n, 3)), p, np.full(n, tau0), ids)
+    ctx.qed_set_next_id(n)
+    fld = q.Fields(q.QED_FIELD_UNIFORM, E=(0.0, E0, 0.0), B=(0.0, 0.0, E0))
+    ctx.qed_gather_push(fld, lep, -1, dt, 0)
+    st, _ = ctx.qed_get_status()
+    g = lep.to_numpy()
+    assert st["events"] == 0 and st["nan_chi"] == 0
+    w_gpu = (tau0 - g["tau"]) / dt
+    p1 = g["p"]
+    E = np.tile([0.0, E0, 0.0], (n, 1))
+    B = np.tile([0.0, 0.0, E0], (n, 1))
+    chi = spectra.chi_lepton(p1, E, B)
+    # 80-bit reference of Eq. 2 on the same inputs
+    pl = p1.astype(np.longdouble)
+    gl = np.sqrt(1 + np.sum(pl * pl, -1))
+    vl = pl / gl[:, None]
+    fl = E.astype(np.longdouble) + np.cross(vl, B.astype(np.longdouble))
+    chil = gl / E_S * np.sqrt(np.sum(fl * fl, -1) - np.sum(vl * E, -1) ** 2)
+    assert np.max(np.abs(chi / chil.astype(np.float64) - 1.0)) < 1e-9
+    assert chi.min() < 1e-5 and chi.max() > 5.0
+    w_ref = tables.rate_rad(rad_table_I, chi, np.sqrt(1.0 + np.sum(p1 * p1, -1)))
+    rel = np.abs(w_gpu / w_ref - 1.0)
+    print(f"chi {chi.min():.2e} .. {chi.max():.2e}; rate rel. error max {rel.max():.2e} (co-moving "
+          f"{rel[sgn > 0].max():.2e})")
+    assert rel.max() < 2e-5
 
 
 def test_uniform_b_full_size_subsample(rad_table_I):
