@@ -320,12 +320,16 @@ def run_sampler(q, torch, weights, n=100_000_000, reps=5):
     return out
 
 
-def run_cascade(q, torch, weights, n=20_000_000, steps=100, dt=0.01, a0=1000.0, ngrid=128, sort_every=20):
+def run_cascade(q, torch, weights, n=200_000_000, steps=100, dt=0.01, a0=1000.0, ngrid=128, sort_every=20):
     """The cascade step (pair creation, both lepton passes with emission, photon
     compaction) on the standing wave at a0 = 1000, captured once as a hipGraph
     and replayed; electrons re-sorted by cell every `sort_every` steps outside the
     graph (sorted into a second buffer and copied back, so that the graph's
-    pointers stay valid).  Table path, and surrogate path when weights are given."""
+    pointers stay valid).  Table path, and surrogate path when weights are given.
+    The 2e8 electrons are drawn on the device (torch's generator, seed 4) with
+    the distributions of workloads.standing_wave_electrons: x uniform in the box,
+    p ~ N(0, 10^2) per component, ids 0..n-1; the initial storage order is by
+    cell (qed_sort_by_cell, untimed)."""
     import workloads
     L = workloads.BOX_L
     res = {}
@@ -338,22 +342,23 @@ def run_cascade(q, torch, weights, n=20_000_000, steps=100, dt=0.01, a0=1000.0, 
         if name == "surrogate":
             for k in (0, 1):
                 ctx.qed_surrogate_io(k, weights[k])
-        ens = workloads.standing_wave_electrons(n, seed=4)
-        cell = np.floor(ens["x"] / (L / ngrid) + 0.5).astype(np.int64) % ngrid
-        order = np.argsort((cell[:, 2] * ngrid + cell[:, 1]) * ngrid + cell[:, 0], kind="stable")
         cap_e, cap_p, cap_g = int(1.25 * n), n // 4, 3 * n
         el, el_b = q.Species(cap_e, "f32"), q.Species(cap_e, "f32")
         po, ph = q.Species(cap_p, "f32"), q.Species(cap_g, "f32")
-        el.load(ens["x"][order], ens["p"][order], None, ens["id"][order])
-        del ens, cell, order
-        e0 = np.zeros((0, 3))
-        po.load(e0, e0, np.zeros(0), np.zeros(0, np.uint64))
-        ph.load(e0, e0, np.zeros(0), np.zeros(0, np.uint64))
-        ctx.qed_init_optical_depth(el, 0)
-        ctx.qed_set_next_id(n)
-        ctx.qed_reserve(cap_g)
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(4)
+        for a in (el_b.x, el_b.y, el_b.z):
+            a[:n].uniform_(0.0, L, generator=gen)
+        for a in (el_b.px, el_b.py, el_b.pz):
+            a[:n].normal_(0.0, 10.0, generator=gen)
+        torch.arange(n, out=el_b.id[:n])
+        el_b.count.fill_(n)
         grid = torch.empty(ngrid ** 3 * 6, dtype=torch.float32, device="cuda")
         fld = q.Fields(q.QED_FIELD_GRID, grid=grid, n=ngrid, L=L)
+        ctx.qed_reserve(cap_e)          # scan state and emitter slots; photons add scan state on first use
+        ctx.qed_sort_by_cell(fld, el_b, el)
+        ctx.qed_init_optical_depth(el, 0)
+        ctx.qed_set_next_id(n)
         ctx.qed_set_step(0)
 
         def one_step():

@@ -24,7 +24,8 @@
  *   - Every particle and field buffer is device memory owned by the caller, which
  *     must keep it alive until the enqueued work has finished.  The library only
  *     allocates its own context memory (tables, emitter list, counters, scan state)
- *     in qed_create / qed_build_tables / qed_reserve.
+ *     in qed_create / qed_build_tables / qed_reserve, or on the first use of a
+ *     larger species (see qed_reserve).
  *   - Particle counts live in device memory (qed_species_t.count), so a sequence of
  *     calls needs no host synchronisation.
  *
@@ -161,8 +162,14 @@ QED_API int qed_create(qed_ctx_t *ctx, const qed_params_t *params);
 QED_API void qed_destroy(qed_ctx_t ctx);
 QED_API const char *qed_last_error(qed_ctx_t ctx);
 
-/* Reserves the context's emitter list and scan state for species of up to
-   `max_particles` elements (allocates; call before graph capture). */
+/* Reserves the context's scan state for species of up to `max_particles`
+   elements and its emitter list (one 128-byte record slot, one mask bit and one
+   list entry per lepton) for lepton species of up to `max_particles` (allocates;
+   call before graph capture).  Without it, or when a species is larger, the
+   entry points grow what they need on first use: the scan state in every entry
+   point that appends or compacts, the emitter list in qed_gather_push for the
+   leptons passed to it, so a large photon species costs no emitter slots.  Such
+   a growing first use synchronises the device and must not be under capture. */
 QED_API int qed_reserve(qed_ctx_t ctx, int64_t max_particles);
 
 /* Sets the next id handed to appended particles (device counter). */

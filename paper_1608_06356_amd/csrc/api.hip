@@ -56,28 +56,47 @@ template <typename T> hipError_t dalloc(T **p, size_t n) {
 }
 
 void free_emitters(qed_ctx *c) {
-  (void)hipFree(c->em_idx); (void)hipFree(c->em_rec); (void)hipFree(c->d_status); (void)hipFree(c->em_mask);
-  c->em_idx = nullptr; c->em_rec = nullptr; c->d_status = nullptr; c->em_mask = nullptr;
+  (void)hipFree(c->em_idx); (void)hipFree(c->em_rec); (void)hipFree(c->em_mask);
+  c->em_idx = nullptr; c->em_rec = nullptr; c->em_mask = nullptr;
+  c->em_cap = 0;
+}
+
+void free_scan(qed_ctx *c) {
+  (void)hipFree(c->d_status);
+  c->d_status = nullptr;
   c->reserved = 0; c->status_len = 0;
 }
 
-int ensure_reserved(qed_ctx *c, int64_t n) {
+// Scan state for species of up to n particles (one status word per tile of
+// the smallest tile size, 256).  Allocates, so not under graph capture.
+int ensure_scan(qed_ctx *c, int64_t n) {
   if (n <= c->reserved) return QED_OK;
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(c, e, "reserve");
-  free_emitters(c);
-  // emitter slots (one per particle), ballot mask, ordered list; scan status
-  // for the largest tile count of any kernel
-  const int64_t em_cap = n;
+  free_scan(c);
   const int64_t status_len = n / 256 + 64;
-  if ((e = dalloc(&c->em_idx, em_cap)) != hipSuccess || (e = dalloc(&c->em_rec, kEmRecMaxBytes * em_cap)) != hipSuccess ||
-      (e = dalloc(&c->d_status, status_len)) != hipSuccess || (e = dalloc(&c->em_mask, n / 64 + 1)) != hipSuccess) {
-    free_emitters(c);
+  if ((e = dalloc(&c->d_status, status_len)) != hipSuccess) {
+    free_scan(c);
     return hip_fail(c, e, "reserve: hipMalloc");
   }
   c->reserved = n;
-  c->em_cap = em_cap;
   c->status_len = status_len;
+  return QED_OK;
+}
+
+// Emitter slots (one record per particle), ballot mask and ordered list for
+// lepton species of up to n particles.  Allocates, so not under graph capture.
+int ensure_emitters(qed_ctx *c, int64_t n) {
+  if (n <= c->em_cap) return QED_OK;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(c, e, "reserve");
+  free_emitters(c);
+  if ((e = dalloc(&c->em_idx, n)) != hipSuccess || (e = dalloc(&c->em_rec, kEmRecMaxBytes * n)) != hipSuccess ||
+      (e = dalloc(&c->em_mask, n / 64 + 1)) != hipSuccess) {
+    free_emitters(c);
+    return hip_fail(c, e, "reserve: hipMalloc");
+  }
+  c->em_cap = n;
   c->em_owner = nullptr;
   return QED_OK;
 }
@@ -124,6 +143,7 @@ void qed_destroy(qed_ctx_t c) {
   if (!c) return;
   (void)hipDeviceSynchronize();
   free_emitters(c);
+  free_scan(c);
   void *ptrs[] = {c->rad_lnh64, c->rad_S64, c->rad_lnh32, c->rad_s0sc, c->rad_q16, c->pair_L64,
                   c->pair_S64, c->pair_L32, c->pair_s0sc, c->pair_q16, c->tab_work, c->d_counters,
                   c->d_next_id, c->d_n_emit, c->d_ticket, c->rad_chk, c->mlp_theta[0], c->mlp_theta[1],
@@ -138,7 +158,8 @@ const char *qed_last_error(qed_ctx_t c) { return c ? c->err.c_str() : "null cont
 int qed_reserve(qed_ctx_t c, int64_t n) {
   if (!c) return QED_ERR_ARG;
   if (n <= 0 || n > (int64_t)INT32_MAX) return fail(c, QED_ERR_ARG, "reserve: n must be in [1, 2^31)");
-  return ensure_reserved(c, n);
+  int r = ensure_scan(c, n);
+  return r ? r : ensure_emitters(c, n);
 }
 
 int qed_set_next_id(qed_ctx_t c, uint64_t v, void *st) {
@@ -264,7 +285,7 @@ int qed_gather_push(qed_ctx_t c, const qed_fields_t *f, qed_species_t *lep, int 
   if (charge != -1 && charge != 1) return fail(c, QED_ERR_ARG, "charge must be -1 or +1");
   if (!(dt > 0)) return fail(c, QED_ERR_ARG, "dt must be > 0");
   if (!c->tables_ready) return fail(c, QED_ERR_STATE, "tables not built (call qed_build_tables)");
-  if ((r = ensure_reserved(c, lep->capacity))) return r;
+  if ((r = ensure_scan(c, lep->capacity)) || (r = ensure_emitters(c, lep->capacity))) return r;
   if ((c->params.flags & QED_FLAG_SURROGATE) && lep->dtype == QED_F32 && !c->mlp_ready)
     return fail(c, QED_ERR_STATE, "QED_FLAG_SURROGATE: surrogate not trained or loaded");
   if ((c->params.flags & QED_FLAG_SURROGATE) && (c->params.flags & QED_FLAG_METHOD_I))
@@ -308,7 +329,7 @@ int qed_create_pairs(qed_ctx_t c, const qed_fields_t *f, qed_species_t *ph, qed_
   if (!(dt > 0)) return fail(c, QED_ERR_ARG, "dt must be > 0");
   if (step < 0 && step != QED_STEP_DEVICE) return fail(c, QED_ERR_ARG, "step must be >= 0 or QED_STEP_DEVICE");
   if (!c->tables_ready) return fail(c, QED_ERR_STATE, "tables not built");
-  if ((r = ensure_reserved(c, ph->capacity))) return r;
+  if ((r = ensure_scan(c, ph->capacity))) return r;
   hipError_t e = qed::launch_pairs(c, f, ph, el, po, dt, step, S(st));
   return e == hipSuccess ? QED_OK : hip_fail(c, e, "create_pairs");
 }
@@ -317,7 +338,7 @@ int qed_compact(qed_ctx_t c, qed_species_t *sp, void *st) {
   if (!c) return QED_ERR_ARG;
   int r = check_species(c, sp, "species");
   if (r) return r;
-  if ((r = ensure_reserved(c, sp->capacity))) return r;
+  if ((r = ensure_scan(c, sp->capacity))) return r;
   hipError_t e = qed::launch_compact(c, sp, S(st));
   return e == hipSuccess ? QED_OK : hip_fail(c, e, "compact");
 }

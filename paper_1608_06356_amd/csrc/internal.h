@@ -35,8 +35,8 @@ struct qed_ctx {
   int64_t *d_step = nullptr;     // device step index (QED_STEP_DEVICE)
 
   // emitter list produced by qed_gather_push
-  int64_t reserved = 0;
-  int64_t em_cap = 0;            // slots (one per particle of the reserved capacity)
+  int64_t reserved = 0;          // species size the scan state covers
+  int64_t em_cap = 0;            // emitter slots (one per lepton of the largest lepton species)
   uint64_t *em_mask = nullptr;   // one bit per particle: optical depth ran out this step
   int32_t *em_idx = nullptr;     // ordered emitter list
   unsigned char *em_rec = nullptr;   // em_cap records of up to kEmRecMaxBytes, slot = particle index
