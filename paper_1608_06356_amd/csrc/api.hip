@@ -250,7 +250,7 @@ int qed_init_optical_depth(qed_ctx_t c, qed_species_t *sp, int64_t step, void *s
 
 int qed_fill_standing_wave(qed_ctx_t c, float *grid, int n, double L, double a0, double t, void *st) {
   if (!c) return QED_ERR_ARG;
-  if (!grid || n < 3 || n > 4096 || !(L > 0)) return fail(c, QED_ERR_ARG, "fill_standing_wave: bad grid");
+  if (!grid || n < 3 || n > kMaxWaveGrid || !(L > 0)) return fail(c, QED_ERR_ARG, "fill_standing_wave: bad grid");
   hipError_t e = qed::launch_standing_wave(grid, n, L, a0, t, 0.0, nullptr, S(st));
   return e == hipSuccess ? QED_OK : hip_fail(c, e, "fill_standing_wave");
 }
@@ -258,7 +258,7 @@ int qed_fill_standing_wave(qed_ctx_t c, float *grid, int n, double L, double a0,
 int qed_fill_standing_wave_at_step(qed_ctx_t c, float *grid, int n, double L, double a0, double t0, double dt,
                                    void *st) {
   if (!c) return QED_ERR_ARG;
-  if (!grid || n < 3 || n > 4096 || !(L > 0)) return fail(c, QED_ERR_ARG, "fill_standing_wave: bad grid");
+  if (!grid || n < 3 || n > kMaxWaveGrid || !(L > 0)) return fail(c, QED_ERR_ARG, "fill_standing_wave: bad grid");
   hipError_t e = qed::launch_standing_wave(grid, n, L, a0, t0, dt, c->d_step, S(st));
   return e == hipSuccess ? QED_OK : hip_fail(c, e, "fill_standing_wave_at_step");
 }

@@ -9,6 +9,8 @@
 
 // Bytes of one emitter record slot (the float64 record; the float32 one is smaller).
 constexpr int64_t kEmRecMaxBytes = 128;
+// Largest node count per side of qed_fill_standing_wave grids.
+constexpr int kMaxWaveGrid = 4096;
 
 struct qed_ctx {
   int device = 0;

@@ -1390,22 +1390,31 @@ __global__ void k_init_tau(const uint64_t *id, double *tau, const int64_t *count
   }
 }
 
-// The node values depend on x only through cos x and sin x: each thread owns
-// node columns ix and writes them for a stride of rows (iy, iz).
+// The fields depend on x only, so every row (iy, iz) of the grid holds the same
+// 6 n floats: each workgroup builds that row in LDS once (cos x, sin x per
+// column) and streams it to its share of the rows with V-wide coalesced stores
+// (float4 when rows and grid are 16-byte aligned, else float2).
+template <typename V>
 __global__ void k_standing_wave(float *grid, int n, double dx, double a0, double t0, double dt_step,
                                 const int64_t *d_step) {
-  const int64_t rows = (int64_t)n * n;
+  extern __shared__ float row_s[];
   const double t = d_step ? t0 + dt_step * (double)*d_step : t0;
   const double ct = cos(t), st = sin(t);
   for (int ix = threadIdx.x; ix < n; ix += blockDim.x) {
     const double x = ix * dx;
     const double ca = a0 * cos(x), sa = a0 * sin(x);
-    const float2 v0 = make_float2(0.0f, (float)(ca * ct)), v1 = make_float2((float)(ca * st), 0.0f),
-                 v2 = make_float2((float)(sa * ct), (float)(sa * st));
-    for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
-      float2 *o = reinterpret_cast<float2 *>(grid + (r * n + ix) * 6);
-      o[0] = v0; o[1] = v1; o[2] = v2;
-    }
+    float *o = row_s + 6 * ix;
+    o[0] = 0.0f; o[1] = (float)(ca * ct); o[2] = (float)(ca * st);
+    o[3] = 0.0f; o[4] = (float)(sa * ct); o[5] = (float)(sa * st);
+  }
+  __syncthreads();
+  constexpr int W = (int)(sizeof(V) / sizeof(float));
+  const int per_row = 6 * n / W;
+  const int64_t rows = (int64_t)n * n;
+  const V *src = reinterpret_cast<const V *>(row_s);
+  for (int k = threadIdx.x; k < per_row; k += blockDim.x) {
+    const V v = src[k];
+    for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) reinterpret_cast<V *>(grid + r * 6 * n)[k] = v;
   }
 }
 
@@ -1504,8 +1513,17 @@ static MlpDev mlp_dev(qed_ctx *c) {
 // Dynamic LDS above the default limit (surrogate emission); called once per
 // context, with the context's device current.
 hipError_t step_set_attributes() {
-  return hipFuncSetAttribute((const void *)k_emit_mlp, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)sizeof(EmitMlpLds));
+  // the standing-wave row: 6 n floats for n up to kMaxWaveGrid
+  const int row_bytes = 6 * kMaxWaveGrid * (int)sizeof(float);
+  hipError_t e = hipFuncSetAttribute((const void *)k_emit_mlp, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)sizeof(EmitMlpLds));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_standing_wave<float4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            row_bytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_standing_wave<float2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            row_bytes);
+  return e;
 }
 
 static int gen_mode(const qed_ctx *c) {
@@ -1661,10 +1679,17 @@ hipError_t launch_init_tau(qed_ctx *c, const qed_species_t *sp, int64_t step, hi
 hipError_t launch_standing_wave(float *grid, int n, double L, double a0, double t0, double dt_step,
                                 const int64_t *d_step, hipStream_t st) {
   const int64_t rows = (int64_t)n * n;
-  const int threads = n >= 256 ? 256 : (n + 63) / 64 * 64;
-  const int64_t blocks = rows < 8192 ? rows : 8192;
-  hipLaunchKernelGGL(k_standing_wave, dim3((unsigned)blocks), dim3(threads), 0, st, grid, n, L / n, a0, t0,
-                     dt_step, d_step);
+  const bool wide = n % 2 == 0 && ((uintptr_t)grid % 16) == 0;
+  const int per_row = wide ? 6 * n / 4 : 3 * n;
+  const int threads = per_row >= 256 ? 256 : (per_row + 63) / 64 * 64;
+  const int64_t blocks = rows < 2048 ? rows : 2048;
+  const size_t lds = (size_t)6 * n * sizeof(float);
+  if (wide)
+    hipLaunchKernelGGL(k_standing_wave<float4>, dim3((unsigned)blocks), dim3(threads), lds, st, grid, n, L / n, a0,
+                       t0, dt_step, d_step);
+  else
+    hipLaunchKernelGGL(k_standing_wave<float2>, dim3((unsigned)blocks), dim3(threads), lds, st, grid, n, L / n, a0,
+                       t0, dt_step, d_step);
   return hipGetLastError();
 }
 

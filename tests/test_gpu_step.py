@@ -153,6 +153,25 @@ def test_f32_chi_where_fields_cancel(rad_table_I):
     assert rel.max() < 2e-5
 
 
+def test_fill_standing_wave_vs_oracle():
+    """qed_fill_standing_wave on even (float4 stores) and odd (float2 stores) grids,
+    and from a grid pointer that is only 8-byte aligned: every node against the
+    oracle's node values (float32 rounding of float64 values)."""
+    torch, q = need_gpu()
+    ctx = q.Context(seed=0)
+    L, a0 = workloads.BOX_L, 500.0
+    for n, t, off in ((128, 0.37, 0), (5, 1.1, 0), (6, 2.3, 2)):
+        buf = torch.full((n ** 3 * 6 + 4,), float("nan"), dtype=torch.float32, device="cuda")
+        grid = buf[off:off + n ** 3 * 6]            # off = 2 floats: 8-byte but not 16-byte aligned
+        ctx.qed_fill_standing_wave(grid, n, L, a0, t)
+        g = grid.cpu().numpy().reshape(n, n, n, 6)   # [iz, iy, ix, component]
+        Eg, Bg = mc.standing_wave_grid(n, L, a0, t)  # [c, ix, iy, iz]
+        ref = np.concatenate([Eg, Bg], 0).transpose(3, 2, 1, 0)
+        np.testing.assert_allclose(g, ref, rtol=2e-7, atol=2e-7 * a0)
+        assert np.isnan(buf[:off].cpu().numpy()).all() and np.isnan(buf[off + n ** 3 * 6:].cpu().numpy()).all()
+    ctx.close()
+
+
 def test_uniform_b_full_size_subsample(rad_table_I):
     """Configuration 1 at full size: the three Fig. 1 ensembles of 1e5 electrons
     each, float64, formula I, 100 steps of dt = 0.01, seed 0, optical depths drawn
