@@ -75,7 +75,7 @@ int ensure_scan(qed_ctx *c, int64_t n) {
   if (e != hipSuccess) return hip_fail(c, e, "reserve");
   free_scan(c);
   const int64_t status_len = n / 256 + 64;
-  if ((e = dalloc(&c->d_status, status_len)) != hipSuccess) {
+  if ((e = dalloc(&c->d_status, 2 * status_len)) != hipSuccess) {   // two regions (see qed_ctx)
     free_scan(c);
     return hip_fail(c, e, "reserve: hipMalloc");
   }
@@ -123,7 +123,7 @@ int qed_create(qed_ctx_t *out, const qed_params_t *p) {
   if (e == hipSuccess) e = dalloc(&c->d_counters, qed::cNumCounters);
   if (e == hipSuccess) e = dalloc(&c->d_next_id, 1);
   if (e == hipSuccess) e = dalloc(&c->d_n_emit, 1);
-  if (e == hipSuccess) e = dalloc(&c->d_ticket, 1);
+  if (e == hipSuccess) e = dalloc(&c->d_ticket, 2);
   if (e == hipSuccess) e = dalloc(&c->d_killed, 1);
   if (e == hipSuccess) e = dalloc(&c->d_step, 1);
   if (e == hipSuccess) e = hipMemset(c->d_step, 0, sizeof(int64_t));

@@ -53,7 +53,9 @@ struct qed_ctx {
   int64_t *d_killed = nullptr;
   const void *killed_owner = nullptr;
 
-  // decoupled look-back scan state
+  // decoupled look-back scan state: two tickets and two status regions of
+  // status_len words; region 1 serves the emitter index so that one launch can
+  // clear the state of both scans of qed_emit_photons
   uint32_t *d_ticket = nullptr;
   uint64_t *d_status = nullptr;
   int64_t status_len = 0;

@@ -1379,6 +1379,14 @@ __global__ void k_zero_scan(uint32_t *ticket, uint64_t *status, int64_t n) {
   if (i < n) status[i] = 0;
 }
 
+// Both scan regions at once: words [0, n0) of region 0, [0, n1) of region 1.
+__global__ void k_zero_scan2(uint32_t *ticket, uint64_t *status, int64_t len, int64_t n0, int64_t n1) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i == 0) { ticket[0] = 0; ticket[1] = 0; }
+  if (i < n0) status[i] = 0;
+  if (i < n1) status[len + i] = 0;
+}
+
 __global__ void k_init_tau(const uint64_t *id, double *tau, const int64_t *count, uint32_t seed,
                            uint64_t step_v, const int64_t *d_step, int64_t cap) {
   const int64_t n = *count;
@@ -1572,19 +1580,23 @@ hipError_t launch_emit(qed_ctx *c, const qed_species_t *lep, const qed_species_t
   const bool wide = lep->capacity >= kEIWideFrom;
   const int64_t eit = wide ? ei_tile<8>() : ei_tile<1>();
   const int64_t etiles = (lep->capacity + eit - 1) / eit;
-  hipError_t e = zero_scan(c, etiles, st);
+  // one launch clears both scans: region 1 for the index, region 0 for the events
+  static_assert(kEmitMlpThreads == kEmitThreads, "emission tile size");
+  const int64_t ntiles = (lep->capacity + kEmitThreads - 1) / kEmitThreads;
+  const int64_t n0 = ntiles + 1, n1 = etiles + 1, nz = n0 > n1 ? n0 : n1;
+  if (nz > c->status_len) return hipErrorInvalidValue;   // reserve() sizes the status regions
+  hipLaunchKernelGGL(k_zero_scan2, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, st, c->d_ticket, c->d_status,
+                     c->status_len, n0, n1);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  const ScanDev isc{c->d_ticket + 1, c->d_status + c->status_len};
   if (wide)
     hipLaunchKernelGGL(k_emit_index<8>, dim3((unsigned)etiles), dim3(kEIThreads), 0, st, c->em_mask, lep->count,
-                     c->em_idx, c->d_n_emit, ScanDev{c->d_ticket, c->d_status}, c->d_counters);
+                     c->em_idx, c->d_n_emit, isc, c->d_counters);
   else
     hipLaunchKernelGGL(k_emit_index<1>, dim3((unsigned)etiles), dim3(kEIThreads), 0, st, c->em_mask, lep->count,
-                     c->em_idx, c->d_n_emit, ScanDev{c->d_ticket, c->d_status}, c->d_counters);
+                     c->em_idx, c->d_n_emit, isc, c->d_counters);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  // the scan needs one zeroed status word per tile of this kernel's tile size
-  const int tile = use_mlp ? kEmitMlpThreads : kEmitThreads;
-  const int64_t ntiles = (lep->capacity + tile - 1) / tile;
-  if ((e = zero_scan(c, ntiles, st)) != hipSuccess) return e;
   const ScanDev sc{c->d_ticket, c->d_status};
   const int recoil = (c->params.flags & QED_FLAG_NO_RECOIL) ? 0 : 1;
   // persistent workgroups: one per CU for the surrogate (its nets fill the LDS),
