@@ -643,13 +643,17 @@ struct EmitArgs {
   TabRange rg;
 };
 
-constexpr int kEmitThreads = 512;
+// Emitters per tile (= threads per workgroup): 1024 for the float32 optical-depth
+// kernel (fewer tiles, a shorter look-back chain, 127 registers), 512 for the
+// float64 and method I kernels, which need more than 128 registers.
+template <typename R, bool M1> constexpr int emit_threads() { return (sizeof(R) == 4 && !M1) ? 1024 : 512; }
 
 template <typename R, bool M1, typename Tab>
 __device__ void emit_tile(const EmitArgs<R> &a, const Tab &tab, const R *lnh, uint32_t tile,
                           uint32_t *scan_s, uint64_t *off_s, int64_t n_em, int64_t ph_count0,
                           uint64_t id0, uint32_t *cnt) {
-  const int64_t r = (int64_t)tile * kEmitThreads + threadIdx.x;
+  constexpr int T = emit_threads<R, M1>();
+  const int64_t r = (int64_t)tile * T + threadIdx.x;
   const bool valid = r < n_em;
   R gph[kKmaxMax];
   double tph[kKmaxMax];
@@ -753,7 +757,7 @@ __device__ void emit_tile(const EmitArgs<R> &a, const Tab &tab, const R *lnh, ui
     }
   }
   count_lds(cnt, cDropped, ndrop);
-  const int64_t last = (n_em - 1) / kEmitThreads;
+  const int64_t last = (n_em - 1) / T;
   if ((int64_t)tile == last && threadIdx.x == 0) {
     const int64_t tot = (int64_t)(toff + total);
     *a.ph.count = ph_count0 + tot < a.ph.cap ? ph_count0 + tot : a.ph.cap;
@@ -764,7 +768,7 @@ __device__ void emit_tile(const EmitArgs<R> &a, const Tab &tab, const R *lnh, ui
 // float path: 16-bit quantile table read through the caches (an emission step
 // touches few rows), float32 ln h staged in LDS
 template <bool M1>
-__global__ __launch_bounds__(kEmitThreads) void k_emit_f32(EmitArgs<float> a) {
+__global__ __launch_bounds__((emit_threads<float, M1>())) void k_emit_f32(EmitArgs<float> a) {
   __shared__ float lnh_s[kRadNChi];
   __shared__ uint32_t scan_s[16];
   __shared__ uint32_t tile_s;
@@ -781,7 +785,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_f32(EmitArgs<float> a) {
   const RowQ16 tab{a.q16, a.s0sc};     // 16-bit quantile table through the caches
   while (true) {
     const uint32_t tile = next_tile(a.sc.ticket, &tile_s);
-    if ((int64_t)tile * kEmitThreads >= n_em) break;
+    if ((int64_t)tile * emit_threads<float, M1>() >= n_em) break;
     emit_tile<float, M1>(a, tab, lnh_s, tile, scan_s, &off_s, n_em, ph0, id0, cnt_s);
   }
   count_flush(cnt_s, a.counters);
@@ -789,7 +793,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_f32(EmitArgs<float> a) {
 
 // double path: float64 master tables read through the caches
 template <bool M1>
-__global__ __launch_bounds__(kEmitThreads) void k_emit_f64(EmitArgs<double> a) {
+__global__ __launch_bounds__((emit_threads<double, M1>())) void k_emit_f64(EmitArgs<double> a) {
   __shared__ double lnh_s[kRadNChi];
   __shared__ uint32_t scan_s[16];
   __shared__ uint32_t tile_s;
@@ -806,7 +810,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_f64(EmitArgs<double> a) {
   const RowF64 tab{a.S64};
   while (true) {
     const uint32_t tile = next_tile(a.sc.ticket, &tile_s);
-    if ((int64_t)tile * kEmitThreads >= n_em) break;
+    if ((int64_t)tile * emit_threads<double, M1>() >= n_em) break;
     emit_tile<double, M1>(a, tab, lnh_s, tile, scan_s, &off_s, n_em, ph0, id0, cnt_s);
   }
   count_flush(cnt_s, a.counters);
@@ -1581,8 +1585,11 @@ hipError_t launch_emit(qed_ctx *c, const qed_species_t *lep, const qed_species_t
   const int64_t eit = wide ? ei_tile<8>() : ei_tile<1>();
   const int64_t etiles = (lep->capacity + eit - 1) / eit;
   // one launch clears both scans: region 1 for the index, region 0 for the events
-  static_assert(kEmitMlpThreads == kEmitThreads, "emission tile size");
-  const int64_t ntiles = (lep->capacity + kEmitThreads - 1) / kEmitThreads;
+  const bool m1 = gen_mode(c) != 0;
+  const int tile = use_mlp ? kEmitMlpThreads
+                           : (lep->dtype == QED_F32 ? (m1 ? emit_threads<float, true>() : emit_threads<float, false>())
+                                                    : (m1 ? emit_threads<double, true>() : emit_threads<double, false>()));
+  const int64_t ntiles = (lep->capacity + tile - 1) / tile;
   const int64_t n0 = ntiles + 1, n1 = etiles + 1, nz = n0 > n1 ? n0 : n1;
   if (nz > c->status_len) return hipErrorInvalidValue;   // reserve() sizes the status regions
   hipLaunchKernelGGL(k_zero_scan2, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, st, c->d_ticket, c->d_status,
@@ -1615,15 +1622,15 @@ hipError_t launch_emit(qed_ctx *c, const qed_species_t *lep, const qed_species_t
                       c->rad_s0sc, c->em_idx, c->em_mask, (const EmRec<float> *)c->em_rec, c->d_n_emit,
                       c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, dstep, sc,
                       c->d_counters, gen_mode(c), c->em_dt, c->range};
-    if (a.gen) hipLaunchKernelGGL(k_emit_f32<true>, dim3(grid), dim3(kEmitThreads), 0, st, a);
-    else hipLaunchKernelGGL(k_emit_f32<false>, dim3(grid), dim3(kEmitThreads), 0, st, a);
+    if (a.gen) hipLaunchKernelGGL(k_emit_f32<true>, dim3(grid), dim3(emit_threads<float, true>()), 0, st, a);
+    else hipLaunchKernelGGL(k_emit_f32<false>, dim3(grid), dim3(emit_threads<float, false>()), 0, st, a);
   } else {
     EmitArgs<double> a{dev_species(lep), dev_species(ph), c->rad_lnh64, c->rad_S64, c->rad_q16,
                        c->rad_s0sc, c->em_idx, c->em_mask, (const EmRec<double> *)c->em_rec, c->d_n_emit,
                        c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, dstep, sc,
                        c->d_counters, gen_mode(c), c->em_dt, c->range};
-    if (a.gen) hipLaunchKernelGGL(k_emit_f64<true>, dim3(grid), dim3(kEmitThreads), 0, st, a);
-    else hipLaunchKernelGGL(k_emit_f64<false>, dim3(grid), dim3(kEmitThreads), 0, st, a);
+    if (a.gen) hipLaunchKernelGGL(k_emit_f64<true>, dim3(grid), dim3(emit_threads<double, true>()), 0, st, a);
+    else hipLaunchKernelGGL(k_emit_f64<false>, dim3(grid), dim3(emit_threads<double, false>()), 0, st, a);
   }
   return hipGetLastError();
 }
