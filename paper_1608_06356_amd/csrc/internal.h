@@ -9,6 +9,11 @@
 
 // Bytes of one emitter record slot (the float64 record; the float32 one is smaller).
 constexpr int64_t kEmRecMaxBytes = 128;
+// Entry of the ordered emitter list: particle index and its record slot.
+struct alignas(8) EmIdx {
+  int32_t i, slot;
+};
+
 // Largest node count per side of qed_fill_standing_wave grids.
 constexpr int kMaxWaveGrid = 4096;
 
@@ -40,7 +45,7 @@ struct qed_ctx {
   int64_t reserved = 0;          // species size the scan state covers
   int64_t em_cap = 0;            // emitter slots (one per lepton of the largest lepton species)
   uint64_t *em_mask = nullptr;   // one bit per particle: optical depth ran out this step
-  int32_t *em_idx = nullptr;     // ordered emitter list
+  EmIdx *em_idx = nullptr;       // ordered emitter list
   unsigned char *em_rec = nullptr;   // em_cap records of up to kEmRecMaxBytes, slot = particle index
   int64_t *d_n_emit = nullptr;
   const void *em_owner = nullptr;   // species (x pointer) the list belongs to

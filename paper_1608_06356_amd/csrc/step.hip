@@ -579,7 +579,7 @@ constexpr int64_t kEIWideFrom = (int64_t)1 << 22;   // capacity from which W = 8
 
 template <int W>
 __global__ __launch_bounds__(kEIThreads) void k_emit_index(const uint64_t *mask, const int64_t *count,
-                                                           int32_t *em_idx, int64_t *n_emit, ScanDev sc,
+                                                           EmIdx *em_idx, int64_t *n_emit, ScanDev sc,
                                                            unsigned long long *counters) {
   __shared__ uint32_t scan_s[16];
   __shared__ uint32_t tile_s;
@@ -609,8 +609,10 @@ __global__ __launch_bounds__(kEIThreads) void k_emit_index(const uint64_t *mask,
 #pragma unroll
   for (int k = 0; k < W; ++k) {
     uint64_t b = m[k];
+    const int32_t wb = (int32_t)((w0 + k) << 6);
+    int32_t slot = wb;   // records of a mask word are packed from its base (rec_slot)
     while (b) {
-      em_idx[r++] = (int32_t)(((w0 + k) << 6) + (__ffsll((long long)b) - 1));
+      em_idx[r++] = EmIdx{wb + (__ffsll((long long)b) - 1), slot++};
       b &= b - 1ull;
     }
   }
@@ -626,8 +628,7 @@ struct EmitArgs {
   const double *S64;           // float64 quantiles (R = double)
   const uint16_t *q16;         // 16-bit quantiles (R = float)
   const float *s0sc;
-  const int32_t *em_idx;
-  const uint64_t *mask;        // emitter mask of the last gather/push (record slots)
+  const EmIdx *em_idx;
   const EmRec<R> *rec;
   const int64_t *n_emit;
   uint64_t *next_id;
@@ -660,8 +661,9 @@ __device__ void emit_tile(const EmitArgs<R> &a, const Tab &tab, const R *lnh, ui
   uint32_t nacc = 0, nev = 0, nrej = 0, ncap = 0;
   R nx = 0, ny = 0, nz = 0, x = 0, y = 0, z = 0;
   if (valid) {
-    const int64_t i = a.em_idx[r];
-    const EmRec<R> rc = a.rec[rec_slot(i, a.mask[i >> 6])];
+    const EmIdx e = a.em_idx[r];
+    const int64_t i = e.i;
+    const EmRec<R> rc = a.rec[e.slot];
     R F[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) F[c] = rc.F[c];
@@ -972,9 +974,10 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
     int64_t i = 0;
     bool recoiled = false;
     if (valid) {
-      i = a.em_idx[r];
+      const EmIdx e = a.em_idx[r];
+      i = e.i;
       id = a.lep.id[i];
-      const EmRec<float> rc = a.rec[rec_slot(i, a.mask[i >> 6])];
+      const EmRec<float> rc = a.rec[e.slot];
 #pragma unroll
       for (int c = 0; c < 6; ++c) F[c] = rc.F[c];
       chi = rc.chi; W = rc.W; rem = a.dtd - rc.tau / rc.W;
@@ -1613,20 +1616,20 @@ hipError_t launch_emit(qed_ctx *c, const qed_species_t *lep, const qed_species_t
   const int64_t *dstep = step < 0 ? c->d_step : nullptr;
   if (use_mlp) {
     EmitArgs<float> a{dev_species(lep), dev_species(ph), c->rad_lnh32, c->rad_S64, c->rad_q16,
-                      c->rad_s0sc, c->em_idx, c->em_mask, (const EmRec<float> *)c->em_rec, c->d_n_emit,
+                      c->rad_s0sc, c->em_idx, (const EmRec<float> *)c->em_rec, c->d_n_emit,
                       c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, dstep, sc,
                       c->d_counters, gen_mode(c), c->em_dt, c->range};
     hipLaunchKernelGGL(k_emit_mlp, dim3(grid), dim3(kEmitMlpThreads), sizeof(EmitMlpLds), st, a, mlp_dev(c));
   } else if (lep->dtype == QED_F32) {
     EmitArgs<float> a{dev_species(lep), dev_species(ph), c->rad_lnh32, c->rad_S64, c->rad_q16,
-                      c->rad_s0sc, c->em_idx, c->em_mask, (const EmRec<float> *)c->em_rec, c->d_n_emit,
+                      c->rad_s0sc, c->em_idx, (const EmRec<float> *)c->em_rec, c->d_n_emit,
                       c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, dstep, sc,
                       c->d_counters, gen_mode(c), c->em_dt, c->range};
     if (a.gen) hipLaunchKernelGGL(k_emit_f32<true>, dim3(grid), dim3(emit_threads<float, true>()), 0, st, a);
     else hipLaunchKernelGGL(k_emit_f32<false>, dim3(grid), dim3(emit_threads<float, false>()), 0, st, a);
   } else {
     EmitArgs<double> a{dev_species(lep), dev_species(ph), c->rad_lnh64, c->rad_S64, c->rad_q16,
-                       c->rad_s0sc, c->em_idx, c->em_mask, (const EmRec<double> *)c->em_rec, c->d_n_emit,
+                       c->rad_s0sc, c->em_idx, (const EmRec<double> *)c->em_rec, c->d_n_emit,
                        c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, dstep, sc,
                        c->d_counters, gen_mode(c), c->em_dt, c->range};
     if (a.gen) hipLaunchKernelGGL(k_emit_f64<true>, dim3(grid), dim3(emit_threads<double, true>()), 0, st, a);
