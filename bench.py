@@ -212,6 +212,24 @@ def run_workload(args, q, torch, flags, train_steps=0):
     return out
 
 
+def stream_copy_gbs(torch, nbytes=1 << 30, reps=5):
+    """Device-to-device copy bandwidth (read + write bytes per second, GB/s) of
+    an nbytes buffer, best of `reps` copies timed with HIP events."""
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        dst.copy_(src)
+        b.record(stream)
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b))
+    del src, dst
+    return 2 * nbytes / (best * 1e-3) / 1e9
+
+
 def _timed(torch, fn, steps):
     """Milliseconds of `steps` calls of fn(k), HIP events on the current stream."""
     stream = torch.cuda.current_stream()
@@ -448,6 +466,7 @@ def main():
     per_particle = 64
     algo = n * per_particle + grid_bytes
     achieved = algo / (gp_ms * 1e-3) / 1e9
+    copy_gbs = stream_copy_gbs(torch)
     out = {
         "metric": "QED MC particle-steps/s, surrogate vs table, at KS<=2e-3 spectrum error",
         "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
@@ -460,7 +479,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_gather_push<float>", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(), "algorithmic_bytes_per_launch": algo,
-                     "avg_launch_ms": gp_ms},
+                     "avg_launch_ms": gp_ms, "stream_copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "events": st,
         "photons": tab["photons"],
     }

@@ -71,10 +71,11 @@ template <typename R>
 __device__ __forceinline__ void weights_tsc(R x, R inv_d, int n, int &j, R w[3]) {
   const R g = x * inv_d;
   const R jf = floor(g + (R)0.5);
-  const R t = g - jf;
-  w[0] = (R)0.5 * ((R)0.5 - t) * ((R)0.5 - t);
-  w[1] = (R)0.75 - t * t;
-  w[2] = (R)0.5 * ((R)0.5 + t) * ((R)0.5 + t);
+  const R t = g - jf, tt = t * t;
+  const R h = (R)0.5 * tt + (R)0.125;     // (1/2)(1/2 -+ t)^2 = 1/8 -+ t/2 + t^2/2
+  w[0] = h - (R)0.5 * t;
+  w[1] = (R)0.75 - tt;
+  w[2] = h + (R)0.5 * t;
   int jj = (int)jf;
   j = jj < 0 ? 0 : (jj > n ? n : jj);
 }
@@ -500,9 +501,9 @@ __global__ __launch_bounds__(kGPThreads, (gp_waves<R, FK, M1>())) void k_gather_
   for (int k = threadIdx.x; k < kRadNChi; k += blockDim.x) lnh_s[k] = a.lnh[k];
   if (FK == QED_FIELD_GRID) {
     __shared__ BoxLds box_s;
-    int j[3] = {0, 0, 0}, rel[3], pit[2];
+    int j[3], rel[3], pit[2];
     R w[3][3];
-    if (live) tsc_setup<R>(f, x, y, z, j, w);
+    tsc_setup<R>(f, x, y, z, j, w);      // dead lanes hold x = 0: harmless, unused
     if (stage_box(box_s, f, live, j, rel, pit)) {   // its barriers also publish lnh_s
       if (live) gather_box<R>(box_s, rel, pit, w, F);
     } else if (live) {
