@@ -61,16 +61,21 @@ __device__ __forceinline__ R h_rad(R chi, const R *lnh, const TabRange &rg) {
 }
 
 // Pair rate h_pair(chi) from L = ln h_pair + 8/(3 chi); 0 below chi = 1e-2.
-template <typename R>
+// Fast (float32): hardware log/exp and reciprocal.
+template <typename R, bool Fast = false>
 __device__ __forceinline__ R h_pair(R chi, const R *L, const TabRange &rg) {
+  using M = Math<R, Fast>;
   if (!(chi >= (R)kPairChiMin)) return (R)0;
   if (chi > (R)rg.pair_hi)
-    return exp(L[kPairNRate - 1] - (R)(8.0 / (3.0 * rg.pair_hi)) + (R)(2.0 / 3.0) * log(chi / (R)rg.pair_hi));
-  const R x = (log(chi) - (R)rg.pair_lnlo) * (R)rg.pair_rate_inv;
+    return M::ex(L[kPairNRate - 1] - (R)(8.0 / (3.0 * rg.pair_hi)) + (R)(2.0 / 3.0) * M::ln(chi / (R)rg.pair_hi));
+  const R x = (M::ln(chi) - (R)rg.pair_lnlo) * (R)rg.pair_rate_inv;
   int i = (int)floor(x);
   i = i < 0 ? 0 : (i > kPairNRate - 2 ? kPairNRate - 2 : i);
   const R f = x - (R)i;
-  return exp(((R)1 - f) * L[i] + f * L[i + 1] - (R)8 / ((R)3 * chi));
+  R inv3chi;
+  if constexpr (Fast) inv3chi = __builtin_amdgcn_rcpf((R)3 * chi);
+  else inv3chi = (R)1 / ((R)3 * chi);
+  return M::ex(((R)1 - f) * L[i] + f * L[i + 1] - (R)8 * inv3chi);
 }
 
 // Row of a 256-row table: linear interpolation of the CDF in ln chi realised by

@@ -119,6 +119,25 @@ __device__ __forceinline__ float chi_lepton_f32(float px, float py, float pz, fl
   return __builtin_amdgcn_sqrtf((float)((1.0 + p2) * (ux * ux + uy * uy + uz * uz) + ne * ne)) * (float)kInvES;
 }
 
+// Eq. (3) for the float32 step (inputs k, E, B float32), in the manner of
+// chi_lepton_f32: the direction k^ to float64 rounding (float32 rsqrt and two
+// float64 Newton steps) and E + k^ x B in float64, where E and -k^ x B can
+// cancel; gamma_ph (float32 |k|) and the final root in float32.
+__device__ __forceinline__ float chi_photon_f32(float kx, float ky, float kz, float gph, const float F[6]) {
+  const double dx = kx, dy = ky, dz = kz;
+  const double k2 = dx * dx + dy * dy + dz * dz;
+  if (!(k2 >= 1e-30)) return 0.0f;
+  double y = (double)__builtin_amdgcn_rsqf((float)k2);
+  y = fma(0.5 * y, fma(-k2 * y, y, 1.0), y);
+  y = fma(0.5 * y, fma(-k2 * y, y, 1.0), y);
+  const double nx = dx * y, ny = dy * y, nz = dz * y;
+  const double bx = F[3], by = F[4], bz = F[5];
+  const double wx = (double)F[0] + (ny * bz - nz * by), wy = (double)F[1] + (nz * bx - nx * bz),
+               wz = (double)F[2] + (nx * by - ny * bx);
+  const double ux = ny * wz - nz * wy, uy = nz * wx - nx * wz, uz = nx * wy - ny * wx;
+  return gph * __builtin_amdgcn_sqrtf((float)(ux * ux + uy * uy + uz * uz)) * (float)kInvES;
+}
+
 // Eq. (3) with |v| = 1: chi_ph = gamma_ph / E_S |k^ x (E + k^ x B)|.
 __device__ __forceinline__ double chi_photon(double kx, double ky, double kz,
                                              double ex, double ey, double ez,

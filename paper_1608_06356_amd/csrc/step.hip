@@ -1149,9 +1149,14 @@ __device__ __forceinline__ bool photon_rate(const PairArgs<R> &a, const R *L, in
   R F[6];
   field_at<R>(a.f, i, x, y, z, F);
   W = 0.0;
-  chi = fields_finite<R>(F) ? chi_photon(kx, ky, kz, F[0], F[1], F[2], F[3], F[4], F[5]) : NAN;
+  if (!fields_finite<R>(F)) { chi = NAN; return false; }
+  if constexpr (sizeof(R) == 4) chi = chi_photon_f32(kx, ky, kz, gph, F);
+  else chi = chi_photon(kx, ky, kz, F[0], F[1], F[2], F[3], F[4], F[5]);
   if (!isfinite(chi)) return false;
-  if (gph >= (R)2) W = kRateUnit * (double)(h_pair<R>((R)chi, L, a.rg) / gph);
+  if (gph >= (R)2) {
+    if constexpr (sizeof(R) == 4) W = kRateUnit * (double)(h_pair<R, true>((R)chi, L, a.rg) * rcp<R>(gph));
+    else W = kRateUnit * (double)(h_pair<R>((R)chi, L, a.rg) / gph);
+  }
   return true;
 }
 
@@ -1177,9 +1182,14 @@ __device__ void pair_tile(const PairArgs<R> &a, const Tab &tab, const R *L, uint
     if (pid == kDeadId) continue;
     const R kx = KX[i], ky = KY[i], kz = KZ[i];
     R x = X[i], y = Y[i], z = Z[i];
-    const R gph = sqrt(kx * kx + ky * ky + kz * kz);
+    const R gph = root<R>(kx * kx + ky * ky + kz * kz);
     if (a.move && gph > (R)0) {
-      x += kx / gph * a.dt; y += ky / gph * a.dt; z += kz / gph * a.dt;
+      if constexpr (sizeof(R) == 4) {
+        const R vdt = rcp<R>(gph) * a.dt;
+        x += kx * vdt; y += ky * vdt; z += kz * vdt;
+      } else {
+        x += kx / gph * a.dt; y += ky / gph * a.dt; z += kz / gph * a.dt;
+      }
       if (a.f.kind == QED_FIELD_GRID) {
         wrap_coord<R>(x, box_len<R>(a.f, 0)); wrap_coord<R>(y, box_len<R>(a.f, 1));
         wrap_coord<R>(z, box_len<R>(a.f, 2));
@@ -1219,7 +1229,7 @@ __device__ void pair_tile(const PairArgs<R> &a, const Tab &tab, const R *L, uint
     const uint64_t pid = a.ph.id[i];
     const R kx = KX[i], ky = KY[i], kz = KZ[i];
     const R x = X[i], y = Y[i], z = Z[i];
-    const R gph = sqrt(kx * kx + ky * ky + kz * kz);
+    const R gph = root<R>(kx * kx + ky * ky + kz * kz);
     double chi, W;
     photon_rate<R>(a, L, i, x, y, z, kx, ky, kz, gph, chi, W);
     const uint4 u = stream4(pid, a.seed, step_of(a.step, a.d_step), kPhotonEvent, 0u);
