@@ -1181,7 +1181,9 @@ __device__ void pair_tile(const PairArgs<R> &a, const Tab &tab, const R *L, uint
     const uint64_t pid = i < n ? a.ph.id[i] : kDeadId;
     if (pid == kDeadId) continue;
     const R kx = KX[i], ky = KY[i], kz = KZ[i];
-    R x = X[i], y = Y[i], z = Z[i];
+    // positions are needed to move the photon or to gather from a grid only
+    R x = 0, y = 0, z = 0;
+    if (a.move || a.f.kind == QED_FIELD_GRID) { x = X[i]; y = Y[i]; z = Z[i]; }
     const R gph = root<R>(kx * kx + ky * ky + kz * kz);
     if (a.move && gph > (R)0) {
       if constexpr (sizeof(R) == 4) {
