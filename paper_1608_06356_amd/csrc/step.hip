@@ -1144,10 +1144,8 @@ constexpr int kPairThreads = 256, kPairItems = 4, kPairTile = kPairThreads * kPa
 // Field, chi_ph and pair rate of photon i after its move; false if the fields
 // are not finite (then chi is NaN and W = 0).
 template <typename R>
-__device__ __forceinline__ bool photon_rate(const PairArgs<R> &a, const R *L, int64_t i, R x, R y, R z, R kx,
-                                            R ky, R kz, R gph, double &chi, double &W) {
-  R F[6];
-  field_at<R>(a.f, i, x, y, z, F);
+__device__ __forceinline__ bool photon_rate_at(const PairArgs<R> &a, const R *L, const R F[6], R kx, R ky, R kz,
+                                               R gph, double &chi, double &W) {
   W = 0.0;
   if (!fields_finite<R>(F)) { chi = NAN; return false; }
   if constexpr (sizeof(R) == 4) chi = chi_photon_f32(kx, ky, kz, gph, F);
@@ -1158,6 +1156,14 @@ __device__ __forceinline__ bool photon_rate(const PairArgs<R> &a, const R *L, in
     else W = kRateUnit * (double)(h_pair<R>((R)chi, L, a.rg) / gph);
   }
   return true;
+}
+
+template <typename R>
+__device__ __forceinline__ bool photon_rate(const PairArgs<R> &a, const R *L, int64_t i, R x, R y, R z, R kx,
+                                            R ky, R kz, R gph, double &chi, double &W) {
+  R F[6];
+  field_at<R>(a.f, i, x, y, z, F);
+  return photon_rate_at<R>(a, L, F, kx, ky, kz, gph, chi, W);
 }
 
 // One tile of kPairTile photons, kPairItems per thread (photon base + it *
@@ -1174,16 +1180,45 @@ __device__ void pair_tile(const PairArgs<R> &a, const Tab &tab, const R *L, uint
   R *X = (R *)a.ph.x, *Y = (R *)a.ph.y, *Z = (R *)a.ph.z;
   const R *KX = (const R *)a.ph.px, *KY = (const R *)a.ph.py, *KZ = (const R *)a.ph.pz;
   uint32_t evbits = 0, nrange = 0, nnan = 0;
+  // float32: every load of the thread's photons first, so that their latencies
+  // overlap (float64 keeps them per photon: the registers would halve its
+  // occupancy); positions are needed to move the photon or to gather from a grid
+  constexpr bool kAhead = sizeof(R) == 4;
+  const bool need_x = a.move || a.f.kind == QED_FIELD_GRID, pp = kAhead && a.f.kind == QED_FIELD_PER_PARTICLE;
+  uint64_t pids[kPairItems];
+  R kk[kPairItems][3], xx[kPairItems][3], Fp[kPairItems][6];
+  double taus[kPairItems];
+#pragma unroll
+  for (int it = 0; it < kPairItems && kAhead; ++it) {
+    const int64_t i = base + (int64_t)it * kPairThreads + threadIdx.x;
+    const bool v = i < n;
+    pids[it] = v ? a.ph.id[i] : kDeadId;
+    kk[it][0] = v ? KX[i] : (R)0; kk[it][1] = v ? KY[i] : (R)0; kk[it][2] = v ? KZ[i] : (R)0;
+    taus[it] = v ? a.ph.tau[i] : 0.0;
+    const bool vx = v && need_x;
+    xx[it][0] = vx ? X[i] : (R)0; xx[it][1] = vx ? Y[i] : (R)0; xx[it][2] = vx ? Z[i] : (R)0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      Fp[it][c] = (v && pp) ? (R)a.f.pE[c][i] : (R)0;
+      Fp[it][3 + c] = (v && pp) ? (R)a.f.pB[c][i] : (R)0;
+    }
+  }
 #pragma unroll
   for (int it = 0; it < kPairItems; ++it) {
     const int64_t i = base + (int64_t)it * kPairThreads + threadIdx.x;
+    if constexpr (!kAhead) {
+      const bool v = i < n;
+      pids[it] = v ? a.ph.id[i] : kDeadId;
+      if (pids[it] != kDeadId) {
+        kk[it][0] = KX[i]; kk[it][1] = KY[i]; kk[it][2] = KZ[i];
+        taus[it] = a.ph.tau[i];
+        xx[it][0] = need_x ? X[i] : (R)0; xx[it][1] = need_x ? Y[i] : (R)0; xx[it][2] = need_x ? Z[i] : (R)0;
+      }
+    }
     // photons converted earlier and not yet compacted away are skipped
-    const uint64_t pid = i < n ? a.ph.id[i] : kDeadId;
-    if (pid == kDeadId) continue;
-    const R kx = KX[i], ky = KY[i], kz = KZ[i];
-    // positions are needed to move the photon or to gather from a grid only
-    R x = 0, y = 0, z = 0;
-    if (a.move || a.f.kind == QED_FIELD_GRID) { x = X[i]; y = Y[i]; z = Z[i]; }
+    if (pids[it] == kDeadId) continue;
+    const R kx = kk[it][0], ky = kk[it][1], kz = kk[it][2];
+    R x = xx[it][0], y = xx[it][1], z = xx[it][2];
     const R gph = root<R>(kx * kx + ky * ky + kz * kz);
     if (a.move && gph > (R)0) {
       if constexpr (sizeof(R) == 4) {
@@ -1199,12 +1234,19 @@ __device__ void pair_tile(const PairArgs<R> &a, const Tab &tab, const R *L, uint
       X[i] = x; Y[i] = y; Z[i] = z;
     }
     double chi, W;
-    if (photon_rate<R>(a, L, i, x, y, z, kx, ky, kz, gph, chi, W)) {
+    R F[6];
+    if (pp) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) F[c] = Fp[it][c];
+    } else {
+      field_at<R>(a.f, i, x, y, z, F);
+    }
+    if (photon_rate_at<R>(a, L, F, kx, ky, kz, gph, chi, W)) {
       nrange += chi > a.rg.pair_hi;
     } else {
       ++nnan;
     }
-    const double tau = a.ph.tau[i];
+    const double tau = taus[it];
     if (W > 0.0 && tau <= W * a.dtd) evbits |= 1u << it;
     else a.ph.tau[i] = tau - W * a.dtd;
   }
