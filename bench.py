@@ -346,7 +346,8 @@ def run_sampler(q, torch, weights, n=100_000_000, reps=5):
     return out
 
 
-def run_cascade(q, torch, weights, n=200_000_000, steps=100, dt=0.01, a0=1000.0, ngrid=128, sort_every=20):
+def run_cascade(q, torch, weights, n=200_000_000, steps=100, dt=0.01, a0=1000.0, ngrid=128, sort_every=20,
+                compact_every=10):
     """The cascade step (pair creation, both lepton passes with emission, photon
     compaction) on the standing wave at a0 = 1000, captured once as a hipGraph
     and replayed; electrons re-sorted by cell every `sort_every` steps outside the
@@ -355,7 +356,11 @@ def run_cascade(q, torch, weights, n=200_000_000, steps=100, dt=0.01, a0=1000.0,
     The 2e8 electrons are drawn on the device (torch's generator, seed 4) with
     the distributions of workloads.standing_wave_electrons: x uniform in the box,
     p ~ N(0, 10^2) per component, ids 0..n-1; the initial storage order is by
-    cell (qed_sort_by_cell, untimed)."""
+    cell (qed_sort_by_cell, untimed).  Photons converted into pairs stay in place
+    as dead slots (pair creation skips them) until the compaction, which runs
+    every `compact_every` steps: a stable compaction moves every photon behind
+    the first hole, so removing a few hundred converted photons each step would
+    move the whole population each step."""
     import workloads
     L = workloads.BOX_L
     res = {}
@@ -387,13 +392,14 @@ def run_cascade(q, torch, weights, n=200_000_000, steps=100, dt=0.01, a0=1000.0,
         ctx.qed_set_next_id(n)
         ctx.qed_set_step(0)
 
-        def one_step():
+        def one_step(compact=True):
             ctx.qed_fill_standing_wave_at_step(grid, ngrid, L, a0, 0.0, dt)
             ctx.qed_create_pairs(fld, ph, el, po, dt, q.QED_STEP_DEVICE)
             for sp, qq in ((el, -1), (po, 1)):
                 ctx.qed_gather_push(fld, sp, qq, dt, q.QED_STEP_DEVICE)
                 ctx.qed_emit_photons(sp, ph, q.QED_STEP_DEVICE)
-            ctx.qed_compact(ph)
+            if compact:
+                ctx.qed_compact(ph)
             ctx.qed_advance_step()
 
         def resort():
@@ -404,15 +410,17 @@ def run_cascade(q, torch, weights, n=200_000_000, steps=100, dt=0.01, a0=1000.0,
 
         one_step()                      # first step eagerly (state advances), then capture
         resort()                        # allocates the sort's scratch outside the timed loop
-        graph = torch.cuda.CUDAGraph()
+        graphs = {}
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            with torch.cuda.graph(graph, stream=side):
-                one_step()
+        for compact in (False, True):   # the step without and with the photon compaction
+            graphs[compact] = torch.cuda.CUDAGraph()
+            with torch.cuda.stream(side):
+                with torch.cuda.graph(graphs[compact], stream=side):
+                    one_step(compact)
         torch.cuda.current_stream().wait_stream(side)
-        for _ in range(2):              # the first replays upload the graph; not timed
-            graph.replay()
+        for compact in (False, True):   # the first replays upload the graphs; not timed
+            graphs[compact].replay()
         torch.cuda.synchronize()
         ctx.qed_get_status()
         processed = torch.zeros(1, dtype=torch.int64, device="cuda")
@@ -421,7 +429,7 @@ def run_cascade(q, torch, weights, n=200_000_000, steps=100, dt=0.01, a0=1000.0,
             if (k + 1) % sort_every == 0:
                 resort()
             processed.add_(el.count + po.count + ph.count)
-            graph.replay()
+            graphs[(k + 1) % compact_every == 0].replay()
 
         for k in range(sort_every):     # untimed warm-up through one re-sort
             step(k)
@@ -434,12 +442,12 @@ def run_cascade(q, torch, weights, n=200_000_000, steps=100, dt=0.01, a0=1000.0,
         res[name] = dict(value=tot / (ms * 1e-3), ms_per_step=ms / steps, electrons=el.n(), positrons=po.n(),
                          photons=ph.n(), pairs=st["pairs"], dropped=st["dropped"],
                          scan_timeouts=st["scan_timeouts"])
-        del graph, el, el_b, po, ph, grid
+        del graphs, el, el_b, po, ph, grid
         ctx.close()
         torch.cuda.empty_cache()
     res["workload"] = (f"cascade step on the standing wave a0={a0:g}, {n} electrons at start, {ngrid}^3 grid, "
-                       f"formula II, pairs + both lepton passes + photon compaction captured in one hipGraph, "
-                       f"{steps} replays, electrons re-sorted every {sort_every} steps")
+                       f"formula II, pairs + both lepton passes (+ photon compaction every {compact_every} steps) "
+                       f"captured as hipGraphs, {steps} replays, electrons re-sorted every {sort_every} steps")
     res["unit"] = "particle-steps/s (electrons + positrons + photons present at the start of each step)"
     if "surrogate" in res:
         res["ratio_surrogate_vs_table"] = res["surrogate"]["value"] / res["table"]["value"]
