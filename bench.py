@@ -360,7 +360,10 @@ def run_cascade(q, torch, weights, n=200_000_000, steps=100, dt=0.01, a0=1000.0,
     as dead slots (pair creation skips them) until the compaction, which runs
     every `compact_every` steps: a stable compaction moves every photon behind
     the first hole, so removing a few hundred converted photons each step would
-    move the whole population each step."""
+    move the whole population each step.  The photons are re-sorted by cell as
+    well, right after a compaction, into a second photon buffer (graphs are
+    captured for both buffers), which keeps their field gathers in pair creation
+    local."""
     import workloads
     L = workloads.BOX_L
     res = {}
@@ -375,7 +378,9 @@ def run_cascade(q, torch, weights, n=200_000_000, steps=100, dt=0.01, a0=1000.0,
                 ctx.qed_surrogate_io(k, weights[k])
         cap_e, cap_p, cap_g = int(1.25 * n), n // 4, 3 * n
         el, el_b = q.Species(cap_e, "f32"), q.Species(cap_e, "f32")
-        po, ph = q.Species(cap_p, "f32"), q.Species(cap_g, "f32")
+        po = q.Species(cap_p, "f32")
+        phs = [q.Species(cap_g, "f32"), q.Species(cap_g, "f32")]
+        cur = [0]                       # photon buffer in use
         gen = torch.Generator(device="cuda")
         gen.manual_seed(4)
         for a in (el_b.x, el_b.y, el_b.z):
@@ -392,7 +397,8 @@ def run_cascade(q, torch, weights, n=200_000_000, steps=100, dt=0.01, a0=1000.0,
         ctx.qed_set_next_id(n)
         ctx.qed_set_step(0)
 
-        def one_step(compact=True):
+        def one_step(compact=True, pb=0):
+            ph = phs[pb]
             ctx.qed_fill_standing_wave_at_step(grid, ngrid, L, a0, 0.0, dt)
             ctx.qed_create_pairs(fld, ph, el, po, dt, q.QED_STEP_DEVICE)
             for sp, qq in ((el, -1), (po, 1)):
@@ -407,47 +413,50 @@ def run_cascade(q, torch, weights, n=200_000_000, steps=100, dt=0.01, a0=1000.0,
             for a, b in ((el.x, el_b.x), (el.y, el_b.y), (el.z, el_b.z), (el.px, el_b.px), (el.py, el_b.py),
                          (el.pz, el_b.pz), (el.tau, el_b.tau), (el.id, el_b.id), (el.count, el_b.count)):
                 a.copy_(b)
+            ctx.qed_sort_by_cell(fld, phs[cur[0]], phs[1 - cur[0]])
+            cur[0] ^= 1
 
         one_step()                      # first step eagerly (state advances), then capture
         resort()                        # allocates the sort's scratch outside the timed loop
         graphs = {}
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
-        for compact in (False, True):   # the step without and with the photon compaction
-            graphs[compact] = torch.cuda.CUDAGraph()
-            with torch.cuda.stream(side):
-                with torch.cuda.graph(graphs[compact], stream=side):
-                    one_step(compact)
+        for pb in (0, 1):               # each photon buffer, the step without and with compaction
+            for compact in (False, True):
+                graphs[compact, pb] = torch.cuda.CUDAGraph()
+                with torch.cuda.stream(side):
+                    with torch.cuda.graph(graphs[compact, pb], stream=side):
+                        one_step(compact, pb)
         torch.cuda.current_stream().wait_stream(side)
-        for compact in (False, True):   # the first replays upload the graphs; not timed
-            graphs[compact].replay()
+        for g in graphs.values():       # the first replays upload the graphs; not timed
+            g.replay()
         torch.cuda.synchronize()
         ctx.qed_get_status()
         processed = torch.zeros(1, dtype=torch.int64, device="cuda")
 
         def step(k):
-            if (k + 1) % sort_every == 0:
+            if k % sort_every == 0:     # right after a compaction (sort_every is a multiple of it)
                 resort()
-            processed.add_(el.count + po.count + ph.count)
-            graphs[(k + 1) % compact_every == 0].replay()
+            processed.add_(el.count + po.count + phs[cur[0]].count)
+            graphs[(k + 1) % compact_every == 0, cur[0]].replay()
 
-        for k in range(sort_every):     # untimed warm-up through one re-sort
+        for k in range(1, sort_every + 1):   # untimed warm-up through one re-sort
             step(k)
         torch.cuda.synchronize()
         ctx.qed_get_status(check=False)
         processed.zero_()
-        ms = _timed(torch, step, steps)
+        ms = _timed(torch, lambda k: step(k + 1), steps)   # same schedule as the warm-up
         st, rc = ctx.qed_get_status(check=False)
         tot = int(processed.item())
         res[name] = dict(value=tot / (ms * 1e-3), ms_per_step=ms / steps, electrons=el.n(), positrons=po.n(),
-                         photons=ph.n(), pairs=st["pairs"], dropped=st["dropped"],
+                         photons=phs[cur[0]].n(), pairs=st["pairs"], dropped=st["dropped"],
                          scan_timeouts=st["scan_timeouts"])
-        del graphs, el, el_b, po, ph, grid
+        del graphs, el, el_b, po, phs, grid
         ctx.close()
         torch.cuda.empty_cache()
     res["workload"] = (f"cascade step on the standing wave a0={a0:g}, {n} electrons at start, {ngrid}^3 grid, "
                        f"formula II, pairs + both lepton passes (+ photon compaction every {compact_every} steps) "
-                       f"captured as hipGraphs, {steps} replays, electrons re-sorted every {sort_every} steps")
+                       f"captured as hipGraphs, {steps} replays, electrons and photons re-sorted every {sort_every} steps")
     res["unit"] = "particle-steps/s (electrons + positrons + photons present at the start of each step)"
     if "surrogate" in res:
         res["ratio_surrogate_vs_table"] = res["surrogate"]["value"] / res["table"]["value"]
