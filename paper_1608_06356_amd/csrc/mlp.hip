@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <type_traits>
+
 #include "internal.h"
 #include "lookup.h"
 #include "qed_device.h"
@@ -268,7 +270,7 @@ struct InferArgs {
 };
 
 struct InferLds {
-  NetLds A, B;
+  NetLdsI A, B;
   float chk[kRadNChi * (2 + 2 * kChkN)];
 };
 
@@ -277,8 +279,8 @@ constexpr int kInferThreads = 512;
 __global__ __launch_bounds__(kInferThreads) void k_infer(InferArgs a) {
   extern __shared__ unsigned char lds_raw[];
   InferLds &S = *reinterpret_cast<InferLds *>(lds_raw);
-  stage_net(a.thA, kA, &S.A, nullptr);
-  stage_net(a.thB, kB, &S.B, nullptr);
+  stage_net_infer(a.thA, kA, &S.A);
+  stage_net_infer(a.thB, kB, &S.B);
   for (int k = threadIdx.x; k < kRadNChi * (2 + 2 * kChkN); k += blockDim.x) S.chk[k] = a.chk[k];
   __syncthreads();
   const RowQ16 tab{a.q16, a.s0sc};
@@ -300,7 +302,7 @@ __global__ __launch_bounds__(kInferThreads) void k_infer(InferArgs a) {
     const bool in_chi = chi >= kRadChiMin && chi <= kRadChiMax;
     float y[2];
     // rates (net B)
-    forward_nc(S.B, 1, 2, xin(in_chi ? chi : 1.0), 0.f, y);
+    forward_inf(S.B, 1, 2, xin(in_chi ? chi : 1.0), 0.f, y);
     const float lchi = logf((float)chi);
     float lh = kBShift0 + kBScale0 * y[0] + lchi;
     const float env = logf(1.001f * (float)kHc1 * (float)chi);
@@ -312,7 +314,7 @@ __global__ __launch_bounds__(kInferThreads) void k_infer(InferArgs a) {
     else lhp = logf(h_pair<float>((float)chi, a.L32, a.rg));
     // xi (net A) with residual check against the Hermite CDF table
     reload_barrier();
-    forward_nc(S.A, 2, 1, xin(in_chi ? chi : 1.0), (float)(t / kTmax), y);
+    forward_inf(S.A, 2, 1, xin(in_chi ? chi : 1.0), (float)(t / kTmax), y);
     const bool in_u = fabsf(t) <= (float)kTmax;
     float s_hat = kAShift + kAScale * y[0] + lchi + 3.0f * (-log1pf(__expf(-t)));
     bool xi_ok = in_chi && in_u && isfinite(s_hat);
@@ -347,12 +349,15 @@ __global__ __launch_bounds__(kInferThreads) void k_infer(InferArgs a) {
   }
 }
 
-// raw forward for tests: y = net(x) for n samples (normalised inputs/outputs)
+// raw forward for tests: y = net(x) for n samples (normalised inputs/outputs),
+// in the K = 16 (Net = NetLds) or K = 32 (Net = NetLdsI) form
+template <class Net>
 __global__ __launch_bounds__(256) void k_forward_raw(const float *theta, int net, const float *x, int64_t n, float *y) {
   extern __shared__ unsigned char lds_raw[];
-  NetLds &S = *reinterpret_cast<NetLds *>(lds_raw);
+  Net &S = *reinterpret_cast<Net *>(lds_raw);
   const Layout L = net == 0 ? kA : kB;
-  stage_net(theta, L, &S, nullptr);
+  if constexpr (std::is_same_v<Net, NetLdsI>) stage_net_infer(theta, L, &S);
+  else stage_net(theta, L, &S, nullptr);
   __syncthreads();
   const int lane = threadIdx.x & 63, j = lane & 15;
   const int64_t ntile = (n + 15) / 16;
@@ -363,7 +368,7 @@ __global__ __launch_bounds__(256) void k_forward_raw(const float *theta, int net
     const float x0 = valid ? x[i * L.nin] : 0.f;
     const float x1 = (valid && L.nin > 1) ? x[i * L.nin + 1] : 0.f;
     float yy[2];
-    forward_nc(S, L.nin, L.nout, x0, x1, yy);
+    infer(S, L.nin, L.nout, x0, x1, yy);
     if (valid && (lane >> 4) == 0)
       for (int o = 0; o < L.nout; ++o) y[i * L.nout + o] = yy[o];
   }
@@ -397,7 +402,10 @@ hipError_t mlp_set_attributes() {
   hipError_t e = hipFuncSetAttribute((const void *)k_train, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)sizeof(TrainLds));
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void *)k_forward_raw, hipFuncAttributeMaxDynamicSharedMemorySize,
+    e = hipFuncSetAttribute((const void *)k_forward_raw<NetLdsI>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)sizeof(NetLdsI));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_forward_raw<NetLds>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)sizeof(NetLds));
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void *)k_infer, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(InferLds));
@@ -411,11 +419,17 @@ hipError_t launch_adam(float *theta, float *grad, float *m, float *v, int net, f
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_forward(const float *theta, int net, const float *x, int64_t n, float *y, hipStream_t st) {
+hipError_t launch_mlp_forward(const float *theta, int net, bool k16, const float *x, int64_t n, float *y,
+                              hipStream_t st) {
   int64_t blocks = ((n + 15) / 16 + 3) / 4;
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_forward_raw, dim3((unsigned)blocks), dim3(256), sizeof(NetLds), st, theta, net, x, n, y);
+  if (k16)
+    hipLaunchKernelGGL(k_forward_raw<NetLds>, dim3((unsigned)blocks), dim3(256), sizeof(NetLds), st, theta, net, x,
+                       n, y);
+  else
+    hipLaunchKernelGGL(k_forward_raw<NetLdsI>, dim3((unsigned)blocks), dim3(256), sizeof(NetLdsI), st, theta, net,
+                       x, n, y);
   return hipGetLastError();
 }
 

@@ -836,7 +836,9 @@ struct MlpDev {
 };
 
 // ln h_rad(chi) from net B for the 64 lanes of a wave; ok = passed the check.
-__device__ __forceinline__ float mlp_lnh(const mlp::NetLds &B, double chi, bool &ok) {
+// Net: mlp::NetLdsI (K = 32 form) or mlp::NetLds (K = 16 form).
+template <class Net>
+__device__ __forceinline__ float mlp_lnh(const Net &B, double chi, bool &ok) {
   const int lane = threadIdx.x & 63;
   const bool in = chi >= kRadChiMin && chi <= kMlpChiMax;
   const float xi_in = mlp::xin(in ? chi : 1.0);
@@ -846,7 +848,7 @@ __device__ __forceinline__ float mlp_lnh(const mlp::NetLds &B, double chi, bool 
     mlp::reload_barrier();
     const float x0 = __shfl(xi_in, q * 16 + (lane & 15), 64);
     float y[2];
-    mlp::forward_nc(B, 1, 1, x0, 0.f, y);   // the photon rate head only
+    mlp::infer(B, 1, 1, x0, 0.f, y);   // the photon rate head only
     if ((lane >> 4) == q) mine = y[0];
   }
   const float lchi = logf((float)chi);
@@ -857,9 +859,9 @@ __device__ __forceinline__ float mlp_lnh(const mlp::NetLds &B, double chi, bool 
 
 template <int FK>
 __global__ __launch_bounds__(kGPThreads, 4) void k_gather_push_mlp(GPArgs<float> a, MlpDev m) {
-  __shared__ mlp::NetLds B;
+  __shared__ mlp::NetLdsI B;
   __shared__ float lnh_s[kRadNChi];
-  mlp::stage_net(m.thB, mlp::kB, &B, nullptr);
+  mlp::stage_net_infer(m.thB, mlp::kB, &B);
   for (int k = threadIdx.x; k < kRadNChi; k += blockDim.x) lnh_s[k] = m.lnh32[k];
   __syncthreads();
   const int64_t n = *a.sp.count;
@@ -879,7 +881,7 @@ __global__ __launch_bounds__(kGPThreads, 4) void k_gather_push_mlp(GPArgs<float>
     const int64_t i = base + threadIdx.x;
     const bool valid = i < n;
     float F[6] = {0, 0, 0, 0, 0, 0};
-    float x = 0, y = 0, z = 0, px = 0, py = 0, pz = 0, g = 1;
+    float x = 0, y = 0, z = 0, px = 0, py = 0, pz = 0, ig = 1;
     double tau = 0.0, chi = 1.0;
     bool live = valid;
     if (live) {
@@ -891,14 +893,16 @@ __global__ __launch_bounds__(kGPThreads, 4) void k_gather_push_mlp(GPArgs<float>
       px = PX[i]; py = PY[i]; pz = PZ[i];
       tau = a.sp.tau[i];
       boris<float>(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5], a.q, a.dt);
-      g = sqrtf(1.f + px * px + py * py + pz * pz);
-      x += px / g * a.dt; y += py / g * a.dt; z += pz / g * a.dt;
+      const float g = root<float>(1.f + px * px + py * py + pz * pz);
+      ig = rcp<float>(g);
+      const float vdt = ig * a.dt;
+      x += px * vdt; y += py * vdt; z += pz * vdt;
       if (FK == QED_FIELD_GRID) {
         wrap_coord<float>(x, box_len<float>(f, 0)); wrap_coord<float>(y, box_len<float>(f, 1));
         wrap_coord<float>(z, box_len<float>(f, 2));
       }
       X[i] = x; Y[i] = y; Z[i] = z; PX[i] = px; PY[i] = py; PZ[i] = pz;
-      chi = chi_lepton(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5]);
+      chi = chi_lepton_f32(px, py, pz, g, F);
     }
     bool ok;
     const float lh = mlp_lnh(B, chi, ok);
@@ -908,7 +912,7 @@ __global__ __launch_bounds__(kGPThreads, 4) void k_gather_push_mlp(GPArgs<float>
       if (isfinite(chi) && chi > 0.0) {
         const float h = ok ? expf(lh) : h_rad<float>((float)chi, lnh_s, m.rg);
         nfb += !ok;
-        W = kRateUnit * (double)(h / g);
+        W = kRateUnit * (double)(h * ig);
       }
       flag = W > 0.0 && tau <= W * a.dtd;
       const uint64_t fbits = __ballot(flag);   // the live lanes' flags (others are not emitters)
@@ -935,7 +939,7 @@ __global__ __launch_bounds__(kGPThreads, 4) void k_gather_push_mlp(GPArgs<float>
 constexpr int kEmitMlpThreads = 512;
 
 struct EmitMlpLds {
-  mlp::NetLds A, B;
+  mlp::NetLds A, B;     // K = 16 form (measured faster at this kernel's occupancy)
   float chk[kRadNChi * (2 + 2 * mlp::kChkN)];
   float lnh[kRadNChi];
 };
