@@ -835,25 +835,45 @@ struct MlpDev {
   float tol;
 };
 
-// ln h_rad(chi) from net B for the 64 lanes of a wave; ok = passed the check.
-// Net: mlp::NetLdsI (K = 32 form) or mlp::NetLds (K = 16 form).
+// First output of a net for the lanes of a wave with `need` (others get 0).
+// The needing lanes are packed by ballot rank into the first ceil(m/16)
+// 16-sample tiles (inputs pushed with ds_permute, outputs pulled back with a
+// shuffle), so a wave makes one forward call per 16 needing lanes.  Samples are
+// columns of the matrix products and do not interact, so every needing lane
+// gets exactly what an unpacked evaluation would give it.
 template <class Net>
-__device__ __forceinline__ float mlp_lnh(const Net &B, double chi, bool &ok) {
+__device__ __forceinline__ float mlp_packed(const Net &N, int nin, bool need, float in0, float in1) {
   const int lane = threadIdx.x & 63;
-  const bool in = chi >= kRadChiMin && chi <= kMlpChiMax;
-  const float xi_in = mlp::xin(in ? chi : 1.0);
-  float mine = 0.f;
+  const uint64_t bal = __ballot(need);
+  const int m = __popcll(bal);
+  if (m == 0) return 0.f;                                      // uniform
+  const int rank = __popcll(bal & ((1ull << lane) - 1ull));     // needing lanes before this one
+  const int dst = need ? rank : m + (lane - rank);              // a permutation of 0..63
+  const float p0 = __int_as_float(__builtin_amdgcn_ds_permute(dst << 2, __float_as_int(in0)));
+  const float p1 = __int_as_float(__builtin_amdgcn_ds_permute(dst << 2, __float_as_int(in1)));
+  float yp = 0.f;
+  const int nt = (m + 15) >> 4;
 #pragma unroll 1
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < nt; ++q) {
     mlp::reload_barrier();
-    const float x0 = __shfl(xi_in, q * 16 + (lane & 15), 64);
+    const float i0 = __shfl(p0, q * 16 + (lane & 15), 64), i1 = __shfl(p1, q * 16 + (lane & 15), 64);
     float y[2];
-    mlp::infer(B, 1, 1, x0, 0.f, y);   // the photon rate head only
-    if ((lane >> 4) == q) mine = y[0];
+    mlp::infer(N, nin, 1, i0, i1, y);
+    if ((lane >> 4) == q) yp = y[0];                           // slot q*16 + (lane & 15) = lane
   }
+  const float y = __shfl(yp, rank, 64);
+  return need ? y : 0.f;
+}
+
+// ln h_rad(chi) from net B for the lanes of a wave with `need`; ok = passed the
+// check.  Net: mlp::NetLdsI (K = 32 form) or mlp::NetLds (K = 16 form).
+template <class Net>
+__device__ __forceinline__ float mlp_lnh(const Net &B, double chi, bool need, bool &ok) {
+  const bool in = chi >= kRadChiMin && chi <= kMlpChiMax;
+  const float mine = mlp_packed(B, 1, need, mlp::xin(in ? chi : 1.0), 0.f);   // the photon rate head only
   const float lchi = logf((float)chi);
   const float lh = mlp::kBShift0 + mlp::kBScale0 * mine + lchi;
-  ok = in && isfinite(lh) && lh <= logf(1.001f * (float)kHc1 * (float)chi);
+  ok = need && in && isfinite(lh) && lh <= logf(1.001f * (float)kHc1 * (float)chi);
   return lh;
 }
 
@@ -905,7 +925,7 @@ __global__ __launch_bounds__(kGPThreads, 4) void k_gather_push_mlp(GPArgs<float>
       chi = chi_lepton_f32(px, py, pz, g, F);
     }
     bool ok;
-    const float lh = mlp_lnh(B, chi, ok);
+    const float lh = mlp_lnh(B, chi, true, ok);
     bool flag = false;
     if (live) {
       double W = 0.0;
@@ -1001,15 +1021,7 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
       const float t = logf(uxi) - log1pf(-uxi);
       const bool in_chi = chi >= kRadChiMin && chi <= kMlpChiMax;
       const float xa0 = mlp::xin(in_chi ? chi : 1.0), xa1 = t / (float)mlp::kTmax;
-      float yA = 0.f;
-#pragma unroll 1
-      for (int q = 0; q < 4; ++q) {
-        mlp::reload_barrier();
-        const float i0 = __shfl(xa0, q * 16 + (lane & 15), 64), i1 = __shfl(xa1, q * 16 + (lane & 15), 64);
-        float yy[2];
-        mlp::forward_nc(S.A, 2, 1, i0, i1, yy);
-        if ((lane >> 4) == q) yA = yy[0];
-      }
+      const float yA = mlp_packed(S.A, 2, active, xa0, xa1);   // only the lanes still active
       const float lchi = logf((float)chi);
       const float s_hat = mlp::kAShift + mlp::kAScale * yA + lchi + 3.0f * (-log1pf(__expf(-t)));
       bool xi_ok = in_chi && fabsf(t) <= (float)mlp::kTmax && isfinite(s_hat);
@@ -1056,7 +1068,7 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
       // rate after a recoil (net B; every lane takes part in the forward pass)
       if (__any(recoil_now)) {
         bool ok;
-        const float lh = mlp_lnh(S.B, recoil_now ? chi : 1.0, ok);
+        const float lh = mlp_lnh(S.B, chi, recoil_now, ok);
         if (recoil_now) {
           float h = 0.f;
           if (isfinite(chi) && chi > 0.0) {
