@@ -4,16 +4,18 @@
 //   net B  log10 chi -> (ln h_rad - ln chi, ln h_pair + 8/(3 chi) - ln chi)
 //
 // Three hidden layers of width 64 with SiLU.  The two 64x64 layers run on
-// v_mfma_f32_16x16x16_bf16 with every operand split into bf16 hi + lo parts and
+// bf16 matrix cores (v_mfma_f32_16x16x16_bf16 for training and the emission
+// kernel, v_mfma_f32_16x16x32_bf16 for the other inference kernels) with every
+// operand split into bf16 hi + lo parts and
 // the three products hi*hi + hi*lo + lo*hi accumulated in float32 (about 16
 // significant bits; one bf16 product alone would leave ~3e-3 relative error,
 // too coarse for the 1e-3 rate target).  Input and output layers (1-2 inputs,
 // 1-2 outputs) are float32 vector code.
 //
-// A wave handles 16 samples.  With the 16x16x16 layout, lane l holds features
+// A forward call evaluates a tile of 16 samples.  Lane l holds features
 // mt*16 + 4*(l/16) + v (mt, v = 0..3) of sample l%16 both as the D result and as
 // the B operand of the next layer, so activations stay in registers between
-// layers.  Training (forward, backward, weight gradients, Adam) uses the same
+// layers; waves that own 64 samples make four calls.  Training (forward, backward, weight gradients, Adam) uses the same
 // products; training data are drawn from the float64 master tables.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -284,14 +286,14 @@ __global__ __launch_bounds__(kInferThreads) void k_infer(InferArgs a) {
   for (int k = threadIdx.x; k < kRadNChi * (2 + 2 * kChkN); k += blockDim.x) S.chk[k] = a.chk[k];
   __syncthreads();
   const RowQ16 tab{a.q16, a.s0sc};
-  const int lane = threadIdx.x & 63, j = lane & 15;
-  const int64_t ntile = (a.n + 15) / 16;
+  const int lane = threadIdx.x & 63;
+  const int64_t ntile = (a.n + 63) / 64;     // 64 samples per wave, one per lane
   const int wpb = blockDim.x >> 6;
   uint32_t nfx = 0, nfr = 0;
   for (int64_t tile = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); tile < ntile;
        tile += (int64_t)gridDim.x * wpb) {
     reload_barrier();
-    const int64_t i = tile * 16 + j;
+    const int64_t i = tile * 64 + lane;
     const bool valid = i < a.n;
     const double chi = valid ? a.chi[i] : 1.0;
     const double gam = valid ? a.gamma[i] : 1.0;
@@ -300,23 +302,36 @@ __global__ __launch_bounds__(kInferThreads) void k_infer(InferArgs a) {
     const float u = unit<float>(r.x), urow = unit<float>(r.z);
     const float t = logf(u) - log1pf(-u);
     const bool in_chi = chi >= kRadChiMin && chi <= kRadChiMax;
-    float y[2];
-    // rates (net B)
-    forward_inf(S.B, 1, 2, xin(in_chi ? chi : 1.0), 0.f, y);
+    const float x0 = xin(in_chi ? chi : 1.0), x1 = (float)(t / kTmax);
+    // the wave's 64 samples go through each net as four 16-sample tiles; lane
+    // q*16 + j keeps the outputs of sample j of tile q, its own
+    float yB0 = 0.f, yB1 = 0.f, yA = 0.f;
+#pragma unroll 1
+    for (int q = 0; q < 4; ++q) {
+      reload_barrier();
+      float y[2];
+      forward_inf(S.B, 1, 2, __shfl(x0, q * 16 + (lane & 15), 64), 0.f, y);    // rates (net B)
+      if ((lane >> 4) == q) { yB0 = y[0]; yB1 = y[1]; }
+    }
+#pragma unroll 1
+    for (int q = 0; q < 4; ++q) {
+      reload_barrier();
+      float y[2];
+      forward_inf(S.A, 2, 1, __shfl(x0, q * 16 + (lane & 15), 64), __shfl(x1, q * 16 + (lane & 15), 64), y);
+      if ((lane >> 4) == q) yA = y[0];                                          // xi (net A)
+    }
     const float lchi = logf((float)chi);
-    float lh = kBShift0 + kBScale0 * y[0] + lchi;
+    float lh = kBShift0 + kBScale0 * yB0 + lchi;
     const float env = logf(1.001f * (float)kHc1 * (float)chi);
     bool rate_ok = in_chi && isfinite(lh) && lh <= env;
     if (!rate_ok) lh = logf(h_rad<float>((float)chi, a.lnh32, a.rg));
     float lhp;
     if (chi < kPairChiMin || gam < 2.0) lhp = -INFINITY;
-    else if (chi <= kPairChiMax && isfinite(y[1])) lhp = kBShift1 + kBScale1 * y[1] + lchi - 8.0f / (3.0f * (float)chi);
+    else if (chi <= kPairChiMax && isfinite(yB1)) lhp = kBShift1 + kBScale1 * yB1 + lchi - 8.0f / (3.0f * (float)chi);
     else lhp = logf(h_pair<float>((float)chi, a.L32, a.rg));
-    // xi (net A) with residual check against the Hermite CDF table
-    reload_barrier();
-    forward_inf(S.A, 2, 1, xin(in_chi ? chi : 1.0), (float)(t / kTmax), y);
+    // xi with residual check against the Hermite CDF table
     const bool in_u = fabsf(t) <= (float)kTmax;
-    float s_hat = kAShift + kAScale * y[0] + lchi + 3.0f * (-log1pf(__expf(-t)));
+    float s_hat = kAShift + kAScale * yA + lchi + 3.0f * (-log1pf(__expf(-t)));
     bool xi_ok = in_chi && in_u && isfinite(s_hat);
     float xi, om;
     if (xi_ok) {
@@ -333,7 +348,7 @@ __global__ __launch_bounds__(kInferThreads) void k_infer(InferArgs a) {
     } else {
       sample_rad<float>(tab, (float)chi, u, urow, xi, om, a.rg);
     }
-    if (valid && (lane >> 4) == 0) {
+    if (valid) {
       a.lnw[i] = (float)((double)lh + log(kRateUnit / gam));
       a.xi[i] = xi;
       if (a.lnwp) a.lnwp[i] = isfinite(lhp) ? (float)((double)lhp + log(kRateUnit / gam)) : -INFINITY;
@@ -439,7 +454,7 @@ hipError_t launch_mlp_sample(qed_ctx *c, const double *chi, const double *gamma,
               step < 0 ? c->d_step : nullptr,
               c->rad_lnh32, c->pair_L32, c->rad_s0sc, c->rad_chk, c->rad_q16, lnw, xi, lnwp, tol,
               c->d_counters + cMlpFallbackXi, make_range(kRadChiMax, kPairChiMax)};
-  int64_t blocks = ((n + 15) / 16 + 7) / 8;
+  int64_t blocks = ((n + 63) / 64 + 7) / 8;
   if (blocks > c->n_cu) blocks = c->n_cu;      // one workgroup per CU (LDS-bound)
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_infer, dim3((unsigned)blocks), dim3(kInferThreads), sizeof(InferLds), st, a);

@@ -1,7 +1,8 @@
 // Device building blocks of the surrogate networks (shared by the training and
 // sampling kernels in mlp.hip and the surrogate variants of the step kernels):
-// split-BF16 64x64 layers on v_mfma_f32_16x16x16_bf16, the 16-sample forward
-// pass, the input normalisation and the residual-check CDF rows.
+// split-BF16 64x64 layers on the K = 16 and K = 32 bf16 matrix instructions,
+// the 16-sample forward passes, the input normalisation and the residual-check
+// CDF rows.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <math.h>
