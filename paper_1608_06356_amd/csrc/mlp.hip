@@ -137,7 +137,7 @@ __device__ void stage_tile(float *dst, const float val[4][4]) {
 }
 
 __global__ __launch_bounds__(kTrainThreads) void k_train(TrainArgs a) {
-  extern __shared__ unsigned char lds_raw[];
+  extern __shared__ __align__(16) unsigned char lds_raw[];
   TrainLds &S = *reinterpret_cast<TrainLds *>(lds_raw);
   const Layout L = a.net == 0 ? kA : kB;
   stage_net(a.theta, L, &S.s, &S.t);
@@ -279,7 +279,7 @@ struct InferLds {
 constexpr int kInferThreads = 512;
 
 __global__ __launch_bounds__(kInferThreads) void k_infer(InferArgs a) {
-  extern __shared__ unsigned char lds_raw[];
+  extern __shared__ __align__(16) unsigned char lds_raw[];
   InferLds &S = *reinterpret_cast<InferLds *>(lds_raw);
   stage_net_infer(a.thA, kA, &S.A);
   stage_net_infer(a.thB, kB, &S.B);
@@ -368,7 +368,7 @@ __global__ __launch_bounds__(kInferThreads) void k_infer(InferArgs a) {
 // in the K = 16 (Net = NetLds) or K = 32 (Net = NetLdsI) form
 template <class Net>
 __global__ __launch_bounds__(256) void k_forward_raw(const float *theta, int net, const float *x, int64_t n, float *y) {
-  extern __shared__ unsigned char lds_raw[];
+  extern __shared__ __align__(16) unsigned char lds_raw[];
   Net &S = *reinterpret_cast<Net *>(lds_raw);
   const Layout L = net == 0 ? kA : kB;
   if constexpr (std::is_same_v<Net, NetLdsI>) stage_net_infer(theta, L, &S);

@@ -965,7 +965,7 @@ struct EmitMlpLds {
 };
 
 __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a, MlpDev m) {
-  extern __shared__ unsigned char lds_raw[];
+  extern __shared__ __align__(16) unsigned char lds_raw[];
   EmitMlpLds &S = *reinterpret_cast<EmitMlpLds *>(lds_raw);
   __shared__ uint32_t scan_s[16];
   __shared__ uint32_t tile_s;
@@ -1483,7 +1483,7 @@ __global__ void k_init_tau(const uint64_t *id, double *tau, const int64_t *count
 template <typename V>
 __global__ void k_standing_wave(float *grid, int n, double dx, double a0, double t0, double dt_step,
                                 const int64_t *d_step) {
-  extern __shared__ float row_s[];
+  extern __shared__ __align__(16) float row_s[];
   const double t = d_step ? t0 + dt_step * (double)*d_step : t0;
   const double ct = cos(t), st = sin(t);
   for (int ix = threadIdx.x; ix < n; ix += blockDim.x) {
