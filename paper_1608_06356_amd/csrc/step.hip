@@ -983,7 +983,6 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
   for (int k = threadIdx.x; k < kRadNChi * (2 + 2 * mlp::kChkN); k += blockDim.x) S.chk[k] = m.chk[k];
   for (int k = threadIdx.x; k < kRadNChi; k += blockDim.x) S.lnh[k] = m.lnh32[k];
   const RowQ16 tab{m.q16, m.s0sc};     // fallback: 16-bit table through the caches
-  const int lane = threadIdx.x & 63;
   while (true) {
     const uint32_t tile = next_tile(a.sc.ticket, &tile_s);
     if ((int64_t)tile * kEmitMlpThreads >= n_em) break;
@@ -1065,7 +1064,7 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
           ++nrej;
         }
       }
-      // rate after a recoil (net B; every lane takes part in the forward pass)
+      // rate after a recoil (net B, evaluated for the lanes that recoiled)
       if (__any(recoil_now)) {
         bool ok;
         const float lh = mlp_lnh(S.B, chi, recoil_now, ok);
