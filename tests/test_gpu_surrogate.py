@@ -46,6 +46,13 @@ def test_forward_and_gradient_vs_oracle(net, netid, k16):
     scale = np.abs(ys).max()
     assert np.max(np.abs(yg - ys)) < 2e-5 * scale
     assert np.max(np.abs(yg - ye)) < 2e-4 * scale          # split products ~ 16 bits
+    # a sample's output does not depend on where it sits in a 16-sample tile
+    # (samples are independent columns of the matrix products): shifting the
+    # inputs by 5 moves every sample to another lane and tile, bit for bit the same
+    y5 = torch.empty((n - 5, nout), dtype=torch.float32, device="cuda")
+    ctx.qed_surrogate_forward(netid, dev(X[5:]), y5, k16=k16)
+    torch.cuda.synchronize()
+    assert np.array_equal(y5.cpu().numpy(), y.cpu().numpy()[5:])
     _, gs = mlp.loss_and_grad(th64, net, X.T.astype(np.float64), T.T.astype(np.float64),
                               M.T.astype(np.float64), mode="split")
     gg = g.cpu().numpy()
@@ -128,6 +135,22 @@ def test_trained_xi_ks_1e7(trained, rad_table_I, chi):
     print(f"chi {chi}: KS(exact) {ks1:.2e} KS(table sampler) {ks2:.2e} xi fallback {fb:.4%}")
     assert ks1 < 2e-3 and ks2 < 2e-3
     assert fb < 0.01          # u outside [1e-4, 1-1e-4] alone is 2e-4
+
+
+def test_sampler_position_independent(trained):
+    """qed_sample with the nets: each sample's ln W_rad, xi and ln W_pair are bit
+    for bit the same when the inputs are shifted by 37 (other lane, other
+    16-sample tile, other wave), with ragged tails on both runs."""
+    torch, q = need_gpu()
+    ctx = trained
+    n, k = 5000 + 37, 37
+    rng = np.random.default_rng(12)
+    chi = 10.0 ** rng.uniform(-3.5, 2.5, n)          # also outside the trained range
+    gam = rng.uniform(1.5, 3e3, n)
+    full = _sample(ctx, q, torch, chi, gam, q.QED_SAMPLER_MLP, step=3)
+    part = _sample(ctx, q, torch, chi[k:], gam[k:], q.QED_SAMPLER_MLP, step=3, seed_ids=k)
+    for a, b in zip(full, part):
+        assert np.array_equal(a[k:], b, equal_nan=True)
 
 
 def test_surrogate_gain_vs_table(trained):
