@@ -192,6 +192,53 @@ def _with_weights(q, trained, **kw):
     return ctx
 
 
+def test_surrogate_step_independent_of_order(trained):
+    """One surrogate step (rate net in the lepton pass, xi net and, after each
+    recoil, the rate net in the emission pass; up to kmax events) on 2e4
+    electrons at chi ~ 1 and ~ 10, and on the same electrons shuffled: every
+    electron's momentum and optical depth and the set of photons are bit for bit
+    the same, so no result depends on which lanes share a tile or a packed
+    forward call."""
+    torch, q = need_gpu()
+    n, b0 = 20000, 2000.0
+    rng = np.random.default_rng(31)
+    gam = np.where(rng.uniform(size=n) < 0.5, 206.0, 2060.0)
+    phi = rng.uniform(0.0, 2.0 * math.pi, n)
+    pm = np.sqrt(gam ** 2 - 1.0)
+    p = np.stack([pm * np.cos(phi), pm * np.sin(phi), np.zeros(n)], axis=-1)
+    x = np.zeros((n, 3))
+    ids = np.arange(n, dtype=np.uint64)
+    tau0 = rng.exponential(size=n)
+
+    def run(order):
+        ctx = _with_weights(q, trained, seed=23, kmax=4, flags=q.QED_FLAG_SURROGATE)
+        lep = q.Species(n, "f32")
+        ph = q.Species(4 * n, "f32")
+        lep.load(x[order], p[order], tau=tau0[order], ids=ids[order])
+        ctx.qed_set_next_id(n)
+        fld = q.Fields(q.QED_FIELD_UNIFORM, B=(0, 0, b0))
+        ctx.qed_gather_push(fld, lep, -1, 0.2, 0)
+        ctx.qed_emit_photons(lep, ph, 0)
+        st, _ = ctx.qed_get_status(check=False)
+        inv = np.argsort(lep.id[:n].cpu().numpy().view(np.uint64))
+        lepton = [a[:n].cpu().numpy()[inv] for a in (lep.px, lep.py, lep.pz, lep.tau)]
+        m = ph.n()
+        phot = np.stack([a[:m].double().cpu().numpy() for a in (ph.px, ph.py, ph.pz, ph.tau)], axis=1)
+        phot = phot[np.lexsort(phot.T[::-1])]
+        return lepton, phot, st
+
+    la, pa, sa = run(np.arange(n))
+    lb, pb, sb = run(rng.permutation(n))
+    print(f"order independence: {pa.shape[0]} photons, events {sa['events']}, capped {sa['capped']}, "
+          f"fallbacks xi {sa['mlp_fallback_xi']} rate {sa['mlp_fallback_rate']}")
+    assert sa["events"] > 2 * n and sa["capped"] > 0          # several events per electron, some capped
+    for a, b in zip(la, lb):
+        assert np.array_equal(a, b)
+    assert np.array_equal(pa, pb)
+    assert {k: sa[k] for k in ("events", "photons", "rejected", "capped")} == \
+           {k: sb[k] for k in ("events", "photons", "rejected", "capped")}
+
+
 def test_surrogate_step_spectrum_and_rate(trained):
     """The emission step with QED_FLAG_SURROGATE (rate net in the lepton pass, xi
     net in the emission pass): 1e7 photons at chi ~ 1 without recoil; event count
