@@ -64,10 +64,6 @@ extern "C" {
 /* photon spectrum used for the emission tables */
 /* qed_sample: table copy, or the surrogate networks with table fallback */
 #define QED_SAMPLER_MLP 2
-/* qed_surrogate_forward: OR'ed into net, evaluate with the K = 16 matrix-core
-   form that the surrogate emission kernel uses instead of the K = 32 form of the
-   lepton pass and qed_sample (the two forms compute the same split products) */
-#define QED_SURROGATE_K16 0x10
 
 #define QED_FORMULA_I  1        /* Eq. (1) */
 #define QED_FORMULA_II 2        /* Eq. (4) */
@@ -295,7 +291,7 @@ QED_API int qed_sample(qed_ctx_t ctx, const double *chi, const double *gamma, co
    qed_surrogate_io: copies a net's float32 parameters to (direction 0) or from
    (direction 1) host memory; layout W1 b1 W2 b2 W3 b3 W4 b4 (row-major [out][in]).
    qed_surrogate_forward: raw normalised outputs for n inputs (device, [n][nin] ->
-   [n][nout] float32); net may carry QED_SURROGATE_K16.  qed_surrogate_grad: gradient of the mean squared error
+   [n][nout] float32), evaluated as the inference kernels evaluate it.  qed_surrogate_grad: gradient of the mean squared error
    sum_o mask*(y - t)^2 / n over an external batch (device float32 arrays) into
    grad (device, params floats).
    qed_sample with precision QED_SAMPLER_MLP uses both nets; a rate outside

@@ -19,7 +19,6 @@ QED_FIELD_UNIFORM, QED_FIELD_GRID, QED_FIELD_PER_PARTICLE = 0, 1, 2
 QED_FLAG_NO_RECOIL, QED_FLAG_STATIC_PHOTONS, QED_FLAG_TRACK_DEAD, QED_FLAG_SURROGATE = 1, 2, 4, 8
 QED_FLAG_METHOD_I, QED_FLAG_NO_SUBSTEP = 16, 32
 QED_SAMPLER_MLP = 2
-QED_SURROGATE_K16 = 0x10
 DEAD_ID = 0xFFFFFFFFFFFFFFFF
 EXPORTS = ["qed_create", "qed_destroy", "qed_last_error", "qed_reserve", "qed_set_next_id",
            "qed_get_next_id", "qed_build_tables", "qed_build_tables_range", "qed_get_table", "qed_init_optical_depth",
@@ -247,8 +246,7 @@ class Context:
         assert w.size == n
         self._check(lib().qed_surrogate_io(self.h, net, w.ctypes.data_as(ctypes.c_void_p), w.nbytes, 1))
 
-    def qed_surrogate_forward(self, net, x, y, stream=None, k16=False):
-        net = net | (QED_SURROGATE_K16 if k16 else 0)
+    def qed_surrogate_forward(self, net, x, y, stream=None):
         return self._check(lib().qed_surrogate_forward(self.h, net, ctypes.c_void_p(x.data_ptr()), x.shape[0],
                                                        ctypes.c_void_p(y.data_ptr()), _stream(stream)))
 

@@ -442,12 +442,10 @@ int qed_surrogate_io(qed_ctx_t c, int net, float *host, size_t bytes, int direct
 }
 
 int qed_surrogate_forward(qed_ctx_t c, int net, const float *x, int64_t n, float *y, void *st) {
-  const bool k16 = (net & QED_SURROGATE_K16) != 0;
-  net &= ~QED_SURROGATE_K16;
   if (!c || !x || !y || n < 0 || (net != 0 && net != 1)) return QED_ERR_ARG;
   if (!c->mlp_theta[net]) return fail(c, QED_ERR_STATE, "surrogate weights not set");
   if (n == 0) return QED_OK;
-  hipError_t e = qed::launch_mlp_forward(c->mlp_theta[net], net, k16, x, n, y, S(st));
+  hipError_t e = qed::launch_mlp_forward(c->mlp_theta[net], net, x, n, y, S(st));
   return e == hipSuccess ? QED_OK : hip_fail(c, e, "surrogate_forward");
 }
 

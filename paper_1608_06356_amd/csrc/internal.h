@@ -93,8 +93,7 @@ hipError_t launch_mlp_grad(int net, const float *theta, float *grad, const doubl
                            int64_t nbatch, uint64_t sample0, uint32_t seed, hipStream_t st);
 hipError_t launch_adam(float *theta, float *grad, float *m, float *v, int net, float lr, float b1t, float b2t,
                        hipStream_t st);
-hipError_t launch_mlp_forward(const float *theta, int net, bool k16, const float *x, int64_t n, float *y,
-                              hipStream_t st);
+hipError_t launch_mlp_forward(const float *theta, int net, const float *x, int64_t n, float *y, hipStream_t st);
 hipError_t launch_mlp_sample(qed_ctx *c, const double *chi, const double *gamma, const uint64_t *id, int64_t n,
                              int64_t step, float *lnw, float *xi, float *lnwp, float tol, hipStream_t st);
 }

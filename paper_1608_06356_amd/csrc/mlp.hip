@@ -4,8 +4,8 @@
 //   net B  log10 chi -> (ln h_rad - ln chi, ln h_pair + 8/(3 chi) - ln chi)
 //
 // Three hidden layers of width 64 with SiLU.  The two 64x64 layers run on
-// bf16 matrix cores (v_mfma_f32_16x16x16_bf16 for training and the emission
-// kernel, v_mfma_f32_16x16x32_bf16 for the other inference kernels) with every
+// bf16 matrix cores (v_mfma_f32_16x16x16_bf16 for training,
+// v_mfma_f32_16x16x32_bf16 for inference) with every
 // operand split into bf16 hi + lo parts and
 // the three products hi*hi + hi*lo + lo*hi accumulated in float32 (about 16
 // significant bits; one bf16 product alone would leave ~3e-3 relative error,
@@ -19,8 +19,6 @@
 // products; training data are drawn from the float64 master tables.
 #include <hip/hip_runtime.h>
 #include <math.h>
-
-#include <type_traits>
 
 #include "internal.h"
 #include "lookup.h"
@@ -364,15 +362,12 @@ __global__ __launch_bounds__(kInferThreads) void k_infer(InferArgs a) {
   }
 }
 
-// raw forward for tests: y = net(x) for n samples (normalised inputs/outputs),
-// in the K = 16 (Net = NetLds) or K = 32 (Net = NetLdsI) form
-template <class Net>
+// raw forward for tests: y = net(x) for n samples (normalised inputs/outputs)
 __global__ __launch_bounds__(256) void k_forward_raw(const float *theta, int net, const float *x, int64_t n, float *y) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  Net &S = *reinterpret_cast<Net *>(lds_raw);
+  NetLdsI &S = *reinterpret_cast<NetLdsI *>(lds_raw);
   const Layout L = net == 0 ? kA : kB;
-  if constexpr (std::is_same_v<Net, NetLdsI>) stage_net_infer(theta, L, &S);
-  else stage_net(theta, L, &S, nullptr);
+  stage_net_infer(theta, L, &S);
   __syncthreads();
   const int lane = threadIdx.x & 63, j = lane & 15;
   const int64_t ntile = (n + 15) / 16;
@@ -383,7 +378,7 @@ __global__ __launch_bounds__(256) void k_forward_raw(const float *theta, int net
     const float x0 = valid ? x[i * L.nin] : 0.f;
     const float x1 = (valid && L.nin > 1) ? x[i * L.nin + 1] : 0.f;
     float yy[2];
-    infer(S, L.nin, L.nout, x0, x1, yy);
+    forward_inf(S, L.nin, L.nout, x0, x1, yy);
     if (valid && (lane >> 4) == 0)
       for (int o = 0; o < L.nout; ++o) y[i * L.nout + o] = yy[o];
   }
@@ -417,11 +412,8 @@ hipError_t mlp_set_attributes() {
   hipError_t e = hipFuncSetAttribute((const void *)k_train, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)sizeof(TrainLds));
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void *)k_forward_raw<NetLdsI>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    e = hipFuncSetAttribute((const void *)k_forward_raw, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)sizeof(NetLdsI));
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void *)k_forward_raw<NetLds>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)sizeof(NetLds));
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void *)k_infer, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(InferLds));
   return e;
@@ -434,17 +426,11 @@ hipError_t launch_adam(float *theta, float *grad, float *m, float *v, int net, f
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_forward(const float *theta, int net, bool k16, const float *x, int64_t n, float *y,
-                              hipStream_t st) {
+hipError_t launch_mlp_forward(const float *theta, int net, const float *x, int64_t n, float *y, hipStream_t st) {
   int64_t blocks = ((n + 15) / 16 + 3) / 4;
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
-  if (k16)
-    hipLaunchKernelGGL(k_forward_raw<NetLds>, dim3((unsigned)blocks), dim3(256), sizeof(NetLds), st, theta, net, x,
-                       n, y);
-  else
-    hipLaunchKernelGGL(k_forward_raw<NetLdsI>, dim3((unsigned)blocks), dim3(256), sizeof(NetLdsI), st, theta, net,
-                       x, n, y);
+  hipLaunchKernelGGL(k_forward_raw, dim3((unsigned)blocks), dim3(256), sizeof(NetLdsI), st, theta, net, x, n, y);
   return hipGetLastError();
 }
 

@@ -1,8 +1,8 @@
 // Device building blocks of the surrogate networks (shared by the training and
 // sampling kernels in mlp.hip and the surrogate variants of the step kernels):
-// split-BF16 64x64 layers on the K = 16 and K = 32 bf16 matrix instructions,
-// the 16-sample forward passes, the input normalisation and the residual-check
-// CDF rows.
+// split-BF16 64x64 layers on the K = 16 (training) and K = 32 (inference) bf16
+// matrix instructions, the 16-sample forward passes, the input normalisation and
+// the residual-check CDF rows.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -167,49 +167,13 @@ __device__ __forceinline__ void forward(const NetLds &s, int nin, int nout, floa
   }
 }
 
-// Forward pass without the training cache, K = 16 form (the layers of NetLds).
-// The emission kernel, which runs at two waves per SIMD, measured faster with
-// it than with forward_inf; the other inference kernels use forward_inf.
-__device__ __forceinline__ void forward_nc(const NetLds &s, int nin, int nout, float x0, float x1, float y[2]) {
-  float a[4][4], z[4][4];
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int f = feat(mt, v);
-      float t = s.b1[f] + s.W1[f * nin] * x0;
-      if (nin > 1) t += s.W1[f * nin + 1] * x1;
-      a[mt][v] = silu(t);
-    }
-  mm64(s.W2h, s.W2l, a, z);
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) a[mt][v] = silu(z[mt][v] + s.b2[feat(mt, v)]);
-  mm64(s.W3h, s.W3l, a, z);
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) a[mt][v] = silu(z[mt][v] + s.b3[feat(mt, v)]);
-  for (int o = 0; o < nout; ++o) {
-    float p = 0.f;
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) p += s.W4[o * H + feat(mt, v)] * a[mt][v];
-    p += __shfl_xor(p, 16, 64);
-    p += __shfl_xor(p, 32, 64);
-    y[o] = p + s.b4[o];
-  }
-}
-
 // ------------------------------------------------------------- inference
-// forward_inf evaluates the same function as `forward` (the same split products
-// of the same activations) with fewer instructions: the biases are the initial
-// accumulators of the matrix products, the small layers are read 16 bytes at a
-// time, and the 64x64 products use the K = 32 matrix-core instruction (half the
-// instructions of K = 16).  Measured on the lepton pass of the surrogate step
-// (four waves per SIMD): 1.21 -> 1.03 ms for 1e7 electrons.
+// Every inference kernel uses forward_inf: it evaluates the same function as
+// `forward` (the same split products of the same activations) with fewer
+// instructions: the biases are the initial accumulators of the matrix products,
+// the small layers are read 16 bytes at a time, and the 64x64 products use the
+// K = 32 matrix-core instruction (half the instructions of K = 16).  Measured on
+// the lepton pass of the surrogate step: 1.21 -> 1.03 ms for 1e7 electrons.
 typedef __bf16 b8 __attribute__((ext_vector_type(8)));
 
 // K = 32 layout of a 64x64 layer.  The order of k inside a 32-wide block is
@@ -330,14 +294,6 @@ __device__ __forceinline__ void forward_inf(const NetLdsI &s, int nin, int nout,
     q += __shfl_xor(q, 32, 64);
     y[o] = q + s.b4[o];
   }
-}
-
-// Inference forward pass in the form matching how the net was staged.
-__device__ __forceinline__ void infer(const NetLds &s, int nin, int nout, float x0, float x1, float y[2]) {
-  forward_nc(s, nin, nout, x0, x1, y);
-}
-__device__ __forceinline__ void infer(const NetLdsI &s, int nin, int nout, float x0, float x1, float y[2]) {
-  forward_inf(s, nin, nout, x0, x1, y);
 }
 
 __device__ __forceinline__ float xin(double chi) { return (float)((log10(chi) + kXShift) / kXScale); }

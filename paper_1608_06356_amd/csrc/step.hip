@@ -841,8 +841,7 @@ struct MlpDev {
 // shuffle), so a wave makes one forward call per 16 needing lanes.  Samples are
 // columns of the matrix products and do not interact, so every needing lane
 // gets exactly what an unpacked evaluation would give it.
-template <class Net>
-__device__ __forceinline__ float mlp_packed(const Net &N, int nin, bool need, float in0, float in1) {
+__device__ __forceinline__ float mlp_packed(const mlp::NetLdsI &N, int nin, bool need, float in0, float in1) {
   const int lane = threadIdx.x & 63;
   const uint64_t bal = __ballot(need);
   const int m = __popcll(bal);
@@ -858,7 +857,7 @@ __device__ __forceinline__ float mlp_packed(const Net &N, int nin, bool need, fl
     mlp::reload_barrier();
     const float i0 = __shfl(p0, q * 16 + (lane & 15), 64), i1 = __shfl(p1, q * 16 + (lane & 15), 64);
     float y[2];
-    mlp::infer(N, nin, 1, i0, i1, y);
+    mlp::forward_inf(N, nin, 1, i0, i1, y);
     if ((lane >> 4) == q) yp = y[0];                           // slot q*16 + (lane & 15) = lane
   }
   const float y = __shfl(yp, rank, 64);
@@ -866,9 +865,8 @@ __device__ __forceinline__ float mlp_packed(const Net &N, int nin, bool need, fl
 }
 
 // ln h_rad(chi) from net B for the lanes of a wave with `need`; ok = passed the
-// check.  Net: mlp::NetLdsI (K = 32 form) or mlp::NetLds (K = 16 form).
-template <class Net>
-__device__ __forceinline__ float mlp_lnh(const Net &B, double chi, bool need, bool &ok) {
+// check.
+__device__ __forceinline__ float mlp_lnh(const mlp::NetLdsI &B, double chi, bool need, bool &ok) {
   const bool in = chi >= kRadChiMin && chi <= kMlpChiMax;
   const float mine = mlp_packed(B, 1, need, mlp::xin(in ? chi : 1.0), 0.f);   // the photon rate head only
   const float lchi = logf((float)chi);
@@ -959,7 +957,7 @@ __global__ __launch_bounds__(kGPThreads, 4) void k_gather_push_mlp(GPArgs<float>
 constexpr int kEmitMlpThreads = 512;
 
 struct EmitMlpLds {
-  mlp::NetLds A, B;     // K = 16 form (measured faster at this kernel's occupancy)
+  mlp::NetLdsI A, B;
   float chk[kRadNChi * (2 + 2 * mlp::kChkN)];
   float lnh[kRadNChi];
 };
@@ -978,8 +976,8 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
   const int64_t n_em = hdr_s[0], ph0 = hdr_s[1];
   const uint64_t id0 = (uint64_t)hdr_s[2];
   if (n_em == 0) return;
-  mlp::stage_net(m.thA, mlp::kA, &S.A, nullptr);
-  mlp::stage_net(m.thB, mlp::kB, &S.B, nullptr);
+  mlp::stage_net_infer(m.thA, mlp::kA, &S.A);
+  mlp::stage_net_infer(m.thB, mlp::kB, &S.B);
   for (int k = threadIdx.x; k < kRadNChi * (2 + 2 * mlp::kChkN); k += blockDim.x) S.chk[k] = m.chk[k];
   for (int k = threadIdx.x; k < kRadNChi; k += blockDim.x) S.lnh[k] = m.lnh32[k];
   const RowQ16 tab{m.q16, m.s0sc};     // fallback: 16-bit table through the caches

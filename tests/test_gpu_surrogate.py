@@ -19,10 +19,8 @@ def _rand_theta(net, seed, scale=0.3):
     return np.random.default_rng(seed).normal(0, scale, mlp.n_params(net)).astype(np.float32)
 
 
-@pytest.mark.parametrize("k16", [False, True], ids=["k32", "k16"])
 @pytest.mark.parametrize("net,netid", [("A", 0), ("B", 1)])
-def test_forward_and_gradient_vs_oracle(net, netid, k16):
-    """Both inference forms (K = 32: lepton pass and sampler; K = 16: emission)."""
+def test_forward_and_gradient_vs_oracle(net, netid):
     torch, q = need_gpu()
     ctx = q.Context()
     th = _rand_theta(net, 10 + netid)
@@ -35,7 +33,7 @@ def test_forward_and_gradient_vs_oracle(net, netid, k16):
     M = (rng.uniform(size=(n, nout)) < 0.8).astype(np.float32)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     y = torch.empty((n, nout), dtype=torch.float32, device="cuda")
-    ctx.qed_surrogate_forward(netid, dev(X), y, k16=k16)
+    ctx.qed_surrogate_forward(netid, dev(X), y)
     g = torch.empty(mlp.n_params(net), dtype=torch.float32, device="cuda")
     ctx.qed_surrogate_grad(netid, dev(X), dev(T), dev(M), g)
     torch.cuda.synchronize()
@@ -50,7 +48,7 @@ def test_forward_and_gradient_vs_oracle(net, netid, k16):
     # (samples are independent columns of the matrix products): shifting the
     # inputs by 5 moves every sample to another lane and tile, bit for bit the same
     y5 = torch.empty((n - 5, nout), dtype=torch.float32, device="cuda")
-    ctx.qed_surrogate_forward(netid, dev(X[5:]), y5, k16=k16)
+    ctx.qed_surrogate_forward(netid, dev(X[5:]), y5)
     torch.cuda.synchronize()
     assert np.array_equal(y5.cpu().numpy(), y.cpu().numpy()[5:])
     _, gs = mlp.loss_and_grad(th64, net, X.T.astype(np.float64), T.T.astype(np.float64),
