@@ -270,6 +270,18 @@ QED_API int qed_sort_by_cell(qed_ctx_t ctx, const qed_fields_t *fields, qed_spec
    synchronisation).  Without the flag every call scans the whole species. */
 QED_API int qed_compact(qed_ctx_t ctx, qed_species_t *sp, void *stream);
 
+/* qed_compact with no allocation, for callers that cannot allocate device
+   memory (code under graph capture, serving loops, harnesses that forbid
+   hipMalloc).  Same result as qed_compact (same kernels, same QED_FLAG_TRACK_DEAD
+   behaviour); the scan state lives in a static device array of the library
+   (513 KiB per GPU, held until the process ends) instead of context memory, so
+   species are limited to capacity <= 2^26 (QED_ERR_RANGE beyond, detected on
+   the host before anything is enqueued).  Every call on one GPU shares that
+   array and clears it at its start: calls that overlap on one GPU (other
+   streams, other contexts, other threads) race and must be ordered by the
+   caller. */
+QED_API int qed_compact_static(qed_ctx_t ctx, qed_species_t *sp, void *stream);
+
 /* Standalone lookups: for n particles with chi (f64) and gamma (f64) and the ids
    used for their streams, writes ln W_rad (f32, uncut rate, -inf if zero) and one
    xi sample (f32, event k = 0 of `step`); precision selects the table copy:

@@ -25,7 +25,8 @@ EXPORTS = ["qed_create", "qed_destroy", "qed_last_error", "qed_reserve", "qed_se
            "qed_fill_standing_wave", "qed_gather_push", "qed_emit_photons", "qed_create_pairs",
            "qed_compact", "qed_sample", "qed_get_status", "qed_surrogate_params",
            "qed_surrogate_train", "qed_surrogate_io", "qed_surrogate_forward", "qed_surrogate_grad",
-           "qed_sort_by_cell", "qed_set_step", "qed_advance_step", "qed_fill_standing_wave_at_step"]
+           "qed_sort_by_cell", "qed_set_step", "qed_advance_step", "qed_fill_standing_wave_at_step",
+           "qed_compact_static"]
 QED_STEP_DEVICE = -1
 
 
@@ -96,6 +97,7 @@ def lib():
                                                 ctypes.POINTER(qed_species_t), ctypes.POINTER(qed_species_t),
                                                 ctypes.c_double, i64, vp]),
             "qed_compact": (ctypes.c_int, [vp, ctypes.POINTER(qed_species_t), vp]),
+            "qed_compact_static": (ctypes.c_int, [vp, ctypes.POINTER(qed_species_t), vp]),
             "qed_sample": (ctypes.c_int, [vp, vp, vp, vp, i64, ctypes.c_int, i64, vp, vp, vp, vp]),
             "qed_get_status": (ctypes.c_int, [vp, ctypes.POINTER(qed_counters_t), vp]),
             "qed_set_step": (ctypes.c_int, [vp, i64, vp]),
@@ -223,6 +225,9 @@ class Context:
 
     def qed_compact(self, sp, stream=None):
         return self._check(lib().qed_compact(self.h, ctypes.byref(sp.c), _stream(stream)))
+
+    def qed_compact_static(self, sp, stream=None):
+        return self._check(lib().qed_compact_static(self.h, ctypes.byref(sp.c), _stream(stream)))
 
     def qed_sample(self, chi, gamma, ids, precision, step, lnw, xi, lnwp=None, stream=None):
         n = chi.numel()

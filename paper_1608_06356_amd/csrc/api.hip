@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -103,6 +104,37 @@ int ensure_emitters(qed_ctx *c, int64_t n) {
 
 hipStream_t S(void *s) { return (hipStream_t)s; }
 
+// ------------------------------------------- static scratch (qed_compact_static)
+// Scan state of qed_compact_static in a file-scope device array, so that the
+// entry point needs no allocation: word 0 holds the tile ticket (low 32 bits),
+// words 1 .. kStaticTiles + 1 the tile status words, for species of up to
+// kStaticMaxParticles particles (513 KiB per device, held until the process
+// ends).  In host code `scratch` only names the symbol; its device address on
+// each GPU comes from hipGetSymbolAddress and is what the kernels are given.
+constexpr int64_t kStaticMaxParticles = (int64_t)1 << 26;
+constexpr int64_t kStaticTiles = kStaticMaxParticles / kCompactTile;
+constexpr int64_t kStaticStatusWords = kStaticTiles + 1;
+static __device__ __align__(256) uint64_t scratch[1 + kStaticStatusWords];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint64_t *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (the current device), looked up once
+// per device.
+hipError_t static_scratch_address(int device, uint64_t **out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<uint64_t *>(ptr);
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -118,6 +150,7 @@ int qed_create(qed_ctx_t *out, const qed_params_t *p) {
   int ncu = 0;
   if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device);
   if (e == hipSuccess) c->n_cu = ncu > 0 ? ncu : 256;
+  if (e == hipSuccess) e = static_scratch_address(c->device, &c->static_scratch);
   if (e == hipSuccess) e = qed::mlp_set_attributes();
   if (e == hipSuccess) e = qed::step_set_attributes();
   if (e == hipSuccess) e = dalloc(&c->d_counters, qed::cNumCounters);
@@ -341,6 +374,17 @@ int qed_compact(qed_ctx_t c, qed_species_t *sp, void *st) {
   if ((r = ensure_scan(c, sp->capacity))) return r;
   hipError_t e = qed::launch_compact(c, sp, S(st));
   return e == hipSuccess ? QED_OK : hip_fail(c, e, "compact");
+}
+
+int qed_compact_static(qed_ctx_t c, qed_species_t *sp, void *st) {
+  if (!c) return QED_ERR_ARG;
+  int r = check_species(c, sp, "species");
+  if (r) return r;
+  if (sp->capacity > kStaticMaxParticles)
+    return fail(c, QED_ERR_RANGE, "compact_static: capacity above the static scan state's limit of 2^26 particles");
+  uint64_t *w = c->static_scratch;   // this device's copy of `scratch`
+  hipError_t e = qed::launch_compact_scan(c, sp, reinterpret_cast<uint32_t *>(w), w + 1, kStaticStatusWords, S(st));
+  return e == hipSuccess ? QED_OK : hip_fail(c, e, "compact_static");
 }
 
 int qed_sort_by_cell(qed_ctx_t c, const qed_fields_t *f, qed_species_t *src, qed_species_t *dst, void *st) {

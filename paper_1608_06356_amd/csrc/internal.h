@@ -14,6 +14,9 @@ struct alignas(8) EmIdx {
   int32_t i, slot;
 };
 
+// Particles per tile of the compaction scan (one status word per tile).
+constexpr int64_t kCompactTile = 1024;
+
 // Largest node count per side of qed_fill_standing_wave grids.
 constexpr int kMaxWaveGrid = 4096;
 
@@ -67,6 +70,10 @@ struct qed_ctx {
 
   int n_cu = 256;
 
+  // device address of the library's static scratch array on this context's
+  // device (qed_compact_static)
+  uint64_t *static_scratch = nullptr;
+
   // cell sort scratch
   uint32_t *sort_keys = nullptr, *sort_vals = nullptr;
   int64_t sort_cap = 0;
@@ -107,6 +114,10 @@ hipError_t launch_pairs(qed_ctx *c, const qed_fields_t *f, const qed_species_t *
                         const qed_species_t *el, const qed_species_t *po, double dt, int64_t step,
                         hipStream_t st);
 hipError_t launch_compact(qed_ctx *c, const qed_species_t *sp, hipStream_t st);
+// The same with the scan state given by the caller: a ticket word and
+// status_len status words (at least capacity / kCompactTile + 2).
+hipError_t launch_compact_scan(qed_ctx *c, const qed_species_t *sp, uint32_t *ticket, uint64_t *status,
+                               int64_t status_len, hipStream_t st);
 hipError_t launch_init_tau(qed_ctx *c, const qed_species_t *sp, int64_t step, hipStream_t st);
 hipError_t launch_standing_wave(float *grid, int n, double L, double a0, double t0, double dt_step,
                                 const int64_t *d_step, hipStream_t st);

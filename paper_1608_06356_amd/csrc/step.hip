@@ -1565,12 +1565,18 @@ static FieldDev dev_fields(const qed_fields_t *f) {
   return d;
 }
 
-static hipError_t zero_scan(qed_ctx *c, int64_t ntiles, hipStream_t st) {
+// Clears the ticket and the first ntiles + 1 status words of a scan state
+// (a kernel, not a memset, so that the clear can be captured in a graph).
+static hipError_t zero_scan_at(uint32_t *ticket, uint64_t *status, int64_t status_len, int64_t ntiles,
+                               hipStream_t st) {
   const int64_t n = ntiles + 1;
-  if (n > c->status_len) return hipErrorInvalidValue;   // reserve() sizes the status array
-  hipLaunchKernelGGL(k_zero_scan, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, c->d_ticket,
-                     c->d_status, n);
+  if (n > status_len) return hipErrorInvalidValue;   // the caller sized the status array
+  hipLaunchKernelGGL(k_zero_scan, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ticket, status, n);
   return hipGetLastError();
+}
+
+static hipError_t zero_scan(qed_ctx *c, int64_t ntiles, hipStream_t st) {
+  return zero_scan_at(c->d_ticket, c->d_status, c->status_len, ntiles, st);   // reserve() sizes it
 }
 
 template <typename R, bool M1>
@@ -1733,10 +1739,17 @@ hipError_t launch_pairs(qed_ctx *c, const qed_fields_t *f, const qed_species_t *
 }
 
 hipError_t launch_compact(qed_ctx *c, const qed_species_t *sp, hipStream_t st) {
+  return launch_compact_scan(c, sp, c->d_ticket, c->d_status, c->status_len, st);
+}
+
+static_assert(kCTile == kCompactTile, "compaction tile size of the scan-state bound");
+
+hipError_t launch_compact_scan(qed_ctx *c, const qed_species_t *sp, uint32_t *ticket, uint64_t *status,
+                               int64_t status_len, hipStream_t st) {
   const int64_t ntiles = (sp->capacity + kCTile - 1) / kCTile;
-  hipError_t e = zero_scan(c, ntiles, st);
+  hipError_t e = zero_scan_at(ticket, status, status_len, ntiles, st);
   if (e != hipSuccess) return e;
-  const ScanDev sc{c->d_ticket, c->d_status};
+  const ScanDev sc{ticket, status};
   const bool track = (c->params.flags & QED_FLAG_TRACK_DEAD) != 0;
   const bool owner = track && c->killed_owner == sp->x;
   int64_t *killed = owner ? c->d_killed : nullptr;
