@@ -285,7 +285,12 @@ def run_pairs(q, torch, n=20_000_000, steps=100, dt=0.01):
     """2e7 static photons, chi_ph log-uniform in [1e-2, 1e2], isotropic, each in its
     own uniform E, B (|E|, |B| <= 2000); pairs appended, float32 state."""
     import workloads
-    w = workloads.pair_photons(n, E_S_1UM, seed=2)
+    w = workloads.pair_photons(n, seed=2)
+    # photon energy for the drawn chi_ph: gamma_ph = chi_ph E_S / |k x (E + k x B)| (Eq. 3, |v| = 1)
+    kh, E, B = w["khat"], w["E"], w["B"]
+    perp = np.linalg.norm(np.cross(kh, E + np.cross(kh, B)), axis=1)
+    w["k"] = kh * (w["chi_target"] * E_S_1UM / perp)[:, None]
+    del kh, E, B, perp
     ctx = q.Context(seed=2, kmax=4, flags=q.QED_FLAG_STATIC_PHOTONS)
     ctx.qed_build_tables(q.QED_FORMULA_I)
     ph, el, po = q.Species(n, "f32"), q.Species(n, "f32"), q.Species(n, "f32")

@@ -282,6 +282,19 @@ QED_API int qed_compact(qed_ctx_t ctx, qed_species_t *sp, void *stream);
    caller. */
 QED_API int qed_compact_static(qed_ctx_t ctx, qed_species_t *sp, void *stream);
 
+/* Quantum parameter of every particle [0, *count) of a species at its current
+   momentum and the fields at its position (uniform, grid or per-particle, as in
+   the step): kind QED_CHI_LEPTON evaluates Eq. (2) with v = p / gamma,
+   QED_CHI_PHOTON Eq. (3) with |v| = 1 and gamma_ph = |k|.  The same device code
+   as the step: float64 arithmetic throughout (float32 species: on the float32
+   values, which float64 holds exactly), in the rearranged form that avoids the
+   cancellation of (E + v x B)^2 - (v . E)^2 for ultra-relativistic particles.
+   Writes chi[i] (device float64 array of at least *count elements). */
+#define QED_CHI_LEPTON 0
+#define QED_CHI_PHOTON 1
+QED_API int qed_eval_chi(qed_ctx_t ctx, const qed_fields_t *fields, const qed_species_t *sp, int kind,
+                         double *chi, void *stream);
+
 /* Standalone lookups: for n particles with chi (f64) and gamma (f64) and the ids
    used for their streams, writes ln W_rad (f32, uncut rate, -inf if zero) and one
    xi sample (f32, event k = 0 of `step`); precision selects the table copy:

@@ -19,6 +19,7 @@ QED_FIELD_UNIFORM, QED_FIELD_GRID, QED_FIELD_PER_PARTICLE = 0, 1, 2
 QED_FLAG_NO_RECOIL, QED_FLAG_STATIC_PHOTONS, QED_FLAG_TRACK_DEAD, QED_FLAG_SURROGATE = 1, 2, 4, 8
 QED_FLAG_METHOD_I, QED_FLAG_NO_SUBSTEP = 16, 32
 QED_SAMPLER_MLP = 2
+QED_CHI_LEPTON, QED_CHI_PHOTON = 0, 1
 DEAD_ID = 0xFFFFFFFFFFFFFFFF
 EXPORTS = ["qed_create", "qed_destroy", "qed_last_error", "qed_reserve", "qed_set_next_id",
            "qed_get_next_id", "qed_build_tables", "qed_build_tables_range", "qed_get_table", "qed_init_optical_depth",
@@ -26,7 +27,7 @@ EXPORTS = ["qed_create", "qed_destroy", "qed_last_error", "qed_reserve", "qed_se
            "qed_compact", "qed_sample", "qed_get_status", "qed_surrogate_params",
            "qed_surrogate_train", "qed_surrogate_io", "qed_surrogate_forward", "qed_surrogate_grad",
            "qed_sort_by_cell", "qed_set_step", "qed_advance_step", "qed_fill_standing_wave_at_step",
-           "qed_compact_static"]
+           "qed_compact_static", "qed_eval_chi"]
 QED_STEP_DEVICE = -1
 
 
@@ -98,6 +99,8 @@ def lib():
                                                 ctypes.c_double, i64, vp]),
             "qed_compact": (ctypes.c_int, [vp, ctypes.POINTER(qed_species_t), vp]),
             "qed_compact_static": (ctypes.c_int, [vp, ctypes.POINTER(qed_species_t), vp]),
+            "qed_eval_chi": (ctypes.c_int, [vp, ctypes.POINTER(qed_fields_t), ctypes.POINTER(qed_species_t),
+                                            ctypes.c_int, vp, vp]),
             "qed_sample": (ctypes.c_int, [vp, vp, vp, vp, i64, ctypes.c_int, i64, vp, vp, vp, vp]),
             "qed_get_status": (ctypes.c_int, [vp, ctypes.POINTER(qed_counters_t), vp]),
             "qed_set_step": (ctypes.c_int, [vp, i64, vp]),
@@ -228,6 +231,11 @@ class Context:
 
     def qed_compact_static(self, sp, stream=None):
         return self._check(lib().qed_compact_static(self.h, ctypes.byref(sp.c), _stream(stream)))
+
+    def qed_eval_chi(self, fields, sp, kind, out, stream=None):
+        """out: device float64 tensor of at least sp.n() elements."""
+        return self._check(lib().qed_eval_chi(self.h, ctypes.byref(fields.c), ctypes.byref(sp.c), int(kind),
+                                              ctypes.c_void_p(out.data_ptr()), _stream(stream)))
 
     def qed_sample(self, chi, gamma, ids, precision, step, lnw, xi, lnwp=None, stream=None):
         n = chi.numel()

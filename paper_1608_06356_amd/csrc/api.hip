@@ -401,6 +401,17 @@ int qed_sort_by_cell(qed_ctx_t c, const qed_fields_t *f, qed_species_t *src, qed
   return e == hipSuccess ? QED_OK : hip_fail(c, e, "sort_by_cell");
 }
 
+int qed_eval_chi(qed_ctx_t c, const qed_fields_t *f, const qed_species_t *sp, int kind, double *chi, void *st) {
+  if (!c) return QED_ERR_ARG;
+  int r = check_species(c, sp, "species");
+  if (r) return r;
+  if ((r = check_fields(c, f))) return r;
+  if (kind != QED_CHI_LEPTON && kind != QED_CHI_PHOTON) return fail(c, QED_ERR_ARG, "eval_chi: bad kind");
+  if (!chi) return fail(c, QED_ERR_ARG, "eval_chi: chi is null");
+  hipError_t e = qed::launch_eval_chi(c, f, sp, kind == QED_CHI_PHOTON, chi, S(st));
+  return e == hipSuccess ? QED_OK : hip_fail(c, e, "eval_chi");
+}
+
 int qed_sample(qed_ctx_t c, const double *chi, const double *gamma, const uint64_t *id, int64_t n,
                int precision, int64_t step, float *lnw, float *xi, float *lnwp, void *st) {
   if (!c) return QED_ERR_ARG;

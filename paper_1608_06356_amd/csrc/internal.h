@@ -122,6 +122,8 @@ hipError_t launch_init_tau(qed_ctx *c, const qed_species_t *sp, int64_t step, hi
 hipError_t launch_standing_wave(float *grid, int n, double L, double a0, double t0, double dt_step,
                                 const int64_t *d_step, hipStream_t st);
 hipError_t launch_set_step(qed_ctx *c, int64_t v, int add, hipStream_t st);
+hipError_t launch_eval_chi(qed_ctx *c, const qed_fields_t *f, const qed_species_t *sp, int photon, double *out,
+                           hipStream_t st);
 hipError_t launch_sample(qed_ctx *c, const double *chi, const double *gamma, const uint64_t *id,
                          int64_t n, int precision, int64_t step, float *lnw, float *xi, float *lnwp,
                          hipStream_t st);

@@ -93,40 +93,38 @@ __device__ __forceinline__ double chi_lepton(double px, double py, double pz,
   return sqrt(g2 * (ux * ux + uy * uy + uz * uz) + ne * ne) * kInvES;
 }
 
-// The same expression for the float32 step, whose inputs (p, E, B) are float32.
-// Only E + n x B needs float64: there E and -n x B can nearly cancel, so n must be
-// exact to float64 rounding.  1/|p| comes from the float32 reciprocal square root
-// refined by two Newton steps in float64 (relative error below 1e-15); the
-// 1/(gamma^2 (1 + beta)) term multiplies the remainder of that cancellation and
-// needs only float32, with gamma the float32 Lorentz factor of p; the final
-// square root is taken in float32.  Result: chi to a few float32 ulps for the
-// given inputs.  |p|^2 below 1e-30 (float32 underflow of the estimate) takes the
-// float64 form above.
-__device__ __forceinline__ float chi_lepton_f32(float px, float py, float pz, float g, const float F[6]) {
+// The same expression for the float32 step, whose inputs (p, E, B) are float32
+// and therefore exact in float64: every operation is float64.  Only 1/|p|
+// starts from the float32 reciprocal square root, refined by two float64 Newton
+// steps (relative error below 1e-15), which saves the float64 division there;
+// gamma, 1/(gamma^2 (1 + beta)) and the final root are float64.  Where E and
+// -n x B nearly cancel, n must be exact to float64 rounding: it is.  |p|^2 below
+// 1e-30 (float32 underflow of the estimate) takes the form above.
+__device__ __forceinline__ double chi_lepton_f32(float px, float py, float pz, const float F[6]) {
   const double dx = px, dy = py, dz = pz;
   const double p2 = dx * dx + dy * dy + dz * dz;
-  if (!(p2 >= 1e-30)) return (float)chi_lepton(dx, dy, dz, F[0], F[1], F[2], F[3], F[4], F[5]);
+  if (!(p2 >= 1e-30)) return chi_lepton(dx, dy, dz, F[0], F[1], F[2], F[3], F[4], F[5]);
   double y = (double)__builtin_amdgcn_rsqf((float)p2);
   y = fma(0.5 * y, fma(-p2 * y, y, 1.0), y);
   y = fma(0.5 * y, fma(-p2 * y, y, 1.0), y);
   const double nx = dx * y, ny = dy * y, nz = dz * y;
   const double ex = F[0], ey = F[1], ez = F[2], bx = F[3], by = F[4], bz = F[5];
   const double cx = ny * bz - nz * by, cy = nz * bx - nx * bz, cz = nx * by - ny * bx;  // n x B
-  const double f = (double)__builtin_amdgcn_rcpf(g * (g + (float)(p2 * y)));
+  const double g2 = 1.0 + p2, g = sqrt(g2);
+  const double f = 1.0 / (g * (g + p2 * y));      // 1 / (gamma^2 (1 + beta))
   const double wx = (ex + cx) - cx * f, wy = (ey + cy) - cy * f, wz = (ez + cz) - cz * f;
   const double ux = ny * wz - nz * wy, uy = nz * wx - nx * wz, uz = nx * wy - ny * wx;  // n x w
   const double ne = nx * ex + ny * ey + nz * ez;
-  return __builtin_amdgcn_sqrtf((float)((1.0 + p2) * (ux * ux + uy * uy + uz * uz) + ne * ne)) * (float)kInvES;
+  return sqrt(g2 * (ux * ux + uy * uy + uz * uz) + ne * ne) * kInvES;
 }
 
-// Eq. (3) for the float32 step (inputs k, E, B float32), in the manner of
-// chi_lepton_f32: the direction k^ to float64 rounding (float32 rsqrt and two
-// float64 Newton steps) and E + k^ x B in float64, where E and -k^ x B can
-// cancel; gamma_ph (float32 |k|) and the final root in float32.
-__device__ __forceinline__ float chi_photon_f32(float kx, float ky, float kz, float gph, const float F[6]) {
+// Eq. (3) for the float32 step (inputs k, E, B float32, exact in float64), all
+// in float64 like chi_lepton_f32: k^ from the refined reciprocal square root,
+// gamma_ph = |k| = k^2 / |k|, E + k^ x B and the root in float64.
+__device__ __forceinline__ double chi_photon_f32(float kx, float ky, float kz, const float F[6]) {
   const double dx = kx, dy = ky, dz = kz;
   const double k2 = dx * dx + dy * dy + dz * dz;
-  if (!(k2 >= 1e-30)) return 0.0f;
+  if (!(k2 >= 1e-30)) return 0.0;
   double y = (double)__builtin_amdgcn_rsqf((float)k2);
   y = fma(0.5 * y, fma(-k2 * y, y, 1.0), y);
   y = fma(0.5 * y, fma(-k2 * y, y, 1.0), y);
@@ -135,7 +133,7 @@ __device__ __forceinline__ float chi_photon_f32(float kx, float ky, float kz, fl
   const double wx = (double)F[0] + (ny * bz - nz * by), wy = (double)F[1] + (nz * bx - nx * bz),
                wz = (double)F[2] + (nx * by - ny * bx);
   const double ux = ny * wz - nz * wy, uy = nz * wx - nx * wz, uz = nx * wy - ny * wx;
-  return gph * __builtin_amdgcn_sqrtf((float)(ux * ux + uy * uy + uz * uz)) * (float)kInvES;
+  return k2 * y * sqrt(ux * ux + uy * uy + uz * uz) * kInvES;
 }
 
 // Eq. (3) with |v| = 1: chi_ph = gamma_ph / E_S |k^ x (E + k^ x B)|.

@@ -528,7 +528,7 @@ __global__ __launch_bounds__(kGPThreads, (gp_waves<R, FK, M1>())) void k_gather_
     }
     X[t] = x; Y[t] = y; Z[t] = z; PX[t] = px; PY[t] = py; PZ[t] = pz;
     double chi;
-    if constexpr (sizeof(R) == 4) chi = chi_lepton_f32(px, py, pz, g, F);
+    if constexpr (sizeof(R) == 4) chi = chi_lepton_f32(px, py, pz, F);
     else chi = chi_lepton(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5]);
     double W = 0.0;
     if (isfinite(chi)) {
@@ -920,7 +920,7 @@ __global__ __launch_bounds__(kGPThreads, 4) void k_gather_push_mlp(GPArgs<float>
         wrap_coord<float>(z, box_len<float>(f, 2));
       }
       X[i] = x; Y[i] = y; Z[i] = z; PX[i] = px; PY[i] = py; PZ[i] = pz;
-      chi = chi_lepton_f32(px, py, pz, g, F);
+      chi = chi_lepton_f32(px, py, pz, F);
     }
     bool ok;
     const float lh = mlp_lnh(B, chi, true, ok);
@@ -1161,7 +1161,7 @@ __device__ __forceinline__ bool photon_rate_at(const PairArgs<R> &a, const R *L,
                                                R gph, double &chi, double &W) {
   W = 0.0;
   if (!fields_finite<R>(F)) { chi = NAN; return false; }
-  if constexpr (sizeof(R) == 4) chi = chi_photon_f32(kx, ky, kz, gph, F);
+  if constexpr (sizeof(R) == 4) chi = chi_photon_f32(kx, ky, kz, F);
   else chi = chi_photon(kx, ky, kz, F[0], F[1], F[2], F[3], F[4], F[5]);
   if (!isfinite(chi)) return false;
   if (gph >= (R)2) {
@@ -1501,6 +1501,27 @@ __global__ void k_standing_wave(float *grid, int n, double dx, double a0, double
   }
 }
 
+// chi of every particle [0, *count) with the fields at its position: Eq. (2)
+// for leptons (photon == 0) or Eq. (3) for photons, with the device functions
+// the step uses (float32 species: chi_*_f32, float64: chi_lepton / chi_photon).
+template <typename R>
+__global__ void k_eval_chi(SpeciesDev sp, FieldDev f, int photon, double *out) {
+  const int64_t n = *sp.count;
+  const R *X = (const R *)sp.x, *Y = (const R *)sp.y, *Z = (const R *)sp.z;
+  const R *PX = (const R *)sp.px, *PY = (const R *)sp.py, *PZ = (const R *)sp.pz;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    R F[6];
+    field_at<R>(f, i, X[i], Y[i], Z[i], F);
+    double chi;
+    if constexpr (sizeof(R) == 4)
+      chi = photon ? chi_photon_f32(PX[i], PY[i], PZ[i], F) : chi_lepton_f32(PX[i], PY[i], PZ[i], F);
+    else
+      chi = photon ? chi_photon(PX[i], PY[i], PZ[i], F[0], F[1], F[2], F[3], F[4], F[5])
+                   : chi_lepton(PX[i], PY[i], PZ[i], F[0], F[1], F[2], F[3], F[4], F[5]);
+    out[i] = chi;
+  }
+}
+
 template <typename R, typename Tab>
 __device__ void sample_one(const Tab &tab, const R *lnh, const R *L, double chi, double gamma,
                            uint64_t id, uint32_t seed, uint64_t step, float *lnw, float *xi_out,
@@ -1801,6 +1822,20 @@ __global__ void k_add_i64(int64_t *p, int64_t v) { *p += v; }
 hipError_t launch_set_step(qed_ctx *c, int64_t v, int add, hipStream_t st) {
   if (add) hipLaunchKernelGGL(k_add_i64, dim3(1), dim3(1), 0, st, c->d_step, v);
   else hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, st, c->d_step, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_chi(qed_ctx *c, const qed_fields_t *f, const qed_species_t *sp, int photon, double *out,
+                           hipStream_t st) {
+  int64_t blocks = (sp->capacity + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (sp->dtype == QED_F32)
+    hipLaunchKernelGGL(k_eval_chi<float>, dim3((unsigned)blocks), dim3(256), 0, st, dev_species(sp), dev_fields(f),
+                       photon, out);
+  else
+    hipLaunchKernelGGL(k_eval_chi<double>, dim3((unsigned)blocks), dim3(256), 0, st, dev_species(sp), dev_fields(f),
+                       photon, out);
+  (void)c;
   return hipGetLastError();
 }
 

@@ -153,6 +153,74 @@ def test_f32_chi_where_fields_cancel(rad_table_I):
     assert rel.max() < 2e-5
 
 
+def _chi_ref80(p, E, B, photon):
+    """Eq. (2) (or Eq. (3) with |v| = 1) evaluated literally in 80-bit floats."""
+    pl, El, Bl = (a.astype(np.longdouble) for a in (p, E, B))
+    pa = np.sqrt(np.sum(pl * pl, -1))
+    g = pa if photon else np.sqrt(1 + pa * pa)
+    v = pl / (pa if photon else g)[:, None]
+    f = El + np.cross(v, Bl)
+    return (g / E_S * np.sqrt(np.maximum(np.sum(f * f, -1) - np.sum(v * El, -1) ** 2, 0))).astype(np.float64)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_chi_vs_oracle_1e6(dtype):
+    """qed_eval_chi (the step's chi code) against the oracle's Eq. (2) / Eq. (3)
+    on the same inputs, relative error <= 1e-6, in the geometries where
+    E + v x B cancels: a crossed field E0 y, E0 z (a plane wave along +x) with
+    leptons within 1e-2 rad of +x (chi ~ gamma (1 - beta) E0 / E_S, down to ~1e-7)
+    and of -x, gamma 10 .. 1e4; random momenta in random per-particle fields; photons
+    isotropic and 1e-3 .. 1e-2 rad from +x in the crossed field.  The oracle's literal
+    float64 form is itself checked against an 80-bit evaluation (its error grows as
+    3e-16 gamma^2, R15, below 3e-8 here)."""
+    torch, q = need_gpu()
+    rng = np.random.default_rng(8)
+    cast = (lambda a: a.astype(np.float32).astype(np.float64)) if dtype == "f32" else (lambda a: a)
+    ctx = q.Context(seed=2)
+    n, E0 = 40000, 2000.0
+    gam = 10.0 ** rng.uniform(1.0, 4.0, n)
+    th = rng.uniform(0.0, 1e-2, n)
+    ph = rng.uniform(0.0, 2 * math.pi, n)
+    sgn = np.where(np.arange(n) % 4 == 3, -1.0, 1.0)
+    pa = np.sqrt(gam ** 2 - 1.0)
+    p_x = cast(np.stack([sgn * pa * np.cos(th), pa * np.sin(th) * np.cos(ph), pa * np.sin(th) * np.sin(ph)], -1))
+    p_r = cast(rng.normal(size=(n, 3)) * (10.0 ** rng.uniform(0, 4, n))[:, None])
+    f32 = lambda a: a.astype(np.float32).astype(np.float64)   # field arrays are float32 in the ABI
+    E_r = f32(rng.uniform(-2000, 2000, (n, 3)))
+    B_r = f32(rng.uniform(-2000, 2000, (n, 3)))
+    k_iso = rng.normal(size=(n, 3))
+    k_iso = cast(k_iso / np.linalg.norm(k_iso, axis=1)[:, None] * (10.0 ** rng.uniform(0, 5, n))[:, None])
+    # photons: chi_ph ~ gamma (1 - cos th) E0 / E_S; the literal form loses ~1/th^2 of
+    # its digits to cancellation, so th >= 1e-3 keeps the oracle itself within 1e-7
+    th2 = rng.uniform(1e-3, 1e-2, n)
+    k_x = cast(np.stack([np.cos(th2), np.sin(th2) * np.cos(ph), np.sin(th2) * np.sin(ph)], -1) * gam[:, None])
+    Ec, Bc = np.tile([0.0, E0, 0.0], (n, 1)), np.tile([0.0, 0.0, E0], (n, 1))
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+    crossed = q.Fields(q.QED_FIELD_UNIFORM, E=(0.0, E0, 0.0), B=(0.0, 0.0, E0))
+    perpart = q.Fields(q.QED_FIELD_PER_PARTICLE, E=[dev(E_r[:, c]) for c in range(3)],
+                       B=[dev(B_r[:, c]) for c in range(3)])
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    cases = (("lepton, crossed field", p_x, crossed, Ec, Bc, False),
+             ("lepton, random fields", p_r, perpart, E_r, B_r, False),
+             ("photon, random fields", k_iso, perpart, E_r, B_r, True),
+             ("photon, near the wave vector", k_x, crossed, Ec, Bc, True))
+    for name, p, fld, E, B, photon in cases:
+        sp = q.Species(n, dtype)
+        sp.load(np.zeros((n, 3)), p)
+        print(f"chi {dtype}: {name}", flush=True)
+        ctx.qed_eval_chi(fld, sp, q.QED_CHI_PHOTON if photon else q.QED_CHI_LEPTON, out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        ref = spectra.chi_photon(p, E, B) if photon else spectra.chi_lepton(p, E, B)
+        ref80 = _chi_ref80(p, E, B, photon)
+        pos = ref80 > 0
+        assert np.max(np.abs(ref[pos] / ref80[pos] - 1)) < 1e-7
+        rel = np.abs(got[pos] / ref[pos] - 1)
+        print(f"  chi {ref[pos].min():.2e} .. {ref.max():.2e}: max rel err {rel.max():.2e}")
+        assert rel.max() <= 1e-6
+        assert np.all(got[~pos] <= 1e-9 * ref.max())
+
+
 def test_fill_standing_wave_vs_oracle():
     """qed_fill_standing_wave on even (float4 stores) and odd (float2 stores) grids,
     and from a grid pointer that is only 8-byte aligned: every node against the
@@ -297,16 +365,25 @@ def test_grid_step_f32_one_step_parity(rad_table_I):
     rad = mc.RadSampler(rad_table_I, "q16")
     r = mc.lepton_step(x, p, tau, ens["id"], E, B, q=-1.0, dt=dt, step=5, seed=1, sampler=rad,
                        next_id=n, L=L)
-    # decisions: the emitter sets agree except where the oracle's margin is tiny
+    # decisions: the first-event decision tau <= W dt of a particle can flip only
+    # if its margin is below the float32 rate error (1e-5 of W dt: the hardware
+    # log/exp of the table lookup, ~1e-6, and the float32 push); the event
+    # counts must agree exactly unless such particles exist
     W = r["W"]
-    assert st["events"] >= r["n_events"] - 5 and st["scan_timeouts"] == 0
+    ambiguous = int(np.count_nonzero(np.abs(tau - W * dt) <= 1e-5 * W * dt))
+    print(f"events GPU {st['events']} oracle {r['n_events']}, ambiguous decisions {ambiguous}")
+    assert abs(st["events"] - r["n_events"]) <= 4 * ambiguous and st["scan_timeouts"] == 0
     np.testing.assert_allclose(g["p"], r["p"], rtol=2e-5, atol=2e-5 * np.abs(r["p"]).max())
     dx = np.abs(g["x"] - r["x"])
     dx = np.minimum(dx, L - dx)
     assert dx.max() < 1e-5
     assert gph["id"].size == r["photons"]["id"].size
     np.testing.assert_array_equal(gph["id"], r["photons"]["id"])
-    np.testing.assert_allclose(np.linalg.norm(gph["p"], axis=1), r["photons"]["gamma"], rtol=2e-3)
+    # gamma_ph: both sides decode the same 16-bit quantiles; float32 interpolation
+    # and decode stay far below the 16-bit step (<= 3e-4 relative in xi)
+    gerr = np.abs(np.linalg.norm(gph["p"], axis=1) / r["photons"]["gamma"] - 1)
+    print(f"gamma_ph max rel err {gerr.max():.2e}")
+    assert gerr.max() <= 3e-4
     np.testing.assert_allclose(gph["tau"], r["photons"]["tau"], rtol=1e-12)
     np.testing.assert_allclose(g["tau"], r["tau"], rtol=2e-4, atol=2e-4 * (W * dt).max())
 
@@ -370,7 +447,9 @@ def test_pairs_one_step_parity(pair_table, dtype):
     dead photons and surviving optical depths against the oracle."""
     torch, q = need_gpu()
     n = 200000
-    ph_in = workloads.pair_photons(n, E_S, seed=2)
+    ph_in = workloads.pair_photons(n, seed=2)
+    ph_in["k"] = ph_in["khat"] * (ph_in["chi_target"] /
+                                  spectra.chi_photon(ph_in["khat"], ph_in["E"], ph_in["B"]))[:, None]
     tau = mc.init_tau(ph_in["id"], seed=2) * 0.05      # many events in one step
     cast = (lambda a: a.astype(np.float32).astype(np.float64)) if dtype == "f32" else (lambda a: a)
     k = cast(ph_in["k"])

@@ -1,5 +1,6 @@
-"""Surrogate networks on the GPU: forward and gradient against the float64
-oracle (same split-BF16 products), training accuracy against the oracle's rate
+"""Surrogate networks on the GPU: forward and gradient against the exact
+float64 oracle network within the derived bound of the GPU's split-bf16
+arithmetic, training accuracy against the oracle's rate
 quadrature and exact CDF, fallback coverage, and the measured gain over the
 table sampler."""
 import math
@@ -10,6 +11,7 @@ import pytest
 
 from oracle import mc, mlp, tables
 from oracle.constants import RATE_UNIT
+from tests import mlp_bound
 from tests.gpu_helpers import need_gpu
 
 pytestmark = pytest.mark.gpu
@@ -21,29 +23,37 @@ def _rand_theta(net, seed, scale=0.3):
 
 @pytest.mark.parametrize("net,netid", [("A", 0), ("B", 1)])
 def test_forward_and_gradient_vs_oracle(net, netid):
+    """Forward (inference form) and gradient (training form) of random nets
+    against the exact float64 network, elementwise within the first-order bound
+    of the GPU's split-bf16 / float32 arithmetic (tests/mlp_bound.py), on 1000
+    samples (62 full 16-sample tiles and a ragged one)."""
     torch, q = need_gpu()
     ctx = q.Context()
     th = _rand_theta(net, 10 + netid)
     ctx.qed_surrogate_io(netid, th)
     nin, nout = mlp.SIZES[net]
-    n = 1000                                   # 62 full tiles and a ragged one
+    n = 1000
     rng = np.random.default_rng(4)
     X = rng.uniform(-1, 1, (n, nin)).astype(np.float32)
     T = rng.normal(size=(n, nout)).astype(np.float32)
     M = (rng.uniform(size=(n, nout)) < 0.8).astype(np.float32)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     y = torch.empty((n, nout), dtype=torch.float32, device="cuda")
+    print(f"surrogate forward/gradient: net {net}, {n} samples", flush=True)
     ctx.qed_surrogate_forward(netid, dev(X), y)
     g = torch.empty(mlp.n_params(net), dtype=torch.float32, device="cuda")
     ctx.qed_surrogate_grad(netid, dev(X), dev(T), dev(M), g)
     torch.cuda.synchronize()
     th64 = th.astype(np.float64)
-    ys, _ = mlp.forward(th64, net, X.T.astype(np.float64), mode="split")
-    ye, _ = mlp.forward(th64, net, X.T.astype(np.float64), mode="exact")
-    yg = y.cpu().numpy().T
-    scale = np.abs(ys).max()
-    assert np.max(np.abs(yg - ys)) < 2e-5 * scale
-    assert np.max(np.abs(yg - ye)) < 2e-4 * scale          # split products ~ 16 bits
+    X64, T64, M64 = (a.T.astype(np.float64) for a in (X, T, M))
+    ye, Ey, _ = mlp_bound.forward_bound(th64, net, X64)
+    _, sy, _ = mlp_bound.forward_bound(th64, net, X64, mode="rss")
+    yg = y.cpu().numpy().T.astype(np.float64)
+    err = np.abs(yg - ye)
+    print(f"  forward: max |err| {err.max():.2e}, max err/bound {np.max(err / Ey):.3f}, "
+          f"max err/sigma {np.max(err / sy):.2f}")
+    assert np.all(err <= Ey)
+    assert np.all(err <= mlp_bound.K_SIGMA * sy)
     # a sample's output does not depend on where it sits in a 16-sample tile
     # (samples are independent columns of the matrix products): shifting the
     # inputs by 5 moves every sample to another lane and tile, bit for bit the same
@@ -51,10 +61,14 @@ def test_forward_and_gradient_vs_oracle(net, netid):
     ctx.qed_surrogate_forward(netid, dev(X[5:]), y5)
     torch.cuda.synchronize()
     assert np.array_equal(y5.cpu().numpy(), y.cpu().numpy()[5:])
-    _, gs = mlp.loss_and_grad(th64, net, X.T.astype(np.float64), T.T.astype(np.float64),
-                              M.T.astype(np.float64), mode="split")
-    gg = g.cpu().numpy()
-    assert np.max(np.abs(gg - gs)) < 1e-4 * np.abs(gs).max()
+    ge, bound = mlp_bound.grad_bound(th64, net, X64, T64, M64)
+    _, sg = mlp_bound.grad_bound(th64, net, X64, T64, M64, mode="rss")
+    gg = g.cpu().numpy().astype(np.float64)
+    gerr = np.abs(gg - ge)
+    print(f"  gradient: max |err| {gerr.max():.2e} (max |g| {np.abs(ge).max():.2e}), "
+          f"max err/bound {np.max(gerr / bound):.3f}, max err/sigma {np.max(gerr / sg):.2f}")
+    assert np.all(gerr <= bound)
+    assert np.all(gerr <= mlp_bound.K_SIGMA * sg)
 
 
 @pytest.fixture(scope="module")

@@ -203,7 +203,8 @@ def test_standing_wave_is_vacuum_solution():
 
 def test_pair_step_yield_and_kinematics(pair_table):
     ps = mc.PairSampler(pair_table, "f64")
-    ph = workloads.pair_photons(50000, E_S, seed=2, chi_lo=0.5, chi_hi=5.0)
+    ph = workloads.pair_photons(50000, seed=2, chi_lo=0.5, chi_hi=5.0)
+    ph["k"] = ph["khat"] * (ph["chi_target"] / spectra.chi_photon(ph["khat"], ph["E"], ph["B"]))[:, None]
     tau = mc.init_tau(ph["id"], seed=2)
     dt = 0.01
     out = mc.photon_step(ph["x"], ph["k"], tau, ph["id"], ph["E"], ph["B"], dt=dt, step=0,
@@ -249,3 +250,94 @@ def test_method1_substep_rates(rad):
             assert np.all(r["N"] == N)
         else:
             assert r["n_events"] == n and rate < W / 5
+
+
+def _gamma(p):
+    return np.sqrt(1.0 + np.sum(np.asarray(p) ** 2, axis=-1))
+
+
+@pytest.mark.parametrize("kmax,dt", [(1, 1e-9), (4, 0.3)])
+def test_recoil_energy_and_direction(rad, kmax, dt):
+    """Recoil (the energies defined under Eq. 1: the photon takes eps_ph = xi eps_e,
+    the lepton keeps the rest): per lepton, gamma after the step plus the energies
+    of its photons equals gamma after the push, as long as no recoil hits the
+    gamma' = 1 floor; photons travel along the lepton's direction and the lepton
+    keeps its direction; a lepton whose events were all below the infrared cut
+    keeps its momentum; the rate after a recoil is the rate at the new chi and
+    gamma.  kmax = 1 with tau = 0: one event per lepton at the start of the step;
+    kmax = 4, dt = 0.3 at chi ~ 10: several events per lepton."""
+    n, b0, g = 20000, 2000.0, 2060.0
+    ens, E, B = _ensemble(n, b0, g, seed=21)
+    tau = np.zeros(n) if kmax == 1 else mc.init_tau(ens["id"], seed=21)
+    out = mc.lepton_step(ens["x"], ens["p"], tau, ens["id"], E, B, q=-1.0, dt=dt, step=0,
+                         seed=21, sampler=rad, next_id=n, kmax=kmax, recoil=True)
+    p_push = mc.boris(ens["p"], E, B, -1.0, dt)
+    g_push, g_out = _gamma(p_push), _gamma(out["p"])
+    ph = out["photons"]
+    assert ph["gamma"].size > n // 10
+    g_ph = np.bincount(ph["parent"], weights=ph["gamma"], minlength=n)
+    emitted = np.bincount(ph["parent"], minlength=n) > 0
+    np.testing.assert_allclose(g_out[emitted] + g_ph[emitted], g_push[emitted], rtol=1e-12)
+    assert np.all(g_out[emitted] > 1.0)
+    # energy really moved: the lepton lost what the photons carry
+    assert np.all(g_out[emitted] < g_push[emitted] - 1.9)
+    # no photon: momentum untouched (events below the cut do not recoil)
+    np.testing.assert_array_equal(out["p"][~emitted], p_push[~emitted])
+    # directions: photon k parallel to the pushed momentum, recoiled p as well
+    nh = p_push / np.linalg.norm(p_push, axis=1)[:, None]
+    kh = ph["k"] / np.linalg.norm(ph["k"], axis=1)[:, None]
+    np.testing.assert_allclose(np.sum(kh * nh[ph["parent"]], axis=1), 1.0, rtol=1e-13)
+    ph_dir = out["p"][emitted] / np.linalg.norm(out["p"][emitted], axis=1)[:, None]
+    np.testing.assert_allclose(np.sum(ph_dir * nh[emitted], axis=1), 1.0, rtol=1e-13)
+    np.testing.assert_allclose(np.linalg.norm(ph["k"], axis=1), ph["gamma"], rtol=1e-14)
+    # the rate left in W is the one at the recoiled state
+    chi_new = spectra.chi_lepton(out["p"][emitted], E[emitted], B[emitted])
+    np.testing.assert_allclose(out["W"][emitted], rad.rate(chi_new, g_out[emitted]), rtol=1e-12)
+    if kmax > 1:
+        assert np.max(np.bincount(ph["parent"], minlength=n)) >= 2
+
+
+def test_cascade_step_energy_and_bookkeeping(rad_table_I, pair_table):
+    """cascade_step in a uniform magnetic field (E = 0: the push does no work):
+    the total energy of electrons, positrons and photons is conserved (photon ->
+    e- + e+ with xi gamma_ph and (1 - xi) gamma_ph, lepton -> lepton + photon with
+    (1 - xi) gamma and xi gamma), up to the gamma' >= 1 floor; every pair adds one
+    electron and one positron, at the same rank, with ids next_id + 2r, + 1;
+    converted photons are removed; ids stay unique and below next_id."""
+    rad = mc.RadSampler(rad_table_I, "f64")
+    pair = mc.PairSampler(pair_table, "f64")
+    n, g0 = 2000, 1.0e4
+    b0 = 20.0 * E_S / g0                          # chi_e = 20 for p perpendicular to B
+    rng = np.random.default_rng(5)
+    phi = rng.uniform(0, 2 * math.pi, n)
+    pm = math.sqrt(g0 * g0 - 1.0)
+    st = dict(el=dict(x=np.zeros((n, 3)), p=np.stack([pm * np.cos(phi), pm * np.sin(phi), np.zeros(n)], -1),
+                      tau=mc.init_tau(np.arange(n, dtype=np.uint64), seed=7), id=np.arange(n, dtype=np.uint64)),
+              po=dict(x=np.zeros((0, 3)), p=np.zeros((0, 3)), tau=np.zeros(0), id=np.zeros(0, np.uint64)),
+              ph=dict(x=np.zeros((0, 3)), p=np.zeros((0, 3)), tau=np.zeros(0), id=np.zeros(0, np.uint64)),
+              next_id=n)
+
+    def energy():
+        return (_gamma(st["el"]["p"]).sum() + _gamma(st["po"]["p"]).sum()
+                + np.linalg.norm(st["ph"]["p"], axis=1).sum())
+
+    e0 = energy()
+    total_pairs = 0
+    for s in range(12):
+        ne, npo = st["el"]["id"].size, st["po"]["id"].size
+        nid = st["next_id"]
+        mc.cascade_step(st, dt=0.05, step=s, seed=7, rad=rad, pair=pair, E0=(0, 0, 0), B0=(0, 0, b0))
+        new_e = st["el"]["id"][ne:]
+        new_p = st["po"]["id"][npo:]
+        assert new_e.size == new_p.size
+        total_pairs += new_e.size
+        if new_e.size:
+            np.testing.assert_array_equal(new_p - new_e, np.ones(new_e.size, np.uint64))
+            np.testing.assert_array_equal((new_e - np.uint64(nid)) % np.uint64(2), np.zeros(new_e.size, np.uint64))
+        assert not np.any(st["ph"]["id"] == mc.DEAD_ID)
+        ids = np.concatenate([st["el"]["id"], st["po"]["id"], st["ph"]["id"]])
+        assert np.unique(ids).size == ids.size and ids.max() < st["next_id"]
+    assert total_pairs > 20 and st["ph"]["id"].size > n
+    assert st["el"]["id"].size == n + total_pairs
+    e1 = energy()
+    assert abs(e1 - e0) < 1e-11 * e0 + 2.0, (e0, e1)

@@ -13,10 +13,10 @@ uniform_b_ensembles  three sub-ensembles in a static uniform B = b0 z, E = 0, wi
     random gyrophase; x = 0.
 standing_wave_electrons  electrons uniform in the periodic box [0, 2 pi)^3 with
     Gaussian momenta of spread 10 m_e c per component.
-pair_photons  photons with chi_ph log-uniform in [1e-2, 1e2], isotropic
-    directions, and E, B drawn uniformly in the ball |E|, |B| <= 2000; the photon
-    energy is set from the drawn chi_ph and the transverse field (the caller
-    passes the normalising Schwinger field).
+pair_photons  photon directions (isotropic unit vectors), E and B drawn uniformly
+    in the ball |E|, |B| <= 2000, and a target chi_ph log-uniform in [1e-2, 1e2];
+    the caller turns the target into the photon energy with its own evaluation
+    of the photon's quantum parameter (this module computes none).
 sampler_inputs  log10 chi uniform in [-3, 2] with gamma = 1000, for the
     standalone sampler.
 single_electron_runs  the Fig. 5 cascade seed: nrun copies of one electron with
@@ -64,17 +64,13 @@ def _in_ball(rng, n, r):
     return d * rad[:, None]
 
 
-def pair_photons(n, e_s, seed=2, chi_lo=1e-2, chi_hi=1e2, fmax=2000.0):
+def pair_photons(n, seed=2, chi_lo=1e-2, chi_hi=1e2, fmax=2000.0):
     rng = np.random.default_rng(seed)
     khat = _isotropic(rng, n)
     E = _in_ball(rng, n, fmax)
     B = _in_ball(rng, n, fmax)
     chi = 10.0 ** rng.uniform(math.log10(chi_lo), math.log10(chi_hi), n)
-    f = E + np.cross(khat, B)
-    fperp = np.linalg.norm(np.cross(khat, f), axis=-1)
-    gph = chi * e_s / fperp
-    return dict(x=np.zeros((n, 3)), k=khat * gph[:, None], E=E, B=B,
-                id=np.arange(n, dtype=np.uint64), chi_target=chi)
+    return dict(x=np.zeros((n, 3)), khat=khat, E=E, B=B, id=np.arange(n, dtype=np.uint64), chi_target=chi)
 
 
 def sampler_inputs(n, seed=3, gamma=1000.0):
