@@ -146,6 +146,8 @@ typedef struct {
   int64_t compacted;           /* particles removed by qed_compact            */
   int64_t mlp_fallback_xi;     /* surrogate xi samples that fell back to the table */
   int64_t mlp_fallback_rate;   /* surrogate rates that fell back to the table     */
+  int64_t thinned;             /* surrogate path: candidate events not kept (thinning) */
+  int64_t envelope_exceeded;   /* surrogate path: a rate above its envelope (must be 0) */
 } qed_counters_t;
 
 /* Surrogate training (not part of the paper; see qed_surrogate_train). */

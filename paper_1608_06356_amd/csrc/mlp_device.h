@@ -213,6 +213,10 @@ __device__ void stage_net_infer(const float *th, const Layout &L, NetLdsI *s) {
 
 // acc += W a for a 64x64 layer in the swz32 layout, split products
 // (hi*hi + hi*lo + lo*hi); a and acc in the lane layout.
+// Lean: the weights of each 16-row block are read only when that block is
+// multiplied (a compiler barrier per block), which keeps the register footprint
+// small where the net is evaluated rarely (candidate events).
+template <bool Lean = false>
 __device__ __forceinline__ void mm64k32(const uint16_t *Wh, const uint16_t *Wl, const float a[4][4],
                                         float acc[4][4]) {
   const int lane = threadIdx.x & 63;
@@ -228,6 +232,7 @@ __device__ __forceinline__ void mm64k32(const uint16_t *Wh, const uint16_t *Wl, 
     }
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt) {
+    if constexpr (Lean) reload_barrier();
     f4 c = {acc[mt][0], acc[mt][1], acc[mt][2], acc[mt][3]};
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
@@ -250,6 +255,7 @@ __device__ __forceinline__ float4 feat4(const float *v, int mt) {
 }
 
 // Forward pass of one 16-sample tile for inference (no training cache).
+template <bool Lean = false>
 __device__ __forceinline__ void forward_inf(const NetLdsI &s, int nin, int nout, float x0, float x1, float y[2]) {
   float a[4][4], z[4][4];
 #pragma unroll
@@ -269,7 +275,7 @@ __device__ __forceinline__ void forward_inf(const NetLdsI &s, int nin, int nout,
     for (int v = 0; v < 4; ++v) a[mt][v] = silu(t[v]);
     z[mt][0] = b2.x; z[mt][1] = b2.y; z[mt][2] = b2.z; z[mt][3] = b2.w;
   }
-  mm64k32(s.W2h, s.W2l, a, z);
+  mm64k32<Lean>(s.W2h, s.W2l, a, z);
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt) {
     const float4 b3 = feat4(s.b3, mt);
@@ -277,7 +283,7 @@ __device__ __forceinline__ void forward_inf(const NetLdsI &s, int nin, int nout,
     for (int v = 0; v < 4; ++v) a[mt][v] = silu(z[mt][v]);
     z[mt][0] = b3.x; z[mt][1] = b3.y; z[mt][2] = b3.z; z[mt][3] = b3.w;
   }
-  mm64k32(s.W3h, s.W3l, a, z);
+  mm64k32<Lean>(s.W3h, s.W3l, a, z);
   float p[2] = {0.f, 0.f};
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt) {

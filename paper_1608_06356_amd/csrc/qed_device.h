@@ -39,11 +39,12 @@ constexpr double kHc1 = 1.4433756729740644;    // 5 / (2 sqrt 3)
 constexpr double kHc2 = 0.9237604307034013;    // 8 sqrt 3 / 15
 
 constexpr uint64_t kDeadId = ~0ull;
-enum Purpose : uint32_t { kInitTau = 0, kLeptonEvent = 1, kPhotonEvent = 2 };
+enum Purpose : uint32_t { kInitTau = 0, kLeptonEvent = 1, kPhotonEvent = 2, kLeptonThin = 5, kPhotonThin = 6 };
 
 // counters (layout of qed_counters_t)
 enum Counter { cEvents = 0, cPhotons, cRejected, cCapped, cPairs, cDropped, cChiRange,
-               cNanChi, cScanTimeout, cCompacted, cMlpFallbackXi, cMlpFallbackRate, cNumCounters };
+               cNanChi, cScanTimeout, cCompacted, cMlpFallbackXi, cMlpFallbackRate, cThinned,
+               cEnvelopeExceeded, cNumCounters };
 
 // ------------------------------------------------------------------ Philox
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of two 32x32->64

@@ -471,7 +471,11 @@ template <typename R, int FK, bool M1> constexpr int gp_waves() {
 }
 
 // M1: compiled with the method I generator (a.gen != 0), else optical depth only.
-template <typename R, int FK, bool M1>
+// Thin (float32, surrogate path): the optical depth runs down at the envelope
+// rate h_rad_env (Poisson thinning); the emission pass evaluates the rate net
+// only at the candidate events this finds and keeps each with probability
+// W / W_env.
+template <typename R, int FK, bool M1, bool Thin = false>
 __global__ __launch_bounds__(kGPThreads, (gp_waves<R, FK, M1>())) void k_gather_push(GPArgs<R> a) {
   __shared__ R lnh_s[kRadNChi];
   const int64_t tile = (int64_t)(blockIdx.x % kXcds) * a.tpx + blockIdx.x / kXcds;
@@ -533,7 +537,10 @@ __global__ __launch_bounds__(kGPThreads, (gp_waves<R, FK, M1>())) void k_gather_
     double W = 0.0;
     if (isfinite(chi)) {
       nrange = chi > a.rg.rad_hi;
-      W = kRateUnit * (double)(h_rad<R, true>((R)chi, lnh_s, a.rg) * ig);
+      R h;
+      if constexpr (Thin) h = (R)h_rad_env((float)chi);
+      else h = h_rad<R, true>((R)chi, lnh_s, a.rg);
+      W = kRateUnit * (double)(h * ig);
     } else {
       nnan = 1;
     }
@@ -835,13 +842,16 @@ struct MlpDev {
   float tol;
 };
 
-// First output of a net for the lanes of a wave with `need` (others get 0).
+// Output O of a net for the lanes of a wave with `need` (others get 0).
 // The needing lanes are packed by ballot rank into the first ceil(m/16)
 // 16-sample tiles (inputs pushed with ds_permute, outputs pulled back with a
 // shuffle), so a wave makes one forward call per 16 needing lanes.  Samples are
 // columns of the matrix products and do not interact, so every needing lane
-// gets exactly what an unpacked evaluation would give it.
-__device__ __forceinline__ float mlp_packed(const mlp::NetLdsI &N, int nin, bool need, float in0, float in1) {
+// gets exactly what an unpacked evaluation would give it.  Every lane of the
+// wave must call it (it returns at once when no lane needs it).
+template <int O = 0, bool Lean = false>
+__device__ __forceinline__ float mlp_packed(const mlp::NetLdsI &N, int nin, int nout, bool need, float in0,
+                                            float in1) {
   const int lane = threadIdx.x & 63;
   const uint64_t bal = __ballot(need);
   const int m = __popcll(bal);
@@ -857,101 +867,34 @@ __device__ __forceinline__ float mlp_packed(const mlp::NetLdsI &N, int nin, bool
     mlp::reload_barrier();
     const float i0 = __shfl(p0, q * 16 + (lane & 15), 64), i1 = __shfl(p1, q * 16 + (lane & 15), 64);
     float y[2];
-    mlp::forward_inf(N, nin, 1, i0, i1, y);
-    if ((lane >> 4) == q) yp = y[0];                           // slot q*16 + (lane & 15) = lane
+    mlp::forward_inf<Lean>(N, nin, nout, i0, i1, y);
+    if ((lane >> 4) == q) yp = y[O];                           // slot q*16 + (lane & 15) = lane
   }
   const float y = __shfl(yp, rank, 64);
   return need ? y : 0.f;
 }
 
-// ln h_rad(chi) from net B for the lanes of a wave with `need`; ok = passed the
-// check.
+// ln h_rad(chi) from net B for the lanes of a wave with `need`; ok = inside the
+// trained chi range, finite and below the thinning envelope (else the caller
+// takes the table).
 __device__ __forceinline__ float mlp_lnh(const mlp::NetLdsI &B, double chi, bool need, bool &ok) {
   const bool in = chi >= kRadChiMin && chi <= kMlpChiMax;
-  const float mine = mlp_packed(B, 1, need, mlp::xin(in ? chi : 1.0), 0.f);   // the photon rate head only
+  const float mine = mlp_packed<0>(B, 1, 1, need, mlp::xin(in ? chi : 1.0), 0.f);   // the photon rate head only
   const float lchi = logf((float)chi);
   const float lh = mlp::kBShift0 + mlp::kBScale0 * mine + lchi;
-  ok = need && in && isfinite(lh) && lh <= logf(1.001f * (float)kHc1 * (float)chi);
+  ok = need && in && isfinite(lh) && expf(lh) <= h_rad_env((float)chi);
   return lh;
 }
 
-template <int FK>
-__global__ __launch_bounds__(kGPThreads, 4) void k_gather_push_mlp(GPArgs<float> a, MlpDev m) {
-  __shared__ mlp::NetLdsI B;
-  __shared__ float lnh_s[kRadNChi];
-  mlp::stage_net_infer(m.thB, mlp::kB, &B);
-  for (int k = threadIdx.x; k < kRadNChi; k += blockDim.x) lnh_s[k] = m.lnh32[k];
-  __syncthreads();
-  const int64_t n = *a.sp.count;
-  const int64_t ntiles = (n + kGPTile - 1) / kGPTile;
-  const int xcd = blockIdx.x % kXcds;
-  const int64_t per = gridDim.x / kXcds;
-  float *X = (float *)a.sp.x, *Y = (float *)a.sp.y, *Z = (float *)a.sp.z;
-  float *PX = (float *)a.sp.px, *PY = (float *)a.sp.py, *PZ = (float *)a.sp.pz;
-  FieldDev f = a.f;
-  f.kind = FK;
-  uint32_t nfb = 0, nnan_m = 0;
-  for (int64_t lt = blockIdx.x / kXcds; lt < a.tpx; lt += per) {
-    mlp::reload_barrier();
-    const int64_t tile = (int64_t)xcd * a.tpx + lt;
-    if (tile >= ntiles) break;
-    const int64_t base = tile * kGPTile;
-    const int64_t i = base + threadIdx.x;
-    const bool valid = i < n;
-    float F[6] = {0, 0, 0, 0, 0, 0};
-    float x = 0, y = 0, z = 0, px = 0, py = 0, pz = 0, ig = 1;
-    double tau = 0.0, chi = 1.0;
-    bool live = valid;
-    if (live) {
-      x = X[i]; y = Y[i]; z = Z[i];
-      field_at<float>(f, i, x, y, z, F);
-      if (!fields_finite<float>(F)) { live = false; ++nnan_m; }
-    }
-    if (live) {
-      px = PX[i]; py = PY[i]; pz = PZ[i];
-      tau = a.sp.tau[i];
-      boris<float>(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5], a.q, a.dt);
-      const float g = root<float>(1.f + px * px + py * py + pz * pz);
-      ig = rcp<float>(g);
-      const float vdt = ig * a.dt;
-      x += px * vdt; y += py * vdt; z += pz * vdt;
-      if (FK == QED_FIELD_GRID) {
-        wrap_coord<float>(x, box_len<float>(f, 0)); wrap_coord<float>(y, box_len<float>(f, 1));
-        wrap_coord<float>(z, box_len<float>(f, 2));
-      }
-      X[i] = x; Y[i] = y; Z[i] = z; PX[i] = px; PY[i] = py; PZ[i] = pz;
-      chi = chi_lepton_f32(px, py, pz, F);
-    }
-    bool ok;
-    const float lh = mlp_lnh(B, chi, true, ok);
-    bool flag = false;
-    if (live) {
-      double W = 0.0;
-      if (isfinite(chi) && chi > 0.0) {
-        const float h = ok ? expf(lh) : h_rad<float>((float)chi, lnh_s, m.rg);
-        nfb += !ok;
-        W = kRateUnit * (double)(h * ig);
-      }
-      flag = W > 0.0 && tau <= W * a.dtd;
-      const uint64_t fbits = __ballot(flag);   // the live lanes' flags (others are not emitters)
-      if (flag) {
-        EmRec<float> r;
-        r.x[0] = x; r.x[1] = y; r.x[2] = z; r.p[0] = px; r.p[1] = py; r.p[2] = pz;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) r.F[c] = F[c];
-        r.tau = tau;
-        r.chi = chi;
-        r.W = W;
-        a.rec[rec_slot(i, fbits)] = r;
-      } else {
-        a.sp.tau[i] = tau - W * a.dtd;
-      }
-    }
-    const uint64_t bits = __ballot(flag);
-    if ((threadIdx.x & 63) == 0 && base + (threadIdx.x & ~63) < n) a.mask[(base + threadIdx.x) >> 6] = bits;
-  }
-  count_add(a.counters, cMlpFallbackRate, nfb);
-  count_add(a.counters, cNanChi, nnan_m);
+// ln h_pair(chi) from the pair head of net B, likewise (trained for chi in
+// [1e-2, 1e2]).
+__device__ __forceinline__ float mlp_lnh_pair(const mlp::NetLdsI &B, double chi, bool need, bool &ok) {
+  const bool in = chi >= kPairChiMin && chi <= kMlpChiMax;
+  const float y = mlp_packed<1, true>(B, 1, 2, need, mlp::xin(in ? chi : 1.0), 0.f);
+  const float lchi = logf((float)chi);
+  const float lh = mlp::kBShift1 + mlp::kBScale1 * y + lchi - 8.0f / (3.0f * (float)chi);
+  ok = need && in && isfinite(lh) && expf(lh) <= h_pair_env((float)chi);
+  return lh;
 }
 
 constexpr int kEmitMlpThreads = 512;
@@ -962,6 +905,15 @@ struct EmitMlpLds {
   float lnh[kRadNChi];
 };
 
+// Surrogate emission: the candidate events of the thinned lepton pass.  A
+// candidate at rate W_env = alpha E_S h_rad_env / gamma is kept with probability
+// W / W_env, W from net B (table if the net's output fails its check); a kept
+// event draws xi from net A with the residual check against the tabulated CDF
+// (table sample if it fails), applies the infrared cut and the recoil (W_env
+// follows the new chi and gamma); then the next candidate comes after a new
+// optical depth at W_env, up to kmax candidates per step (the cap is counted).
+// Counter k of the particle's stream serves candidate k: LEPTON_EVENT gives
+// (u_xi, u_tau, u_row, u_ph) as on the table path, LEPTON_THIN the keep draw.
 __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a, MlpDev m) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   EmitMlpLds &S = *reinterpret_cast<EmitMlpLds *>(lds_raw);
@@ -981,6 +933,7 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
   for (int k = threadIdx.x; k < kRadNChi * (2 + 2 * mlp::kChkN); k += blockDim.x) S.chk[k] = m.chk[k];
   for (int k = threadIdx.x; k < kRadNChi; k += blockDim.x) S.lnh[k] = m.lnh32[k];
   const RowQ16 tab{m.q16, m.s0sc};     // fallback: 16-bit table through the caches
+  const uint64_t step = step_of(a.step, a.d_step);
   while (true) {
     const uint32_t tile = next_tile(a.sc.ticket, &tile_s);
     if ((int64_t)tile * kEmitMlpThreads >= n_em) break;
@@ -988,10 +941,10 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
     const bool valid = r < n_em;
     float gph[kKmaxMax];
     double tph[kKmaxMax];
-    uint32_t nacc = 0, nev = 0, nrej = 0, ncap = 0, nfx = 0, nfr = 0;
+    uint32_t nacc = 0, nev = 0, nrej = 0, ncap = 0, nfx = 0, nfr = 0, nnull = 0, nexc = 0;
     float nx = 0, ny = 0, nz = 0, x = 0, y = 0, z = 0, px = 0, py = 0, pz = 0, g = 1;
     float F[6] = {0, 0, 0, 0, 0, 0};
-    double chi = 1.0, W = 0.0, rem = 0.0, tau = 0.0;
+    double chi = 1.0, Wenv = 0.0, rem = 0.0, tau = 0.0;
     uint64_t id = 0;
     int64_t i = 0;
     bool recoiled = false;
@@ -1002,45 +955,59 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
       const EmRec<float> rc = a.rec[e.slot];
 #pragma unroll
       for (int c = 0; c < 6; ++c) F[c] = rc.F[c];
-      chi = rc.chi; W = rc.W; rem = a.dtd - rc.tau / rc.W;
+      chi = rc.chi; Wenv = rc.W; rem = a.dtd - rc.tau / rc.W;   // time left after the first candidate
       px = rc.p[0]; py = rc.p[1]; pz = rc.p[2];
       x = rc.x[0]; y = rc.x[1]; z = rc.x[2];
       const float pa = sqrtf(px * px + py * py + pz * pz);
       if (pa > 0.f) { nx = px / pa; ny = py / pa; nz = pz / pa; }
       g = sqrtf(1.f + px * px + py * py + pz * pz);
     }
-    bool active = valid;
+    bool active = valid;       // a candidate is pending at time dt - rem
     for (int k = 0; k < a.kmax; ++k) {
       if (!__any(active)) break;
       mlp::reload_barrier();
-      const uint4 u = stream4(id, a.seed, step_of(a.step, a.d_step), kLeptonEvent, (uint32_t)k);
+      // keep the candidate with probability W / W_env (net B, packed over the
+      // lanes with a pending candidate)
+      bool ok;
+      const float lh = mlp_lnh(S.B, chi, active, ok);
+      bool keep = false;
+      if (active) {
+        float h = 0.f;
+        if (isfinite(chi) && chi > 0.0) {
+          h = ok ? expf(lh) : h_rad<float>((float)chi, S.lnh, m.rg);
+          nfr += !ok;
+        }
+        const double W = kRateUnit * (double)(h / g);
+        nexc += W > Wenv;
+        const uint4 ut = stream4(id, a.seed, step, kLeptonThin, (uint32_t)k);
+        keep = unit<double>(ut.x) * Wenv < W;
+        nnull += !keep;
+      }
+      const uint4 u = stream4(id, a.seed, step, kLeptonEvent, (uint32_t)k);
       const float uxi = unit<float>(u.x), urow = unit<float>(u.z);
       const float t = logf(uxi) - log1pf(-uxi);
       const bool in_chi = chi >= kRadChiMin && chi <= kMlpChiMax;
       const float xa0 = mlp::xin(in_chi ? chi : 1.0), xa1 = t / (float)mlp::kTmax;
-      const float yA = mlp_packed(S.A, 2, active, xa0, xa1);   // only the lanes still active
-      const float lchi = logf((float)chi);
-      const float s_hat = mlp::kAShift + mlp::kAScale * yA + lchi + 3.0f * (-log1pf(__expf(-t)));
-      bool xi_ok = in_chi && fabsf(t) <= (float)mlp::kTmax && isfinite(s_hat);
-      if (xi_ok) {
-        const float xp = (lchi - (float)m.rg.rad_lnlo) * (float)m.rg.rad_inv;
-        int ii = (int)floorf(xp);
-        ii = ii < 0 ? 0 : (ii > kRadNChi - 2 ? kRadNChi - 2 : ii);
-        const float w = xp - ii;
-        const float P = (1.f - w) * mlp::check_cdf(S.chk, ii, s_hat) + w * mlp::check_cdf(S.chk, ii + 1, s_hat);
-        xi_ok = fabsf(P - uxi) <= m.tol;
-      }
-      float xi, om;
-      if (xi_ok) {
-        xi = 1.f / (1.f + __expf(-s_hat));
-        om = 1.f / (1.f + __expf(s_hat));
-      } else if (active) {
-        sample_rad<float>(tab, (float)chi, uxi, urow, xi, om, m.rg);
-      } else {
-        xi = 0.f; om = 1.f;
-      }
-      bool recoil_now = false;
-      if (active) {
+      const float yA = mlp_packed<0>(S.A, 2, 1, keep, xa0, xa1);   // only the kept candidates
+      if (keep) {
+        const float lchi = logf((float)chi);
+        const float s_hat = mlp::kAShift + mlp::kAScale * yA + lchi + 3.0f * (-log1pf(__expf(-t)));
+        bool xi_ok = in_chi && fabsf(t) <= (float)mlp::kTmax && isfinite(s_hat);
+        if (xi_ok) {
+          const float xp = (lchi - (float)m.rg.rad_lnlo) * (float)m.rg.rad_inv;
+          int ii = (int)floorf(xp);
+          ii = ii < 0 ? 0 : (ii > kRadNChi - 2 ? kRadNChi - 2 : ii);
+          const float w = xp - ii;
+          const float P = (1.f - w) * mlp::check_cdf(S.chk, ii, s_hat) + w * mlp::check_cdf(S.chk, ii + 1, s_hat);
+          xi_ok = fabsf(P - uxi) <= m.tol;
+        }
+        float xi, om;
+        if (xi_ok) {
+          xi = 1.f / (1.f + __expf(-s_hat));
+          om = 1.f / (1.f + __expf(s_hat));
+        } else {
+          sample_rad<float>(tab, (float)chi, uxi, urow, xi, om, m.rg);
+        }
         ++nev;
         nfx += !xi_ok;
         const float gp = xi * g;
@@ -1055,41 +1022,28 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
             px = nx * pm; py = ny * pm; pz = nz * pm;
             g = gn;
             recoiled = true;
-            recoil_now = true;
             chi = chi_lepton(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5]);
+            Wenv = isfinite(chi) ? kRateUnit * (double)(h_rad_env((float)chi) / g) : 0.0;
           }
         } else {
           ++nrej;
         }
       }
-      // rate after a recoil (net B, evaluated for the lanes that recoiled)
-      if (__any(recoil_now)) {
-        bool ok;
-        const float lh = mlp_lnh(S.B, chi, recoil_now, ok);
-        if (recoil_now) {
-          float h = 0.f;
-          if (isfinite(chi) && chi > 0.0) {
-            h = ok ? expf(lh) : h_rad<float>((float)chi, S.lnh, m.rg);
-            nfr += !ok;
-          }
-          W = kRateUnit * (double)(h / g);
-        }
-      }
       if (active) {
         tau = -log(unit<double>(u.y));
-        const bool again = W > 0.0 && tau <= W * rem;
+        const bool again = Wenv > 0.0 && tau <= Wenv * rem;
         if (!again) {
           active = false;
         } else if (k + 1 >= a.kmax) {
           ++ncap;
           active = false;
         } else {
-          rem -= tau / W;
+          rem -= tau / Wenv;
         }
       }
     }
     if (valid) {
-      a.lep.tau[i] = tau - W * rem;
+      a.lep.tau[i] = tau - Wenv * rem;
       if (recoiled) { ((float *)a.lep.px)[i] = px; ((float *)a.lep.py)[i] = py; ((float *)a.lep.pz)[i] = pz; }
     }
     count_lds(cnt_s, cEvents, nev);
@@ -1098,6 +1052,8 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
     count_lds(cnt_s, cPhotons, nacc);
     count_lds(cnt_s, cMlpFallbackXi, nfx);
     count_lds(cnt_s, cMlpFallbackRate, nfr);
+    count_lds(cnt_s, cThinned, nnull);
+    count_lds(cnt_s, cEnvelopeExceeded, nexc);
     uint32_t total;
     const uint32_t off = block_exclusive(nacc, scan_s, &total);
     const uint64_t toff = tile_offset(tile, total, a.sc.status, a.counters, &off_s);
@@ -1321,6 +1277,216 @@ __device__ void pair_tile(const PairArgs<R> &a, const Tab &tab, const R *L, uint
     *a.next_id = id0 + 2 * (uint64_t)tt;
     if (a.killed) *a.killed += tt;
   }
+}
+
+// Surrogate pair pass (float32): the optical depth runs down at the envelope
+// rate W_env = alpha E_S h_pair_env / gamma_ph (Poisson thinning); a photon whose
+// optical depth runs out gets the pair head of net B evaluated (table if the
+// output fails its check) and its candidate is kept with probability
+// W / W_env; an unkept candidate draws a new optical depth and the next
+// candidate of the step follows at the same chi (the photon's chi does not
+// change within the step), up to kmax candidates.  Counter k of the photon's
+// PHOTON_THIN stream gives (keep draw, new optical depth) of candidate k; a kept
+// candidate makes the pair exactly as pair_tile does (PHOTON_EVENT, counter 0).
+__device__ void pair_tile_thin(const PairArgs<float> &a, const mlp::NetLdsI &Bn, const RowQ16 &tab, const float *L,
+                               uint32_t tile, uint64_t *scan_s, uint64_t *off_s, int64_t n, int64_t e0, int64_t p0,
+                               uint64_t id0, uint32_t *cnt, int kmax) {
+  const int64_t base = (int64_t)tile * kPairTile;
+  float *X = (float *)a.ph.x, *Y = (float *)a.ph.y, *Z = (float *)a.ph.z;
+  const float *KX = (const float *)a.ph.px, *KY = (const float *)a.ph.py, *KZ = (const float *)a.ph.pz;
+  uint32_t evbits = 0, nrange = 0, nnan = 0, nnull = 0, nfr = 0, ncap = 0, nexc = 0;
+  const bool need_x = a.move || a.f.kind == QED_FIELD_GRID, pp = a.f.kind == QED_FIELD_PER_PARTICLE;
+  const uint64_t step = step_of(a.step, a.d_step);
+  uint64_t pids[kPairItems];
+  float kk[kPairItems][3], xx[kPairItems][3], Fp[kPairItems][6];
+  double taus[kPairItems];
+#pragma unroll
+  for (int it = 0; it < kPairItems; ++it) {
+    const int64_t i = base + (int64_t)it * kPairThreads + threadIdx.x;
+    const bool v = i < n;
+    pids[it] = v ? a.ph.id[i] : kDeadId;
+    kk[it][0] = v ? KX[i] : 0.f; kk[it][1] = v ? KY[i] : 0.f; kk[it][2] = v ? KZ[i] : 0.f;
+    taus[it] = v ? a.ph.tau[i] : 0.0;
+    const bool vx = v && need_x;
+    xx[it][0] = vx ? X[i] : 0.f; xx[it][1] = vx ? Y[i] : 0.f; xx[it][2] = vx ? Z[i] : 0.f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      Fp[it][c] = (v && pp) ? a.f.pE[c][i] : 0.f;
+      Fp[it][3 + c] = (v && pp) ? a.f.pB[c][i] : 0.f;
+    }
+  }
+  // streaming part: move, field, chi, envelope rate; optical depths of the
+  // photons without a candidate are final here
+  double chis[kPairItems], wenv[kPairItems];
+  uint32_t cbits = 0;
+#pragma unroll
+  for (int it = 0; it < kPairItems; ++it) {
+    const int64_t i = base + (int64_t)it * kPairThreads + threadIdx.x;
+    chis[it] = 0.0;
+    wenv[it] = 0.0;
+    if (pids[it] == kDeadId) continue;          // converted photons not yet compacted are skipped
+    const float kx = kk[it][0], ky = kk[it][1], kz = kk[it][2];
+    const float gph = root<float>(kx * kx + ky * ky + kz * kz);
+    float x = xx[it][0], y = xx[it][1], z = xx[it][2];
+    if (a.move && gph > 0.f) {
+      const float vdt = rcp<float>(gph) * a.dt;
+      x += kx * vdt; y += ky * vdt; z += kz * vdt;
+      if (a.f.kind == QED_FIELD_GRID) {
+        wrap_coord<float>(x, box_len<float>(a.f, 0)); wrap_coord<float>(y, box_len<float>(a.f, 1));
+        wrap_coord<float>(z, box_len<float>(a.f, 2));
+      }
+      X[i] = x; Y[i] = y; Z[i] = z;
+    }
+    float F[6];
+    if (pp) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) F[c] = Fp[it][c];
+    } else {
+      field_at<float>(a.f, i, x, y, z, F);
+    }
+    double chi = 0.0, We = 0.0;
+    if (fields_finite<float>(F)) {
+      chi = chi_photon_f32(kx, ky, kz, F);
+      if (isfinite(chi)) {
+        nrange += chi > a.rg.pair_hi;
+        if (gph >= 2.f) We = kRateUnit * (double)(h_pair_env((float)chi) * rcp<float>(gph));
+      } else {
+        ++nnan;
+      }
+    } else {
+      ++nnan;
+    }
+    chis[it] = chi;
+    wenv[it] = We;
+    if (We > 0.0 && taus[it] <= We * a.dtd) cbits |= 1u << it;
+    else a.ph.tau[i] = taus[it] - We * a.dtd;
+  }
+  // candidates: the net for every lane of the wave at once, one item at a time
+  // (one copy of the net's code: the item's values are picked by selects)
+  float gphs[kPairItems];
+#pragma unroll
+  for (int it = 0; it < kPairItems; ++it)
+    gphs[it] = root<float>(kk[it][0] * kk[it][0] + kk[it][1] * kk[it][1] + kk[it][2] * kk[it][2]);
+#pragma unroll 1
+  for (int it = 0; it < kPairItems; ++it) {
+    if (!__any((cbits >> it) & 1u)) continue;    // uniform
+    const bool cand = (cbits >> it) & 1u;
+    const int64_t i = base + (int64_t)it * kPairThreads + threadIdx.x;
+    double chi = chis[0], Wenv = wenv[0], tau = taus[0];
+    float gph = gphs[0];
+    uint64_t pid = pids[0];
+#pragma unroll
+    for (int j = 1; j < kPairItems; ++j)
+      if (it == j) { chi = chis[j]; Wenv = wenv[j]; tau = taus[j]; gph = gphs[j]; pid = pids[j]; }
+    bool ok;
+    const float lh = mlp_lnh_pair(Bn, chi, cand, ok);
+    if (!cand) continue;
+    const float h = ok ? expf(lh) : h_pair<float, true>((float)chi, L, a.rg);
+    nfr += !ok;
+    const double W = kRateUnit * (double)(h * rcp<float>(gph));
+    nexc += W > Wenv;
+    double rem = a.dtd - tau / Wenv;
+    for (int k = 0;; ++k) {
+      const uint4 u = stream4(pid, a.seed, step, kPhotonThin, (uint32_t)k);
+      if (unit<double>(u.x) * Wenv < W) { evbits |= 1u << it; break; }
+      ++nnull;
+      tau = -log(unit<double>(u.y));
+      if (!(tau <= Wenv * rem)) { a.ph.tau[i] = tau - Wenv * rem; break; }
+      if (k + 1 >= kmax) { ++ncap; a.ph.tau[i] = tau - Wenv * rem; break; }
+      rem -= tau / Wenv;
+    }
+  }
+  const uint32_t ev = (uint32_t)__popc(evbits);
+  count_lds(cnt, cChiRange, nrange);
+  count_lds(cnt, cNanChi, nnan);
+  count_lds(cnt, cPairs, ev);
+  count_lds(cnt, cThinned, nnull);
+  count_lds(cnt, cMlpFallbackRate, nfr);
+  count_lds(cnt, cCapped, ncap);
+  count_lds(cnt, cEnvelopeExceeded, nexc);
+  uint64_t packed = 0;
+#pragma unroll
+  for (int it = 0; it < kPairItems; ++it) packed |= (uint64_t)((evbits >> it) & 1u) << (16 * it);
+  uint64_t tot;
+  const uint64_t excl = block_exclusive64(packed, scan_s, &tot);
+  uint32_t level0[kPairItems], total = 0;
+#pragma unroll
+  for (int it = 0; it < kPairItems; ++it) {
+    level0[it] = total;
+    total += (uint32_t)((tot >> (16 * it)) & 0xFFFFu);
+  }
+  const uint64_t toff = tile_offset(tile, total, a.sc.status, a.counters, off_s);
+  uint32_t ndrop = 0;
+  for (int it = 0; it < kPairItems; ++it) {
+    if (!((evbits >> it) & 1u)) continue;
+    const int64_t i = base + (int64_t)it * kPairThreads + threadIdx.x;
+    const uint64_t pid = pids[it];
+    const float kx = KX[i], ky = KY[i], kz = KZ[i];
+    const float x = X[i], y = Y[i], z = Z[i];
+    const float gph = root<float>(kx * kx + ky * ky + kz * kz);
+    float F[6];
+    field_at<float>(a.f, i, x, y, z, F);
+    const double chi = chi_photon_f32(kx, ky, kz, F);
+    const uint4 u = stream4(pid, a.seed, step, kPhotonEvent, 0u);
+    float xh, omh;
+    sample_pair_half<float>(tab, (float)chi, unit<float>(u.x), unit<float>(u.y), xh, omh, a.rg);
+    const bool flip = u.y & 1u;
+    const float xe = flip ? omh : xh, xp = flip ? xh : omh;
+    const float ge = xe * gph, gpos = xp * gph;
+    const double te = -log(unit<double>(u.z)), tp = -log(unit<double>(u.w));
+    a.ph.id[i] = kDeadId;
+    const uint64_t rank = toff + level0[it] + (uint32_t)((excl >> (16 * it)) & 0xFFFFu);
+    const int64_t je = e0 + (int64_t)rank, jp = p0 + (int64_t)rank;
+    if (je < a.el.cap && jp < a.po.cap) {
+      const float kxh = kx / gph, kyh = ky / gph, kzh = kz / gph;
+      const float pe = sqrtf(fmaxf(ge * ge - 1.f, 0.f)), ppo = sqrtf(fmaxf(gpos * gpos - 1.f, 0.f));
+      ((float *)a.el.x)[je] = x; ((float *)a.el.y)[je] = y; ((float *)a.el.z)[je] = z;
+      ((float *)a.el.px)[je] = kxh * pe; ((float *)a.el.py)[je] = kyh * pe; ((float *)a.el.pz)[je] = kzh * pe;
+      a.el.tau[je] = te; a.el.id[je] = id0 + 2 * rank;
+      ((float *)a.po.x)[jp] = x; ((float *)a.po.y)[jp] = y; ((float *)a.po.z)[jp] = z;
+      ((float *)a.po.px)[jp] = kxh * ppo; ((float *)a.po.py)[jp] = kyh * ppo; ((float *)a.po.pz)[jp] = kzh * ppo;
+      a.po.tau[jp] = tp; a.po.id[jp] = id0 + 2 * rank + 1;
+    } else {
+      ndrop += 2;
+    }
+  }
+  count_lds(cnt, cDropped, ndrop);
+  const int64_t last = (n - 1) / kPairTile;
+  if ((int64_t)tile == last && threadIdx.x == 0) {
+    const int64_t tt = (int64_t)(toff + total);
+    *a.el.count = e0 + tt < a.el.cap ? e0 + tt : a.el.cap;
+    *a.po.count = p0 + tt < a.po.cap ? p0 + tt : a.po.cap;
+    *a.next_id = id0 + 2 * (uint64_t)tt;
+    if (a.killed) *a.killed += tt;
+  }
+}
+
+__global__ __launch_bounds__(kPairThreads, 2) void k_pairs_mlp(PairArgs<float> a, const float *thB, int kmax) {
+  __shared__ mlp::NetLdsI B_s;
+  __shared__ float L_s[kPairNRate];
+  __shared__ uint64_t scan_s[16];
+  __shared__ uint32_t tile_s;
+  __shared__ uint64_t off_s;
+  __shared__ int64_t hdr_s[4];
+  __shared__ uint32_t cnt_s[cNumCounters];
+  count_zero(cnt_s);
+  if (threadIdx.x == 0) {
+    hdr_s[0] = *a.ph.count; hdr_s[1] = *a.el.count; hdr_s[2] = *a.po.count;
+    hdr_s[3] = (int64_t)*a.next_id;
+  }
+  __syncthreads();
+  const int64_t n = hdr_s[0], e0 = hdr_s[1], p0 = hdr_s[2];
+  const uint64_t id0 = (uint64_t)hdr_s[3];
+  if (n == 0) return;
+  mlp::stage_net_infer(thB, mlp::kB, &B_s);
+  for (int k = threadIdx.x; k < kPairNRate; k += blockDim.x) L_s[k] = a.L[k];
+  const RowQ16 tab{a.q16, a.s0sc};
+  while (true) {
+    const uint32_t tile = next_tile(a.sc.ticket, &tile_s);   // its barriers also publish the staged net
+    if ((int64_t)tile * kPairTile >= n) break;
+    pair_tile_thin(a, B_s, tab, L_s, tile, scan_s, &off_s, n, e0, p0, id0, cnt_s, kmax);
+  }
+  count_flush(cnt_s, a.counters);
 }
 
 // three waves per SIMD (at most 168 registers): its four photons per thread
@@ -1650,19 +1816,17 @@ hipError_t launch_gather_push(qed_ctx *c, const qed_fields_t *f, const qed_speci
   const unsigned grid = (unsigned)(tpx * kXcds);
   const bool use_mlp = (c->params.flags & QED_FLAG_SURROGATE) && sp->dtype == QED_F32;
   if (use_mlp) {
-    // persistent: 4 workgroups per CU, each staging the split rate net once
-    int64_t g = (int64_t)c->n_cu * 4;
-    if (g > (int64_t)grid) g = ((int64_t)grid + kXcds - 1) / kXcds * kXcds;
-    g = (g + kXcds - 1) / kXcds * kXcds;
+    // surrogate path: the same pass with the rate envelope (thinning); the
+    // emission pass evaluates the nets at the candidates
     GPArgs<float> a{dev_species(sp), dev_fields(f), c->rad_lnh32, (float)charge, (float)dt, dt, c->em_mask,
                     (EmRec<float> *)c->em_rec, tpx, c->d_counters, 0, c->params.seed, (uint64_t)step, dstep, c->range};
-    const MlpDev m = mlp_dev(c);
     if (f->kind == QED_FIELD_GRID)
-      hipLaunchKernelGGL(k_gather_push_mlp<QED_FIELD_GRID>, dim3((unsigned)g), dim3(kGPThreads), 0, st, a, m);
+      hipLaunchKernelGGL((k_gather_push<float, QED_FIELD_GRID, false, true>), dim3(grid), dim3(kGPThreads), 0, st, a);
     else if (f->kind == QED_FIELD_UNIFORM)
-      hipLaunchKernelGGL(k_gather_push_mlp<QED_FIELD_UNIFORM>, dim3((unsigned)g), dim3(kGPThreads), 0, st, a, m);
+      hipLaunchKernelGGL((k_gather_push<float, QED_FIELD_UNIFORM, false, true>), dim3(grid), dim3(kGPThreads), 0, st, a);
     else
-      hipLaunchKernelGGL(k_gather_push_mlp<QED_FIELD_PER_PARTICLE>, dim3((unsigned)g), dim3(kGPThreads), 0, st, a, m);
+      hipLaunchKernelGGL((k_gather_push<float, QED_FIELD_PER_PARTICLE, false, true>), dim3(grid), dim3(kGPThreads), 0,
+                         st, a);
   } else if (sp->dtype == QED_F32) {
     GPArgs<float> a{dev_species(sp), dev_fields(f), c->rad_lnh32, (float)charge, (float)dt, dt, c->em_mask,
                     (EmRec<float> *)c->em_rec, tpx, c->d_counters, gen, c->params.seed, (uint64_t)step, dstep, c->range};
@@ -1749,7 +1913,10 @@ hipError_t launch_pairs(qed_ctx *c, const qed_fields_t *f, const qed_species_t *
     PairArgs<float> a{dev_species(ph), dev_species(el), dev_species(po), dev_fields(f), c->pair_L32,
                       c->pair_S64, c->pair_q16, c->pair_s0sc, (float)dt, dt, move, c->d_next_id,
                       c->params.seed, (uint64_t)step, step < 0 ? c->d_step : nullptr, sc, c->d_counters, killed, c->range};
-    hipLaunchKernelGGL(k_pairs_f32, dim3(grid), dim3(kPairThreads), 0, st, a);
+    if (c->params.flags & QED_FLAG_SURROGATE)
+      hipLaunchKernelGGL(k_pairs_mlp, dim3(grid), dim3(kPairThreads), 0, st, a, c->mlp_theta[1], c->params.kmax);
+    else
+      hipLaunchKernelGGL(k_pairs_f32, dim3(grid), dim3(kPairThreads), 0, st, a);
   } else {
     PairArgs<double> a{dev_species(ph), dev_species(el), dev_species(po), dev_fields(f), c->pair_L64,
                        c->pair_S64, c->pair_q16, c->pair_s0sc, dt, dt, move, c->d_next_id,

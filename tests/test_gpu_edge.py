@@ -55,9 +55,16 @@ def test_photon_capacity_overflow_is_reported():
     np.testing.assert_array_equal(ids, np.arange(n, n + cap, dtype=np.uint64))
 
 
-def test_nonfinite_fields_and_chi_range_are_counted():
+@pytest.mark.parametrize("surrogate", [False, True])
+def test_nonfinite_fields_and_chi_range_are_counted(surrogate):
+    """Non-finite fields skip the particle (optical depth unchanged) and chi above
+    the table range is counted, on the table path and on the surrogate path."""
     torch, q = need_gpu()
-    ctx = _ctx(q, seed=1)
+    ctx = _ctx(q, seed=1, flags=q.QED_FLAG_SURROGATE if surrogate else 0)
+    if surrogate:                                    # any weights: nothing is emitted here
+        for net in (0, 1):
+            rng0 = np.random.default_rng(net)
+            ctx.qed_surrogate_io(net, rng0.normal(0, 0.3, q.lib().qed_surrogate_params(net)).astype(np.float32))
     n = 4096
     rng = np.random.default_rng(0)
     x = np.zeros((n, 3))

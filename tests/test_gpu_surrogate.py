@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 from oracle import mc, mlp, tables
-from oracle.constants import RATE_UNIT
+from oracle.constants import E_S, RATE_UNIT
 from tests import mlp_bound
 from tests.gpu_helpers import need_gpu
 
@@ -166,9 +166,12 @@ def test_sampler_position_independent(trained):
 
 
 def test_surrogate_gain_vs_table(trained):
-    """What the trained networks change against the plain table sampler on the
-    same 1e8 lookups (rate + xi + pair rate): throughput and LDS footprint are
-    measured and reported; correctness is covered by the tests above."""
+    """What the trained networks gain over the plain table sampler on the same
+    1e8 lookups (rate + xi + pair rate for every sample, qed_sample): the
+    measured throughput ratio surrogate / table is the result.  On this GPU the
+    table (in LDS and the caches) is cheaper than two 3 x 64 networks per sample,
+    so the ratio is well below 1: the test states that outcome (0.02 < ratio < 1)
+    rather than a gain."""
     torch, q = need_gpu()
     ctx = trained
     n = 100_000_000
@@ -190,10 +193,10 @@ def test_surrogate_gain_vs_table(trained):
         torch.cuda.synchronize()
         res[name] = n * 3 / (e0.elapsed_time(e1) * 1e-3)
     st, _ = ctx.qed_get_status(check=False)
+    ratio = res["mlp"] / res["table_f32"]
     print(f"samples/s: table {res['table_f32']:.3e}  surrogate {res['mlp']:.3e}  "
-          f"ratio {res['mlp'] / res['table_f32']:.3f}; xi fallback fraction "
-          f"{st['mlp_fallback_xi'] / (4 * n):.4%}")
-    assert res["mlp"] > 0 and res["table_f32"] > 0
+          f"ratio surrogate/table {ratio:.3f}; xi fallback fraction {st['mlp_fallback_xi'] / (4 * n):.4%}")
+    assert 0.02 < ratio < 1.0
 
 
 def _with_weights(q, trained, **kw):
@@ -243,7 +246,7 @@ def test_surrogate_step_independent_of_order(trained):
     lb, pb, sb = run(rng.permutation(n))
     print(f"order independence: {pa.shape[0]} photons, events {sa['events']}, capped {sa['capped']}, "
           f"fallbacks xi {sa['mlp_fallback_xi']} rate {sa['mlp_fallback_rate']}")
-    assert sa["events"] > 2 * n and sa["capped"] > 0          # several events per electron, some capped
+    assert sa["events"] > 1.5 * n and sa["capped"] > 0        # several events per electron, some capped
     for a, b in zip(la, lb):
         assert np.array_equal(a, b)
     assert np.array_equal(pa, pb)
@@ -252,14 +255,18 @@ def test_surrogate_step_independent_of_order(trained):
 
 
 def test_surrogate_step_spectrum_and_rate(trained):
-    """The emission step with QED_FLAG_SURROGATE (rate net in the lepton pass, xi
-    net in the emission pass): 1e7 photons at chi ~ 1 without recoil; event count
-    against the oracle's rate integral (Poisson z-test) and the accepted xi
+    """The emission step with QED_FLAG_SURROGATE (candidate events at the rate
+    envelope in the lepton pass, kept with the rate net's W / W_env, xi net in
+    the emission pass): 1e6 electrons at chi ~ 1 without recoil for 20 steps of
+    0.05 (~1e7 photons).  Kept events are Poisson with mean n W T (the optical
+    depth with carry makes the step size irrelevant; kmax caps only defer
+    candidates to the next step): their count must match the oracle's rate
+    integral within the surrogate's 1e-3 rate bar plus 4 sigma; the accepted xi
     against the exact truncated CDF (KS <= 2e-3)."""
     torch, q = need_gpu()
     import workloads
     from oracle.constants import E_S
-    n, b0, g = 1_000_000, 2000.0, 206.0
+    n, b0, g, dt, steps = 1_000_000, 2000.0, 206.0, 0.05, 20
     ctx = _with_weights(q, trained, seed=21, kmax=4, flags=q.QED_FLAG_NO_RECOIL | q.QED_FLAG_SURROGATE)
     ens = workloads.uniform_b_ensembles(n, seed=21, triples=((b0, g),))[0]
     lep = q.Species(n, "f32")
@@ -269,20 +276,19 @@ def test_surrogate_step_spectrum_and_rate(trained):
     ctx.qed_set_next_id(n)
     fld = q.Fields(q.QED_FIELD_UNIFORM, B=(0, 0, b0))
     ctx.qed_get_status(check=False)
-    s, dt = 0, 0.05
-    while ph.n() < 10_000_000:
-        ctx.qed_gather_push(fld, lep, -1, dt, s)
-        ctx.qed_emit_photons(lep, ph, s)
-        s += 1
+    for s_ in range(steps):
+        ctx.qed_gather_push(fld, lep, -1, dt, s_)
+        ctx.qed_emit_photons(lep, ph, s_)
     st, rc = ctx.qed_get_status()
     chi = g * math.sqrt(1 - 1 / g ** 2) * b0 / E_S
     row = tables.fine_row("I", chi, tables.RAD_M)
     W = RATE_UNIT * row.total / g
-    # events: the first event of each particle is decided by gather/push, later
-    # ones within a step by the emission pass; over s steps the count is
-    # Poisson with mean n W s dt up to the optical depth left at the end (< n)
-    mean = n * W * s * dt
-    assert abs(st["events"] - mean) < 4 * math.sqrt(mean) + n, (st["events"], mean)
+    mean = n * W * steps * dt
+    rel = st["events"] / mean - 1
+    print(f"surrogate step: events {st['events']} (oracle mean {mean:.0f}, rel {rel:+.2e}), candidates not kept "
+          f"{st['thinned']} ({st['thinned'] / (st['events'] + st['thinned']):.3f}), capped {st['capped']}")
+    assert abs(st["events"] - mean) < 1e-3 * mean + 4 * math.sqrt(mean), (st["events"], mean)
+    assert st["envelope_exceeded"] == 0
     nph = ph.n()
     gam = torch.sqrt(ph.px[:nph].double() ** 2 + ph.py[:nph].double() ** 2 + ph.pz[:nph].double() ** 2)
     xi = np.sort((gam / g).cpu().numpy())
@@ -292,10 +298,50 @@ def test_surrogate_step_spectrum_and_rate(trained):
     Pe = (np.interp(np.log(xi) - np.log1p(-np.minimum(xi, 1 - 1e-7)), row.s, P) - Pc) / (1 - Pc)
     m = xi.size
     ks = max(np.max(np.arange(1, m + 1) / m - Pe), np.max(Pe - np.arange(m) / m))
-    print(f"surrogate step: {s} steps, events {st['events']} (mean {mean:.0f}), photons {m}, KS {ks:.2e}, "
-          f"fallbacks xi {st['mlp_fallback_xi']} rate {st['mlp_fallback_rate']}")
-    assert ks < 2e-3
+    print(f"  photons {m}, KS {ks:.2e}, fallbacks xi {st['mlp_fallback_xi']} rate {st['mlp_fallback_rate']}")
+    assert m > 9_000_000 and ks < 2e-3
     assert st["mlp_fallback_xi"] < 0.01 * st["events"]
+
+
+def test_surrogate_pairs_yield_and_spectrum_1e7(trained, pair_table):
+    """Pair creation with QED_FLAG_SURROGATE (candidates at the envelope
+    h_pair_env, kept with the pair head of the rate net): 1e7 photons at
+    chi_ph = 1, one step with W dt = 1.  The pair yield against 1 - exp(-W dt)
+    with W from the oracle's quadrature, within the surrogate's 1e-3 rate bar
+    plus 4 sigma; the electron energy fraction against the exact Eq. (6) CDF
+    (one-sample KS <= 2e-3)."""
+    torch, q = need_gpu()
+    n, gph, chi = 10_000_000, 1000.0, 1.0
+    ctx = _with_weights(q, trained, seed=31, kmax=4, flags=q.QED_FLAG_STATIC_PHOTONS | q.QED_FLAG_SURROGATE)
+    ph, el, po = q.Species(n, "f32"), q.Species(n, "f32"), q.Species(n, "f32")
+    b = chi * E_S / gph
+    ph.load(np.zeros((n, 3)), np.tile([gph, 0.0, 0.0], (n, 1)), ids=np.arange(n, dtype=np.uint64))
+    ctx.qed_init_optical_depth(ph, 0)
+    ctx.qed_set_next_id(n)
+    fld = q.Fields(q.QED_FIELD_UNIFORM, B=(0, 0, b))
+    row = tables.fine_row("pair", chi, tables.PAIR_M)
+    W = RATE_UNIT * 2 * row.total / gph
+    dt = 1.0 / W
+    ctx.qed_get_status(check=False)
+    ctx.qed_create_pairs(fld, ph, el, po, dt, 0)
+    st, rc = ctx.qed_get_status()
+    m = el.n()
+    pr = 1 - math.exp(-W * dt)
+    sig = math.sqrt(n * pr * (1 - pr))
+    slack = 1e-3 * n * W * dt * math.exp(-W * dt)      # d(yield) for a 1e-3 rate error
+    print(f"surrogate pairs {m} (oracle mean {n * pr:.0f}, z {(m - n * pr) / sig:+.2f}), candidates not kept "
+          f"{st['thinned']}, rate fallbacks {st['mlp_fallback_rate']}")
+    assert abs(m - n * pr) < slack + 4 * sig
+    assert st["envelope_exceeded"] == 0 and st["pairs"] == m
+    ge = torch.sqrt(1 + el.px[:m].double() ** 2 + el.py[:m].double() ** 2 + el.pz[:m].double() ** 2)
+    xi = np.sort((ge / gph).cpu().numpy())
+    P = row.F / row.total
+    s_samp = np.log(xi) - np.log1p(-xi)
+    Ph = np.interp(-np.abs(s_samp), row.s, P)
+    Pe = np.where(s_samp <= 0, 0.5 * Ph, 1 - 0.5 * Ph)
+    ks = max(np.max(np.arange(1, m + 1) / m - Pe), np.max(Pe - np.arange(m) / m))
+    print(f"  KS(exact) {ks:.2e}")
+    assert ks < 2e-3
 
 
 def test_surrogate_step_matches_table_step_standing_wave(trained):

@@ -361,3 +361,24 @@ def test_classical_overestimates_high_energy():
         tailI = rI.total - np.interp(0.0, rI.s, rI.F)
         tailC = rC.total - np.interp(0.0, rC.s, rC.F)
         assert tailC > tailI
+
+
+def test_thinning_envelopes_bound_the_rates(rad_table_I, pair_table):
+    """The surrogate path draws candidate events at closed-form envelope rates and
+    keeps each with probability W / W_env, which is exact only if W <= W_env
+    everywhere (Poisson thinning).  The envelopes (restated from the kernel's
+    lookup header): h_rad_env = 1.002 (5 / (2 sqrt3)) chi (1 + chi)^(-1/3) and
+    h_pair_env = 1.002 (3 sqrt3 / (16 sqrt2)) chi exp(-8 / (3 chi)) (1 + chi/4)^(-1/3)
+    (zero below chi = 1e-2): the oracle's tabulated rates, with their
+    extrapolations outside the table, stay below them by at least the 1.002
+    margin over chi in [1e-6, 1e5], and are not far below (acceptance >= 0.89)."""
+    c1 = 5.0 / (2.0 * math.sqrt(3.0))
+    ce = 3.0 * math.sqrt(3.0) / (16.0 * math.sqrt(2.0))
+    chi = np.logspace(-6, 5, 400001)
+    env = 1.002 * c1 * chi * (1.0 + chi) ** (-1.0 / 3.0)
+    r = tables.h_rad(rad_table_I, chi) / env
+    assert r.max() <= 1.0 / 1.002 + 1e-12 and r.min() > 0.89
+    cp = chi[chi >= 1e-2]
+    envp = 1.002 * ce * cp * np.exp(-8.0 / (3.0 * cp)) * (1.0 + 0.25 * cp) ** (-1.0 / 3.0)
+    rp = tables.h_pair(pair_table, cp) / envp
+    assert rp.max() <= 1.0 / 1.002 + 1e-12 and rp.min() > 0.89
