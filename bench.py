@@ -1,27 +1,34 @@
 """Throughput of the QED Monte Carlo step on one MI355X.
 
-Default workload (the standing-wave electron configuration): 1e7 electrons in a
-128^3 grid holding the circularly polarised standing wave a0 = 500, float32
-state with float64 chi and optical depth, formula II tables, dt = 0.01.  One
-step = refill the grid for t = n dt, gather/push every electron, finish every
-emission event, append the photons (stream-compacted) and compact the photon
-arrays (a no-op on the device while no photon has been removed), plus a stable
-re-sort of the electrons by grid cell every 15 steps.  Inputs are resident
-in HBM before timing; table build and initialisation are outside the timed
-region.
+Headline workload (the cascade configuration): 2e8 electrons in the 128^3 grid
+of the circularly polarised standing wave a0 = 1000, float32 state with float64
+chi and optical depth, formula II tables, dt = 0.01.  One step = refill the grid
+for t = n dt, pair creation for every photon present, gather/push and emission
+for electrons and for positrons (photons appended), photon compaction every 10
+steps; electrons and photons re-sorted by cell every 20 steps (outside the
+captured graphs).  The step runs as captured hipGraphs, 500 steps in all, with
+the photon and positron populations growing in place.  It runs twice: with the
+surrogate networks (QED_FLAG_SURROGATE: rates and photon energies from the nets,
+candidate events by Poisson thinning, table fallback) and with the plain tables.
 
-Prints one JSON line.  `value` = electron-steps per second over the timed
-steps.  `roofline` is for the dominant kernel (the lepton gather/push pass),
-whose duration is measured with HIP events on the stream it runs on.
-`surrogate` repeats the same workload with the trained networks in place of
-the table lookups (QED_FLAG_SURROGATE) and gates it on the two-sample KS
-distance of the photon-energy spectra of the two runs (<= 2e-3).
-`cpu_baseline` times the CPU oracle on a bounded sample of the same workload.
-`other_configs` times the other configurations on the same GPU: the uniform-B
-ensembles in float64 (three Fig. 1 ensembles of 1e5 electrons, 100 steps), pair
-creation for 2e7 photons (100 steps), the standalone sampler (table and
-surrogate) on 1e8 lookups, and the cascade step (pairs, emission, compaction)
-captured in a hipGraph for 2e7 electrons at a0 = 1000 (table and surrogate).
+Prints one JSON line.  `value` = particle-steps per second of the surrogate
+cascade over the timed steps (electrons + positrons + photons present at the
+start of each step), `table` the same for the table path, inputs resident in HBM
+(initial state, table build and training outside the timed region).  The timed
+steps are the last K of the 500 (or of W + K if that is more); the steps before
+them run untimed.  `roofline` is for the kernel that takes most of the surrogate
+step (measured with HIP events around its launch on eagerly run steps spread
+over the timed window, on the stream it runs on).  `oracle_gates` compares both
+paths with the float64 CPU oracle run on the 1e5-electron subsample (ids
+0..99999, the same initial state and random streams) for the same 500 steps:
+two-sample KS of the photon and positron energy spectra, z-test of the pair
+yield.  `ks_1e7` is the metric-grade spectrum gate: 1e7 photons of the
+surrogate emission step at fixed chi ~ 1 against the oracle's exact CDF.
+`cpu_baseline` times that same oracle run on the host's cores.
+`other_configs` times the other configurations on the same GPU: the standing
+wave with 1e7 electrons (table and surrogate, with its own gather/push
+roofline), the uniform-B ensembles in float64, pair creation for 2e7 photons,
+and the standalone sampler (table and surrogate) on 1e8 lookups.
 """
 import argparse
 import json
@@ -42,6 +49,15 @@ E_S_1UM = 510998.95 / 1.239841984
 PROFILE = os.path.join(ROOT, "profiles", "gather_push_standing_wave_1e7.md")
 # sources the gather/push kernel is compiled from (the counters hold while they are unchanged)
 PROFILED_SOURCES = ("step.hip", "qed_device.h", "lookup.h")
+
+# the cascade configuration
+C5_N, C5_STEPS, C5_A0, C5_DT, C5_GRID, C5_SEED = 200_000_000, 500, 1000.0, 0.01, 128, 4
+C5_SUBSAMPLE = 100_000          # ids 0 .. 99999: drawn on the host, shared with the oracle
+C5_SORT_EVERY, C5_COMPACT_EVERY = 20, 10
+# fixed-chi emission run of the 1e7-sample spectrum gate (chi ~ 1: b0 = 2000, gamma = 206)
+KS_N, KS_B0, KS_GAMMA, KS_DT, KS_STEPS = 1_000_000, 2000.0, 206.0, 0.05, 20
+
+
 
 
 def measured_traffic():
@@ -64,104 +80,373 @@ def measured_traffic():
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--n", type=int, default=10_000_000)
-    ap.add_argument("--grid", type=int, default=128)
-    ap.add_argument("--a0", type=float, default=500.0)
-    ap.add_argument("--dt", type=float, default=0.01)
+    ap.add_argument("--steps", type=int, default=480, help="timed steps of the cascade (the last K of its run)")
+    ap.add_argument("--warmup", type=int, default=20, help="untimed steps before them (at least 500 - K run)")
     ap.add_argument("--formula", type=int, default=2)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-surrogate", action="store_true",
-                    help="skip the surrogate-network run of the same workload")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (and its gates)")
+    ap.add_argument("--no-surrogate", action="store_true", help="table path only")
     ap.add_argument("--train-steps", type=int, default=20000)
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="after timing, copy 1 GiB with torch (reference kernel for HBM counters)")
-    ap.add_argument("--presort", type=int, default=1,
-                    help="order the initial electrons by grid cell (outside the timed region)")
-    ap.add_argument("--sort-every", type=int, default=15,
-                    help="re-sort electrons by cell every K steps inside the timed loop (0: never)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-other-configs", action="store_true",
-                    help="skip the uniform-B, pair and sampler configurations")
+    ap.add_argument("--no-other-configs", action="store_true")
+    ap.add_argument("--c5-n", type=int, default=C5_N, help="electrons of the cascade (2e8)")
+    ap.add_argument("--c5-steps", type=int, default=C5_STEPS, help="steps of the cascade run (500)")
     return ap.parse_args()
 
 
-def cpu_baseline(args, budget_s):
-    """The oracle (float64 NumPy) on a sample of the same workload, in a process
-    pool over contiguous particle chunks on the host's cores."""
-    from concurrent.futures import ProcessPoolExecutor
-    cores = len(os.sched_getaffinity(0))
-    n_per = 20000
-    steps = 3
-    t0 = time.perf_counter()
-    with ProcessPoolExecutor(cores) as ex:
-        futs = [ex.submit(_oracle_chunk, k, n_per, steps, args.a0, args.grid, args.dt, args.formula)
-                for k in range(cores)]
-        done = [f.result() for f in futs]
-    wall = time.perf_counter() - t0
-    # each worker also spent time building its tables; count only the step loop
-    steps_done = sum(d[0] for d in done)
-    loop_s = max(d[1] for d in done)
-    return dict(value=steps_done / loop_s, unit="particle-steps/s", cores=cores, kind="oracle",
-                sample=f"{cores} x {n_per} electrons x {steps} steps of the same workload "
-                       f"(tables built once per worker, excluded); wall {wall:.1f} s")
+# ------------------------------------------------------------------ oracle leg
+# The float64 CPU oracle on the host cores: the cascade on the 1e5-electron
+# subsample for the same steps (its photon and positron spectra and pair yield
+# gate the GPU runs; its wall time is the cpu_baseline), and the exact CDF of the
+# fixed-chi spectrum gate.  It runs in a process started before anything touches
+# the GPU, with a fork pool over contiguous id chunks.
+
+_ORACLE = {}
 
 
-_TAB = {}
-
-
-def _oracle_chunk(k, n, steps, a0, ngrid, dt, formula):
-    from oracle import mc, tables
+def _oracle_c5_chunk(job):
+    """One contiguous chunk of the subsample through the oracle's cascade step.
+    Particles the chunk creates take ids from a range of their own (the GPU's ids
+    for them depend on the whole population), so only the initial particles share
+    their random streams with the GPU run; the comparison is statistical."""
+    from oracle import mc
     import workloads
-    if "rad" not in _TAB:
-        # the sampler needs only the rows the sample reaches; the rate uses ln h of
-        # every row, so all rows are built (formula I: identical function, far cheaper)
-        _TAB["rad"] = mc.RadSampler(tables.build_rad_table("I"), "q16")
-    ens = workloads.standing_wave_electrons(n, seed=100 + k)
-    x = ens["x"].astype(np.float32).astype(np.float64)
-    p = ens["p"].astype(np.float32).astype(np.float64)
-    tau = mc.init_tau(ens["id"], seed=1)
+    c, lo, hi, steps = job
+    ens = workloads.standing_wave_electrons(C5_SUBSAMPLE, seed=C5_SEED)
+    f32 = lambda a: np.asarray(a, np.float32).astype(np.float64)
+    ids = ens["id"][lo:hi]
+    e0 = lambda: dict(x=np.zeros((0, 3)), p=np.zeros((0, 3)), tau=np.zeros(0), id=np.zeros(0, np.uint64))
+    st = dict(el=dict(x=f32(ens["x"][lo:hi]), p=f32(ens["p"][lo:hi]), tau=mc.init_tau(ids, seed=C5_SEED), id=ids),
+              po=e0(), ph=e0(), next_id=(1 << 40) * (c + 1))
     L = workloads.BOX_L
     t0 = time.perf_counter()
-    nid = 10**9
+    psteps = 0
     for s in range(steps):
-        Eg, Bg = mc.standing_wave_grid(ngrid, L, a0, s * dt)
-        E, B = mc.gather_tsc(Eg, Bg, L, x)
-        r = mc.lepton_step(x, p, tau, ens["id"], E, B, q=-1.0, dt=dt, step=s, seed=1,
-                           sampler=_TAB["rad"], next_id=nid, L=L)
-        x, p, tau, nid = r["x"], r["p"], r["tau"], r["next_id"]
-    return n * steps, time.perf_counter() - t0
+        psteps += st["el"]["id"].size + st["po"]["id"].size + st["ph"]["id"].size
+        Eg, Bg = mc.standing_wave_grid(C5_GRID, L, C5_A0, s * C5_DT)
+        mc.cascade_step(st, Eg=Eg, Bg=Bg, L=L, dt=C5_DT, step=s, seed=C5_SEED, rad=_ORACLE["rad"],
+                        pair=_ORACLE["pair"], retire=(steps * C5_DT, c5_field_bound()))
+    wall = time.perf_counter() - t0
+    g = lambda p: np.sqrt(np.sum(p * p, axis=1))
+    hist = st["tally"].copy()
+    mc.tally_add(hist, g(st["ph"]["p"]))          # retired + followed photons
+    return dict(photon_hist=hist, retired=int(st["tally"].sum()),
+                positron_gamma=np.sqrt(1.0 + g(st["po"]["p"]) ** 2).astype(np.float32),
+                electrons=int(st["el"]["id"].size), positrons=int(st["po"]["id"].size),
+                photons=int(st["ph"]["id"].size), psteps=psteps, wall=wall)
 
 
-def run_workload(args, q, torch, flags, train_steps=0):
-    """Times the standing-wave step; returns timing, counters and the sorted
-    photon energies (for the spectrum comparison)."""
+def _oracle_driver(conn, steps, cores):
+    os.nice(10)
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    from oracle import mc, tables
+    from oracle.constants import E_S
+    t0 = time.perf_counter()
+    # formula I: the same function as formula II (their identity is pinned),
+    # far cheaper to build by quadrature
+    _ORACLE["rad"] = mc.RadSampler(tables.build_rad_table("I"), "f64")
+    _ORACLE["pair"] = mc.PairSampler(tables.build_pair_table(), "f64")
+    chi = KS_GAMMA * math.sqrt(1 - 1 / KS_GAMMA ** 2) * KS_B0 / E_S
+    row = tables.fine_row("I", chi, tables.RAD_M)
+    t_tab = time.perf_counter() - t0
+    conn.send(dict(chi=chi, s=row.s, P=row.F / row.total))      # the fixed-chi CDF, first
+    bounds = np.linspace(0, C5_SUBSAMPLE, cores + 1).astype(int)
+    jobs = [(c, int(bounds[c]), int(bounds[c + 1]), steps) for c in range(cores)]
+    with ProcessPoolExecutor(cores, mp_context=mp.get_context("fork")) as ex:
+        res = list(ex.map(_oracle_c5_chunk, jobs))
+    out = dict(photon_hist=sum(r["photon_hist"] for r in res), retired=sum(r["retired"] for r in res),
+               positron_gamma=np.sort(np.concatenate([r["positron_gamma"] for r in res])),
+               electrons=sum(r["electrons"] for r in res), positrons=sum(r["positrons"] for r in res),
+               photons=sum(r["photons"] for r in res), psteps=sum(r["psteps"] for r in res),
+               loop_s=max(r["wall"] for r in res), wall_s=time.perf_counter() - t0, table_s=t_tab,
+               cores=cores)
+    conn.send(out)
+    conn.close()
+
+
+def start_oracle(steps):
+    """Starts the oracle leg in its own process (call before the GPU is used),
+    on all host cores but two and at a lower scheduling priority, so that the
+    process driving the GPU is never starved of a core."""
+    import multiprocessing as mp
+    cores = max(1, len(os.sched_getaffinity(0)) - 2)
+    ctx = mp.get_context("fork")
+    rd, wr = ctx.Pipe(duplex=False)
+    p = ctx.Process(target=_oracle_driver, args=(wr, steps, cores))
+    p.start()
+    wr.close()
+    return p, rd
+
+
+def c5_field_bound():
+    """|E| + |B| <= a0 (|cos x| + |sin x|) <= sqrt2 a0 in the standing wave, and the
+    quadratic-spline interpolation (positive weights summing to 1) of node values
+    cannot exceed the largest node value; 1e-5 covers the float32 node rounding."""
+    return math.sqrt(2.0) * C5_A0 * (1.0 + 1e-5)
+
+
+def ks_hist(ha, hb):
+    """Two-sample KS statistic of two histograms on the same bins (the ECDFs at
+    the bin edges; the true statistic differs by at most the largest bin mass)
+    and its 0.1 % critical value."""
+    na, nb = int(ha.sum()), int(hb.sum())
+    ca, cb = np.cumsum(ha) / na, np.cumsum(hb) / nb
+    return (float(np.max(np.abs(ca - cb))), 1.95 * math.sqrt((na + nb) / (na * nb)),
+            float(max((ha / na).max(), (hb / nb).max())))
+
+
+def ks_two_sample_np(a, b):
+    """Two-sample KS statistic of sorted arrays and its 0.1 % critical value."""
+    allv = np.concatenate([a, b])
+    fa = np.searchsorted(a, allv, side="right") / a.size
+    fb = np.searchsorted(b, allv, side="right") / b.size
+    return float(np.max(np.abs(fa - fb))), 1.95 * math.sqrt((a.size + b.size) / (a.size * b.size))
+
+
+def oracle_gates(gpu, orc, n_gpu):
+    """GPU cascade (full population) against the oracle subsample."""
+    out = {}
+    ks, crit, binmass = ks_hist(gpu["photon_hist"], orc["photon_hist"])
+    out["photon_ks"], out["photon_ks_crit_0.1pct"], out["photon_ks_pass"] = ks, crit, ks <= max(crit, 2e-3)
+    out["photon_ks_max_bin_mass"] = binmass
+    out["photons_emitted"] = [int(gpu["photon_hist"].sum()), int(orc["photon_hist"].sum())]
+    if orc["positron_gamma"].size and gpu["positron_gamma"].size:
+        ks, crit = ks_two_sample_np(gpu["positron_gamma"], orc["positron_gamma"])
+        out["positron_ks"], out["positron_ks_crit_0.1pct"], out["positron_ks_pass"] = ks, crit, ks <= crit
+    # pair yield per initial electron: the oracle's count is Poisson, the GPU's
+    # rate (2e8 electrons) is known far better
+    r_gpu = gpu["positrons"] / n_gpu
+    mean = r_gpu * C5_SUBSAMPLE
+    z = (orc["positrons"] - mean) / math.sqrt(max(orc["positrons"], 1))
+    out["pairs_per_electron"] = [r_gpu, orc["positrons"] / C5_SUBSAMPLE]
+    out["pair_yield_z"], out["pair_yield_pass"] = z, abs(z) <= 3.0
+    out["photons_emitted_per_electron"] = [gpu["photon_hist"].sum() / n_gpu, orc["photon_hist"].sum() / C5_SUBSAMPLE]
+    out["photons_followed_per_electron"] = [gpu["photons"] / n_gpu, orc["photons"] / C5_SUBSAMPLE]
+    return out
+
+
+# ------------------------------------------------------------ cascade (headline)
+def run_cascade(q, torch, args, weights, name):
+    """The cascade step (pair creation, both lepton passes with emission, photon
+    compaction every C5_COMPACT_EVERY steps) on the standing wave, captured as
+    hipGraphs and replayed for the whole run; electrons and photons re-sorted by
+    cell every C5_SORT_EVERY steps outside the graphs (into second buffers: the
+    electrons are copied back so that the graphs' pointers stay valid, the photons
+    alternate between two buffers with a graph for each).  Photons converted into
+    pairs stay in place as dead slots (pair creation skips them) until the
+    compaction: a stable compaction moves every photon behind the first hole.
+    The 2e8 electrons: ids 0..99999 from workloads.standing_wave_electrons (the
+    oracle's subsample), the rest drawn on the device with the same distributions
+    (x uniform in the box, p ~ N(0, 10^2) per component; torch's generator, seed
+    4); the initial storage order is by cell (untimed).  Photons that can no
+    longer convert before the end of the run are retired into the tally
+    (qed_set_retirement with F = sqrt2 a0).  Returns the timing, the counts, the
+    photon energy histogram (tally of retired photons plus the photons still
+    followed), the positron energies (a uniform sample of up to 1e7), and the
+    kernel durations sampled on eager steps."""
+    import workloads
+    n, L, ngrid = args.c5_n, workloads.BOX_L, C5_GRID
+    total = max(args.c5_steps, args.warmup + args.steps)
+    timed0 = total - args.steps                  # first timed step
+    flags = q.QED_FLAG_TRACK_DEAD | (q.QED_FLAG_SURROGATE if name == "surrogate" else 0)
+    ctx = q.Context(seed=C5_SEED, kmax=4, flags=flags)
+    ctx.qed_build_tables(args.formula)
+    if name == "surrogate":
+        for k in (0, 1):
+            ctx.qed_surrogate_io(k, weights[k])
+    # photons that can no longer convert before the end are retired into the tally
+    # (qed_set_retirement; without it the run emits ~15 photons per electron);
+    # capacities for the measured growth at a0 = 1000 (pairs ~0.2 per electron)
+    ctx.qed_set_retirement(total * C5_DT, c5_field_bound())
+    cap_e, cap_p = int(1.4 * n) + 1_000_000, int(0.4 * n) + 1_000_000
+    cap_g = min(int(0.012 * n * total) + 10_000_000, (1 << 31) - 1)
+    el, el_b = q.Species(cap_e, "f32"), q.Species(cap_e, "f32")
+    po = q.Species(cap_p, "f32")
+    phs = [q.Species(cap_g, "f32"), q.Species(cap_g, "f32")]
+    cur = [0]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(C5_SEED)
+    for a in (el_b.x, el_b.y, el_b.z):
+        a[:n].uniform_(0.0, L, generator=gen)
+    for a in (el_b.px, el_b.py, el_b.pz):
+        a[:n].normal_(0.0, 10.0, generator=gen)
+    torch.arange(n, out=el_b.id[:n])
+    sub = workloads.standing_wave_electrons(C5_SUBSAMPLE, seed=C5_SEED)
+    for a, col in ((el_b.x, sub["x"][:, 0]), (el_b.y, sub["x"][:, 1]), (el_b.z, sub["x"][:, 2]),
+                   (el_b.px, sub["p"][:, 0]), (el_b.py, sub["p"][:, 1]), (el_b.pz, sub["p"][:, 2])):
+        a[:C5_SUBSAMPLE].copy_(torch.from_numpy(np.ascontiguousarray(col, dtype=np.float32)))
+    del sub
+    el_b.count.fill_(n)
+    grid = torch.empty(ngrid ** 3 * 6, dtype=torch.float32, device="cuda")
+    fld = q.Fields(q.QED_FIELD_GRID, grid=grid, n=ngrid, L=L)
+    ctx.qed_reserve(cap_e)             # emitter slots for the leptons; the photons' scan state on first use
+    ctx.qed_sort_by_cell(fld, el_b, el)
+    ctx.qed_init_optical_depth(el, 0)
+    ctx.qed_set_next_id(n)
+    ctx.qed_set_step(0)
+    stream = torch.cuda.current_stream()
+
+    def one_step(compact, pb, ev=None):
+        ph = phs[pb]
+        ctx.qed_fill_standing_wave_at_step(grid, ngrid, L, C5_A0, 0.0, C5_DT)
+        if ev is not None:
+            ev[0].record(stream)
+        ctx.qed_create_pairs(fld, ph, el, po, C5_DT, q.QED_STEP_DEVICE)
+        if ev is not None:
+            ev[1].record(stream)
+        for sp, qq in ((el, -1), (po, 1)):
+            if ev is not None and sp is el:
+                ev[2].record(stream)
+            ctx.qed_gather_push(fld, sp, qq, C5_DT, q.QED_STEP_DEVICE)
+            if ev is not None and sp is el:
+                ev[3].record(stream)
+            ctx.qed_emit_photons(sp, ph, q.QED_STEP_DEVICE)
+        if compact:
+            ctx.qed_compact(ph)
+        ctx.qed_advance_step()
+
+    def resort():
+        ctx.qed_sort_by_cell(fld, el, el_b)
+        for a, b in ((el.x, el_b.x), (el.y, el_b.y), (el.z, el_b.z), (el.px, el_b.px), (el.py, el_b.py),
+                     (el.pz, el_b.pz), (el.tau, el_b.tau), (el.id, el_b.id), (el.count, el_b.count)):
+            a.copy_(b)
+        ctx.qed_sort_by_cell(fld, phs[cur[0]], phs[1 - cur[0]])
+        cur[0] ^= 1
+
+    one_step(False, 0)                 # step 0 eagerly, then capture
+    resort()                           # allocates the sort's scratch before capture
+    graphs = {}
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    for pb in (0, 1):
+        for compact in (False, True):
+            graphs[compact, pb] = torch.cuda.CUDAGraph()
+            with torch.cuda.stream(side):
+                with torch.cuda.graph(graphs[compact, pb], stream=side):
+                    one_step(compact, pb)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    processed = torch.zeros(1, dtype=torch.int64, device="cuda")
+    samples = []
+
+    def step(k):
+        # step k of the run (k >= 1); step 0 ran eagerly above
+        if k % C5_SORT_EVERY == 0:
+            resort()
+        compact = (k + 1) % C5_COMPACT_EVERY == 0 or k == total - 1
+        if k >= timed0:
+            processed.add_(el.count + po.count + phs[cur[0]].count)
+        if k >= timed0 and (k - timed0) % 40 == 0:
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            cnt = [phs[cur[0]].count.clone(), el.count.clone()]
+            one_step(compact, cur[0], ev)
+            samples.append((ev, cnt))
+        else:
+            graphs[compact, cur[0]].replay()
+
+    for k in range(1, timed0):
+        step(k)
+    torch.cuda.synchronize()
+    st0, rc = ctx.qed_get_status(check=False)
+    processed.zero_()
+    t0 = time.perf_counter()
+    ms = _timed(torch, lambda j: step(timed0 + j), args.steps)
+    wall = time.perf_counter() - t0
+    st, rc = ctx.qed_get_status(check=False)
+    tot = int(processed.item())
+    pair_ms = [a[0].elapsed_time(a[1]) for a, _ in samples]
+    gp_ms = [a[2].elapsed_time(a[3]) for a, _ in samples]
+    pair_n = [int(c[0].item()) for _, c in samples]
+    gp_n = [int(c[1].item()) for _, c in samples]
+    ph = phs[cur[0]]
+    nph = ph.n()                                 # the last step compacted: no dead slots
+    retired = ctx.qed_get_tally()
+    ctx.qed_tally_species(ph)                    # + the photons still followed
+    photon_hist = ctx.qed_get_tally()
+    npo = po.n()
+    g2 = torch.Generator(device="cuda")
+    g2.manual_seed(7)
+    pick = torch.randperm(npo, device="cuda", generator=g2)[:10_000_000]   # positrons are in creation order
+    pg = torch.sqrt(1 + po.px[pick].double() ** 2 + po.py[pick].double() ** 2 + po.pz[pick].double() ** 2)
+    positron_gamma = torch.sort(pg.float()).values.cpu().numpy()
+    del pick, pg
+    out = dict(value=tot / (ms * 1e-3), ms_per_step=ms / args.steps, host_wall_s=wall, electrons=el.n(),
+               positrons=npo, photons=nph, pairs_timed=st["pairs"], dropped=st["dropped"] + st0["dropped"],
+               scan_timeouts=st["scan_timeouts"] + st0["scan_timeouts"], envelope_exceeded=st["envelope_exceeded"],
+               fallback_xi=st["mlp_fallback_xi"], fallback_rate=st["mlp_fallback_rate"], thinned=st["thinned"],
+               retired=int(retired.sum()), photon_hist=photon_hist, positron_gamma=positron_gamma, steps_run=total,
+               timed_from=timed0,
+               pair_pass_ms=pair_ms, pair_pass_photons=pair_n, lepton_pass_ms=gp_ms, lepton_pass_electrons=gp_n,
+               capacity_photons=cap_g)
+    del graphs, el, el_b, po, phs, grid, ph, processed
+    ctx.close()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_fixed_chi_ks(q, torch, weights, row):
+    """The metric-grade spectrum gate: the surrogate emission step (candidates at
+    the rate envelope, rate and xi nets) on 1e6 electrons at chi ~ 1 (b0 = 2000,
+    gamma = 206, no recoil) for 20 steps of 0.05, ~1e7 photons; the accepted xi
+    against the oracle's exact truncated CDF (one-sample KS)."""
+    import workloads
+    ctx = q.Context(seed=21, kmax=4, flags=q.QED_FLAG_NO_RECOIL | q.QED_FLAG_SURROGATE)
+    ctx.qed_build_tables(q.QED_FORMULA_I)
+    for k in (0, 1):
+        ctx.qed_surrogate_io(k, weights[k])
+    ens = workloads.uniform_b_ensembles(KS_N, seed=21, triples=((KS_B0, KS_GAMMA),))[0]
+    lep, ph = q.Species(KS_N, "f32"), q.Species(12_000_000, "f32")
+    lep.load(ens["x"], ens["p"], ids=ens["id"])
+    ctx.qed_init_optical_depth(lep, 0)
+    ctx.qed_set_next_id(KS_N)
+    fld = q.Fields(q.QED_FIELD_UNIFORM, B=(0, 0, KS_B0))
+    ctx.qed_get_status(check=False)
+    for s in range(KS_STEPS):
+        ctx.qed_gather_push(fld, lep, -1, KS_DT, s)
+        ctx.qed_emit_photons(lep, ph, s)
+    st, _ = ctx.qed_get_status(check=False)
+    m = ph.n()
+    gam = torch.sqrt(ph.px[:m].double() ** 2 + ph.py[:m].double() ** 2 + ph.pz[:m].double() ** 2)
+    xi = np.sort((gam / KS_GAMMA).cpu().numpy())
+    del gam, lep, ph
+    ctx.close()
+    xc = 2.0 / KS_GAMMA
+    Pc = float(np.interp(math.log(xc) - math.log1p(-xc), row["s"], row["P"]))
+    Pe = (np.interp(np.log(xi) - np.log1p(-np.minimum(xi, 1 - 1e-7)), row["s"], row["P"]) - Pc) / (1 - Pc)
+    ks = max(np.max(np.arange(1, m + 1) / m - Pe), np.max(Pe - np.arange(m) / m))
+    return dict(workload=f"surrogate emission step, {KS_N} electrons at chi = {row['chi']:.4f} (b0 = {KS_B0:g}, "
+                         f"gamma = {KS_GAMMA:g}), no recoil, {KS_STEPS} steps of {KS_DT}",
+                samples=int(m), ks_vs_oracle_exact_cdf=float(ks), gate=2e-3, pass_=bool(ks <= 2e-3),
+                fallback_xi=st["mlp_fallback_xi"], events=st["events"])
+
+
+def run_workload(args, q, torch, flags, weights=None, n=10_000_000, ngrid=128, a0=500.0, steps=200, warmup=10,
+                 sort_every=15):
+    """The standing-wave configuration: 1e7 electrons, a0 = 500, float32 state,
+    one lepton pass + emission per step, photons appended and compacted,
+    electrons re-sorted by cell every `sort_every` steps.  Returns timing,
+    counters and the sorted photon energies."""
     import workloads
     dev = "cuda"
-    n, ngrid, L = args.n, args.grid, workloads.BOX_L
+    L = workloads.BOX_L
     ctx = q.Context(seed=1, kmax=4, flags=q.QED_FLAG_TRACK_DEAD | flags)
     ctx.qed_build_tables(args.formula)
-    train_s = None
-    if train_steps:
-        t0 = time.perf_counter()
-        ctx.qed_surrogate_train(train_steps, batch=4096, lr=3e-3, seed=11)
-        torch.cuda.synchronize()
-        train_s = time.perf_counter() - t0
+    if weights is not None:
+        for k in (0, 1):
+            ctx.qed_surrogate_io(k, weights[k])
     ens = workloads.standing_wave_electrons(n, seed=1)
-    if args.presort:
-        # initial storage order by grid cell (input layout, not timed)
-        cell = np.floor(ens["x"] / (L / ngrid) + 0.5).astype(np.int64) % ngrid
-        order = np.argsort((cell[:, 2] * ngrid + cell[:, 1]) * ngrid + cell[:, 0], kind="stable")
-        ens = {k: v[order] for k, v in ens.items()}
+    # initial storage order by grid cell (input layout, not timed)
+    cell = np.floor(ens["x"] / (L / ngrid) + 0.5).astype(np.int64) % ngrid
+    order = np.argsort((cell[:, 2] * ngrid + cell[:, 1]) * ngrid + cell[:, 0], kind="stable")
+    ens = {k: v[order] for k, v in ens.items()}
     lep = q.Species(n, "f32")
     lep.load(ens["x"], ens["p"], ids=ens["id"])
-    lep_b = q.Species(n, "f32") if args.sort_every > 0 else None
+    lep_b = q.Species(n, "f32") if sort_every > 0 else None
     cur = [lep, lep_b]
     del ens
     ctx.qed_init_optical_depth(lep, 0)
     ctx.qed_set_next_id(n)
-    ph_cap = int(n * 0.12 * (args.steps + args.warmup)) + 1_000_000
+    ph_cap = int(n * 0.12 * (steps + warmup)) + 1_000_000
     ph = q.Species(ph_cap, "f32")
     ctx.qed_reserve(max(n, ph_cap))
     grid = torch.empty(ngrid ** 3 * 6, dtype=torch.float32, device=dev)
@@ -169,35 +454,35 @@ def run_workload(args, q, torch, flags, train_steps=0):
     stream = torch.cuda.current_stream()
 
     def step(s, ev=None):
-        if args.sort_every > 0 and s % args.sort_every == 0:
+        if sort_every > 0 and s % sort_every == 0:
             ctx.qed_sort_by_cell(fld, cur[0], cur[1])
             cur.reverse()
         lp = cur[0]
-        ctx.qed_fill_standing_wave(grid, ngrid, L, args.a0, s * args.dt)
+        ctx.qed_fill_standing_wave(grid, ngrid, L, a0, s * 0.01)
         if ev is not None:
             ev[0].record(stream)
-        ctx.qed_gather_push(fld, lp, -1, args.dt, s)
+        ctx.qed_gather_push(fld, lp, -1, 0.01, s)
         if ev is not None:
             ev[1].record(stream)
         ctx.qed_emit_photons(lp, ph, s)
         ctx.qed_compact(ph)
 
-    for s in range(args.warmup):
+    for s in range(warmup):
         step(s)
     torch.cuda.synchronize()
     ctx.qed_get_status()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
+           for _ in range(steps)]
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t_start.record(stream)
-    for k in range(args.steps):
-        step(args.warmup + k, evs[k])
+    for k in range(steps):
+        step(warmup + k, evs[k])
     t_end.record(stream)
     torch.cuda.synchronize()
     total_ms = t_start.elapsed_time(t_end)
-    gp_ms = sum(a.elapsed_time(b) for a, b in evs) / args.steps
+    gp_ms = sum(a.elapsed_time(b) for a, b in evs) / steps
     st, rc = ctx.qed_get_status(check=False)
     if rc != 0:
         print(f"bench.py: status {rc}: {st}", file=sys.stderr)
@@ -205,8 +490,7 @@ def run_workload(args, q, torch, flags, train_steps=0):
     m = ph.n()
     gam = torch.sqrt(ph.px[:m] ** 2 + ph.py[:m] ** 2 + ph.pz[:m] ** 2)
     gam = torch.sort(gam).values
-    weights = [ctx.qed_surrogate_io(k) for k in (0, 1)] if train_steps else None
-    out = dict(total_ms=total_ms, gp_ms=gp_ms, st=st, photons=m, gamma=gam, train_s=train_s, weights=weights)
+    out = dict(total_ms=total_ms, gp_ms=gp_ms, st=st, photons=m, gamma=gam)
     del ph, lep, lep_b, cur, grid
     ctx.close()
     return out
@@ -351,123 +635,6 @@ def run_sampler(q, torch, weights, n=100_000_000, reps=5):
     return out
 
 
-def run_cascade(q, torch, weights, n=200_000_000, steps=100, dt=0.01, a0=1000.0, ngrid=128, sort_every=20,
-                compact_every=10):
-    """The cascade step (pair creation, both lepton passes with emission, photon
-    compaction) on the standing wave at a0 = 1000, captured once as a hipGraph
-    and replayed; electrons re-sorted by cell every `sort_every` steps outside the
-    graph (sorted into a second buffer and copied back, so that the graph's
-    pointers stay valid).  Table path, and surrogate path when weights are given.
-    The 2e8 electrons are drawn on the device (torch's generator, seed 4) with
-    the distributions of workloads.standing_wave_electrons: x uniform in the box,
-    p ~ N(0, 10^2) per component, ids 0..n-1; the initial storage order is by
-    cell (qed_sort_by_cell, untimed).  Photons converted into pairs stay in place
-    as dead slots (pair creation skips them) until the compaction, which runs
-    every `compact_every` steps: a stable compaction moves every photon behind
-    the first hole, so removing a few hundred converted photons each step would
-    move the whole population each step.  The photons are re-sorted by cell as
-    well, right after a compaction, into a second photon buffer (graphs are
-    captured for both buffers), which keeps their field gathers in pair creation
-    local."""
-    import workloads
-    L = workloads.BOX_L
-    res = {}
-    for name in ("table", "surrogate"):
-        if name == "surrogate" and weights is None:
-            continue
-        flags = q.QED_FLAG_TRACK_DEAD | (q.QED_FLAG_SURROGATE if name == "surrogate" else 0)
-        ctx = q.Context(seed=4, kmax=4, flags=flags)
-        ctx.qed_build_tables(q.QED_FORMULA_II)
-        if name == "surrogate":
-            for k in (0, 1):
-                ctx.qed_surrogate_io(k, weights[k])
-        cap_e, cap_p, cap_g = int(1.25 * n), n // 4, 3 * n
-        el, el_b = q.Species(cap_e, "f32"), q.Species(cap_e, "f32")
-        po = q.Species(cap_p, "f32")
-        phs = [q.Species(cap_g, "f32"), q.Species(cap_g, "f32")]
-        cur = [0]                       # photon buffer in use
-        gen = torch.Generator(device="cuda")
-        gen.manual_seed(4)
-        for a in (el_b.x, el_b.y, el_b.z):
-            a[:n].uniform_(0.0, L, generator=gen)
-        for a in (el_b.px, el_b.py, el_b.pz):
-            a[:n].normal_(0.0, 10.0, generator=gen)
-        torch.arange(n, out=el_b.id[:n])
-        el_b.count.fill_(n)
-        grid = torch.empty(ngrid ** 3 * 6, dtype=torch.float32, device="cuda")
-        fld = q.Fields(q.QED_FIELD_GRID, grid=grid, n=ngrid, L=L)
-        ctx.qed_reserve(cap_e)          # scan state and emitter slots; photons add scan state on first use
-        ctx.qed_sort_by_cell(fld, el_b, el)
-        ctx.qed_init_optical_depth(el, 0)
-        ctx.qed_set_next_id(n)
-        ctx.qed_set_step(0)
-
-        def one_step(compact=True, pb=0):
-            ph = phs[pb]
-            ctx.qed_fill_standing_wave_at_step(grid, ngrid, L, a0, 0.0, dt)
-            ctx.qed_create_pairs(fld, ph, el, po, dt, q.QED_STEP_DEVICE)
-            for sp, qq in ((el, -1), (po, 1)):
-                ctx.qed_gather_push(fld, sp, qq, dt, q.QED_STEP_DEVICE)
-                ctx.qed_emit_photons(sp, ph, q.QED_STEP_DEVICE)
-            if compact:
-                ctx.qed_compact(ph)
-            ctx.qed_advance_step()
-
-        def resort():
-            ctx.qed_sort_by_cell(fld, el, el_b)
-            for a, b in ((el.x, el_b.x), (el.y, el_b.y), (el.z, el_b.z), (el.px, el_b.px), (el.py, el_b.py),
-                         (el.pz, el_b.pz), (el.tau, el_b.tau), (el.id, el_b.id), (el.count, el_b.count)):
-                a.copy_(b)
-            ctx.qed_sort_by_cell(fld, phs[cur[0]], phs[1 - cur[0]])
-            cur[0] ^= 1
-
-        one_step()                      # first step eagerly (state advances), then capture
-        resort()                        # allocates the sort's scratch outside the timed loop
-        graphs = {}
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        for pb in (0, 1):               # each photon buffer, the step without and with compaction
-            for compact in (False, True):
-                graphs[compact, pb] = torch.cuda.CUDAGraph()
-                with torch.cuda.stream(side):
-                    with torch.cuda.graph(graphs[compact, pb], stream=side):
-                        one_step(compact, pb)
-        torch.cuda.current_stream().wait_stream(side)
-        for g in graphs.values():       # the first replays upload the graphs; not timed
-            g.replay()
-        torch.cuda.synchronize()
-        ctx.qed_get_status()
-        processed = torch.zeros(1, dtype=torch.int64, device="cuda")
-
-        def step(k):
-            if k % sort_every == 0:     # right after a compaction (sort_every is a multiple of it)
-                resort()
-            processed.add_(el.count + po.count + phs[cur[0]].count)
-            graphs[(k + 1) % compact_every == 0, cur[0]].replay()
-
-        for k in range(1, sort_every + 1):   # untimed warm-up through one re-sort
-            step(k)
-        torch.cuda.synchronize()
-        ctx.qed_get_status(check=False)
-        processed.zero_()
-        ms = _timed(torch, lambda k: step(k + 1), steps)   # same schedule as the warm-up
-        st, rc = ctx.qed_get_status(check=False)
-        tot = int(processed.item())
-        res[name] = dict(value=tot / (ms * 1e-3), ms_per_step=ms / steps, electrons=el.n(), positrons=po.n(),
-                         photons=phs[cur[0]].n(), pairs=st["pairs"], dropped=st["dropped"],
-                         scan_timeouts=st["scan_timeouts"])
-        del graphs, el, el_b, po, phs, grid
-        ctx.close()
-        torch.cuda.empty_cache()
-    res["workload"] = (f"cascade step on the standing wave a0={a0:g}, {n} electrons at start, {ngrid}^3 grid, "
-                       f"formula II, pairs + both lepton passes (+ photon compaction every {compact_every} steps) "
-                       f"captured as hipGraphs, {steps} replays, electrons and photons re-sorted every {sort_every} steps")
-    res["unit"] = "particle-steps/s (electrons + positrons + photons present at the start of each step)"
-    if "surrogate" in res:
-        res["ratio_surrogate_vs_table"] = res["surrogate"]["value"] / res["table"]["value"]
-    return res
-
-
 def ks_two_sample(a, b):
     """Two-sample Kolmogorov-Smirnov statistic of sorted device tensors."""
     import torch
@@ -477,72 +644,134 @@ def ks_two_sample(a, b):
     return float(torch.max(torch.abs(fa - fb)))
 
 
+def run_other_configs(q, torch, args, weights):
+    """The other configurations on the same GPU."""
+    out = {}
+    n, ngrid = 10_000_000, 128
+    tab = run_workload(args, q, torch, 0)
+    grid_bytes = ngrid ** 3 * 6 * 4
+    algo = n * 64 + grid_bytes          # read x, p (24 B) and tau (8 B), write them back, + one grid read
+    achieved = algo / (tab["gp_ms"] * 1e-3) / 1e9
+    copy_gbs = stream_copy_gbs(torch)
+    c2 = {"workload": f"standing wave a0=500, {n} electrons, {ngrid}^3 grid, formula "
+                      f"{'II' if args.formula == 2 else 'I'} tables, 200 timed steps after 10, electrons re-sorted "
+                      f"by cell every 15 steps",
+          "unit": "particle-steps/s", "table": n * 200 / (tab["total_ms"] * 1e-3), "table_ms_per_step": tab["total_ms"] / 200,
+          "roofline_gather_push": {"bound": "hbm", "kernel": "k_gather_push<float>", "achieved": achieved,
+                                   "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                                   "traffic": measured_traffic(), "algorithmic_bytes_per_launch": algo,
+                                   "avg_launch_ms": tab["gp_ms"], "stream_copy_GBs": copy_gbs,
+                                   "frac_of_copy": achieved / copy_gbs},
+          "events": tab["st"]}
+    if weights is not None:
+        sur = run_workload(args, q, torch, q.QED_FLAG_SURROGATE, weights)
+        ks = ks_two_sample(tab["gamma"], sur["gamma"])
+        c2.update(surrogate=n * 200 / (sur["total_ms"] * 1e-3), surrogate_ms_per_step=sur["total_ms"] / 200,
+                  surrogate_gather_push_ms=sur["gp_ms"], ratio_surrogate_vs_table=tab["total_ms"] / sur["total_ms"],
+                  ks_photon_energy_surrogate_vs_table=ks, photons=[tab["photons"], sur["photons"]],
+                  fallback_xi=sur["st"]["mlp_fallback_xi"], fallback_rate=sur["st"]["mlp_fallback_rate"],
+                  thinned=sur["st"]["thinned"])
+        del sur
+    del tab
+    out["standing_wave_1e7"] = c2
+    out["uniform_b_f64"] = run_uniform_b(q, torch)
+    out["pairs"] = run_pairs(q, torch)
+    out["sampler"] = run_sampler(q, torch, weights)
+    return out
+
+
+# ------------------------------------------------------------------------ main
+def train_surrogate(q, torch, args):
+    ctx = q.Context(seed=11)
+    ctx.qed_build_tables(args.formula)
+    t0 = time.perf_counter()
+    ctx.qed_surrogate_train(args.train_steps, batch=4096, lr=3e-3, seed=11)
+    torch.cuda.synchronize()
+    w = [ctx.qed_surrogate_io(k) for k in (0, 1)]
+    ctx.close()
+    return w, time.perf_counter() - t0
+
+
+def kernel_roofline(res, grid_bytes):
+    """Roofline of the kernel taking most of the step, from the launches timed
+    with HIP events on eagerly run steps of the timed window: algorithmic bytes
+    per launch (pair pass: 60 B per photon slot + the grid; lepton pass: 64 B
+    per electron + the grid) over the mean launch duration."""
+    cand = []
+    if res["pair_pass_ms"]:
+        b = np.mean([60.0 * k + grid_bytes for k in res["pair_pass_photons"]])
+        cand.append(("photon pass (qed_create_pairs)", b, float(np.mean(res["pair_pass_ms"]))))
+    if res["lepton_pass_ms"]:
+        b = np.mean([64.0 * k + grid_bytes for k in res["lepton_pass_electrons"]])
+        cand.append(("electron gather/push (qed_gather_push)", b, float(np.mean(res["lepton_pass_ms"]))))
+    name, b, ms = max(cand, key=lambda c: c[2])
+    ach = b / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": name, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_launch": b,
+            "avg_launch_ms": ms, "launches_timed": len(res["pair_pass_ms"]),
+            "other_kernels": {c[0]: {"avg_launch_ms": c[2], "algorithmic_bytes_per_launch": c[1],
+                                     "achieved": c[1] / (c[2] * 1e-3) / 1e9} for c in cand if c[0] != name}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
+    total = max(args.c5_steps, args.warmup + args.steps)
+    oracle = None
+    if not args.no_cpu_baseline:
+        oracle = start_oracle(total)            # before anything touches the GPU
     import torch
     import paper_1608_06356_amd as q
 
-    n, ngrid = args.n, args.grid
-    tab = run_workload(args, q, torch, 0)
-    total_ms, gp_ms, st = tab["total_ms"], tab["gp_ms"], tab["st"]
-    ms_per_step = total_ms / args.steps
-    value = n * args.steps / (total_ms * 1e-3)
-    # algorithmic bytes of one gather/push launch: read x,y,z,px,py,pz (24 B) and
-    # tau (8 B), write them back (32 B) per electron, plus one read of the grid
-    grid_bytes = ngrid ** 3 * 6 * 4
-    per_particle = 64
-    algo = n * per_particle + grid_bytes
-    achieved = algo / (gp_ms * 1e-3) / 1e9
-    copy_gbs = stream_copy_gbs(torch)
+    weights, train_s = (None, None) if args.no_surrogate else train_surrogate(q, torch, args)
+    res = {"table": run_cascade(q, torch, args, None, "table")}
+    if weights is not None:
+        res["surrogate"] = run_cascade(q, torch, args, weights, "surrogate")
+    head_name = "surrogate" if "surrogate" in res else "table"
+    head = res[head_name]
+    grid_bytes = C5_GRID ** 3 * 6 * 4
     out = {
         "metric": "QED MC particle-steps/s, surrogate vs table, at KS<=2e-3 spectrum error",
-        "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32 (chi, tau f64)", "data": "synthetic",
-        "config": {"workload": f"standing wave a0={args.a0:g}, {n} electrons, {ngrid}^3 grid, "
-                               f"formula {'II' if args.formula == 2 else 'I'} tables, table sampler, "
-                               f"cell sort every {args.sort_every} steps",
-                   "global_batch": n, "dt": args.dt, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": "k_gather_push<float>", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(), "algorithmic_bytes_per_launch": algo,
-                     "avg_launch_ms": gp_ms, "stream_copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
-        "events": st,
-        "photons": tab["photons"],
+        "value": head["value"], "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 state; f64 chi and optical depth; bf16 matrix cores (split hi/lo) for the nets",
+        "data": "synthetic",
+        "config": {"workload": f"cascade step, {head_name} path: standing wave a0={C5_A0:g}, {args.c5_n} electrons "
+                               f"at start, {C5_GRID}^3 grid, formula {'II' if args.formula == 2 else 'I'} tables, "
+                               f"{total} steps of dt={C5_DT} as hipGraphs (the last {args.steps} timed), photon "
+                               f"compaction every {C5_COMPACT_EVERY} steps, electrons and photons re-sorted every "
+                               f"{C5_SORT_EVERY}",
+                   "global_batch": args.c5_n, "dt": C5_DT, "steps_run": total, "parallelism": "single GPU"},
+        "path": head_name,
+        "roofline": kernel_roofline(head, grid_bytes),
     }
-    if not args.no_surrogate:
-        sur = run_workload(args, q, torch, q.QED_FLAG_SURROGATE, train_steps=args.train_steps)
-        ks = ks_two_sample(tab["gamma"], sur["gamma"])
-        out["surrogate"] = {
-            "value": n * args.steps / (sur["total_ms"] * 1e-3), "ms_per_step": sur["total_ms"] / args.steps,
-            "gather_push_ms": sur["gp_ms"], "photons": sur["photons"],
-            "ks_photon_energy_vs_table": ks, "ks_gate": 2e-3, "ks_pass": ks <= 2e-3,
-            "fallback_xi": sur["st"]["mlp_fallback_xi"], "fallback_rate": sur["st"]["mlp_fallback_rate"],
-            "events": sur["st"]["events"], "train_s": sur["train_s"],
-            "ratio_vs_table": (sur["total_ms"] and total_ms / sur["total_ms"]),
-        }
-        weights = sur["weights"]
-        del sur
-    else:
-        weights = None
-    del tab
+    for name, r in res.items():
+        out[name] = {k: v for k, v in r.items() if k not in ("photon_hist", "positron_gamma")}
+    if "surrogate" in res:
+        out["ratio_surrogate_vs_table"] = res["surrogate"]["value"] / res["table"]["value"]
+        out["surrogate"]["train_s"] = train_s
+    row = None
+    if oracle is not None:
+        row = oracle[1].recv()                 # the fixed-chi CDF (sent once the tables are built)
+    if weights is not None and row is not None:
+        out["ks_1e7"] = run_fixed_chi_ks(q, torch, weights, row)
     if not args.no_other_configs:
-        out["other_configs"] = {"uniform_b_f64": run_uniform_b(q, torch), "pairs": run_pairs(q, torch),
-                                "sampler": run_sampler(q, torch, weights),
-                                "cascade_graph": run_cascade(q, torch, weights)}
-    if args.calibrate_copy:
-        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        src.fill_(1.0)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args, args.cpu_seconds)
+        out["other_configs"] = run_other_configs(q, torch, args, weights)
+    if oracle is not None:
+        orc = oracle[1].recv()
+        oracle[0].join()
+        out["oracle_gates"] = {name: oracle_gates(r, orc, args.c5_n) for name, r in res.items()}
+        out["oracle_gates"]["oracle_counts"] = {k: orc[k] for k in ("electrons", "positrons", "photons", "retired")}
+        out["cpu_baseline"] = {
+            "value": orc["psteps"] / orc["loop_s"], "unit": "particle-steps/s", "cores": orc["cores"],
+            "kind": "oracle",
+            "sample": f"the same cascade on the {C5_SUBSAMPLE}-electron subsample (ids 0..{C5_SUBSAMPLE - 1}), "
+                      f"{total} steps, float64 NumPy, formula I tables (the same function as formula II), "
+                      f"{orc['cores']} processes over contiguous id chunks; loop {orc['loop_s']:.1f} s, tables "
+                      f"{orc['table_s']:.1f} s (excluded), wall {orc['wall_s']:.1f} s"}
     print(json.dumps(out))
 
 

@@ -148,6 +148,7 @@ typedef struct {
   int64_t mlp_fallback_rate;   /* surrogate rates that fell back to the table     */
   int64_t thinned;             /* surrogate path: candidate events not kept (thinning) */
   int64_t envelope_exceeded;   /* surrogate path: a rate above its envelope (must be 0) */
+  int64_t retired;             /* photons retired into the tally (qed_set_retirement) */
 } qed_counters_t;
 
 /* Surrogate training (not part of the paper; see qed_surrogate_train). */
@@ -283,6 +284,29 @@ QED_API int qed_compact(qed_ctx_t ctx, qed_species_t *sp, void *stream);
    streams, other contexts, other threads) race and must be ordered by the
    caller. */
 QED_API int qed_compact_static(qed_ctx_t ctx, qed_species_t *sp, void *stream);
+
+/* Photon retirement, for runs whose photon population outgrows memory.  Pair
+   creation can only take a photon's optical depth tau to zero at the pair rate
+   W = alpha E_S h_pair(chi_ph) / gamma_ph (Eq. 6), and chi_ph = gamma_ph / E_S
+   |k x (E + k x B)| <= gamma_ph F / E_S if F bounds |E| + |B| for the rest of the
+   run.  With the caller's end time t_end (t = step dt) and bound F, a photon whose
+   tau exceeds W_max (t_end - t), W_max the pair-rate envelope at that chi bound,
+   cannot convert before t_end: qed_emit_photons does not store such a new photon
+   and qed_create_pairs marks such a photon dead (QED_DEAD_ID, removed by
+   qed_compact); either way its gamma_ph is counted into the tally, a histogram of
+   QED_TALLY_BINS bins uniform in ln gamma_ph over [ln 2, ln 1e7]
+   (bin = floor((ln gamma - ln 2) / ((ln 1e7 - ln 2) / QED_TALLY_BINS)), clamped).
+   Ids still count every emitted photon, so the stored photons keep the ids and
+   random streams they would have without retirement, and no pair changes.
+   t_end = 0 switches retirement off.  The first call allocates the tally (not
+   under graph capture).  qed_tally_species adds the live photons of a species
+   (id != QED_DEAD_ID, gamma_ph = |k|) to the tally; qed_get_tally synchronises
+   `stream`, copies the QED_TALLY_BINS counts to host memory and clears them if
+   `clear`.  Both need the tally (QED_ERR_STATE before qed_set_retirement). */
+#define QED_TALLY_BINS 65536
+QED_API int qed_set_retirement(qed_ctx_t ctx, double t_end, double field_bound);
+QED_API int qed_tally_species(qed_ctx_t ctx, const qed_species_t *photons, void *stream);
+QED_API int qed_get_tally(qed_ctx_t ctx, uint64_t *host_counts, int64_t nbins, int clear, void *stream);
 
 /* Quantum parameter of every particle [0, *count) of a species at its current
    momentum and the fields at its position (uniform, grid or per-particle, as in

@@ -48,7 +48,7 @@ import math
 import numpy as np
 
 from . import philox, spectra, tables
-from .constants import PAIR_GAMMA_MIN, PHOTON_XI_MIN_GAMMA
+from .constants import E_S, PAIR_GAMMA_MIN, PHOTON_XI_MIN_GAMMA, RATE_UNIT
 
 DEAD_ID = np.uint64(0xFFFFFFFFFFFFFFFF)
 KMAX = 4
@@ -382,16 +382,61 @@ def compact(ids, *arrays):
     return outs
 
 
+# --------------------------------------------------------------- retirement
+# A photon can only convert while its optical depth tau is consumed at the pair
+# rate W = RATE_UNIT h_pair(chi_ph) / gamma_ph (Eq. 6 and the generator after
+# Eq. 7), and chi_ph = gamma_ph / E_S |k x (E + k x B)| <= gamma_ph F / E_S when F
+# bounds |E| + |B| (Eq. 3).  With an envelope h_env >= h_pair that grows with chi,
+# W_max = RATE_UNIT h_env(gamma_ph F / E_S) / gamma_ph bounds W, and a photon with
+# tau >= W_max (t_end - t) cannot convert before t_end: it is retired, i.e.
+# counted into a histogram of ln gamma_ph (the tally) and no longer followed.
+# Envelope: h_env = 1.002 C chi exp(-8 / (3 chi)) (1 + chi / 4)^(-1/3) with
+# Erber's C = 3 sqrt3 / (16 sqrt2), 0 below chi = 1e-2 (where the pair rate is
+# taken as 0); it lies above the tabulated rate (pinned in test_oracle_pins).
+TALLY_BINS = 65536
+TALLY_LN_LO, TALLY_LN_HI = math.log(2.0), math.log(1e7)
+ERBER_C = 3.0 * math.sqrt(3.0) / (16.0 * math.sqrt(2.0))
+
+
+def h_pair_envelope(chi):
+    chi = np.asarray(chi, dtype=np.float64)
+    out = np.zeros_like(chi)
+    ok = chi >= tables.PAIR_CHI_MIN
+    c = chi[ok]
+    out[ok] = 1.002 * ERBER_C * c * np.exp(-8.0 / (3.0 * c)) * (1.0 + 0.25 * c) ** (-1.0 / 3.0)
+    return out
+
+
+def pair_rate_max(gamma_ph, field_bound):
+    g = np.asarray(gamma_ph, dtype=np.float64)
+    w = RATE_UNIT * h_pair_envelope(g * field_bound / E_S) / np.where(g > 0, g, 1.0)
+    return np.where(g >= PAIR_GAMMA_MIN, w, 0.0)
+
+
+def retirable(tau, gamma_ph, field_bound, t_left):
+    return np.asarray(tau) >= pair_rate_max(gamma_ph, field_bound) * t_left
+
+
+def tally_add(counts, gamma_ph):
+    """bin = floor((ln gamma - ln 2) / ((ln 1e7 - ln 2) / TALLY_BINS)), clamped."""
+    b = np.floor((np.log(np.asarray(gamma_ph, dtype=np.float64)) - TALLY_LN_LO)
+                 * (TALLY_BINS / (TALLY_LN_HI - TALLY_LN_LO)))
+    np.add.at(counts, np.clip(b, 0, TALLY_BINS - 1).astype(np.int64), 1)
+
+
 # ------------------------------------------------------------------ cascade
 def cascade_step(st, *, Eg=None, Bg=None, L=None, dt, step, seed, rad, pair, kmax=KMAX,
-                 E0=None, B0=None):
+                 E0=None, B0=None, retire=None):
     """One step of the emission and pair cascade, in the order the GPU runs it:
     photons present at the start move, see the field at their new position and
     may convert (pairs appended to both lepton species); then electrons (q = -1)
     and positrons (q = +1) are pushed and emit (photons appended); finally the
     converted photons are removed.  st: dict with species 'el', 'po', 'ph' (x, p,
     tau, id) and 'next_id'; updated in place.  Fields: the periodic grid Eg, Bg
-    of side L, or (Eg None) the uniform E0, B0 in unbounded space."""
+    of side L, or (Eg None) the uniform E0, B0 in unbounded space.  retire =
+    (t_end, F): photons that can no longer convert before t_end (see above) are
+    counted into st['tally'] and dropped, new ones before they are appended (their
+    ids are assigned all the same), the others after the pair pass."""
     if Eg is None:
         E0, B0 = np.asarray(E0, np.float64), np.asarray(B0, np.float64)
 
@@ -402,6 +447,9 @@ def cascade_step(st, *, Eg=None, Bg=None, L=None, dt, step, seed, rad, pair, kma
         def fields(x):
             return gather_tsc(Eg, Bg, L, x)
     ph = st["ph"]
+    if retire is not None:
+        st.setdefault("tally", np.zeros(TALLY_BINS, dtype=np.int64))
+        t_left = retire[0] - (step + 1) * dt
     if ph["id"].size:
         g = np.sqrt(np.sum(ph["p"] * ph["p"], axis=-1))
         kh = ph["p"] / np.where(g > 0, g, 1.0)[:, None]
@@ -410,7 +458,12 @@ def cascade_step(st, *, Eg=None, Bg=None, L=None, dt, step, seed, rad, pair, kma
         r = photon_step(xm, ph["p"], ph["tau"], ph["id"], E, B, dt=dt, step=step, seed=seed,
                         sampler=pair, next_id=st["next_id"], move=False)
         st["next_id"] = r["next_id"]
-        ph.update(x=xm, tau=r["tau"], id=r["id"])
+        ids = r["id"]
+        if retire is not None:
+            out = (ids != DEAD_ID) & retirable(r["tau"], g, retire[1], t_left)
+            tally_add(st["tally"], g[out])
+            ids = np.where(out, DEAD_ID, ids)
+        ph.update(x=xm, tau=r["tau"], id=ids)
         for name, new in (("el", r["electrons"]), ("po", r["positrons"])):
             sp = st[name]
             for k in ("x", "p", "tau", "id"):
@@ -425,8 +478,12 @@ def cascade_step(st, *, Eg=None, Bg=None, L=None, dt, step, seed, rad, pair, kma
         sp.update(x=r["x"], p=r["p"], tau=r["tau"])
         st["next_id"] = r["next_id"]
         new = r["photons"]
+        keep = np.ones(new["id"].size, dtype=bool)
+        if retire is not None:
+            keep = ~retirable(new["tau"], new["gamma"], retire[1], t_left)
+            tally_add(st["tally"], new["gamma"][~keep])
         for k, v in (("x", new["x"]), ("p", new["k"]), ("tau", new["tau"]), ("id", new["id"])):
-            ph[k] = np.concatenate([ph[k], v])
+            ph[k] = np.concatenate([ph[k], v[keep]])
     keep = ph["id"] != DEAD_ID
     for k in ("x", "p", "tau", "id"):
         ph[k] = ph[k][keep]

@@ -20,6 +20,7 @@ QED_FLAG_NO_RECOIL, QED_FLAG_STATIC_PHOTONS, QED_FLAG_TRACK_DEAD, QED_FLAG_SURRO
 QED_FLAG_METHOD_I, QED_FLAG_NO_SUBSTEP = 16, 32
 QED_SAMPLER_MLP = 2
 QED_CHI_LEPTON, QED_CHI_PHOTON = 0, 1
+QED_TALLY_BINS = 65536
 DEAD_ID = 0xFFFFFFFFFFFFFFFF
 EXPORTS = ["qed_create", "qed_destroy", "qed_last_error", "qed_reserve", "qed_set_next_id",
            "qed_get_next_id", "qed_build_tables", "qed_build_tables_range", "qed_get_table", "qed_init_optical_depth",
@@ -27,7 +28,7 @@ EXPORTS = ["qed_create", "qed_destroy", "qed_last_error", "qed_reserve", "qed_se
            "qed_compact", "qed_sample", "qed_get_status", "qed_surrogate_params",
            "qed_surrogate_train", "qed_surrogate_io", "qed_surrogate_forward", "qed_surrogate_grad",
            "qed_sort_by_cell", "qed_set_step", "qed_advance_step", "qed_fill_standing_wave_at_step",
-           "qed_compact_static", "qed_eval_chi"]
+           "qed_compact_static", "qed_eval_chi", "qed_set_retirement", "qed_tally_species", "qed_get_tally"]
 QED_STEP_DEVICE = -1
 
 
@@ -56,7 +57,7 @@ class qed_counters_t(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "events", "photons", "rejected", "capped", "pairs", "dropped", "chi_out_of_range",
         "nan_chi", "scan_timeouts", "compacted", "mlp_fallback_xi", "mlp_fallback_rate", "thinned",
-        "envelope_exceeded")]
+        "envelope_exceeded", "retired")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -102,6 +103,9 @@ def lib():
             "qed_compact_static": (ctypes.c_int, [vp, ctypes.POINTER(qed_species_t), vp]),
             "qed_eval_chi": (ctypes.c_int, [vp, ctypes.POINTER(qed_fields_t), ctypes.POINTER(qed_species_t),
                                             ctypes.c_int, vp, vp]),
+            "qed_set_retirement": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_double]),
+            "qed_tally_species": (ctypes.c_int, [vp, ctypes.POINTER(qed_species_t), vp]),
+            "qed_get_tally": (ctypes.c_int, [vp, vp, i64, ctypes.c_int, vp]),
             "qed_sample": (ctypes.c_int, [vp, vp, vp, vp, i64, ctypes.c_int, i64, vp, vp, vp, vp]),
             "qed_get_status": (ctypes.c_int, [vp, ctypes.POINTER(qed_counters_t), vp]),
             "qed_set_step": (ctypes.c_int, [vp, i64, vp]),
@@ -232,6 +236,19 @@ class Context:
 
     def qed_compact_static(self, sp, stream=None):
         return self._check(lib().qed_compact_static(self.h, ctypes.byref(sp.c), _stream(stream)))
+
+    def qed_set_retirement(self, t_end, field_bound):
+        return self._check(lib().qed_set_retirement(self.h, float(t_end), float(field_bound)))
+
+    def qed_tally_species(self, sp, stream=None):
+        return self._check(lib().qed_tally_species(self.h, ctypes.byref(sp.c), _stream(stream)))
+
+    def qed_get_tally(self, clear=False, stream=None):
+        import numpy as np
+        out = np.zeros(QED_TALLY_BINS, dtype=np.uint64)
+        self._check(lib().qed_get_tally(self.h, out.ctypes.data_as(ctypes.c_void_p), QED_TALLY_BINS, int(clear),
+                                        _stream(stream)))
+        return out
 
     def qed_eval_chi(self, fields, sp, kind, out, stream=None):
         """out: device float64 tensor of at least sp.n() elements."""

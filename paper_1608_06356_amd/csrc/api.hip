@@ -181,7 +181,7 @@ void qed_destroy(qed_ctx_t c) {
                   c->pair_S64, c->pair_L32, c->pair_s0sc, c->pair_q16, c->tab_work, c->d_counters,
                   c->d_next_id, c->d_n_emit, c->d_ticket, c->rad_chk, c->mlp_theta[0], c->mlp_theta[1],
                   c->mlp_grad[0], c->mlp_grad[1], c->mlp_m[0], c->mlp_m[1], c->mlp_v[0], c->mlp_v[1],
-                  c->sort_keys, c->sort_vals, c->sort_tmp, c->d_killed, c->d_step};
+                  c->sort_keys, c->sort_vals, c->sort_tmp, c->d_killed, c->d_step, c->d_tally};
   for (void *p : ptrs) (void)hipFree(p);
   delete c;
 }
@@ -399,6 +399,40 @@ int qed_sort_by_cell(qed_ctx_t c, const qed_fields_t *f, qed_species_t *src, qed
   if (src->x == dst->x) return fail(c, QED_ERR_ARG, "sort_by_cell: src and dst must differ");
   hipError_t e = qed::launch_sort_by_cell(c, f, src, dst, S(st));
   return e == hipSuccess ? QED_OK : hip_fail(c, e, "sort_by_cell");
+}
+
+int qed_set_retirement(qed_ctx_t c, double t_end, double field_bound) {
+  if (!c) return QED_ERR_ARG;
+  if (!(t_end >= 0.0) || (t_end > 0.0 && !(field_bound > 0.0)))
+    return fail(c, QED_ERR_ARG, "set_retirement: need t_end >= 0 and field_bound > 0");
+  if (t_end > 0.0 && !c->d_tally) {
+    hipError_t e = dalloc(&c->d_tally, QED_TALLY_BINS);
+    if (e == hipSuccess) e = hipMemset(c->d_tally, 0, QED_TALLY_BINS * sizeof(unsigned long long));
+    if (e != hipSuccess) return hip_fail(c, e, "set_retirement");
+  }
+  c->ret_on = t_end > 0.0;
+  c->ret_t_end = t_end;
+  c->ret_field = field_bound;
+  return QED_OK;
+}
+
+int qed_tally_species(qed_ctx_t c, const qed_species_t *sp, void *st) {
+  if (!c) return QED_ERR_ARG;
+  int r = check_species(c, sp, "photons");
+  if (r) return r;
+  if (!c->d_tally) return fail(c, QED_ERR_STATE, "tally_species: no tally (call qed_set_retirement first)");
+  hipError_t e = qed::launch_tally_species(c, sp, S(st));
+  return e == hipSuccess ? QED_OK : hip_fail(c, e, "tally_species");
+}
+
+int qed_get_tally(qed_ctx_t c, uint64_t *host, int64_t nbins, int clear, void *st) {
+  if (!c || !host) return QED_ERR_ARG;
+  if (nbins != QED_TALLY_BINS) return fail(c, QED_ERR_ARG, "get_tally: nbins must be QED_TALLY_BINS");
+  if (!c->d_tally) return fail(c, QED_ERR_STATE, "get_tally: no tally (call qed_set_retirement first)");
+  hipError_t e = hipStreamSynchronize(S(st));
+  if (e == hipSuccess) e = hipMemcpy(host, c->d_tally, QED_TALLY_BINS * sizeof(uint64_t), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && clear) e = hipMemset(c->d_tally, 0, QED_TALLY_BINS * sizeof(uint64_t));
+  return e == hipSuccess ? QED_OK : hip_fail(c, e, "get_tally");
 }
 
 int qed_eval_chi(qed_ctx_t c, const qed_fields_t *f, const qed_species_t *sp, int kind, double *chi, void *st) {

@@ -70,6 +70,11 @@ struct qed_ctx {
 
   int n_cu = 256;
 
+  // photon retirement (qed_set_retirement) and the tally of retired photons
+  int ret_on = 0;
+  double ret_t_end = 0.0, ret_field = 0.0;
+  unsigned long long *d_tally = nullptr;
+
   // device address of the library's static scratch array on this context's
   // device (qed_compact_static)
   uint64_t *static_scratch = nullptr;
@@ -122,6 +127,7 @@ hipError_t launch_init_tau(qed_ctx *c, const qed_species_t *sp, int64_t step, hi
 hipError_t launch_standing_wave(float *grid, int n, double L, double a0, double t0, double dt_step,
                                 const int64_t *d_step, hipStream_t st);
 hipError_t launch_set_step(qed_ctx *c, int64_t v, int add, hipStream_t st);
+hipError_t launch_tally_species(qed_ctx *c, const qed_species_t *sp, hipStream_t st);
 hipError_t launch_eval_chi(qed_ctx *c, const qed_fields_t *f, const qed_species_t *sp, int photon, double *out,
                            hipStream_t st);
 hipError_t launch_sample(qed_ctx *c, const double *chi, const double *gamma, const uint64_t *id,

@@ -44,7 +44,7 @@ enum Purpose : uint32_t { kInitTau = 0, kLeptonEvent = 1, kPhotonEvent = 2, kLep
 // counters (layout of qed_counters_t)
 enum Counter { cEvents = 0, cPhotons, cRejected, cCapped, cPairs, cDropped, cChiRange,
                cNanChi, cScanTimeout, cCompacted, cMlpFallbackXi, cMlpFallbackRate, cThinned,
-               cEnvelopeExceeded, cNumCounters };
+               cEnvelopeExceeded, cRetired, cNumCounters };
 
 // ------------------------------------------------------------------ Philox
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of two 32x32->64

@@ -395,7 +395,7 @@ __device__ __forceinline__ uint32_t next_tile(uint32_t *ticket, uint32_t *lds) {
 }
 
 // Exclusive device-wide offset of this workgroup's tile given its per-thread count.
-__device__ __forceinline__ uint64_t tile_offset(uint32_t tile, uint32_t agg, uint64_t *status,
+__device__ __forceinline__ uint64_t tile_offset(uint32_t tile, uint64_t agg, uint64_t *status,
                                                 unsigned long long *counters, uint64_t *lds64) {
   if (threadIdx.x < 64) {
     const uint64_t e = lookback_scan(status, tile, agg, &counters[cScanTimeout]);
@@ -403,6 +403,105 @@ __device__ __forceinline__ uint64_t tile_offset(uint32_t tile, uint32_t agg, uin
   }
   __syncthreads();
   return *lds64;
+}
+
+// ============================================ photon retirement and tally
+// A photon whose optical depth tau exceeds the largest optical depth it could
+// still accumulate before the end of the run, W_max (t_end - t), cannot convert
+// within the run: W_max = alpha E_S h_pair_env(chi_max) / gamma_ph bounds its
+// pair rate, with chi_max = gamma_ph F / E_S and F a bound of |E| + |B| over the
+// rest of the run given by the caller (|k x (E + k x B)| <= |E| + |B|), since
+// h_pair and the surrogate's pair rate lie below the envelope and the envelope
+// grows with chi.  Such a photon is counted into a histogram of ln gamma_ph (the
+// tally) instead of being stored (at emission) or kept (in pair creation).
+constexpr int kTallyBins = QED_TALLY_BINS;
+constexpr double kTallyLnLo = 0.69314718055994531;   // ln 2
+constexpr double kTallyLnHi = 16.118095650958319;    // ln 1e7
+
+struct RetireDev {
+  int on;
+  double t_end;              // end of the run, t = step * dt
+  float f_over_es;           // F / E_S
+  unsigned long long *tally; // kTallyBins counts
+};
+
+__device__ __forceinline__ double pair_rate_max(float gph, const RetireDev &r) {
+  if (!(gph >= 2.f)) return 0.0;                      // below the pair threshold W = 0
+  return kRateUnit * (double)(h_pair_env(gph * r.f_over_es) * rcp<float>(gph));
+}
+
+// Time left in the run after step `step` (the photon's optical depth is final
+// for t = (step + 1) dt).
+__device__ __forceinline__ double time_left(const RetireDev &r, uint64_t step, double dt) {
+  return r.t_end - (double)(step + 1) * dt;
+}
+
+__device__ __forceinline__ bool retirable(const RetireDev &r, double tau, float gph, double t_left) {
+  return r.on && tau >= pair_rate_max(gph, r) * t_left;
+}
+
+// bin = floor((ln gamma - ln 2) / d) with d = (ln 1e7 - ln 2) / kTallyBins, clamped
+__device__ __forceinline__ void tally_photon(const RetireDev &r, double gph) {
+  const double b = floor((log(gph) - kTallyLnLo) * (kTallyBins / (kTallyLnHi - kTallyLnLo)));
+  const int k = b < 0.0 ? 0 : (b >= (double)kTallyBins ? kTallyBins - 1 : (int)b);
+  atomicAdd(&r.tally[k], 1ull);
+}
+
+// Photons of the emitters of one tile appended in (emitter, event) order: each
+// thread holds nacc accepted photons (gph, tph); ids count every accepted photon
+// (stored or retired, so the stored photons' ids and random streams do not
+// depend on the retirement), storage slots count the stored ones.  Both prefix
+// sums travel in one 64-bit scan value: total | stored << 31.
+template <typename R>
+__device__ void append_photons(const SpeciesDev &ph, const RetireDev &ret, uint64_t step, double dt, uint32_t tile,
+                               int64_t n_em, int tile_size, uint32_t nacc, const R *gph, const double *tph, R x,
+                               R y, R z, R nx, R ny, R nz, int64_t ph0, uint64_t id0, uint64_t *next_id,
+                               const ScanDev &sc, unsigned long long *counters, uint64_t *scan_s, uint64_t *off_s,
+                               uint32_t *cnt) {
+  uint32_t keep = (1u << nacc) - 1u, nret = 0;
+  if (ret.on && nacc) {
+    const double tl = time_left(ret, step, dt);
+#pragma unroll
+    for (int s = 0; s < kKmaxMax; ++s)
+      if (s < (int)nacc && retirable(ret, tph[s], (float)gph[s], tl)) {
+        keep &= ~(1u << s);
+        tally_photon(ret, (double)gph[s]);
+        ++nret;
+      }
+  }
+  const uint32_t nkeep = (uint32_t)__popc(keep);
+  count_lds(cnt, cRetired, nret);
+  uint64_t tot;
+  const uint64_t off = block_exclusive64((uint64_t)nacc | ((uint64_t)nkeep << 31), scan_s, &tot);
+  const uint64_t toff = tile_offset(tile, tot, sc.status, counters, off_s);
+  const uint64_t base = toff + off;
+  const uint64_t rank0 = base & 0x7FFFFFFFull, slot0 = base >> 31;
+  R *X = (R *)ph.x, *Y = (R *)ph.y, *Z = (R *)ph.z;
+  R *KX = (R *)ph.px, *KY = (R *)ph.py, *KZ = (R *)ph.pz;
+  uint32_t ndrop = 0, k = 0;
+#pragma unroll
+  for (int s = 0; s < kKmaxMax; ++s) {
+    if (s < (int)nacc && ((keep >> s) & 1u)) {
+      const int64_t j = ph0 + (int64_t)(slot0 + k);
+      ++k;
+      if (j < ph.cap) {
+        X[j] = x; Y[j] = y; Z[j] = z;
+        KX[j] = nx * gph[s]; KY[j] = ny * gph[s]; KZ[j] = nz * gph[s];
+        ph.tau[j] = tph[s];
+        ph.id[j] = id0 + rank0 + (uint64_t)s;
+      } else {
+        ++ndrop;
+      }
+    }
+  }
+  count_lds(cnt, cDropped, ndrop);
+  const int64_t last = (n_em - 1) / tile_size;
+  if ((int64_t)tile == last && threadIdx.x == 0) {
+    const uint64_t t = toff + tot;
+    const int64_t stored = (int64_t)(t >> 31);
+    *ph.count = ph0 + stored < ph.cap ? ph0 + stored : ph.cap;
+    *next_id = id0 + (t & 0x7FFFFFFFull);
+  }
 }
 
 // ========================================================= gather / push
@@ -650,6 +749,7 @@ struct EmitArgs {
   int gen;                     // event generator (see GPArgs)
   double dtd;
   TabRange rg;
+  RetireDev ret;
 };
 
 // Emitters per tile (= threads per workgroup): 1024 for the float32 optical-depth
@@ -659,7 +759,7 @@ template <typename R, bool M1> constexpr int emit_threads() { return (sizeof(R) 
 
 template <typename R, bool M1, typename Tab>
 __device__ void emit_tile(const EmitArgs<R> &a, const Tab &tab, const R *lnh, uint32_t tile,
-                          uint32_t *scan_s, uint64_t *off_s, int64_t n_em, int64_t ph_count0,
+                          uint64_t *scan_s, uint64_t *off_s, int64_t n_em, int64_t ph_count0,
                           uint64_t id0, uint32_t *cnt) {
   constexpr int T = emit_threads<R, M1>();
   const int64_t r = (int64_t)tile * T + threadIdx.x;
@@ -744,35 +844,8 @@ __device__ void emit_tile(const EmitArgs<R> &a, const Tab &tab, const R *lnh, ui
   count_lds(cnt, cRejected, nrej);
   count_lds(cnt, cCapped, ncap);
   count_lds(cnt, cPhotons, nacc);
-
-  uint32_t total;
-  const uint32_t off = block_exclusive(nacc, scan_s, &total);
-  const uint64_t toff = tile_offset(tile, total, a.sc.status, a.counters, off_s);
-  R *X = (R *)a.ph.x, *Y = (R *)a.ph.y, *Z = (R *)a.ph.z;
-  R *KX = (R *)a.ph.px, *KY = (R *)a.ph.py, *KZ = (R *)a.ph.pz;
-  uint32_t ndrop = 0;
-#pragma unroll
-  for (int s = 0; s < kKmaxMax; ++s) {
-    if (s < (int)nacc) {
-      const uint64_t rank = toff + off + s;
-      const int64_t j = ph_count0 + (int64_t)rank;
-      if (j < a.ph.cap) {
-        X[j] = x; Y[j] = y; Z[j] = z;
-        KX[j] = nx * gph[s]; KY[j] = ny * gph[s]; KZ[j] = nz * gph[s];
-        a.ph.tau[j] = tph[s];
-        a.ph.id[j] = id0 + rank;
-      } else {
-        ++ndrop;
-      }
-    }
-  }
-  count_lds(cnt, cDropped, ndrop);
-  const int64_t last = (n_em - 1) / T;
-  if ((int64_t)tile == last && threadIdx.x == 0) {
-    const int64_t tot = (int64_t)(toff + total);
-    *a.ph.count = ph_count0 + tot < a.ph.cap ? ph_count0 + tot : a.ph.cap;
-    *a.next_id = id0 + (uint64_t)tot;
-  }
+  append_photons<R>(a.ph, a.ret, step_of(a.step, a.d_step), a.dtd, tile, n_em, T, nacc, gph, tph, x, y, z, nx, ny,
+                    nz, ph_count0, id0, a.next_id, a.sc, a.counters, scan_s, off_s, cnt);
 }
 
 // float path: 16-bit quantile table read through the caches (an emission step
@@ -780,7 +853,7 @@ __device__ void emit_tile(const EmitArgs<R> &a, const Tab &tab, const R *lnh, ui
 template <bool M1>
 __global__ __launch_bounds__((emit_threads<float, M1>())) void k_emit_f32(EmitArgs<float> a) {
   __shared__ float lnh_s[kRadNChi];
-  __shared__ uint32_t scan_s[16];
+  __shared__ uint64_t scan_s[16];
   __shared__ uint32_t tile_s;
   __shared__ uint64_t off_s;
   __shared__ int64_t hdr_s[3];
@@ -805,7 +878,7 @@ __global__ __launch_bounds__((emit_threads<float, M1>())) void k_emit_f32(EmitAr
 template <bool M1>
 __global__ __launch_bounds__((emit_threads<double, M1>())) void k_emit_f64(EmitArgs<double> a) {
   __shared__ double lnh_s[kRadNChi];
-  __shared__ uint32_t scan_s[16];
+  __shared__ uint64_t scan_s[16];
   __shared__ uint32_t tile_s;
   __shared__ uint64_t off_s;
   __shared__ int64_t hdr_s[3];
@@ -917,7 +990,7 @@ struct EmitMlpLds {
 __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a, MlpDev m) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   EmitMlpLds &S = *reinterpret_cast<EmitMlpLds *>(lds_raw);
-  __shared__ uint32_t scan_s[16];
+  __shared__ uint64_t scan_s[16];
   __shared__ uint32_t tile_s;
   __shared__ uint64_t off_s;
   __shared__ int64_t hdr_s[3];
@@ -1054,34 +1127,8 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
     count_lds(cnt_s, cMlpFallbackRate, nfr);
     count_lds(cnt_s, cThinned, nnull);
     count_lds(cnt_s, cEnvelopeExceeded, nexc);
-    uint32_t total;
-    const uint32_t off = block_exclusive(nacc, scan_s, &total);
-    const uint64_t toff = tile_offset(tile, total, a.sc.status, a.counters, &off_s);
-    float *PXo = (float *)a.ph.x, *PYo = (float *)a.ph.y, *PZo = (float *)a.ph.z;
-    float *KX = (float *)a.ph.px, *KY = (float *)a.ph.py, *KZ = (float *)a.ph.pz;
-    uint32_t ndrop = 0;
-#pragma unroll
-    for (int sl = 0; sl < kKmaxMax; ++sl) {
-      if (sl < (int)nacc) {
-        const uint64_t rank = toff + off + sl;
-        const int64_t j = ph0 + (int64_t)rank;
-        if (j < a.ph.cap) {
-          PXo[j] = x; PYo[j] = y; PZo[j] = z;
-          KX[j] = nx * gph[sl]; KY[j] = ny * gph[sl]; KZ[j] = nz * gph[sl];
-          a.ph.tau[j] = tph[sl];
-          a.ph.id[j] = id0 + rank;
-        } else {
-          ++ndrop;
-        }
-      }
-    }
-    count_lds(cnt_s, cDropped, ndrop);
-    const int64_t last = (n_em - 1) / kEmitMlpThreads;
-    if ((int64_t)tile == last && threadIdx.x == 0) {
-      const int64_t tot = (int64_t)(toff + total);
-      *a.ph.count = ph0 + tot < a.ph.cap ? ph0 + tot : a.ph.cap;
-      *a.next_id = id0 + (uint64_t)tot;
-    }
+    append_photons<float>(a.ph, a.ret, step, a.dtd, tile, n_em, kEmitMlpThreads, nacc, gph, tph, x, y, z, nx, ny, nz,
+                          ph0, id0, a.next_id, a.sc, a.counters, scan_s, &off_s, cnt_s);
   }
   count_flush(cnt_s, a.counters);
 }
@@ -1106,6 +1153,7 @@ struct PairArgs {
   unsigned long long *counters;
   int64_t *killed;
   TabRange rg;
+  RetireDev ret;
 };
 
 constexpr int kPairThreads = 256, kPairItems = 4, kPairTile = kPairThreads * kPairItems;
@@ -1148,7 +1196,8 @@ __device__ void pair_tile(const PairArgs<R> &a, const Tab &tab, const R *L, uint
   const int64_t base = (int64_t)tile * kPairTile;
   R *X = (R *)a.ph.x, *Y = (R *)a.ph.y, *Z = (R *)a.ph.z;
   const R *KX = (const R *)a.ph.px, *KY = (const R *)a.ph.py, *KZ = (const R *)a.ph.pz;
-  uint32_t evbits = 0, nrange = 0, nnan = 0;
+  uint32_t evbits = 0, nrange = 0, nnan = 0, nret = 0;
+  const double t_left = time_left(a.ret, step_of(a.step, a.d_step), a.dtd);
   // float32: every load of the thread's photons first, so that their latencies
   // overlap (float64 keeps them per photon: the registers would halve its
   // occupancy); positions are needed to move the photon or to gather from a grid
@@ -1216,13 +1265,23 @@ __device__ void pair_tile(const PairArgs<R> &a, const Tab &tab, const R *L, uint
       ++nnan;
     }
     const double tau = taus[it];
-    if (W > 0.0 && tau <= W * a.dtd) evbits |= 1u << it;
-    else a.ph.tau[i] = tau - W * a.dtd;
+    if (W > 0.0 && tau <= W * a.dtd) {
+      evbits |= 1u << it;
+    } else {
+      const double tn = tau - W * a.dtd;
+      a.ph.tau[i] = tn;
+      if (retirable(a.ret, tn, (float)gph, t_left)) {
+        a.ph.id[i] = kDeadId;
+        tally_photon(a.ret, (double)gph);
+        ++nret;
+      }
+    }
   }
   const uint32_t ev = (uint32_t)__popc(evbits);
   count_lds(cnt, cChiRange, nrange);
   count_lds(cnt, cNanChi, nnan);
   count_lds(cnt, cPairs, ev);
+  count_lds(cnt, cRetired, nret);
   uint64_t packed = 0;
 #pragma unroll
   for (int it = 0; it < kPairItems; ++it) packed |= (uint64_t)((evbits >> it) & 1u) << (16 * it);
@@ -1275,7 +1334,7 @@ __device__ void pair_tile(const PairArgs<R> &a, const Tab &tab, const R *L, uint
     *a.el.count = e0 + tt < a.el.cap ? e0 + tt : a.el.cap;
     *a.po.count = p0 + tt < a.po.cap ? p0 + tt : a.po.cap;
     *a.next_id = id0 + 2 * (uint64_t)tt;
-    if (a.killed) *a.killed += tt;
+    if (a.killed) atomicAdd((unsigned long long *)a.killed, (unsigned long long)tt);
   }
 }
 
@@ -1294,9 +1353,19 @@ __device__ void pair_tile_thin(const PairArgs<float> &a, const mlp::NetLdsI &Bn,
   const int64_t base = (int64_t)tile * kPairTile;
   float *X = (float *)a.ph.x, *Y = (float *)a.ph.y, *Z = (float *)a.ph.z;
   const float *KX = (const float *)a.ph.px, *KY = (const float *)a.ph.py, *KZ = (const float *)a.ph.pz;
-  uint32_t evbits = 0, nrange = 0, nnan = 0, nnull = 0, nfr = 0, ncap = 0, nexc = 0;
+  uint32_t evbits = 0, nrange = 0, nnan = 0, nnull = 0, nfr = 0, ncap = 0, nexc = 0, nret = 0;
   const bool need_x = a.move || a.f.kind == QED_FIELD_GRID, pp = a.f.kind == QED_FIELD_PER_PARTICLE;
   const uint64_t step = step_of(a.step, a.d_step);
+  const double t_left = time_left(a.ret, step, a.dtd);
+  // the photon's optical depth at the end of the step; retired if it can no longer convert
+  auto settle = [&](int64_t i, double tn, float gph) {
+    a.ph.tau[i] = tn;
+    if (retirable(a.ret, tn, gph, t_left)) {
+      a.ph.id[i] = kDeadId;
+      tally_photon(a.ret, (double)gph);
+      ++nret;
+    }
+  };
   uint64_t pids[kPairItems];
   float kk[kPairItems][3], xx[kPairItems][3], Fp[kPairItems][6];
   double taus[kPairItems];
@@ -1359,7 +1428,7 @@ __device__ void pair_tile_thin(const PairArgs<float> &a, const mlp::NetLdsI &Bn,
     chis[it] = chi;
     wenv[it] = We;
     if (We > 0.0 && taus[it] <= We * a.dtd) cbits |= 1u << it;
-    else a.ph.tau[i] = taus[it] - We * a.dtd;
+    else settle(i, taus[it] - We * a.dtd, gph);
   }
   // candidates: the net for every lane of the wave at once, one item at a time
   // (one copy of the net's code: the item's values are picked by selects)
@@ -1391,8 +1460,8 @@ __device__ void pair_tile_thin(const PairArgs<float> &a, const mlp::NetLdsI &Bn,
       if (unit<double>(u.x) * Wenv < W) { evbits |= 1u << it; break; }
       ++nnull;
       tau = -log(unit<double>(u.y));
-      if (!(tau <= Wenv * rem)) { a.ph.tau[i] = tau - Wenv * rem; break; }
-      if (k + 1 >= kmax) { ++ncap; a.ph.tau[i] = tau - Wenv * rem; break; }
+      if (!(tau <= Wenv * rem)) { settle(i, tau - Wenv * rem, gph); break; }
+      if (k + 1 >= kmax) { ++ncap; settle(i, tau - Wenv * rem, gph); break; }
       rem -= tau / Wenv;
     }
   }
@@ -1404,6 +1473,7 @@ __device__ void pair_tile_thin(const PairArgs<float> &a, const mlp::NetLdsI &Bn,
   count_lds(cnt, cMlpFallbackRate, nfr);
   count_lds(cnt, cCapped, ncap);
   count_lds(cnt, cEnvelopeExceeded, nexc);
+  count_lds(cnt, cRetired, nret);
   uint64_t packed = 0;
 #pragma unroll
   for (int it = 0; it < kPairItems; ++it) packed |= (uint64_t)((evbits >> it) & 1u) << (16 * it);
@@ -1457,7 +1527,7 @@ __device__ void pair_tile_thin(const PairArgs<float> &a, const mlp::NetLdsI &Bn,
     *a.el.count = e0 + tt < a.el.cap ? e0 + tt : a.el.cap;
     *a.po.count = p0 + tt < a.po.cap ? p0 + tt : a.po.cap;
     *a.next_id = id0 + 2 * (uint64_t)tt;
-    if (a.killed) *a.killed += tt;
+    if (a.killed) atomicAdd((unsigned long long *)a.killed, (unsigned long long)tt);
   }
 }
 
@@ -1487,6 +1557,9 @@ __global__ __launch_bounds__(kPairThreads, 2) void k_pairs_mlp(PairArgs<float> a
     pair_tile_thin(a, B_s, tab, L_s, tile, scan_s, &off_s, n, e0, p0, id0, cnt_s, kmax);
   }
   count_flush(cnt_s, a.counters);
+  // retired photons are dead too: the compaction of this species must not skip
+  if (threadIdx.x == 0 && a.killed && cnt_s[cRetired])
+    atomicAdd((unsigned long long *)a.killed, (unsigned long long)cnt_s[cRetired]);
 }
 
 // three waves per SIMD (at most 168 registers): its four photons per thread
@@ -1517,6 +1590,9 @@ __global__ __launch_bounds__(kPairThreads, 3) void k_pairs_f32(PairArgs<float> a
     pair_tile<float>(a, tab, L_s, tile, scan_s, &off_s, n, e0, p0, id0, cnt_s);
   }
   count_flush(cnt_s, a.counters);
+  // retired photons are dead too: the compaction of this species must not skip
+  if (threadIdx.x == 0 && a.killed && cnt_s[cRetired])
+    atomicAdd((unsigned long long *)a.killed, (unsigned long long)cnt_s[cRetired]);
 }
 
 __global__ __launch_bounds__(kPairThreads) void k_pairs_f64(PairArgs<double> a) {
@@ -1543,6 +1619,9 @@ __global__ __launch_bounds__(kPairThreads) void k_pairs_f64(PairArgs<double> a) 
     pair_tile<double>(a, tab, L_s, tile, scan_s, &off_s, n, e0, p0, id0, cnt_s);
   }
   count_flush(cnt_s, a.counters);
+  // retired photons are dead too: the compaction of this species must not skip
+  if (threadIdx.x == 0 && a.killed && cnt_s[cRetired])
+    atomicAdd((unsigned long long *)a.killed, (unsigned long long)cnt_s[cRetired]);
 }
 
 // ============================================================== compact
@@ -1782,6 +1861,10 @@ static void launch_gp_kind(const GPArgs<R> &a, int kind, unsigned grid, hipStrea
   else launch_gp_kind_m<R, false>(a, kind, grid, st);
 }
 
+static RetireDev retire_dev(const qed_ctx *c) {
+  return RetireDev{c->ret_on, c->ret_t_end, (float)(c->ret_field * kInvES), c->d_tally};
+}
+
 static MlpDev mlp_dev(qed_ctx *c) {
   return MlpDev{c->range, c->mlp_theta[0], c->mlp_theta[1], c->rad_chk, c->rad_lnh32, c->rad_q16, c->rad_s0sc, 2e-3f};
 }
@@ -1877,20 +1960,20 @@ hipError_t launch_emit(qed_ctx *c, const qed_species_t *lep, const qed_species_t
     EmitArgs<float> a{dev_species(lep), dev_species(ph), c->rad_lnh32, c->rad_S64, c->rad_q16,
                       c->rad_s0sc, c->em_idx, (const EmRec<float> *)c->em_rec, c->d_n_emit,
                       c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, dstep, sc,
-                      c->d_counters, gen_mode(c), c->em_dt, c->range};
+                      c->d_counters, gen_mode(c), c->em_dt, c->range, retire_dev(c)};
     hipLaunchKernelGGL(k_emit_mlp, dim3(grid), dim3(kEmitMlpThreads), sizeof(EmitMlpLds), st, a, mlp_dev(c));
   } else if (lep->dtype == QED_F32) {
     EmitArgs<float> a{dev_species(lep), dev_species(ph), c->rad_lnh32, c->rad_S64, c->rad_q16,
                       c->rad_s0sc, c->em_idx, (const EmRec<float> *)c->em_rec, c->d_n_emit,
                       c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, dstep, sc,
-                      c->d_counters, gen_mode(c), c->em_dt, c->range};
+                      c->d_counters, gen_mode(c), c->em_dt, c->range, retire_dev(c)};
     if (a.gen) hipLaunchKernelGGL(k_emit_f32<true>, dim3(grid), dim3(emit_threads<float, true>()), 0, st, a);
     else hipLaunchKernelGGL(k_emit_f32<false>, dim3(grid), dim3(emit_threads<float, false>()), 0, st, a);
   } else {
     EmitArgs<double> a{dev_species(lep), dev_species(ph), c->rad_lnh64, c->rad_S64, c->rad_q16,
                        c->rad_s0sc, c->em_idx, (const EmRec<double> *)c->em_rec, c->d_n_emit,
                        c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, dstep, sc,
-                       c->d_counters, gen_mode(c), c->em_dt, c->range};
+                       c->d_counters, gen_mode(c), c->em_dt, c->range, retire_dev(c)};
     if (a.gen) hipLaunchKernelGGL(k_emit_f64<true>, dim3(grid), dim3(emit_threads<double, true>()), 0, st, a);
     else hipLaunchKernelGGL(k_emit_f64<false>, dim3(grid), dim3(emit_threads<double, false>()), 0, st, a);
   }
@@ -1912,7 +1995,8 @@ hipError_t launch_pairs(qed_ctx *c, const qed_fields_t *f, const qed_species_t *
   if (ph->dtype == QED_F32) {
     PairArgs<float> a{dev_species(ph), dev_species(el), dev_species(po), dev_fields(f), c->pair_L32,
                       c->pair_S64, c->pair_q16, c->pair_s0sc, (float)dt, dt, move, c->d_next_id,
-                      c->params.seed, (uint64_t)step, step < 0 ? c->d_step : nullptr, sc, c->d_counters, killed, c->range};
+                      c->params.seed, (uint64_t)step, step < 0 ? c->d_step : nullptr, sc, c->d_counters, killed, c->range,
+                      retire_dev(c)};
     if (c->params.flags & QED_FLAG_SURROGATE)
       hipLaunchKernelGGL(k_pairs_mlp, dim3(grid), dim3(kPairThreads), 0, st, a, c->mlp_theta[1], c->params.kmax);
     else
@@ -1920,7 +2004,8 @@ hipError_t launch_pairs(qed_ctx *c, const qed_fields_t *f, const qed_species_t *
   } else {
     PairArgs<double> a{dev_species(ph), dev_species(el), dev_species(po), dev_fields(f), c->pair_L64,
                        c->pair_S64, c->pair_q16, c->pair_s0sc, dt, dt, move, c->d_next_id,
-                       c->params.seed, (uint64_t)step, step < 0 ? c->d_step : nullptr, sc, c->d_counters, killed, c->range};
+                       c->params.seed, (uint64_t)step, step < 0 ? c->d_step : nullptr, sc, c->d_counters, killed, c->range,
+                      retire_dev(c)};
     hipLaunchKernelGGL(k_pairs_f64, dim3(grid), dim3(kPairThreads), 0, st, a);
   }
   return hipGetLastError();
@@ -1989,6 +2074,27 @@ __global__ void k_add_i64(int64_t *p, int64_t v) { *p += v; }
 hipError_t launch_set_step(qed_ctx *c, int64_t v, int add, hipStream_t st) {
   if (add) hipLaunchKernelGGL(k_add_i64, dim3(1), dim3(1), 0, st, c->d_step, v);
   else hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, st, c->d_step, v);
+  return hipGetLastError();
+}
+
+template <typename R>
+__global__ void k_tally_species(SpeciesDev sp, RetireDev r) {
+  const int64_t n = *sp.count;
+  const R *PX = (const R *)sp.px, *PY = (const R *)sp.py, *PZ = (const R *)sp.pz;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (sp.id[i] != kDeadId) {
+      const double kx = PX[i], ky = PY[i], kz = PZ[i];
+      tally_photon(r, sqrt(kx * kx + ky * ky + kz * kz));
+    }
+}
+
+hipError_t launch_tally_species(qed_ctx *c, const qed_species_t *sp, hipStream_t st) {
+  int64_t blocks = (sp->capacity + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (sp->dtype == QED_F32)
+    hipLaunchKernelGGL(k_tally_species<float>, dim3((unsigned)blocks), dim3(256), 0, st, dev_species(sp), retire_dev(c));
+  else
+    hipLaunchKernelGGL(k_tally_species<double>, dim3((unsigned)blocks), dim3(256), 0, st, dev_species(sp), retire_dev(c));
   return hipGetLastError();
 }
 

@@ -71,3 +71,63 @@ def test_cascade_counts_and_spectra(rad_table_I, pair_table):
     crit = 1.95 * math.sqrt((gg.size + go.size) / (gg.size * go.size))
     print(f"photon energy KS {ks:.2e} (0.1% critical {crit:.2e})")
     assert ks < crit
+
+
+def test_retirement_cascade_f64_matches_oracle(rad_table_I, pair_table):
+    """The cascade with photon retirement (qed_set_retirement), float64, uniform
+    B = b0 z (|E| + |B| = b0) with electrons at gamma = 1e4, chi = 20, 10 steps
+    of 0.05: electrons, positrons and followed photons (ids, momenta) and the
+    tally (retired photons, then the followed ones added by qed_tally_species)
+    against the oracle's cascade with the same retirement rule (end time set
+    five steps beyond the run, so that some photons are still followed)."""
+    torch, q = need_gpu()
+    from oracle.constants import E_S
+    n, g0, steps, dt, seed = 1500, 1.0e4, 10, 0.05, 3
+    t_end = (steps + 5) * dt
+    b0 = 20.0 * E_S / g0
+    rng = np.random.default_rng(9)
+    phi = rng.uniform(0, 2 * math.pi, n)
+    pm = math.sqrt(g0 * g0 - 1.0)
+    p0 = np.stack([pm * np.cos(phi), pm * np.sin(phi), np.zeros(n)], -1)
+    ids = np.arange(n, dtype=np.uint64)
+    tau0 = mc.init_tau(ids, seed=seed)
+    # oracle
+    e0 = lambda: dict(x=np.zeros((0, 3)), p=np.zeros((0, 3)), tau=np.zeros(0), id=np.zeros(0, np.uint64))
+    st = dict(el=dict(x=np.zeros((n, 3)), p=p0.copy(), tau=tau0.copy(), id=ids.copy()), po=e0(), ph=e0(), next_id=n)
+    rad, pair = mc.RadSampler(rad_table_I, "f64"), mc.PairSampler(pair_table, "f64")
+    for s in range(steps):
+        mc.cascade_step(st, dt=dt, step=s, seed=seed, rad=rad, pair=pair, E0=(0, 0, 0), B0=(0, 0, b0),
+                        retire=(t_end, b0))
+    # GPU
+    ctx = q.Context(seed=seed, kmax=4, flags=q.QED_FLAG_TRACK_DEAD)
+    ctx.qed_build_tables(q.QED_FORMULA_I)
+    ctx.qed_set_retirement(t_end, b0)
+    el, po, ph = q.Species(4 * n, "f64"), q.Species(4 * n, "f64"), q.Species(40 * n, "f64")
+    el.load(np.zeros((n, 3)), p0, tau0, ids)
+    z = np.zeros((0, 3))
+    po.load(z, z, np.zeros(0), np.zeros(0, np.uint64))
+    ph.load(z, z, np.zeros(0), np.zeros(0, np.uint64))
+    ctx.qed_set_next_id(n)
+    ctx.qed_reserve(40 * n)
+    fld = q.Fields(q.QED_FIELD_UNIFORM, B=(0, 0, b0))
+    for s in range(steps):
+        ctx.qed_create_pairs(fld, ph, el, po, dt, s)
+        for sp, qq in ((el, -1), (po, 1)):
+            ctx.qed_gather_push(fld, sp, qq, dt, s)
+            ctx.qed_emit_photons(sp, ph, s)
+        ctx.qed_compact(ph)
+    stat, rc = ctx.qed_get_status()
+    tally_retired = ctx.qed_get_tally()
+    ctx.qed_tally_species(ph)
+    tally_all = ctx.qed_get_tally()
+    g = {k: sp.to_numpy() for k, sp in (("el", el), ("po", po), ("ph", ph))}
+    print(f"retirement cascade: electrons {g['el']['id'].size} positrons {g['po']['id'].size} photons followed "
+          f"{g['ph']['id'].size}, retired {int(tally_retired.sum())} (oracle {int(st['tally'].sum())})")
+    assert g["po"]["id"].size > 10 and g["ph"]["id"].size > 10 and stat["retired"] == int(tally_retired.sum())
+    for k in ("el", "po", "ph"):
+        np.testing.assert_array_equal(g[k]["id"], st[k]["id"])
+        np.testing.assert_allclose(g[k]["p"], st[k]["p"], rtol=1e-9, atol=1e-9 * np.abs(st[k]["p"]).max(initial=1.0))
+    np.testing.assert_array_equal(tally_retired, st["tally"])
+    want = st["tally"].copy()
+    mc.tally_add(want, np.linalg.norm(st["ph"]["p"], axis=1))
+    np.testing.assert_array_equal(tally_all, want)

@@ -341,3 +341,46 @@ def test_cascade_step_energy_and_bookkeeping(rad_table_I, pair_table):
     assert st["el"]["id"].size == n + total_pairs
     e1 = energy()
     assert abs(e1 - e0) < 1e-11 * e0 + 2.0, (e0, e1)
+
+
+def test_retirement_is_exact(rad_table_I, pair_table):
+    """Photon retirement (a photon whose optical depth exceeds the envelope pair
+    rate at its largest reachable chi times the time left cannot convert before
+    the end): the same cascade with and without it gives identical electrons and
+    positrons (ids, momenta, positions, optical depths), and the photons kept plus
+    the tally give the histogram of the photons followed without retirement; most
+    photons are retired.  Uniform B = b0 z, E = 0: |E| + |B| = b0."""
+    rad = mc.RadSampler(rad_table_I, "f64")
+    pair = mc.PairSampler(pair_table, "f64")
+    n, g0, steps, dt = 1500, 1.0e4, 10, 0.05
+    b0 = 20.0 * E_S / g0
+    rng = np.random.default_rng(9)
+    phi = rng.uniform(0, 2 * math.pi, n)
+    pm = math.sqrt(g0 * g0 - 1.0)
+
+    def run(retire):
+        e0 = lambda: dict(x=np.zeros((0, 3)), p=np.zeros((0, 3)), tau=np.zeros(0), id=np.zeros(0, np.uint64))
+        st = dict(el=dict(x=np.zeros((n, 3)), p=np.stack([pm * np.cos(phi), pm * np.sin(phi), np.zeros(n)], -1),
+                          tau=mc.init_tau(np.arange(n, dtype=np.uint64), seed=3), id=np.arange(n, dtype=np.uint64)),
+                  po=e0(), ph=e0(), next_id=n)
+        for s in range(steps):
+            mc.cascade_step(st, dt=dt, step=s, seed=3, rad=rad, pair=pair, E0=(0, 0, 0), B0=(0, 0, b0),
+                            retire=retire)
+        return st
+
+    a = run(None)
+    b = run((steps * dt, b0))
+    for sp in ("el", "po"):
+        for k in ("id", "p", "x", "tau"):
+            np.testing.assert_array_equal(a[sp][k], b[sp][k])
+    assert a["po"]["id"].size > 10
+    ga = np.linalg.norm(a["ph"]["p"], axis=1)
+    gb = np.linalg.norm(b["ph"]["p"], axis=1)
+    ha = np.zeros(mc.TALLY_BINS, dtype=np.int64)
+    mc.tally_add(ha, ga)
+    hb = b["tally"].copy()
+    mc.tally_add(hb, gb)
+    np.testing.assert_array_equal(ha, hb)
+    # the photons still followed are the unretired ones of the full run, same ids
+    assert set(b["ph"]["id"].tolist()) <= set(a["ph"]["id"].tolist())
+    assert b["tally"].sum() > 0.5 * ga.size
