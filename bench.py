@@ -230,8 +230,8 @@ def run_cascade(q, torch, args, weights, name):
     compaction every C5_COMPACT_EVERY steps) on the standing wave, captured as
     hipGraphs and replayed for the whole run; electrons and photons re-sorted by
     cell every C5_SORT_EVERY steps outside the graphs (into second buffers: the
-    electrons are copied back so that the graphs' pointers stay valid, the photons
-    alternate between two buffers with a graph for each).  Photons converted into
+    electrons and positrons are copied back so that the graphs' pointers stay
+    valid, the photons alternate between two buffers with a graph for each).  Photons converted into
     pairs stay in place as dead slots (pair creation skips them) until the
     compaction: a stable compaction moves every photon behind the first hole.
     The 2e8 electrons: ids 0..99999 from workloads.standing_wave_electrons (the
@@ -260,7 +260,7 @@ def run_cascade(q, torch, args, weights, name):
     cap_e, cap_p = int(1.4 * n) + 1_000_000, int(0.4 * n) + 1_000_000
     cap_g = min(int(0.012 * n * total) + 10_000_000, (1 << 31) - 1)
     el, el_b = q.Species(cap_e, "f32"), q.Species(cap_e, "f32")
-    po = q.Species(cap_p, "f32")
+    po, po_b = q.Species(cap_p, "f32"), q.Species(cap_p, "f32")
     phs = [q.Species(cap_g, "f32"), q.Species(cap_g, "f32")]
     cur = [0]
     gen = torch.Generator(device="cuda")
@@ -305,10 +305,13 @@ def run_cascade(q, torch, args, weights, name):
         ctx.qed_advance_step()
 
     def resort():
-        ctx.qed_sort_by_cell(fld, el, el_b)
-        for a, b in ((el.x, el_b.x), (el.y, el_b.y), (el.z, el_b.z), (el.px, el_b.px), (el.py, el_b.py),
-                     (el.pz, el_b.pz), (el.tau, el_b.tau), (el.id, el_b.id), (el.count, el_b.count)):
-            a.copy_(b)
+        for sp, spb in ((el, el_b), (po, po_b)):
+            ctx.qed_sort_by_cell(fld, sp, spb)
+            nn = spb.n()
+            for a, b in ((sp.x, spb.x), (sp.y, spb.y), (sp.z, spb.z), (sp.px, spb.px), (sp.py, spb.py),
+                         (sp.pz, spb.pz), (sp.tau, spb.tau), (sp.id, spb.id)):
+                a[:nn].copy_(b[:nn])
+            sp.count.copy_(spb.count)
         ctx.qed_sort_by_cell(fld, phs[cur[0]], phs[1 - cur[0]])
         cur[0] ^= 1
 
@@ -377,7 +380,7 @@ def run_cascade(q, torch, args, weights, name):
                timed_from=timed0,
                pair_pass_ms=pair_ms, pair_pass_photons=pair_n, lepton_pass_ms=gp_ms, lepton_pass_electrons=gp_n,
                capacity_photons=cap_g)
-    del graphs, el, el_b, po, phs, grid, ph, processed
+    del graphs, el, el_b, po, po_b, phs, grid, ph, processed
     ctx.close()
     torch.cuda.synchronize()
     torch.cuda.empty_cache()

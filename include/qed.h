@@ -261,8 +261,10 @@ QED_API int qed_create_pairs(qed_ctx_t ctx, const qed_fields_t *fields, qed_spec
    inside a block, i.e. ((k/4 * NBy + j/4) * NBx + i/4) * 64 + ((k%4) * 4 + j%4) * 4 + i%4
    with NBx = ceil(nx/4), NBy = ceil(ny/4).  Ids, optical depths
    and therefore every random stream move with the particles.  A periodic sort is
-   what keeps qed_gather_push's field reads local.  Allocates its scratch on the
-   first call for a given capacity (call once before graph capture). */
+   what keeps qed_gather_push's field reads local.  Sorts the *count particles
+   present: reads the count from the device, which synchronises `stream`.
+   Allocates its scratch on the first call for a given capacity; not for graph
+   capture. */
 QED_API int qed_sort_by_cell(qed_ctx_t ctx, const qed_fields_t *fields, qed_species_t *src,
                              qed_species_t *dst, void *stream);
 

@@ -61,9 +61,11 @@ __global__ void k_permute(const R *sx, const R *sy, const R *sz, const R *spx, c
   if (blockIdx.x == 0 && threadIdx.x == 0) *dcount = n;
 }
 
+// Sorts the n particles the species holds (n read from the device by the caller).
 template <typename R>
-hipError_t sort_impl(qed_ctx *c, const qed_fields_t *f, const qed_species_t *s, qed_species_t *d, hipStream_t st) {
-  const int64_t cap = s->capacity;
+hipError_t sort_impl(qed_ctx *c, const qed_fields_t *f, const qed_species_t *s, qed_species_t *d, int64_t n,
+                     hipStream_t st) {
+  const int64_t cap = n > 0 ? n : 1;
   int64_t blocks = (cap + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   uint32_t *k0 = c->sort_keys, *k1 = c->sort_keys + cap, *v0 = c->sort_vals, *v1 = c->sort_vals + cap;
@@ -78,7 +80,9 @@ hipError_t sort_impl(qed_ctx *c, const qed_fields_t *f, const qed_species_t *s, 
   ++bits;   // the all-ones sentinel of unused slots sorts last
   if (bits > 32) bits = 32;
   size_t need = 0;
-  if ((e = rocprim::radix_sort_pairs(nullptr, need, k0, k1, v0, v1, (size_t)cap, 0u, bits, st)) != hipSuccess) return e;
+  // scratch sized for the capacity, so that it is allocated once per species size
+  if ((e = rocprim::radix_sort_pairs(nullptr, need, k0, k1, v0, v1, (size_t)s->capacity, 0u, bits, st)) != hipSuccess)
+    return e;
   if (need > c->sort_tmp_bytes) {
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
     (void)hipFree(c->sort_tmp);
@@ -87,7 +91,10 @@ hipError_t sort_impl(qed_ctx *c, const qed_fields_t *f, const qed_species_t *s, 
     if ((e = hipMalloc(&c->sort_tmp, need)) != hipSuccess) return e;
     c->sort_tmp_bytes = need;
   }
-  if ((e = rocprim::radix_sort_pairs(c->sort_tmp, need, k0, k1, v0, v1, (size_t)cap, 0u, bits, st)) != hipSuccess)
+  size_t need_n = 0;
+  if ((e = rocprim::radix_sort_pairs(nullptr, need_n, k0, k1, v0, v1, (size_t)cap, 0u, bits, st)) != hipSuccess)
+    return e;
+  if ((e = rocprim::radix_sort_pairs(c->sort_tmp, need_n, k0, k1, v0, v1, (size_t)cap, 0u, bits, st)) != hipSuccess)
     return e;
   const int64_t pblocks = (blocks + 7) / 8 * 8;
   hipLaunchKernelGGL(k_permute<R>, dim3((unsigned)pblocks), dim3(256), 0, st, (const R *)s->x, (const R *)s->y,
@@ -112,7 +119,14 @@ hipError_t launch_sort_by_cell(qed_ctx *c, const qed_fields_t *f, const qed_spec
     if ((e = hipMalloc(&c->sort_vals, 2 * s->capacity * sizeof(uint32_t))) != hipSuccess) return e;
     c->sort_cap = s->capacity;
   }
-  return s->dtype == QED_F32 ? sort_impl<float>(c, f, s, d, st) : sort_impl<double>(c, f, s, d, st);
+  // sort only the particles present: the count is read from the device (this
+  // synchronises the stream; the sort is not for graph capture anyway)
+  int64_t n = 0;
+  hipError_t e = hipMemcpyAsync(&n, s->count, sizeof(n), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return e;
+  if (n > s->capacity) n = s->capacity;
+  return s->dtype == QED_F32 ? sort_impl<float>(c, f, s, d, n, st) : sort_impl<double>(c, f, s, d, n, st);
 }
 
 }  // namespace qed

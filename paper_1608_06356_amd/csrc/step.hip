@@ -577,8 +577,12 @@ template <typename R, int FK, bool M1> constexpr int gp_waves() {
 template <typename R, int FK, bool M1, bool Thin = false>
 __global__ __launch_bounds__(kGPThreads, (gp_waves<R, FK, M1>())) void k_gather_push(GPArgs<R> a) {
   __shared__ R lnh_s[kRadNChi];
-  const int64_t tile = (int64_t)(blockIdx.x % kXcds) * a.tpx + blockIdx.x / kXcds;
+  // tiles per XCD for the particles present (the grid is sized by the capacity;
+  // dealing by the count keeps all eight XCDs busy when the species is not full)
   const int64_t n = *a.sp.count;
+  const int64_t tpx = ((n + kGPTile - 1) / kGPTile + kXcds - 1) / kXcds;
+  if ((int64_t)(blockIdx.x / kXcds) >= tpx) return;
+  const int64_t tile = (int64_t)(blockIdx.x % kXcds) * tpx + blockIdx.x / kXcds;
   const int64_t base = tile * kGPTile;
   if (base >= n) return;
   // the tile's slices of the arrays (uniform bases, 32-bit thread offsets)
