@@ -286,22 +286,22 @@ def run_cascade(q, torch, args, weights, name):
     stream = torch.cuda.current_stream()
 
     def one_step(compact, pb, ev=None):
+        # ev: events around the parts of the step (pairs, electron push, electron
+        # emission, positron push, positron emission, compaction)
+        rec = (lambda k: ev[k].record(stream)) if ev is not None else (lambda k: None)
         ph = phs[pb]
         ctx.qed_fill_standing_wave_at_step(grid, ngrid, L, C5_A0, 0.0, C5_DT)
-        if ev is not None:
-            ev[0].record(stream)
+        rec(0)
         ctx.qed_create_pairs(fld, ph, el, po, C5_DT, q.QED_STEP_DEVICE)
-        if ev is not None:
-            ev[1].record(stream)
+        rec(1)
         for sp, qq in ((el, -1), (po, 1)):
-            if ev is not None and sp is el:
-                ev[2].record(stream)
             ctx.qed_gather_push(fld, sp, qq, C5_DT, q.QED_STEP_DEVICE)
-            if ev is not None and sp is el:
-                ev[3].record(stream)
+            rec(2 if sp is el else 4)
             ctx.qed_emit_photons(sp, ph, q.QED_STEP_DEVICE)
+            rec(3 if sp is el else 5)
         if compact:
             ctx.qed_compact(ph)
+        rec(6)
         ctx.qed_advance_step()
 
     def resort():
@@ -338,9 +338,11 @@ def run_cascade(q, torch, args, weights, name):
         compact = (k + 1) % C5_COMPACT_EVERY == 0 or k == total - 1
         if k >= timed0:
             processed.add_(el.count + po.count + phs[cur[0]].count)
-        if k >= timed0 and (k - timed0) % 40 == 0:
-            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-            cnt = [phs[cur[0]].count.clone(), el.count.clone()]
+        # every 23rd timed step runs eagerly with events around its parts: 23 is
+        # prime to the re-sort interval, so the samples see every phase of it
+        if k >= timed0 and (k - timed0) % 23 == 3 % min(args.steps, 23):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
+            cnt = [phs[cur[0]].count.clone(), el.count.clone(), po.count.clone()]
             one_step(compact, cur[0], ev)
             samples.append((ev, cnt))
         else:
@@ -357,9 +359,13 @@ def run_cascade(q, torch, args, weights, name):
     st, rc = ctx.qed_get_status(check=False)
     tot = int(processed.item())
     pair_ms = [a[0].elapsed_time(a[1]) for a, _ in samples]
-    gp_ms = [a[2].elapsed_time(a[3]) for a, _ in samples]
+    gp_ms = [a[1].elapsed_time(a[2]) for a, _ in samples]
     pair_n = [int(c[0].item()) for _, c in samples]
     gp_n = [int(c[1].item()) for _, c in samples]
+    parts = {name: [a[i].elapsed_time(a[i + 1]) for a, _ in samples] for i, name in
+             enumerate(("pairs", "electron_push", "electron_emission", "positron_push", "positron_emission",
+                        "compaction"))}
+    parts["positrons"] = [int(c[2].item()) for _, c in samples]
     ph = phs[cur[0]]
     nph = ph.n()                                 # the last step compacted: no dead slots
     retired = ctx.qed_get_tally()
@@ -379,6 +385,7 @@ def run_cascade(q, torch, args, weights, name):
                retired=int(retired.sum()), photon_hist=photon_hist, positron_gamma=positron_gamma, steps_run=total,
                timed_from=timed0,
                pair_pass_ms=pair_ms, pair_pass_photons=pair_n, lepton_pass_ms=gp_ms, lepton_pass_electrons=gp_n,
+               sampled_step_parts_ms=parts,
                capacity_photons=cap_g)
     del graphs, el, el_b, po, po_b, phs, grid, ph, processed
     ctx.close()

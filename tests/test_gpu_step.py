@@ -613,8 +613,9 @@ def test_method1_substep_f64_parity(rad_table_I):
 
 def test_method1_dt_study():
     """The paper's time-step study (Fig. 3 discussion) with method I, float32, no
-    recoil, chi ~ 1: Dt = 0.2/W and Dt = 6/W with adaptive sub-steps reproduce the
-    rate W; Dt = 6/W without sub-steps saturates at one event per step."""
+    recoil, chi ~ 1: Dt = 0.007/W, 0.2/W and 6/W with adaptive sub-steps reproduce
+    the rate W (at 0.007/W and 0.2/W a single sub-step, as the paper finds the two
+    alike); Dt = 6/W without sub-steps saturates at one event per step."""
     torch, q = need_gpu()
     from oracle.constants import RATE_UNIT
     n, b0, g = 200000, 2000.0, 206.0
@@ -622,7 +623,7 @@ def test_method1_dt_study():
     W = RATE_UNIT * tables.fine_row("I", chi, tables.RAD_M, need_rho=False).total / g
     ens = workloads.uniform_b_ensembles(n, seed=8, triples=((b0, g),))[0]
     fld = q.Fields(q.QED_FIELD_UNIFORM, B=(0, 0, b0))
-    for wdt, flags in ((0.2, 0), (6.0, 0), (6.0, q.QED_FLAG_NO_SUBSTEP)):
+    for wdt, flags in ((0.007, 0), (0.2, 0), (6.0, 0), (6.0, q.QED_FLAG_NO_SUBSTEP)):
         ctx = q.Context(seed=8, kmax=4 if wdt < 1 else 4, flags=q.QED_FLAG_METHOD_I | q.QED_FLAG_NO_RECOIL | flags)
         ctx.qed_build_tables(q.QED_FORMULA_I)
         lep = q.Species(n, "f32")
@@ -641,6 +642,7 @@ def test_method1_dt_study():
             assert abs(rate * dt - 1) < 1e-12
         elif wdt < 1:
             mean = n * steps * wdt
+            print(f"method I, Dt = {wdt}/W: events {st['events']} (mean {mean:.0f})")
             assert abs(st["events"] - mean) < 4 * math.sqrt(mean)
         else:
             # 30 sub-steps of p = 0.2, kmax = 4 caps the events: compare the capped
