@@ -53,7 +53,7 @@ PROFILED_SOURCES = ("step.hip", "qed_device.h", "lookup.h")
 # the cascade configuration
 C5_N, C5_STEPS, C5_A0, C5_DT, C5_GRID, C5_SEED = 200_000_000, 500, 1000.0, 0.01, 128, 4
 C5_SUBSAMPLE = 100_000          # ids 0 .. 99999: drawn on the host, shared with the oracle
-C5_SORT_EVERY, C5_COMPACT_EVERY = 20, 10
+C5_SORT_EVERY, C5_COMPACT_EVERY = 10, 10
 # fixed-chi emission run of the 1e7-sample spectrum gate (chi ~ 1: b0 = 2000, gamma = 206)
 KS_N, KS_B0, KS_GAMMA, KS_DT, KS_STEPS = 1_000_000, 2000.0, 206.0, 0.05, 20
 
@@ -89,6 +89,7 @@ def parse():
     ap.add_argument("--no-other-configs", action="store_true")
     ap.add_argument("--c5-n", type=int, default=C5_N, help="electrons of the cascade (2e8)")
     ap.add_argument("--c5-steps", type=int, default=C5_STEPS, help="steps of the cascade run (500)")
+    ap.add_argument("--c5-sort-every", type=int, default=C5_SORT_EVERY, help="re-sort interval of the cascade")
     return ap.parse_args()
 
 
@@ -229,9 +230,8 @@ def run_cascade(q, torch, args, weights, name):
     """The cascade step (pair creation, both lepton passes with emission, photon
     compaction every C5_COMPACT_EVERY steps) on the standing wave, captured as
     hipGraphs and replayed for the whole run; electrons and photons re-sorted by
-    cell every C5_SORT_EVERY steps outside the graphs (into second buffers: the
-    electrons and positrons are copied back so that the graphs' pointers stay
-    valid, the photons alternate between two buffers with a graph for each).  Photons converted into
+    cell every `--c5-sort-every` steps outside the graphs (from one set of
+    species buffers into the other; graphs are captured for both sets).  Photons converted into
     pairs stay in place as dead slots (pair creation skips them) until the
     compaction: a stable compaction moves every photon behind the first hole.
     The 2e8 electrons: ids 0..99999 from workloads.standing_wave_electrons (the
@@ -259,37 +259,39 @@ def run_cascade(q, torch, args, weights, name):
     ctx.qed_set_retirement(total * C5_DT, c5_field_bound())
     cap_e, cap_p = int(1.4 * n) + 1_000_000, int(0.4 * n) + 1_000_000
     cap_g = min(int(0.012 * n * total) + 10_000_000, (1 << 31) - 1)
-    el, el_b = q.Species(cap_e, "f32"), q.Species(cap_e, "f32")
-    po, po_b = q.Species(cap_p, "f32"), q.Species(cap_p, "f32")
-    phs = [q.Species(cap_g, "f32"), q.Species(cap_g, "f32")]
+    # two sets of species: a re-sort moves every species from the set in use to
+    # the other one (graphs are captured for both sets)
+    sets = [dict(el=q.Species(cap_e, "f32"), po=q.Species(cap_p, "f32"), ph=q.Species(cap_g, "f32"))
+            for _ in range(2)]
     cur = [0]
+    src = sets[1]["el"]
     gen = torch.Generator(device="cuda")
     gen.manual_seed(C5_SEED)
-    for a in (el_b.x, el_b.y, el_b.z):
+    for a in (src.x, src.y, src.z):
         a[:n].uniform_(0.0, L, generator=gen)
-    for a in (el_b.px, el_b.py, el_b.pz):
+    for a in (src.px, src.py, src.pz):
         a[:n].normal_(0.0, 10.0, generator=gen)
-    torch.arange(n, out=el_b.id[:n])
+    torch.arange(n, out=src.id[:n])
     sub = workloads.standing_wave_electrons(C5_SUBSAMPLE, seed=C5_SEED)
-    for a, col in ((el_b.x, sub["x"][:, 0]), (el_b.y, sub["x"][:, 1]), (el_b.z, sub["x"][:, 2]),
-                   (el_b.px, sub["p"][:, 0]), (el_b.py, sub["p"][:, 1]), (el_b.pz, sub["p"][:, 2])):
+    for a, col in ((src.x, sub["x"][:, 0]), (src.y, sub["x"][:, 1]), (src.z, sub["x"][:, 2]),
+                   (src.px, sub["p"][:, 0]), (src.py, sub["p"][:, 1]), (src.pz, sub["p"][:, 2])):
         a[:C5_SUBSAMPLE].copy_(torch.from_numpy(np.ascontiguousarray(col, dtype=np.float32)))
     del sub
-    el_b.count.fill_(n)
+    src.count.fill_(n)
     grid = torch.empty(ngrid ** 3 * 6, dtype=torch.float32, device="cuda")
     fld = q.Fields(q.QED_FIELD_GRID, grid=grid, n=ngrid, L=L)
     ctx.qed_reserve(cap_e)             # emitter slots for the leptons; the photons' scan state on first use
-    ctx.qed_sort_by_cell(fld, el_b, el)
-    ctx.qed_init_optical_depth(el, 0)
+    ctx.qed_sort_by_cell(fld, src, sets[0]["el"])
+    ctx.qed_init_optical_depth(sets[0]["el"], 0)
     ctx.qed_set_next_id(n)
     ctx.qed_set_step(0)
     stream = torch.cuda.current_stream()
 
-    def one_step(compact, pb, ev=None):
+    def one_step(compact, sid, ev=None):
         # ev: events around the parts of the step (pairs, electron push, electron
         # emission, positron push, positron emission, compaction)
         rec = (lambda k: ev[k].record(stream)) if ev is not None else (lambda k: None)
-        ph = phs[pb]
+        el, po, ph = sets[sid]["el"], sets[sid]["po"], sets[sid]["ph"]
         ctx.qed_fill_standing_wave_at_step(grid, ngrid, L, C5_A0, 0.0, C5_DT)
         rec(0)
         ctx.qed_create_pairs(fld, ph, el, po, C5_DT, q.QED_STEP_DEVICE)
@@ -305,14 +307,9 @@ def run_cascade(q, torch, args, weights, name):
         ctx.qed_advance_step()
 
     def resort():
-        for sp, spb in ((el, el_b), (po, po_b)):
-            ctx.qed_sort_by_cell(fld, sp, spb)
-            nn = spb.n()
-            for a, b in ((sp.x, spb.x), (sp.y, spb.y), (sp.z, spb.z), (sp.px, spb.px), (sp.py, spb.py),
-                         (sp.pz, spb.pz), (sp.tau, spb.tau), (sp.id, spb.id)):
-                a[:nn].copy_(b[:nn])
-            sp.count.copy_(spb.count)
-        ctx.qed_sort_by_cell(fld, phs[cur[0]], phs[1 - cur[0]])
+        a, b = sets[cur[0]], sets[1 - cur[0]]
+        for k in ("el", "po", "ph"):
+            ctx.qed_sort_by_cell(fld, a[k], b[k])
         cur[0] ^= 1
 
     one_step(False, 0)                 # step 0 eagerly, then capture
@@ -320,12 +317,12 @@ def run_cascade(q, torch, args, weights, name):
     graphs = {}
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
-    for pb in (0, 1):
+    for sid in (0, 1):
         for compact in (False, True):
-            graphs[compact, pb] = torch.cuda.CUDAGraph()
+            graphs[compact, sid] = torch.cuda.CUDAGraph()
             with torch.cuda.stream(side):
-                with torch.cuda.graph(graphs[compact, pb], stream=side):
-                    one_step(compact, pb)
+                with torch.cuda.graph(graphs[compact, sid], stream=side):
+                    one_step(compact, sid)
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
     processed = torch.zeros(1, dtype=torch.int64, device="cuda")
@@ -333,16 +330,17 @@ def run_cascade(q, torch, args, weights, name):
 
     def step(k):
         # step k of the run (k >= 1); step 0 ran eagerly above
-        if k % C5_SORT_EVERY == 0:
+        if k % args.c5_sort_every == 0:
             resort()
         compact = (k + 1) % C5_COMPACT_EVERY == 0 or k == total - 1
+        sp = sets[cur[0]]
         if k >= timed0:
-            processed.add_(el.count + po.count + phs[cur[0]].count)
+            processed.add_(sp["el"].count + sp["po"].count + sp["ph"].count)
         # every 23rd timed step runs eagerly with events around its parts: 23 is
         # prime to the re-sort interval, so the samples see every phase of it
         if k >= timed0 and (k - timed0) % 23 == 3 % min(args.steps, 23):
             ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
-            cnt = [phs[cur[0]].count.clone(), el.count.clone(), po.count.clone()]
+            cnt = [sp["ph"].count.clone(), sp["el"].count.clone(), sp["po"].count.clone()]
             one_step(compact, cur[0], ev)
             samples.append((ev, cnt))
         else:
@@ -366,7 +364,7 @@ def run_cascade(q, torch, args, weights, name):
              enumerate(("pairs", "electron_push", "electron_emission", "positron_push", "positron_emission",
                         "compaction"))}
     parts["positrons"] = [int(c[2].item()) for _, c in samples]
-    ph = phs[cur[0]]
+    el, po, ph = sets[cur[0]]["el"], sets[cur[0]]["po"], sets[cur[0]]["ph"]
     nph = ph.n()                                 # the last step compacted: no dead slots
     retired = ctx.qed_get_tally()
     ctx.qed_tally_species(ph)                    # + the photons still followed
@@ -387,7 +385,7 @@ def run_cascade(q, torch, args, weights, name):
                pair_pass_ms=pair_ms, pair_pass_photons=pair_n, lepton_pass_ms=gp_ms, lepton_pass_electrons=gp_n,
                sampled_step_parts_ms=parts,
                capacity_photons=cap_g)
-    del graphs, el, el_b, po, po_b, phs, grid, ph, processed
+    del graphs, sets, el, po, ph, grid, processed
     ctx.close()
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
@@ -752,8 +750,8 @@ def main():
         "config": {"workload": f"cascade step, {head_name} path: standing wave a0={C5_A0:g}, {args.c5_n} electrons "
                                f"at start, {C5_GRID}^3 grid, formula {'II' if args.formula == 2 else 'I'} tables, "
                                f"{total} steps of dt={C5_DT} as hipGraphs (the last {args.steps} timed), photon "
-                               f"compaction every {C5_COMPACT_EVERY} steps, electrons and photons re-sorted every "
-                               f"{C5_SORT_EVERY}",
+                               f"compaction every {C5_COMPACT_EVERY} steps, all species re-sorted by cell every "
+                               f"{args.c5_sort_every}",
                    "global_batch": args.c5_n, "dt": C5_DT, "steps_run": total, "parallelism": "single GPU"},
         "path": head_name,
         "roofline": kernel_roofline(head, grid_bytes),

@@ -147,7 +147,7 @@ typedef struct {
   int64_t mlp_fallback_xi;     /* surrogate xi samples that fell back to the table */
   int64_t mlp_fallback_rate;   /* surrogate rates that fell back to the table     */
   int64_t thinned;             /* surrogate path: candidate events not kept (thinning) */
-  int64_t envelope_exceeded;   /* surrogate path: a rate above its envelope (must be 0) */
+  int64_t envelope_exceeded;   /* surrogate path: a rate outside [0.89, 1] x its envelope (must be 0) */
   int64_t retired;             /* photons retired into the tally (qed_set_retirement) */
 } qed_counters_t;
 

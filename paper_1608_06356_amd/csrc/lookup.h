@@ -89,6 +89,11 @@ __device__ __forceinline__ R h_pair(R chi, const R *L, const TabRange &rg) {
 // bare forms stays within [0.90, 0.99999] (photons) and [0.93, 0.9992] (pairs)
 // over chi in [1e-5, 1e4].
 constexpr double kEnvMargin = 1.002;
+// Lower bound of rate / envelope (both envelopes, over the same chi range):
+// a candidate whose keep draw u is below it is kept without evaluating the rate
+// (the squeeze of rejection sampling), which is exact as long as the rate used
+// also stays above it (the surrogate's rates are within 1e-3 of the table's).
+constexpr double kEnvSqueeze = 0.89;
 constexpr double kErberC = 0.22963966338592295;   // 3 sqrt3 / (16 sqrt2)
 __device__ __forceinline__ float h_rad_env(float chi) {
   if (!(chi > 0.f)) return 0.f;

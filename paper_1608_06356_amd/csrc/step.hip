@@ -1043,23 +1043,25 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
     for (int k = 0; k < a.kmax; ++k) {
       if (!__any(active)) break;
       mlp::reload_barrier();
-      // keep the candidate with probability W / W_env (net B, packed over the
-      // lanes with a pending candidate)
+      // keep the candidate with probability W / W_env: below the squeeze the
+      // draw keeps it at once, above it W comes from net B (packed over the
+      // lanes that need it)
+      const double ukeep = unit<double>(stream4(id, a.seed, step, kLeptonThin, (uint32_t)k).x);
+      const bool need_w = active && !(ukeep < kEnvSqueeze);
       bool ok;
-      const float lh = mlp_lnh(S.B, chi, active, ok);
-      bool keep = false;
-      if (active) {
+      const float lh = mlp_lnh(S.B, chi, need_w, ok);
+      bool keep = active && ukeep < kEnvSqueeze;
+      if (need_w) {
         float h = 0.f;
         if (isfinite(chi) && chi > 0.0) {
           h = ok ? expf(lh) : h_rad<float>((float)chi, S.lnh, m.rg);
           nfr += !ok;
         }
         const double W = kRateUnit * (double)(h / g);
-        nexc += W > Wenv;
-        const uint4 ut = stream4(id, a.seed, step, kLeptonThin, (uint32_t)k);
-        keep = unit<double>(ut.x) * Wenv < W;
-        nnull += !keep;
+        nexc += W > Wenv || W < kEnvSqueeze * Wenv;
+        keep = ukeep * Wenv < W;
       }
+      nnull += active && !keep;
       const uint4 u = stream4(id, a.seed, step, kLeptonEvent, (uint32_t)k);
       const float uxi = unit<float>(u.x), urow = unit<float>(u.z);
       const float t = logf(uxi) - log1pf(-uxi);
@@ -1410,24 +1412,32 @@ __device__ void pair_tile_thin(const PairArgs<float> &a, const mlp::NetLdsI &Bn,
       }
       X[i] = x; Y[i] = y; Z[i] = z;
     }
-    float F[6];
-    if (pp) {
-#pragma unroll
-      for (int c = 0; c < 6; ++c) F[c] = Fp[it][c];
+    double chi = -1.0, We = 0.0;
+    if (a.ret.on) {
+      // with the caller's field bound the envelope is the photon's largest pair
+      // rate for the rest of the run, W_max(gamma_ph): no field is gathered
+      // unless a candidate event comes up (chi < 0: evaluated below)
+      We = pair_rate_max(gph, a.ret);
     } else {
-      field_at<float>(a.f, i, x, y, z, F);
-    }
-    double chi = 0.0, We = 0.0;
-    if (fields_finite<float>(F)) {
-      chi = chi_photon_f32(kx, ky, kz, F);
-      if (isfinite(chi)) {
-        nrange += chi > a.rg.pair_hi;
-        if (gph >= 2.f) We = kRateUnit * (double)(h_pair_env((float)chi) * rcp<float>(gph));
+      float F[6];
+      if (pp) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) F[c] = Fp[it][c];
+      } else {
+        field_at<float>(a.f, i, x, y, z, F);
+      }
+      chi = 0.0;
+      if (fields_finite<float>(F)) {
+        chi = chi_photon_f32(kx, ky, kz, F);
+        if (isfinite(chi)) {
+          nrange += chi > a.rg.pair_hi;
+          if (gph >= 2.f) We = kRateUnit * (double)(h_pair_env((float)chi) * rcp<float>(gph));
+        } else {
+          ++nnan;
+        }
       } else {
         ++nnan;
       }
-    } else {
-      ++nnan;
     }
     chis[it] = chi;
     wenv[it] = We;
@@ -1451,16 +1461,35 @@ __device__ void pair_tile_thin(const PairArgs<float> &a, const mlp::NetLdsI &Bn,
 #pragma unroll
     for (int j = 1; j < kPairItems; ++j)
       if (it == j) { chi = chis[j]; Wenv = wenv[j]; tau = taus[j]; gph = gphs[j]; pid = pids[j]; }
+    if (cand && chi < 0.0) {
+      // candidate of the field-free envelope: the field at the moved position
+      float F[6];
+      field_at<float>(a.f, i, X[i], Y[i], Z[i], F);
+      chi = 0.0;
+      if (fields_finite<float>(F)) {
+        chi = chi_photon_f32(KX[i], KY[i], KZ[i], F);
+        if (isfinite(chi)) nrange += chi > a.rg.pair_hi;
+        else { ++nnan; chi = 0.0; }
+      } else {
+        ++nnan;
+      }
+    }
+    // with the local envelope (chi known) the first keep draw below the squeeze
+    // keeps the candidate without the net; otherwise the pair head gives W
+    const uint4 u0 = stream4(pid, a.seed, step, kPhotonThin, 0u);
+    const bool squeeze = !a.ret.on && unit<double>(u0.x) < kEnvSqueeze;
+    const bool need_w = cand && !squeeze;
     bool ok;
-    const float lh = mlp_lnh_pair(Bn, chi, cand, ok);
+    const float lh = mlp_lnh_pair(Bn, chi, need_w, ok);
     if (!cand) continue;
-    const float h = ok ? expf(lh) : h_pair<float, true>((float)chi, L, a.rg);
+    if (squeeze) { evbits |= 1u << it; continue; }
+    const float h = !(chi >= kPairChiMin) ? 0.f : (ok ? expf(lh) : h_pair<float, true>((float)chi, L, a.rg));
     nfr += !ok;
     const double W = kRateUnit * (double)(h * rcp<float>(gph));
-    nexc += W > Wenv;
+    nexc += W > Wenv || (!a.ret.on && W < kEnvSqueeze * Wenv);
     double rem = a.dtd - tau / Wenv;
     for (int k = 0;; ++k) {
-      const uint4 u = stream4(pid, a.seed, step, kPhotonThin, (uint32_t)k);
+      const uint4 u = k == 0 ? u0 : stream4(pid, a.seed, step, kPhotonThin, (uint32_t)k);
       if (unit<double>(u.x) * Wenv < W) { evbits |= 1u << it; break; }
       ++nnull;
       tau = -log(unit<double>(u.y));
