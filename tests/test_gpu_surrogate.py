@@ -303,16 +303,21 @@ def test_surrogate_step_spectrum_and_rate(trained):
     assert st["mlp_fallback_xi"] < 0.01 * st["events"]
 
 
-def test_surrogate_pairs_yield_and_spectrum_1e7(trained, pair_table):
+@pytest.mark.parametrize("field_bound", [False, True])
+def test_surrogate_pairs_yield_and_spectrum_1e7(trained, pair_table, field_bound):
     """Pair creation with QED_FLAG_SURROGATE (candidates at the envelope
-    h_pair_env, kept with the pair head of the rate net): 1e7 photons at
-    chi_ph = 1, one step with W dt = 1.  The pair yield against 1 - exp(-W dt)
-    with W from the oracle's quadrature, within the surrogate's 1e-3 rate bar
-    plus 4 sigma; the electron energy fraction against the exact Eq. (6) CDF
-    (one-sample KS <= 2e-3)."""
+    h_pair_env at the photon's chi, or, with a field bound F from
+    qed_set_retirement, at the photon's largest rate h_pair_env(gamma_ph F / E_S)
+    with no field gathered for non-candidates; kept with the pair head of the
+    rate net): 1e7 photons at chi_ph = 1, one step with W dt = 1.  The pair yield
+    against 1 - exp(-W dt) with W from the oracle's quadrature, within the
+    surrogate's 1e-3 rate bar plus 4 sigma; the electron energy fraction against
+    the exact Eq. (6) CDF (one-sample KS <= 2e-3)."""
     torch, q = need_gpu()
     n, gph, chi = 10_000_000, 1000.0, 1.0
     ctx = _with_weights(q, trained, seed=31, kmax=4, flags=q.QED_FLAG_STATIC_PHOTONS | q.QED_FLAG_SURROGATE)
+    if field_bound:                     # |E| + |B| = b; the end far away: nothing is retired
+        ctx.qed_set_retirement(1e3, chi * E_S / gph)
     ph, el, po = q.Species(n, "f32"), q.Species(n, "f32"), q.Species(n, "f32")
     b = chi * E_S / gph
     ph.load(np.zeros((n, 3)), np.tile([gph, 0.0, 0.0], (n, 1)), ids=np.arange(n, dtype=np.uint64))
@@ -332,7 +337,7 @@ def test_surrogate_pairs_yield_and_spectrum_1e7(trained, pair_table):
     print(f"surrogate pairs {m} (oracle mean {n * pr:.0f}, z {(m - n * pr) / sig:+.2f}), candidates not kept "
           f"{st['thinned']}, rate fallbacks {st['mlp_fallback_rate']}")
     assert abs(m - n * pr) < slack + 4 * sig
-    assert st["envelope_exceeded"] == 0 and st["pairs"] == m
+    assert st["envelope_exceeded"] == 0 and st["pairs"] == m and st["retired"] == 0
     ge = torch.sqrt(1 + el.px[:m].double() ** 2 + el.py[:m].double() ** 2 + el.pz[:m].double() ** 2)
     xi = np.sort((ge / gph).cpu().numpy())
     P = row.F / row.total
