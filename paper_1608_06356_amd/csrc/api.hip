@@ -102,6 +102,28 @@ int ensure_emitters(qed_ctx *c, int64_t n) {
   return QED_OK;
 }
 
+void free_cands(qed_ctx *c) {
+  (void)hipFree(c->cand_mask); (void)hipFree(c->cand_idx); (void)hipFree(c->d_n_cand);
+  c->cand_mask = nullptr; c->cand_idx = nullptr; c->d_n_cand = nullptr;
+  c->cand_cap = 0;
+}
+
+// Candidate mask and list of the surrogate pair pass for photon species of up
+// to n particles.  Allocates, so not under graph capture.
+int ensure_cands(qed_ctx *c, int64_t n) {
+  if (n <= c->cand_cap) return QED_OK;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(c, e, "create_pairs");
+  free_cands(c);
+  if ((e = dalloc(&c->cand_mask, n / 64 + 1)) != hipSuccess || (e = dalloc(&c->cand_idx, n)) != hipSuccess ||
+      (e = dalloc(&c->d_n_cand, 1)) != hipSuccess) {
+    free_cands(c);
+    return hip_fail(c, e, "create_pairs: hipMalloc");
+  }
+  c->cand_cap = n;
+  return QED_OK;
+}
+
 hipStream_t S(void *s) { return (hipStream_t)s; }
 
 // ------------------------------------------- static scratch (qed_compact_static)
@@ -177,6 +199,7 @@ void qed_destroy(qed_ctx_t c) {
   (void)hipDeviceSynchronize();
   free_emitters(c);
   free_scan(c);
+  free_cands(c);
   void *ptrs[] = {c->rad_lnh64, c->rad_S64, c->rad_lnh32, c->rad_s0sc, c->rad_q16, c->pair_L64,
                   c->pair_S64, c->pair_L32, c->pair_s0sc, c->pair_q16, c->tab_work, c->d_counters,
                   c->d_next_id, c->d_n_emit, c->d_ticket, c->rad_chk, c->mlp_theta[0], c->mlp_theta[1],
@@ -363,6 +386,8 @@ int qed_create_pairs(qed_ctx_t c, const qed_fields_t *f, qed_species_t *ph, qed_
   if (step < 0 && step != QED_STEP_DEVICE) return fail(c, QED_ERR_ARG, "step must be >= 0 or QED_STEP_DEVICE");
   if (!c->tables_ready) return fail(c, QED_ERR_STATE, "tables not built");
   if ((r = ensure_scan(c, ph->capacity))) return r;
+  if ((c->params.flags & QED_FLAG_SURROGATE) && ph->dtype == QED_F32 && (r = ensure_cands(c, ph->capacity)))
+    return r;
   hipError_t e = qed::launch_pairs(c, f, ph, el, po, dt, step, S(st));
   return e == hipSuccess ? QED_OK : hip_fail(c, e, "create_pairs");
 }

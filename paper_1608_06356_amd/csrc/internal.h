@@ -56,6 +56,13 @@ struct qed_ctx {
   int em_charge = 0;
   double em_dt = 0.0;
 
+  // candidate events of the surrogate pair pass: ballot mask and ordered list
+  // over the photons (sized for the largest photon species)
+  int64_t cand_cap = 0;
+  uint64_t *cand_mask = nullptr;
+  int32_t *cand_idx = nullptr;
+  int64_t *d_n_cand = nullptr;
+
   // dead-particle count of the species compacted last (pairs add to it; compaction
   // skips its work when it is zero)
   int64_t *d_killed = nullptr;

@@ -688,9 +688,10 @@ constexpr int kEIThreads = 256;
 template <int W> constexpr int64_t ei_tile() { return (int64_t)kEIThreads * W * 64; }
 constexpr int64_t kEIWideFrom = (int64_t)1 << 22;   // capacity from which W = 8
 
-template <int W>
+// Idx = EmIdx: (particle index, record slot); Idx = int32_t: the particle index alone.
+template <int W, typename Idx>
 __global__ __launch_bounds__(kEIThreads) void k_emit_index(const uint64_t *mask, const int64_t *count,
-                                                           EmIdx *em_idx, int64_t *n_emit, ScanDev sc,
+                                                           Idx *em_idx, int64_t *n_emit, ScanDev sc,
                                                            unsigned long long *counters) {
   __shared__ uint32_t scan_s[16];
   __shared__ uint32_t tile_s;
@@ -723,7 +724,9 @@ __global__ __launch_bounds__(kEIThreads) void k_emit_index(const uint64_t *mask,
     const int32_t wb = (int32_t)((w0 + k) << 6);
     int32_t slot = wb;   // records of a mask word are packed from its base (rec_slot)
     while (b) {
-      em_idx[r++] = EmIdx{wb + (__ffsll((long long)b) - 1), slot++};
+      const int32_t p = wb + (__ffsll((long long)b) - 1);
+      if constexpr (sizeof(Idx) == sizeof(EmIdx)) em_idx[r++] = EmIdx{p, slot++};
+      else em_idx[r++] = p;
       b &= b - 1ull;
     }
   }
@@ -1344,253 +1347,256 @@ __device__ void pair_tile(const PairArgs<R> &a, const Tab &tab, const R *L, uint
   }
 }
 
-// Surrogate pair pass (float32): the optical depth runs down at the envelope
-// rate W_env = alpha E_S h_pair_env / gamma_ph (Poisson thinning); a photon whose
-// optical depth runs out gets the pair head of net B evaluated (table if the
-// output fails its check) and its candidate is kept with probability
-// W / W_env; an unkept candidate draws a new optical depth and the next
-// candidate of the step follows at the same chi (the photon's chi does not
-// change within the step), up to kmax candidates.  Counter k of the photon's
+// Surrogate pair pass (float32): Poisson thinning.  A photon's optical depth
+// runs down at the envelope rate W_env (alpha E_S h_pair_env(chi) / gamma_ph at
+// the photon's chi, or, with the retirement's field bound, the largest pair
+// rate W_max(gamma_ph) it can reach, which needs no field); a photon whose
+// optical depth runs out within the step is a candidate: it gets the pair head
+// of net B (the table if the output fails its check) and its candidate is kept
+// with probability W / W_env; an unkept candidate draws a new optical depth and
+// the next candidate of the step follows at the same chi (the photon's chi does
+// not change within the step), up to kmax candidates.  Counter k of the photon's
 // PHOTON_THIN stream gives (keep draw, new optical depth) of candidate k; a kept
 // candidate makes the pair exactly as pair_tile does (PHOTON_EVENT, counter 0).
-__device__ void pair_tile_thin(const PairArgs<float> &a, const mlp::NetLdsI &Bn, const RowQ16 &tab, const float *L,
-                               uint32_t tile, uint64_t *scan_s, uint64_t *off_s, int64_t n, int64_t e0, int64_t p0,
-                               uint64_t id0, uint32_t *cnt, int kmax) {
-  const int64_t base = (int64_t)tile * kPairTile;
-  float *X = (float *)a.ph.x, *Y = (float *)a.ph.y, *Z = (float *)a.ph.z;
-  const float *KX = (const float *)a.ph.px, *KY = (const float *)a.ph.py, *KZ = (const float *)a.ph.pz;
-  uint32_t evbits = 0, nrange = 0, nnan = 0, nnull = 0, nfr = 0, ncap = 0, nexc = 0, nret = 0;
-  const bool need_x = a.move || a.f.kind == QED_FIELD_GRID, pp = a.f.kind == QED_FIELD_PER_PARTICLE;
-  const uint64_t step = step_of(a.step, a.d_step);
-  const double t_left = time_left(a.ret, step, a.dtd);
-  // the photon's optical depth at the end of the step; retired if it can no longer convert
-  auto settle = [&](int64_t i, double tn, float gph) {
-    a.ph.tau[i] = tn;
-    if (retirable(a.ret, tn, gph, t_left)) {
-      a.ph.id[i] = kDeadId;
-      tally_photon(a.ret, (double)gph);
-      ++nret;
-    }
-  };
-  uint64_t pids[kPairItems];
-  float kk[kPairItems][3], xx[kPairItems][3], Fp[kPairItems][6];
-  double taus[kPairItems];
-#pragma unroll
-  for (int it = 0; it < kPairItems; ++it) {
-    const int64_t i = base + (int64_t)it * kPairThreads + threadIdx.x;
-    const bool v = i < n;
-    pids[it] = v ? a.ph.id[i] : kDeadId;
-    kk[it][0] = v ? KX[i] : 0.f; kk[it][1] = v ? KY[i] : 0.f; kk[it][2] = v ? KZ[i] : 0.f;
-    taus[it] = v ? a.ph.tau[i] : 0.0;
-    const bool vx = v && need_x;
-    xx[it][0] = vx ? X[i] : 0.f; xx[it][1] = vx ? Y[i] : 0.f; xx[it][2] = vx ? Z[i] : 0.f;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      Fp[it][c] = (v && pp) ? a.f.pE[c][i] : 0.f;
-      Fp[it][3 + c] = (v && pp) ? a.f.pB[c][i] : 0.f;
-    }
-  }
-  // streaming part: move, field, chi, envelope rate; optical depths of the
-  // photons without a candidate are final here
-  double chis[kPairItems], wenv[kPairItems];
-  uint32_t cbits = 0;
-#pragma unroll
-  for (int it = 0; it < kPairItems; ++it) {
-    const int64_t i = base + (int64_t)it * kPairThreads + threadIdx.x;
-    chis[it] = 0.0;
-    wenv[it] = 0.0;
-    if (pids[it] == kDeadId) continue;          // converted photons not yet compacted are skipped
-    const float kx = kk[it][0], ky = kk[it][1], kz = kk[it][2];
-    const float gph = root<float>(kx * kx + ky * ky + kz * kz);
-    float x = xx[it][0], y = xx[it][1], z = xx[it][2];
-    if (a.move && gph > 0.f) {
-      const float vdt = rcp<float>(gph) * a.dt;
-      x += kx * vdt; y += ky * vdt; z += kz * vdt;
-      if (a.f.kind == QED_FIELD_GRID) {
-        wrap_coord<float>(x, box_len<float>(a.f, 0)); wrap_coord<float>(y, box_len<float>(a.f, 1));
-        wrap_coord<float>(z, box_len<float>(a.f, 2));
-      }
-      X[i] = x; Y[i] = y; Z[i] = z;
-    }
-    double chi = -1.0, We = 0.0;
-    if (a.ret.on) {
-      // with the caller's field bound the envelope is the photon's largest pair
-      // rate for the rest of the run, W_max(gamma_ph): no field is gathered
-      // unless a candidate event comes up (chi < 0: evaluated below)
-      We = pair_rate_max(gph, a.ret);
-    } else {
-      float F[6];
-      if (pp) {
-#pragma unroll
-        for (int c = 0; c < 6; ++c) F[c] = Fp[it][c];
-      } else {
-        field_at<float>(a.f, i, x, y, z, F);
-      }
-      chi = 0.0;
-      if (fields_finite<float>(F)) {
-        chi = chi_photon_f32(kx, ky, kz, F);
-        if (isfinite(chi)) {
-          nrange += chi > a.rg.pair_hi;
-          if (gph >= 2.f) We = kRateUnit * (double)(h_pair_env((float)chi) * rcp<float>(gph));
-        } else {
-          ++nnan;
-        }
-      } else {
-        ++nnan;
-      }
-    }
-    chis[it] = chi;
-    wenv[it] = We;
-    if (We > 0.0 && taus[it] <= We * a.dtd) cbits |= 1u << it;
-    else settle(i, taus[it] - We * a.dtd, gph);
-  }
-  // candidates: the net for every lane of the wave at once, one item at a time
-  // (one copy of the net's code: the item's values are picked by selects)
-  float gphs[kPairItems];
-#pragma unroll
-  for (int it = 0; it < kPairItems; ++it)
-    gphs[it] = root<float>(kk[it][0] * kk[it][0] + kk[it][1] * kk[it][1] + kk[it][2] * kk[it][2]);
-#pragma unroll 1
-  for (int it = 0; it < kPairItems; ++it) {
-    if (!__any((cbits >> it) & 1u)) continue;    // uniform
-    const bool cand = (cbits >> it) & 1u;
-    const int64_t i = base + (int64_t)it * kPairThreads + threadIdx.x;
-    double chi = chis[0], Wenv = wenv[0], tau = taus[0];
-    float gph = gphs[0];
-    uint64_t pid = pids[0];
-#pragma unroll
-    for (int j = 1; j < kPairItems; ++j)
-      if (it == j) { chi = chis[j]; Wenv = wenv[j]; tau = taus[j]; gph = gphs[j]; pid = pids[j]; }
-    if (cand && chi < 0.0) {
-      // candidate of the field-free envelope: the field at the moved position
-      float F[6];
-      field_at<float>(a.f, i, X[i], Y[i], Z[i], F);
-      chi = 0.0;
-      if (fields_finite<float>(F)) {
-        chi = chi_photon_f32(KX[i], KY[i], KZ[i], F);
-        if (isfinite(chi)) nrange += chi > a.rg.pair_hi;
-        else { ++nnan; chi = 0.0; }
-      } else {
-        ++nnan;
-      }
-    }
-    // with the local envelope (chi known) the first keep draw below the squeeze
-    // keeps the candidate without the net; otherwise the pair head gives W
-    const uint4 u0 = stream4(pid, a.seed, step, kPhotonThin, 0u);
-    const bool squeeze = !a.ret.on && unit<double>(u0.x) < kEnvSqueeze;
-    const bool need_w = cand && !squeeze;
-    bool ok;
-    const float lh = mlp_lnh_pair(Bn, chi, need_w, ok);
-    if (!cand) continue;
-    if (squeeze) { evbits |= 1u << it; continue; }
-    const float h = !(chi >= kPairChiMin) ? 0.f : (ok ? expf(lh) : h_pair<float, true>((float)chi, L, a.rg));
-    nfr += !ok;
-    const double W = kRateUnit * (double)(h * rcp<float>(gph));
-    nexc += W > Wenv || (!a.ret.on && W < kEnvSqueeze * Wenv);
-    double rem = a.dtd - tau / Wenv;
-    for (int k = 0;; ++k) {
-      const uint4 u = k == 0 ? u0 : stream4(pid, a.seed, step, kPhotonThin, (uint32_t)k);
-      if (unit<double>(u.x) * Wenv < W) { evbits |= 1u << it; break; }
-      ++nnull;
-      tau = -log(unit<double>(u.y));
-      if (!(tau <= Wenv * rem)) { settle(i, tau - Wenv * rem, gph); break; }
-      if (k + 1 >= kmax) { ++ncap; settle(i, tau - Wenv * rem, gph); break; }
-      rem -= tau / Wenv;
-    }
-  }
-  const uint32_t ev = (uint32_t)__popc(evbits);
-  count_lds(cnt, cChiRange, nrange);
-  count_lds(cnt, cNanChi, nnan);
-  count_lds(cnt, cPairs, ev);
-  count_lds(cnt, cThinned, nnull);
-  count_lds(cnt, cMlpFallbackRate, nfr);
-  count_lds(cnt, cCapped, ncap);
-  count_lds(cnt, cEnvelopeExceeded, nexc);
-  count_lds(cnt, cRetired, nret);
-  uint64_t packed = 0;
-#pragma unroll
-  for (int it = 0; it < kPairItems; ++it) packed |= (uint64_t)((evbits >> it) & 1u) << (16 * it);
-  uint64_t tot;
-  const uint64_t excl = block_exclusive64(packed, scan_s, &tot);
-  uint32_t level0[kPairItems], total = 0;
-#pragma unroll
-  for (int it = 0; it < kPairItems; ++it) {
-    level0[it] = total;
-    total += (uint32_t)((tot >> (16 * it)) & 0xFFFFu);
-  }
-  const uint64_t toff = tile_offset(tile, total, a.sc.status, a.counters, off_s);
-  uint32_t ndrop = 0;
-  for (int it = 0; it < kPairItems; ++it) {
-    if (!((evbits >> it) & 1u)) continue;
-    const int64_t i = base + (int64_t)it * kPairThreads + threadIdx.x;
-    const uint64_t pid = pids[it];
-    const float kx = KX[i], ky = KY[i], kz = KZ[i];
-    const float x = X[i], y = Y[i], z = Z[i];
-    const float gph = root<float>(kx * kx + ky * ky + kz * kz);
-    float F[6];
-    field_at<float>(a.f, i, x, y, z, F);
-    const double chi = chi_photon_f32(kx, ky, kz, F);
-    const uint4 u = stream4(pid, a.seed, step, kPhotonEvent, 0u);
-    float xh, omh;
-    sample_pair_half<float>(tab, (float)chi, unit<float>(u.x), unit<float>(u.y), xh, omh, a.rg);
-    const bool flip = u.y & 1u;
-    const float xe = flip ? omh : xh, xp = flip ? xh : omh;
-    const float ge = xe * gph, gpos = xp * gph;
-    const double te = -log(unit<double>(u.z)), tp = -log(unit<double>(u.w));
+// Three launches: k_photon_thin moves every photon, runs its optical depth down
+// at W_env and marks the candidates in a ballot mask (the other photons'
+// optical depths are final there); k_emit_index lists the candidates in photon
+// order; k_pair_cand takes them one per lane, so that the net runs on full
+// waves of candidates, and appends the pairs at their rank in candidate order,
+// i.e. in photon order as pair_tile does.
+constexpr int kPTThreads = 256, kPTItems = 4, kPTTile = kPTThreads * kPTItems;
+
+// optical depth of a photon at the end of the step; retired if it can no longer
+// convert before the end of the run
+__device__ __forceinline__ void photon_settle(const PairArgs<float> &a, int64_t i, double tn, float gph,
+                                              double t_left, uint32_t &nret) {
+  a.ph.tau[i] = tn;
+  if (retirable(a.ret, tn, gph, t_left)) {
     a.ph.id[i] = kDeadId;
-    const uint64_t rank = toff + level0[it] + (uint32_t)((excl >> (16 * it)) & 0xFFFFu);
-    const int64_t je = e0 + (int64_t)rank, jp = p0 + (int64_t)rank;
-    if (je < a.el.cap && jp < a.po.cap) {
-      const float kxh = kx / gph, kyh = ky / gph, kzh = kz / gph;
-      const float pe = sqrtf(fmaxf(ge * ge - 1.f, 0.f)), ppo = sqrtf(fmaxf(gpos * gpos - 1.f, 0.f));
-      ((float *)a.el.x)[je] = x; ((float *)a.el.y)[je] = y; ((float *)a.el.z)[je] = z;
-      ((float *)a.el.px)[je] = kxh * pe; ((float *)a.el.py)[je] = kyh * pe; ((float *)a.el.pz)[je] = kzh * pe;
-      a.el.tau[je] = te; a.el.id[je] = id0 + 2 * rank;
-      ((float *)a.po.x)[jp] = x; ((float *)a.po.y)[jp] = y; ((float *)a.po.z)[jp] = z;
-      ((float *)a.po.px)[jp] = kxh * ppo; ((float *)a.po.py)[jp] = kyh * ppo; ((float *)a.po.pz)[jp] = kzh * ppo;
-      a.po.tau[jp] = tp; a.po.id[jp] = id0 + 2 * rank + 1;
-    } else {
-      ndrop += 2;
-    }
-  }
-  count_lds(cnt, cDropped, ndrop);
-  const int64_t last = (n - 1) / kPairTile;
-  if ((int64_t)tile == last && threadIdx.x == 0) {
-    const int64_t tt = (int64_t)(toff + total);
-    *a.el.count = e0 + tt < a.el.cap ? e0 + tt : a.el.cap;
-    *a.po.count = p0 + tt < a.po.cap ? p0 + tt : a.po.cap;
-    *a.next_id = id0 + 2 * (uint64_t)tt;
-    if (a.killed) atomicAdd((unsigned long long *)a.killed, (unsigned long long)tt);
+    tally_photon(a.ret, (double)gph);
+    ++nret;
   }
 }
 
-__global__ __launch_bounds__(kPairThreads, 2) void k_pairs_mlp(PairArgs<float> a, const float *thB, int kmax) {
+// Envelope rate of a photon with energy gph at chi (chi unused with the field
+// bound); 0 below the pair threshold.
+__device__ __forceinline__ double photon_envelope(const PairArgs<float> &a, double chi, float gph) {
+  if (a.ret.on) return pair_rate_max(gph, a.ret);
+  return gph >= 2.f ? kRateUnit * (double)(h_pair_env((float)chi) * rcp<float>(gph)) : 0.0;
+}
+
+// FieldFree: the envelope of the retirement's field bound (no field gathered).
+template <bool FieldFree>
+__global__ __launch_bounds__(kPTThreads) void k_photon_thin(PairArgs<float> a, uint64_t *cmask) {
+  __shared__ uint32_t cnt_s[cNumCounters];
+  count_zero(cnt_s);
+  __syncthreads();
+  const int64_t n = *a.ph.count;
+  float *X = (float *)a.ph.x, *Y = (float *)a.ph.y, *Z = (float *)a.ph.z;
+  const float *KX = (const float *)a.ph.px, *KY = (const float *)a.ph.py, *KZ = (const float *)a.ph.pz;
+  const bool need_x = a.move || a.f.kind == QED_FIELD_GRID;
+  const uint64_t step = step_of(a.step, a.d_step);
+  const double t_left = time_left(a.ret, step, a.dtd);
+  uint32_t nrange = 0, nnan = 0, nret = 0;
+  for (int64_t tile = blockIdx.x; tile * kPTTile < n; tile += gridDim.x) {
+    // every load of the tile first (photon tile * kPTTile + it * kPTThreads + thread)
+    uint64_t pids[kPTItems];
+    float kk[kPTItems][3], xx[kPTItems][3];
+    double taus[kPTItems];
+#pragma unroll
+    for (int it = 0; it < kPTItems; ++it) {
+      const int64_t i = tile * kPTTile + (int64_t)it * kPTThreads + threadIdx.x;
+      const bool v = i < n, vx = v && need_x;
+      pids[it] = v ? a.ph.id[i] : kDeadId;
+      kk[it][0] = v ? KX[i] : 0.f; kk[it][1] = v ? KY[i] : 0.f; kk[it][2] = v ? KZ[i] : 0.f;
+      taus[it] = v ? a.ph.tau[i] : 0.0;
+      xx[it][0] = vx ? X[i] : 0.f; xx[it][1] = vx ? Y[i] : 0.f; xx[it][2] = vx ? Z[i] : 0.f;
+    }
+#pragma unroll
+    for (int it = 0; it < kPTItems; ++it) {
+      const int64_t i = tile * kPTTile + (int64_t)it * kPTThreads + threadIdx.x;
+      bool cand = false;
+      if (pids[it] != kDeadId) {             // converted photons not yet compacted are skipped
+        const float kx = kk[it][0], ky = kk[it][1], kz = kk[it][2];
+        const float gph = root<float>(kx * kx + ky * ky + kz * kz);
+        float x = xx[it][0], y = xx[it][1], z = xx[it][2];
+        if (a.move && gph > 0.f) {
+          const float vdt = rcp<float>(gph) * a.dt;
+          x += kx * vdt; y += ky * vdt; z += kz * vdt;
+          if (a.f.kind == QED_FIELD_GRID) {
+            wrap_coord<float>(x, box_len<float>(a.f, 0)); wrap_coord<float>(y, box_len<float>(a.f, 1));
+            wrap_coord<float>(z, box_len<float>(a.f, 2));
+          }
+          X[i] = x; Y[i] = y; Z[i] = z;
+        }
+        double We = 0.0;
+        if constexpr (FieldFree) {
+          We = photon_envelope(a, 0.0, gph);
+        } else {
+          // the local envelope needs chi: the field at the moved position
+          float F[6];
+          field_at<float>(a.f, i, x, y, z, F);
+          if (fields_finite<float>(F)) {
+            const double chi = chi_photon_f32(kx, ky, kz, F);
+            if (isfinite(chi)) {
+              nrange += chi > a.rg.pair_hi;
+              We = photon_envelope(a, chi, gph);
+            } else {
+              ++nnan;
+            }
+          } else {
+            ++nnan;
+          }
+        }
+        cand = We > 0.0 && taus[it] <= We * a.dtd;
+        if (!cand) photon_settle(a, i, taus[it] - We * a.dtd, gph, t_left, nret);
+      }
+      const uint64_t bal = __ballot(cand);
+      if ((threadIdx.x & 63) == 0 && i < n) cmask[i >> 6] = bal;   // lane 0 holds a multiple of 64
+    }
+  }
+  count_lds(cnt_s, cChiRange, nrange);
+  count_lds(cnt_s, cNanChi, nnan);
+  count_lds(cnt_s, cRetired, nret);
+  count_flush(cnt_s, a.counters);
+  // retired photons are dead too: the compaction of this species must not skip
+  if (threadIdx.x == 0 && a.killed && cnt_s[cRetired])
+    atomicAdd((unsigned long long *)a.killed, (unsigned long long)cnt_s[cRetired]);
+}
+
+constexpr int kPCThreads = 256;   // candidates per tile, one per thread
+
+__global__ __launch_bounds__(kPCThreads) void k_pair_cand(PairArgs<float> a, const int32_t *cidx,
+                                                          const int64_t *n_cand, const float *thB, int kmax) {
   __shared__ mlp::NetLdsI B_s;
   __shared__ float L_s[kPairNRate];
-  __shared__ uint64_t scan_s[16];
+  __shared__ uint32_t scan_s[16];
   __shared__ uint32_t tile_s;
   __shared__ uint64_t off_s;
   __shared__ int64_t hdr_s[4];
   __shared__ uint32_t cnt_s[cNumCounters];
   count_zero(cnt_s);
   if (threadIdx.x == 0) {
-    hdr_s[0] = *a.ph.count; hdr_s[1] = *a.el.count; hdr_s[2] = *a.po.count;
+    hdr_s[0] = *n_cand; hdr_s[1] = *a.el.count; hdr_s[2] = *a.po.count;
     hdr_s[3] = (int64_t)*a.next_id;
   }
   __syncthreads();
-  const int64_t n = hdr_s[0], e0 = hdr_s[1], p0 = hdr_s[2];
+  const int64_t nc = hdr_s[0], e0 = hdr_s[1], p0 = hdr_s[2];
   const uint64_t id0 = (uint64_t)hdr_s[3];
-  if (n == 0) return;
+  if (nc == 0) return;
   mlp::stage_net_infer(thB, mlp::kB, &B_s);
   for (int k = threadIdx.x; k < kPairNRate; k += blockDim.x) L_s[k] = a.L[k];
   const RowQ16 tab{a.q16, a.s0sc};
+  const float *X = (const float *)a.ph.x, *Y = (const float *)a.ph.y, *Z = (const float *)a.ph.z;
+  const float *KX = (const float *)a.ph.px, *KY = (const float *)a.ph.py, *KZ = (const float *)a.ph.pz;
+  const uint64_t step = step_of(a.step, a.d_step);
+  const double t_left = time_left(a.ret, step, a.dtd);
+  uint32_t nrange = 0, nnan = 0, nev = 0, nnull = 0, nfr = 0, ncap = 0, nexc = 0, nret = 0, ndrop = 0;
   while (true) {
     const uint32_t tile = next_tile(a.sc.ticket, &tile_s);   // its barriers also publish the staged net
-    if ((int64_t)tile * kPairTile >= n) break;
-    pair_tile_thin(a, B_s, tab, L_s, tile, scan_s, &off_s, n, e0, p0, id0, cnt_s, kmax);
+    if ((int64_t)tile * kPCThreads >= nc) break;
+    const int64_t r = (int64_t)tile * kPCThreads + threadIdx.x;
+    const bool valid = r < nc;
+    const int64_t i = valid ? (int64_t)cidx[r] : 0;
+    uint64_t pid = kDeadId;
+    float kx = 0.f, ky = 0.f, kz = 0.f, x = 0.f, y = 0.f, z = 0.f, gph = 0.f;
+    float F[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    double tau = 0.0, chi = 0.0, We = 0.0;
+    if (valid) {
+      pid = a.ph.id[i];
+      kx = KX[i]; ky = KY[i]; kz = KZ[i];
+      x = X[i]; y = Y[i]; z = Z[i];                 // moved by k_photon_thin
+      tau = a.ph.tau[i];                            // the optical depth before the step
+      gph = root<float>(kx * kx + ky * ky + kz * kz);
+      field_at<float>(a.f, i, x, y, z, F);
+      // (without the field bound k_photon_thin counted these already)
+      if (fields_finite<float>(F)) {
+        chi = chi_photon_f32(kx, ky, kz, F);
+        if (isfinite(chi)) {
+          nrange += a.ret.on && chi > a.rg.pair_hi;
+        } else {
+          nnan += a.ret.on;
+          chi = 0.0;
+        }
+      } else {
+        nnan += a.ret.on;
+      }
+      We = photon_envelope(a, chi, gph);           // the envelope k_photon_thin used
+    }
+    // with the local envelope the first keep draw below the squeeze keeps the
+    // candidate without the net; otherwise the pair head gives W
+    const uint4 u0 = stream4(pid, a.seed, step, kPhotonThin, 0u);
+    const bool squeeze = !a.ret.on && unit<double>(u0.x) < kEnvSqueeze;
+    const bool need_w = valid && !squeeze;
+    bool ok;
+    const float lh = mlp_lnh_pair(B_s, chi, need_w, ok);
+    bool ev = false;
+    if (valid) {
+      if (squeeze) {
+        ev = true;
+      } else {
+        const float h = !(chi >= kPairChiMin) ? 0.f : (ok ? expf(lh) : h_pair<float, true>((float)chi, L_s, a.rg));
+        nfr += !ok;
+        const double W = kRateUnit * (double)(h * rcp<float>(gph));
+        nexc += W > We || (!a.ret.on && W < kEnvSqueeze * We);
+        double rem = a.dtd - tau / We;
+        for (int k = 0;; ++k) {
+          const uint4 u = k == 0 ? u0 : stream4(pid, a.seed, step, kPhotonThin, (uint32_t)k);
+          if (unit<double>(u.x) * We < W) { ev = true; break; }
+          ++nnull;
+          tau = -log(unit<double>(u.y));
+          if (!(tau <= We * rem)) { photon_settle(a, i, tau - We * rem, gph, t_left, nret); break; }
+          if (k + 1 >= kmax) { ++ncap; photon_settle(a, i, tau - We * rem, gph, t_left, nret); break; }
+          rem -= tau / We;
+        }
+      }
+    }
+    nev += ev;
+    uint32_t total;
+    const uint32_t excl = block_exclusive(ev ? 1u : 0u, scan_s, &total);
+    const uint64_t toff = tile_offset(tile, total, a.sc.status, a.counters, &off_s);
+    if (ev) {
+      const uint4 u = stream4(pid, a.seed, step, kPhotonEvent, 0u);
+      float xh, omh;
+      sample_pair_half<float>(tab, (float)chi, unit<float>(u.x), unit<float>(u.y), xh, omh, a.rg);
+      const bool flip = u.y & 1u;
+      const float xe = flip ? omh : xh, xp = flip ? xh : omh;
+      const float ge = xe * gph, gpos = xp * gph;
+      const double te = -log(unit<double>(u.z)), tp = -log(unit<double>(u.w));
+      a.ph.id[i] = kDeadId;
+      const uint64_t rank = toff + excl;
+      const int64_t je = e0 + (int64_t)rank, jp = p0 + (int64_t)rank;
+      if (je < a.el.cap && jp < a.po.cap) {
+        const float kxh = kx / gph, kyh = ky / gph, kzh = kz / gph;
+        const float pe = sqrtf(fmaxf(ge * ge - 1.f, 0.f)), ppo = sqrtf(fmaxf(gpos * gpos - 1.f, 0.f));
+        ((float *)a.el.x)[je] = x; ((float *)a.el.y)[je] = y; ((float *)a.el.z)[je] = z;
+        ((float *)a.el.px)[je] = kxh * pe; ((float *)a.el.py)[je] = kyh * pe; ((float *)a.el.pz)[je] = kzh * pe;
+        a.el.tau[je] = te; a.el.id[je] = id0 + 2 * rank;
+        ((float *)a.po.x)[jp] = x; ((float *)a.po.y)[jp] = y; ((float *)a.po.z)[jp] = z;
+        ((float *)a.po.px)[jp] = kxh * ppo; ((float *)a.po.py)[jp] = kyh * ppo; ((float *)a.po.pz)[jp] = kzh * ppo;
+        a.po.tau[jp] = tp; a.po.id[jp] = id0 + 2 * rank + 1;
+      } else {
+        ndrop += 2;
+      }
+    }
+    if ((int64_t)tile == (nc - 1) / kPCThreads && threadIdx.x == 0) {
+      const int64_t tt = (int64_t)(toff + total);
+      *a.el.count = e0 + tt < a.el.cap ? e0 + tt : a.el.cap;
+      *a.po.count = p0 + tt < a.po.cap ? p0 + tt : a.po.cap;
+      *a.next_id = id0 + 2 * (uint64_t)tt;
+      if (a.killed) atomicAdd((unsigned long long *)a.killed, (unsigned long long)tt);
+    }
   }
+  count_lds(cnt_s, cChiRange, nrange);
+  count_lds(cnt_s, cNanChi, nnan);
+  count_lds(cnt_s, cPairs, nev);
+  count_lds(cnt_s, cThinned, nnull);
+  count_lds(cnt_s, cMlpFallbackRate, nfr);
+  count_lds(cnt_s, cCapped, ncap);
+  count_lds(cnt_s, cEnvelopeExceeded, nexc);
+  count_lds(cnt_s, cRetired, nret);
+  count_lds(cnt_s, cDropped, ndrop);
   count_flush(cnt_s, a.counters);
-  // retired photons are dead too: the compaction of this species must not skip
   if (threadIdx.x == 0 && a.killed && cnt_s[cRetired])
     atomicAdd((unsigned long long *)a.killed, (unsigned long long)cnt_s[cRetired]);
 }
@@ -1976,10 +1982,10 @@ hipError_t launch_emit(qed_ctx *c, const qed_species_t *lep, const qed_species_t
   if (e != hipSuccess) return e;
   const ScanDev isc{c->d_ticket + 1, c->d_status + c->status_len};
   if (wide)
-    hipLaunchKernelGGL(k_emit_index<8>, dim3((unsigned)etiles), dim3(kEIThreads), 0, st, c->em_mask, lep->count,
+    hipLaunchKernelGGL((k_emit_index<8, EmIdx>), dim3((unsigned)etiles), dim3(kEIThreads), 0, st, c->em_mask, lep->count,
                      c->em_idx, c->d_n_emit, isc, c->d_counters);
   else
-    hipLaunchKernelGGL(k_emit_index<1>, dim3((unsigned)etiles), dim3(kEIThreads), 0, st, c->em_mask, lep->count,
+    hipLaunchKernelGGL((k_emit_index<1, EmIdx>), dim3((unsigned)etiles), dim3(kEIThreads), 0, st, c->em_mask, lep->count,
                      c->em_idx, c->d_n_emit, isc, c->d_counters);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const ScanDev sc{c->d_ticket, c->d_status};
@@ -2017,8 +2023,11 @@ hipError_t launch_pairs(qed_ctx *c, const qed_fields_t *f, const qed_species_t *
                         const qed_species_t *el, const qed_species_t *po, double dt, int64_t step,
                         hipStream_t st) {
   const int64_t ntiles = (ph->capacity + kPairTile - 1) / kPairTile;
-  hipError_t e = zero_scan(c, ntiles, st);
-  if (e != hipSuccess) return e;
+  const bool thin = (c->params.flags & QED_FLAG_SURROGATE) && ph->dtype == QED_F32;
+  if (!thin) {   // (the thinned pass clears its two scans itself)
+    hipError_t e = zero_scan(c, ntiles, st);
+    if (e != hipSuccess) return e;
+  }
   const ScanDev sc{c->d_ticket, c->d_status};
   const int move = (c->params.flags & QED_FLAG_STATIC_PHOTONS) ? 0 : 1;
   const int64_t wgs = (int64_t)c->n_cu * 4;   // persistent, tiles from the ticket
@@ -2030,10 +2039,36 @@ hipError_t launch_pairs(qed_ctx *c, const qed_fields_t *f, const qed_species_t *
                       c->pair_S64, c->pair_q16, c->pair_s0sc, (float)dt, dt, move, c->d_next_id,
                       c->params.seed, (uint64_t)step, step < 0 ? c->d_step : nullptr, sc, c->d_counters, killed, c->range,
                       retire_dev(c)};
-    if (c->params.flags & QED_FLAG_SURROGATE)
-      hipLaunchKernelGGL(k_pairs_mlp, dim3(grid), dim3(kPairThreads), 0, st, a, c->mlp_theta[1], c->params.kmax);
-    else
+    if (thin) {
+      // thinning pass, candidate list, candidates (region 0 of the scan state
+      // for the candidates' appends, region 1 for the list)
+      const bool wide = ph->capacity >= kEIWideFrom;
+      const int64_t eit = wide ? ei_tile<8>() : ei_tile<1>();
+      const int64_t etiles = (ph->capacity + eit - 1) / eit;
+      const int64_t ctiles = (ph->capacity + kPCThreads - 1) / kPCThreads;
+      const int64_t n0 = ctiles + 1, n1 = etiles + 1, nz = n0 > n1 ? n0 : n1;
+      if (nz > c->status_len || ph->capacity > c->cand_cap) return hipErrorInvalidValue;
+      hipLaunchKernelGGL(k_zero_scan2, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, st, c->d_ticket,
+                         c->d_status, c->status_len, n0, n1);
+      const int64_t ttiles = (ph->capacity + kPTTile - 1) / kPTTile, twgs = (int64_t)c->n_cu * 8;
+      const unsigned tgrid = (unsigned)(ttiles < twgs ? ttiles : twgs);
+      if (a.ret.on)
+        hipLaunchKernelGGL(k_photon_thin<true>, dim3(tgrid), dim3(kPTThreads), 0, st, a, c->cand_mask);
+      else
+        hipLaunchKernelGGL(k_photon_thin<false>, dim3(tgrid), dim3(kPTThreads), 0, st, a, c->cand_mask);
+      const ScanDev isc{c->d_ticket + 1, c->d_status + c->status_len};
+      if (wide)
+        hipLaunchKernelGGL((k_emit_index<8, int32_t>), dim3((unsigned)etiles), dim3(kEIThreads), 0, st, c->cand_mask,
+                           ph->count, c->cand_idx, c->d_n_cand, isc, c->d_counters);
+      else
+        hipLaunchKernelGGL((k_emit_index<1, int32_t>), dim3((unsigned)etiles), dim3(kEIThreads), 0, st, c->cand_mask,
+                           ph->count, c->cand_idx, c->d_n_cand, isc, c->d_counters);
+      const int64_t cwgs = (int64_t)c->n_cu * 4;
+      hipLaunchKernelGGL(k_pair_cand, dim3((unsigned)(ctiles < cwgs ? ctiles : cwgs)), dim3(kPCThreads), 0, st, a,
+                         c->cand_idx, c->d_n_cand, c->mlp_theta[1], c->params.kmax);
+    } else {
       hipLaunchKernelGGL(k_pairs_f32, dim3(grid), dim3(kPairThreads), 0, st, a);
+    }
   } else {
     PairArgs<double> a{dev_species(ph), dev_species(el), dev_species(po), dev_fields(f), c->pair_L64,
                        c->pair_S64, c->pair_q16, c->pair_s0sc, dt, dt, move, c->d_next_id,
