@@ -149,6 +149,9 @@ typedef struct {
   int64_t thinned;             /* surrogate path: candidate events not kept (thinning) */
   int64_t envelope_exceeded;   /* surrogate path: a rate outside [0.89, 1] x its envelope (must be 0) */
   int64_t retired;             /* photons retired into the tally (qed_set_retirement) */
+  int64_t box_fallback;        /* lepton-pass workgroups on a grid whose stencil box did
+                                  not fit in LDS (they gather from global memory: a
+                                  sign that the species needs qed_sort_by_cell) */
 } qed_counters_t;
 
 /* Surrogate training (not part of the paper; see qed_surrogate_train). */

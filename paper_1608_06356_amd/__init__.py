@@ -57,7 +57,7 @@ class qed_counters_t(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "events", "photons", "rejected", "capped", "pairs", "dropped", "chi_out_of_range",
         "nan_chi", "scan_timeouts", "compacted", "mlp_fallback_xi", "mlp_fallback_rate", "thinned",
-        "envelope_exceeded", "retired")]
+        "envelope_exceeded", "retired", "box_fallback")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

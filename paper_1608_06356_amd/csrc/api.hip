@@ -573,6 +573,8 @@ int qed_surrogate_grad(qed_ctx_t c, int net, const float *x, const float *t, con
   return e == hipSuccess ? QED_OK : hip_fail(c, e, "surrogate_grad");
 }
 
+static_assert(sizeof(qed_counters_t) == sizeof(int64_t) * qed::cNumCounters, "counter layout");
+
 int qed_get_status(qed_ctx_t c, qed_counters_t *out, void *st) {
   if (!c || !out) return QED_ERR_ARG;
   unsigned long long h[qed::cNumCounters];

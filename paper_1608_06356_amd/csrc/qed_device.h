@@ -44,7 +44,7 @@ enum Purpose : uint32_t { kInitTau = 0, kLeptonEvent = 1, kPhotonEvent = 2, kLep
 // counters (layout of qed_counters_t)
 enum Counter { cEvents = 0, cPhotons, cRejected, cCapped, cPairs, cDropped, cChiRange,
                cNanChi, cScanTimeout, cCompacted, cMlpFallbackXi, cMlpFallbackRate, cThinned,
-               cEnvelopeExceeded, cRetired, cNumCounters };
+               cEnvelopeExceeded, cRetired, cBoxFallback, cNumCounters };
 
 // ------------------------------------------------------------------ Philox
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of two 32x32->64
@@ -94,13 +94,33 @@ __device__ __forceinline__ double chi_lepton(double px, double py, double pz,
   return sqrt(g2 * (ux * ux + uy * uy + uz * uz) + ne * ne) * kInvES;
 }
 
+// Float64 square root and reciprocal from the float32 hardware estimates
+// (relative error below 2^-22) refined by two float64 Newton steps, which
+// square the error each time: below 1e-15 relative, for a fraction of the
+// instructions of the correctly rounded float64 sequences.  Arguments outside
+// [1e-30, 1e30] (float32 range of the estimate) take those sequences.
+__device__ __forceinline__ double sqrt_nr(double s) {
+  if (!(s >= 1e-30 && s <= 1e30)) return sqrt(s);
+  double y = (double)__builtin_amdgcn_rsqf((float)s);      // 1 / sqrt(s)
+  y = fma(0.5 * y, fma(-s * y, y, 1.0), y);
+  y = fma(0.5 * y, fma(-s * y, y, 1.0), y);
+  return s * y;
+}
+__device__ __forceinline__ double rcp_nr(double d) {
+  if (!(d >= 1e-30 && d <= 1e30)) return 1.0 / d;
+  double y = (double)__builtin_amdgcn_rcpf((float)d);
+  y = fma(y, fma(-d, y, 1.0), y);
+  y = fma(y, fma(-d, y, 1.0), y);
+  return y;
+}
+
 // The same expression for the float32 step, whose inputs (p, E, B) are float32
 // and therefore exact in float64: every operation is float64.  Only 1/|p|
 // starts from the float32 reciprocal square root, refined by two float64 Newton
 // steps (relative error below 1e-15), which saves the float64 division there;
-// gamma, 1/(gamma^2 (1 + beta)) and the final root are float64.  Where E and
-// -n x B nearly cancel, n must be exact to float64 rounding: it is.  |p|^2 below
-// 1e-30 (float32 underflow of the estimate) takes the form above.
+// gamma, 1/(gamma^2 (1 + beta)) and the final root likewise (sqrt_nr, rcp_nr).
+// Where E and -n x B nearly cancel, n must be exact to float64 rounding: it is.
+// |p|^2 below 1e-30 (float32 underflow of the estimate) takes the form above.
 __device__ __forceinline__ double chi_lepton_f32(float px, float py, float pz, const float F[6]) {
   const double dx = px, dy = py, dz = pz;
   const double p2 = dx * dx + dy * dy + dz * dz;
@@ -111,17 +131,17 @@ __device__ __forceinline__ double chi_lepton_f32(float px, float py, float pz, c
   const double nx = dx * y, ny = dy * y, nz = dz * y;
   const double ex = F[0], ey = F[1], ez = F[2], bx = F[3], by = F[4], bz = F[5];
   const double cx = ny * bz - nz * by, cy = nz * bx - nx * bz, cz = nx * by - ny * bx;  // n x B
-  const double g2 = 1.0 + p2, g = sqrt(g2);
-  const double f = 1.0 / (g * (g + p2 * y));      // 1 / (gamma^2 (1 + beta))
+  const double g2 = 1.0 + p2, g = sqrt_nr(g2);
+  const double f = rcp_nr(g * (g + p2 * y));      // 1 / (gamma^2 (1 + beta))
   const double wx = (ex + cx) - cx * f, wy = (ey + cy) - cy * f, wz = (ez + cz) - cz * f;
   const double ux = ny * wz - nz * wy, uy = nz * wx - nx * wz, uz = nx * wy - ny * wx;  // n x w
   const double ne = nx * ex + ny * ey + nz * ez;
-  return sqrt(g2 * (ux * ux + uy * uy + uz * uz) + ne * ne) * kInvES;
+  return sqrt_nr(g2 * (ux * ux + uy * uy + uz * uz) + ne * ne) * kInvES;
 }
 
 // Eq. (3) for the float32 step (inputs k, E, B float32, exact in float64), all
 // in float64 like chi_lepton_f32: k^ from the refined reciprocal square root,
-// gamma_ph = |k| = k^2 / |k|, E + k^ x B and the root in float64.
+// gamma_ph = |k| = k^2 / |k|, E + k^ x B and the (refined) root in float64.
 __device__ __forceinline__ double chi_photon_f32(float kx, float ky, float kz, const float F[6]) {
   const double dx = kx, dy = ky, dz = kz;
   const double k2 = dx * dx + dy * dy + dz * dz;
@@ -134,7 +154,7 @@ __device__ __forceinline__ double chi_photon_f32(float kx, float ky, float kz, c
   const double wx = (double)F[0] + (ny * bz - nz * by), wy = (double)F[1] + (nz * bx - nx * bz),
                wz = (double)F[2] + (nx * by - ny * bx);
   const double ux = ny * wz - nz * wy, uy = nz * wx - nx * wz, uz = nx * wy - ny * wx;
-  return k2 * y * sqrt(ux * ux + uy * uy + uz * uz) * kInvES;
+  return k2 * y * sqrt_nr(ux * ux + uy * uy + uz * uz) * kInvES;
 }
 
 // Eq. (3) with |v| = 1: chi_ph = gamma_ph / E_S |k^ x (E + k^ x B)|.

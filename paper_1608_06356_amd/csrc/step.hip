@@ -506,13 +506,18 @@ __device__ void append_photons(const SpeciesDev &ph, const RetireDev &ret, uint6
 
 // ========================================================= gather / push
 // A pure streaming pass with no dependency between workgroups.  Workgroups are
-// dispatched round-robin over the 8 XCDs; block b works on tile
-// (b % 8) * tiles_per_xcd + b / 8, so each XCD sweeps a contiguous eighth of
-// the particle array and its L2 holds the grid around those particles.  A
+// dispatched round-robin over the 8 XCDs; the tiles are dealt to the XCDs in
+// chunks of kGPChunk consecutive tiles, chunk c to XCD c % 8, so that an XCD's
+// L2 holds the grid around the particles of the chunk it works on (consecutive
+// particles are close after a cell sort) while every part of the array, such
+// as the unsorted particles appended since the last sort, is spread over all
+// eight XCDs.  Block b = 8 k + x works on tile
+// ((k / kGPChunk) * 8 + x) * kGPChunk + k % kGPChunk.  A
 // particle whose optical depth runs out within the step sets its bit in a
 // ballot mask and writes the fields, chi, rate and remaining time of its first
 // event to its own slot; k_emit_index turns the mask into the ordered list.
 constexpr int kXcds = 8;
+constexpr int64_t kGPChunk = 32;
 
 // Emitter record, written by the emitter to its own slot and read once by
 // k_emit: what the event loop needs beyond the particle's id.
@@ -532,7 +537,6 @@ struct GPArgs {
   double dtd;
   uint64_t *mask;        // one bit per particle
   EmRec<R> *rec;         // slot = particle index
-  int64_t tpx;           // tiles per XCD
   unsigned long long *counters;
   int gen;               // 0: optical depth; 1: method I with sub-steps; 2: method I, one step
   uint32_t seed;
@@ -577,12 +581,11 @@ template <typename R, int FK, bool M1> constexpr int gp_waves() {
 template <typename R, int FK, bool M1, bool Thin = false>
 __global__ __launch_bounds__(kGPThreads, (gp_waves<R, FK, M1>())) void k_gather_push(GPArgs<R> a) {
   __shared__ R lnh_s[kRadNChi];
-  // tiles per XCD for the particles present (the grid is sized by the capacity;
-  // dealing by the count keeps all eight XCDs busy when the species is not full)
+  // (the grid is sized by the capacity: blocks beyond the particles present
+  // return, and they are the last ones dispatched)
   const int64_t n = *a.sp.count;
-  const int64_t tpx = ((n + kGPTile - 1) / kGPTile + kXcds - 1) / kXcds;
-  if ((int64_t)(blockIdx.x / kXcds) >= tpx) return;
-  const int64_t tile = (int64_t)(blockIdx.x % kXcds) * tpx + blockIdx.x / kXcds;
+  const int64_t k = blockIdx.x / kXcds;
+  const int64_t tile = ((k / kGPChunk) * kXcds + blockIdx.x % kXcds) * kGPChunk + k % kGPChunk;
   const int64_t base = tile * kGPTile;
   if (base >= n) return;
   // the tile's slices of the arrays (uniform bases, 32-bit thread offsets)
@@ -613,8 +616,9 @@ __global__ __launch_bounds__(kGPThreads, (gp_waves<R, FK, M1>())) void k_gather_
     tsc_setup<R>(f, x, y, z, j, w);      // dead lanes hold x = 0: harmless, unused
     if (stage_box(box_s, f, live, j, rel, pit)) {   // its barriers also publish lnh_s
       if (live) gather_box<R>(box_s, rel, pit, w, F);
-    } else if (live) {
-      gather_global<R>(f, j, w, F);
+    } else {
+      if (live) gather_global<R>(f, j, w, F);
+      if (threadIdx.x == 0) atomicAdd(&a.counters[cBoxFallback], 1ull);
     }
     if (live && !fields_finite<R>(F)) { live = false; nnan = 1; }   // skipped and counted
   } else {
@@ -1934,14 +1938,15 @@ hipError_t launch_gather_push(qed_ctx *c, const qed_fields_t *f, const qed_speci
   const int gen = gen_mode(c);
   const int64_t *dstep = step < 0 ? c->d_step : nullptr;
   const int64_t ntiles = (sp->capacity + kGPTile - 1) / kGPTile;
-  const int64_t tpx = (ntiles + kXcds - 1) / kXcds;
-  const unsigned grid = (unsigned)(tpx * kXcds);
+  // every tile below ntiles has its block: chunks per XCD times the chunk times 8
+  const int64_t cpx = ((ntiles + kGPChunk - 1) / kGPChunk + kXcds - 1) / kXcds;
+  const unsigned grid = (unsigned)(cpx * kGPChunk * kXcds);
   const bool use_mlp = (c->params.flags & QED_FLAG_SURROGATE) && sp->dtype == QED_F32;
   if (use_mlp) {
     // surrogate path: the same pass with the rate envelope (thinning); the
     // emission pass evaluates the nets at the candidates
     GPArgs<float> a{dev_species(sp), dev_fields(f), c->rad_lnh32, (float)charge, (float)dt, dt, c->em_mask,
-                    (EmRec<float> *)c->em_rec, tpx, c->d_counters, 0, c->params.seed, (uint64_t)step, dstep, c->range};
+                    (EmRec<float> *)c->em_rec, c->d_counters, 0, c->params.seed, (uint64_t)step, dstep, c->range};
     if (f->kind == QED_FIELD_GRID)
       hipLaunchKernelGGL((k_gather_push<float, QED_FIELD_GRID, false, true>), dim3(grid), dim3(kGPThreads), 0, st, a);
     else if (f->kind == QED_FIELD_UNIFORM)
@@ -1951,11 +1956,11 @@ hipError_t launch_gather_push(qed_ctx *c, const qed_fields_t *f, const qed_speci
                          st, a);
   } else if (sp->dtype == QED_F32) {
     GPArgs<float> a{dev_species(sp), dev_fields(f), c->rad_lnh32, (float)charge, (float)dt, dt, c->em_mask,
-                    (EmRec<float> *)c->em_rec, tpx, c->d_counters, gen, c->params.seed, (uint64_t)step, dstep, c->range};
+                    (EmRec<float> *)c->em_rec, c->d_counters, gen, c->params.seed, (uint64_t)step, dstep, c->range};
     launch_gp_kind<float>(a, f->kind, grid, st);
   } else {
     GPArgs<double> a{dev_species(sp), dev_fields(f), c->rad_lnh64, (double)charge, dt, dt, c->em_mask,
-                     (EmRec<double> *)c->em_rec, tpx, c->d_counters, gen, c->params.seed, (uint64_t)step, dstep, c->range};
+                     (EmRec<double> *)c->em_rec, c->d_counters, gen, c->params.seed, (uint64_t)step, dstep, c->range};
     launch_gp_kind<double>(a, f->kind, grid, st);
   }
   return hipGetLastError();
