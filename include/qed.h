@@ -252,7 +252,18 @@ QED_API int qed_emit_photons(qed_ctx_t ctx, qed_species_t *leptons, qed_species_
    (zero below gamma_ph = 2), optical depth; on an event xi = eps_e/eps_ph from the
    half-spectrum of Eq. (6), the electron gets xi gamma_ph and the positron the rest,
    both along the photon, appended at the same rank; the photon's id becomes
-   QED_DEAD_ID (remove it with qed_compact). */
+   QED_DEAD_ID (remove it with qed_compact).  Pairs are ranked in photon order.
+   Float32 species: a streaming launch takes every photon's step and marks the
+   photons with an event in a ballot mask, a second lists them in photon order
+   and a third makes their pairs (then a one-thread launch advances the counts);
+   float64 species: one launch.  With QED_FLAG_SURROGATE (float32) the optical
+   depth runs down at the envelope alpha E_S h_pair_env(chi_ph) / gamma_ph, or,
+   after qed_set_retirement, at the largest pair rate W_max(gamma_ph) the field
+   bound allows (no field gathered), and each candidate event is kept with
+   probability W / W_env, W from the pair head of the rate net (Poisson
+   thinning; the table where the net's output fails its check).  The event mask
+   and list are sized for the photon capacity on the first call with a larger
+   capacity (allocation: not under graph capture). */
 QED_API int qed_create_pairs(qed_ctx_t ctx, const qed_fields_t *fields, qed_species_t *photons,
                      qed_species_t *electrons, qed_species_t *positrons, double dt,
                      int64_t step, void *stream);

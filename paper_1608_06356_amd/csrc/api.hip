@@ -108,8 +108,9 @@ void free_cands(qed_ctx *c) {
   c->cand_cap = 0;
 }
 
-// Candidate mask and list of the surrogate pair pass for photon species of up
-// to n particles.  Allocates, so not under graph capture.
+// Event (or, on the surrogate path, candidate) mask and list of the float32
+// pair pass for photon species of up to n particles.  Allocates, so not under
+// graph capture.
 int ensure_cands(qed_ctx *c, int64_t n) {
   if (n <= c->cand_cap) return QED_OK;
   hipError_t e = hipDeviceSynchronize();
@@ -386,8 +387,7 @@ int qed_create_pairs(qed_ctx_t c, const qed_fields_t *f, qed_species_t *ph, qed_
   if (step < 0 && step != QED_STEP_DEVICE) return fail(c, QED_ERR_ARG, "step must be >= 0 or QED_STEP_DEVICE");
   if (!c->tables_ready) return fail(c, QED_ERR_STATE, "tables not built");
   if ((r = ensure_scan(c, ph->capacity))) return r;
-  if ((c->params.flags & QED_FLAG_SURROGATE) && ph->dtype == QED_F32 && (r = ensure_cands(c, ph->capacity)))
-    return r;
+  if (ph->dtype == QED_F32 && (r = ensure_cands(c, ph->capacity))) return r;
   hipError_t e = qed::launch_pairs(c, f, ph, el, po, dt, step, S(st));
   return e == hipSuccess ? QED_OK : hip_fail(c, e, "create_pairs");
 }

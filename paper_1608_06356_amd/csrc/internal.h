@@ -56,8 +56,9 @@ struct qed_ctx {
   int em_charge = 0;
   double em_dt = 0.0;
 
-  // candidate events of the surrogate pair pass: ballot mask and ordered list
-  // over the photons (sized for the largest photon species)
+  // photons of the float32 pair pass with an event (surrogate path: a
+  // candidate event) this step: ballot mask and ordered list (sized for the
+  // largest photon species)
   int64_t cand_cap = 0;
   uint64_t *cand_mask = nullptr;
   int32_t *cand_idx = nullptr;

@@ -687,7 +687,9 @@ __global__ __launch_bounds__(kGPThreads, (gp_waves<R, FK, M1>())) void k_gather_
 // 64-bit words; popcounts are scanned across the workgroup and across tiles
 // (decoupled look-back), and every set bit writes its particle index at its
 // rank.  Large species take W = 8 (tiles of 131072 particles, a short look-back
-// chain), small ones W = 1 (more workgroups).
+// chain), small ones W = 1 (more workgroups).  Persistent workgroups take the
+// tiles of the particles present from the ticket, so that a launch sized for a
+// large capacity costs little when the species holds few particles.
 constexpr int kEIThreads = 256;
 template <int W> constexpr int64_t ei_tile() { return (int64_t)kEIThreads * W * 64; }
 constexpr int64_t kEIWideFrom = (int64_t)1 << 22;   // capacity from which W = 8
@@ -700,42 +702,44 @@ __global__ __launch_bounds__(kEIThreads) void k_emit_index(const uint64_t *mask,
   __shared__ uint32_t scan_s[16];
   __shared__ uint32_t tile_s;
   __shared__ uint64_t off_s;
-  const uint32_t tile = next_tile(sc.ticket, &tile_s);
   const int64_t n = *count;
-  const int64_t base = (int64_t)tile * ei_tile<W>();
-  if (base >= n) {
-    if (tile == 0 && threadIdx.x == 0) *n_emit = 0;
-    return;
-  }
-  const int64_t w0 = (base >> 6) + (int64_t)threadIdx.x * W;
-  uint64_t m[W];
-  uint32_t c = 0;
-#pragma unroll
-  for (int k = 0; k < W; ++k) {
-    const int64_t w = w0 + k;
-    m[k] = (w << 6) < n ? mask[w] : 0ull;
-    const int64_t valid = n - (w << 6);
-    if (valid < 64 && valid > 0) m[k] &= (1ull << valid) - 1ull;
-    c += (uint32_t)__popcll(m[k]);
-  }
-  uint32_t total;
-  const uint32_t off = block_exclusive(c, scan_s, &total);
-  const uint64_t toff = tile_offset(tile, total, sc.status, counters, &off_s);
-  uint64_t r = toff + off;
-#pragma unroll
-  for (int k = 0; k < W; ++k) {
-    uint64_t b = m[k];
-    const int32_t wb = (int32_t)((w0 + k) << 6);
-    int32_t slot = wb;   // records of a mask word are packed from its base (rec_slot)
-    while (b) {
-      const int32_t p = wb + (__ffsll((long long)b) - 1);
-      if constexpr (sizeof(Idx) == sizeof(EmIdx)) em_idx[r++] = EmIdx{p, slot++};
-      else em_idx[r++] = p;
-      b &= b - 1ull;
+  while (true) {
+    const uint32_t tile = next_tile(sc.ticket, &tile_s);
+    const int64_t base = (int64_t)tile * ei_tile<W>();
+    if (base >= n) {
+      if (tile == 0 && threadIdx.x == 0) *n_emit = 0;
+      return;
     }
+    const int64_t w0 = (base >> 6) + (int64_t)threadIdx.x * W;
+    uint64_t m[W];
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      const int64_t w = w0 + k;
+      m[k] = (w << 6) < n ? mask[w] : 0ull;
+      const int64_t valid = n - (w << 6);
+      if (valid < 64 && valid > 0) m[k] &= (1ull << valid) - 1ull;
+      c += (uint32_t)__popcll(m[k]);
+    }
+    uint32_t total;
+    const uint32_t off = block_exclusive(c, scan_s, &total);
+    const uint64_t toff = tile_offset(tile, total, sc.status, counters, &off_s);
+    uint64_t r = toff + off;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      uint64_t b = m[k];
+      const int32_t wb = (int32_t)((w0 + k) << 6);
+      int32_t slot = wb;   // records of a mask word are packed from its base (rec_slot)
+      while (b) {
+        const int32_t p = wb + (__ffsll((long long)b) - 1);
+        if constexpr (sizeof(Idx) == sizeof(EmIdx)) em_idx[r++] = EmIdx{p, slot++};
+        else em_idx[r++] = p;
+        b &= b - 1ull;
+      }
+    }
+    const int64_t last = (n - 1) / ei_tile<W>();
+    if ((int64_t)tile == last && threadIdx.x == 0) *n_emit = (int64_t)(toff + total);
   }
-  const int64_t last = (n - 1) / ei_tile<W>();
-  if ((int64_t)tile == last && threadIdx.x == 0) *n_emit = (int64_t)(toff + total);
 }
 
 // ================================================================ emit
@@ -1196,7 +1200,7 @@ __device__ __forceinline__ bool photon_rate(const PairArgs<R> &a, const R *L, in
   return photon_rate_at<R>(a, L, F, kx, ky, kz, gph, chi, W);
 }
 
-// One tile of kPairTile photons, kPairItems per thread (photon base + it *
+// Float64 pair pass.  One tile of kPairTile photons, kPairItems per thread (photon base + it *
 // kPairThreads + thread, so that a pass over `it` is coalesced).  Pass 1 moves
 // every photon and decides its event; the offsets of the pairs follow the photon
 // index through one scan of per-level counts packed 16 bits per level; pass 2
@@ -1211,40 +1215,22 @@ __device__ void pair_tile(const PairArgs<R> &a, const Tab &tab, const R *L, uint
   const R *KX = (const R *)a.ph.px, *KY = (const R *)a.ph.py, *KZ = (const R *)a.ph.pz;
   uint32_t evbits = 0, nrange = 0, nnan = 0, nret = 0;
   const double t_left = time_left(a.ret, step_of(a.step, a.d_step), a.dtd);
-  // float32: every load of the thread's photons first, so that their latencies
-  // overlap (float64 keeps them per photon: the registers would halve its
-  // occupancy); positions are needed to move the photon or to gather from a grid
-  constexpr bool kAhead = sizeof(R) == 4;
-  const bool need_x = a.move || a.f.kind == QED_FIELD_GRID, pp = kAhead && a.f.kind == QED_FIELD_PER_PARTICLE;
+  // loads per photon (all of a thread's photons at once would halve the
+  // occupancy in float64); positions are needed to move the photon or to
+  // gather from a grid
+  const bool need_x = a.move || a.f.kind == QED_FIELD_GRID;
   uint64_t pids[kPairItems];
-  R kk[kPairItems][3], xx[kPairItems][3], Fp[kPairItems][6];
+  R kk[kPairItems][3], xx[kPairItems][3];
   double taus[kPairItems];
-#pragma unroll
-  for (int it = 0; it < kPairItems && kAhead; ++it) {
-    const int64_t i = base + (int64_t)it * kPairThreads + threadIdx.x;
-    const bool v = i < n;
-    pids[it] = v ? a.ph.id[i] : kDeadId;
-    kk[it][0] = v ? KX[i] : (R)0; kk[it][1] = v ? KY[i] : (R)0; kk[it][2] = v ? KZ[i] : (R)0;
-    taus[it] = v ? a.ph.tau[i] : 0.0;
-    const bool vx = v && need_x;
-    xx[it][0] = vx ? X[i] : (R)0; xx[it][1] = vx ? Y[i] : (R)0; xx[it][2] = vx ? Z[i] : (R)0;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      Fp[it][c] = (v && pp) ? (R)a.f.pE[c][i] : (R)0;
-      Fp[it][3 + c] = (v && pp) ? (R)a.f.pB[c][i] : (R)0;
-    }
-  }
 #pragma unroll
   for (int it = 0; it < kPairItems; ++it) {
     const int64_t i = base + (int64_t)it * kPairThreads + threadIdx.x;
-    if constexpr (!kAhead) {
-      const bool v = i < n;
-      pids[it] = v ? a.ph.id[i] : kDeadId;
-      if (pids[it] != kDeadId) {
-        kk[it][0] = KX[i]; kk[it][1] = KY[i]; kk[it][2] = KZ[i];
-        taus[it] = a.ph.tau[i];
-        xx[it][0] = need_x ? X[i] : (R)0; xx[it][1] = need_x ? Y[i] : (R)0; xx[it][2] = need_x ? Z[i] : (R)0;
-      }
+    const bool v = i < n;
+    pids[it] = v ? a.ph.id[i] : kDeadId;
+    if (pids[it] != kDeadId) {
+      kk[it][0] = KX[i]; kk[it][1] = KY[i]; kk[it][2] = KZ[i];
+      taus[it] = a.ph.tau[i];
+      xx[it][0] = need_x ? X[i] : (R)0; xx[it][1] = need_x ? Y[i] : (R)0; xx[it][2] = need_x ? Z[i] : (R)0;
     }
     // photons converted earlier and not yet compacted away are skipped
     if (pids[it] == kDeadId) continue;
@@ -1266,12 +1252,7 @@ __device__ void pair_tile(const PairArgs<R> &a, const Tab &tab, const R *L, uint
     }
     double chi, W;
     R F[6];
-    if (pp) {
-#pragma unroll
-      for (int c = 0; c < 6; ++c) F[c] = Fp[it][c];
-    } else {
-      field_at<R>(a.f, i, x, y, z, F);
-    }
+    field_at<R>(a.f, i, x, y, z, F);
     if (photon_rate_at<R>(a, L, F, kx, ky, kz, gph, chi, W)) {
       nrange += chi > a.rg.pair_hi;
     } else {
@@ -1605,37 +1586,159 @@ __global__ __launch_bounds__(kPCThreads) void k_pair_cand(PairArgs<float> a, con
     atomicAdd((unsigned long long *)a.killed, (unsigned long long)cnt_s[cRetired]);
 }
 
-// three waves per SIMD (at most 168 registers): its four photons per thread
-// otherwise take 172 and two waves
-__global__ __launch_bounds__(kPairThreads, 3) void k_pairs_f32(PairArgs<float> a) {
+// Table pair pass (float32) in three launches like the surrogate pass:
+// k_photon_table runs every photon's step (move, field, chi_ph, W_pair from
+// the table, optical depth) and marks the photons whose optical depth runs out
+// within the step in a ballot mask; k_emit_index lists them in photon order;
+// k_pair_events makes the pair of each listed photon at its position in the
+// list, which is its rank in photon order as pair_tile ranks them, and
+// k_pair_commit advances the counts.  The streaming kernel has no scan, so its
+// workgroups do not wait on each other; the events (a few per thousand photons)
+// are handled one per thread.
+// FK: the field kind (a.f.kind), a template parameter so that each kind keeps
+// only its own field code and registers: at most 128 (four waves per SIMD),
+// 168 on a grid (three waves: its four 27-node gathers in flight).
+template <int FK> constexpr int pt_waves() { return FK == QED_FIELD_GRID ? 3 : 4; }
+template <int FK>
+__global__ __launch_bounds__(kPTThreads, (pt_waves<FK>())) void k_photon_table(PairArgs<float> a, uint64_t *emask) {
   __shared__ float L_s[kPairNRate];
-  __shared__ uint64_t scan_s[16];
-  __shared__ uint32_t tile_s;
-  __shared__ uint64_t off_s;
-  __shared__ int64_t hdr_s[4];
   __shared__ uint32_t cnt_s[cNumCounters];
   count_zero(cnt_s);
-  if (threadIdx.x == 0) {
-    hdr_s[0] = *a.ph.count; hdr_s[1] = *a.el.count; hdr_s[2] = *a.po.count;
-    hdr_s[3] = (int64_t)*a.next_id;
-  }
-  __syncthreads();
-  const int64_t n = hdr_s[0], e0 = hdr_s[1], p0 = hdr_s[2];
-  const uint64_t id0 = (uint64_t)hdr_s[3];
-  if (n == 0) return;
   for (int k = threadIdx.x; k < kPairNRate; k += blockDim.x) L_s[k] = a.L[k];
-  // the 16-bit inverse-CDF table is read through the caches: only events sample
-  // it, and without it in LDS several workgroups share a CU
-  const RowQ16 tab{a.q16, a.s0sc};
-  while (true) {
-    const uint32_t tile = next_tile(a.sc.ticket, &tile_s);
-    if ((int64_t)tile * kPairTile >= n) break;
-    pair_tile<float>(a, tab, L_s, tile, scan_s, &off_s, n, e0, p0, id0, cnt_s);
+  __syncthreads();
+  a.f.kind = FK;
+  const int64_t n = *a.ph.count;
+  float *X = (float *)a.ph.x, *Y = (float *)a.ph.y, *Z = (float *)a.ph.z;
+  const float *KX = (const float *)a.ph.px, *KY = (const float *)a.ph.py, *KZ = (const float *)a.ph.pz;
+  const bool need_x = a.move || FK == QED_FIELD_GRID;
+  constexpr bool pp = FK == QED_FIELD_PER_PARTICLE;
+  const double t_left = time_left(a.ret, step_of(a.step, a.d_step), a.dtd);
+  uint32_t nrange = 0, nnan = 0, nret = 0;
+  for (int64_t tile = blockIdx.x; tile * kPTTile < n; tile += gridDim.x) {
+    // every load of the thread's photons first, so that their latencies overlap
+    uint64_t pids[kPTItems];
+    float kk[kPTItems][3], xx[kPTItems][3], Fp[kPTItems][pp ? 6 : 1];
+    double taus[kPTItems];
+#pragma unroll
+    for (int it = 0; it < kPTItems; ++it) {
+      const int64_t i = tile * kPTTile + (int64_t)it * kPTThreads + threadIdx.x;
+      const bool v = i < n, vx = v && need_x;
+      pids[it] = v ? a.ph.id[i] : kDeadId;
+      kk[it][0] = v ? KX[i] : 0.f; kk[it][1] = v ? KY[i] : 0.f; kk[it][2] = v ? KZ[i] : 0.f;
+      taus[it] = v ? a.ph.tau[i] : 0.0;
+      xx[it][0] = vx ? X[i] : 0.f; xx[it][1] = vx ? Y[i] : 0.f; xx[it][2] = vx ? Z[i] : 0.f;
+      if constexpr (pp) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          Fp[it][c] = v ? a.f.pE[c][i] : 0.f;
+          Fp[it][3 + c] = v ? a.f.pB[c][i] : 0.f;
+        }
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < kPTItems; ++it) {
+      const int64_t i = tile * kPTTile + (int64_t)it * kPTThreads + threadIdx.x;
+      bool ev = false;
+      if (pids[it] != kDeadId) {             // converted photons not yet compacted are skipped
+        const float kx = kk[it][0], ky = kk[it][1], kz = kk[it][2];
+        float x = xx[it][0], y = xx[it][1], z = xx[it][2];
+        const float gph = root<float>(kx * kx + ky * ky + kz * kz);
+        if (a.move && gph > 0.f) {
+          const float vdt = rcp<float>(gph) * a.dt;
+          x += kx * vdt; y += ky * vdt; z += kz * vdt;
+          if (a.f.kind == QED_FIELD_GRID) {
+            wrap_coord<float>(x, box_len<float>(a.f, 0)); wrap_coord<float>(y, box_len<float>(a.f, 1));
+            wrap_coord<float>(z, box_len<float>(a.f, 2));
+          }
+          X[i] = x; Y[i] = y; Z[i] = z;
+        }
+        double chi, W;
+        float F[6];
+        if constexpr (pp) {
+#pragma unroll
+          for (int c = 0; c < 6; ++c) F[c] = Fp[it][c];
+        } else {
+          field_at<float>(a.f, i, x, y, z, F);
+        }
+        if (photon_rate_at<float>(a, L_s, F, kx, ky, kz, gph, chi, W)) nrange += chi > a.rg.pair_hi;
+        else ++nnan;
+        ev = W > 0.0 && taus[it] <= W * a.dtd;
+        if (!ev) photon_settle(a, i, taus[it] - W * a.dtd, gph, t_left, nret);
+      }
+      const uint64_t bal = __ballot(ev);
+      if ((threadIdx.x & 63) == 0 && i < n) emask[i >> 6] = bal;   // lane 0 holds a multiple of 64
+    }
   }
+  count_lds(cnt_s, cChiRange, nrange);
+  count_lds(cnt_s, cNanChi, nnan);
+  count_lds(cnt_s, cRetired, nret);
   count_flush(cnt_s, a.counters);
   // retired photons are dead too: the compaction of this species must not skip
   if (threadIdx.x == 0 && a.killed && cnt_s[cRetired])
     atomicAdd((unsigned long long *)a.killed, (unsigned long long)cnt_s[cRetired]);
+}
+
+__global__ __launch_bounds__(256) void k_pair_events(PairArgs<float> a, const int32_t *eidx, const int64_t *n_ev) {
+  __shared__ float L_s[kPairNRate];
+  __shared__ int64_t hdr_s[4];
+  __shared__ uint32_t cnt_s[cNumCounters];
+  count_zero(cnt_s);
+  if (threadIdx.x == 0) {
+    hdr_s[0] = *n_ev; hdr_s[1] = *a.el.count; hdr_s[2] = *a.po.count; hdr_s[3] = (int64_t)*a.next_id;
+  }
+  __syncthreads();
+  const int64_t nev = hdr_s[0], e0 = hdr_s[1], p0 = hdr_s[2];
+  const uint64_t id0 = (uint64_t)hdr_s[3];
+  if (nev == 0 || (int64_t)blockIdx.x * blockDim.x >= nev) return;
+  for (int k = threadIdx.x; k < kPairNRate; k += blockDim.x) L_s[k] = a.L[k];
+  __syncthreads();
+  const RowQ16 tab{a.q16, a.s0sc};
+  const float *X = (const float *)a.ph.x, *Y = (const float *)a.ph.y, *Z = (const float *)a.ph.z;
+  const float *KX = (const float *)a.ph.px, *KY = (const float *)a.ph.py, *KZ = (const float *)a.ph.pz;
+  const uint64_t step = step_of(a.step, a.d_step);
+  uint32_t ndrop = 0;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nev; r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = eidx[r];
+    const uint64_t pid = a.ph.id[i];
+    const float kx = KX[i], ky = KY[i], kz = KZ[i];
+    const float x = X[i], y = Y[i], z = Z[i];      // moved by k_photon_table
+    const float gph = root<float>(kx * kx + ky * ky + kz * kz);
+    double chi, W;
+    photon_rate<float>(a, L_s, i, x, y, z, kx, ky, kz, gph, chi, W);
+    const uint4 u = stream4(pid, a.seed, step, kPhotonEvent, 0u);
+    float xh, omh;
+    sample_pair_half<float>(tab, (float)chi, unit<float>(u.x), unit<float>(u.y), xh, omh, a.rg);
+    const bool flip = u.y & 1u;
+    const float xe = flip ? omh : xh, xp = flip ? xh : omh;
+    const float ge = xe * gph, gpos = xp * gph;
+    const double te = -log(unit<double>(u.z)), tp = -log(unit<double>(u.w));
+    a.ph.id[i] = kDeadId;
+    const int64_t je = e0 + r, jp = p0 + r;
+    if (je < a.el.cap && jp < a.po.cap) {
+      const float kxh = kx / gph, kyh = ky / gph, kzh = kz / gph;
+      const float pe = sqrtf(fmaxf(ge * ge - 1.f, 0.f)), ppo = sqrtf(fmaxf(gpos * gpos - 1.f, 0.f));
+      ((float *)a.el.x)[je] = x; ((float *)a.el.y)[je] = y; ((float *)a.el.z)[je] = z;
+      ((float *)a.el.px)[je] = kxh * pe; ((float *)a.el.py)[je] = kyh * pe; ((float *)a.el.pz)[je] = kzh * pe;
+      a.el.tau[je] = te; a.el.id[je] = id0 + 2 * (uint64_t)r;
+      ((float *)a.po.x)[jp] = x; ((float *)a.po.y)[jp] = y; ((float *)a.po.z)[jp] = z;
+      ((float *)a.po.px)[jp] = kxh * ppo; ((float *)a.po.py)[jp] = kyh * ppo; ((float *)a.po.pz)[jp] = kzh * ppo;
+      a.po.tau[jp] = tp; a.po.id[jp] = id0 + 2 * (uint64_t)r + 1;
+    } else {
+      ndrop += 2;
+    }
+  }
+  count_lds(cnt_s, cDropped, ndrop);
+  count_flush(cnt_s, a.counters);
+}
+
+// After the events: pairs appended (up to the capacities), ids used, photons killed.
+__global__ void k_pair_commit(PairArgs<float> a, const int64_t *n_ev) {
+  const int64_t tt = *n_ev, e0 = *a.el.count, p0 = *a.po.count;
+  *a.el.count = e0 + tt < a.el.cap ? e0 + tt : a.el.cap;
+  *a.po.count = p0 + tt < a.po.cap ? p0 + tt : a.po.cap;
+  *a.next_id += 2 * (uint64_t)tt;
+  if (tt) atomicAdd(&a.counters[cPairs], (unsigned long long)tt);
+  if (a.killed && tt) atomicAdd((unsigned long long *)a.killed, (unsigned long long)tt);
 }
 
 __global__ __launch_bounds__(kPairThreads) void k_pairs_f64(PairArgs<double> a) {
@@ -1973,6 +2076,7 @@ hipError_t launch_emit(qed_ctx *c, const qed_species_t *lep, const qed_species_t
   const bool wide = lep->capacity >= kEIWideFrom;
   const int64_t eit = wide ? ei_tile<8>() : ei_tile<1>();
   const int64_t etiles = (lep->capacity + eit - 1) / eit;
+  const unsigned eig = (unsigned)(etiles < 2 * (int64_t)c->n_cu ? etiles : 2 * (int64_t)c->n_cu);   // persistent
   // one launch clears both scans: region 1 for the index, region 0 for the events
   const bool m1 = gen_mode(c) != 0;
   const int tile = use_mlp ? kEmitMlpThreads
@@ -1987,10 +2091,10 @@ hipError_t launch_emit(qed_ctx *c, const qed_species_t *lep, const qed_species_t
   if (e != hipSuccess) return e;
   const ScanDev isc{c->d_ticket + 1, c->d_status + c->status_len};
   if (wide)
-    hipLaunchKernelGGL((k_emit_index<8, EmIdx>), dim3((unsigned)etiles), dim3(kEIThreads), 0, st, c->em_mask, lep->count,
+    hipLaunchKernelGGL((k_emit_index<8, EmIdx>), dim3(eig), dim3(kEIThreads), 0, st, c->em_mask, lep->count,
                      c->em_idx, c->d_n_emit, isc, c->d_counters);
   else
-    hipLaunchKernelGGL((k_emit_index<1, EmIdx>), dim3((unsigned)etiles), dim3(kEIThreads), 0, st, c->em_mask, lep->count,
+    hipLaunchKernelGGL((k_emit_index<1, EmIdx>), dim3(eig), dim3(kEIThreads), 0, st, c->em_mask, lep->count,
                      c->em_idx, c->d_n_emit, isc, c->d_counters);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const ScanDev sc{c->d_ticket, c->d_status};
@@ -2029,7 +2133,7 @@ hipError_t launch_pairs(qed_ctx *c, const qed_fields_t *f, const qed_species_t *
                         hipStream_t st) {
   const int64_t ntiles = (ph->capacity + kPairTile - 1) / kPairTile;
   const bool thin = (c->params.flags & QED_FLAG_SURROGATE) && ph->dtype == QED_F32;
-  if (!thin) {   // (the thinned pass clears its two scans itself)
+  if (ph->dtype != QED_F32) {   // (the float32 passes clear their scans themselves)
     hipError_t e = zero_scan(c, ntiles, st);
     if (e != hipSuccess) return e;
   }
@@ -2050,6 +2154,7 @@ hipError_t launch_pairs(qed_ctx *c, const qed_fields_t *f, const qed_species_t *
       const bool wide = ph->capacity >= kEIWideFrom;
       const int64_t eit = wide ? ei_tile<8>() : ei_tile<1>();
       const int64_t etiles = (ph->capacity + eit - 1) / eit;
+      const unsigned eig = (unsigned)(etiles < 2 * (int64_t)c->n_cu ? etiles : 2 * (int64_t)c->n_cu);
       const int64_t ctiles = (ph->capacity + kPCThreads - 1) / kPCThreads;
       const int64_t n0 = ctiles + 1, n1 = etiles + 1, nz = n0 > n1 ? n0 : n1;
       if (nz > c->status_len || ph->capacity > c->cand_cap) return hipErrorInvalidValue;
@@ -2063,16 +2168,43 @@ hipError_t launch_pairs(qed_ctx *c, const qed_fields_t *f, const qed_species_t *
         hipLaunchKernelGGL(k_photon_thin<false>, dim3(tgrid), dim3(kPTThreads), 0, st, a, c->cand_mask);
       const ScanDev isc{c->d_ticket + 1, c->d_status + c->status_len};
       if (wide)
-        hipLaunchKernelGGL((k_emit_index<8, int32_t>), dim3((unsigned)etiles), dim3(kEIThreads), 0, st, c->cand_mask,
+        hipLaunchKernelGGL((k_emit_index<8, int32_t>), dim3(eig), dim3(kEIThreads), 0, st, c->cand_mask,
                            ph->count, c->cand_idx, c->d_n_cand, isc, c->d_counters);
       else
-        hipLaunchKernelGGL((k_emit_index<1, int32_t>), dim3((unsigned)etiles), dim3(kEIThreads), 0, st, c->cand_mask,
+        hipLaunchKernelGGL((k_emit_index<1, int32_t>), dim3(eig), dim3(kEIThreads), 0, st, c->cand_mask,
                            ph->count, c->cand_idx, c->d_n_cand, isc, c->d_counters);
       const int64_t cwgs = (int64_t)c->n_cu * 4;
       hipLaunchKernelGGL(k_pair_cand, dim3((unsigned)(ctiles < cwgs ? ctiles : cwgs)), dim3(kPCThreads), 0, st, a,
                          c->cand_idx, c->d_n_cand, c->mlp_theta[1], c->params.kmax);
     } else {
-      hipLaunchKernelGGL(k_pairs_f32, dim3(grid), dim3(kPairThreads), 0, st, a);
+      // streaming pass, event list (region 1 of the scan state), events, counts
+      const bool wide = ph->capacity >= kEIWideFrom;
+      const int64_t eit = wide ? ei_tile<8>() : ei_tile<1>();
+      const int64_t etiles = (ph->capacity + eit - 1) / eit;
+      const unsigned eig = (unsigned)(etiles < 2 * (int64_t)c->n_cu ? etiles : 2 * (int64_t)c->n_cu);
+      if (etiles + 1 > c->status_len || ph->capacity > c->cand_cap) return hipErrorInvalidValue;
+      hipLaunchKernelGGL(k_zero_scan2, dim3((unsigned)((etiles + 1 + 255) / 256)), dim3(256), 0, st, c->d_ticket,
+                         c->d_status, c->status_len, (int64_t)1, etiles + 1);
+      const int64_t ttiles = (ph->capacity + kPTTile - 1) / kPTTile, twgs = (int64_t)c->n_cu * 8;
+      const unsigned tgrid = (unsigned)(ttiles < twgs ? ttiles : twgs);
+      if (f->kind == QED_FIELD_GRID)
+        hipLaunchKernelGGL(k_photon_table<QED_FIELD_GRID>, dim3(tgrid), dim3(kPTThreads), 0, st, a, c->cand_mask);
+      else if (f->kind == QED_FIELD_UNIFORM)
+        hipLaunchKernelGGL(k_photon_table<QED_FIELD_UNIFORM>, dim3(tgrid), dim3(kPTThreads), 0, st, a, c->cand_mask);
+      else
+        hipLaunchKernelGGL(k_photon_table<QED_FIELD_PER_PARTICLE>, dim3(tgrid), dim3(kPTThreads), 0, st, a,
+                           c->cand_mask);
+      const ScanDev isc{c->d_ticket + 1, c->d_status + c->status_len};
+      if (wide)
+        hipLaunchKernelGGL((k_emit_index<8, int32_t>), dim3(eig), dim3(kEIThreads), 0, st, c->cand_mask,
+                           ph->count, c->cand_idx, c->d_n_cand, isc, c->d_counters);
+      else
+        hipLaunchKernelGGL((k_emit_index<1, int32_t>), dim3(eig), dim3(kEIThreads), 0, st, c->cand_mask,
+                           ph->count, c->cand_idx, c->d_n_cand, isc, c->d_counters);
+      const int64_t ewgs = (int64_t)c->n_cu * 4, eblocks = (ph->capacity + 255) / 256;
+      hipLaunchKernelGGL(k_pair_events, dim3((unsigned)(eblocks < ewgs ? eblocks : ewgs)), dim3(256), 0, st, a,
+                         c->cand_idx, c->d_n_cand);
+      hipLaunchKernelGGL(k_pair_commit, dim3(1), dim3(1), 0, st, a, c->d_n_cand);
     }
   } else {
     PairArgs<double> a{dev_species(ph), dev_species(el), dev_species(po), dev_fields(f), c->pair_L64,
