@@ -607,6 +607,12 @@ def run_pairs(q, torch, n=20_000_000, steps=100, dt=0.01):
                         f"float32 state, {steps} steps; every photon slot is checked each step",
                value=n * steps / (ms * 1e-3), unit="photon-steps/s", ms_per_step=ms / steps, pairs=st["pairs"],
                chi_out_of_range=st["chi_out_of_range"])
+    # per photon and step: read id, k, tau and the photon's E, B (52 B), write tau (8 B); the
+    # (rare) pairs and the event list are left out
+    ach = 60.0 * n / (ms / steps * 1e-3) / 1e9
+    out["roofline"] = {"bound": "hbm", "kernel": "photon pass (qed_create_pairs), whole call", "achieved": ach,
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                       "algorithmic_bytes_per_call": 60 * n}
     del ph, el, po, Et, Bt
     ctx.close()
     return out
