@@ -5,8 +5,8 @@ of the circularly polarised standing wave a0 = 1000, float32 state with float64
 chi and optical depth, formula II tables, dt = 0.01.  One step = refill the grid
 for t = n dt, pair creation for every photon present, gather/push and emission
 for electrons and for positrons (photons appended), photon compaction every 10
-steps; electrons and photons re-sorted by cell every 20 steps (outside the
-captured graphs).  The step runs as captured hipGraphs, 500 steps in all, with
+steps; electrons and positrons (on the table path photons too) re-sorted by
+cell every 14 steps (outside the captured graphs).  The step runs as captured hipGraphs, 500 steps in all, with
 the photon and positron populations growing in place.  It runs twice: with the
 surrogate networks (QED_FLAG_SURROGATE: rates and photon energies from the nets,
 candidate events by Poisson thinning, table fallback) and with the plain tables.
@@ -55,7 +55,7 @@ PROFILED_SOURCES = ("step.hip", "qed_device.h", "lookup.h")
 # the cascade configuration
 C5_N, C5_STEPS, C5_A0, C5_DT, C5_GRID, C5_SEED = 200_000_000, 500, 1000.0, 0.01, 128, 4
 C5_SUBSAMPLE = 100_000          # ids 0 .. 99999: drawn on the host, shared with the oracle
-C5_SORT_EVERY, C5_COMPACT_EVERY = 10, 10
+C5_SORT_EVERY, C5_COMPACT_EVERY = 14, 10
 # fixed-chi emission run of the 1e7-sample spectrum gate (chi ~ 1: b0 = 2000, gamma = 206)
 KS_N, KS_B0, KS_GAMMA, KS_DT, KS_STEPS = 1_000_000, 2000.0, 206.0, 0.05, 20
 
@@ -233,9 +233,10 @@ def oracle_gates(gpu, orc, n_gpu):
 def run_cascade(q, torch, args, weights, name):
     """The cascade step (pair creation, both lepton passes with emission, photon
     compaction every C5_COMPACT_EVERY steps) on the standing wave, captured as
-    hipGraphs and replayed for the whole run; electrons and photons re-sorted by
-    cell every `--c5-sort-every` steps outside the graphs (from one set of
-    species buffers into the other; graphs are captured for both sets).  Photons converted into
+    hipGraphs and replayed for the whole run; leptons (on the table path photons
+    too) re-sorted by cell every `--c5-sort-every` steps outside the graphs (from
+    one set of species buffers into the other; graphs are captured for both
+    sets).  Photons converted into
     pairs stay in place as dead slots (pair creation skips them) until the
     compaction: a stable compaction moves every photon behind the first hole.
     The 2e8 electrons: ids 0..99999 from workloads.standing_wave_electrons (the
@@ -263,10 +264,15 @@ def run_cascade(q, torch, args, weights, name):
     ctx.qed_set_retirement(total * C5_DT, c5_field_bound())
     cap_e, cap_p = int(1.4 * n) + 1_000_000, int(0.4 * n) + 1_000_000
     cap_g = min(int(0.012 * n * total) + 10_000_000, (1 << 31) - 1)
-    # two sets of species: a re-sort moves every species from the set in use to
-    # the other one (graphs are captured for both sets)
-    sets = [dict(el=q.Species(cap_e, "f32"), po=q.Species(cap_p, "f32"), ph=q.Species(cap_g, "f32"))
-            for _ in range(2)]
+    # two sets of species: a re-sort moves every sorted species from the set in
+    # use to the other one (graphs are captured for both sets).  The table path
+    # gathers the field for every photon and re-sorts them too; the surrogate
+    # path gathers it only at candidate events, so its photons keep their
+    # creation order (which follows the sorted leptons) in one buffer both sets share
+    sorted_species = ("el", "po", "ph") if name == "table" else ("el", "po")
+    ph_shared = None if "ph" in sorted_species else q.Species(cap_g, "f32")
+    sets = [dict(el=q.Species(cap_e, "f32"), po=q.Species(cap_p, "f32"),
+                 ph=ph_shared if ph_shared is not None else q.Species(cap_g, "f32")) for _ in range(2)]
     cur = [0]
     src = sets[1]["el"]
     gen = torch.Generator(device="cuda")
@@ -312,7 +318,7 @@ def run_cascade(q, torch, args, weights, name):
 
     def resort():
         a, b = sets[cur[0]], sets[1 - cur[0]]
-        for k in ("el", "po", "ph"):
+        for k in sorted_species:
             ctx.qed_sort_by_cell(fld, a[k], b[k])
         cur[0] ^= 1
 
@@ -389,7 +395,7 @@ def run_cascade(q, torch, args, weights, name):
                pair_pass_ms=pair_ms, pair_pass_photons=pair_n, lepton_pass_ms=gp_ms, lepton_pass_electrons=gp_n,
                sampled_step_parts_ms=parts,
                capacity_photons=cap_g)
-    del graphs, sets, el, po, ph, grid, processed
+    del graphs, sets, ph_shared, el, po, ph, grid, processed
     ctx.close()
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
@@ -770,7 +776,7 @@ def main():
         "config": {"workload": f"cascade step, {head_name} path: standing wave a0={C5_A0:g}, {args.c5_n} electrons "
                                f"at start, {C5_GRID}^3 grid, formula {'II' if args.formula == 2 else 'I'} tables, "
                                f"{total} steps of dt={C5_DT} as hipGraphs (the last {args.steps} timed), photon "
-                               f"compaction every {C5_COMPACT_EVERY} steps, all species re-sorted by cell every "
+                               f"compaction every {C5_COMPACT_EVERY} steps, leptons (table path: and photons) re-sorted by cell every "
                                f"{args.c5_sort_every}",
                    "global_batch": args.c5_n, "dt": C5_DT, "steps_run": total, "parallelism": "single GPU"},
         "path": head_name,
