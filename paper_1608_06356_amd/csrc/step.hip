@@ -42,7 +42,7 @@ struct FieldDev {
   const float *pE[3], *pB[3];
 };
 
-constexpr int kGPThreads = 256, kGPTile = kGPThreads;   // gather/push workgroup = tile
+constexpr int kGPThreads = 256;   // gather/push workgroup
 
 struct ScanDev {
   uint32_t *ticket;
@@ -180,30 +180,39 @@ __device__ __forceinline__ int row_extreme(int v) {
   return v;
 }
 
-// Box of the workgroup.  Every thread calls it; live: the thread holds a
-// particle with stencil centre j.  On success the box is in LDS, rel holds the
+// Box of the workgroup.  Every thread calls it; live[it]: the thread holds
+// particle it, with stencil centre j[it].  On success the box is in LDS, rel holds the
 // thread's stencil corner (node j-1) in box coordinates and pit the row and
 // plane pitches (odd, which spreads neighbouring rows and planes over the LDS
 // banks).  Returns false (uniformly) when the box exceeds kBoxCap nodes.  Its
 // first barrier also publishes whatever the caller wrote to LDS before.
-__device__ __forceinline__ bool stage_box(BoxLds &S, const FieldDev &f, bool live, const int j[3], int rel[3],
-                                          int pit[2]) {
+template <int IT>
+__device__ __forceinline__ bool stage_box(BoxLds &S, const FieldDev &f, const bool live[IT], const int j[IT][3],
+                                          int rel[IT][3], int pit[2]) {
   const int n3[3] = {f.nx, f.ny, f.nz};
-  int jj[3];
+  int jj[IT][3];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) jj[d] = j[d] == n3[d] ? 0 : j[d];
+  for (int it = 0; it < IT; ++it)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) jj[it][d] = j[it][d] == n3[d] ? 0 : j[it][d];
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) { S.ref[d] = jj[d]; S.lo[d] = INT_MAX; S.hi[d] = INT_MIN; }
+    for (int d = 0; d < 3; ++d) { S.ref[d] = jj[0][d]; S.lo[d] = INT_MAX; S.hi[d] = INT_MIN; }
     S.bad = 0;
   }
   __syncthreads();
-  // row extremes, then one LDS atomic per row of 16 lanes
+  // extremes over the thread's particles, then over each row of 16 lanes, then
+  // one LDS atomic per row
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    rel[d] = centred(jj[d], S.ref[d], n3[d]);
-    const int lo = row_extreme<false>(live ? rel[d] : INT_MAX);
-    const int hi = row_extreme<true>(live ? rel[d] : INT_MIN);
+    int lo = INT_MAX, hi = INT_MIN;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      rel[it][d] = centred(jj[it][d], S.ref[d], n3[d]);
+      if (live[it]) { lo = min(lo, rel[it][d]); hi = max(hi, rel[it][d]); }
+    }
+    lo = row_extreme<false>(lo);
+    hi = row_extreme<true>(hi);
     if ((threadIdx.x & 15) == 0) { atomicMin(&S.lo[d], lo); atomicMax(&S.hi[d], hi); }
   }
   __syncthreads();
@@ -267,13 +276,18 @@ __device__ __forceinline__ bool stage_box(BoxLds &S, const FieldDev &f, bool liv
   }
   // the stencil of every live particle lies inside the box by construction;
   // checked anyway, so that the LDS reads below can never leave it
-  bool fits = true;
+  bool bad = false;
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    rel[d] -= bmin[d] + 1;
-    fits = fits && rel[d] >= 0 && rel[d] + 2 < bdim[d];
+  for (int it = 0; it < IT; ++it) {
+    bool fits = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      rel[it][d] -= bmin[d] + 1;
+      fits = fits && rel[it][d] >= 0 && rel[it][d] + 2 < bdim[d];
+    }
+    bad = bad || (live[it] && !fits);
   }
-  if (live && !fits) S.bad = 1;
+  if (bad) S.bad = 1;
   pit[0] = px;
   pit[1] = pxy;
   __syncthreads();
@@ -567,26 +581,34 @@ __device__ __forceinline__ int method1_next(uint64_t id, uint32_t seed, uint64_t
   return N;
 }
 
-// Waves per SIMD the compiler must allow for (bounds the registers): the
-// single-precision grid kernel without method I is the hot one.
+// Waves per SIMD the compiler must allow for (bounds the registers), and
+// particles per thread: the single-precision grid kernel without method I is
+// the hot one; it takes two particles per thread, so that the workgroup's
+// fixed work (the box's extent, its staging and the barriers) is shared by 512
+// particles.
 template <typename R, int FK, bool M1> constexpr int gp_waves() {
-  return (sizeof(R) == 4 && FK == QED_FIELD_GRID && !M1) ? kGPWaves : 1;
+  return (sizeof(R) == 4 && FK == QED_FIELD_GRID && !M1) ? kGPWaves - 1 : 1;   // two particles: 102 registers
+}
+template <typename R, int FK, bool M1> constexpr int gp_items() {
+  return (sizeof(R) == 4 && FK == QED_FIELD_GRID && !M1) ? 2 : 1;
 }
 
 // M1: compiled with the method I generator (a.gen != 0), else optical depth only.
 // Thin (float32, surrogate path): the optical depth runs down at the envelope
 // rate h_rad_env (Poisson thinning); the emission pass evaluates the rate net
 // only at the candidate events this finds and keeps each with probability
-// W / W_env.
+// W / W_env.  Particle it of thread t is base + it * kGPThreads + t.
 template <typename R, int FK, bool M1, bool Thin = false>
 __global__ __launch_bounds__(kGPThreads, (gp_waves<R, FK, M1>())) void k_gather_push(GPArgs<R> a) {
+  constexpr int IT = gp_items<R, FK, M1>();
+  constexpr int64_t kTile = (int64_t)kGPThreads * IT;
   __shared__ R lnh_s[kRadNChi];
   // (the grid is sized by the capacity: blocks beyond the particles present
   // return, and they are the last ones dispatched)
   const int64_t n = *a.sp.count;
   const int64_t k = blockIdx.x / kXcds;
   const int64_t tile = ((k / kGPChunk) * kXcds + blockIdx.x % kXcds) * kGPChunk + k % kGPChunk;
-  const int64_t base = tile * kGPTile;
+  const int64_t base = tile * kTile;
   if (base >= n) return;
   // the tile's slices of the arrays (uniform bases, 32-bit thread offsets)
   const int t = threadIdx.x;
@@ -595,92 +617,119 @@ __global__ __launch_bounds__(kGPThreads, (gp_waves<R, FK, M1>())) void k_gather_
   double *TAU = a.sp.tau + base;
   FieldDev f = a.f;
   f.kind = FK;
-  const int64_t i = base + t;
-  bool flag = false;
-  uint32_t nnan = 0, nrange = 0;
-  R F[6];
-  bool live = i < n;
-  // every load of the particle is issued up front, to overlap with the staging
-  R x = 0, y = 0, z = 0, px = 0, py = 0, pz = 0;
-  double tau = 0.0;
-  if (live) {
-    x = X[t]; y = Y[t]; z = Z[t];
-    px = PX[t]; py = PY[t]; pz = PZ[t];
-    tau = TAU[t];
+  bool live[IT];
+  // every load of the thread's particles is issued up front, to overlap with the staging
+  R xs[IT][3], ps[IT][3];
+  double taus[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int o = it * kGPThreads + t;
+    live[it] = base + o < n;
+    xs[it][0] = live[it] ? X[o] : (R)0; xs[it][1] = live[it] ? Y[o] : (R)0; xs[it][2] = live[it] ? Z[o] : (R)0;
+    ps[it][0] = live[it] ? PX[o] : (R)0; ps[it][1] = live[it] ? PY[o] : (R)0; ps[it][2] = live[it] ? PZ[o] : (R)0;
+    taus[it] = live[it] ? TAU[o] : 0.0;
   }
-  for (int k = threadIdx.x; k < kRadNChi; k += blockDim.x) lnh_s[k] = a.lnh[k];
+  for (int q = threadIdx.x; q < kRadNChi; q += blockDim.x) lnh_s[q] = a.lnh[q];
+
+  // push, chi, rate and event decision of particle it, with its fields F
+  auto finish = [&](int it, R F[6], bool ok) {
+    const int o = it * kGPThreads + t;
+    const int64_t i = base + o;
+    bool flag = false, nan = false, range = false;
+    if (ok && !fields_finite<R>(F)) { ok = false; nan = true; }   // skipped and counted
+    if (ok) {
+      R px = ps[it][0], py = ps[it][1], pz = ps[it][2], x = xs[it][0], y = xs[it][1], z = xs[it][2];
+      const double tau = taus[it];
+      boris<R>(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5], a.q, a.dt);
+      const R g = root<R>((R)1 + px * px + py * py + pz * pz);
+      const R ig = rcp<R>(g), vdt = ig * a.dt;
+      x += px * vdt; y += py * vdt; z += pz * vdt;
+      if (FK == QED_FIELD_GRID) {
+        wrap_coord<R>(x, box_len<R>(f, 0)); wrap_coord<R>(y, box_len<R>(f, 1));
+        wrap_coord<R>(z, box_len<R>(f, 2));
+      }
+      X[o] = x; Y[o] = y; Z[o] = z; PX[o] = px; PY[o] = py; PZ[o] = pz;
+      double chi;
+      if constexpr (sizeof(R) == 4) chi = chi_lepton_f32(px, py, pz, F);
+      else chi = chi_lepton(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5]);
+      double W = 0.0;
+      if (isfinite(chi)) {
+        range = chi > a.rg.rad_hi;
+        R h;
+        if constexpr (Thin) h = (R)h_rad_env((float)chi);
+        else h = h_rad<R, true>((R)chi, lnh_s, a.rg);
+        W = kRateUnit * (double)(h * ig);
+      } else {
+        nan = true;
+      }
+      int j0 = 0, nsub = 1;
+      if (M1 && a.gen) {
+        // method I: first sub-step with an event, if any
+        const uint64_t id = a.sp.id[i];
+        nsub = method1_nsub(W, a.dtd, a.gen);
+        j0 = W > 0.0 ? method1_next(id, a.seed, step_of(a.step, a.d_step), 0, nsub, W, a.dtd) : nsub;
+        flag = j0 < nsub;
+      } else {
+        flag = W > 0.0 && tau <= W * a.dtd;
+      }
+      const uint64_t fbits = __ballot(flag);   // the live lanes' flags (others are not emitters)
+      if (flag) {
+        EmRec<R> r;
+        r.x[0] = x; r.x[1] = y; r.x[2] = z; r.p[0] = px; r.p[1] = py; r.p[2] = pz;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) r.F[c] = F[c];
+        r.tau = tau;
+        r.chi = chi;
+        r.W = W;
+        r.j0 = j0;
+        r.nsub = nsub;
+        a.rec[rec_slot(i, fbits)] = r;
+      } else if (!(M1 && a.gen)) {
+        TAU[o] = tau - W * a.dtd;
+      }
+    }
+    const uint64_t bits = __ballot(flag);
+    if ((t & 63) == 0 && base + (o & ~63) < n) a.mask[(base + o) >> 6] = bits;
+    count_flags(a.counters, cNanChi, nan);
+    count_flags(a.counters, cChiRange, range);
+  };
+
   if (FK == QED_FIELD_GRID) {
     __shared__ BoxLds box_s;
-    int j[3], rel[3], pit[2];
-    R w[3][3];
-    tsc_setup<R>(f, x, y, z, j, w);      // dead lanes hold x = 0: harmless, unused
-    if (stage_box(box_s, f, live, j, rel, pit)) {   // its barriers also publish lnh_s
-      if (live) gather_box<R>(box_s, rel, pit, w, F);
-    } else {
-      if (live) gather_global<R>(f, j, w, F);
-      if (threadIdx.x == 0) atomicAdd(&a.counters[cBoxFallback], 1ull);
+    int j[IT][3], rel[IT][3], pit[2];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      R w[3][3];
+      tsc_setup<R>(f, xs[it][0], xs[it][1], xs[it][2], j[it], w);   // dead particles hold x = 0: unused
     }
-    if (live && !fields_finite<R>(F)) { live = false; nnan = 1; }   // skipped and counted
+    const bool boxed = stage_box<IT>(box_s, f, live, j, rel, pit);   // its barriers also publish lnh_s
+    if (!boxed && threadIdx.x == 0) atomicAdd(&a.counters[cBoxFallback], 1ull);
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      // one particle after the other, the weights recomputed from the position
+      // (held opaque, so that they are not kept from above): the two gathers
+      // in flight together would need more registers than five waves leave
+      R x = xs[it][0], y = xs[it][1], z = xs[it][2];
+      if (IT > 1) asm volatile("" : "+v"(x), "+v"(y), "+v"(z));
+      int jc[3];
+      R w[3][3];
+      tsc_setup<R>(f, x, y, z, jc, w);
+      R F[6];
+      if (live[it]) {
+        if (boxed) gather_box<R>(box_s, rel[it], pit, w, F);
+        else gather_global<R>(f, jc, w, F);
+      }
+      finish(it, F, live[it]);
+    }
   } else {
     __syncthreads();
-    if (live) {
-      field_at<R>(f, i, x, y, z, F);
-      if (!fields_finite<R>(F)) { live = false; nnan = 1; }   // skipped and counted
-    }
-  }
-  if (live) {
-    boris<R>(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5], a.q, a.dt);
-    const R g = root<R>((R)1 + px * px + py * py + pz * pz);
-    const R ig = rcp<R>(g), vdt = ig * a.dt;
-    x += px * vdt; y += py * vdt; z += pz * vdt;
-    if (FK == QED_FIELD_GRID) {
-      wrap_coord<R>(x, box_len<R>(f, 0)); wrap_coord<R>(y, box_len<R>(f, 1));
-      wrap_coord<R>(z, box_len<R>(f, 2));
-    }
-    X[t] = x; Y[t] = y; Z[t] = z; PX[t] = px; PY[t] = py; PZ[t] = pz;
-    double chi;
-    if constexpr (sizeof(R) == 4) chi = chi_lepton_f32(px, py, pz, F);
-    else chi = chi_lepton(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5]);
-    double W = 0.0;
-    if (isfinite(chi)) {
-      nrange = chi > a.rg.rad_hi;
-      R h;
-      if constexpr (Thin) h = (R)h_rad_env((float)chi);
-      else h = h_rad<R, true>((R)chi, lnh_s, a.rg);
-      W = kRateUnit * (double)(h * ig);
-    } else {
-      nnan = 1;
-    }
-    int j0 = 0, nsub = 1;
-    if (M1 && a.gen) {
-      // method I: first sub-step with an event, if any
-      const uint64_t id = a.sp.id[i];
-      nsub = method1_nsub(W, a.dtd, a.gen);
-      j0 = W > 0.0 ? method1_next(id, a.seed, step_of(a.step, a.d_step), 0, nsub, W, a.dtd) : nsub;
-      flag = j0 < nsub;
-    } else {
-      flag = W > 0.0 && tau <= W * a.dtd;
-    }
-    const uint64_t fbits = __ballot(flag);   // the live lanes' flags (others are not emitters)
-    if (flag) {
-      EmRec<R> r;
-      r.x[0] = x; r.x[1] = y; r.x[2] = z; r.p[0] = px; r.p[1] = py; r.p[2] = pz;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) r.F[c] = F[c];
-      r.tau = tau;
-      r.chi = chi;
-      r.W = W;
-      r.j0 = j0;
-      r.nsub = nsub;
-      a.rec[rec_slot(i, fbits)] = r;
-    } else if (!(M1 && a.gen)) {
-      TAU[t] = tau - W * a.dtd;
+    for (int it = 0; it < IT; ++it) {
+      R F[6];
+      if (live[it]) field_at<R>(f, base + it * kGPThreads + t, xs[it][0], xs[it][1], xs[it][2], F);
+      finish(it, F, live[it]);
     }
   }
-  const uint64_t bits = __ballot(flag);
-  if ((t & 63) == 0 && base + (t & ~63) < n) a.mask[(base + t) >> 6] = bits;
-  count_flags(a.counters, cNanChi, nnan != 0);
-  count_flags(a.counters, cChiRange, nrange != 0);
 }
 
 // Ordered emitter list from the ballot mask: each thread owns W consecutive
@@ -1991,20 +2040,33 @@ static hipError_t zero_scan(qed_ctx *c, int64_t ntiles, hipStream_t st) {
   return zero_scan_at(c->d_ticket, c->d_status, c->status_len, ntiles, st);   // reserve() sizes it
 }
 
+// Blocks of a gather/push launch for a species of this capacity: every tile has
+// its block (chunks per XCD, times the chunk, times the 8 XCDs).
+template <typename R, int FK, bool M1>
+static unsigned gp_grid(int64_t capacity) {
+  const int64_t tile = (int64_t)kGPThreads * gp_items<R, FK, M1>();
+  const int64_t ntiles = (capacity + tile - 1) / tile;
+  const int64_t cpx = ((ntiles + kGPChunk - 1) / kGPChunk + kXcds - 1) / kXcds;
+  return (unsigned)(cpx * kGPChunk * kXcds);
+}
+
 template <typename R, bool M1>
-static void launch_gp_kind_m(const GPArgs<R> &a, int kind, unsigned grid, hipStream_t st) {
+static void launch_gp_kind_m(const GPArgs<R> &a, int kind, int64_t cap, hipStream_t st) {
   if (kind == QED_FIELD_GRID)
-    hipLaunchKernelGGL((k_gather_push<R, QED_FIELD_GRID, M1>), dim3(grid), dim3(kGPThreads), 0, st, a);
+    hipLaunchKernelGGL((k_gather_push<R, QED_FIELD_GRID, M1>), dim3(gp_grid<R, QED_FIELD_GRID, M1>(cap)),
+                       dim3(kGPThreads), 0, st, a);
   else if (kind == QED_FIELD_UNIFORM)
-    hipLaunchKernelGGL((k_gather_push<R, QED_FIELD_UNIFORM, M1>), dim3(grid), dim3(kGPThreads), 0, st, a);
+    hipLaunchKernelGGL((k_gather_push<R, QED_FIELD_UNIFORM, M1>), dim3(gp_grid<R, QED_FIELD_UNIFORM, M1>(cap)),
+                       dim3(kGPThreads), 0, st, a);
   else
-    hipLaunchKernelGGL((k_gather_push<R, QED_FIELD_PER_PARTICLE, M1>), dim3(grid), dim3(kGPThreads), 0, st, a);
+    hipLaunchKernelGGL((k_gather_push<R, QED_FIELD_PER_PARTICLE, M1>),
+                       dim3(gp_grid<R, QED_FIELD_PER_PARTICLE, M1>(cap)), dim3(kGPThreads), 0, st, a);
 }
 
 template <typename R>
-static void launch_gp_kind(const GPArgs<R> &a, int kind, unsigned grid, hipStream_t st) {
-  if (a.gen) launch_gp_kind_m<R, true>(a, kind, grid, st);
-  else launch_gp_kind_m<R, false>(a, kind, grid, st);
+static void launch_gp_kind(const GPArgs<R> &a, int kind, int64_t cap, hipStream_t st) {
+  if (a.gen) launch_gp_kind_m<R, true>(a, kind, cap, st);
+  else launch_gp_kind_m<R, false>(a, kind, cap, st);
 }
 
 static RetireDev retire_dev(const qed_ctx *c) {
@@ -2040,10 +2102,7 @@ hipError_t launch_gather_push(qed_ctx *c, const qed_fields_t *f, const qed_speci
                               double dt, int64_t step, hipStream_t st) {
   const int gen = gen_mode(c);
   const int64_t *dstep = step < 0 ? c->d_step : nullptr;
-  const int64_t ntiles = (sp->capacity + kGPTile - 1) / kGPTile;
-  // every tile below ntiles has its block: chunks per XCD times the chunk times 8
-  const int64_t cpx = ((ntiles + kGPChunk - 1) / kGPChunk + kXcds - 1) / kXcds;
-  const unsigned grid = (unsigned)(cpx * kGPChunk * kXcds);
+  const int64_t cap = sp->capacity;
   const bool use_mlp = (c->params.flags & QED_FLAG_SURROGATE) && sp->dtype == QED_F32;
   if (use_mlp) {
     // surrogate path: the same pass with the rate envelope (thinning); the
@@ -2051,20 +2110,22 @@ hipError_t launch_gather_push(qed_ctx *c, const qed_fields_t *f, const qed_speci
     GPArgs<float> a{dev_species(sp), dev_fields(f), c->rad_lnh32, (float)charge, (float)dt, dt, c->em_mask,
                     (EmRec<float> *)c->em_rec, c->d_counters, 0, c->params.seed, (uint64_t)step, dstep, c->range};
     if (f->kind == QED_FIELD_GRID)
-      hipLaunchKernelGGL((k_gather_push<float, QED_FIELD_GRID, false, true>), dim3(grid), dim3(kGPThreads), 0, st, a);
+      hipLaunchKernelGGL((k_gather_push<float, QED_FIELD_GRID, false, true>),
+                         dim3(gp_grid<float, QED_FIELD_GRID, false>(cap)), dim3(kGPThreads), 0, st, a);
     else if (f->kind == QED_FIELD_UNIFORM)
-      hipLaunchKernelGGL((k_gather_push<float, QED_FIELD_UNIFORM, false, true>), dim3(grid), dim3(kGPThreads), 0, st, a);
+      hipLaunchKernelGGL((k_gather_push<float, QED_FIELD_UNIFORM, false, true>),
+                         dim3(gp_grid<float, QED_FIELD_UNIFORM, false>(cap)), dim3(kGPThreads), 0, st, a);
     else
-      hipLaunchKernelGGL((k_gather_push<float, QED_FIELD_PER_PARTICLE, false, true>), dim3(grid), dim3(kGPThreads), 0,
-                         st, a);
+      hipLaunchKernelGGL((k_gather_push<float, QED_FIELD_PER_PARTICLE, false, true>),
+                         dim3(gp_grid<float, QED_FIELD_PER_PARTICLE, false>(cap)), dim3(kGPThreads), 0, st, a);
   } else if (sp->dtype == QED_F32) {
     GPArgs<float> a{dev_species(sp), dev_fields(f), c->rad_lnh32, (float)charge, (float)dt, dt, c->em_mask,
                     (EmRec<float> *)c->em_rec, c->d_counters, gen, c->params.seed, (uint64_t)step, dstep, c->range};
-    launch_gp_kind<float>(a, f->kind, grid, st);
+    launch_gp_kind<float>(a, f->kind, cap, st);
   } else {
     GPArgs<double> a{dev_species(sp), dev_fields(f), c->rad_lnh64, (double)charge, dt, dt, c->em_mask,
                      (EmRec<double> *)c->em_rec, c->d_counters, gen, c->params.seed, (uint64_t)step, dstep, c->range};
-    launch_gp_kind<double>(a, f->kind, grid, st);
+    launch_gp_kind<double>(a, f->kind, cap, st);
   }
   return hipGetLastError();
 }
