@@ -6,7 +6,7 @@ chi and optical depth, formula II tables, dt = 0.01.  One step = refill the grid
 for t = n dt, pair creation for every photon present, gather/push and emission
 for electrons and for positrons (photons appended), photon compaction every 10
 steps; electrons and positrons (on the table path photons too) re-sorted by
-cell every 14 steps (outside the captured graphs).  The step runs as captured hipGraphs, 500 steps in all, with
+cell every 12 steps (outside the captured graphs).  The step runs as captured hipGraphs, 500 steps in all, with
 the photon and positron populations growing in place.  It runs twice: with the
 surrogate networks (QED_FLAG_SURROGATE: rates and photon energies from the nets,
 candidate events by Poisson thinning, table fallback) and with the plain tables.
@@ -55,7 +55,7 @@ PROFILED_SOURCES = ("step.hip", "qed_device.h", "lookup.h")
 # the cascade configuration
 C5_N, C5_STEPS, C5_A0, C5_DT, C5_GRID, C5_SEED = 200_000_000, 500, 1000.0, 0.01, 128, 4
 C5_SUBSAMPLE = 100_000          # ids 0 .. 99999: drawn on the host, shared with the oracle
-C5_SORT_EVERY, C5_COMPACT_EVERY = 14, 10
+C5_SORT_EVERY, C5_COMPACT_EVERY = 12, 10
 # fixed-chi emission run of the 1e7-sample spectrum gate (chi ~ 1: b0 = 2000, gamma = 206)
 KS_N, KS_B0, KS_GAMMA, KS_DT, KS_STEPS = 1_000_000, 2000.0, 206.0, 0.05, 20
 
