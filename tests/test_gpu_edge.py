@@ -132,13 +132,14 @@ def test_converted_photons_are_not_converted_twice(pair_table):
     k = np.tile([gph, 0.0, 0.0], (n, 1))
     tau = np.full(n, 1e-6)                         # every photon converts in the first pass
     ids = np.arange(n, dtype=np.uint64)
-    for dt in ("f64",):
+    for dt in ("f64", "f32"):
         ph, el, po = q.Species(n, dt), q.Species(2 * n, dt), q.Species(2 * n, dt)
         ph.load(x, k, tau, ids)
         e0 = np.zeros((0, 3))
         el.load(e0, e0, np.zeros(0), np.zeros(0, np.uint64))
         po.load(e0, e0, np.zeros(0), np.zeros(0, np.uint64))
         ctx.qed_set_next_id(n)
+        ctx.qed_get_status(check=False)
         fld = q.Fields(q.QED_FIELD_UNIFORM, B=(0, 0, b))
         ctx.qed_create_pairs(fld, ph, el, po, 0.01, 0)
         first = ph.to_numpy()
@@ -156,3 +157,32 @@ def test_converted_photons_are_not_converted_twice(pair_table):
                            sampler=mc.PairSampler(pair_table, "f64"), next_id=2 * n)
         assert r["pairs"].size == 0
         np.testing.assert_array_equal(r["x"], first["x"])
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_pair_capacity_overflow_is_reported(dtype):
+    """More pairs than the lepton capacities: the first pairs in photon order are
+    kept (ids next_id + 2r and + 1), the rest are dropped and counted, the counts
+    stop at the capacities, every converted photon is dead and the status says
+    QED_ERR_CAPACITY."""
+    torch, q = need_gpu()
+    ctx = q.Context(seed=4)
+    ctx.qed_build_tables(q.QED_FORMULA_I)
+    n, cap, b, chi = 5000, 1234, 2000.0, 30.0
+    gph = chi * E_S / b
+    ph, el, po = q.Species(n, dtype), q.Species(cap, dtype), q.Species(cap, dtype)
+    ph.load(np.zeros((n, 3)), np.tile([gph, 0.0, 0.0], (n, 1)), np.full(n, 1e-6), np.arange(n, dtype=np.uint64))
+    e0 = np.zeros((0, 3))
+    el.load(e0, e0, np.zeros(0), np.zeros(0, np.uint64))
+    po.load(e0, e0, np.zeros(0), np.zeros(0, np.uint64))
+    ctx.qed_set_next_id(n)
+    fld = q.Fields(q.QED_FIELD_UNIFORM, B=(0, 0, b))
+    ctx.qed_create_pairs(fld, ph, el, po, 0.01, 0)
+    st, rc = ctx.qed_get_status(check=False)
+    assert rc == q.QED_ERR_CAPACITY
+    assert st["pairs"] == n and st["dropped"] == 2 * (n - cap)
+    assert el.n() == cap and po.n() == cap
+    np.testing.assert_array_equal(el.to_numpy()["id"], n + 2 * np.arange(cap, dtype=np.uint64))
+    np.testing.assert_array_equal(po.to_numpy()["id"], n + 1 + 2 * np.arange(cap, dtype=np.uint64))
+    assert np.all(ph.to_numpy()["id"] == mc.DEAD_ID)
+    assert ctx.qed_get_next_id() == n + 2 * n
