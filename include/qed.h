@@ -271,9 +271,13 @@ QED_API int qed_create_pairs(qed_ctx_t ctx, const qed_fields_t *fields, qed_spec
 /* Stable reordering of src into dst (caller-owned, same dtype, capacity >= src's)
    by the grid cell of each particle's nearest node, so that the quadratic-spline
    gather of neighbouring threads reads neighbouring nodes.  Key of node (i,j,k):
-   cells grouped in 4x4x4 blocks, blocks in z-major order and cells in z-major order
-   inside a block, i.e. ((k/4 * NBy + j/4) * NBx + i/4) * 64 + ((k%4) * 4 + j%4) * 4 + i%4
-   with NBx = ceil(nx/4), NBy = ceil(ny/4).  Ids, optical depths
+   cells grouped in 4x4x4 blocks, blocks along the Morton curve of their
+   coordinates (i/4, j/4, k/4) (bit b of i/4, j/4, k/4 to bits 3b, 3b+1, 3b+2) and
+   cells in z-major order inside a block: Morton(i/4, j/4, k/4) * 64 +
+   ((k%4) * 4 + j%4) * 4 + i%4.  Grids with more than 256 blocks along an axis
+   (3 bits per block-coordinate bit would overflow the 32-bit key) order the
+   blocks z-major instead: ((k/4 * NBy + j/4) * NBx + i/4), NBx = ceil(nx/4),
+   NBy = ceil(ny/4).  Ids, optical depths
    and therefore every random stream move with the particles.  A periodic sort is
    what keeps qed_gather_push's field reads local.  Sorts the *count particles
    present: reads the count from the device, which synchronises `stream`.

@@ -5,6 +5,7 @@
 // every random stream, travel with the particles, so the physics is unchanged;
 // only the storage order (and with it the append order) changes.
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <rocprim/device/device_radix_sort.hpp>
 
 #include "internal.h"
@@ -18,9 +19,24 @@ namespace {
 // stages in LDS.
 constexpr int kBlk = 4;
 
+// Bits of v (below 2^10) spread to every third position (bit k to bit 3k).
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {
+  v &= 0x3FFu;
+  v = (v | (v << 16)) & 0x030000FFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+// Key of a particle: block of kBlk^3 cells, then the cell inside the block
+// (z-major).  Blocks follow the Morton (Z-order) curve of their coordinates
+// when morton != 0 (x in the lowest bit of each triple), so that neighbouring
+// blocks lie close in the sorted order in every direction; otherwise z-major.
 template <typename R>
 __global__ void k_cell_keys(const R *x, const R *y, const R *z, const int64_t *count, int64_t cap, int nx,
-                            int ny, int nz, double dx, double dy, double dz, uint32_t *keys, uint32_t *vals) {
+                            int ny, int nz, double dx, double dy, double dz, int morton, uint32_t *keys,
+                            uint32_t *vals) {
   const int64_t n = *count;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cap; i += (int64_t)gridDim.x * blockDim.x) {
     uint32_t key = 0xFFFFFFFFu;
@@ -31,9 +47,10 @@ __global__ void k_cell_keys(const R *x, const R *y, const R *z, const int64_t *c
       jy = jy < 0 ? 0 : (jy >= ny ? jy - ny : jy);
       jz = jz < 0 ? 0 : (jz >= nz ? jz - nz : jz);
       jx = jx >= nx ? nx - 1 : jx; jy = jy >= ny ? ny - 1 : jy; jz = jz >= nz ? nz - 1 : jz;
-      // blocks of kBlk^3 cells in z-major order, cells z-major inside a block
       const int nbx = (nx + kBlk - 1) / kBlk, nby = (ny + kBlk - 1) / kBlk;
-      const uint32_t blk = (uint32_t)(((jz / kBlk) * nby + jy / kBlk) * nbx + jx / kBlk);
+      const uint32_t bx = (uint32_t)(jx / kBlk), by = (uint32_t)(jy / kBlk), bz = (uint32_t)(jz / kBlk);
+      const uint32_t blk = morton ? spread3(bx) | (spread3(by) << 1) | (spread3(bz) << 2)
+                                  : (bz * (uint32_t)nby + by) * (uint32_t)nbx + bx;
       key = blk * (uint32_t)(kBlk * kBlk * kBlk) + (uint32_t)(((jz % kBlk) * kBlk + jy % kBlk) * kBlk + jx % kBlk);
     }
     keys[i] = key;
@@ -69,14 +86,24 @@ hipError_t sort_impl(qed_ctx *c, const qed_fields_t *f, const qed_species_t *s, 
   int64_t blocks = (cap + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   uint32_t *k0 = c->sort_keys, *k1 = c->sort_keys + cap, *v0 = c->sort_vals, *v1 = c->sort_vals + cap;
+  // Morton order of the blocks when its codes (3 bits per bit of the largest
+  // block coordinate) and the 6 cell bits fit the 32-bit key
+  const int nbmax = std::max((f->nx + kBlk - 1) / kBlk, std::max((f->ny + kBlk - 1) / kBlk, (f->nz + kBlk - 1) / kBlk));
+  unsigned mb = 0;
+  while ((1 << mb) < nbmax) ++mb;
+  const int morton = 3 * mb + 6 <= 31 ? 1 : 0;
   hipLaunchKernelGGL(k_cell_keys<R>, dim3((unsigned)blocks), dim3(256), 0, st, (const R *)s->x, (const R *)s->y,
-                     (const R *)s->z, s->count, cap, f->nx, f->ny, f->nz, f->dx, f->dy, f->dz, k0, v0);
+                     (const R *)s->z, s->count, cap, f->nx, f->ny, f->nz, f->dx, f->dy, f->dz, morton, k0, v0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const uint64_t cells = (uint64_t)((f->nx + kBlk - 1) / kBlk) * ((f->ny + kBlk - 1) / kBlk) *
                         ((f->nz + kBlk - 1) / kBlk) * (kBlk * kBlk * kBlk);
   unsigned bits = 1;
-  while ((1ull << bits) <= cells) ++bits;
+  if (morton) {
+    bits = 3 * mb + 6;                          // keys below 2^bits
+  } else {
+    while ((1ull << bits) <= cells) ++bits;
+  }
   ++bits;   // the all-ones sentinel of unused slots sorts last
   if (bits > 32) bits = 32;
   size_t need = 0;

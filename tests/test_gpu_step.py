@@ -542,10 +542,21 @@ def test_pair_spectrum_and_yield_1e7(pair_table):
     assert ks1 < 2e-3 and ks2 < 2e-3
 
 
+def _morton3(bx, by, bz, bits):
+    """Morton code with x in the lowest bit of each triple (bit loop)."""
+    code = np.zeros_like(bx)
+    for k in range(bits):
+        code |= ((bx >> k) & 1) << (3 * k)
+        code |= ((by >> k) & 1) << (3 * k + 1)
+        code |= ((bz >> k) & 1) << (3 * k + 2)
+    return code
+
+
 def test_sort_by_cell_stable_permutation():
     """qed_sort_by_cell: destination = source permuted by a stable sort of the
-    nearest-node cell key (4x4x4 blocks in z-major order, cells z-major inside a
-    block); counts and every array travel together."""
+    nearest-node cell key (4x4x4 blocks along the Morton curve of their
+    coordinates, cells z-major inside a block); counts and every array travel
+    together."""
     torch, q = need_gpu()
     ctx = q.Context()
     n, cap, ng, L = 100003, 120000, 30, workloads.BOX_L
@@ -565,7 +576,8 @@ def test_sort_by_cell_stable_permutation():
     j = np.floor(x / d + 0.5).astype(np.int64)
     j[j >= ng] -= ng
     nb = (ng + 3) // 4
-    blk = ((j[:, 2] // 4) * nb + j[:, 1] // 4) * nb + j[:, 0] // 4
+    mbits = int(np.ceil(np.log2(nb)))
+    blk = _morton3(j[:, 0] // 4, j[:, 1] // 4, j[:, 2] // 4, mbits)
     key = blk * 64 + ((j[:, 2] % 4) * 4 + j[:, 1] % 4) * 4 + j[:, 0] % 4
     order = np.argsort(key, kind="stable")
     assert b.n() == n
