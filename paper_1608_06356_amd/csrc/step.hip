@@ -581,154 +581,204 @@ __device__ __forceinline__ int method1_next(uint64_t id, uint32_t seed, uint64_t
   return N;
 }
 
-// Waves per SIMD the compiler must allow for (bounds the registers), and
-// particles per thread: the single-precision grid kernel without method I is
-// the hot one; it takes two particles per thread, so that the workgroup's
-// fixed work (the box's extent, its staging and the barriers) is shared by 512
-// particles.
+// Waves per SIMD the compiler must allow for (bounds the registers): the
+// single-precision grid kernel without method I is the hot one.
 template <typename R, int FK, bool M1> constexpr int gp_waves() {
-  return (sizeof(R) == 4 && FK == QED_FIELD_GRID && !M1) ? kGPWaves - 1 : 1;   // two particles: 102 registers
-}
-template <typename R, int FK, bool M1> constexpr int gp_items() {
-  return (sizeof(R) == 4 && FK == QED_FIELD_GRID && !M1) ? 2 : 1;
+  return (sizeof(R) == 4 && FK == QED_FIELD_GRID && !M1) ? kGPWaves : 1;
 }
 
-// M1: compiled with the method I generator (a.gen != 0), else optical depth only.
-// Thin (float32, surrogate path): the optical depth runs down at the envelope
-// rate h_rad_env (Poisson thinning); the emission pass evaluates the rate net
-// only at the candidate events this finds and keeps each with probability
-// W / W_env.  Particle it of thread t is base + it * kGPThreads + t.
+// First particle of this workgroup's tile, for tiles of `tile_size` particles
+// dealt to the XCDs in chunks of kGPChunk tiles.
+__device__ __forceinline__ int64_t gp_tile_base(int64_t tile_size) {
+  const int64_t k = blockIdx.x / kXcds;
+  return (((k / kGPChunk) * kXcds + blockIdx.x % kXcds) * kGPChunk + k % kGPChunk) * tile_size;
+}
+
+template <typename R>
+struct GPTile {   // the tile's slices of the particle arrays (uniform bases, 32-bit offsets)
+  R *x, *y, *z, *px, *py, *pz;
+  double *tau;
+  __device__ GPTile(const SpeciesDev &sp, int64_t base)
+      : x((R *)sp.x + base), y((R *)sp.y + base), z((R *)sp.z + base), px((R *)sp.px + base),
+        py((R *)sp.py + base), pz((R *)sp.pz + base), tau(sp.tau + base) {}
+};
+
+// Push, chi, rate and event decision of particle o of the tile (offset from
+// base; ok: present, with fields F): a particle with non-finite fields is
+// skipped and counted; the others are written back, with either the record of
+// their first event within the step or their reduced optical depth.  Then the
+// wave's mask word and counters.  Every lane of the wave calls it (the record
+// slot is ranked among the wave's emitters).
+template <typename R, int FK, bool M1, bool Thin>
+__device__ __forceinline__ void gp_finish(const GPArgs<R> &a, const GPTile<R> &P, const FieldDev &f,
+                                          const R *lnh_s, int64_t base, int o, int64_t n, bool ok, R x, R y, R z,
+                                          R px, R py, R pz, double tau, const R F[6]) {
+  const int64_t i = base + o;
+  bool flag = false, nan = false, range = false;
+  if (ok && !fields_finite<R>(F)) { ok = false; nan = true; }
+  if (ok) {
+    boris<R>(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5], a.q, a.dt);
+    const R g = root<R>((R)1 + px * px + py * py + pz * pz);
+    const R ig = rcp<R>(g), vdt = ig * a.dt;
+    x += px * vdt; y += py * vdt; z += pz * vdt;
+    if (FK == QED_FIELD_GRID) {
+      wrap_coord<R>(x, box_len<R>(f, 0)); wrap_coord<R>(y, box_len<R>(f, 1));
+      wrap_coord<R>(z, box_len<R>(f, 2));
+    }
+    P.x[o] = x; P.y[o] = y; P.z[o] = z; P.px[o] = px; P.py[o] = py; P.pz[o] = pz;
+    double chi;
+    if constexpr (sizeof(R) == 4) chi = chi_lepton_f32(px, py, pz, F);
+    else chi = chi_lepton(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5]);
+    double W = 0.0;
+    if (isfinite(chi)) {
+      range = chi > a.rg.rad_hi;
+      R h;
+      if constexpr (Thin) h = (R)h_rad_env((float)chi);
+      else h = h_rad<R, true>((R)chi, lnh_s, a.rg);
+      W = kRateUnit * (double)(h * ig);
+    } else {
+      nan = true;
+    }
+    int j0 = 0, nsub = 1;
+    if (M1 && a.gen) {
+      // method I: first sub-step with an event, if any
+      const uint64_t id = a.sp.id[i];
+      nsub = method1_nsub(W, a.dtd, a.gen);
+      j0 = W > 0.0 ? method1_next(id, a.seed, step_of(a.step, a.d_step), 0, nsub, W, a.dtd) : nsub;
+      flag = j0 < nsub;
+    } else {
+      flag = W > 0.0 && tau <= W * a.dtd;
+    }
+    const uint64_t fbits = __ballot(flag);   // the live lanes' flags (others are not emitters)
+    if (flag) {
+      EmRec<R> r;
+      r.x[0] = x; r.x[1] = y; r.x[2] = z; r.p[0] = px; r.p[1] = py; r.p[2] = pz;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) r.F[c] = F[c];
+      r.tau = tau;
+      r.chi = chi;
+      r.W = W;
+      r.j0 = j0;
+      r.nsub = nsub;
+      a.rec[rec_slot(i, fbits)] = r;
+    } else if (!(M1 && a.gen)) {
+      P.tau[o] = tau - W * a.dtd;
+    }
+  }
+  const uint64_t bits = __ballot(flag);
+  if ((threadIdx.x & 63) == 0 && base + (o & ~63) < n) a.mask[(base + o) >> 6] = bits;
+  count_flags(a.counters, cNanChi, nan);
+  count_flags(a.counters, cChiRange, range);
+}
+
+// One particle per thread.  M1: compiled with the method I generator
+// (a.gen != 0), else optical depth only.  Thin (float32, surrogate path): the
+// optical depth runs down at the envelope rate h_rad_env (Poisson thinning);
+// the emission pass evaluates the rate net only at the candidate events this
+// finds and keeps each with probability W / W_env.
 template <typename R, int FK, bool M1, bool Thin = false>
 __global__ __launch_bounds__(kGPThreads, (gp_waves<R, FK, M1>())) void k_gather_push(GPArgs<R> a) {
-  constexpr int IT = gp_items<R, FK, M1>();
-  constexpr int64_t kTile = (int64_t)kGPThreads * IT;
   __shared__ R lnh_s[kRadNChi];
   // (the grid is sized by the capacity: blocks beyond the particles present
   // return, and they are the last ones dispatched)
   const int64_t n = *a.sp.count;
-  const int64_t k = blockIdx.x / kXcds;
-  const int64_t tile = ((k / kGPChunk) * kXcds + blockIdx.x % kXcds) * kGPChunk + k % kGPChunk;
-  const int64_t base = tile * kTile;
+  const int64_t base = gp_tile_base(kGPThreads);
   if (base >= n) return;
-  // the tile's slices of the arrays (uniform bases, 32-bit thread offsets)
   const int t = threadIdx.x;
-  R *X = (R *)a.sp.x + base, *Y = (R *)a.sp.y + base, *Z = (R *)a.sp.z + base;
-  R *PX = (R *)a.sp.px + base, *PY = (R *)a.sp.py + base, *PZ = (R *)a.sp.pz + base;
-  double *TAU = a.sp.tau + base;
+  const int64_t i = base + t;
   FieldDev f = a.f;
   f.kind = FK;
+  const bool live = i < n;
+  // every load of the particle is issued up front, to overlap with the staging
+  R x = 0, y = 0, z = 0, px = 0, py = 0, pz = 0;
+  double tau = 0.0;
+  const GPTile<R> P(a.sp, base);
+  if (live) {
+    x = P.x[t]; y = P.y[t]; z = P.z[t];
+    px = P.px[t]; py = P.py[t]; pz = P.pz[t];
+    tau = P.tau[t];
+  }
+  for (int q = threadIdx.x; q < kRadNChi; q += blockDim.x) lnh_s[q] = a.lnh[q];
+  R F[6];
+  if (FK == QED_FIELD_GRID) {
+    __shared__ BoxLds box_s;
+    int j[1][3], rel[1][3], pit[2];
+    R w[3][3];
+    tsc_setup<R>(f, x, y, z, j[0], w);      // dead lanes hold x = 0: harmless, unused
+    if (stage_box<1>(box_s, f, &live, j, rel, pit)) {   // its barriers also publish lnh_s
+      if (live) gather_box<R>(box_s, rel[0], pit, w, F);
+    } else {
+      if (live) gather_global<R>(f, j[0], w, F);
+      if (threadIdx.x == 0) atomicAdd(&a.counters[cBoxFallback], 1ull);
+    }
+  } else {
+    __syncthreads();
+    if (live) field_at<R>(f, i, x, y, z, F);
+  }
+  gp_finish<R, FK, M1, Thin>(a, P, f, lnh_s, base, t, n, live, x, y, z, px, py, pz, tau, F);
+}
+
+// Dense float32 species on a grid, optical depth only (the launcher takes it
+// for species sized for at least kDenseGP particles per cell): two particles
+// per thread, particle it of thread t at base + it * kGPThreads + t, so that
+// the workgroup's fixed work (the box's extent, its staging and the barriers)
+// is shared by 512 particles.  A sparse species' 512 particles span too many
+// cells for one box, so it keeps the kernel above.
+constexpr int64_t kDenseGP = 64;
+template <bool Thin>
+__global__ __launch_bounds__(kGPThreads, kGPWaves - 1) void k_gather_push2(GPArgs<float> a) {
+  using R = float;
+  constexpr int IT = 2;
+  __shared__ R lnh_s[kRadNChi];
+  __shared__ BoxLds box_s;
+  const int64_t n = *a.sp.count;
+  const int64_t base = gp_tile_base((int64_t)kGPThreads * IT);
+  if (base >= n) return;
+  const int t = threadIdx.x;
+  FieldDev f = a.f;
+  f.kind = QED_FIELD_GRID;
   bool live[IT];
   // every load of the thread's particles is issued up front, to overlap with the staging
   R xs[IT][3], ps[IT][3];
   double taus[IT];
+  const GPTile<R> P(a.sp, base);
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
     const int o = it * kGPThreads + t;
     live[it] = base + o < n;
-    xs[it][0] = live[it] ? X[o] : (R)0; xs[it][1] = live[it] ? Y[o] : (R)0; xs[it][2] = live[it] ? Z[o] : (R)0;
-    ps[it][0] = live[it] ? PX[o] : (R)0; ps[it][1] = live[it] ? PY[o] : (R)0; ps[it][2] = live[it] ? PZ[o] : (R)0;
-    taus[it] = live[it] ? TAU[o] : 0.0;
+    xs[it][0] = live[it] ? P.x[o] : (R)0; xs[it][1] = live[it] ? P.y[o] : (R)0; xs[it][2] = live[it] ? P.z[o] : (R)0;
+    ps[it][0] = live[it] ? P.px[o] : (R)0; ps[it][1] = live[it] ? P.py[o] : (R)0;
+    ps[it][2] = live[it] ? P.pz[o] : (R)0;
+    taus[it] = live[it] ? P.tau[o] : 0.0;
   }
   for (int q = threadIdx.x; q < kRadNChi; q += blockDim.x) lnh_s[q] = a.lnh[q];
 
-  // push, chi, rate and event decision of particle it, with its fields F
-  auto finish = [&](int it, R F[6], bool ok) {
-    const int o = it * kGPThreads + t;
-    const int64_t i = base + o;
-    bool flag = false, nan = false, range = false;
-    if (ok && !fields_finite<R>(F)) { ok = false; nan = true; }   // skipped and counted
-    if (ok) {
-      R px = ps[it][0], py = ps[it][1], pz = ps[it][2], x = xs[it][0], y = xs[it][1], z = xs[it][2];
-      const double tau = taus[it];
-      boris<R>(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5], a.q, a.dt);
-      const R g = root<R>((R)1 + px * px + py * py + pz * pz);
-      const R ig = rcp<R>(g), vdt = ig * a.dt;
-      x += px * vdt; y += py * vdt; z += pz * vdt;
-      if (FK == QED_FIELD_GRID) {
-        wrap_coord<R>(x, box_len<R>(f, 0)); wrap_coord<R>(y, box_len<R>(f, 1));
-        wrap_coord<R>(z, box_len<R>(f, 2));
-      }
-      X[o] = x; Y[o] = y; Z[o] = z; PX[o] = px; PY[o] = py; PZ[o] = pz;
-      double chi;
-      if constexpr (sizeof(R) == 4) chi = chi_lepton_f32(px, py, pz, F);
-      else chi = chi_lepton(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5]);
-      double W = 0.0;
-      if (isfinite(chi)) {
-        range = chi > a.rg.rad_hi;
-        R h;
-        if constexpr (Thin) h = (R)h_rad_env((float)chi);
-        else h = h_rad<R, true>((R)chi, lnh_s, a.rg);
-        W = kRateUnit * (double)(h * ig);
-      } else {
-        nan = true;
-      }
-      int j0 = 0, nsub = 1;
-      if (M1 && a.gen) {
-        // method I: first sub-step with an event, if any
-        const uint64_t id = a.sp.id[i];
-        nsub = method1_nsub(W, a.dtd, a.gen);
-        j0 = W > 0.0 ? method1_next(id, a.seed, step_of(a.step, a.d_step), 0, nsub, W, a.dtd) : nsub;
-        flag = j0 < nsub;
-      } else {
-        flag = W > 0.0 && tau <= W * a.dtd;
-      }
-      const uint64_t fbits = __ballot(flag);   // the live lanes' flags (others are not emitters)
-      if (flag) {
-        EmRec<R> r;
-        r.x[0] = x; r.x[1] = y; r.x[2] = z; r.p[0] = px; r.p[1] = py; r.p[2] = pz;
+  int j[IT][3], rel[IT][3], pit[2];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) r.F[c] = F[c];
-        r.tau = tau;
-        r.chi = chi;
-        r.W = W;
-        r.j0 = j0;
-        r.nsub = nsub;
-        a.rec[rec_slot(i, fbits)] = r;
-      } else if (!(M1 && a.gen)) {
-        TAU[o] = tau - W * a.dtd;
-      }
-    }
-    const uint64_t bits = __ballot(flag);
-    if ((t & 63) == 0 && base + (o & ~63) < n) a.mask[(base + o) >> 6] = bits;
-    count_flags(a.counters, cNanChi, nan);
-    count_flags(a.counters, cChiRange, range);
-  };
-
-  if (FK == QED_FIELD_GRID) {
-    __shared__ BoxLds box_s;
-    int j[IT][3], rel[IT][3], pit[2];
+  for (int it = 0; it < IT; ++it) {
+    R w[3][3];
+    tsc_setup<R>(f, xs[it][0], xs[it][1], xs[it][2], j[it], w);   // dead particles hold x = 0: unused
+  }
+  const bool boxed = stage_box<IT>(box_s, f, live, j, rel, pit);   // its barriers also publish lnh_s
+  if (!boxed && threadIdx.x == 0) atomicAdd(&a.counters[cBoxFallback], 1ull);
 #pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      R w[3][3];
-      tsc_setup<R>(f, xs[it][0], xs[it][1], xs[it][2], j[it], w);   // dead particles hold x = 0: unused
+  for (int it = 0; it < IT; ++it) {
+    // one particle after the other, the weights recomputed from the position
+    // (held opaque, so that they are not kept live across the staging): two
+    // gathers in flight together, or weights held through the staging, would
+    // need more registers than five waves leave
+    R x = xs[it][0], y = xs[it][1], z = xs[it][2];
+    asm volatile("" : "+v"(x), "+v"(y), "+v"(z));
+    int jc[3];
+    R w[3][3];
+    tsc_setup<R>(f, x, y, z, jc, w);
+    R F[6];
+    if (live[it]) {
+      if (boxed) gather_box<R>(box_s, rel[it], pit, w, F);
+      else gather_global<R>(f, jc, w, F);
     }
-    const bool boxed = stage_box<IT>(box_s, f, live, j, rel, pit);   // its barriers also publish lnh_s
-    if (!boxed && threadIdx.x == 0) atomicAdd(&a.counters[cBoxFallback], 1ull);
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      // one particle after the other, the weights recomputed from the position
-      // (held opaque, so that they are not kept from above): the two gathers
-      // in flight together would need more registers than five waves leave
-      R x = xs[it][0], y = xs[it][1], z = xs[it][2];
-      if (IT > 1) asm volatile("" : "+v"(x), "+v"(y), "+v"(z));
-      int jc[3];
-      R w[3][3];
-      tsc_setup<R>(f, x, y, z, jc, w);
-      R F[6];
-      if (live[it]) {
-        if (boxed) gather_box<R>(box_s, rel[it], pit, w, F);
-        else gather_global<R>(f, jc, w, F);
-      }
-      finish(it, F, live[it]);
-    }
-  } else {
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      R F[6];
-      if (live[it]) field_at<R>(f, base + it * kGPThreads + t, xs[it][0], xs[it][1], xs[it][2], F);
-      finish(it, F, live[it]);
-    }
+    gp_finish<R, QED_FIELD_GRID, false, Thin>(a, P, f, lnh_s, base, it * kGPThreads + t, n, live[it], xs[it][0],
+                                              xs[it][1], xs[it][2], ps[it][0], ps[it][1], ps[it][2], taus[it], F);
   }
 }
 
@@ -2040,33 +2090,46 @@ static hipError_t zero_scan(qed_ctx *c, int64_t ntiles, hipStream_t st) {
   return zero_scan_at(c->d_ticket, c->d_status, c->status_len, ntiles, st);   // reserve() sizes it
 }
 
-// Blocks of a gather/push launch for a species of this capacity: every tile has
-// its block (chunks per XCD, times the chunk, times the 8 XCDs).
-template <typename R, int FK, bool M1>
-static unsigned gp_grid(int64_t capacity) {
-  const int64_t tile = (int64_t)kGPThreads * gp_items<R, FK, M1>();
+// Blocks of a gather/push launch for a species of this capacity, IT particles
+// per thread: every tile has its block (chunks per XCD, times the chunk, times
+// the 8 XCDs).
+static unsigned gp_grid(int64_t capacity, int it) {
+  const int64_t tile = (int64_t)kGPThreads * it;
   const int64_t ntiles = (capacity + tile - 1) / tile;
   const int64_t cpx = ((ntiles + kGPChunk - 1) / kGPChunk + kXcds - 1) / kXcds;
   return (unsigned)(cpx * kGPChunk * kXcds);
 }
 
-template <typename R, bool M1>
-static void launch_gp_kind_m(const GPArgs<R> &a, int kind, int64_t cap, hipStream_t st) {
-  if (kind == QED_FIELD_GRID)
-    hipLaunchKernelGGL((k_gather_push<R, QED_FIELD_GRID, M1>), dim3(gp_grid<R, QED_FIELD_GRID, M1>(cap)),
+// Two particles per thread (k_gather_push2) for a dense float32 species on a grid.
+static bool gp_dense(const qed_fields_t *f, const qed_species_t *sp) {
+  return sp->dtype == QED_F32 && f->kind == QED_FIELD_GRID &&
+         sp->capacity >= kDenseGP * (int64_t)f->nx * f->ny * f->nz;
+}
+
+template <typename R, bool M1, bool Thin>
+static void launch_gp_kind_m(const GPArgs<R> &a, int kind, int64_t cap, bool dense, hipStream_t st) {
+  if (kind == QED_FIELD_GRID) {
+    if constexpr (sizeof(R) == 4 && !M1) {
+      if (dense) {
+        hipLaunchKernelGGL((k_gather_push2<Thin>), dim3(gp_grid(cap, 2)), dim3(kGPThreads), 0, st, a);
+        return;
+      }
+    }
+    hipLaunchKernelGGL((k_gather_push<R, QED_FIELD_GRID, M1, Thin>), dim3(gp_grid(cap, 1)), dim3(kGPThreads), 0, st,
+                       a);
+  } else if (kind == QED_FIELD_UNIFORM) {
+    hipLaunchKernelGGL((k_gather_push<R, QED_FIELD_UNIFORM, M1, Thin>), dim3(gp_grid(cap, 1)), dim3(kGPThreads), 0,
+                       st, a);
+  } else {
+    hipLaunchKernelGGL((k_gather_push<R, QED_FIELD_PER_PARTICLE, M1, Thin>), dim3(gp_grid(cap, 1)),
                        dim3(kGPThreads), 0, st, a);
-  else if (kind == QED_FIELD_UNIFORM)
-    hipLaunchKernelGGL((k_gather_push<R, QED_FIELD_UNIFORM, M1>), dim3(gp_grid<R, QED_FIELD_UNIFORM, M1>(cap)),
-                       dim3(kGPThreads), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_gather_push<R, QED_FIELD_PER_PARTICLE, M1>),
-                       dim3(gp_grid<R, QED_FIELD_PER_PARTICLE, M1>(cap)), dim3(kGPThreads), 0, st, a);
+  }
 }
 
 template <typename R>
-static void launch_gp_kind(const GPArgs<R> &a, int kind, int64_t cap, hipStream_t st) {
-  if (a.gen) launch_gp_kind_m<R, true>(a, kind, cap, st);
-  else launch_gp_kind_m<R, false>(a, kind, cap, st);
+static void launch_gp_kind(const GPArgs<R> &a, int kind, int64_t cap, bool dense, hipStream_t st) {
+  if (a.gen) launch_gp_kind_m<R, true, false>(a, kind, cap, dense, st);
+  else launch_gp_kind_m<R, false, false>(a, kind, cap, dense, st);
 }
 
 static RetireDev retire_dev(const qed_ctx *c) {
@@ -2109,23 +2172,15 @@ hipError_t launch_gather_push(qed_ctx *c, const qed_fields_t *f, const qed_speci
     // emission pass evaluates the nets at the candidates
     GPArgs<float> a{dev_species(sp), dev_fields(f), c->rad_lnh32, (float)charge, (float)dt, dt, c->em_mask,
                     (EmRec<float> *)c->em_rec, c->d_counters, 0, c->params.seed, (uint64_t)step, dstep, c->range};
-    if (f->kind == QED_FIELD_GRID)
-      hipLaunchKernelGGL((k_gather_push<float, QED_FIELD_GRID, false, true>),
-                         dim3(gp_grid<float, QED_FIELD_GRID, false>(cap)), dim3(kGPThreads), 0, st, a);
-    else if (f->kind == QED_FIELD_UNIFORM)
-      hipLaunchKernelGGL((k_gather_push<float, QED_FIELD_UNIFORM, false, true>),
-                         dim3(gp_grid<float, QED_FIELD_UNIFORM, false>(cap)), dim3(kGPThreads), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_gather_push<float, QED_FIELD_PER_PARTICLE, false, true>),
-                         dim3(gp_grid<float, QED_FIELD_PER_PARTICLE, false>(cap)), dim3(kGPThreads), 0, st, a);
+    launch_gp_kind_m<float, false, true>(a, f->kind, cap, gp_dense(f, sp), st);
   } else if (sp->dtype == QED_F32) {
     GPArgs<float> a{dev_species(sp), dev_fields(f), c->rad_lnh32, (float)charge, (float)dt, dt, c->em_mask,
                     (EmRec<float> *)c->em_rec, c->d_counters, gen, c->params.seed, (uint64_t)step, dstep, c->range};
-    launch_gp_kind<float>(a, f->kind, cap, st);
+    launch_gp_kind<float>(a, f->kind, cap, gp_dense(f, sp), st);
   } else {
     GPArgs<double> a{dev_species(sp), dev_fields(f), c->rad_lnh64, (double)charge, dt, dt, c->em_mask,
                      (EmRec<double> *)c->em_rec, c->d_counters, gen, c->params.seed, (uint64_t)step, dstep, c->range};
-    launch_gp_kind<double>(a, f->kind, cap, st);
+    launch_gp_kind<double>(a, f->kind, cap, false, st);
   }
   return hipGetLastError();
 }
