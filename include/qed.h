@@ -234,7 +234,9 @@ QED_API int qed_fill_standing_wave_at_step(qed_ctx_t ctx, float *grid, int n, do
    step are flagged in the context's emitter mask (one bit per particle) and their
    record (fields seen, chi, W, time left after the first event) is kept at their
    index; qed_emit_photons lists them in index order and finishes them.  One kernel
-   launch.  Fails with QED_ERR_STATE if the tables are missing. */
+   launch: two particles per thread for a float32 species on a GRID whose capacity
+   is at least 64 particles per cell, one otherwise (the results are the same).
+   Fails with QED_ERR_STATE if the tables are missing. */
 QED_API int qed_gather_push(qed_ctx_t ctx, const qed_fields_t *fields, qed_species_t *leptons,
                     int charge, double dt, int64_t step, void *stream);
 
