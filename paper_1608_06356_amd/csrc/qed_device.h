@@ -139,6 +139,32 @@ __device__ __forceinline__ double chi_lepton_f32(float px, float py, float pz, c
   return sqrt_nr(g2 * (ux * ux + uy * uy + uz * uz) + ne * ne) * kInvES;
 }
 
+// Upper bound of chi_e (Eq. 2) in float32 arithmetic, for the envelope of the
+// thinned lepton pass, which needs a bound and not the value (the candidates'
+// chi is evaluated in float64 where they are finished).  With a = gamma E + p x B
+// and s = p.E, chi E_S = sqrt(|a|^2 - s^2) for the same inputs.  With u = 2^-24,
+// each component of a is off by at most 6u times the sum A of the magnitudes of
+// its three terms (gamma = sqrt(1 + p^2) itself within 3u), s by at most 3u
+// times its own such sum S, so |a|^2 - s^2 is within 17u (A_x^2 + A_y^2 + A_z^2
+// + S^2) of the exact value (|a_x| <= A_x, |s| <= S); 32u times that sum is
+// added before the root, whose rounding and the scaling are covered by a factor
+// 1 + 2^-20.  Where E and -v x B nearly cancel
+// the bound exceeds chi by up to ~1e-3 gamma |E| / E_S, elsewhere by ~1e-6
+// relative.
+__device__ __forceinline__ float chi_lepton_upper_f32(float px, float py, float pz, float g, const float F[6]) {
+  const float ex = F[0], ey = F[1], ez = F[2], bx = F[3], by = F[4], bz = F[5];
+  const float ax = g * ex + (py * bz - pz * by), ay = g * ey + (pz * bx - px * bz),
+              az = g * ez + (px * by - py * bx);
+  const float s = px * ex + py * ey + pz * ez;
+  const float Ax = fabsf(g * ex) + fabsf(py * bz) + fabsf(pz * by);
+  const float Ay = fabsf(g * ey) + fabsf(pz * bx) + fabsf(px * bz);
+  const float Az = fabsf(g * ez) + fabsf(px * by) + fabsf(py * bx);
+  const float S = fabsf(px * ex) + fabsf(py * ey) + fabsf(pz * ez);
+  const float T = ax * ax + ay * ay + az * az - s * s;
+  const float D = 0x1p-19f * (Ax * Ax + Ay * Ay + Az * Az + S * S);
+  return __builtin_amdgcn_sqrtf(fmaxf(T + D, 0.f)) * (float)(kInvES * (1.0 + 0x1p-20));
+}
+
 // Eq. (3) for the float32 step (inputs k, E, B float32, exact in float64), all
 // in float64 like chi_lepton_f32: k^ from the refined reciprocal square root,
 // gamma_ph = |k| = k^2 / |k|, E + k^ x B and the (refined) root in float64.

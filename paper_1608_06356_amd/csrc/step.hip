@@ -538,7 +538,7 @@ constexpr int64_t kGPChunk = 32;
 template <typename R>
 struct alignas(16) EmRec {
   R x[3], p[3], F[6];       // position after the push, momentum p^{n+1/2}, E and B at x^n
-  double tau, chi, W;       // optical depth at the start of the step, chi and rate
+  double tau, chi, W;       // optical depth at the start of the step, chi (thinned pass: its bound) and rate
   int32_t j0, nsub;         // method I: sub-step of the first event, number of sub-steps
 };
 
@@ -626,8 +626,11 @@ __device__ __forceinline__ void gp_finish(const GPArgs<R> &a, const GPTile<R> &P
       wrap_coord<R>(z, box_len<R>(f, 2));
     }
     P.x[o] = x; P.y[o] = y; P.z[o] = z; P.px[o] = px; P.py[o] = py; P.pz[o] = pz;
+    // Thin: the envelope needs only an upper bound of chi (float32 with its
+    // rounding bound); the emission pass evaluates chi itself for the candidates
     double chi;
-    if constexpr (sizeof(R) == 4) chi = chi_lepton_f32(px, py, pz, F);
+    if constexpr (Thin) chi = (double)chi_lepton_upper_f32(px, py, pz, g, F);
+    else if constexpr (sizeof(R) == 4) chi = chi_lepton_f32(px, py, pz, F);
     else chi = chi_lepton(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5]);
     double W = 0.0;
     if (isfinite(chi)) {
@@ -1131,7 +1134,7 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
     uint32_t nacc = 0, nev = 0, nrej = 0, ncap = 0, nfx = 0, nfr = 0, nnull = 0, nexc = 0;
     float nx = 0, ny = 0, nz = 0, x = 0, y = 0, z = 0, px = 0, py = 0, pz = 0, g = 1;
     float F[6] = {0, 0, 0, 0, 0, 0};
-    double chi = 1.0, Wenv = 0.0, rem = 0.0, tau = 0.0;
+    double chi = 1.0, Wenv = 0.0, rem = 0.0, tau = 0.0, sq = kEnvSqueeze;
     uint64_t id = 0;
     int64_t i = 0;
     bool recoiled = false;
@@ -1142,7 +1145,13 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
       const EmRec<float> rc = a.rec[e.slot];
 #pragma unroll
       for (int c = 0; c < 6; ++c) F[c] = rc.F[c];
-      chi = rc.chi; Wenv = rc.W; rem = a.dtd - rc.tau / rc.W;   // time left after the first candidate
+      // chi itself, in float64; the lepton pass ran the envelope at its bound
+      // rc.chi >= chi, so the squeeze (a lower bound of W / W_env) scales by
+      // h_env(chi) / h_env(rc.chi) <= 1
+      chi = chi_lepton_f32(rc.p[0], rc.p[1], rc.p[2], rc.F);
+      const float he = h_rad_env((float)rc.chi);
+      sq = he > 0.f ? kEnvSqueeze * (double)(h_rad_env((float)chi) / he) : 0.0;
+      Wenv = rc.W; rem = a.dtd - rc.tau / rc.W;   // time left after the first candidate
       px = rc.p[0]; py = rc.p[1]; pz = rc.p[2];
       x = rc.x[0]; y = rc.x[1]; z = rc.x[2];
       const float pa = sqrtf(px * px + py * py + pz * pz);
@@ -1157,10 +1166,10 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
       // draw keeps it at once, above it W comes from net B (packed over the
       // lanes that need it)
       const double ukeep = unit<double>(stream4(id, a.seed, step, kLeptonThin, (uint32_t)k).x);
-      const bool need_w = active && !(ukeep < kEnvSqueeze);
+      const bool need_w = active && !(ukeep < sq);
       bool ok;
       const float lh = mlp_lnh(S.B, chi, need_w, ok);
-      bool keep = active && ukeep < kEnvSqueeze;
+      bool keep = active && ukeep < sq;
       if (need_w) {
         float h = 0.f;
         if (isfinite(chi) && chi > 0.0) {
@@ -1168,7 +1177,7 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
           nfr += !ok;
         }
         const double W = kRateUnit * (double)(h / g);
-        nexc += W > Wenv || W < kEnvSqueeze * Wenv;
+        nexc += W > Wenv || W < sq * Wenv;
         keep = ukeep * Wenv < W;
       }
       nnull += active && !keep;
@@ -1213,6 +1222,7 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
             recoiled = true;
             chi = chi_lepton(px, py, pz, F[0], F[1], F[2], F[3], F[4], F[5]);
             Wenv = isfinite(chi) ? kRateUnit * (double)(h_rad_env((float)chi) / g) : 0.0;
+            sq = kEnvSqueeze;
           }
         } else {
           ++nrej;

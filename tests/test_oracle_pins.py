@@ -182,6 +182,75 @@ def test_chi_closed_forms():
     assert chi[0] == 0.0 and abs(chi[1] / (2 * 50 * E0 / constants.E_S) - 1) < 1e-14
 
 
+def _chi_upper_f32(p, E, B):
+    """The thinned lepton pass's float32 upper bound of chi (restated from the
+    kernel's device header), every operation rounded to float32 separately
+    (the device contracts some into fused multiply-adds: fewer roundings)."""
+    f = np.float32
+    px, py, pz = (p[:, i].astype(f) for i in range(3))
+    ex, ey, ez = (E[:, i].astype(f) for i in range(3))
+    bx, by, bz = (B[:, i].astype(f) for i in range(3))
+    g = np.sqrt(f(1) + (px * px + py * py + pz * pz))
+    ax = g * ex + (py * bz - pz * by)
+    ay = g * ey + (pz * bx - px * bz)
+    az = g * ez + (px * by - py * bx)
+    s = px * ex + py * ey + pz * ez
+    Ax = abs(g * ex) + abs(py * bz) + abs(pz * by)
+    Ay = abs(g * ey) + abs(pz * bx) + abs(px * bz)
+    Az = abs(g * ez) + abs(px * by) + abs(py * bx)
+    S = abs(px * ex) + abs(py * ey) + abs(pz * ez)
+    T = ax * ax + ay * ay + az * az - s * s
+    D = f(2.0 ** -19) * (Ax * Ax + Ay * Ay + Az * Az + S * S)
+    return np.sqrt(np.maximum(T + D, f(0))) * f((1.0 / constants.E_S) * (1.0 + 2.0 ** -20))
+
+
+def test_float32_chi_bound_lies_above_chi():
+    """The thinned lepton pass runs its envelope at a float32 upper bound of chi
+    (Eq. 2) rather than chi itself; thinning stays exact only if the bound is
+    never below chi.  Reference: chi E_S = sqrt(|gamma E + p x B|^2 - (p.E)^2)
+    for the same float32 inputs in extended precision (its rounding is ~1e-19
+    of the terms, the bound's margin 2e-6).  Generic inputs (gamma up to 1e6,
+    fields up to 1e4) and inputs where E and -v x B cancel to 1e-9 .. 1e-2: the
+    bound is always at or above chi, and within 2e-5 of it wherever |a|^2 - s^2
+    keeps a tenth of the squared term sums."""
+    rng = np.random.default_rng(5)
+    n = 200000
+
+    def unit(m):
+        v = rng.normal(size=(m, 3))
+        return v / np.linalg.norm(v, axis=1)[:, None]
+
+    gam = 10.0 ** rng.uniform(0, 6, n)
+    nhat = unit(n)
+    p = (np.sqrt(gam * gam - 1.0)[:, None] * nhat).astype(np.float32)
+    E = (10.0 ** rng.uniform(-2, 4, n))[:, None] * unit(n)
+    B = (10.0 ** rng.uniform(-2, 4, n))[:, None] * unit(n)
+    # cancelling half: E perpendicular to p, B = (n x E) / beta (1 + delta)
+    h = n // 2
+    Eh = E[:h] - np.sum(E[:h] * nhat[:h], axis=1)[:, None] * nhat[:h]
+    beta = np.sqrt(1.0 - 1.0 / gam[:h] ** 2)
+    delta = rng.choice([-1.0, 1.0], h) * 10.0 ** rng.uniform(-9, -2, h)
+    E[:h] = Eh
+    B[:h] = np.cross(nhat[:h], Eh) / beta[:, None] * (1.0 + delta)[:, None]
+    E = E.astype(np.float32)
+    B = B.astype(np.float32)
+    up = _chi_upper_f32(p, E, B).astype(np.float64)
+    L = np.longdouble
+    pl, El, Bl = p.astype(L), E.astype(L), B.astype(L)
+    gl = np.sqrt(L(1) + np.sum(pl * pl, axis=1))
+    a = gl[:, None] * El + np.cross(pl, Bl)
+    T = np.sum(a * a, axis=1) - np.sum(pl * El, axis=1) ** 2
+    chi = (np.sqrt(np.maximum(T, L(0))) / L(constants.E_S)).astype(np.float64)
+    assert np.all(up >= chi), np.max((chi - up) / np.maximum(chi, 1e-300))
+    # the margin's size: (sum of the squared term sums) / T sets the excess
+    A2 = np.sum((gl[:, None] * np.abs(El) + np.abs(pl[:, [1, 2, 0]] * Bl[:, [2, 0, 1]])
+                 + np.abs(pl[:, [2, 0, 1]] * Bl[:, [1, 2, 0]])) ** 2, axis=1)
+    S2 = np.sum(np.abs(pl * El), axis=1) ** 2
+    generic = (T >= L(0.1) * (A2 + S2)).astype(bool)
+    assert generic.sum() > n // 3 and (~generic).sum() > n // 4
+    assert np.max(up[generic] / chi[generic] - 1.0) < 2e-5
+
+
 # ------------------------------------------------------------------- pairs
 def test_pair_erber_asymptote_and_sign():
     """Small chi: h_pair -> 3 sqrt3 / (16 sqrt2) chi exp(-8/(3 chi)) (Erber) only
