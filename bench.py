@@ -390,6 +390,7 @@ def run_cascade(q, torch, args, weights, name):
                positrons=npo, photons=nph, pairs_timed=st["pairs"], dropped=st["dropped"] + st0["dropped"],
                scan_timeouts=st["scan_timeouts"] + st0["scan_timeouts"], envelope_exceeded=st["envelope_exceeded"],
                fallback_xi=st["mlp_fallback_xi"], fallback_rate=st["mlp_fallback_rate"], thinned=st["thinned"],
+               box_fallback=st["box_fallback"],
                retired=int(retired.sum()), photon_hist=photon_hist, positron_gamma=positron_gamma, steps_run=total,
                timed_from=timed0,
                pair_pass_ms=pair_ms, pair_pass_photons=pair_n, lepton_pass_ms=gp_ms, lepton_pass_electrons=gp_n,

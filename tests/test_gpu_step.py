@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from oracle import mc, spectra, tables
-from oracle.constants import E_S
+from oracle.constants import E_S, RATE_UNIT
 from tests.gpu_helpers import need_gpu
 
 import workloads
@@ -151,6 +151,58 @@ def test_f32_chi_where_fields_cancel(rad_table_I):
     print(f"chi {chi.min():.2e} .. {chi.max():.2e}; rate rel. error max {rel.max():.2e} (co-moving "
           f"{rel[sgn > 0].max():.2e})")
     assert rel.max() < 2e-5
+
+
+def test_thinned_pass_envelope_where_fields_cancel(rad_table_I):
+    """Surrogate path (Poisson thinning): the lepton pass runs the optical depth
+    down at the envelope rate alpha E_S h_env(chi_b) / gamma at a float32 upper
+    bound chi_b of chi, and thinning is exact only if that envelope is never below
+    the rate.  Same crossed-field geometry as above (chi from ~2e-6 co-moving to
+    ~20 counter-propagating, no events: tau0 = 50): the applied rate
+    (tau0 - tau1) / dt is at or above the oracle's rate at the oracle's chi of the
+    pushed momentum for every electron, at or above the envelope at that chi
+    (within the float32 evaluation of the envelope, 2e-5), and within 1e-4 of it
+    for the counter-propagating electrons, where nothing cancels."""
+    torch, q = need_gpu()
+    rng = np.random.default_rng(6)
+    n, E0, dt, tau0 = 20000, 2000.0, 1e-3, 50.0
+    gam = 10.0 ** rng.uniform(1.0, 3.0, n)
+    th = rng.uniform(0.0, 1e-2, n) * np.where(np.arange(n) % 2 == 0, 1.0, 0.0)
+    th[np.arange(n) % 4 == 1] = 0.0
+    ph = rng.uniform(0.0, 2.0 * math.pi, n)
+    sgn = np.where(np.arange(n) % 4 == 3, -1.0, 1.0)
+    pa = np.sqrt(gam ** 2 - 1.0)
+    p = np.stack([sgn * pa * np.cos(th), pa * np.sin(th) * np.cos(ph), pa * np.sin(th) * np.sin(ph)], -1)
+    p = p.astype(np.float32).astype(np.float64)
+    ctx = q.Context(seed=2, kmax=4, flags=q.QED_FLAG_SURROGATE)
+    ctx.qed_build_tables(q.QED_FORMULA_I)
+    for net in (0, 1):                              # any weights: the pass uses the envelope only
+        rng0 = np.random.default_rng(net)
+        ctx.qed_surrogate_io(net, rng0.normal(0, 0.3, q.lib().qed_surrogate_params(net)).astype(np.float32))
+    lep = q.Species(n, "f32")
+    lep.load(np.zeros((n, 3)), p, np.full(n, tau0), np.arange(n, dtype=np.uint64))
+    ctx.qed_set_next_id(n)
+    fld = q.Fields(q.QED_FIELD_UNIFORM, E=(0.0, E0, 0.0), B=(0.0, 0.0, E0))
+    print(f"thinned lepton pass, crossed field E0 = {E0}, {n} electrons", flush=True)
+    ctx.qed_gather_push(fld, lep, -1, dt, 0)
+    st, _ = ctx.qed_get_status()
+    g = lep.to_numpy()
+    assert st["nan_chi"] == 0
+    assert np.all(g["tau"] > 0.0)                 # no candidate within the step
+    w_gpu = (tau0 - g["tau"]) / dt
+    p1 = g["p"]
+    gamma1 = np.sqrt(1.0 + np.sum(p1 * p1, -1))
+    chi = spectra.chi_lepton(p1, np.tile([0.0, E0, 0.0], (n, 1)), np.tile([0.0, 0.0, E0], (n, 1)))
+    assert chi.min() < 1e-5 and chi.max() > 5.0
+    w_rate = tables.rate_rad(rad_table_I, chi, gamma1)
+    c1 = 5.0 / (2.0 * math.sqrt(3.0))
+    w_env = RATE_UNIT * 1.002 * c1 * chi * (1.0 + chi) ** (-1.0 / 3.0) / gamma1
+    infl = w_gpu / w_env
+    print(f"  applied / envelope at chi: min {infl.min():.6f}, counter-propagating max "
+          f"{infl[sgn < 0].max():.6f}, co-moving max {infl[sgn > 0].max():.3e}")
+    assert np.all(w_gpu >= w_rate)
+    assert infl.min() > 1.0 - 2e-5
+    assert infl[sgn < 0].max() < 1.0 + 1e-4
 
 
 def _chi_ref80(p, E, B, photon):
