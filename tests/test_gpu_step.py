@@ -719,45 +719,86 @@ def test_method1_dt_study():
 
 
 def test_box_staging_equals_global_gather():
-    """The lepton pass's two gathers give the same particles bit for bit: the
+    """The lepton pass's kernels and gathers give the same particles bit for bit.
+    A float32 species on a grid takes two particles per thread when its capacity
+    holds at least 64 particles per cell, one otherwise; in either, the
     workgroups of a cell-sorted dense species stage their stencil boxes in LDS
     (box_fallback near 0), those of the same particles in random order find
-    their boxes too large and gather from global memory (box_fallback > 0); the
-    pushed momenta, positions and optical depths, matched by id, are identical.
-    2e6 electrons on a 32^3 grid (61 per cell), standing wave a0 = 500: several
-    XCD chunks of 512-particle tiles and a ragged last tile."""
+    their boxes too large and gather from global memory (box_fallback > 0).  The
+    pushed momenta, positions and optical depths, matched by id, and the photons
+    of the emission that follows are identical for the two orders; between the
+    two kernels (separate compilations) they agree to float32 rounding.  2e6
+    electrons on a 32^3 grid (61 per cell), standing wave a0 = 500, capacity 2e6
+    (one particle per thread) or 2.2e6 (two): several XCD chunks of tiles and a
+    ragged last tile."""
     torch, q = need_gpu()
     n, ng, L, dt, a0 = 2_000_003, 32, workloads.BOX_L, 0.01, 500.0
     ens = workloads.standing_wave_electrons(n, seed=12)
     x, p, ids = ens["x"], ens["p"], ens["id"]
     tau = mc.init_tau(ids, seed=3)
+    tau[::7] *= 1e-3                                # some emitters within the step
     grid = torch.empty(ng ** 3 * 6, dtype=torch.float32, device="cuda")
     fld = q.Fields(q.QED_FIELD_GRID, grid=grid, n=ng, L=L)
     res = {}
-    for name in ("sorted", "random"):
-        ctx = q.Context(seed=3, kmax=4)
-        ctx.qed_build_tables(q.QED_FORMULA_I)
-        ctx.qed_fill_standing_wave(grid, ng, L, a0, 0.21)
-        a = q.Species(n, "f32")
-        if name == "sorted":
-            src = q.Species(n, "f32")
-            src.load(x, p, tau, ids)
-            ctx.qed_sort_by_cell(fld, src, a)
-            del src
-        else:
-            perm = np.random.default_rng(5).permutation(n)
-            a.load(x[perm], p[perm], tau[perm], ids[perm])
-        ctx.qed_reserve(n)
-        ctx.qed_get_status(check=False)
-        ctx.qed_gather_push(fld, a, -1, dt, 0)
-        st, _ = ctx.qed_get_status()
-        g = a.to_numpy()
-        o = np.argsort(g["id"])
-        res[name] = (st, {k: g[k][o] for k in ("x", "p", "tau", "id")})
-        ctx.close()
-    (s0, r0), (s1, r1) = res["sorted"], res["random"]
-    print(f"box fallbacks: sorted {s0['box_fallback']}, random order {s1['box_fallback']}")
-    # (a sorted tile can straddle two distant blocks and fall back too: rare)
-    assert s1["box_fallback"] > 0 and s0["box_fallback"] * 100 < s1["box_fallback"]
-    for k in ("id", "x", "p", "tau"):
-        np.testing.assert_array_equal(r0[k], r1[k])
+    for cap in (n, 2_200_000):
+        for name in ("sorted", "random"):
+            print(f"lepton pass: capacity {cap}, {name} order", flush=True)
+            ctx = q.Context(seed=3, kmax=4)
+            ctx.qed_build_tables(q.QED_FORMULA_I)
+            ctx.qed_fill_standing_wave(grid, ng, L, a0, 0.21)
+            a = q.Species(cap, "f32")
+            if name == "sorted":
+                src = q.Species(cap, "f32")
+                src.load(x, p, tau, ids)
+                ctx.qed_sort_by_cell(fld, src, a)
+                del src
+            else:
+                perm = np.random.default_rng(5).permutation(n)
+                a.load(x[perm], p[perm], tau[perm], ids[perm])
+            ph = q.Species(400_000, "f32")
+            ctx.qed_set_next_id(n)
+            ctx.qed_reserve(cap)
+            ctx.qed_get_status(check=False)
+            ctx.qed_gather_push(fld, a, -1, dt, 0)
+            st, _ = ctx.qed_get_status()
+            g = a.to_numpy()
+            o = np.argsort(g["id"])
+            out = {k: g[k][o] for k in ("x", "p", "tau", "id")}
+            ctx.qed_emit_photons(a, ph, 0)
+            st2, _ = ctx.qed_get_status()
+            gp = ph.to_numpy()
+            # photon ids follow the emitters' storage order: compare the photons
+            # as a set, ordered by their emitter's position, energy and time
+            key = np.lexsort((gp["tau"], gp["p"][:, 0], gp["x"][:, 2], gp["x"][:, 1], gp["x"][:, 0]))
+            out.update(ph_x=gp["x"][key], ph_k=gp["p"][key], ph_tau=gp["tau"][key])
+            res[cap, name] = (st, st2, out)
+            ctx.close()
+    for (cap, name), (st, st2, out) in res.items():
+        print(f"capacity {cap}, {name}: box fallbacks {st['box_fallback']}, photons {out['ph_x'].shape[0]}")
+    for cap in (n, 2_200_000):
+        (s0, e0, r0), (s1, e1, r1) = res[cap, "sorted"], res[cap, "random"]
+        assert r0["ph_x"].shape[0] > 1000 and e0["dropped"] == 0 and e1["dropped"] == 0
+        # within one kernel the two gathers agree bit for bit
+        for k in r0:
+            np.testing.assert_array_equal(r1[k], r0[k])
+        # (a sorted tile can straddle two distant blocks and fall back too: rare)
+        assert s1["box_fallback"] > 0 and s0["box_fallback"] * 100 < s1["box_fallback"]
+    # the two kernels are separate compilations whose fused multiply-adds
+    # differ: the particles agree to float32 rounding (positions within 2 ulp of
+    # the box length 2 pi, momenta within 16 ulp of the larger of |p| and the
+    # step's kick a0 dt, the magnitude of the push's intermediates), the photons
+    # in number and energy
+    a, b = res[n, "sorted"][2], res[2_200_000, "sorted"][2]
+    np.testing.assert_array_equal(a["id"], b["id"])
+    for k, scale, tol in (("x", 1.0, 2.0 ** -20), ("p", np.maximum(np.abs(a["p"]), a0 * dt), 2.0 ** -19)):
+        d = np.max(np.abs(b[k] - a[k]) / scale)
+        print(f"one vs two particles per thread: {k} max diff {d:.2e}, "
+              f"{np.mean(b[k] != a[k]):.2e} of the values differ")
+        assert d <= tol
+    # the optical depth drops by W dt <~ 0.1, W within ~1e-6 (chi from the momenta above)
+    np.testing.assert_allclose(b["tau"], a["tau"], rtol=1e-6, atol=1e-6)
+    assert abs(b["ph_x"].shape[0] - a["ph_x"].shape[0]) <= 2
+    ga = np.sort(np.linalg.norm(a["ph_k"], axis=1))
+    gb = np.sort(np.linalg.norm(b["ph_k"], axis=1))
+    if ga.size == gb.size:
+        np.testing.assert_allclose(gb, ga, rtol=1e-5)
