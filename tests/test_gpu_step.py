@@ -388,11 +388,14 @@ def _c2_setup(q, n, seed=1, a0=500.0, ngrid=128):
     return ens, x32, p32
 
 
-def test_grid_step_f32_one_step_parity(rad_table_I):
-    """Standing wave a0 = 500 on a 128^3 grid, float32 state: one step per particle
-    against the oracle (float64 arithmetic on the same float32 inputs)."""
+@pytest.mark.parametrize("ngrid,cap", [(128, None), (32, 2_200_000)], ids=["one_per_thread", "two_per_thread"])
+def test_grid_step_f32_one_step_parity(rad_table_I, ngrid, cap):
+    """Standing wave a0 = 500, float32 state: one step per particle against the
+    oracle (float64 arithmetic on the same float32 inputs), on a 128^3 grid with a
+    species of 1e5 (one particle per thread) and on a 32^3 grid with a species
+    sized for 2.2e6 (two per thread: at least 64 per cell) holding the same 1e5."""
     torch, q = need_gpu()
-    n, a0, ngrid, L, dt = 100000, 500.0, 128, workloads.BOX_L, 0.01
+    n, a0, L, dt = 100000, 500.0, workloads.BOX_L, 0.01
     ctx = q.Context(seed=1, kmax=4)
     ctx.qed_build_tables(q.QED_FORMULA_I)
     ens, x, p = _c2_setup(q, n)
@@ -400,7 +403,8 @@ def test_grid_step_f32_one_step_parity(rad_table_I):
     # give half of the particles a small optical depth so that many emit
     tau[::2] *= 1e-3
     grid = torch.empty(ngrid ** 3 * 6, dtype=torch.float32, device="cuda")
-    lep = q.Species(n, "f32")
+    print(f"grid step parity: {ngrid}^3, capacity {cap or n}", flush=True)
+    lep = q.Species(cap or n, "f32")
     ph = q.Species(4 * n, "f32")
     lep.load(x, p, tau, ens["id"])
     ctx.qed_set_next_id(n)
