@@ -235,8 +235,12 @@ QED_API int qed_fill_standing_wave_at_step(qed_ctx_t ctx, float *grid, int n, do
    record (fields seen, chi, W, time left after the first event) is kept at their
    index; qed_emit_photons lists them in index order and finishes them.  One kernel
    launch: two particles per thread for a float32 species on a GRID whose capacity
-   is at least 64 particles per cell, one otherwise (the results are the same).
-   Fails with QED_ERR_STATE if the tables are missing. */
+   is at least 64 particles per cell, one otherwise (the two agree to float32
+   rounding).  With QED_FLAG_SURROGATE (float32) the optical depth runs down at a
+   closed-form envelope of the rate evaluated at a float32 upper bound of chi
+   (Poisson thinning: qed_emit_photons evaluates chi in float64 and keeps each
+   candidate event with probability W / W_env).  Fails with QED_ERR_STATE if the
+   tables are missing. */
 QED_API int qed_gather_push(qed_ctx_t ctx, const qed_fields_t *fields, qed_species_t *leptons,
                     int charge, double dt, int64_t step, void *stream);
 
@@ -245,7 +249,9 @@ QED_API int qed_gather_push(qed_ctx_t ctx, const qed_fields_t *fields, qed_speci
    a photon of energy xi gamma along p with its own optical depth, recoils the lepton
    to (1 - xi) gamma, draws a new tau, and continues while the optical depth runs out
    again within the step (at most kmax events).  Photons are appended after
-   photons->count in (emitter index, k) order. */
+   photons->count in (emitter index, k) order; with QED_FLAG_SURROGATE (float32)
+   the first events of all emitters come first, in emitter order, then the later
+   events of the emitters that have them, in (emitter index, k) order. */
 QED_API int qed_emit_photons(qed_ctx_t ctx, qed_species_t *leptons, qed_species_t *photons,
                      int64_t step, void *stream);
 
@@ -372,9 +378,9 @@ QED_API int qed_sample(qed_ctx_t ctx, const double *chi, const double *gamma, co
    table, and a xi sample falls back when u is outside [1e-4, 1 - 1e-4] or the
    tabulated CDF at the predicted xi differs from u by more than 2e-3.  Fallbacks
    are counted (mlp_fallback_*).
-   With QED_FLAG_SURROGATE in the context parameters, qed_gather_push and
-   qed_emit_photons on float32 species use the same nets and checks in place of
-   the table lookups.  The surrogate paths need both nets, trained or loaded
+   With QED_FLAG_SURROGATE in the context parameters, qed_gather_push,
+   qed_emit_photons and qed_create_pairs on float32 species use the same nets and
+   checks in place of the table lookups, through Poisson thinning.  The surrogate paths need both nets, trained or loaded
    (QED_ERR_STATE otherwise). */
 QED_API int qed_surrogate_params(int net);
 QED_API int qed_surrogate_train(qed_ctx_t ctx, const qed_train_spec_t *spec, void *stream);

@@ -58,7 +58,9 @@ template <typename T> hipError_t dalloc(T **p, size_t n) {
 
 void free_emitters(qed_ctx *c) {
   (void)hipFree(c->em_idx); (void)hipFree(c->em_rec); (void)hipFree(c->em_mask);
+  (void)hipFree(c->cont_idx); (void)hipFree(c->d_n_cont);
   c->em_idx = nullptr; c->em_rec = nullptr; c->em_mask = nullptr;
+  c->cont_idx = nullptr; c->d_n_cont = nullptr;
   c->em_cap = 0;
 }
 
@@ -85,15 +87,17 @@ int ensure_scan(qed_ctx *c, int64_t n) {
   return QED_OK;
 }
 
-// Emitter slots (one record per particle), ballot mask and ordered list for
-// lepton species of up to n particles.  Allocates, so not under graph capture.
+// Emitter slots (one record per particle), ballot mask, ordered list and the
+// list of the surrogate emission's second pass for lepton species of up to n
+// particles.  Allocates, so not under graph capture.
 int ensure_emitters(qed_ctx *c, int64_t n) {
   if (n <= c->em_cap) return QED_OK;
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(c, e, "reserve");
   free_emitters(c);
   if ((e = dalloc(&c->em_idx, n)) != hipSuccess || (e = dalloc(&c->em_rec, kEmRecMaxBytes * n)) != hipSuccess ||
-      (e = dalloc(&c->em_mask, n / 64 + 1)) != hipSuccess) {
+      (e = dalloc(&c->em_mask, n / 64 + 1)) != hipSuccess || (e = dalloc(&c->cont_idx, n)) != hipSuccess ||
+      (e = dalloc(&c->d_n_cont, 1)) != hipSuccess) {
     free_emitters(c);
     return hip_fail(c, e, "reserve: hipMalloc");
   }

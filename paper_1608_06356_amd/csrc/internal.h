@@ -50,6 +50,8 @@ struct qed_ctx {
   uint64_t *em_mask = nullptr;   // one bit per particle: optical depth ran out this step
   EmIdx *em_idx = nullptr;       // ordered emitter list
   unsigned char *em_rec = nullptr;   // em_cap records of up to kEmRecMaxBytes, slot = particle index
+  int32_t *cont_idx = nullptr;   // surrogate emission: emitters with a further candidate (list positions)
+  int64_t *d_n_cont = nullptr;
   int64_t *d_n_emit = nullptr;
   const void *em_owner = nullptr;   // species (x pointer) the list belongs to
   int em_dtype = -1;

@@ -1104,7 +1104,20 @@ struct EmitMlpLds {
 // optical depth at W_env, up to kmax candidates per step (the cap is counted).
 // Counter k of the particle's stream serves candidate k: LEPTON_EVENT gives
 // (u_xi, u_tau, u_row, u_ph) as on the table path, LEPTON_THIN the keep draw.
-__global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a, MlpDev m) {
+//
+// Two passes.  Cont = false takes every emitter's first candidate; with
+// kmax > 1 an emitter with a further candidate within the step sets its bit in
+// cont_mask (at its position in the emitter list) and is left to the second
+// pass.  Cont = true takes the emitters of that list (cont_idx, n_cont, in
+// emitter order), re-runs their first candidate (identical: the same streams
+// and per-lane arithmetic; neither counted nor appended again) and goes on with
+// candidates 1 .. kmax - 1.  Packed densely, the few emitters with a second
+// candidate fill whole net calls instead of a few lanes of every wave.  The
+// photons of the second pass follow all those of the first, in (emitter, event)
+// order.
+template <bool Cont>
+__global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a, MlpDev m, uint64_t *cont_mask,
+                                                              const int32_t *cont_idx, const int64_t *n_cont) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   EmitMlpLds &S = *reinterpret_cast<EmitMlpLds *>(lds_raw);
   __shared__ uint64_t scan_s[16];
@@ -1113,11 +1126,16 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
   __shared__ int64_t hdr_s[3];
   __shared__ uint32_t cnt_s[cNumCounters];
   count_zero(cnt_s);
-  if (threadIdx.x == 0) { hdr_s[0] = *a.n_emit; hdr_s[1] = *a.ph.count; hdr_s[2] = (int64_t)*a.next_id; }
+  if (threadIdx.x == 0) {
+    hdr_s[0] = Cont ? *n_cont : *a.n_emit;
+    hdr_s[1] = *a.ph.count;
+    hdr_s[2] = (int64_t)*a.next_id;
+  }
   __syncthreads();
   const int64_t n_em = hdr_s[0], ph0 = hdr_s[1];
   const uint64_t id0 = (uint64_t)hdr_s[2];
   if (n_em == 0) return;
+  const int klim = Cont ? a.kmax : 1;
   mlp::stage_net_infer(m.thA, mlp::kA, &S.A);
   mlp::stage_net_infer(m.thB, mlp::kB, &S.B);
   for (int k = threadIdx.x; k < kRadNChi * (2 + 2 * mlp::kChkN); k += blockDim.x) S.chk[k] = m.chk[k];
@@ -1139,7 +1157,7 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
     int64_t i = 0;
     bool recoiled = false;
     if (valid) {
-      const EmIdx e = a.em_idx[r];
+      const EmIdx e = a.em_idx[Cont ? (int64_t)cont_idx[r] : r];
       i = e.i;
       id = a.lep.id[i];
       const EmRec<float> rc = a.rec[e.slot];
@@ -1159,9 +1177,10 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
       g = sqrtf(1.f + px * px + py * py + pz * pz);
     }
     bool active = valid;       // a candidate is pending at time dt - rem
-    for (int k = 0; k < a.kmax; ++k) {
+    for (int k = 0; k < klim; ++k) {
       if (!__any(active)) break;
       mlp::reload_barrier();
+      const bool counted = !Cont || k > 0;   // the second pass re-runs candidate 0 silently
       // keep the candidate with probability W / W_env: below the squeeze the
       // draw keeps it at once, above it W comes from net B (packed over the
       // lanes that need it)
@@ -1174,13 +1193,13 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
         float h = 0.f;
         if (isfinite(chi) && chi > 0.0) {
           h = ok ? expf(lh) : h_rad<float>((float)chi, S.lnh, m.rg);
-          nfr += !ok;
+          nfr += counted && !ok;
         }
         const double W = kRateUnit * (double)(h / g);
-        nexc += W > Wenv || W < sq * Wenv;
+        nexc += counted && (W > Wenv || W < sq * Wenv);
         keep = ukeep * Wenv < W;
       }
-      nnull += active && !keep;
+      nnull += counted && active && !keep;
       const uint4 u = stream4(id, a.seed, step, kLeptonEvent, (uint32_t)k);
       const float uxi = unit<float>(u.x), urow = unit<float>(u.z);
       const float t = logf(uxi) - log1pf(-uxi);
@@ -1206,14 +1225,16 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
         } else {
           sample_rad<float>(tab, (float)chi, uxi, urow, xi, om, m.rg);
         }
-        ++nev;
-        nfx += !xi_ok;
+        nev += counted;
+        nfx += counted && !xi_ok;
         const float gp = xi * g;
         if (gp >= 2.f) {
+          if (counted) {
 #pragma unroll
-          for (int sl = 0; sl < kKmaxMax; ++sl)
-            if (sl == (int)nacc) { gph[sl] = gp; tph[sl] = -log(unit<double>(u.w)); }
-          ++nacc;
+            for (int sl = 0; sl < kKmaxMax; ++sl)
+              if (sl == (int)nacc) { gph[sl] = gp; tph[sl] = -log(unit<double>(u.w)); }
+            ++nacc;
+          }
           if (a.recoil) {
             const float gn = fmaxf(om * g, 1.f);
             const float pm = sqrtf(fmaxf(gn * gn - 1.f, 0.f));
@@ -1225,7 +1246,7 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
             sq = kEnvSqueeze;
           }
         } else {
-          ++nrej;
+          nrej += counted;
         }
       }
       if (active) {
@@ -1241,7 +1262,14 @@ __global__ __launch_bounds__(kEmitMlpThreads) void k_emit_mlp(EmitArgs<float> a,
         }
       }
     }
-    if (valid) {
+    // first pass: a lane still active has a further candidate within the step
+    const bool cont = !Cont && active;
+    if (!Cont) {
+      const uint64_t cb = __ballot(cont);
+      const int64_t r0 = (int64_t)tile * kEmitMlpThreads + (threadIdx.x & ~63);
+      if ((threadIdx.x & 63) == 0 && r0 < n_em) cont_mask[r0 >> 6] = cb;
+    }
+    if (valid && !cont) {
       a.lep.tau[i] = tau - Wenv * rem;
       if (recoiled) { ((float *)a.lep.px)[i] = px; ((float *)a.lep.py)[i] = py; ((float *)a.lep.pz)[i] = pz; }
     }
@@ -2155,8 +2183,11 @@ static MlpDev mlp_dev(qed_ctx *c) {
 hipError_t step_set_attributes() {
   // the standing-wave row: 6 n floats for n up to kMaxWaveGrid
   const int row_bytes = 6 * kMaxWaveGrid * (int)sizeof(float);
-  hipError_t e = hipFuncSetAttribute((const void *)k_emit_mlp, hipFuncAttributeMaxDynamicSharedMemorySize,
+  hipError_t e = hipFuncSetAttribute((const void *)k_emit_mlp<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)sizeof(EmitMlpLds));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_emit_mlp<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)sizeof(EmitMlpLds));
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void *)k_standing_wave<float4>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             row_bytes);
@@ -2235,7 +2266,23 @@ hipError_t launch_emit(qed_ctx *c, const qed_species_t *lep, const qed_species_t
                       c->rad_s0sc, c->em_idx, (const EmRec<float> *)c->em_rec, c->d_n_emit,
                       c->d_next_id, c->params.seed, c->params.kmax, recoil, (uint64_t)step, dstep, sc,
                       c->d_counters, gen_mode(c), c->em_dt, c->range, retire_dev(c)};
-    hipLaunchKernelGGL(k_emit_mlp, dim3(grid), dim3(kEmitMlpThreads), sizeof(EmitMlpLds), st, a, mlp_dev(c));
+    hipLaunchKernelGGL(k_emit_mlp<false>, dim3(grid), dim3(kEmitMlpThreads), sizeof(EmitMlpLds), st, a, mlp_dev(c),
+                       c->em_mask, (const int32_t *)nullptr, (const int64_t *)nullptr);
+    if (c->params.kmax > 1) {
+      // the emitters with a further candidate (bits in the emitter mask, which
+      // the list above no longer needs), listed in emitter order and finished
+      // in a second pass; both scan regions cleared again
+      hipLaunchKernelGGL(k_zero_scan2, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, st, c->d_ticket,
+                         c->d_status, c->status_len, n0, n1);
+      if (wide)
+        hipLaunchKernelGGL((k_emit_index<8, int32_t>), dim3(eig), dim3(kEIThreads), 0, st, c->em_mask, c->d_n_emit,
+                           c->cont_idx, c->d_n_cont, isc, c->d_counters);
+      else
+        hipLaunchKernelGGL((k_emit_index<1, int32_t>), dim3(eig), dim3(kEIThreads), 0, st, c->em_mask, c->d_n_emit,
+                           c->cont_idx, c->d_n_cont, isc, c->d_counters);
+      hipLaunchKernelGGL(k_emit_mlp<true>, dim3(grid), dim3(kEmitMlpThreads), sizeof(EmitMlpLds), st, a,
+                         mlp_dev(c), (uint64_t *)nullptr, c->cont_idx, c->d_n_cont);
+    }
   } else if (lep->dtype == QED_F32) {
     EmitArgs<float> a{dev_species(lep), dev_species(ph), c->rad_lnh32, c->rad_S64, c->rad_q16,
                       c->rad_s0sc, c->em_idx, (const EmRec<float> *)c->em_rec, c->d_n_emit,
