@@ -78,6 +78,13 @@ __global__ void k_permute(const R *sx, const R *sy, const R *sz, const R *spx, c
   if (blockIdx.x == 0 && threadIdx.x == 0) *dcount = n;
 }
 
+// Onesweep radix sort with 11-bit digits: the keys (at most 22 bits) take two
+// passes instead of three.
+using SortCfg = rocprim::radix_sort_config<
+    rocprim::default_config, rocprim::default_config,
+    rocprim::radix_sort_onesweep_config<rocprim::kernel_config<1024, 16>, rocprim::kernel_config<1024, 16>, 11,
+                                        rocprim::block_radix_rank_algorithm::match>>;
+
 // Sorts the n particles the species holds (n read from the device by the caller).
 template <typename R>
 hipError_t sort_impl(qed_ctx *c, const qed_fields_t *f, const qed_species_t *s, qed_species_t *d, int64_t n,
@@ -108,7 +115,7 @@ hipError_t sort_impl(qed_ctx *c, const qed_fields_t *f, const qed_species_t *s, 
   if (bits > 32) bits = 32;
   size_t need = 0;
   // scratch sized for the capacity, so that it is allocated once per species size
-  if ((e = rocprim::radix_sort_pairs(nullptr, need, k0, k1, v0, v1, (size_t)s->capacity, 0u, bits, st)) != hipSuccess)
+  if ((e = rocprim::radix_sort_pairs<SortCfg>(nullptr, need, k0, k1, v0, v1, (size_t)s->capacity, 0u, bits, st)) != hipSuccess)
     return e;
   if (need > c->sort_tmp_bytes) {
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
@@ -119,9 +126,9 @@ hipError_t sort_impl(qed_ctx *c, const qed_fields_t *f, const qed_species_t *s, 
     c->sort_tmp_bytes = need;
   }
   size_t need_n = 0;
-  if ((e = rocprim::radix_sort_pairs(nullptr, need_n, k0, k1, v0, v1, (size_t)cap, 0u, bits, st)) != hipSuccess)
+  if ((e = rocprim::radix_sort_pairs<SortCfg>(nullptr, need_n, k0, k1, v0, v1, (size_t)cap, 0u, bits, st)) != hipSuccess)
     return e;
-  if ((e = rocprim::radix_sort_pairs(c->sort_tmp, need_n, k0, k1, v0, v1, (size_t)cap, 0u, bits, st)) != hipSuccess)
+  if ((e = rocprim::radix_sort_pairs<SortCfg>(c->sort_tmp, need_n, k0, k1, v0, v1, (size_t)cap, 0u, bits, st)) != hipSuccess)
     return e;
   const int64_t pblocks = (blocks + 7) / 8 * 8;
   hipLaunchKernelGGL(k_permute<R>, dim3((unsigned)pblocks), dim3(256), 0, st, (const R *)s->x, (const R *)s->y,
