@@ -1,7 +1,7 @@
 // Stable reordering of a species by grid cell (nearest node of the quadratic
 // stencil, cells grouped in 4x4x4 blocks), so that the field gather of
 // neighbouring threads touches neighbouring nodes.  Keys are radix-sorted with rocPRIM (stable), then every
-// array is gathered into the destination species.  Particle ids, and therefore
+// array is gathered into the destination species, one array per launch.  Particle ids, and therefore
 // every random stream, travel with the particles, so the physics is unchanged;
 // only the storage order (and with it the append order) changes.
 #include <hip/hip_runtime.h>
@@ -58,25 +58,28 @@ __global__ void k_cell_keys(const R *x, const R *y, const R *z, const int64_t *c
   }
 }
 
-template <typename R>
-__global__ void k_permute(const R *sx, const R *sy, const R *sz, const R *spx, const R *spy, const R *spz,
-                          const double *stau, const uint64_t *sid, R *dx_, R *dy_, R *dz_, R *dpx, R *dpy, R *dpz,
-                          double *dtau, uint64_t *did, const uint32_t *perm, const int64_t *count,
-                          int64_t *dcount) {
+// One array at a time, so that its source lines alone compete for the L2
+// (the gathers follow a permutation that is nearly the identity once the
+// particles have been sorted before), four consecutive destinations per
+// thread.  The grid covers the array; block b takes chunk (b % 8) *
+// (gridDim.x / 8) + b / 8, so that each XCD (blocks are dealt round-robin over
+// the 8) sweeps its own eighth of the sorted order and its L2 keeps that
+// stretch's source lines.
+template <typename T>
+__global__ void k_permute4(const T *src, T *dst, const uint32_t *perm, const int64_t *count) {
   const int64_t n = *count;
-  // gridDim.x is a multiple of 8: block b takes chunk (b % 8) * (gridDim.x / 8) + b / 8, so
-  // that each XCD (blocks are dealt round-robin over the 8) gathers from one
-  // contiguous stretch of the sorted order and its L2 keeps that stretch's
-  // source lines
   const int64_t lb = (int64_t)(blockIdx.x % 8u) * (gridDim.x / 8u) + blockIdx.x / 8u;
-  for (int64_t j = lb * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t i = perm[j];
-    dx_[j] = sx[i]; dy_[j] = sy[i]; dz_[j] = sz[i];
-    dpx[j] = spx[i]; dpy[j] = spy[i]; dpz[j] = spz[i];
-    dtau[j] = stau[i]; did[j] = sid[i];
+  const int64_t j = 4 * (lb * blockDim.x + threadIdx.x);
+  if (j + 4 <= n) {
+    const uint32_t i0 = perm[j], i1 = perm[j + 1], i2 = perm[j + 2], i3 = perm[j + 3];
+    const T a = src[i0], b = src[i1], c = src[i2], d = src[i3];
+    dst[j] = a; dst[j + 1] = b; dst[j + 2] = c; dst[j + 3] = d;
+  } else {
+    for (int64_t k = j; k < n; ++k) dst[k] = src[perm[k]];
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) *dcount = n;
 }
+
+__global__ void k_set_count(const int64_t *src, int64_t *dst) { *dst = *src; }
 
 // Onesweep radix sort with 11-bit digits: the keys (at most 22 bits) take two
 // passes instead of three.
@@ -130,11 +133,15 @@ hipError_t sort_impl(qed_ctx *c, const qed_fields_t *f, const qed_species_t *s, 
     return e;
   if ((e = rocprim::radix_sort_pairs<SortCfg>(c->sort_tmp, need_n, k0, k1, v0, v1, (size_t)cap, 0u, bits, st)) != hipSuccess)
     return e;
-  const int64_t pblocks = (blocks + 7) / 8 * 8;
-  hipLaunchKernelGGL(k_permute<R>, dim3((unsigned)pblocks), dim3(256), 0, st, (const R *)s->x, (const R *)s->y,
-                     (const R *)s->z, (const R *)s->px, (const R *)s->py, (const R *)s->pz, s->tau, s->id,
-                     (R *)d->x, (R *)d->y, (R *)d->z, (R *)d->px, (R *)d->py, (R *)d->pz, d->tau, d->id, v1,
-                     s->count, d->count);
+  const int64_t qblocks = ((cap + 1023) / 1024 + 7) / 8 * 8;   // 256 threads x 4 destinations, 8 | blocks
+  const void *sa[6] = {s->x, s->y, s->z, s->px, s->py, s->pz};
+  void *da[6] = {d->x, d->y, d->z, d->px, d->py, d->pz};
+  for (int k = 0; k < 6; ++k)
+    hipLaunchKernelGGL(k_permute4<R>, dim3((unsigned)qblocks), dim3(256), 0, st, (const R *)sa[k], (R *)da[k], v1,
+                       s->count);
+  hipLaunchKernelGGL(k_permute4<double>, dim3((unsigned)qblocks), dim3(256), 0, st, s->tau, d->tau, v1, s->count);
+  hipLaunchKernelGGL(k_permute4<uint64_t>, dim3((unsigned)qblocks), dim3(256), 0, st, s->id, d->id, v1, s->count);
+  hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, st, s->count, d->count);
   return hipGetLastError();
 }
 
