@@ -254,6 +254,48 @@ def test_surrogate_step_independent_of_order(trained):
            {k: sb[k] for k in ("events", "photons", "rejected", "capped")}
 
 
+def test_surrogate_emission_passes(trained):
+    """The surrogate emission runs every emitter's first candidate in one pass
+    and, with kmax > 1, the emitters with a further candidate within the step in
+    a second pass that re-runs their first candidate silently.  The photons of
+    the first pass come first: a run with kmax = 1 (no second pass; further
+    candidates counted as capped) appends exactly the first photons of the run
+    with kmax = 4, bit for bit (positions, momenta, optical depths, ids), and
+    the electrons without a further candidate end the step identically.  2e4
+    electrons at chi ~ 1 and ~ 10, dt = 0.2: several candidates per electron."""
+    torch, q = need_gpu()
+    n, b0 = 20000, 2000.0
+    rng = np.random.default_rng(37)
+    gam = np.where(rng.uniform(size=n) < 0.5, 206.0, 2060.0)
+    phi = rng.uniform(0.0, 2.0 * math.pi, n)
+    pm = np.sqrt(gam ** 2 - 1.0)
+    p = np.stack([pm * np.cos(phi), pm * np.sin(phi), np.zeros(n)], axis=-1)
+    tau0 = rng.exponential(size=n)
+    out = {}
+    for kmax in (1, 4):
+        print(f"surrogate emission passes: kmax {kmax}", flush=True)
+        ctx = _with_weights(q, trained, seed=29, kmax=kmax, flags=q.QED_FLAG_SURROGATE)
+        lep = q.Species(n, "f32")
+        ph = q.Species(4 * n, "f32")
+        lep.load(np.zeros((n, 3)), p, tau=tau0, ids=np.arange(n, dtype=np.uint64))
+        ctx.qed_set_next_id(n)
+        fld = q.Fields(q.QED_FIELD_UNIFORM, B=(0, 0, b0))
+        ctx.qed_gather_push(fld, lep, -1, 0.2, 0)
+        ctx.qed_emit_photons(lep, ph, 0)
+        st, _ = ctx.qed_get_status(check=False)
+        out[kmax] = (st, lep.to_numpy(), ph.to_numpy())
+    (s1, l1, p1), (s4, l4, p4) = out[1], out[4]
+    m = p1["id"].size
+    print(f"  kmax 1: {m} photons, capped {s1['capped']}; kmax 4: {p4['id'].size} photons, capped {s4['capped']}")
+    assert s1["capped"] > 100 and p4["id"].size > m > 1000
+    for k in ("x", "p", "tau", "id"):
+        np.testing.assert_array_equal(p1[k][:m] if k != "id" else p1[k], p4[k][:m])
+    # electrons whose step ended after the first candidate: identical in both runs
+    same = np.all(l1["p"] == l4["p"], axis=1) & (l1["tau"] == l4["tau"])
+    print(f"  electrons identical in both runs: {same.sum()} of {n}")
+    assert same.sum() == n - s1["capped"]     # the capped ones are those the second pass finishes
+
+
 def test_surrogate_step_spectrum_and_rate(trained):
     """The emission step with QED_FLAG_SURROGATE (candidate events at the rate
     envelope in the lepton pass, kept with the rate net's W / W_env, xi net in
