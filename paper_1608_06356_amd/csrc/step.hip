@@ -296,9 +296,10 @@ __device__ __forceinline__ bool stage_box(BoxLds &S, const FieldDev &f, const bo
 
 // Gather from the staged box.  A row of the stencil (three nodes along x) is
 // 72 contiguous bytes of LDS; row offsets are byte offsets built from the
-// pitches with adds only, and the next row's reads are issued before the
-// current row's products so that LDS latency overlaps the arithmetic.
-template <typename R>
+// pitches with adds only.  DB: the next row's reads are issued before the
+// current row's products, so that LDS latency overlaps the arithmetic (18 more
+// registers); without it the other waves of the SIMD hide that latency.
+template <typename R, bool DB = true>
 __device__ __forceinline__ void gather_box(const BoxLds &S, const int c0[3], const int pit[2], const R w[3][3],
                                            R F[6]) {
 #pragma unroll
@@ -313,10 +314,14 @@ __device__ __forceinline__ void gather_box(const BoxLds &S, const int c0[3], con
 #pragma unroll
     for (int k = 0; k < 9; ++k) dst[k] = q[k];
   };
-  load_row(v[0], 0);
+  if constexpr (DB) load_row(v[0], 0);
 #pragma unroll
   for (int r = 0; r < 9; ++r) {
-    if (r + 1 < 9) load_row(v[(r + 1) & 1], r + 1);
+    if constexpr (DB) {
+      if (r + 1 < 9) load_row(v[(r + 1) & 1], r + 1);
+    } else {
+      load_row(v[r & 1], r);
+    }
     const float2 *u = v[r & 1];
     const R wyz = w[1][r % 3] * w[2][r / 3];
 #pragma unroll
@@ -729,7 +734,7 @@ __global__ __launch_bounds__(kGPThreads, (gp_waves<R, FK, M1>())) void k_gather_
 // cells for one box, so it keeps the kernel above.
 constexpr int64_t kDenseGP = 64;
 template <bool Thin>
-__global__ __launch_bounds__(kGPThreads, kGPWaves - 1) void k_gather_push2(GPArgs<float> a) {
+__global__ __launch_bounds__(kGPThreads, kGPWaves) void k_gather_push2(GPArgs<float> a) {
   using R = float;
   constexpr int IT = 2;
   __shared__ R lnh_s[kRadNChi];
@@ -741,18 +746,14 @@ __global__ __launch_bounds__(kGPThreads, kGPWaves - 1) void k_gather_push2(GPArg
   FieldDev f = a.f;
   f.kind = QED_FIELD_GRID;
   bool live[IT];
-  // every load of the thread's particles is issued up front, to overlap with the staging
-  R xs[IT][3], ps[IT][3];
-  double taus[IT];
+  // positions up front (the box needs them); momenta and optical depths after the staging
+  R xs[IT][3];
   const GPTile<R> P(a.sp, base);
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
     const int o = it * kGPThreads + t;
     live[it] = base + o < n;
     xs[it][0] = live[it] ? P.x[o] : (R)0; xs[it][1] = live[it] ? P.y[o] : (R)0; xs[it][2] = live[it] ? P.z[o] : (R)0;
-    ps[it][0] = live[it] ? P.px[o] : (R)0; ps[it][1] = live[it] ? P.py[o] : (R)0;
-    ps[it][2] = live[it] ? P.pz[o] : (R)0;
-    taus[it] = live[it] ? P.tau[o] : 0.0;
   }
   for (int q = threadIdx.x; q < kRadNChi; q += blockDim.x) lnh_s[q] = a.lnh[q];
 
@@ -766,10 +767,16 @@ __global__ __launch_bounds__(kGPThreads, kGPWaves - 1) void k_gather_push2(GPArg
   if (!boxed && threadIdx.x == 0) atomicAdd(&a.counters[cBoxFallback], 1ull);
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
-    // one particle after the other, the weights recomputed from the position
-    // (held opaque, so that they are not kept live across the staging): two
-    // gathers in flight together, or weights held through the staging, would
-    // need more registers than five waves leave
+    // one particle after the other, its momentum and optical depth loaded
+    // here, the weights recomputed from the position (held opaque, so that they
+    // are not kept live across the staging) and the rows read one at a time:
+    // 72 registers, which six waves per SIMD allow (the LDS allows six
+    // workgroups per CU); holding any of these through the staging or a second
+    // row in flight needs more and measured slower
+    const int o = it * kGPThreads + t;
+    R px = 0, py = 0, pz = 0;
+    double tau = 0.0;
+    if (live[it]) { px = P.px[o]; py = P.py[o]; pz = P.pz[o]; tau = P.tau[o]; }
     R x = xs[it][0], y = xs[it][1], z = xs[it][2];
     asm volatile("" : "+v"(x), "+v"(y), "+v"(z));
     int jc[3];
@@ -777,11 +784,11 @@ __global__ __launch_bounds__(kGPThreads, kGPWaves - 1) void k_gather_push2(GPArg
     tsc_setup<R>(f, x, y, z, jc, w);
     R F[6];
     if (live[it]) {
-      if (boxed) gather_box<R>(box_s, rel[it], pit, w, F);
+      if (boxed) gather_box<R, false>(box_s, rel[it], pit, w, F);
       else gather_global<R>(f, jc, w, F);
     }
-    gp_finish<R, QED_FIELD_GRID, false, Thin>(a, P, f, lnh_s, base, it * kGPThreads + t, n, live[it], xs[it][0],
-                                              xs[it][1], xs[it][2], ps[it][0], ps[it][1], ps[it][2], taus[it], F);
+    gp_finish<R, QED_FIELD_GRID, false, Thin>(a, P, f, lnh_s, base, o, n, live[it], xs[it][0], xs[it][1],
+                                              xs[it][2], px, py, pz, tau, F);
   }
 }
 
