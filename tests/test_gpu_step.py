@@ -444,6 +444,59 @@ def test_grid_step_f32_one_step_parity(rad_table_I, ngrid, cap):
     np.testing.assert_allclose(g["tau"], r["tau"], rtol=2e-4, atol=2e-4 * (W * dt).max())
 
 
+def test_two_per_thread_small_and_ragged_counts(rad_table_I):
+    """The two-particle lepton pass (a species sized for at least 64 particles
+    per cell: capacity 40000 on an 8^3 grid) at counts that leave tiles partly
+    empty: none, one, the first half of a 512-particle tile and one more, a whole
+    tile and one more, three tiles and one more.  Each count against the oracle
+    step on the same float32 inputs (events, momenta, positions, photon ids and
+    energies), to the bars of the one-step parity test."""
+    torch, q = need_gpu()
+    ng, a0, L, dt, t = 8, 500.0, workloads.BOX_L, 0.01, 0.37
+    ens, x_all, p_all = _c2_setup(q, 1537)
+    tau_all = mc.init_tau(ens["id"], seed=1)
+    tau_all[::2] *= 1e-3
+    grid = torch.empty(ng ** 3 * 6, dtype=torch.float32, device="cuda")
+    Eg, Bg = mc.standing_wave_grid(ng, L, a0, t)
+    rad = mc.RadSampler(rad_table_I, "q16")
+    for n in (0, 1, 256, 257, 512, 513, 1537):
+        print(f"two per thread, {n} electrons", flush=True)
+        ctx = q.Context(seed=1, kmax=4)
+        ctx.qed_build_tables(q.QED_FORMULA_I)
+        ctx.qed_fill_standing_wave(grid, ng, L, a0, t)
+        fld = q.Fields(q.QED_FIELD_GRID, grid=grid, n=ng, L=L)
+        lep = q.Species(40_000, "f32")
+        ph = q.Species(8192, "f32")
+        x, p, tau, ids = x_all[:n], p_all[:n], tau_all[:n], ens["id"][:n]
+        if n:
+            lep.load(x, p, tau, ids)
+        ctx.qed_set_next_id(n)
+        ctx.qed_gather_push(fld, lep, -1, dt, 5)
+        ctx.qed_emit_photons(lep, ph, 5)
+        st, rc = ctx.qed_get_status()
+        assert st["scan_timeouts"] == 0 and st["dropped"] == 0
+        if n == 0:
+            assert lep.n() == 0 and ph.n() == 0 and st["events"] == 0
+            ctx.close()
+            continue
+        g, gph = lep.to_numpy(), ph.to_numpy()
+        E, B = mc.gather_tsc(Eg, Bg, L, x)
+        r = mc.lepton_step(x, p, tau, ids, E, B, q=-1.0, dt=dt, step=5, seed=1, sampler=rad, next_id=n, L=L)
+        W = r["W"]
+        ambiguous = int(np.count_nonzero(np.abs(tau - W * dt) <= 1e-5 * W * dt))
+        assert abs(st["events"] - r["n_events"]) <= 4 * ambiguous
+        np.testing.assert_array_equal(g["id"], ids)
+        np.testing.assert_allclose(g["p"], r["p"], rtol=2e-5, atol=2e-5 * np.abs(r["p"]).max())
+        dx = np.abs(g["x"] - r["x"])
+        assert np.minimum(dx, L - dx).max() < 1e-5
+        np.testing.assert_array_equal(gph["id"], r["photons"]["id"])
+        if gph["id"].size:
+            gerr = np.abs(np.linalg.norm(gph["p"], axis=1) / r["photons"]["gamma"] - 1)
+            assert gerr.max() <= 3e-4
+        np.testing.assert_allclose(g["tau"], r["tau"], rtol=2e-4, atol=2e-4 * (W * dt).max())
+        ctx.close()
+
+
 def test_emitted_spectrum_ks_1e7(rad_table_I):
     """Fixed chi ~ 1 (Fig. 1 b), no recoil, float32 path: 1e7 emitted photons.
     xi against the exact truncated CDF (one-sample KS) and against the oracle's
