@@ -205,6 +205,80 @@ def test_thinned_pass_envelope_where_fields_cancel(rad_table_I):
     assert infl[sgn < 0].max() < 1.0 + 1e-4
 
 
+@pytest.mark.parametrize("cap", [2000, 40_000], ids=["one_per_thread", "two_per_thread"])
+def test_thinned_pass_on_a_grid(rad_table_I, cap):
+    """Surrogate path on a grid (standing wave a0 = 500, 8^3 grid, 1537 electrons,
+    tau0 = 50: no candidate within the step), with the species sized for the
+    one-particle and for the two-particle lepton kernel: the push against the
+    oracle step on the same float32 inputs (the bars of the one-step parity
+    test), and the applied rate (tau0 - tau1) / dt at or above the oracle's rate
+    at the oracle's chi of the pushed momentum, at or above the envelope at that
+    chi (2e-5: the float32 gather and envelope), and at most the envelope at the
+    bound the float32 evaluation of chi guarantees for the kernel's own fields
+    (chi^2 E_S^2 + 32u (|A|^2 + S^2), u = 2^-24, A and S the sums of magnitudes
+    of the terms of a = gamma E + p x B and s = p.E), those fields being within
+    28u a0 per component of the oracle's (27 weighted nodes of magnitude <= a0,
+    weights summing to 1), which moves |a| by up to sqrt(3) (gamma + |p|) 28u a0
+    and |s| by up to sqrt(3) |p| 28u a0; 1e-5 to spare for the float32 envelope."""
+    torch, q = need_gpu()
+    ng, a0, L, dt, t, n, tau0 = 8, 500.0, workloads.BOX_L, 0.01, 0.37, 1537, 50.0
+    ens, x, p = _c2_setup(q, n)
+    ctx = q.Context(seed=1, kmax=4, flags=q.QED_FLAG_SURROGATE)
+    ctx.qed_build_tables(q.QED_FORMULA_I)
+    for net in (0, 1):                              # any weights: the pass uses the envelope only
+        rng0 = np.random.default_rng(net)
+        ctx.qed_surrogate_io(net, rng0.normal(0, 0.3, q.lib().qed_surrogate_params(net)).astype(np.float32))
+    grid = torch.empty(ng ** 3 * 6, dtype=torch.float32, device="cuda")
+    ctx.qed_fill_standing_wave(grid, ng, L, a0, t)
+    fld = q.Fields(q.QED_FIELD_GRID, grid=grid, n=ng, L=L)
+    lep = q.Species(cap, "f32")
+    tau = np.full(n, tau0)
+    lep.load(x, p, tau, ens["id"])
+    ctx.qed_set_next_id(n)
+    print(f"thinned pass on a grid, capacity {cap}", flush=True)
+    ctx.qed_gather_push(fld, lep, -1, dt, 5)
+    st, _ = ctx.qed_get_status()
+    g = lep.to_numpy()
+    assert st["nan_chi"] == 0 and np.all(g["tau"] > 0.0)
+    Eg, Bg = mc.standing_wave_grid(ng, L, a0, t)
+    E, B = mc.gather_tsc(Eg, Bg, L, x)
+    rad = mc.RadSampler(rad_table_I, "q16")
+    r = mc.lepton_step(x, p, tau, ens["id"], E, B, q=-1.0, dt=dt, step=5, seed=1, sampler=rad, next_id=n, L=L)
+    assert r["n_events"] == 0
+    np.testing.assert_allclose(g["p"], r["p"], rtol=2e-5, atol=2e-5 * np.abs(r["p"]).max())
+    dx = np.abs(g["x"] - r["x"])
+    assert np.minimum(dx, L - dx).max() < 1e-5
+    p1 = g["p"]
+    gamma1 = np.sqrt(1.0 + np.sum(p1 * p1, -1))
+    chi = spectra.chi_lepton(p1, E, B)
+    w_rate = tables.rate_rad(rad_table_I, chi, gamma1)
+    c1 = 5.0 / (2.0 * math.sqrt(3.0))
+
+    def env(c):
+        return RATE_UNIT * 1.002 * c1 * c * (1.0 + c) ** (-1.0 / 3.0) / gamma1
+
+    px, py, pz = p1[:, 0], p1[:, 1], p1[:, 2]
+    ge = np.abs(gamma1[:, None] * E)
+    A2 = ((ge[:, 0] + np.abs(py * B[:, 2]) + np.abs(pz * B[:, 1])) ** 2
+          + (ge[:, 1] + np.abs(pz * B[:, 0]) + np.abs(px * B[:, 2])) ** 2
+          + (ge[:, 2] + np.abs(px * B[:, 1]) + np.abs(py * B[:, 0])) ** 2)
+    S2 = np.sum(np.abs(p1 * E), -1) ** 2
+    u = 2.0 ** -24
+    pa = np.linalg.norm(p1, axis=1)
+    a_mag = np.linalg.norm(gamma1[:, None] * E + np.cross(p1, B), axis=1)
+    s_mag = np.abs(np.sum(p1 * E, -1))
+    da = math.sqrt(3.0) * (gamma1 + pa) * 28.0 * u * a0
+    ds = math.sqrt(3.0) * pa * 28.0 * u * a0
+    gather = 2.0 * a_mag * da + da ** 2 + 2.0 * s_mag * ds + ds ** 2
+    chi_hi = np.sqrt(chi ** 2 + (32.0 * u * (A2 + S2) + gather) / E_S ** 2) * (1.0 + 2.0 ** -20)
+    w_gpu = (tau0 - g["tau"]) / dt
+    lo, hi = w_gpu / env(chi), w_gpu / env(chi_hi)
+    print(f"  chi {chi.min():.2e} .. {chi.max():.2e}; applied / envelope at chi {lo.min():.6f} .. {lo.max():.6f}, "
+          f"at the bound max {hi.max():.6f}")
+    assert np.all(w_gpu >= w_rate)
+    assert lo.min() > 1.0 - 2e-5 and hi.max() < 1.0 + 1e-5
+
+
 def _chi_ref80(p, E, B, photon):
     """Eq. (2) (or Eq. (3) with |v| = 1) evaluated literally in 80-bit floats."""
     pl, El, Bl = (a.astype(np.longdouble) for a in (p, E, B))
